@@ -1,0 +1,179 @@
+"""CPU FP64 oracle for FARM's query-time relational scoring.
+
+TEST INFRASTRUCTURE ONLY. Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package. It shares no code with
+the GPU library (``paper_2606_15476_amd``) and never imports it.
+
+The arithmetic lives in ``farm_oracle.c`` (plain loops, double precision); this
+module builds it with gcc on first use and marshals numpy arrays. Every
+function cites the passage it follows in the C source's header.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "farm_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "_build", "libfarm_oracle.so")
+
+MAX_REL = 8
+NO_ID = 0xFFFFFFFF
+
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, no fast-math, OpenMP)."""
+    os.makedirs(os.path.dirname(_LIB_PATH), exist_ok=True)
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(build())
+        P = ctypes.c_void_p
+        i64, i32 = ctypes.c_int64, ctypes.c_int32
+        lib.farm_oracle_predicate.restype = ctypes.c_double
+        lib.farm_oracle_predicate.argtypes = [ctypes.c_int, P, P, P]
+        lib.farm_oracle_score.restype = ctypes.c_int
+        lib.farm_oracle_score.argtypes = [i64, ctypes.c_int, P, P, P, P, P, i32, P, P, P, P, P, P, P, P, P]
+        lib.farm_oracle_score_pairs.restype = ctypes.c_int
+        lib.farm_oracle_score_pairs.argtypes = [i64, ctypes.c_int, P, P, P, P, P, i32, P, P, P, P, P,
+                                                i64, P, P, P, P, P, P]
+        lib.farm_oracle_topk.restype = ctypes.c_int
+        lib.farm_oracle_topk.argtypes = [i64, P, P, i32, P]
+        lib.farm_oracle_topk_bounded.restype = ctypes.c_int
+        lib.farm_oracle_topk_bounded.argtypes = [i64, ctypes.c_int, P, P, P, P, P, i32, P, P, P, P, P,
+                                                 i32, P, P, P, P, P]
+        _lib = lib
+    return _lib
+
+
+def _c(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def set_threads(n: int | None):
+    """Limit OpenMP threads (None = library default)."""
+    if n is None:
+        os.environ.pop("OMP_NUM_THREADS", None)
+    else:
+        os.environ["OMP_NUM_THREADS"] = str(int(n))
+
+
+def predicate(p: int, ci, cj, right) -> float:
+    """P_p(i, j) in FP64 for float32 centers and viewer right vector."""
+    lib = _load()
+    a, pa = _c(ci, np.float32)
+    b, pb = _c(cj, np.float32)
+    r, pr = _c(right, np.float32)
+    return float(lib.farm_oracle_predicate(int(p), pa, pb, pr))
+
+
+def _scene_args(scene):
+    desc, pd = _c(scene.desc, np.float32)
+    cen, pc = _c(scene.center, np.float32)
+    ids, pi = _c(scene.ids, np.uint32)
+    if scene.cls is None:
+        cls, pk = None, None
+    else:
+        cls, pk = _c(scene.cls, np.int32)
+    vr, pv = _c(scene.view_right, np.float32)
+    keep = (desc, cen, ids, cls, vr)
+    return keep, [int(desc.shape[0]), int(desc.shape[1]), pd, pc, pi, pk, pv]
+
+
+def _query_args(qb):
+    tg, pt = _c(qb.target, np.float32)
+    if qb.target_cls is None:
+        tc, ptc = None, None
+    else:
+        tc, ptc = _c(qb.target_cls, np.int32)
+    ro, pro = _c(qb.rel_off, np.int32)
+    rp, prp = _c(qb.rel_pred, np.int32)
+    ra, pra = _c(qb.rel_anchor.reshape(-1, qb.target.shape[1]) if qb.rel_anchor.size else
+                 np.zeros((1, qb.target.shape[1]), np.float32), np.float32)
+    keep = (tg, tc, ro, rp, ra)
+    return keep, [int(tg.shape[0]), pt, ptc, pro, prp, pra]
+
+
+def score(scene, qb, terms: bool = False):
+    """Full FP64 scores [q, n]; with ``terms`` also s_sem [q, n], t_r and b_r [r_tot, n]."""
+    lib = _load()
+    k1, sa = _scene_args(scene)
+    k2, qa = _query_args(qb)
+    n, q = sa[0], qa[0]
+    r_tot = int(qb.rel_off[-1])
+    out = np.zeros((q, n), np.float64)
+    sem = np.zeros((q, n), np.float64) if terms else None
+    t = np.zeros((r_tot, n), np.float64) if terms else None
+    b = np.zeros((r_tot, n), np.uint32) if terms else None
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p) if a is not None and a.size else None
+    rc = lib.farm_oracle_score(*sa, *qa, ptr(out), ptr(sem), ptr(t), ptr(b))
+    if rc:
+        raise ValueError(f"oracle score failed ({rc})")
+    del k1, k2
+    return (out, sem, t, b) if terms else out
+
+
+def score_pairs(scene, qb, qsel, osel):
+    """FP64 scores of selected (query, object) pairs; returns (s, s_sem, t[m,8], b[m,8])."""
+    lib = _load()
+    k1, sa = _scene_args(scene)
+    k2, qa = _query_args(qb)
+    qs, pq = _c(qsel, np.int32)
+    os_, po = _c(osel, np.int64)
+    m = int(qs.shape[0])
+    out = np.zeros(max(m, 1), np.float64)
+    sem = np.zeros(max(m, 1), np.float64)
+    t = np.zeros((max(m, 1), MAX_REL), np.float64)
+    b = np.zeros((max(m, 1), MAX_REL), np.uint32)
+    rc = lib.farm_oracle_score_pairs(*sa, *qa, m, pq, po, out.ctypes.data_as(ctypes.c_void_p),
+                                     sem.ctypes.data_as(ctypes.c_void_p), t.ctypes.data_as(ctypes.c_void_p),
+                                     b.ctypes.data_as(ctypes.c_void_p))
+    if rc:
+        raise ValueError(f"oracle score_pairs failed ({rc})")
+    del k1, k2
+    return out[:m], sem[:m], t[:m], b[:m]
+
+
+def topk(scores_row, ids, k: int):
+    """Indices of the first min(k, n) objects by (score desc, id asc); -1 padding."""
+    lib = _load()
+    s, ps = _c(scores_row, np.float64)
+    i, pi = _c(ids, np.uint32)
+    out = np.zeros(k, np.int64)
+    rc = lib.farm_oracle_topk(int(s.shape[0]), ps, pi, int(k), out.ctypes.data_as(ctypes.c_void_p))
+    if rc:
+        raise ValueError(f"oracle topk failed ({rc})")
+    return out
+
+
+def topk_bounded(scene, qb, k: int):
+    """Exact TopK via the soft-blend bound; returns (idx[q,k], score[q,k], t[q,k,8], b[q,k,8], n_scored[q])."""
+    lib = _load()
+    k1, sa = _scene_args(scene)
+    k2, qa = _query_args(qb)
+    q = qa[0]
+    idx = np.zeros((q, k), np.int64)
+    sc = np.zeros((q, k), np.float64)
+    t = np.zeros((q, k, MAX_REL), np.float64)
+    b = np.zeros((q, k, MAX_REL), np.uint32)
+    ns = np.zeros(q, np.int64)
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    rc = lib.farm_oracle_topk_bounded(*sa, *qa, int(k), p(idx), p(sc), p(t), p(b), p(ns))
+    if rc:
+        raise ValueError(f"oracle topk_bounded failed ({rc})")
+    del k1, k2
+    return idx, sc, t, b, ns

@@ -1,0 +1,89 @@
+"""Brute-force joint-binding enumeration for tiny scenes (test infrastructure only).
+
+This is the score *before* the star decomposition: for a candidate target e,
+every binding eta of the anchor variables (a_1..a_R) to memory entities other
+than e is verified and the best one kept (Appendix "Robust Relational
+Retrieval Formulation", soft verification: score(e) is the maximum of
+Verify(eta) over bindings with eta(x_star) = e).  Verify aggregates the unary
+target score and the induced relational scores with the composite rule of the
+Appendix "Retrieval Details", composite-scoring step:
+
+    Verify(eta) = s_sem(e) * ((1 - w) + w * gmean_r( sim(eta(a_r), q_r) * P_r(e, eta(a_r)) ))
+
+Each relation's term folds the anchor's own description match sim(a, q_r)
+into the relational score (the anchor's unary predicate and the relation share
+the anchor variable).  Pure Python on math.* in double precision; it shares no
+code with ``farm_oracle.c`` and costs O(N^(R+1)) -- use N <= 16, R <= 3.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+
+W = 0.5
+CLASS_FACTOR = 0.3
+
+
+def _unit(v):
+    s = math.sqrt(sum(float(x) * float(x) for x in v))
+    return [float(x) / s for x in v]
+
+
+def _sim(u, v):
+    return max(0.0, sum(a * b for a, b in zip(u, v)))
+
+
+def _sigmoid(x):
+    return 1.0 / (1.0 + math.exp(-x))
+
+
+def soft_relation(pred, ci, cj, right):
+    """The five closed-form soft predicates, written from their definitions."""
+    dx, dy, dz = (float(ci[0]) - float(cj[0]), float(ci[1]) - float(cj[1]), float(ci[2]) - float(cj[2]))
+    if pred == 0:  # near: Gaussian on centroid distance, sigma 0.5 m
+        return math.exp(-(dx * dx + dy * dy + dz * dz) / (2 * 0.25))
+    if pred == 1:  # above: sigmoid of the vertical offset, temperature 0.1 m
+        return _sigmoid(dz / 0.1)
+    if pred == 2:  # below
+        return _sigmoid(-dz / 0.1)
+    lateral = dx * float(right[0]) + dy * float(right[1])
+    if pred == 4:  # right of
+        return _sigmoid(lateral / 0.1)
+    if pred == 3:  # left of
+        return _sigmoid(-lateral / 0.1)
+    raise ValueError(pred)
+
+
+def brute_scores(scene, qb):
+    """Scores [q][n] by enumerating all anchor bindings (list of lists of floats)."""
+    n = scene.desc.shape[0]
+    units = [_unit(scene.desc[i]) for i in range(n)]
+    out = []
+    for k in range(qb.target.shape[0]):
+        qt = _unit(qb.target[k])
+        tcls = int(qb.target_cls[k]) if qb.target_cls is not None else -1
+        a0, a1 = int(qb.rel_off[k]), int(qb.rel_off[k + 1])
+        rels = [(int(qb.rel_pred[r]), _unit(qb.rel_anchor[r])) for r in range(a0, a1)]
+        row = []
+        for e in range(n):
+            kappa = 1.0
+            if tcls >= 0 and scene.cls is not None and int(scene.cls[e]) >= 0 and int(scene.cls[e]) != tcls:
+                kappa = CLASS_FACTOR
+            s_sem = kappa * _sim(units[e], qt)
+            if not rels:
+                row.append(s_sem)
+                continue
+            others = [j for j in range(n) if j != e]
+            best = None
+            if not others:
+                best = s_sem * (1 - W)
+            for binding in itertools.product(others, repeat=len(rels)):
+                prod = 1.0
+                for (pred, qr), j in zip(rels, binding):
+                    prod *= _sim(units[j], qr) * soft_relation(pred, scene.center[e], scene.center[j], scene.view_right)
+                v = s_sem * ((1 - W) + W * prod ** (1.0 / len(rels)))
+                if best is None or v > best:
+                    best = v
+            row.append(best)
+        out.append(row)
+    return out

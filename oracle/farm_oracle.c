@@ -1,0 +1,403 @@
+/*
+ * farm_oracle.c -- plain, slow, FP64 reference for FARM's query-time
+ * relational scoring.  TEST INFRASTRUCTURE ONLY: only the test suite, the smoke
+ * check and the CPU-baseline leg of the benchmark may load this library.  It
+ * shares no code, header or constant table with the GPU library.
+ *
+ * What it computes (paper, Section 2.3 "Executable query specification and
+ * compositional retrieval"; Appendix "Robust Relational Retrieval
+ * Formulation", soft verification and query-time complexity; Appendix
+ * "Retrieval Details", steps 3-5 and the "Why soft, not hard?" paragraph):
+ *
+ *   sim(i, v)   = max(0, <u_i, v^>), u_i and v^ the L2-normalised descriptor
+ *                 and query vector (unary score s_sigma in [0, 1]);
+ *   s_sem(i)    = kappa_i * sim(i, q_t), kappa_i = 0.3 when both the parsed
+ *                 target class and the object's class are known and differ
+ *                 (composite-scoring step: the soft class factor), else 1;
+ *   t_r(i)      = max_{j != i} sim(j, q_r) * P_{p_r}(i, j)
+ *                 (greedy binding of each anchor of the star-shaped query:
+ *                 conditioning on the target separates the anchors, so the
+ *                 joint maximum over bindings is the per-relation maximum);
+ *   b_r(i)      = the maximising anchor's object id (smallest id on ties);
+ *   gbar(i)     = (prod_r t_r(i))^(1/R), 1 when R = 0 (geometric mean of the
+ *                 predicate scores);
+ *   s(i)        = s_sem(i) * ((1 - w) + w * gbar(i)), w = 0.5;
+ *   TopK        = the first min(K, N) objects ordered by (s desc, id asc).
+ *
+ * Predicates (Appendix "Retrieval Details", predicate evaluation), with
+ * D = c_i - c_j the target-minus-anchor box-center offset and sig(u) the
+ * logistic function:
+ *   NEAR     = exp(-|D|^2 / (2 * 0.5^2))          (Gaussian, sigma = 0.5 m)
+ *   ABOVE    = sig(D_z / 0.1),  BELOW = sig(-D_z / 0.1)
+ *   RIGHT_OF = sig((D_x r_x + D_y r_y) / 0.1),  LEFT_OF = sig(-(...) / 0.1)
+ * where (r_x, r_y) is the scene viewer's right vector.  The temperatures
+ * (0.1 m), the Gaussian's normalisation, the clamp at zero and the viewer
+ * convention are readings where the paper is silent.
+ *
+ * Everything is computed in double precision from the float inputs, with plain
+ * loops in the order of the definition.  OpenMP parallelises only the
+ * independent outer loop over queries (or sampled targets).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_W 0.5
+#define ORACLE_CLASS_FACTOR 0.3
+#define ORACLE_NEAR_SIGMA 0.5
+#define ORACLE_TAU 0.1
+#define ORACLE_MAX_REL 8
+#define ORACLE_NO_ID 0xFFFFFFFFu
+
+enum { P_NEAR = 0, P_ABOVE = 1, P_BELOW = 2, P_LEFT_OF = 3, P_RIGHT_OF = 4 };
+
+static double logistic(double u) { return 1.0 / (1.0 + exp(-u)); }
+
+/* Soft predicate P_p(i, j) for target center ci and anchor center cj. */
+double oracle_predicate(int p, const double* ci, const double* cj, const double* right) {
+    double dx = ci[0] - cj[0], dy = ci[1] - cj[1], dz = ci[2] - cj[2];
+    switch (p) {
+    case P_NEAR: {
+        double d2 = dx * dx + dy * dy + dz * dz;
+        return exp(-d2 / (2.0 * ORACLE_NEAR_SIGMA * ORACLE_NEAR_SIGMA));
+    }
+    case P_ABOVE: return logistic(dz / ORACLE_TAU);
+    case P_BELOW: return logistic(-dz / ORACLE_TAU);
+    case P_RIGHT_OF: return logistic((dx * right[0] + dy * right[1]) / ORACLE_TAU);
+    case P_LEFT_OF: return logistic(-(dx * right[0] + dy * right[1]) / ORACLE_TAU);
+    default: return NAN;
+    }
+}
+
+/* Exported wrapper so tests can pin single predicate values. */
+double farm_oracle_predicate(int p, const float* ci, const float* cj, const float* right) {
+    double a[3] = {ci[0], ci[1], ci[2]}, b[3] = {cj[0], cj[1], cj[2]}, r[2] = {right[0], right[1]};
+    return oracle_predicate(p, a, b, r);
+}
+
+static void unit_vector(const float* v, int d, double* out) {
+    double ss = 0.0;
+    for (int k = 0; k < d; ++k) ss += (double)v[k] * (double)v[k];
+    double nrm = sqrt(ss);
+    for (int k = 0; k < d; ++k) out[k] = (double)v[k] / nrm;
+}
+
+static double clamped_cosine(const double* u, const double* v, int d) {
+    double dot = 0.0;
+    for (int k = 0; k < d; ++k) dot += u[k] * v[k];
+    return dot > 0.0 ? dot : 0.0;
+}
+
+typedef struct {
+    int64_t n;
+    int d;
+    double* u;        /* [n][d] normalised descriptors */
+    double* c;        /* [n][3] centers */
+    const uint32_t* id;
+    const int32_t* cls;
+    double right[2];
+} scene64;
+
+static int scene_init(scene64* s, int64_t n, int d, const float* desc, const float* center,
+                      const uint32_t* id, const int32_t* cls, const float* right) {
+    s->n = n;
+    s->d = d;
+    s->u = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * (size_t)d);
+    s->c = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * 3);
+    if (!s->u || !s->c) return -2;
+    for (int64_t i = 0; i < n; ++i) {
+        unit_vector(desc + (size_t)i * d, d, s->u + (size_t)i * d);
+        for (int k = 0; k < 3; ++k) s->c[i * 3 + k] = center[i * 3 + k];
+    }
+    s->id = id;
+    s->cls = cls;
+    s->right[0] = right[0];
+    s->right[1] = right[1];
+    return 0;
+}
+
+static void scene_free(scene64* s) {
+    free(s->u);
+    free(s->c);
+}
+
+/* Per-query state: normalised target, anchor similarities per relation. */
+typedef struct {
+    int r;                      /* number of relations */
+    int pred[ORACLE_MAX_REL];
+    double* sem;                /* [n]  s_sem(i) */
+    double* asim;               /* [r][n] sim(j, q_r) */
+} query64;
+
+static int query_init(query64* qs, const scene64* s, const float* target, int32_t tcls,
+                      int r, const int32_t* pred, const float* anchors) {
+    int64_t n = s->n;
+    int d = s->d;
+    qs->r = r;
+    qs->sem = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    qs->asim = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * (size_t)(r > 0 ? r : 1));
+    double* v = (double*)malloc(sizeof(double) * (size_t)d);
+    if (!qs->sem || !qs->asim || !v) { free(v); return -2; }
+    unit_vector(target, d, v);
+    for (int64_t i = 0; i < n; ++i) {
+        double kappa = (tcls >= 0 && s->cls && s->cls[i] >= 0 && s->cls[i] != tcls) ? ORACLE_CLASS_FACTOR : 1.0;
+        qs->sem[i] = kappa * clamped_cosine(s->u + (size_t)i * d, v, d);
+    }
+    for (int rr = 0; rr < r; ++rr) {
+        qs->pred[rr] = pred[rr];
+        unit_vector(anchors + (size_t)rr * d, d, v);
+        for (int64_t j = 0; j < n; ++j) qs->asim[(size_t)rr * n + j] = clamped_cosine(s->u + (size_t)j * d, v, d);
+    }
+    free(v);
+    return 0;
+}
+
+static void query_free(query64* qs) {
+    free(qs->sem);
+    free(qs->asim);
+}
+
+/* t_r(i) and b_r(i): exhaustive maximum over anchors j != i. */
+static void relation_term(const scene64* s, const query64* qs, int rr, int64_t i, double* t, uint32_t* b) {
+    double best = -1.0;
+    uint32_t best_id = ORACLE_NO_ID;
+    const double* a = qs->asim + (size_t)rr * s->n;
+    for (int64_t j = 0; j < s->n; ++j) {
+        if (j == i) continue;
+        double v = a[j] * oracle_predicate(qs->pred[rr], s->c + i * 3, s->c + j * 3, s->right);
+        if (v > best || (v == best && s->id[j] < best_id)) {
+            best = v;
+            best_id = s->id[j];
+        }
+    }
+    if (best < 0.0) best = 0.0; /* N = 1: no anchor exists */
+    *t = best;
+    *b = best_id;
+}
+
+static double composite(double sem, int r, const double* t) {
+    double gbar = 1.0;
+    if (r > 0) {
+        double prod = 1.0;
+        for (int rr = 0; rr < r; ++rr) prod *= t[rr];
+        gbar = pow(prod, 1.0 / (double)r);
+    }
+    return sem * ((1.0 - ORACLE_W) + ORACLE_W * gbar);
+}
+
+static int check_query_meta(int32_t q, const int32_t* rel_off, const int32_t* rel_pred) {
+    if (rel_off[0] != 0) return -1;
+    for (int32_t k = 0; k < q; ++k) {
+        int r = rel_off[k + 1] - rel_off[k];
+        if (r < 0 || r > ORACLE_MAX_REL) return -1;
+        for (int rr = rel_off[k]; rr < rel_off[k + 1]; ++rr)
+            if (rel_pred[rr] < 0 || rel_pred[rr] > 4) return -1;
+    }
+    return 0;
+}
+
+/*
+ * Full scores for every (query, object).
+ *   scores[q][n]          composite scores
+ *   sem[q][n]             s_sem (may be NULL)
+ *   rel_terms[r_tot][n]   t_r (may be NULL)
+ *   rel_anchor_id[r_tot][n] b_r (may be NULL)
+ * Returns 0, -1 on invalid metadata, -2 on allocation failure.
+ */
+int farm_oracle_score(int64_t n, int d, const float* desc, const float* center, const uint32_t* id,
+                      const int32_t* cls, const float* right, int32_t q, const float* target,
+                      const int32_t* target_cls, const int32_t* rel_off, const int32_t* rel_pred,
+                      const float* rel_anchor, double* scores, double* sem, double* rel_terms,
+                      uint32_t* rel_anchor_id) {
+    if (check_query_meta(q, rel_off, rel_pred)) return -1;
+    scene64 s;
+    if (scene_init(&s, n, d, desc, center, id, cls, right)) { scene_free(&s); return -2; }
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t k = 0; k < q; ++k) {
+        query64 qs;
+        int r = rel_off[k + 1] - rel_off[k];
+        int r0 = rel_off[k];
+        if (query_init(&qs, &s, target + (size_t)k * d, target_cls ? target_cls[k] : -1, r,
+                       rel_pred + r0, rel_anchor + (size_t)r0 * d)) {
+            query_free(&qs);
+#pragma omp atomic write
+            err = -2;
+            continue;
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            double t[ORACLE_MAX_REL];
+            for (int rr = 0; rr < r; ++rr) {
+                uint32_t b;
+                relation_term(&s, &qs, rr, i, &t[rr], &b);
+                if (rel_terms) rel_terms[(size_t)(r0 + rr) * n + i] = t[rr];
+                if (rel_anchor_id) rel_anchor_id[(size_t)(r0 + rr) * n + i] = b;
+            }
+            scores[(size_t)k * n + i] = composite(qs.sem[i], r, t);
+            if (sem) sem[(size_t)k * n + i] = qs.sem[i];
+        }
+        query_free(&qs);
+    }
+    scene_free(&s);
+    return err;
+}
+
+/*
+ * Scores of selected (query, object) pairs only: out[m] for pair m =
+ * (qsel[m], osel[m]); each costs O(R * N) after the query's similarities.
+ * rel_terms/rel_anchor_id, when not NULL, are [m][8] (unused slots = 0 / NO_ID).
+ */
+int farm_oracle_score_pairs(int64_t n, int d, const float* desc, const float* center, const uint32_t* id,
+                            const int32_t* cls, const float* right, int32_t q, const float* target,
+                            const int32_t* target_cls, const int32_t* rel_off, const int32_t* rel_pred,
+                            const float* rel_anchor, int64_t m, const int32_t* qsel, const int64_t* osel,
+                            double* out, double* out_sem, double* rel_terms, uint32_t* rel_anchor_id) {
+    if (check_query_meta(q, rel_off, rel_pred)) return -1;
+    for (int64_t p = 0; p < m; ++p)
+        if (qsel[p] < 0 || qsel[p] >= q || osel[p] < 0 || osel[p] >= n) return -1;
+    scene64 s;
+    if (scene_init(&s, n, d, desc, center, id, cls, right)) { scene_free(&s); return -2; }
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t k = 0; k < q; ++k) {
+        int64_t cnt = 0;
+        for (int64_t p = 0; p < m; ++p) cnt += (qsel[p] == k);
+        if (!cnt) continue;
+        query64 qs;
+        int r = rel_off[k + 1] - rel_off[k];
+        int r0 = rel_off[k];
+        if (query_init(&qs, &s, target + (size_t)k * d, target_cls ? target_cls[k] : -1, r,
+                       rel_pred + r0, rel_anchor + (size_t)r0 * d)) {
+            query_free(&qs);
+#pragma omp atomic write
+            err = -2;
+            continue;
+        }
+        for (int64_t p = 0; p < m; ++p) {
+            if (qsel[p] != k) continue;
+            int64_t i = osel[p];
+            double t[ORACLE_MAX_REL];
+            for (int rr = 0; rr < ORACLE_MAX_REL; ++rr) {
+                uint32_t b = ORACLE_NO_ID;
+                t[rr] = 0.0;
+                if (rr < r) relation_term(&s, &qs, rr, i, &t[rr], &b);
+                if (rel_terms) rel_terms[p * ORACLE_MAX_REL + rr] = t[rr];
+                if (rel_anchor_id) rel_anchor_id[p * ORACLE_MAX_REL + rr] = b;
+            }
+            out[p] = composite(qs.sem[i], r, t);
+            if (out_sem) out_sem[p] = qs.sem[i];
+        }
+        query_free(&qs);
+    }
+    scene_free(&s);
+    return err;
+}
+
+/* TopK of one score row: first min(k, n) indices by (score desc, id asc). */
+static int topk_cmp_scores_desc(const double* sc, const uint32_t* id, int64_t a, int64_t b) {
+    if (sc[a] > sc[b]) return -1;
+    if (sc[a] < sc[b]) return 1;
+    return (id[a] < id[b]) ? -1 : (id[a] > id[b]);
+}
+
+int farm_oracle_topk(int64_t n, const double* scores, const uint32_t* id, int32_t k, int64_t* out_idx) {
+    /* Selection by repeated scans: plain and obviously correct. */
+    int64_t kk = k < n ? k : n;
+    unsigned char* taken = (unsigned char*)calloc((size_t)(n > 0 ? n : 1), 1);
+    if (!taken) return -2;
+    for (int64_t r = 0; r < kk; ++r) {
+        int64_t best = -1;
+        for (int64_t i = 0; i < n; ++i) {
+            if (taken[i]) continue;
+            if (best < 0 || topk_cmp_scores_desc(scores, id, i, best) < 0) best = i;
+        }
+        taken[best] = 1;
+        out_idx[r] = best;
+    }
+    for (int64_t r = kk; r < k; ++r) out_idx[r] = -1;
+    free(taken);
+    return 0;
+}
+
+/*
+ * Exact TopK of large queries without scoring every object.  The soft blend
+ * bounds every score: (1 - w) s_sem(i) <= s(i) <= s_sem(i) (the spatial factor
+ * stays in [1 - w, 1]; "Why soft, not hard?" paragraph).  Let L be the K-th
+ * largest lower bound (1 - w) s_sem.  K objects score at least L, so an object
+ * with s_sem(i) < L scores strictly below them and cannot enter the TopK.
+ * Only objects with s_sem(i) >= L are scored, exhaustively over anchors.
+ *   out_idx[q][k] object indices (-1 padding), out_score[q][k],
+ *   n_scored[q]   how many objects were scored exactly (may be NULL).
+ */
+int farm_oracle_topk_bounded(int64_t n, int d, const float* desc, const float* center, const uint32_t* id,
+                             const int32_t* cls, const float* right, int32_t q, const float* target,
+                             const int32_t* target_cls, const int32_t* rel_off, const int32_t* rel_pred,
+                             const float* rel_anchor, int32_t k, int64_t* out_idx, double* out_score,
+                             double* out_terms, uint32_t* out_anchor_id, int64_t* n_scored) {
+    if (check_query_meta(q, rel_off, rel_pred) || k < 1) return -1;
+    scene64 s;
+    if (scene_init(&s, n, d, desc, center, id, cls, right)) { scene_free(&s); return -2; }
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t qq = 0; qq < q; ++qq) {
+        query64 qs;
+        int r = rel_off[qq + 1] - rel_off[qq];
+        int r0 = rel_off[qq];
+        double* full = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+        double* lower = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+        int64_t* sel = (int64_t*)malloc(sizeof(int64_t) * (size_t)k);
+        if (!full || !lower || !sel ||
+            query_init(&qs, &s, target + (size_t)qq * d, target_cls ? target_cls[qq] : -1, r,
+                       rel_pred + r0, rel_anchor + (size_t)r0 * d)) {
+            free(full); free(lower); free(sel);
+#pragma omp atomic write
+            err = -2;
+            continue;
+        }
+        /* K-th largest lower bound. */
+        for (int64_t i = 0; i < n; ++i) lower[i] = (1.0 - ORACLE_W) * qs.sem[i];
+        double L = -1.0;
+        if (n > 0) {
+            int64_t kk = k < n ? k : n;
+            /* plain partial selection of the kk-th largest value */
+            double* tmp = (double*)malloc(sizeof(double) * (size_t)n);
+            memcpy(tmp, lower, sizeof(double) * (size_t)n);
+            for (int64_t rr = 0; rr < kk; ++rr) {
+                int64_t bi = rr;
+                for (int64_t i = rr + 1; i < n; ++i) if (tmp[i] > tmp[bi]) bi = i;
+                double x = tmp[rr]; tmp[rr] = tmp[bi]; tmp[bi] = x;
+            }
+            L = tmp[kk - 1];
+            free(tmp);
+        }
+        int64_t cnt = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            if (qs.sem[i] >= L) {
+                double t[ORACLE_MAX_REL];
+                for (int rr = 0; rr < r; ++rr) { uint32_t b; relation_term(&s, &qs, rr, i, &t[rr], &b); }
+                full[i] = composite(qs.sem[i], r, t);
+                ++cnt;
+            } else {
+                full[i] = -INFINITY; /* provably outside the TopK */
+            }
+        }
+        if (n_scored) n_scored[qq] = cnt;
+        farm_oracle_topk(n, full, s.id, k, sel);
+        for (int32_t rr = 0; rr < k; ++rr) {
+            out_idx[(size_t)qq * k + rr] = sel[rr];
+            out_score[(size_t)qq * k + rr] = sel[rr] >= 0 ? full[sel[rr]] : -INFINITY;
+            for (int e = 0; e < ORACLE_MAX_REL; ++e) {
+                double tv = 0.0;
+                uint32_t b = ORACLE_NO_ID;
+                if (sel[rr] >= 0 && e < r) relation_term(&s, &qs, e, sel[rr], &tv, &b);
+                if (out_terms) out_terms[((size_t)qq * k + rr) * ORACLE_MAX_REL + e] = tv;
+                if (out_anchor_id) out_anchor_id[((size_t)qq * k + rr) * ORACLE_MAX_REL + e] = b;
+            }
+        }
+        free(full); free(lower); free(sel);
+        query_free(&qs);
+    }
+    scene_free(&s);
+    return err;
+}

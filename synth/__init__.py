@@ -1,0 +1,253 @@
+"""Seeded synthetic scenes and query batches for the relational retrieval path.
+
+This module only draws random inputs. It holds none of the scoring arithmetic
+(no similarity, no predicate, no composite): both the CPU oracle and the GPU
+path consume what it produces, and neither imports the other.
+
+A scene stands in for the object-level memory of the paper (Section 2.2,
+"Representation"): per object a retrieval descriptor, a 3-D axis-aligned box
+(center, full extents), a unique object id, a category id, and one viewer frame
+per scene (the right-pointing unit vector of a virtual viewer in the ground
+plane). A query batch stands in for the parsed query graph (Section 2.3,
+"Executable query specification"): a target embedding, a target class and an
+ordered list of (predicate, anchor embedding) relations, stored in CSR form.
+
+The paper's benchmarks (ReferIt3D/ScanNet, IRef-VLA/HM3D, FARM-Scenes) are not
+available; the configurations below replace them with synthetic scenes whose
+extents echo the paper's scene-scale range (a room, a two-floor office, a
+15,000 m^2 outdoor/indoor site, cf. the FARM-Scenes data card).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+# Predicate ids, in the order the C ABI uses.
+NEAR, ABOVE, BELOW, LEFT_OF, RIGHT_OF = 0, 1, 2, 3, 4
+PRED_NAMES = ("near", "above", "below", "left_of", "right_of")
+NUM_PRED = 5
+
+
+@dataclasses.dataclass
+class Scene:
+    desc: np.ndarray        # [n, d] float32, unnormalised rows
+    center: np.ndarray      # [n, 3] float32, metres, z up
+    extent: np.ndarray      # [n, 3] float32, full side lengths (> 0)
+    ids: np.ndarray         # [n] uint32, unique, never 0xFFFFFFFF
+    cls: np.ndarray         # [n] int32, category id (>= 0)
+    view_right: np.ndarray  # [2] float32, viewer right vector (x, y)
+    centroids: np.ndarray   # [C, d] float32, category centroids (unit rows)
+
+    @property
+    def n(self) -> int:
+        return int(self.desc.shape[0])
+
+    @property
+    def d(self) -> int:
+        return int(self.desc.shape[1])
+
+
+@dataclasses.dataclass
+class QueryBatch:
+    target: np.ndarray      # [q, d] float32
+    target_cls: np.ndarray  # [q] int32 (-1 = no class)
+    rel_off: np.ndarray     # [q + 1] int32, CSR offsets into the relation arrays
+    rel_pred: np.ndarray    # [r_tot] int32 predicate ids
+    rel_anchor: np.ndarray  # [r_tot, d] float32
+    planted: np.ndarray     # [q] int64 index of the object the query was drawn from (diagnostic only)
+
+    @property
+    def q(self) -> int:
+        return int(self.target.shape[0])
+
+    @property
+    def r_tot(self) -> int:
+        return int(self.rel_pred.shape[0])
+
+    def subset(self, rows) -> "QueryBatch":
+        rows = np.asarray(rows, dtype=np.int64)
+        offs, preds, anchors = [0], [], []
+        for r in rows:
+            a, b = int(self.rel_off[r]), int(self.rel_off[r + 1])
+            preds.append(self.rel_pred[a:b])
+            anchors.append(self.rel_anchor[a:b])
+            offs.append(offs[-1] + (b - a))
+        d = self.target.shape[1]
+        return QueryBatch(
+            target=np.ascontiguousarray(self.target[rows]),
+            target_cls=np.ascontiguousarray(self.target_cls[rows]),
+            rel_off=np.asarray(offs, dtype=np.int32),
+            rel_pred=np.ascontiguousarray(np.concatenate(preds) if preds else np.zeros(0, np.int32)).astype(np.int32),
+            rel_anchor=np.ascontiguousarray(np.concatenate(anchors) if anchors else np.zeros((0, d), np.float32)).astype(np.float32),
+            planted=np.ascontiguousarray(self.planted[rows]),
+        )
+
+
+@dataclasses.dataclass(frozen=True)
+class Config:
+    name: str
+    seed: int
+    n: int
+    d: int
+    n_cat: int
+    noise: float            # descriptor noise norm (per-component std = noise / sqrt(d))
+    layout: str             # "uniform_room" | "rooms_two_floor" | "site_mix"
+    q: int
+    r_min: int
+    r_max: int
+    k: int = 10
+
+
+TINY = Config("tiny", 0, 64, 512, 16, 0.15, "uniform_room", 8, 2, 2)
+MID = Config("mid", 1, 2000, 1024, 200, 0.10, "rooms_two_floor", 256, 1, 3)
+PRECISION = Config("precision", 2, 20000, 1152, 500, 0.10, "site_mix", 4096, 1, 4)
+CONFIGS = {c.name: c for c in (TINY, MID, PRECISION)}
+
+
+def _unit_rows(x: np.ndarray) -> np.ndarray:
+    return x / np.linalg.norm(x, axis=1, keepdims=True)
+
+
+def _noisy(rng: np.random.Generator, base: np.ndarray, noise: float) -> np.ndarray:
+    d = base.shape[-1]
+    eps = rng.standard_normal(base.shape) * (noise / math.sqrt(d))
+    return _unit_rows(np.atleast_2d(base + eps))
+
+
+def _centers(rng: np.random.Generator, n: int, layout: str) -> np.ndarray:
+    if layout == "uniform_room":
+        return rng.uniform([0.0, 0.0, 0.0], [10.0, 10.0, 3.0], size=(n, 3))
+    if layout == "rooms_two_floor":
+        n_rooms = 20
+        room_xy = rng.uniform(0.0, 60.0, size=(n_rooms, 2))
+        room_base = rng.choice([0.0, 3.0], size=n_rooms)
+        room = rng.integers(0, n_rooms, size=n)
+        xy = room_xy[room] + rng.normal(0.0, 2.0, size=(n, 2))
+        z = room_base[room] + rng.uniform(0.0, 3.0, size=n)
+        return np.column_stack([xy, z])
+    if layout == "site_mix":
+        # Half indoor (40 rooms on three floors spanning 0-10 m), half outdoor
+        # (uniform over the 150 x 100 m footprint, objects up to 2 m high).
+        n_in = n // 2
+        n_out = n - n_in
+        n_rooms = 40
+        floor_h = 10.0 / 3.0
+        room_xy = rng.uniform([0.0, 0.0], [150.0, 100.0], size=(n_rooms, 2))
+        room_base = rng.integers(0, 3, size=n_rooms) * floor_h
+        room = rng.integers(0, n_rooms, size=n_in)
+        xy_in = room_xy[room] + rng.normal(0.0, 2.0, size=(n_in, 2))
+        z_in = room_base[room] + rng.uniform(0.0, floor_h, size=n_in)
+        xy_out = rng.uniform([0.0, 0.0], [150.0, 100.0], size=(n_out, 2))
+        z_out = rng.uniform(0.0, 2.0, size=n_out)
+        c = np.concatenate([np.column_stack([xy_in, z_in]), np.column_stack([xy_out, z_out])])
+        return c[rng.permutation(n)]
+    raise ValueError(f"unknown layout {layout!r}")
+
+
+def make_scene(cfg: Config, seed: int | None = None, n: int | None = None) -> Scene:
+    """Draw one scene. ``seed``/``n`` override the config's values."""
+    seed = cfg.seed if seed is None else seed
+    n = cfg.n if n is None else n
+    rng = np.random.default_rng([seed, 0x5CE9E])
+    centroids = _unit_rows(rng.standard_normal((cfg.n_cat, cfg.d)))
+    cls = rng.integers(0, cfg.n_cat, size=n).astype(np.int32)
+    desc = _noisy(rng, centroids[cls], cfg.noise) if n else np.zeros((0, cfg.d))
+    center = _centers(rng, n, cfg.layout)
+    extent = np.exp(rng.uniform(math.log(0.1), math.log(2.0), size=(n, 3)))
+    # Object ids are unique but unrelated to the storage order, so that the
+    # id tie-break is exercised independently of the index order.
+    ids = (rng.choice(16 * max(n, 1), size=n, replace=False) + 1).astype(np.uint32)
+    yaw = rng.uniform(0.0, 2.0 * math.pi)
+    view_right = np.array([math.sin(yaw), -math.cos(yaw)], dtype=np.float32)
+    return Scene(
+        desc=np.ascontiguousarray(desc, dtype=np.float32),
+        center=np.ascontiguousarray(center, dtype=np.float32),
+        extent=np.ascontiguousarray(extent, dtype=np.float32),
+        ids=ids,
+        cls=cls,
+        view_right=view_right,
+        centroids=centroids.astype(np.float32),
+    )
+
+
+def _plant_anchor(rng, scene: Scene, o: int, pred: int, c64: np.ndarray, r64: np.ndarray) -> int:
+    """Pick the anchor object for a planted relation by a geometric rule.
+
+    The rule only decides which object the query talks about (the nearest
+    object lying clearly on the named side of the target); it is not the
+    predicate's soft score, which the scorers compute.
+    """
+    d = c64 - c64[o]
+    dist = np.sqrt((d * d).sum(axis=1))
+    dist[o] = np.inf
+    if pred == NEAR:
+        ok = np.isfinite(dist)
+    elif pred in (ABOVE, BELOW):
+        # Target above the anchor: anchor lies at least 0.3 m lower.
+        side = -d[:, 2] if pred == ABOVE else d[:, 2]
+        ok = side > 0.3
+    else:
+        lateral = -(d[:, 0] * r64[0] + d[:, 1] * r64[1])  # (target - anchor) . right
+        side = lateral if pred == RIGHT_OF else -lateral
+        ok = side > 0.3
+    ok &= np.isfinite(dist)
+    if not ok.any():
+        return -1
+    cand = np.flatnonzero(ok)
+    return int(cand[np.argmin(dist[cand])])
+
+
+def make_queries(cfg: Config, scene: Scene, seed: int | None = None, q: int | None = None,
+                 r_min: int | None = None, r_max: int | None = None,
+                 with_class: bool = True) -> QueryBatch:
+    """Draw a query batch against ``scene``.
+
+    Each query picks a planted target object, uses a noisy copy of its category
+    centroid as the target embedding, and draws R relations; each relation has
+    a uniformly drawn predicate and the anchor embedding of a noisy centroid of
+    a geometrically suitable anchor object's category.
+    """
+    seed = cfg.seed if seed is None else seed
+    q = cfg.q if q is None else q
+    r_min = cfg.r_min if r_min is None else r_min
+    r_max = cfg.r_max if r_max is None else r_max
+    rng = np.random.default_rng([seed, 0x9E27])
+    n, d = scene.n, scene.d
+    c64 = scene.center.astype(np.float64)
+    r64 = scene.view_right.astype(np.float64)
+    targets, tcls, offs, preds, anchors, planted = [], [], [0], [], [], []
+    for _ in range(q):
+        o = int(rng.integers(0, n))
+        k = int(scene.cls[o])
+        targets.append(_noisy(rng, scene.centroids[k][None].astype(np.float64), cfg.noise)[0])
+        tcls.append(k if with_class else -1)
+        planted.append(o)
+        r = int(rng.integers(r_min, r_max + 1))
+        for _ in range(r):
+            for _attempt in range(16):
+                p = int(rng.integers(0, NUM_PRED))
+                j = _plant_anchor(rng, scene, o, p, c64, r64) if n > 1 else -1
+                if j >= 0:
+                    break
+            if j < 0:  # degenerate scene: any object's category
+                j = int(rng.integers(0, n))
+            preds.append(p)
+            anchors.append(_noisy(rng, scene.centroids[int(scene.cls[j])][None].astype(np.float64), cfg.noise)[0])
+        offs.append(len(preds))
+    return QueryBatch(
+        target=np.ascontiguousarray(np.asarray(targets, dtype=np.float32).reshape(q, d)),
+        target_cls=np.asarray(tcls, dtype=np.int32),
+        rel_off=np.asarray(offs, dtype=np.int32),
+        rel_pred=np.asarray(preds, dtype=np.int32),
+        rel_anchor=np.ascontiguousarray(np.asarray(anchors, dtype=np.float32).reshape(len(preds), d)),
+        planted=np.asarray(planted, dtype=np.int64),
+    )
+
+
+def make_workload(name: str, **kw):
+    cfg = CONFIGS[name]
+    scene = make_scene(cfg, n=kw.pop("n", None), seed=kw.pop("scene_seed", None))
+    queries = make_queries(cfg, scene, **kw)
+    return cfg, scene, queries

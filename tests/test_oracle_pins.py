@@ -1,0 +1,271 @@
+"""Pins for the FP64 oracle against facts the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed-form
+predicate values, hand-built scenes with known winners and closed-form scores,
+a brute-force joint-binding enumeration (pre-decomposition definition),
+library routines for the special case R = 0, and invariants of the method
+(bounds of the soft blend, duality/antisymmetry of predicates, permutation and
+relation-order invariance).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.brute import brute_scores
+from synth import (ABOVE, BELOW, LEFT_OF, NEAR, RIGHT_OF, CONFIGS, QueryBatch, Scene,
+                   make_queries, make_scene)
+from tests import _golden
+
+LN3_TENTH = 0.1 * math.log(3.0)
+
+
+# ---------------------------------------------------------------- predicates
+def test_near_closed_form():
+    r = [1.0, 0.0]
+    assert oracle.predicate(NEAR, [0, 0, 0], [0, 0, 0], r) == 1.0
+    # |D| = 0.5 m = sigma  ->  exp(-1/2)
+    assert oracle.predicate(NEAR, [0, 0, 0], [0.5, 0, 0], r) == pytest.approx(math.exp(-0.5), rel=1e-15)
+    assert oracle.predicate(NEAR, [1, 2, 3], [1, 2, 4], r) == pytest.approx(math.exp(-2.0), rel=1e-15)
+    # symmetric
+    a, b = [0.3, -1.2, 2.0], [1.1, 0.4, 1.5]
+    assert oracle.predicate(NEAR, a, b, r) == oracle.predicate(NEAR, b, a, r)
+
+
+def test_above_below_closed_form_and_duality():
+    r = [1.0, 0.0]
+    assert oracle.predicate(ABOVE, [0, 0, 0], [0, 0, 0], r) == 0.5
+    # target 0.1 ln 3 above the anchor: sig(ln 3) = 3/4
+    assert oracle.predicate(ABOVE, [0, 0, 0], [0, 0, -LN3_TENTH], r) == pytest.approx(0.75, abs=2e-8)
+    assert oracle.predicate(BELOW, [0, 0, 0], [0, 0, -LN3_TENTH], r) == pytest.approx(0.25, abs=2e-8)
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        a, b = rng.uniform(-3, 3, 3), rng.uniform(-3, 3, 3)
+        up = oracle.predicate(ABOVE, a, b, r)
+        dn = oracle.predicate(BELOW, a, b, r)
+        assert up + dn == pytest.approx(1.0, abs=1e-15)
+        assert dn == pytest.approx(oracle.predicate(ABOVE, b, a, r), abs=1e-15)
+        # no horizontal gate: moving the anchor sideways changes nothing
+        b2 = np.array(b, dtype=np.float32).copy()
+        b2[:2] += np.float32(7.0)
+        assert oracle.predicate(ABOVE, a, b2, r) == pytest.approx(up, abs=1e-6)
+
+
+def test_left_right_antisymmetry_and_viewer():
+    rng = np.random.default_rng(4)
+    for _ in range(50):
+        yaw = rng.uniform(0, 2 * math.pi)
+        r = np.array([math.sin(yaw), -math.cos(yaw)], np.float32)
+        a, b = rng.uniform(-5, 5, 3).astype(np.float32), rng.uniform(-5, 5, 3).astype(np.float32)
+        lt = oracle.predicate(LEFT_OF, a, b, r)
+        rt = oracle.predicate(RIGHT_OF, a, b, r)
+        assert lt + rt == pytest.approx(1.0, abs=1e-15)
+        assert lt == pytest.approx(oracle.predicate(RIGHT_OF, b, a, r), abs=1e-15)
+        # turning the viewer around swaps left and right
+        assert oracle.predicate(LEFT_OF, a, b, -r) == pytest.approx(rt, abs=1e-15)
+        # height plays no part
+        a2 = a.copy()
+        a2[2] += 3.0
+        assert oracle.predicate(RIGHT_OF, a2, b, r) == pytest.approx(rt, abs=1e-15)
+    # closed form: target 0.1 ln 3 along the right vector
+    r = np.array([0.0, -1.0], np.float32)
+    assert oracle.predicate(RIGHT_OF, [0, -LN3_TENTH, 0], [0, 0, 0], r) == pytest.approx(0.75, abs=2e-8)
+
+
+def test_left_right_translation_invariant():
+    rng = np.random.default_rng(5)
+    r = np.array([0.6, 0.8], np.float32)
+    for _ in range(20):
+        a, b = rng.uniform(-2, 2, 3), rng.uniform(-2, 2, 3)
+        sh = rng.uniform(-2, 2, 3)
+        v0 = oracle.predicate(RIGHT_OF, a, b, r)
+        v1 = oracle.predicate(RIGHT_OF, np.float64(a) + sh, np.float64(b) + sh, r)
+        assert v1 == pytest.approx(v0, abs=1e-6)
+
+
+# ---------------------------------------------------------------- hand scenes
+@pytest.mark.parametrize("path", _golden.all_paths(), ids=lambda p: p.rsplit("/", 1)[-1])
+def test_golden_scenes(path):
+    g, scene, queries = _golden.load(path)
+    for qb, spec in queries:
+        s, sem, t, b = oracle.score(scene, qb, terms=True)
+        order = oracle.topk(s[0], scene.ids, scene.n)
+        assert [int(scene.ids[i]) for i in order] == spec["expect_order"]
+        for sid, expr in spec["expect_score"].items():
+            i = int(np.flatnonzero(scene.ids == int(sid))[0])
+            assert s[0, i] == pytest.approx(_golden.evaluate(expr), abs=1e-6), sid
+        for sid, anchors in spec.get("expect_anchor", {}).items():
+            i = int(np.flatnonzero(scene.ids == int(sid))[0])
+            assert [int(x) for x in b[:, i]] == anchors, sid
+
+
+@pytest.mark.parametrize("path", _golden.all_paths(), ids=lambda p: p.rsplit("/", 1)[-1])
+def test_golden_scenes_brute_force(path):
+    """The independent joint-binding enumeration reaches the same closed forms."""
+    g, scene, queries = _golden.load(path)
+    for qb, spec in queries:
+        bs = brute_scores(scene, qb)[0]
+        for sid, expr in spec["expect_score"].items():
+            i = int(np.flatnonzero(scene.ids == int(sid))[0])
+            assert bs[i] == pytest.approx(_golden.evaluate(expr), abs=1e-6), sid
+
+
+# ---------------------------------------------------------------- brute force
+def _tiny(seed, n, r, q=3, d=6, n_cat=3):
+    cfg = CONFIGS["tiny"]
+    rng = np.random.default_rng(seed)
+    cent = rng.standard_normal((n_cat, d))
+    cent /= np.linalg.norm(cent, axis=1, keepdims=True)
+    cls = rng.integers(0, n_cat, n).astype(np.int32)
+    desc = cent[cls] + 0.4 * rng.standard_normal((n, d))
+    scene = Scene(desc=desc.astype(np.float32), center=rng.uniform(0, 2, (n, 3)).astype(np.float32),
+                  extent=np.ones((n, 3), np.float32), ids=rng.permutation(100)[:n].astype(np.uint32) + 1,
+                  cls=cls, view_right=np.array([math.cos(seed), math.sin(seed)], np.float32),
+                  centroids=cent.astype(np.float32))
+    offs = [0]
+    preds = []
+    for _ in range(q):
+        for _ in range(r):
+            preds.append(int(rng.integers(0, 5)))
+        offs.append(len(preds))
+    qb = QueryBatch(target=rng.standard_normal((q, d)).astype(np.float32),
+                    target_cls=rng.integers(-1, n_cat, q).astype(np.int32),
+                    rel_off=np.asarray(offs, np.int32), rel_pred=np.asarray(preds, np.int32),
+                    rel_anchor=rng.standard_normal((len(preds), d)).astype(np.float32),
+                    planted=np.zeros(q, np.int64))
+    return scene, qb
+
+
+@pytest.mark.parametrize("n,r", [(1, 1), (2, 1), (2, 2), (5, 0), (5, 1), (6, 2), (7, 3), (9, 2)])
+def test_star_decomposition_equals_joint_enumeration(n, r):
+    for seed in range(3):
+        scene, qb = _tiny(seed * 31 + n * 7 + r, n, r)
+        s = oracle.score(scene, qb)
+        bs = np.asarray(brute_scores(scene, qb))
+        np.testing.assert_allclose(s, bs, rtol=1e-12, atol=1e-14)
+
+
+# ---------------------------------------------------------------- invariants
+@pytest.fixture(scope="module")
+def small_world():
+    cfg = CONFIGS["mid"]
+    scene = make_scene(cfg, n=120, seed=11)
+    qb = make_queries(cfg, scene, seed=12, q=12, r_min=0, r_max=4)
+    s, sem, t, b = oracle.score(scene, qb, terms=True)
+    return scene, qb, s, sem, t, b
+
+
+def test_r0_equals_class_weighted_clamped_cosine(small_world):
+    scene, qb, s, sem, t, b = small_world
+    u = scene.desc.astype(np.float64)
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    for k in range(qb.q):
+        v = qb.target[k].astype(np.float64)
+        v /= np.linalg.norm(v)
+        cos = np.maximum(u @ v, 0.0)
+        kappa = np.where((qb.target_cls[k] >= 0) & (scene.cls != qb.target_cls[k]), 0.3, 1.0)
+        np.testing.assert_allclose(sem[k], kappa * cos, rtol=1e-12, atol=1e-15)
+        if qb.rel_off[k + 1] == qb.rel_off[k]:
+            np.testing.assert_allclose(s[k], sem[k], rtol=0, atol=0)
+
+
+def test_soft_blend_bounds(small_world):
+    """The spatial factor stays in [1 - w, 1] ('Why soft, not hard?')."""
+    scene, qb, s, sem, t, b = small_world
+    assert np.all(s <= sem * (1 + 1e-15))
+    assert np.all(s >= 0.5 * sem * (1 - 1e-15))
+    assert np.all((t >= 0) & (t <= 1))
+
+
+def test_relation_terms_compose(small_world):
+    scene, qb, s, sem, t, b = small_world
+    for k in range(qb.q):
+        a0, a1 = qb.rel_off[k], qb.rel_off[k + 1]
+        if a1 == a0:
+            continue
+        g = np.exp(np.mean(np.log(np.maximum(t[a0:a1], 1e-300)), axis=0))
+        g = np.where(np.any(t[a0:a1] == 0, axis=0), 0.0, g)
+        np.testing.assert_allclose(s[k], sem[k] * (0.5 + 0.5 * g), rtol=1e-12, atol=1e-300)
+
+
+def test_bound_anchor_attains_term(small_world):
+    scene, qb, s, sem, t, b = small_world
+    u = scene.desc.astype(np.float64)
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    id2idx = {int(x): i for i, x in enumerate(scene.ids)}
+    for rr in range(qb.r_tot):
+        v = qb.rel_anchor[rr].astype(np.float64)
+        v /= np.linalg.norm(v)
+        a = np.maximum(u @ v, 0.0)
+        for i in range(0, scene.n, 17):
+            j = id2idx[int(b[rr, i])]
+            assert j != i
+            val = a[j] * oracle.predicate(int(qb.rel_pred[rr]), scene.center[i], scene.center[j], scene.view_right)
+            assert val == pytest.approx(t[rr, i], rel=1e-12, abs=1e-300)
+
+
+def test_object_permutation_invariance(small_world):
+    scene, qb, s, sem, t, b = small_world
+    perm = np.random.default_rng(0).permutation(scene.n)
+    sp = Scene(desc=scene.desc[perm], center=scene.center[perm], extent=scene.extent[perm],
+               ids=scene.ids[perm], cls=scene.cls[perm], view_right=scene.view_right, centroids=scene.centroids)
+    s2 = oracle.score(sp, qb)
+    np.testing.assert_allclose(s2, s[:, perm], rtol=1e-12, atol=1e-300)
+    for k in range(qb.q):
+        o1 = scene.ids[oracle.topk(s[k], scene.ids, 10)]
+        o2 = sp.ids[oracle.topk(s2[k], sp.ids, 10)]
+        assert list(o1) == list(o2)
+
+
+def test_relation_order_invariance(small_world):
+    scene, qb, s, sem, t, b = small_world
+    rng = np.random.default_rng(1)
+    preds, anchors = [], []
+    for k in range(qb.q):
+        a0, a1 = qb.rel_off[k], qb.rel_off[k + 1]
+        p = rng.permutation(a1 - a0) + a0
+        preds.append(qb.rel_pred[p])
+        anchors.append(qb.rel_anchor[p])
+    qb2 = QueryBatch(target=qb.target, target_cls=qb.target_cls, rel_off=qb.rel_off,
+                     rel_pred=np.concatenate(preds).astype(np.int32),
+                     rel_anchor=np.concatenate(anchors).astype(np.float32), planted=qb.planted)
+    np.testing.assert_allclose(oracle.score(scene, qb2), s, rtol=1e-12, atol=1e-300)
+
+
+def test_no_class_gives_pure_cosine(small_world):
+    scene, qb, s, sem, t, b = small_world
+    qb2 = QueryBatch(target=qb.target, target_cls=np.full(qb.q, -1, np.int32), rel_off=qb.rel_off,
+                     rel_pred=qb.rel_pred, rel_anchor=qb.rel_anchor, planted=qb.planted)
+    _, sem2, _, _ = oracle.score(scene, qb2, terms=True)
+    assert np.all(sem2 >= sem - 1e-15)
+    mism = (qb.target_cls[:, None] != scene.cls[None, :])
+    np.testing.assert_allclose(sem[mism], 0.3 * sem2[mism], rtol=1e-12, atol=1e-300)
+
+
+# ---------------------------------------------------------------- TopK
+def test_topk_matches_lexsort():
+    rng = np.random.default_rng(9)
+    for n in (1, 5, 37, 300):
+        ids = (rng.permutation(10 * n)[:n] + 1).astype(np.uint32)
+        sc = np.round(rng.uniform(0, 1, n), 2)  # many exact ties
+        for k in (1, 3, 10, n + 4):
+            got = oracle.topk(sc, ids, k)
+            want = np.lexsort((ids, -sc))[:k]
+            assert list(got[: min(k, n)]) == list(want)
+            assert np.all(got[min(k, n):] == -1)
+
+
+def test_bounded_topk_equals_full_topk(small_world):
+    scene, qb, s, sem, t, b = small_world
+    idx, sc, tt, bb, ns = oracle.topk_bounded(scene, qb, 10)
+    for k in range(qb.q):
+        want = oracle.topk(s[k], scene.ids, 10)
+        assert list(idx[k]) == list(want)
+        np.testing.assert_allclose(sc[k], s[k, want], rtol=1e-15)
+        assert ns[k] <= scene.n
+    # pairs entry point agrees with the full scores
+    qsel = np.repeat(np.arange(qb.q), 5).astype(np.int32)
+    osel = np.tile(np.arange(0, scene.n, scene.n // 5)[:5], qb.q).astype(np.int64)
+    ps, psem, pt, pb = oracle.score_pairs(scene, qb, qsel, osel)
+    np.testing.assert_allclose(ps, s[qsel, osel], rtol=1e-15)
