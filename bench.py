@@ -1,0 +1,197 @@
+"""Benchmark of the relational retrieval hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload precision] [--form f32]
+                    [--no-cpu-baseline]
+
+One step = one pass of the whole hot path over one batch resident in HBM:
+query normalisation, similarity GEMM, relational pass (relation terms +
+composite), TopK and the ScoredCandidate breakdown of the winners
+(farm_query_topk), for the 4,096-query batch of the N = 20,000 scene.  The
+scene is built once (farm_build_memory) outside the timed region.
+
+Prints ONE JSON line with the throughput (queries/s), batch latency
+percentiles, the roofline of the dominant kernel (timed live with the
+library's HIP-event phase timer on the launch stream) and the CPU oracle
+timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Published MI355X peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_MFMA_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
+
+# Algorithmic floating-point operations of one (target, anchor) evaluation,
+# counted on the definition (offsets, squares/products, scaling by 1/tau or
+# 1/(2 sigma^2), exp, 1 + e, reciprocal, times the anchor similarity, max);
+# a transcendental counts as one operation.
+FLOP_PER_PAIR = {0: 12, 1: 7, 2: 7, 3: 11, 4: 11}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--workload", default="precision")
+    p.add_argument("--form", default="f32", choices=["f32"])
+    p.add_argument("--k", type=int, default=10)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-sample", type=int, default=0, help="queries in the CPU-oracle sample (0 = auto)")
+    return p.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU layout is design-only "
+              "in this build.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2606_15476_amd as farm
+    from synth import CONFIGS, make_queries, make_scene
+
+    cfg = CONFIGS[args.workload]
+    t0 = time.time()
+    scene = make_scene(cfg)
+    qb = make_queries(cfg, scene)
+    log(f"[bench] generated {cfg.name}: n={scene.n} d={scene.d} q={qb.q} R={qb.r_tot} in {time.time() - t0:.1f}s")
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    mem = farm.Memory(t(scene.desc), t(scene.center), t(scene.extent), t(scene.ids.view(np.int32)), t(scene.cls),
+                      scene.view_right)
+    ws = farm.Workspace(mem, qb.q, qb.r_tot, 64)
+    target, anchors = t(qb.target), t(qb.rel_anchor)
+    k = args.k
+    oid = torch.empty((qb.q, k), dtype=torch.int32, device=dev)
+    osc = torch.empty((qb.q, k), dtype=torch.float32, device=dev)
+    ot = torch.empty((qb.q, k, 8), dtype=torch.float32, device=dev)
+    ob = torch.empty((qb.q, k, 8), dtype=torch.int32, device=dev)
+    dtype = {"f32": farm.F32}[args.form]
+
+    def step():
+        farm.query_topk(mem, ws, target, qb.target_cls, qb.rel_off, qb.rel_pred, anchors, k, oid, osc, ot, ob,
+                        dtype=dtype)
+
+    for w in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {w + 1}/{args.warmup} done")
+    ws.status()
+    ws.set_timing(True)
+    ws.timings(reset=True)
+    torch.cuda.synchronize()
+    times = []
+    t_start = time.perf_counter()
+    for s in range(args.steps):
+        a = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - a)
+        log(f"[bench] step {s + 1}/{args.steps}: {times[-1] * 1e3:.2f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    phases = ws.timings(reset=True)
+    ws.set_timing(False)
+    ws.status()
+
+    qps = qb.q * args.steps / elapsed
+    ms_step = elapsed / args.steps * 1e3
+    # dominant kernel: the relational pass
+    pair_ms, pair_n = phases["pair"]
+    gemm_ms, gemm_n = phases["gemm"]
+    dominant = "pair" if pair_ms >= gemm_ms else "gemm"
+    n = scene.n
+    pairs_per_launch = float(qb.r_tot) * n * (n - 1)
+    flop_pair = sum(FLOP_PER_PAIR[int(p)] for p in qb.rel_pred) * float(n) * (n - 1)
+    if dominant == "pair":
+        avg_s = pair_ms / max(pair_n, 1) / 1e3
+        achieved = flop_pair / avg_s / 1e12
+        roofline = {"bound": "alu", "kernel": "k_pair_exhaustive", "achieved": round(achieved, 3),
+                    "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
+                    "traffic": None, "pair_evals_per_launch": pairs_per_launch,
+                    "avg_launch_ms": round(avg_s * 1e3, 3)}
+    else:
+        avg_s = gemm_ms / max(gemm_n, 1) / 1e3
+        flop = 2.0 * (qb.q + qb.r_tot) * n * scene.d
+        achieved = flop / avg_s / 1e12
+        peak = PEAK_MFMA_TFLOPS[args.form]
+        roofline = {"bound": "mfma", "kernel": "k_sim_gemm_" + args.form, "achieved": round(achieved, 2),
+                    "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                    "avg_launch_ms": round(avg_s * 1e3, 3)}
+    phase_ms = {p: round(v[0] / max(v[1], 1), 3) for p, v in phases.items() if v[1]}
+
+    cpu = None
+    recall = None
+    if not args.no_cpu_baseline:
+        cpu, recall = cpu_baseline(scene, qb, oid, osc, k, args.cpu_sample)
+
+    lat = np.asarray(times) * 1e3
+    out = {
+        "metric": "queries/s at N=20k objects, K=10",
+        "value": round(qps, 2),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded scene generator; the paper's datasets are not used)",
+        "config": {"workload": f"{cfg.name}: N={scene.n} objects, D={scene.d}, Q={qb.q} queries, "
+                               f"R~U{{{cfg.r_min}..{cfg.r_max}}} (R_tot={qb.r_tot}), K={k}, exhaustive FP32",
+                   "form": args.form, "global_batch": qb.q, "parallelism": "none (1 GPU)"},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
+                       "what": "whole-batch latency of one step"},
+        "phase_ms": phase_ms,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "recall_at_10_vs_oracle": recall,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(scene, qb, oid, osc, k, sample):
+    """Time the FP64 oracle (plain exhaustive scoring + TopK) on a sample of the batch."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    m = sample or max(4, min(16, threads))
+    sub = qb.subset(range(m))
+    oracle._load()
+    log(f"[bench] cpu baseline: oracle on {m} queries, {threads} threads")
+    a = time.perf_counter()
+    s64 = oracle.score(scene, sub)
+    order = [oracle.topk(s64[i], scene.ids, k) for i in range(m)]
+    secs = time.perf_counter() - a
+    ids = oid[:m].cpu().numpy().view(np.uint32)
+    hits = [len(set(int(x) for x in ids[i]) & set(int(x) for x in scene.ids[order[i]])) / k for i in range(m)]
+    log(f"[bench] cpu baseline: {secs:.1f}s, recall@{k} on the sample {np.mean(hits):.4f}")
+    return ({"value": round(m / secs, 4), "unit": "queries/s", "cores": min(threads, m), "kind": "oracle",
+             "sample": f"first {m} queries of the batch, full exhaustive FP64 scoring of all {scene.n} objects + TopK",
+             "seconds": round(secs, 2)},
+            {"value": float(np.mean(hits)), "queries": m, "what": "|TopK_gpu & TopK_oracle| / K on the CPU sample"})
+
+
+if __name__ == "__main__":
+    main()

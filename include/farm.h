@@ -1,0 +1,229 @@
+/*
+ * farm.h -- C ABI of libfarm, the MI355X (gfx950) library for FARM's
+ * query-time relational retrieval over an object-level spatial memory.
+ *
+ * The operation (paper, Section 2.3 "Robust Relational Object Retrieval";
+ * Appendix "Robust Relational Retrieval Formulation" and Appendix "Retrieval
+ * Details", steps 3-5 and 7):
+ *
+ *   memory   : n objects, each with a descriptor (d floats), a 3-D box
+ *              (center, full extents), a unique id and an optional class id;
+ *              one viewer frame per scene (its right vector in the x-y plane).
+ *   query    : a target embedding q_t, an optional target class, and R <= 8
+ *              relations (predicate p_r, anchor embedding q_r).
+ *   sim(i,v) = max(0, cos(desc_i, v))
+ *   s_sem(i) = kappa_i * sim(i, q_t)      kappa_i = 0.3 if both classes are
+ *                                          known (>= 0) and differ, else 1
+ *   t_r(i)   = max_{j != i} sim(j, q_r) * P_{p_r}(c_i, c_j)
+ *   b_r(i)   = id of the maximising anchor (smallest id on ties)
+ *   s(i)     = s_sem(i) * (0.5 + 0.5 * (prod_r t_r(i))^(1/R))   (1 if R = 0)
+ *   TopK     = first min(K, n) objects by (s desc, id asc)
+ *
+ *   predicates, D = c_i - c_j (target minus anchor box center), sig = logistic:
+ *   FARM_NEAR      exp(-|D|^2 / (2 * 0.5^2))
+ *   FARM_ABOVE     sig(D_z / 0.1)            FARM_BELOW    sig(-D_z / 0.1)
+ *   FARM_RIGHT_OF  sig((D_x r_x + D_y r_y) / 0.1)
+ *   FARM_LEFT_OF   sig(-(D_x r_x + D_y r_y) / 0.1)
+ *
+ * Conventions shared by every entry point:
+ *   - Every function returns a farm_status; farm_last_error() gives a message
+ *     for the calling thread's last failure.  Nothing aborts and no C++
+ *     exception crosses the ABI.
+ *   - "device" pointers are HIP device allocations on the current device;
+ *     "host" pointers are ordinary process memory.  All arrays are dense,
+ *     row-major, without padding.
+ *   - stream is a hipStream_t passed as void* (NULL = the default stream).
+ *     Calls are stream-ordered and return before the GPU work finishes,
+ *     except where stated.  Input pointers are borrowed for the duration of
+ *     the call's GPU work; output buffers are owned by the caller.
+ *   - Floating point is FP32 throughout the scoring path (no FP64 on the GPU).
+ */
+#ifndef FARM_H
+#define FARM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define FARM_API __attribute__((visibility("default")))
+#else
+#define FARM_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FARM_OK = 0,
+  FARM_ERR_INVALID_ARG = -1, /* bad pointer, size, predicate id, R > 8, K < 1,
+                                non-finite or zero-norm vector, duplicate id */
+  FARM_ERR_OOM = -2,         /* device allocation failed or exceeds a budget */
+  FARM_ERR_HIP = -3,         /* a HIP runtime call failed */
+  FARM_ERR_UNSUPPORTED = -4  /* valid request outside what this build serves */
+} farm_status;
+
+typedef enum { FARM_F32 = 0, FARM_BF16 = 1, FARM_FP8_E4M3 = 2 } farm_dtype;
+
+typedef enum { FARM_NEAR = 0, FARM_ABOVE = 1, FARM_BELOW = 2, FARM_LEFT_OF = 3, FARM_RIGHT_OF = 4 } farm_pred;
+
+#define FARM_MAX_REL 8          /* relations per query */
+#define FARM_MAX_K 1024         /* TopK size */
+#define FARM_NO_ID 0xFFFFFFFFu  /* padding id (reserved: never a valid object id) */
+
+/* build flags: which reduced-precision descriptor copies to keep */
+#define FARM_BUILD_BF16 0x1u
+#define FARM_BUILD_FP8 0x2u
+
+typedef struct farm_memory farm_memory;       /* device-resident scene, immutable once built */
+typedef struct farm_workspace farm_workspace; /* per-stream scratch for scoring calls */
+
+/*
+ * Build the device-resident memory of one scene (memory representation of
+ * Section 2.2: per-entity geometry and retrieval embedding; one viewer frame).
+ *   n            number of objects, 1 <= n < 2^31
+ *   d            descriptor width, 1 <= d <= 8192
+ *   desc         device [n][d] FP32 descriptors, any non-zero norm
+ *   center       device [n][3] FP32 box centers (metres, z up)
+ *   extent       device [n][3] FP32 full box side lengths, > 0
+ *   id           device [n] uint32 object ids, unique, != FARM_NO_ID
+ *   cls          device [n] int32 class ids (-1 = unknown) or NULL (all unknown)
+ *   view_right_x/y  the scene viewer's right vector in the ground plane
+ *   flags        FARM_BUILD_* bits
+ *   out          receives the handle
+ * The library copies everything it needs; the inputs can be freed afterwards.
+ * Synchronises `stream` to validate the inputs (finite values, non-zero
+ * norms, positive extents, unique ids): FARM_ERR_INVALID_ARG names the first
+ * violation.  Free with farm_free_memory.
+ */
+FARM_API farm_status farm_build_memory(int64_t n, int32_t d, const float* desc, const float* center,
+                              const float* extent, const uint32_t* id, const int32_t* cls,
+                              float view_right_x, float view_right_y, uint32_t flags, void* stream,
+                              farm_memory** out);
+
+/* Release a memory handle (synchronises the device first). NULL is a no-op. */
+FARM_API farm_status farm_free_memory(farm_memory* mem);
+
+/* n, d and the device bytes the handle holds (any out pointer may be NULL). */
+FARM_API farm_status farm_memory_info(const farm_memory* mem, int64_t* n, int32_t* d, size_t* bytes);
+
+/*
+ * Scratch for scoring calls on one memory: normalised query vectors, the
+ * similarity matrix, metadata staging and TopK candidate buffers, sized for up
+ * to max_q queries, max_rel relations (all queries together) and TopK size
+ * max_k (1..FARM_MAX_K; with reduced-precision rescoring the candidate count
+ * rescore_mult*k must fit too) per call.  A workspace serves one stream at a
+ * time: calls that share it must be ordered on one stream.  Allocates device
+ * memory and one pinned host staging block; free with farm_workspace_free.
+ */
+FARM_API farm_status farm_workspace_create(const farm_memory* mem, int32_t max_q, int32_t max_rel, int32_t max_k,
+                                  farm_workspace** out);
+FARM_API farm_status farm_workspace_free(farm_workspace* ws);
+FARM_API farm_status farm_workspace_bytes(const farm_workspace* ws, size_t* bytes);
+
+/* Projected device bytes of a workspace of this shape (for admission). */
+FARM_API farm_status farm_workspace_estimate(const farm_memory* mem, int32_t max_q, int32_t max_rel, int32_t max_k,
+                                    size_t* bytes);
+
+/*
+ * Score every (query, object) pair exhaustively (the plain method).
+ *   q, d         number of queries; d must equal the memory's d
+ *   target       device [q][d] FP32 target embeddings (any non-zero norm)
+ *   target_cls   host [q] int32 parsed target classes (-1 = none) or NULL
+ *   rel_off      host [q+1] int32 CSR offsets, rel_off[0] = 0, non-decreasing,
+ *                at most FARM_MAX_REL relations per query
+ *   rel_pred     host [rel_off[q]] int32 farm_pred values
+ *   rel_anchor   device [rel_off[q]][d] FP32 anchor embeddings
+ *   scores       device [q][n] FP32 out: s(i)
+ *   rel_terms    device [rel_off[q]][n] FP32 out: t_r(i), or NULL
+ *   rel_anchor_id device [rel_off[q]][n] uint32 out: b_r(i), or NULL
+ *                (FARM_NO_ID when n = 1)
+ * Host arguments are read before the call returns.  Device input vectors
+ * that are non-finite or have zero norm are reported by the next
+ * farm_workspace_status call; their rows' outputs are unspecified.
+ */
+FARM_API farm_status farm_score_query(const farm_memory* mem, farm_workspace* ws, int32_t q, int32_t d,
+                             const float* target, const int32_t* target_cls, const int32_t* rel_off,
+                             const int32_t* rel_pred, const float* rel_anchor, float* scores,
+                             float* rel_terms, uint32_t* rel_anchor_id, void* stream);
+
+/*
+ * TopK of precomputed score rows.
+ *   scores       device [q][n] FP32 (n = the memory's n; NaN not allowed)
+ *   k            1 <= k <= FARM_MAX_K; k > n returns n entries, then padding
+ *   out_id       device [q][k] uint32 ids (FARM_NO_ID padding)
+ *   out_score    device [q][k] FP32 scores (-INFINITY padding)
+ *   out_index    device [q][k] int32 object indices (-1 padding) or NULL
+ * Order: score descending, then id ascending.
+ */
+FARM_API farm_status farm_topk(const farm_memory* mem, farm_workspace* ws, const float* scores, int32_t q,
+                      int32_t k, uint32_t* out_id, float* out_score, int32_t* out_index, void* stream);
+
+/* Options of the fused path. */
+typedef struct {
+  int32_t dtype;        /* farm_dtype of the similarity GEMM (FARM_F32 = exact path) */
+  int32_t rescore_mult; /* reduced precision: rescore the top rescore_mult*k in FP32 (>= 1) */
+} farm_score_opts;
+
+/*
+ * Fused score + TopK, returning ScoredCandidate records (Appendix "Retrieval
+ * Details", output step: target, composite score, per-predicate breakdown,
+ * bound landmarks).
+ *   query arguments as in farm_score_query
+ *   opts         NULL = FP32 exact path
+ *   k            1 <= k <= FARM_MAX_K
+ *   out_id, out_score     device [q][k]
+ *   out_terms     device [q][k][FARM_MAX_REL] FP32 t_r of each returned
+ *                 object (0 beyond the query's R), or NULL
+ *   out_anchor_id device [q][k][FARM_MAX_REL] uint32 b_r (FARM_NO_ID beyond R),
+ *                 or NULL
+ * With a reduced-precision dtype the similarity GEMM runs in BF16 or FP8
+ * e4m3 (per-row scales) and the top rescore_mult*k candidates are rescored
+ * in FP32 before the final TopK; the memory must have been built with the
+ * matching FARM_BUILD_* flag.
+ */
+FARM_API farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t q, int32_t d,
+                            const float* target, const int32_t* target_cls, const int32_t* rel_off,
+                            const int32_t* rel_pred, const float* rel_anchor,
+                            const farm_score_opts* opts, int32_t k, uint32_t* out_id, float* out_score,
+                            float* out_terms, uint32_t* out_anchor_id, void* stream);
+
+/* Phases timed by the workspace's optional phase timer. */
+typedef enum {
+  FARM_PHASE_NORMALIZE = 0, /* query vector normalisation (and quantisation) */
+  FARM_PHASE_GEMM = 1,      /* similarity GEMM */
+  FARM_PHASE_PAIR = 2,      /* relational pass (relation terms + composite) */
+  FARM_PHASE_TOPK = 3,      /* TopK selection */
+  FARM_PHASE_RESCORE = 4,   /* reduced-precision candidates rescored in FP32 */
+  FARM_PHASE_EXPLAIN = 5,   /* ScoredCandidate breakdown of the winners */
+  FARM_PHASE_COUNT = 6
+} farm_phase;
+
+/*
+ * Phase timer: when enabled, every scoring call on this workspace brackets each
+ * phase with HIP events on its stream (a small serialisation cost).  Read the
+ * accumulated milliseconds and launch counts per phase with
+ * farm_workspace_timings (synchronises the events; resets when reset != 0).
+ *   ms     host [FARM_PHASE_COUNT] out, may be NULL
+ *   count  host [FARM_PHASE_COUNT] out, may be NULL
+ */
+FARM_API farm_status farm_workspace_set_timing(farm_workspace* ws, int32_t enable);
+FARM_API farm_status farm_workspace_timings(farm_workspace* ws, double* ms, int64_t* count, int32_t reset);
+
+/*
+ * Synchronise `stream` and report whether any scoring call since the last
+ * check saw an invalid device input vector (FARM_ERR_INVALID_ARG) -- then
+ * clear the flag.
+ */
+FARM_API farm_status farm_workspace_status(farm_workspace* ws, void* stream);
+
+/* Message for the calling thread's last failure ("" if none). */
+FARM_API const char* farm_last_error(void);
+
+/* Library version string. */
+FARM_API const char* farm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FARM_H */

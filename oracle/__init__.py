@@ -52,6 +52,8 @@ def _load():
                                                 i64, P, P, P, P, P, P]
         lib.farm_oracle_topk.restype = ctypes.c_int
         lib.farm_oracle_topk.argtypes = [i64, P, P, i32, P]
+        lib.farm_oracle_binding_value.restype = ctypes.c_double
+        lib.farm_oracle_binding_value.argtypes = [i64, ctypes.c_int, P, P, P, ctypes.c_int, P, i64, i64]
         lib.farm_oracle_topk_bounded.restype = ctypes.c_int
         lib.farm_oracle_topk_bounded.argtypes = [i64, ctypes.c_int, P, P, P, P, P, i32, P, P, P, P, P,
                                                  i32, P, P, P, P, P]
@@ -177,3 +179,14 @@ def topk_bounded(scene, qb, k: int):
         raise ValueError(f"oracle topk_bounded failed ({rc})")
     del k1, k2
     return idx, sc, t, b, ns
+
+
+def binding_value(scene, pred: int, anchor_vec, i: int, j: int) -> float:
+    """sim(j, q_r) * P_pred(i, j) in FP64 for one candidate binding."""
+    lib = _load()
+    desc, pd = _c(scene.desc, np.float32)
+    cen, pc = _c(scene.center, np.float32)
+    vr, pv = _c(scene.view_right, np.float32)
+    av, pa = _c(anchor_vec, np.float32)
+    return float(lib.farm_oracle_binding_value(int(desc.shape[0]), int(desc.shape[1]), pd, pc, pv, int(pred), pa,
+                                               int(i), int(j)))

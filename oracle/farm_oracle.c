@@ -401,3 +401,25 @@ int farm_oracle_topk_bounded(int64_t n, int d, const float* desc, const float* c
     scene_free(&s);
     return err;
 }
+
+/*
+ * Value of one binding: sim(j, q_r) * P_p(i, j) in FP64 -- used to check that
+ * an anchor chosen by another implementation attains the relation term.
+ */
+double farm_oracle_binding_value(int64_t n, int d, const float* desc, const float* center, const float* right,
+                                 int p, const float* anchor, int64_t i, int64_t j) {
+    if (i < 0 || j < 0 || i >= n || j >= n || p < 0 || p > 4) return NAN;
+    double* u = (double*)malloc(sizeof(double) * (size_t)d);
+    double* v = (double*)malloc(sizeof(double) * (size_t)d);
+    if (!u || !v) { free(u); free(v); return NAN; }
+    unit_vector(desc + (size_t)j * d, d, u);
+    unit_vector(anchor, d, v);
+    double a = clamped_cosine(u, v, d);
+    double ci[3] = {center[i * 3], center[i * 3 + 1], center[i * 3 + 2]};
+    double cj[3] = {center[j * 3], center[j * 3 + 1], center[j * 3 + 2]};
+    double r[2] = {right[0], right[1]};
+    double val = a * oracle_predicate(p, ci, cj, r);
+    free(u);
+    free(v);
+    return val;
+}

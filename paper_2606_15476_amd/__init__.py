@@ -1,0 +1,185 @@
+"""MI355X-native FARM query-time relational retrieval.
+
+Thin Python binding over libfarm.so (the C ABI declared in include/farm.h).
+Every step of the scoring path runs in the library's HIP kernels; this module
+only marshals arguments: torch CUDA tensors become device pointers, numpy
+arrays become host pointers, torch streams become hipStream_t handles.
+There is no CPU fallback: if the library is missing the import fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import _lib
+from ._lib import (FARM_BUILD_BF16, FARM_BUILD_FP8, FARM_MAX_K, FARM_MAX_REL, FARM_NO_ID, F32, BF16, FP8_E4M3,
+                   NEAR, ABOVE, BELOW, LEFT_OF, RIGHT_OF, FarmError, lib_path)
+
+__all__ = [
+    "Memory", "Workspace", "score_query", "topk", "query_topk", "workspace_estimate", "FarmError",
+    "FARM_BUILD_BF16", "FARM_BUILD_FP8", "FARM_MAX_K", "FARM_MAX_REL", "FARM_NO_ID", "F32", "BF16",
+    "FP8_E4M3", "NEAR", "ABOVE", "BELOW", "LEFT_OF", "RIGHT_OF", "lib_path",
+]
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device (cuda) tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _host_i32(a):
+    if a is None:
+        return None, None
+    arr = np.ascontiguousarray(np.asarray(a), dtype=np.int32)
+    return arr, arr.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    handle = getattr(stream, "cuda_stream", stream)
+    return ctypes.c_void_p(int(handle)) if handle else None
+
+
+class Memory:
+    """Device-resident scene (farm_build_memory)."""
+
+    def __init__(self, desc, center, extent, ids, cls, view_right, flags: int = 0, stream=None):
+        import torch
+        n, d = int(desc.shape[0]), int(desc.shape[1])
+        for name, t, dt in (("desc", desc, torch.float32), ("center", center, torch.float32),
+                            ("extent", extent, torch.float32)):
+            if t.dtype != dt:
+                raise ValueError(f"{name} must be {dt}")
+        if ids.dtype not in (torch.int32, getattr(torch, "uint32", torch.int32)):
+            raise ValueError("ids must be a 32-bit integer tensor (bit pattern of uint32)")
+        if cls is not None and cls.dtype != torch.int32:
+            raise ValueError("cls must be int32")
+        h = ctypes.c_void_p()
+        _lib.check(_lib.L.farm_build_memory(n, d, _ptr(desc), _ptr(center), _ptr(extent), _ptr(ids), _ptr(cls),
+                                            float(view_right[0]), float(view_right[1]), int(flags),
+                                            _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.n, self.d, self.flags = n, d, int(flags)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("memory was freed")
+        return self._h
+
+    @property
+    def bytes(self) -> int:
+        b = ctypes.c_size_t()
+        _lib.check(_lib.L.farm_memory_info(self.handle, None, None, ctypes.byref(b)))
+        return int(b.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.L.farm_free_memory(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Workspace:
+    """Per-stream scratch for scoring calls (farm_workspace_create)."""
+
+    def __init__(self, mem: Memory, max_q: int, max_rel: int, max_k: int = 64):
+        h = ctypes.c_void_p()
+        _lib.check(_lib.L.farm_workspace_create(mem.handle, int(max_q), int(max_rel), int(max_k), ctypes.byref(h)))
+        self._h = h
+        self.mem = mem
+        self.max_q, self.max_rel, self.max_k = int(max_q), int(max_rel), int(max_k)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("workspace was freed")
+        return self._h
+
+    @property
+    def bytes(self) -> int:
+        b = ctypes.c_size_t()
+        _lib.check(_lib.L.farm_workspace_bytes(self.handle, ctypes.byref(b)))
+        return int(b.value)
+
+    def set_timing(self, enable: bool = True):
+        """Enable the native per-phase HIP-event timer of this workspace."""
+        _lib.check(_lib.L.farm_workspace_set_timing(self.handle, 1 if enable else 0))
+
+    def timings(self, reset: bool = False) -> dict:
+        """{phase: (total_ms, launches)} accumulated by the phase timer."""
+        ms = (ctypes.c_double * len(_lib.PHASES))()
+        cnt = (ctypes.c_int64 * len(_lib.PHASES))()
+        _lib.check(_lib.L.farm_workspace_timings(self.handle, ms, cnt, 1 if reset else 0))
+        return {p: (float(ms[i]), int(cnt[i])) for i, p in enumerate(_lib.PHASES)}
+
+    def status(self, stream=None):
+        _lib.check(_lib.L.farm_workspace_status(self.handle, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.L.farm_workspace_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def workspace_estimate(mem: Memory, max_q: int, max_rel: int, max_k: int = 64) -> int:
+    b = ctypes.c_size_t()
+    _lib.check(_lib.L.farm_workspace_estimate(mem.handle, int(max_q), int(max_rel), int(max_k), ctypes.byref(b)))
+    return int(b.value)
+
+
+def score_query(mem: Memory, ws: Workspace, target, target_cls, rel_off, rel_pred, rel_anchor, scores,
+                rel_terms=None, rel_anchor_id=None, stream=None):
+    """farm_score_query: full score rows (and optional t_r, b_r) into caller tensors."""
+    tc, ptc = _host_i32(target_cls)
+    ro, pro = _host_i32(rel_off)
+    rp, prp = _host_i32(rel_pred)
+    q, d = int(target.shape[0]), int(target.shape[1])
+    _lib.check(_lib.L.farm_score_query(mem.handle, ws.handle, q, d, _ptr(target), ptc, pro, prp,
+                                       _ptr(rel_anchor) if rel_anchor is not None and rel_anchor.numel() else None,
+                                       _ptr(scores), _ptr(rel_terms), _ptr(rel_anchor_id), _stream(stream)))
+    del tc, ro, rp
+
+
+def topk(mem: Memory, ws: Workspace, scores, k: int, out_id, out_score, out_index=None, stream=None):
+    """farm_topk over precomputed score rows."""
+    q = int(scores.shape[0])
+    _lib.check(_lib.L.farm_topk(mem.handle, ws.handle, _ptr(scores), q, int(k), _ptr(out_id), _ptr(out_score),
+                                _ptr(out_index), _stream(stream)))
+
+
+def query_topk(mem: Memory, ws: Workspace, target, target_cls, rel_off, rel_pred, rel_anchor, k: int, out_id,
+               out_score, out_terms=None, out_anchor_id=None, dtype: int = F32, rescore_mult: int = 4,
+               stream=None):
+    """farm_query_topk: fused scoring + TopK + ScoredCandidate breakdown."""
+    tc, ptc = _host_i32(target_cls)
+    ro, pro = _host_i32(rel_off)
+    rp, prp = _host_i32(rel_pred)
+    q, d = int(target.shape[0]), int(target.shape[1])
+    opts = _lib.ScoreOpts(int(dtype), int(rescore_mult))
+    _lib.check(_lib.L.farm_query_topk(mem.handle, ws.handle, q, d, _ptr(target), ptc, pro, prp,
+                                      _ptr(rel_anchor) if rel_anchor is not None and rel_anchor.numel() else None,
+                                      ctypes.byref(opts), int(k), _ptr(out_id), _ptr(out_score), _ptr(out_terms),
+                                      _ptr(out_anchor_id), _stream(stream)))
+    del tc, ro, rp

@@ -1,0 +1,87 @@
+"""ctypes declarations of libfarm.so (include/farm.h).  Loads the in-tree
+library built by ``python -m paper_2606_15476_amd.build``; raises if absent."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_PATH = os.path.join(_HERE, "libfarm.so")
+
+FARM_OK, FARM_ERR_INVALID_ARG, FARM_ERR_OOM, FARM_ERR_HIP, FARM_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
+F32, BF16, FP8_E4M3 = 0, 1, 2
+NEAR, ABOVE, BELOW, LEFT_OF, RIGHT_OF = 0, 1, 2, 3, 4
+FARM_MAX_REL = 8
+FARM_MAX_K = 1024
+FARM_NO_ID = 0xFFFFFFFF
+FARM_BUILD_BF16, FARM_BUILD_FP8 = 0x1, 0x2
+
+EXPORTS = (
+    "farm_build_memory", "farm_free_memory", "farm_memory_info", "farm_workspace_create", "farm_workspace_free",
+    "farm_workspace_bytes", "farm_workspace_estimate", "farm_score_query", "farm_topk", "farm_query_topk",
+    "farm_workspace_status", "farm_last_error", "farm_version", "farm_workspace_set_timing",
+    "farm_workspace_timings",
+)
+PHASES = ("normalize", "gemm", "pair", "topk", "rescore", "explain")
+
+_STATUS = {FARM_ERR_INVALID_ARG: "invalid argument", FARM_ERR_OOM: "out of memory", FARM_ERR_HIP: "HIP error",
+           FARM_ERR_UNSUPPORTED: "unsupported"}
+
+
+class FarmError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class ScoreOpts(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("rescore_mult", ctypes.c_int32)]
+
+
+def lib_path() -> str:
+    return _PATH
+
+
+def _declare(lib):
+    P, i64, i32, u32, f32, sz = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
+                                 ctypes.c_float, ctypes.c_size_t)
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "farm_build_memory": [i64, i32, P, P, P, P, P, f32, f32, u32, P, pp],
+        "farm_free_memory": [P],
+        "farm_memory_info": [P, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(sz)],
+        "farm_workspace_create": [P, i32, i32, i32, pp],
+        "farm_workspace_free": [P],
+        "farm_workspace_bytes": [P, ctypes.POINTER(sz)],
+        "farm_workspace_estimate": [P, i32, i32, i32, ctypes.POINTER(sz)],
+        "farm_score_query": [P, P, i32, i32, P, P, P, P, P, P, P, P, P],
+        "farm_topk": [P, P, P, i32, i32, P, P, P, P],
+        "farm_query_topk": [P, P, i32, i32, P, P, P, P, P, ctypes.POINTER(ScoreOpts), i32, P, P, P, P, P],
+        "farm_workspace_status": [P, P],
+        "farm_workspace_set_timing": [P, i32],
+        "farm_workspace_timings": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32],
+        "farm_last_error": [],
+        "farm_version": [],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_char_p if name in ("farm_last_error", "farm_version") else ctypes.c_int
+    return lib
+
+
+def load(path: str | None = None):
+    path = path or _PATH
+    if not os.path.exists(path):
+        raise ImportError(f"libfarm.so not built at {path}; run `python paper_2606_15476_amd/build.py` "
+                          "(the HIP library is required: there is no fallback)")
+    return _declare(ctypes.CDLL(path))
+
+
+L = load()
+
+
+def check(status: int):
+    if status != FARM_OK:
+        msg = L.farm_last_error()
+        raise FarmError(status, msg.decode() if msg else "")

@@ -1,0 +1,561 @@
+// api.hip -- the C ABI (include/farm.h): argument checks, device memory
+// ownership, metadata staging and the launch sequence of each entry point.
+//
+// Launch sequence of a scoring call (all on the caller's stream):
+//   1. host metadata (classes, CSR relation offsets, predicates) is checked on
+//      the host, written to a pinned staging block and copied to the device;
+//   2. target and anchor vectors are L2-normalised into the workspace;
+//   3. the similarity GEMM fills sim[q + R][n] (clamped cosine, class factor
+//      on target rows);
+//   4. the relational pass produces s(i) (and optionally t_r, b_r);
+//   5. (fused path) TopK, then the ScoredCandidate breakdown of the winners.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+
+#include "farm_internal.h"
+
+namespace farm {
+
+static thread_local std::string g_error;
+
+void set_error(const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+}
+
+farm_status hip_fail(hipError_t e, const char* what) {
+  set_error("%s: %s", what, hipGetErrorString(e));
+  return FARM_ERR_HIP;
+}
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+  }
+  ~DeviceGuard() {
+    int cur;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+template <class T>
+farm_status dalloc(std::vector<void*>& allocs, size_t& bytes, T** p, size_t count, const char* what) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  void* v = nullptr;
+  hipError_t e = hipMalloc(&v, count * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("device allocation of %zu bytes for %s failed: %s", count * sizeof(T), what, hipGetErrorString(e));
+    return FARM_ERR_OOM;
+  }
+  allocs.push_back(v);
+  bytes += count * sizeof(T);
+  *p = static_cast<T*>(v);
+  return FARM_OK;
+}
+
+void free_all(std::vector<void*>& allocs) {
+  for (void* p : allocs) (void)hipFree(p);
+  allocs.clear();
+}
+
+#define FARM_TRY(expr)                  \
+  do {                                  \
+    farm_status st_ = (expr);           \
+    if (st_ != FARM_OK) return st_;     \
+  } while (0)
+
+#define FARM_HIP(expr, what)                     \
+  do {                                           \
+    hipError_t e_ = (expr);                      \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+size_t workspace_bytes_for(const farm_memory* mem, int32_t max_q, int32_t max_rel, int32_t max_k) {
+  size_t rows = (size_t)max_q + (size_t)max_rel;
+  size_t ld_s = (size_t)round_up(mem->n, kRowAlign);
+  size_t b = 0;
+  b += rows * mem->ldk * sizeof(float);                    // qn
+  if (mem->dn_bf16) b += rows * mem->ldk * sizeof(uint16_t);
+  if (mem->dn_fp8) b += rows * mem->ldk + rows * sizeof(float);
+  b += rows * ld_s * sizeof(float);                         // sim
+  b += (size_t)max_q * ld_s * sizeof(float);                // scores
+  b += (size_t)(2 * max_q + 1 + 2 * (size_t)max_rel) * sizeof(int32_t);
+  b += sizeof(int);
+  b += 2 * (size_t)topk_candidate_capacity(mem->n, max_q, max_k) * (sizeof(uint64_t) + sizeof(int32_t));
+  b += (size_t)max_q * max_k * sizeof(int32_t);
+  return b;
+}
+
+farm_status check_queries(const farm_memory* mem, const farm_workspace* ws, int32_t q, int32_t d,
+                          const float* target, const int32_t* rel_off, const int32_t* rel_pred,
+                          const float* rel_anchor, int32_t* r_tot) {
+  if (!mem || !ws) { set_error("null memory or workspace"); return FARM_ERR_INVALID_ARG; }
+  if (ws->mem != mem) { set_error("workspace was created for another memory"); return FARM_ERR_INVALID_ARG; }
+  if (q < 0 || q > ws->max_q) { set_error("q = %d outside [0, %d]", q, ws->max_q); return FARM_ERR_INVALID_ARG; }
+  if (d != mem->d) { set_error("query width %d != memory width %d", d, mem->d); return FARM_ERR_INVALID_ARG; }
+  if (q > 0 && (!target || !rel_off)) { set_error("null target or rel_off"); return FARM_ERR_INVALID_ARG; }
+  if (q == 0) { *r_tot = 0; return FARM_OK; }
+  if (rel_off[0] != 0) { set_error("rel_off[0] = %d, expected 0", rel_off[0]); return FARM_ERR_INVALID_ARG; }
+  for (int32_t k = 0; k < q; ++k) {
+    int32_t r = rel_off[k + 1] - rel_off[k];
+    if (r < 0 || r > kMaxRel) {
+      set_error("query %d has %d relations (allowed 0..%d)", k, r, kMaxRel);
+      return FARM_ERR_INVALID_ARG;
+    }
+  }
+  int32_t R = rel_off[q];
+  if (R > ws->max_rel) { set_error("%d relations exceed the workspace's %d", R, ws->max_rel); return FARM_ERR_INVALID_ARG; }
+  if (R > 0 && (!rel_pred || !rel_anchor)) { set_error("null rel_pred or rel_anchor"); return FARM_ERR_INVALID_ARG; }
+  for (int32_t r = 0; r < R; ++r)
+    if (rel_pred[r] < FARM_NEAR || rel_pred[r] > FARM_RIGHT_OF) {
+      set_error("relation %d has predicate id %d", r, rel_pred[r]);
+      return FARM_ERR_INVALID_ARG;
+    }
+  *r_tot = R;
+  return FARM_OK;
+}
+
+// Phase timer: brackets a phase with events on the call's stream when enabled.
+struct PhaseTimer {
+  farm_workspace* ws;
+  hipStream_t s;
+  int phase;
+  hipEvent_t a = nullptr, b = nullptr;
+  static hipEvent_t take(farm_workspace* w) {
+    if (!w->ev_pool.empty()) {
+      hipEvent_t e = w->ev_pool.back();
+      w->ev_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  PhaseTimer(farm_workspace* w, hipStream_t st, int ph) : ws(w), s(st), phase(ph) {
+    if (!ws->timing) return;
+    a = take(ws);
+    b = take(ws);
+    if (a) (void)hipEventRecord(a, s);
+  }
+  ~PhaseTimer() {
+    if (!ws->timing || !a || !b) return;
+    (void)hipEventRecord(b, s);
+    ws->pending.push_back({phase, a, b});
+  }
+};
+
+// Stage the per-call metadata and return device views of it.
+farm_status stage_meta(farm_workspace* ws, int32_t q, int32_t R, const int32_t* target_cls, const int32_t* rel_off,
+                       const int32_t* rel_pred, hipStream_t s, MetaView* view) {
+  if (ws->meta_pending) {
+    FARM_HIP(hipEventSynchronize(ws->meta_done), "waiting for the previous metadata copy");
+    ws->meta_pending = false;
+  }
+  int32_t* h = ws->h_meta;
+  for (int32_t k = 0; k < q; ++k) h[k] = target_cls ? target_cls[k] : -1;
+  memcpy(h + q, rel_off, sizeof(int32_t) * (size_t)(q + 1));
+  if (R) memcpy(h + 2 * q + 1, rel_pred, sizeof(int32_t) * (size_t)R);
+  int32_t* rq = h + 2 * q + 1 + R;
+  for (int32_t k = 0; k < q; ++k)
+    for (int32_t r = rel_off[k]; r < rel_off[k + 1]; ++r) rq[r] = k;
+  size_t len = (size_t)(2 * q + 1 + 2 * R);
+  FARM_HIP(hipMemcpyAsync(ws->d_meta, h, len * sizeof(int32_t), hipMemcpyHostToDevice, s), "metadata copy");
+  FARM_HIP(hipEventRecord(ws->meta_done, s), "metadata event");
+  ws->meta_pending = true;
+  view->tcls = ws->d_meta;
+  view->rel_off = ws->d_meta + q;
+  view->rel_pred = ws->d_meta + 2 * q + 1;
+  view->rel_query = ws->d_meta + 2 * q + 1 + R;
+  return FARM_OK;
+}
+
+// Steps 2 and 3: normalised query rows and the FP32 similarity matrix.
+farm_status similarities_f32(const farm_memory* mem, farm_workspace* ws, int32_t q, int32_t R, const float* target,
+                             const float* rel_anchor, const MetaView& meta, hipStream_t s) {
+  const int32_t ldk = mem->ldk;
+  {
+    PhaseTimer t(ws, s, FARM_PHASE_NORMALIZE);
+    FARM_HIP(launch_normalize_rows(target, q, mem->d, ldk, ws->qn, nullptr, nullptr, nullptr, ws->status, s),
+             "normalize targets");
+    FARM_HIP(launch_normalize_rows(rel_anchor, R, mem->d, ldk, ws->qn + (int64_t)q * ldk, nullptr, nullptr,
+                                   nullptr, ws->status, s),
+             "normalize anchors");
+  }
+  PhaseTimer t(ws, s, FARM_PHASE_GEMM);
+  FARM_HIP(launch_sim_gemm_f32(ws->qn, mem->dn, (int64_t)q + R, mem->n, ldk, ws->sim, ws->ld_s, meta.tcls, q,
+                               mem->cls, s),
+           "similarity GEMM");
+  return FARM_OK;
+}
+
+}  // namespace
+}  // namespace farm
+
+using namespace farm;
+
+extern "C" {
+
+const char* farm_last_error(void) { return g_error.c_str(); }
+
+const char* farm_version(void) { return "farm-mi355x 0.1 (gfx950)"; }
+
+farm_status farm_build_memory(int64_t n, int32_t d, const float* desc, const float* center, const float* extent,
+                              const uint32_t* id, const int32_t* cls, float view_right_x, float view_right_y,
+                              uint32_t flags, void* stream, farm_memory** out) {
+  try {
+    if (!out) { set_error("out is NULL"); return FARM_ERR_INVALID_ARG; }
+    *out = nullptr;
+    if (n < 1 || n >= (int64_t(1) << 31)) { set_error("n = %lld outside [1, 2^31)", (long long)n); return FARM_ERR_INVALID_ARG; }
+    if (d < 1 || d > 8192) { set_error("d = %d outside [1, 8192]", d); return FARM_ERR_INVALID_ARG; }
+    if (!desc || !center || !extent || !id) { set_error("null input pointer"); return FARM_ERR_INVALID_ARG; }
+    if (!std::isfinite(view_right_x) || !std::isfinite(view_right_y)) {
+      set_error("viewer right vector is not finite");
+      return FARM_ERR_INVALID_ARG;
+    }
+    if (flags & ~(FARM_BUILD_BF16 | FARM_BUILD_FP8)) { set_error("unknown build flags 0x%x", flags); return FARM_ERR_INVALID_ARG; }
+    hipStream_t s = (hipStream_t)stream;
+    int device = 0;
+    FARM_HIP(hipGetDevice(&device), "hipGetDevice");
+    auto* mem = new (std::nothrow) farm_memory();
+    if (!mem) { set_error("host allocation failed"); return FARM_ERR_OOM; }
+    mem->device = device;
+    mem->n = n;
+    mem->d = d;
+    mem->ldk = (int32_t)round_up(d, kKPad);
+    mem->flags = flags;
+    mem->rx = view_right_x;
+    mem->ry = view_right_y;
+    auto fail = [&](farm_status st) {
+      (void)hipStreamSynchronize(s);
+      free_all(mem->allocs);
+      delete mem;
+      return st;
+    };
+    farm_status st = FARM_OK;
+    const size_t nn = (size_t)n;
+    if ((st = dalloc(mem->allocs, mem->bytes, &mem->dn, nn * mem->ldk, "descriptors"))) return fail(st);
+    if (flags & FARM_BUILD_BF16)
+      if ((st = dalloc(mem->allocs, mem->bytes, &mem->dn_bf16, nn * mem->ldk, "BF16 descriptors"))) return fail(st);
+    if (flags & FARM_BUILD_FP8) {
+      if ((st = dalloc(mem->allocs, mem->bytes, &mem->dn_fp8, nn * mem->ldk, "FP8 descriptors"))) return fail(st);
+      if ((st = dalloc(mem->allocs, mem->bytes, &mem->dn_scale, nn, "FP8 scales"))) return fail(st);
+    }
+    if ((st = dalloc(mem->allocs, mem->bytes, &mem->x, nn, "x"))) return fail(st);
+    if ((st = dalloc(mem->allocs, mem->bytes, &mem->y, nn, "y"))) return fail(st);
+    if ((st = dalloc(mem->allocs, mem->bytes, &mem->z, nn, "z"))) return fail(st);
+    if ((st = dalloc(mem->allocs, mem->bytes, &mem->hr_hi, nn, "lateral hi"))) return fail(st);
+    if ((st = dalloc(mem->allocs, mem->bytes, &mem->hr_lo, nn, "lateral lo"))) return fail(st);
+    if ((st = dalloc(mem->allocs, mem->bytes, &mem->ext, nn * 3, "extents"))) return fail(st);
+    if ((st = dalloc(mem->allocs, mem->bytes, &mem->id, nn, "ids"))) return fail(st);
+    if (cls)
+      if ((st = dalloc(mem->allocs, mem->bytes, &mem->cls, nn, "classes"))) return fail(st);
+
+    // validation scratch: flags + id hash table (freed before returning)
+    std::vector<void*> tmp;
+    size_t tmp_bytes = 0;
+    int* d_flags = nullptr;
+    uint32_t* table = nullptr;
+    int64_t tsize = 2;
+    while (tsize < 2 * n) tsize <<= 1;
+    if ((st = dalloc(tmp, tmp_bytes, &d_flags, 1, "validation flags"))) return fail(st);
+    if ((st = dalloc(tmp, tmp_bytes, &table, (size_t)tsize, "id table"))) { free_all(tmp); return fail(st); }
+    auto fail_tmp = [&](farm_status st2) { (void)hipStreamSynchronize(s); free_all(tmp); return fail(st2); };
+    hipError_t e;
+    if ((e = hipMemsetAsync(d_flags, 0, sizeof(int), s)) != hipSuccess) return fail_tmp(hip_fail(e, "memset"));
+    if ((e = launch_validate_memory(desc, center, extent, id, n, d, d_flags, table, tsize, s)) != hipSuccess)
+      return fail_tmp(hip_fail(e, "validate"));
+    if ((e = launch_normalize_rows(desc, n, d, mem->ldk, mem->dn, mem->dn_bf16, mem->dn_fp8, mem->dn_scale, d_flags,
+                                   s)) != hipSuccess)
+      return fail_tmp(hip_fail(e, "normalize descriptors"));
+    if ((e = launch_geometry(center, extent, n, view_right_x, view_right_y, mem->x, mem->y, mem->z, mem->hr_hi,
+                             mem->hr_lo, mem->ext, s)) != hipSuccess)
+      return fail_tmp(hip_fail(e, "geometry"));
+    if ((e = hipMemcpyAsync(mem->id, id, nn * sizeof(uint32_t), hipMemcpyDeviceToDevice, s)) != hipSuccess)
+      return fail_tmp(hip_fail(e, "copy ids"));
+    if (cls && (e = hipMemcpyAsync(mem->cls, cls, nn * sizeof(int32_t), hipMemcpyDeviceToDevice, s)) != hipSuccess)
+      return fail_tmp(hip_fail(e, "copy classes"));
+    int h_flags = 0;
+    if ((e = hipMemcpyAsync(&h_flags, d_flags, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess)
+      return fail_tmp(hip_fail(e, "read flags"));
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail_tmp(hip_fail(e, "build synchronize"));
+    free_all(tmp);
+    if (h_flags) {
+      set_error("invalid scene:%s%s%s%s%s%s", (h_flags & kBadDesc) ? " non-finite descriptor;" : "",
+                (h_flags & kZeroNorm) ? " zero-norm descriptor;" : "",
+                (h_flags & kBadCenter) ? " non-finite center;" : "",
+                (h_flags & kBadExtent) ? " non-positive or non-finite extent;" : "",
+                (h_flags & kBadId) ? " reserved id 0xFFFFFFFF;" : "", (h_flags & kDupId) ? " duplicate id;" : "");
+      return fail(FARM_ERR_INVALID_ARG);
+    }
+    *out = mem;
+    return FARM_OK;
+  } catch (...) {
+    set_error("unexpected host exception in farm_build_memory");
+    return FARM_ERR_OOM;
+  }
+}
+
+farm_status farm_free_memory(farm_memory* mem) {
+  if (!mem) return FARM_OK;
+  DeviceGuard g(mem->device);
+  (void)hipDeviceSynchronize();
+  free_all(mem->allocs);
+  delete mem;
+  return FARM_OK;
+}
+
+farm_status farm_memory_info(const farm_memory* mem, int64_t* n, int32_t* d, size_t* bytes) {
+  if (!mem) { set_error("null memory"); return FARM_ERR_INVALID_ARG; }
+  if (n) *n = mem->n;
+  if (d) *d = mem->d;
+  if (bytes) *bytes = mem->bytes;
+  return FARM_OK;
+}
+
+farm_status farm_workspace_estimate(const farm_memory* mem, int32_t max_q, int32_t max_rel, int32_t max_k,
+                                    size_t* bytes) {
+  if (!mem || !bytes || max_q < 1 || max_rel < 0 || max_k < 1 || max_k > FARM_MAX_K) {
+    set_error("invalid workspace shape");
+    return FARM_ERR_INVALID_ARG;
+  }
+  *bytes = workspace_bytes_for(mem, max_q, max_rel, max_k);
+  return FARM_OK;
+}
+
+farm_status farm_workspace_create(const farm_memory* mem, int32_t max_q, int32_t max_rel, int32_t max_k,
+                                  farm_workspace** out) {
+  try {
+    if (!out) { set_error("out is NULL"); return FARM_ERR_INVALID_ARG; }
+    *out = nullptr;
+    if (!mem || max_q < 1 || max_rel < 0 || max_k < 1 || max_k > FARM_MAX_K) {
+      set_error("invalid workspace shape (max_q %d, max_rel %d, max_k %d)", max_q, max_rel, max_k);
+      return FARM_ERR_INVALID_ARG;
+    }
+    DeviceGuard g(mem->device);
+    auto* ws = new (std::nothrow) farm_workspace();
+    if (!ws) { set_error("host allocation failed"); return FARM_ERR_OOM; }
+    ws->mem = mem;
+    ws->device = mem->device;
+    ws->max_q = max_q;
+    ws->max_rel = max_rel;
+    ws->ld_s = round_up(mem->n, kRowAlign);
+    auto fail = [&](farm_status st) {
+      free_all(ws->allocs);
+      if (ws->h_meta) (void)hipHostFree(ws->h_meta);
+      if (ws->meta_done) (void)hipEventDestroy(ws->meta_done);
+      delete ws;
+      return st;
+    };
+    const size_t rows = (size_t)max_q + (size_t)max_rel;
+    farm_status st;
+    if ((st = dalloc(ws->allocs, ws->bytes, &ws->qn, rows * mem->ldk, "query vectors"))) return fail(st);
+    if (mem->dn_bf16 && (st = dalloc(ws->allocs, ws->bytes, &ws->qn_bf16, rows * mem->ldk, "BF16 query vectors")))
+      return fail(st);
+    if (mem->dn_fp8) {
+      if ((st = dalloc(ws->allocs, ws->bytes, &ws->qn_fp8, rows * mem->ldk, "FP8 query vectors"))) return fail(st);
+      if ((st = dalloc(ws->allocs, ws->bytes, &ws->qn_scale, rows, "FP8 query scales"))) return fail(st);
+    }
+    if ((st = dalloc(ws->allocs, ws->bytes, &ws->sim, rows * ws->ld_s, "similarity matrix"))) return fail(st);
+    if ((st = dalloc(ws->allocs, ws->bytes, &ws->scores, (size_t)max_q * ws->ld_s, "scores"))) return fail(st);
+    ws->meta_len = 2 * (int64_t)max_q + 1 + 2 * (int64_t)max_rel;
+    if ((st = dalloc(ws->allocs, ws->bytes, &ws->d_meta, (size_t)ws->meta_len, "metadata"))) return fail(st);
+    if ((st = dalloc(ws->allocs, ws->bytes, &ws->status, 1, "status"))) return fail(st);
+    ws->cand_cap = topk_candidate_capacity(mem->n, max_q, max_k);
+    for (int b = 0; b < 2; ++b) {
+      if ((st = dalloc(ws->allocs, ws->bytes, &ws->cand_key[b], (size_t)ws->cand_cap, "TopK keys"))) return fail(st);
+      if ((st = dalloc(ws->allocs, ws->bytes, &ws->cand_idx[b], (size_t)ws->cand_cap, "TopK indices"))) return fail(st);
+    }
+    if ((st = dalloc(ws->allocs, ws->bytes, &ws->rs_idx, (size_t)max_q * max_k, "winner indices"))) return fail(st);
+    hipError_t e = hipHostMalloc((void**)&ws->h_meta, (size_t)ws->meta_len * sizeof(int32_t), hipHostMallocDefault);
+    if (e != hipSuccess) { ws->h_meta = nullptr; return fail(hip_fail(e, "pinned metadata staging")); }
+    e = hipEventCreateWithFlags(&ws->meta_done, hipEventDisableTiming);
+    if (e != hipSuccess) { ws->meta_done = nullptr; return fail(hip_fail(e, "event")); }
+    e = hipMemset(ws->status, 0, sizeof(int));
+    if (e != hipSuccess) return fail(hip_fail(e, "status clear"));
+    *out = ws;
+    return FARM_OK;
+  } catch (...) {
+    set_error("unexpected host exception in farm_workspace_create");
+    return FARM_ERR_OOM;
+  }
+}
+
+farm_status farm_workspace_set_timing(farm_workspace* ws, int32_t enable) {
+  if (!ws) { set_error("null workspace"); return FARM_ERR_INVALID_ARG; }
+  ws->timing = enable != 0;
+  return FARM_OK;
+}
+
+farm_status farm_workspace_timings(farm_workspace* ws, double* ms, int64_t* count, int32_t reset) {
+  if (!ws) { set_error("null workspace"); return FARM_ERR_INVALID_ARG; }
+  DeviceGuard g(ws->device);
+  for (auto& p : ws->pending) {
+    FARM_HIP(hipEventSynchronize(p.b), "timer synchronize");
+    float t = 0.f;
+    FARM_HIP(hipEventElapsedTime(&t, p.a, p.b), "timer elapsed");
+    ws->phase_ms[p.phase] += t;
+    ws->phase_count[p.phase] += 1;
+    ws->ev_pool.push_back(p.a);
+    ws->ev_pool.push_back(p.b);
+  }
+  ws->pending.clear();
+  for (int i = 0; i < FARM_PHASE_COUNT; ++i) {
+    if (ms) ms[i] = ws->phase_ms[i];
+    if (count) count[i] = ws->phase_count[i];
+    if (reset) {
+      ws->phase_ms[i] = 0;
+      ws->phase_count[i] = 0;
+    }
+  }
+  return FARM_OK;
+}
+
+farm_status farm_workspace_free(farm_workspace* ws) {
+  if (!ws) return FARM_OK;
+  DeviceGuard g(ws->device);
+  (void)hipDeviceSynchronize();
+  for (auto& p : ws->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (hipEvent_t e : ws->ev_pool) (void)hipEventDestroy(e);
+  free_all(ws->allocs);
+  if (ws->h_meta) (void)hipHostFree(ws->h_meta);
+  if (ws->meta_done) (void)hipEventDestroy(ws->meta_done);
+  delete ws;
+  return FARM_OK;
+}
+
+farm_status farm_workspace_bytes(const farm_workspace* ws, size_t* bytes) {
+  if (!ws || !bytes) { set_error("null argument"); return FARM_ERR_INVALID_ARG; }
+  *bytes = ws->bytes;
+  return FARM_OK;
+}
+
+farm_status farm_workspace_status(farm_workspace* ws, void* stream) {
+  if (!ws) { set_error("null workspace"); return FARM_ERR_INVALID_ARG; }
+  DeviceGuard g(ws->device);
+  hipStream_t s = (hipStream_t)stream;
+  int h = 0;
+  FARM_HIP(hipMemcpyAsync(&h, ws->status, sizeof(int), hipMemcpyDeviceToHost, s), "read status");
+  FARM_HIP(hipStreamSynchronize(s), "status synchronize");
+  if (h) {
+    FARM_HIP(hipMemsetAsync(ws->status, 0, sizeof(int), s), "status clear");
+    FARM_HIP(hipStreamSynchronize(s), "status synchronize");
+    set_error("a scoring call saw a%s%s query vector", (h & kBadDesc) ? " non-finite" : "",
+              (h & kZeroNorm) ? " zero-norm" : "");
+    return FARM_ERR_INVALID_ARG;
+  }
+  return FARM_OK;
+}
+
+farm_status farm_score_query(const farm_memory* mem, farm_workspace* ws, int32_t q, int32_t d, const float* target,
+                             const int32_t* target_cls, const int32_t* rel_off, const int32_t* rel_pred,
+                             const float* rel_anchor, float* scores, float* rel_terms, uint32_t* rel_anchor_id,
+                             void* stream) {
+  try {
+    int32_t R = 0;
+    FARM_TRY(check_queries(mem, ws, q, d, target, rel_off, rel_pred, rel_anchor, &R));
+    if (q > 0 && !scores) { set_error("scores is NULL"); return FARM_ERR_INVALID_ARG; }
+    if (q == 0) return FARM_OK;
+    DeviceGuard g(mem->device);
+    hipStream_t s = (hipStream_t)stream;
+    MetaView meta;
+    FARM_TRY(stage_meta(ws, q, R, target_cls, rel_off, rel_pred, s, &meta));
+    FARM_TRY(similarities_f32(mem, ws, q, R, target, rel_anchor, meta, s));
+    PhaseTimer t(ws, s, FARM_PHASE_PAIR);
+    FARM_HIP(launch_pair_exhaustive(mem, ws->sim, ws->ld_s, q, meta, scores, mem->n, rel_terms, rel_anchor_id, s),
+             "relational pass");
+    return FARM_OK;
+  } catch (...) {
+    set_error("unexpected host exception in farm_score_query");
+    return FARM_ERR_HIP;
+  }
+}
+
+farm_status farm_topk(const farm_memory* mem, farm_workspace* ws, const float* scores, int32_t q, int32_t k,
+                      uint32_t* out_id, float* out_score, int32_t* out_index, void* stream) {
+  try {
+    if (!mem || !ws || ws->mem != mem) { set_error("null or mismatched memory/workspace"); return FARM_ERR_INVALID_ARG; }
+    if (q < 0 || q > ws->max_q) { set_error("q = %d outside [0, %d]", q, ws->max_q); return FARM_ERR_INVALID_ARG; }
+    if (k < 1 || k > FARM_MAX_K) { set_error("k = %d outside [1, %d]", k, FARM_MAX_K); return FARM_ERR_INVALID_ARG; }
+    if (q == 0) return FARM_OK;
+    if (!scores || !out_id || !out_score) { set_error("null pointer"); return FARM_ERR_INVALID_ARG; }
+    if ((int64_t)q * ((mem->n + 4095) / 4096) * k > ws->cand_cap) {
+      set_error("k = %d exceeds the workspace's max_k", k);
+      return FARM_ERR_INVALID_ARG;
+    }
+    DeviceGuard g(mem->device);
+    hipStream_t s = (hipStream_t)stream;
+    uint64_t* key;
+    int32_t* idx;
+    PhaseTimer t(ws, s, FARM_PHASE_TOPK);
+    FARM_HIP(launch_topk(mem, ws, scores, mem->n, q, k, &key, &idx, s), "topk");
+    FARM_HIP(launch_topk_emit(key, idx, q, k, out_id, out_score, out_index, s), "topk emit");
+    return FARM_OK;
+  } catch (...) {
+    set_error("unexpected host exception in farm_topk");
+    return FARM_ERR_HIP;
+  }
+}
+
+farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t q, int32_t d, const float* target,
+                            const int32_t* target_cls, const int32_t* rel_off, const int32_t* rel_pred,
+                            const float* rel_anchor, const farm_score_opts* opts, int32_t k, uint32_t* out_id,
+                            float* out_score, float* out_terms, uint32_t* out_anchor_id, void* stream) {
+  try {
+    int32_t R = 0;
+    FARM_TRY(check_queries(mem, ws, q, d, target, rel_off, rel_pred, rel_anchor, &R));
+    if (k < 1 || k > FARM_MAX_K) { set_error("k = %d outside [1, %d]", k, FARM_MAX_K); return FARM_ERR_INVALID_ARG; }
+    if (q == 0) return FARM_OK;
+    if (!out_id || !out_score) { set_error("null output pointer"); return FARM_ERR_INVALID_ARG; }
+    int32_t dtype = opts ? opts->dtype : FARM_F32;
+    if (dtype != FARM_F32) { set_error("dtype %d not supported by this build", dtype); return FARM_ERR_UNSUPPORTED; }
+    if ((int64_t)q * ((mem->n + 4095) / 4096) * k > ws->cand_cap) {
+      set_error("k = %d exceeds the workspace's max_k", k);
+      return FARM_ERR_INVALID_ARG;
+    }
+    DeviceGuard g(mem->device);
+    hipStream_t s = (hipStream_t)stream;
+    MetaView meta;
+    FARM_TRY(stage_meta(ws, q, R, target_cls, rel_off, rel_pred, s, &meta));
+    FARM_TRY(similarities_f32(mem, ws, q, R, target, rel_anchor, meta, s));
+    {
+      PhaseTimer t(ws, s, FARM_PHASE_PAIR);
+      FARM_HIP(launch_pair_exhaustive(mem, ws->sim, ws->ld_s, q, meta, ws->scores, ws->ld_s, nullptr, nullptr, s),
+               "relational pass");
+    }
+    uint64_t* key;
+    int32_t* idx;
+    {
+      PhaseTimer t(ws, s, FARM_PHASE_TOPK);
+      FARM_HIP(launch_topk(mem, ws, ws->scores, ws->ld_s, q, k, &key, &idx, s), "topk");
+      FARM_HIP(launch_topk_emit(key, idx, q, k, out_id, out_score, ws->rs_idx, s), "topk emit");
+    }
+    PhaseTimer t(ws, s, FARM_PHASE_EXPLAIN);
+    FARM_HIP(launch_explain(mem, ws->sim, ws->ld_s, q, meta, ws->rs_idx, k, out_terms, out_anchor_id, s), "explain");
+    return FARM_OK;
+  } catch (...) {
+    set_error("unexpected host exception in farm_query_topk");
+    return FARM_ERR_HIP;
+  }
+}
+
+}  // extern "C"

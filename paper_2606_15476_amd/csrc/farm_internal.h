@@ -1,0 +1,155 @@
+// farm_internal.h -- private declarations shared by libfarm's translation units.
+// Not installed; the public ABI is include/farm.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/farm.h"
+
+namespace farm {
+
+constexpr int kMaxRel = FARM_MAX_REL;
+constexpr int kKPad = 32;          // descriptor rows are zero-padded to a multiple of this
+constexpr int kRowAlign = 64;      // similarity-matrix rows are padded to a multiple of this
+constexpr float kW = 0.5f;         // soft-blend weight of the relational factor
+constexpr float kClassFactor = 0.3f;
+constexpr float kFp8Max = 448.0f;  // largest finite OCP e4m3 value
+
+// Validation flag bits raised by device-side checks.
+enum : int {
+  kBadDesc = 1 << 0,
+  kZeroNorm = 1 << 1,
+  kBadCenter = 1 << 2,
+  kBadExtent = 1 << 3,
+  kBadId = 1 << 4,
+  kDupId = 1 << 5,
+  kBadQuery = 1 << 6,
+};
+
+inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+}  // namespace farm
+
+struct farm_memory {
+  int64_t n = 0;
+  int32_t d = 0;
+  int32_t ldk = 0;  // padded descriptor row length (elements)
+  int device = 0;
+  uint32_t flags = 0;
+  float rx = 0.f, ry = 0.f;
+  // descriptors, L2-normalised, zero-padded to ldk
+  float* dn = nullptr;        // [n][ldk] FP32 master
+  uint16_t* dn_bf16 = nullptr;  // [n][ldk] BF16 (RNE)
+  uint8_t* dn_fp8 = nullptr;    // [n][ldk] OCP e4m3, scaled by 1/dn_scale
+  float* dn_scale = nullptr;    // [n] per-row FP32 scale (amax / 448)
+  // geometry, structure of arrays
+  float* x = nullptr;
+  float* y = nullptr;
+  float* z = nullptr;
+  float* hr_hi = nullptr;  // lateral coordinate c . r as an unevaluated sum hi + lo
+  float* hr_lo = nullptr;
+  float* ext = nullptr;    // [3][n] extents
+  uint32_t* id = nullptr;
+  int32_t* cls = nullptr;
+  size_t bytes = 0;
+  std::vector<void*> allocs;
+};
+
+struct farm_workspace {
+  const farm_memory* mem = nullptr;
+  int device = 0;
+  int32_t max_q = 0, max_rel = 0;
+  int64_t ld_s = 0;          // row stride of the similarity / score matrices
+  float* qn = nullptr;        // [max_q + max_rel][ldk] normalised query vectors
+  uint16_t* qn_bf16 = nullptr;
+  uint8_t* qn_fp8 = nullptr;
+  float* qn_scale = nullptr;
+  float* sim = nullptr;       // [max_q + max_rel][ld_s] clamped similarities (target rows x kappa)
+  float* scores = nullptr;    // [max_q][ld_s] composite scores (fused path)
+  int32_t* d_meta = nullptr;  // device copy of the metadata block below
+  int32_t* h_meta = nullptr;  // pinned host staging of the metadata block
+  int64_t meta_len = 0;       // int32 elements in the metadata block
+  hipEvent_t meta_done = nullptr;
+  bool meta_pending = false;
+  int* status = nullptr;      // device validation flags
+  // TopK candidate ping-pong buffers
+  uint64_t* cand_key[2] = {nullptr, nullptr};
+  int32_t* cand_idx[2] = {nullptr, nullptr};
+  int64_t cand_cap = 0;       // elements per buffer
+  // rescoring buffers
+  int32_t* rs_idx = nullptr;  // [max_q][FARM_MAX_K * rescore]
+  // optional phase timer: pending (start, stop) event pairs per phase
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  struct PendingPhase { int phase; hipEvent_t a, b; };
+  std::vector<PendingPhase> pending;
+  double phase_ms[FARM_PHASE_COUNT] = {0};
+  int64_t phase_count[FARM_PHASE_COUNT] = {0};
+  size_t bytes = 0;
+  std::vector<void*> allocs;
+};
+
+// Metadata block layout (int32), written by the host per call:
+//   [0, q)                 target class per query
+//   [q, 2q + 1)            rel_off
+//   [2q + 1, 2q + 1 + R)   rel_pred
+//   [.., + R)              query index of each relation
+struct MetaView {
+  const int32_t* tcls;
+  const int32_t* rel_off;
+  const int32_t* rel_pred;
+  const int32_t* rel_query;
+};
+
+namespace farm {
+
+void set_error(const char* fmt, ...);
+farm_status hip_fail(hipError_t e, const char* what);
+
+// ---- prep.hip
+hipError_t launch_validate_memory(const float* desc, const float* center, const float* extent,
+                                  const uint32_t* id, int64_t n, int32_t d, int* flags,
+                                  uint32_t* table, int64_t table_size, hipStream_t s);
+hipError_t launch_normalize_rows(const float* src, int64_t rows, int32_t d, int32_t ldk, float* dst_f32,
+                                 uint16_t* dst_bf16, uint8_t* dst_fp8, float* dst_scale, int* flags,
+                                 hipStream_t s);
+hipError_t launch_geometry(const float* center, const float* extent, int64_t n, float rx, float ry,
+                           float* x, float* y, float* z, float* hr_hi, float* hr_lo, float* ext,
+                           hipStream_t s);
+
+// ---- gemm.hip: sim[row][col] = kappa(row, col) * max(0, <a_row, b_col>)
+hipError_t launch_sim_gemm_f32(const float* a, const float* b, int64_t m, int64_t n, int32_t ldk,
+                               float* c, int64_t ldc, const int32_t* row_cls, int64_t n_cls_rows,
+                               const int32_t* col_cls, hipStream_t s);
+hipError_t launch_sim_gemm_bf16(const uint16_t* a, const uint16_t* b, int64_t m, int64_t n, int32_t ldk,
+                                float* c, int64_t ldc, const int32_t* row_cls, int64_t n_cls_rows,
+                                const int32_t* col_cls, hipStream_t s);
+hipError_t launch_sim_gemm_fp8(const uint8_t* a, const float* a_scale, const uint8_t* b, const float* b_scale,
+                               int64_t m, int64_t n, int32_t ldk, float* c, int64_t ldc,
+                               const int32_t* row_cls, int64_t n_cls_rows, const int32_t* col_cls,
+                               hipStream_t s);
+
+// ---- pair.hip
+hipError_t launch_pair_exhaustive(const farm_memory* mem, const float* sim, int64_t ld_s, int32_t q,
+                                  MetaView meta, float* scores, int64_t ld_out, float* rel_terms,
+                                  uint32_t* rel_anchor_id, hipStream_t s);
+// ScoredCandidate breakdown for selected objects: t_r and b_r recomputed for
+// each (query, rank) entry of idx[q][k].
+hipError_t launch_explain(const farm_memory* mem, const float* sim, int64_t ld_s, int32_t q, MetaView meta,
+                          const int32_t* idx, int32_t k, float* out_terms, uint32_t* out_anchor_id,
+                          hipStream_t s);
+
+// ---- topk.hip
+// Select the top k of each score row.  Writes (key, index) of the winners in
+// order into out_key/out_idx [q][k]; candidate buffers come from the workspace.
+hipError_t launch_topk(const farm_memory* mem, farm_workspace* ws, const float* scores, int64_t ld_scores,
+                       int32_t q, int32_t k, uint64_t** out_key, int32_t** out_idx, hipStream_t s);
+hipError_t launch_topk_emit(const uint64_t* key, const int32_t* idx, int32_t q, int32_t k, uint32_t* out_id,
+                            float* out_score, int32_t* out_index, hipStream_t s);
+int64_t topk_candidate_capacity(int64_t n, int32_t max_q, int32_t max_k);
+
+}  // namespace farm

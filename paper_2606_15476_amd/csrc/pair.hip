@@ -1,0 +1,341 @@
+// pair.hip -- the relational pass: per-relation max over anchors and the
+// soft composite.
+//
+// For query q with relations r = (p_r, q_r) and the clamped similarities
+// a_r(j) = sim(j, q_r) (rows of the similarity matrix):
+//   t_r(i) = max_{j != i} a_r(j) * P_{p_r}(c_i, c_j)        (greedy star binding,
+//            Appendix "Robust Relational Retrieval Formulation", query-time complexity)
+//   s(i)   = s_sem(i) * (0.5 + 0.5 * exp(mean_r log t_r(i)))  (geometric-mean blend,
+//            Appendix "Retrieval Details", composite-scoring step)
+//
+// Arithmetic forms used on the GPU (algebraically equal to the definitions):
+//   Near:        log(a_j) - 2 |c_i - c_j|^2 is maximised in the log domain,
+//                no transcendental per pair; t = exp(max).
+//   Above/Below: P = 1 / (1 + 2^(dz * c)), c = -+(1/tau) log2(e), with
+//                dz = z_i - z_j; exp2 and reciprocal on the transcendental unit.
+//   Left/Right:  the same sigmoid on the lateral offset dh = h_i - h_j, with h
+//                kept as an unevaluated float pair hi + lo (see prep.hip).
+// All offsets are formed as differences of coordinates before any scaling,
+// so the argument error is relative to the offset, not to the distance from
+// the origin.  The geometric mean is formed as exp of the mean of logs, which
+// neither overflows nor underflows for R <= 8 relations.
+//
+// Exhaustive kernel: one block per (512 targets, query); each thread owns two
+// targets; anchors stream through LDS in chunks of 512 as (value, coordinates)
+// float4 records that every lane reads as a broadcast.  Only the chunk that
+// overlaps the block's own targets carries the j != i test.
+#include <math.h>
+
+#include "farm_internal.h"
+
+namespace farm {
+namespace {
+
+enum Family { kFamNear = 0, kFamVert = 1, kFamLat = 2 };
+
+// (1/tau) * log2(e) with tau = 0.1 m
+constexpr float kInvTauLog2e = 14.426950408889634f;
+
+__device__ inline int family_of(int p) {
+  return p == FARM_NEAR ? kFamNear : (p == FARM_ABOVE || p == FARM_BELOW) ? kFamVert : kFamLat;
+}
+
+// exponent scale c such that P = 1 / (1 + 2^(offset * c))
+__device__ inline float sigmoid_scale(int p) {
+  return (p == FARM_ABOVE || p == FARM_RIGHT_OF) ? -kInvTauLog2e : kInvTauLog2e;
+}
+
+__device__ inline float rcp_approx(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ inline float exp2_approx(float v) { return __builtin_amdgcn_exp2f(v); }
+
+// Per-target coordinates, family-specific.
+struct Tgt {
+  float u0, u1, u2;
+};
+
+__device__ inline Tgt load_target(int fam, int64_t i, const float* x, const float* y, const float* z,
+                                  const float* hhi, const float* hlo) {
+  Tgt t{0.f, 0.f, 0.f};
+  if (fam == kFamNear) {
+    t.u0 = x[i]; t.u1 = y[i]; t.u2 = z[i];
+  } else if (fam == kFamVert) {
+    t.u0 = z[i];
+  } else {
+    t.u0 = hhi[i]; t.u1 = hlo[i];
+  }
+  return t;
+}
+
+// Anchor record: (value, coordinates).  Near stores log(a_j).
+__device__ inline float4 anchor_record(int fam, float a, int64_t j, const float* x, const float* y, const float* z,
+                                       const float* hhi, const float* hlo) {
+  // a = 0 maps to a large finite negative log so that such anchors still order by
+  // distance (any of them is a valid binding of a zero term).
+  if (fam == kFamNear) return make_float4(a > 0.f ? logf(a) : -1.0e30f, x[j], y[j], z[j]);
+  if (fam == kFamVert) return make_float4(a, z[j], 0.f, 0.f);
+  return make_float4(a, hhi[j], hlo[j], 0.f);
+}
+
+// Value of one (target, anchor) pair in the family's comparison domain:
+// log domain for Near, linear for the sigmoid families.
+template <int FAM>
+__device__ inline float pair_value(const Tgt& t, const float4& rec, float c) {
+  if (FAM == kFamNear) {
+    float dx = t.u0 - rec.y, dy = t.u1 - rec.z, dz = t.u2 - rec.w;
+    float d2 = dx * dx;
+    d2 = fmaf(dy, dy, d2);
+    d2 = fmaf(dz, dz, d2);
+    return fmaf(-2.0f, d2, rec.x);
+  } else if (FAM == kFamVert) {
+    float e = exp2_approx((t.u0 - rec.y) * c);
+    return rec.x * rcp_approx(1.0f + e);
+  } else {
+    float dh = (t.u0 - rec.y) + (t.u1 - rec.z);
+    float e = exp2_approx(dh * c);
+    return rec.x * rcp_approx(1.0f + e);
+  }
+}
+
+// Initial "best" in the comparison domain (below any attainable value).
+template <int FAM>
+__device__ inline float value_floor() {
+  return FAM == kFamNear ? -INFINITY : -1.0f;
+}
+
+// Linear relation term from the family-domain maximum.
+template <int FAM>
+__device__ inline float term_of(float best) {
+  if (FAM == kFamNear) return expf(best);
+  return best > 0.f ? best : 0.f;
+}
+
+constexpr int kThreads = 256;
+constexpr int kTpt = 2;                      // targets per thread
+constexpr int kTile = kThreads * kTpt;       // targets per block
+constexpr int kChunk = 512;                  // anchors per LDS chunk
+
+template <int FAM, bool SELF, bool WITH_ARG>
+__device__ inline void scan_chunk(const float4* __restrict__ rec, const uint32_t* __restrict__ rid, int cnt,
+                                  int64_t j0, const Tgt* t, const int64_t* ti, float c, float* best,
+                                  uint32_t* bid) {
+  for (int jj = 0; jj < cnt; ++jj) {
+    float4 r = rec[jj];
+#pragma unroll
+    for (int u = 0; u < kTpt; ++u) {
+      float v = pair_value<FAM>(t[u], r, c);
+      if (SELF && j0 + jj == ti[u]) v = -INFINITY;
+      if (WITH_ARG) {
+        uint32_t idj = rid[jj];
+        bool take = v > best[u] || (v == best[u] && idj < bid[u] && v != -INFINITY);
+        best[u] = take ? v : best[u];
+        bid[u] = take ? idj : bid[u];
+      } else {
+        best[u] = fmaxf(best[u], v);
+      }
+    }
+  }
+}
+
+template <int FAM, bool WITH_ARG>
+__device__ void relation_pass(const float* __restrict__ arow, int64_t n, int64_t tile0, const int64_t* ti,
+                              const Tgt* t, float c, const float* x, const float* y, const float* z,
+                              const float* hhi, const float* hlo, const uint32_t* ids, float4* rec,
+                              uint32_t* rid, float* best, uint32_t* bid) {
+#pragma unroll
+  for (int u = 0; u < kTpt; ++u) {
+    best[u] = value_floor<FAM>();
+    bid[u] = FARM_NO_ID;
+  }
+  const int64_t tile1 = tile0 + kTile;
+  for (int64_t c0 = 0; c0 < n; c0 += kChunk) {
+    int cnt = (int)(n - c0 < kChunk ? n - c0 : kChunk);
+    __syncthreads();
+    for (int jj = threadIdx.x; jj < cnt; jj += kThreads) {
+      int64_t j = c0 + jj;
+      rec[jj] = anchor_record(FAM, arow[j], j, x, y, z, hhi, hlo);
+      if (WITH_ARG) rid[jj] = ids[j];
+    }
+    __syncthreads();
+    bool overlap = c0 < tile1 && c0 + cnt > tile0;
+    if (overlap)
+      scan_chunk<FAM, true, WITH_ARG>(rec, rid, cnt, c0, t, ti, c, best, bid);
+    else
+      scan_chunk<FAM, false, WITH_ARG>(rec, rid, cnt, c0, t, ti, c, best, bid);
+  }
+}
+
+template <bool WITH_ARG>
+__global__ __launch_bounds__(kThreads) void k_pair_exhaustive(
+    const float* __restrict__ sim, int64_t ld_s, int32_t q, MetaView meta, const float* __restrict__ x,
+    const float* __restrict__ y, const float* __restrict__ z, const float* __restrict__ hhi,
+    const float* __restrict__ hlo, const uint32_t* __restrict__ ids, int64_t n, float* __restrict__ scores,
+    int64_t ld_out, float* __restrict__ rel_terms, uint32_t* __restrict__ rel_anchor_id) {
+  __shared__ float4 rec[kChunk];
+  __shared__ uint32_t rid[WITH_ARG ? kChunk : 1];
+  const int32_t qq = blockIdx.y;
+  const int64_t tile0 = (int64_t)blockIdx.x * kTile;
+  int64_t ti[kTpt];
+#pragma unroll
+  for (int u = 0; u < kTpt; ++u) {
+    int64_t i = tile0 + threadIdx.x + u * kThreads;
+    ti[u] = i < n ? i : n - 1;  // out-of-range lanes shadow the last target and do not store
+  }
+  const int r0 = meta.rel_off[qq], r1 = meta.rel_off[qq + 1];
+  float lsum[kTpt];
+#pragma unroll
+  for (int u = 0; u < kTpt; ++u) lsum[u] = 0.f;
+
+  for (int r = r0; r < r1; ++r) {
+    const int p = meta.rel_pred[r];
+    const int fam = family_of(p);
+    const float c = sigmoid_scale(p);
+    const float* arow = sim + (int64_t)(q + r) * ld_s;
+    Tgt t[kTpt];
+#pragma unroll
+    for (int u = 0; u < kTpt; ++u) t[u] = load_target(fam, ti[u], x, y, z, hhi, hlo);
+    float best[kTpt];
+    uint32_t bid[kTpt];
+    float term[kTpt];
+    if (fam == kFamNear) {
+      relation_pass<kFamNear, WITH_ARG>(arow, n, tile0, ti, t, c, x, y, z, hhi, hlo, ids, rec, rid, best, bid);
+#pragma unroll
+      for (int u = 0; u < kTpt; ++u) {
+        term[u] = term_of<kFamNear>(best[u]);
+        lsum[u] += best[u];  // already log t
+      }
+    } else {
+      if (fam == kFamVert)
+        relation_pass<kFamVert, WITH_ARG>(arow, n, tile0, ti, t, c, x, y, z, hhi, hlo, ids, rec, rid, best, bid);
+      else
+        relation_pass<kFamLat, WITH_ARG>(arow, n, tile0, ti, t, c, x, y, z, hhi, hlo, ids, rec, rid, best, bid);
+#pragma unroll
+      for (int u = 0; u < kTpt; ++u) {
+        term[u] = term_of<kFamVert>(best[u]);
+        lsum[u] += logf(term[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kTpt; ++u) {
+      int64_t i = tile0 + threadIdx.x + u * kThreads;
+      if (i < n) {
+        if (rel_terms) rel_terms[(int64_t)r * n + i] = term[u];
+        if (WITH_ARG && rel_anchor_id) rel_anchor_id[(int64_t)r * n + i] = bid[u];
+      }
+    }
+  }
+  const int R = r1 - r0;
+#pragma unroll
+  for (int u = 0; u < kTpt; ++u) {
+    int64_t i = tile0 + threadIdx.x + u * kThreads;
+    if (i < n) {
+      float sem = sim[(int64_t)qq * ld_s + i];
+      float g = R > 0 ? expf(lsum[u] / (float)R) : 1.0f;
+      scores[(int64_t)qq * ld_out + i] = sem * ((1.0f - kW) + kW * g);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- explain
+// One block per (query, rank): recompute every relation's term and bound
+// anchor for the selected object with the same per-pair arithmetic as the
+// pass above (identical values), reducing (value, id) across the block.
+template <int FAM>
+__device__ void explain_relation(const float* __restrict__ arow, int64_t n, int64_t i, float c, const float* x,
+                                 const float* y, const float* z, const float* hhi, const float* hlo,
+                                 const uint32_t* ids, float* red_v, uint32_t* red_id, float& out_t,
+                                 uint32_t& out_b) {
+  Tgt t = load_target(FAM, i, x, y, z, hhi, hlo);
+  float best = value_floor<FAM>();
+  uint32_t bid = FARM_NO_ID;
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+    if (j == i) continue;
+    float4 r = anchor_record(FAM, arow[j], j, x, y, z, hhi, hlo);
+    float v = pair_value<FAM>(t, r, c);
+    uint32_t idj = ids[j];
+    if (v > best || (v == best && idj < bid && v != -INFINITY)) {
+      best = v;
+      bid = idj;
+    }
+  }
+  red_v[threadIdx.x] = best;
+  red_id[threadIdx.x] = bid;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      float v2 = red_v[threadIdx.x + w];
+      uint32_t b2 = red_id[threadIdx.x + w];
+      float v1 = red_v[threadIdx.x];
+      uint32_t b1 = red_id[threadIdx.x];
+      if (v2 > v1 || (v2 == v1 && b2 < b1)) {
+        red_v[threadIdx.x] = v2;
+        red_id[threadIdx.x] = b2;
+      }
+    }
+    __syncthreads();
+  }
+  out_t = term_of<FAM>(red_v[0]);
+  out_b = red_id[0];
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_explain(const float* __restrict__ sim, int64_t ld_s, int32_t q,
+                                                 MetaView meta, const int32_t* __restrict__ idx, int32_t k,
+                                                 const float* __restrict__ x, const float* __restrict__ y,
+                                                 const float* __restrict__ z, const float* __restrict__ hhi,
+                                                 const float* __restrict__ hlo, const uint32_t* __restrict__ ids,
+                                                 int64_t n, float* __restrict__ out_terms,
+                                                 uint32_t* __restrict__ out_anchor_id) {
+  __shared__ float red_v[256];
+  __shared__ uint32_t red_id[256];
+  const int32_t qq = blockIdx.y, kk = blockIdx.x;
+  const int64_t slot = (int64_t)qq * k + kk;
+  const int32_t i = idx[slot];
+  const int r0 = meta.rel_off[qq], r1 = meta.rel_off[qq + 1];
+  for (int e = 0; e < kMaxRel; ++e) {
+    float tv = 0.f;
+    uint32_t b = FARM_NO_ID;
+    if (i >= 0 && e < r1 - r0) {
+      const int r = r0 + e;
+      const int p = meta.rel_pred[r];
+      const float* arow = sim + (int64_t)(q + r) * ld_s;
+      const float c = sigmoid_scale(p);
+      switch (family_of(p)) {
+        case kFamNear: explain_relation<kFamNear>(arow, n, i, c, x, y, z, hhi, hlo, ids, red_v, red_id, tv, b); break;
+        case kFamVert: explain_relation<kFamVert>(arow, n, i, c, x, y, z, hhi, hlo, ids, red_v, red_id, tv, b); break;
+        default: explain_relation<kFamLat>(arow, n, i, c, x, y, z, hhi, hlo, ids, red_v, red_id, tv, b); break;
+      }
+    }
+    if (threadIdx.x == 0) {
+      if (out_terms) out_terms[slot * kMaxRel + e] = tv;
+      if (out_anchor_id) out_anchor_id[slot * kMaxRel + e] = b;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_pair_exhaustive(const farm_memory* mem, const float* sim, int64_t ld_s, int32_t q, MetaView meta,
+                                  float* scores, int64_t ld_out, float* rel_terms, uint32_t* rel_anchor_id,
+                                  hipStream_t s) {
+  if (q <= 0) return hipSuccess;
+  int64_t n = mem->n;
+  dim3 grid((unsigned)((n + kTile - 1) / kTile), (unsigned)q);
+  if (rel_anchor_id)
+    hipLaunchKernelGGL(k_pair_exhaustive<true>, grid, dim3(kThreads), 0, s, sim, ld_s, q, meta, mem->x, mem->y,
+                       mem->z, mem->hr_hi, mem->hr_lo, mem->id, n, scores, ld_out, rel_terms, rel_anchor_id);
+  else
+    hipLaunchKernelGGL(k_pair_exhaustive<false>, grid, dim3(kThreads), 0, s, sim, ld_s, q, meta, mem->x, mem->y,
+                       mem->z, mem->hr_hi, mem->hr_lo, mem->id, n, scores, ld_out, rel_terms, rel_anchor_id);
+  return hipGetLastError();
+}
+
+hipError_t launch_explain(const farm_memory* mem, const float* sim, int64_t ld_s, int32_t q, MetaView meta,
+                          const int32_t* idx, int32_t k, float* out_terms, uint32_t* out_anchor_id, hipStream_t s) {
+  if (q <= 0 || k <= 0 || (!out_terms && !out_anchor_id)) return hipSuccess;
+  dim3 grid((unsigned)k, (unsigned)q);
+  hipLaunchKernelGGL(k_explain, grid, dim3(256), 0, s, sim, ld_s, q, meta, idx, k, mem->x, mem->y, mem->z,
+                     mem->hr_hi, mem->hr_lo, mem->id, mem->n, out_terms, out_anchor_id);
+  return hipGetLastError();
+}
+
+}  // namespace farm

@@ -1,0 +1,198 @@
+// prep.hip -- building the device-resident memory and preparing query vectors.
+//
+// * Validation of a scene (finite descriptors and geometry, non-zero norms,
+//   positive extents, unique ids) in one pass plus a hash probe for ids.
+// * Row L2 normalisation into an FP32 master, with optional BF16 (round to
+//   nearest even) and OCP FP8 e4m3 (per-row scale amax/448, round to nearest
+//   even, saturating) copies; rows are zero-padded to a multiple of 32 so that
+//   the similarity GEMM never needs a K tail.
+// * Geometry in structure-of-arrays form, plus the lateral coordinate
+//   h = c . r (viewer right vector) as an unevaluated sum hi + lo of two floats
+//   computed with error-free transformations, so that lateral offsets
+//   h_i - h_j stay accurate to a few ulps of the offset itself even 100 m from
+//   the origin (LeftOf/RightOf evaluate a sigmoid of that offset divided by
+//   0.1 m).
+#include <math.h>
+
+#include "farm_internal.h"
+
+namespace farm {
+namespace {
+
+__device__ inline bool finitef(float v) { return isfinite(v); }
+
+__global__ void k_validate(const float* __restrict__ desc, const float* __restrict__ center,
+                           const float* __restrict__ extent, const uint32_t* __restrict__ id, int64_t n,
+                           int32_t d, int* __restrict__ flags, uint32_t* __restrict__ table, int64_t table_mask) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int bad = 0;
+  for (int k = 0; k < 3; ++k) {
+    float c = center[i * 3 + k];
+    float e = extent[i * 3 + k];
+    if (!finitef(c)) bad |= kBadCenter;
+    if (!finitef(e) || !(e > 0.f)) bad |= kBadExtent;
+  }
+  uint32_t v = id[i];
+  if (v == FARM_NO_ID) {
+    bad |= kBadId;
+  } else {
+    // open addressing with linear probing; the table holds FARM_NO_ID when empty
+    uint32_t h = v * 2654435761u;
+    int64_t slot = (int64_t)(h & (uint32_t)table_mask);
+    for (int64_t probe = 0; probe <= table_mask; ++probe) {
+      uint32_t prev = atomicCAS(&table[slot], FARM_NO_ID, v);
+      if (prev == FARM_NO_ID) break;
+      if (prev == v) { bad |= kDupId; break; }
+      slot = (slot + 1) & table_mask;
+    }
+  }
+  if (bad) atomicOr(flags, bad);
+  (void)desc;
+  (void)d;
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__device__ inline uint16_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// OCP FP8 e4m3 ("e4m3fn": bias 7, no infinities, max 448), round to nearest
+// even, saturating at +-448.
+__device__ inline uint8_t fp8_e4m3_rne(float f) {
+  uint8_t sign = (__float_as_uint(f) >> 31) ? 0x80 : 0x00;
+  float a = fabsf(f);
+  if (!(a < kFp8Max)) return sign | 0x7E;
+  if (a < 0.015625f) {                      // below 2^-6: subnormal grid of 2^-9
+    float m = rintf(a * 512.0f);            // exact scaling, RNE
+    return sign | (uint8_t)m;               // m == 8 is the smallest normal (code 0x08)
+  }
+  int e;
+  float fr = frexpf(a, &e);                 // a = fr * 2^e, fr in [0.5, 1)
+  float m = rintf((fr * 2.0f - 1.0f) * 8.0f);  // mantissa of 1.mmm, RNE
+  int ex = e - 1;
+  if (m >= 8.0f) { m = 0.0f; ex += 1; }
+  int code = ((ex + 7) << 3) | (int)m;
+  if (code > 0x7E) code = 0x7E;
+  return sign | (uint8_t)code;
+}
+
+// One block per row: L2 norm, then the FP32 / BF16 / FP8 copies.
+__global__ __launch_bounds__(256) void k_normalize_rows(const float* __restrict__ src, int64_t rows, int32_t d,
+                                                        int32_t ldk, float* __restrict__ dst,
+                                                        uint16_t* __restrict__ dst_bf16,
+                                                        uint8_t* __restrict__ dst_fp8,
+                                                        float* __restrict__ dst_scale, int* __restrict__ flags) {
+  __shared__ float red[256];
+  __shared__ int bad_sh;
+  int64_t row = blockIdx.x;
+  const float* s = src + row * (int64_t)d;
+  int tid = threadIdx.x;
+  if (tid == 0) bad_sh = 0;
+  __syncthreads();
+  float ss = 0.f, amax = 0.f;
+  bool bad = false;
+  for (int k = tid; k < d; k += 256) {
+    float v = s[k];
+    if (!isfinite(v)) bad = true;
+    ss = fmaf(v, v, ss);
+  }
+  if (bad) bad_sh = 1;
+  red[tid] = ss;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  float nrm = sqrtf(red[0]);
+  bool zero = !(nrm > 0.f) || !isfinite(nrm);
+  if (tid == 0 && (bad_sh || zero)) atomicOr(flags, bad_sh ? kBadDesc : kZeroNorm);
+  float inv = zero ? 0.f : 1.0f / nrm;
+  float* o = dst + row * (int64_t)ldk;
+  for (int k = tid; k < ldk; k += 256) {
+    float v = k < d ? s[k] * inv : 0.f;
+    if (zero) v = 0.f;
+    o[k] = v;
+    amax = fmaxf(amax, fabsf(v));
+    if (dst_bf16) dst_bf16[row * (int64_t)ldk + k] = bf16_rne(v);
+  }
+  if (!dst_fp8) return;
+  __syncthreads();
+  red[tid] = amax;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] = fmaxf(red[tid], red[tid + w]);
+    __syncthreads();
+  }
+  float scale = red[0] > 0.f ? red[0] / kFp8Max : 1.0f;
+  if (tid == 0) dst_scale[row] = scale;
+  for (int k = tid; k < ldk; k += 256) {
+    float v = o[k];
+    dst_fp8[row * (int64_t)ldk + k] = fp8_e4m3_rne(v / scale);
+  }
+}
+
+// Error-free transformations (Knuth two-sum, FMA two-product).
+__device__ inline void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+__global__ void k_geometry(const float* __restrict__ center, const float* __restrict__ extent, int64_t n, float rx,
+                           float ry, float* __restrict__ x, float* __restrict__ y, float* __restrict__ z,
+                           float* __restrict__ hhi, float* __restrict__ hlo, float* __restrict__ ext) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float cx = center[i * 3 + 0], cy = center[i * 3 + 1], cz = center[i * 3 + 2];
+  x[i] = cx;
+  y[i] = cy;
+  z[i] = cz;
+  float p1 = cx * rx, e1 = fmaf(cx, rx, -p1);
+  float p2 = cy * ry, e2 = fmaf(cy, ry, -p2);
+  float s, e3;
+  two_sum(p1, p2, s, e3);
+  float lo = e1 + e2 + e3;
+  float hi;
+  two_sum(s, lo, hi, lo);
+  hhi[i] = hi;
+  hlo[i] = lo;
+  for (int k = 0; k < 3; ++k) ext[k * n + i] = extent[i * 3 + k];
+}
+
+}  // namespace
+
+hipError_t launch_validate_memory(const float* desc, const float* center, const float* extent, const uint32_t* id,
+                                  int64_t n, int32_t d, int* flags, uint32_t* table, int64_t table_size,
+                                  hipStream_t s) {
+  int64_t blocks = (table_size + 255) / 256;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, table, table_size, FARM_NO_ID);
+  blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_validate, dim3((unsigned)blocks), dim3(256), 0, s, desc, center, extent, id, n, d, flags,
+                     table, table_size - 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalize_rows(const float* src, int64_t rows, int32_t d, int32_t ldk, float* dst_f32,
+                                 uint16_t* dst_bf16, uint8_t* dst_fp8, float* dst_scale, int* flags, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_normalize_rows, dim3((unsigned)rows), dim3(256), 0, s, src, rows, d, ldk, dst_f32, dst_bf16,
+                     dst_fp8, dst_scale, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_geometry(const float* center, const float* extent, int64_t n, float rx, float ry, float* x,
+                           float* y, float* z, float* hr_hi, float* hr_lo, float* ext, hipStream_t s) {
+  int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_geometry, dim3((unsigned)blocks), dim3(256), 0, s, center, extent, n, rx, ry, x, y, z, hr_hi,
+                     hr_lo, ext);
+  return hipGetLastError();
+}
+
+}  // namespace farm

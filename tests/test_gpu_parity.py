@@ -1,0 +1,344 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Element-wise comparisons at sizes the oracle finishes in seconds (several
+tiles and ragged tails), sampled comparisons at the full benchmark size, and
+the edge cases of the method (one object, no relations, eight relations, K > n,
+exact ties).  Criteria and their derivation: tests/_parity.py.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import CONFIGS, QueryBatch, Scene, make_queries, make_scene
+from tests import _golden
+from tests._parity import ABS, REL, assert_topk_valid, assert_values_close
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def farm():
+    import paper_2606_15476_amd as farm
+    return farm
+
+
+def _ws(farm, mem, qb, max_k=64):
+    return farm.Workspace(mem, max(qb.q, 1), max(qb.r_tot, 1), max_k)
+
+
+def _check_full(farm, scene, qb, label):
+    from tests import _gpu
+    mem = _gpu.build_memory(scene)
+    ws = _ws(farm, mem, qb)
+    s, t, b = _gpu.score_full(mem, ws, qb, terms=True)
+    s64, sem64, t64, b64 = oracle.score(scene, qb, terms=True)
+    print(f"[{label}] n={scene.n} d={scene.d} q={qb.q} R={qb.r_tot}", flush=True)
+    assert_values_close(s, s64, f"{label} scores")
+    if qb.r_tot:
+        assert_values_close(t, t64, f"{label} relation terms")
+        # every bound anchor attains its term (within tolerance), never the target itself
+        idx_of = {int(v): i for i, v in enumerate(scene.ids)}
+        rng = np.random.default_rng(0)
+        for r in range(qb.r_tot):
+            cols = rng.choice(scene.n, size=min(scene.n, 24), replace=False)
+            for i in cols:
+                if scene.n == 1:
+                    assert b[r, i] == 0xFFFFFFFF
+                    continue
+                j = idx_of[int(b[r, i])]
+                assert j != i
+                v = oracle.binding_value(scene, int(qb.rel_pred[r]), qb.rel_anchor[r], int(i), j)
+                assert abs(v - t64[r, i]) <= REL * t64[r, i] + ABS, (label, r, i)
+    return mem, ws, s64
+
+
+def _topk_against_full(farm, mem, ws, scene, qb, s64, k, label):
+    from tests import _gpu
+    ids, sc, terms, anch = _gpu.query_topk(mem, ws, qb, k)
+    for qq in range(qb.q):
+        order = oracle.topk(s64[qq], scene.ids, min(k + 8, scene.n))
+        o_ids = scene.ids[order[order >= 0]]
+        o_sc = s64[qq, order[order >= 0]]
+        by_id = {int(v): s64[qq, i] for i, v in enumerate(scene.ids)}
+        assert_topk_valid(ids[qq], sc[qq], o_ids, o_sc, lambda g: by_id[g], k)
+    return ids, sc, terms, anch
+
+
+# ---------------------------------------------------------------- golden scenes
+@pytest.mark.parametrize("path", _golden.all_paths(), ids=lambda p: p.rsplit("/", 1)[-1])
+def test_golden_scenes_gpu(farm, path):
+    from tests import _gpu
+    g, scene, queries = _golden.load(path)
+    mem = _gpu.build_memory(scene)
+    for qb, spec in queries:
+        ws = _ws(farm, mem, qb)
+        s, t, b = _gpu.score_full(mem, ws, qb, terms=True)
+        for sid, expr in spec["expect_score"].items():
+            i = int(np.flatnonzero(scene.ids == int(sid))[0])
+            assert s[0, i] == pytest.approx(_golden.evaluate(expr), rel=REL, abs=ABS), sid
+        for sid, anchors in spec.get("expect_anchor", {}).items():
+            i = int(np.flatnonzero(scene.ids == int(sid))[0])
+            assert [int(x) for x in b[:, i]] == anchors, sid
+        ids, sc, terms, anch = _gpu.query_topk(mem, ws, qb, len(spec["expect_order"]) + 2)
+        n_ok = len(spec["expect_order"])
+        assert [int(x) for x in ids[0, :n_ok]] == spec["expect_order"]
+        assert all(int(x) == 0xFFFFFFFF for x in ids[0, n_ok:])
+        for sid, anchors in spec.get("expect_anchor", {}).items():
+            r = spec["expect_order"].index(int(sid))
+            assert [int(x) for x in anch[0, r, :len(anchors)]] == anchors
+
+
+# ---------------------------------------------------------------- configs
+def test_tiny_config_full_parity(farm):
+    cfg = CONFIGS["tiny"]
+    scene = make_scene(cfg)
+    qb = make_queries(cfg, scene)
+    mem, ws, s64 = _check_full(farm, scene, qb, "tiny")
+    _topk_against_full(farm, mem, ws, scene, qb, s64, cfg.k, "tiny")
+
+
+def test_mid_config_subset_full_parity(farm):
+    cfg = CONFIGS["mid"]
+    scene = make_scene(cfg)
+    qb = make_queries(cfg, scene).subset(range(0, 256, 8))  # 32 queries, all predicate mixes
+    mem, ws, s64 = _check_full(farm, scene, qb, "mid/32")
+    ids, sc, terms, anch = _topk_against_full(farm, mem, ws, scene, qb, s64, cfg.k, "mid/32")
+    # ScoredCandidate breakdown: terms of the returned objects match the oracle's
+    idx_of = {int(v): i for i, v in enumerate(scene.ids)}
+    _, _, t64, _ = oracle.score(scene, qb, terms=True)
+    for qq in range(qb.q):
+        r0, r1 = qb.rel_off[qq], qb.rel_off[qq + 1]
+        for rank in range(cfg.k):
+            i = idx_of[int(ids[qq, rank])]
+            assert_values_close(terms[qq, rank, : r1 - r0], t64[r0:r1, i], "breakdown terms")
+            assert np.all(terms[qq, rank, r1 - r0:] == 0)
+            assert np.all(anch[qq, rank, r1 - r0:] == 0xFFFFFFFF)
+
+
+def test_mid_config_topk_all_queries(farm):
+    from tests import _gpu
+    cfg = CONFIGS["mid"]
+    scene = make_scene(cfg)
+    qb = make_queries(cfg, scene)
+    mem = _gpu.build_memory(scene)
+    ws = _ws(farm, mem, qb)
+    ids, sc, terms, anch = _gpu.query_topk(mem, ws, qb, cfg.k)
+    oidx, osc, ot, ob, ns = oracle.topk_bounded(scene, qb, cfg.k + 8)
+    _check_bounded(scene, qb, ids, sc, oidx, osc, cfg.k)
+
+
+def _check_bounded(scene, qb, ids, sc, oidx, osc, k, rows=None):
+    rows = range(qb.q) if rows is None else rows
+    for row, qq in enumerate(rows):
+        o_ids = scene.ids[oidx[row][oidx[row] >= 0]]
+        o_sc = osc[row][oidx[row] >= 0]
+        known = {int(a): float(b) for a, b in zip(o_ids, o_sc)}
+
+        def lookup(g, qq=qq, known=known):
+            if g in known:
+                return known[g]
+            i = int(np.flatnonzero(scene.ids == g)[0])
+            return float(oracle.score_pairs(scene, qb, np.array([qq], np.int32), np.array([i], np.int64))[0][0])
+
+        assert_topk_valid(ids[qq], sc[qq], o_ids, o_sc, lookup, k)
+
+
+# ---------------------------------------------------------------- full size (benchmark launch shape)
+@pytest.fixture(scope="module")
+def precision_world():
+    cfg = CONFIGS["precision"]
+    scene = make_scene(cfg)
+    qb = make_queries(cfg, scene)
+    return cfg, scene, qb
+
+
+def test_precision_config_sampled_topk(farm, precision_world):
+    """N = 20,000, D = 1,152, 4,096 queries in one launch, as the benchmark times it;
+    16 sampled queries are checked against the oracle's exact TopK."""
+    from tests import _gpu
+    cfg, scene, qb = precision_world
+    mem = _gpu.build_memory(scene)
+    ws = farm.Workspace(mem, qb.q, qb.r_tot, 64)
+    print(f"[precision] query_topk n={scene.n} q={qb.q} R={qb.r_tot}", flush=True)
+    ids, sc, terms, anch = _gpu.query_topk(mem, ws, qb, cfg.k)
+    rows = list(np.random.default_rng(7).choice(qb.q, size=16, replace=False))
+    sub = qb.subset(rows)
+    oidx, osc, ot, ob, ns = oracle.topk_bounded(scene, sub, cfg.k + 6)
+    sub_ids = ids[rows]
+    sub_sc = sc[rows]
+    _check_bounded(scene, sub, sub_ids, sub_sc, oidx, osc, cfg.k)
+    # breakdown of the winners
+    idx_of = {int(v): i for i, v in enumerate(scene.ids)}
+    for row, qq in enumerate(rows):
+        r = int(qb.rel_off[qq + 1] - qb.rel_off[qq])
+        for rank in range(cfg.k):
+            if int(sub_ids[row, rank]) == int(scene.ids[oidx[row, rank]]):
+                assert_values_close(terms[qq, rank, :r], ot[row, rank, :r], "winner terms")
+
+
+def test_precision_config_sampled_full_scores(farm, precision_world):
+    """farm_score_query at N = 20,000 for 32 queries; 2,048 sampled (query, object) scores."""
+    from tests import _gpu
+    cfg, scene, qb = precision_world
+    sub = qb.subset(range(0, 4096, 128))
+    mem = _gpu.build_memory(scene)
+    ws = farm.Workspace(mem, sub.q, sub.r_tot, 16)
+    s, t, b = _gpu.score_full(mem, ws, sub, terms=True)
+    rng = np.random.default_rng(3)
+    qsel = rng.integers(0, sub.q, 2048).astype(np.int32)
+    osel = rng.integers(0, scene.n, 2048).astype(np.int64)
+    ps, psem, pt, pb = oracle.score_pairs(scene, sub, qsel, osel)
+    assert_values_close(s[qsel, osel], ps, "sampled scores")
+    for m in range(0, 2048, 7):
+        qq, i = qsel[m], osel[m]
+        r0, r1 = sub.rel_off[qq], sub.rel_off[qq + 1]
+        assert_values_close(t[r0:r1, i], pt[m, : r1 - r0], "sampled terms")
+
+
+# ---------------------------------------------------------------- edge cases
+def _random_scene(n, d, seed, n_cat=5):
+    rng = np.random.default_rng(seed)
+    cent = rng.standard_normal((n_cat, d))
+    cls = rng.integers(0, n_cat, n).astype(np.int32)
+    desc = cent[cls] + 0.3 * rng.standard_normal((n, d))
+    return Scene(desc=desc.astype(np.float32), center=rng.uniform(0, 6, (n, 3)).astype(np.float32),
+                 extent=np.full((n, 3), 0.4, np.float32),
+                 ids=(rng.permutation(4 * n)[:n] + 1).astype(np.uint32), cls=cls,
+                 view_right=np.array([0.8, -0.6], np.float32), centroids=cent.astype(np.float32))
+
+
+def _random_queries(scene, q, rs, seed):
+    rng = np.random.default_rng(seed)
+    d = scene.d
+    offs = [0]
+    preds = []
+    for k in range(q):
+        for _ in range(rs[k % len(rs)]):
+            preds.append(int(rng.integers(0, 5)))
+        offs.append(len(preds))
+    return QueryBatch(target=rng.standard_normal((q, d)).astype(np.float32),
+                      target_cls=rng.integers(-1, 5, q).astype(np.int32), rel_off=np.asarray(offs, np.int32),
+                      rel_pred=np.asarray(preds, np.int32),
+                      rel_anchor=rng.standard_normal((len(preds), d)).astype(np.float32).reshape(len(preds), d),
+                      planted=np.zeros(q, np.int64))
+
+
+@pytest.mark.parametrize("n,d,rs", [(1, 8, [1, 0]), (2, 4, [2]), (513, 100, [0, 1, 8]), (1029, 36, [3, 5]),
+                                    (4099, 64, [1, 2])])
+def test_edge_shapes(farm, n, d, rs):
+    scene = _random_scene(n, d, seed=n + d)
+    qb = _random_queries(scene, 6, rs, seed=n)
+    mem, ws, s64 = _check_full(farm, scene, qb, f"edge n={n} d={d}")
+    _topk_against_full(farm, mem, ws, scene, qb, s64, 10, "edge")
+
+
+def test_k_larger_than_n_pads(farm):
+    from tests import _gpu
+    scene = _random_scene(7, 16, seed=1)
+    qb = _random_queries(scene, 3, [1], seed=2)
+    mem = _gpu.build_memory(scene)
+    ws = _ws(farm, mem, qb)
+    ids, sc, terms, anch = _gpu.query_topk(mem, ws, qb, 12)
+    s64 = oracle.score(scene, qb)
+    for qq in range(qb.q):
+        want = scene.ids[oracle.topk(s64[qq], scene.ids, 7)]
+        assert [int(x) for x in ids[qq, :7]] == [int(x) for x in want]
+        assert np.all(ids[qq, 7:] == 0xFFFFFFFF) and np.all(np.isneginf(sc[qq, 7:]))
+        assert np.all(anch[qq, 7:] == 0xFFFFFFFF)
+
+
+def test_topk_exact_ties_break_by_id(farm):
+    """farm_topk alone: equal scores ordered by ascending id, ids in reverse storage order."""
+    import torch
+    from tests import _gpu
+    n = 5000
+    scene = _random_scene(n, 8, seed=5)
+    scene.ids = (np.arange(n, 0, -1) * 3).astype(np.uint32)  # descending ids
+    mem = _gpu.build_memory(scene)
+    ws = farm.Workspace(mem, 4, 1, 64)
+    rng = np.random.default_rng(0)
+    scores = np.round(rng.uniform(0, 1, (4, n)), 2).astype(np.float32)  # heavy ties
+    scores[1] = 0.5
+    scores[2, :10] = -np.inf
+    dev = _gpu.to_dev(scores)
+    for k in (1, 10, 64):
+        oid = torch.empty((4, k), dtype=torch.int32, device="cuda")
+        osc = torch.empty((4, k), dtype=torch.float32, device="cuda")
+        oix = torch.empty((4, k), dtype=torch.int32, device="cuda")
+        farm.topk(mem, ws, dev, k, oid, osc, oix)
+        torch.cuda.synchronize()
+        got = oid.cpu().numpy().view(np.uint32)
+        for qq in range(4):
+            want = np.lexsort((scene.ids, -scores[qq]))[:k]
+            assert list(got[qq]) == list(scene.ids[want])
+            assert list(oix.cpu().numpy()[qq]) == list(want)
+            np.testing.assert_array_equal(osc.cpu().numpy()[qq], scores[qq, want])
+
+
+def test_deterministic(farm):
+    from tests import _gpu
+    cfg = CONFIGS["mid"]
+    scene = make_scene(cfg, n=3000)
+    qb = make_queries(cfg, scene, q=16)
+    mem = _gpu.build_memory(scene)
+    ws = _ws(farm, mem, qb)
+    a = _gpu.score_full(mem, ws, qb, terms=True)
+    b = _gpu.score_full(mem, ws, qb, terms=True)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+# ---------------------------------------------------------------- invalid input
+def test_invalid_scenes_rejected(farm):
+    from tests import _gpu
+    base = _random_scene(50, 8, seed=9)
+
+    def variant(**kw):
+        s = Scene(desc=base.desc.copy(), center=base.center.copy(), extent=base.extent.copy(), ids=base.ids.copy(),
+                  cls=base.cls.copy(), view_right=base.view_right, centroids=base.centroids)
+        for k, v in kw.items():
+            getattr(s, k)[...] = v
+        return s
+
+    bad = []
+    s = variant(); s.ids[7] = s.ids[3]; bad.append(("duplicate id", s))
+    s = variant(); s.desc[5, 2] = np.nan; bad.append(("non-finite", s))
+    s = variant(); s.desc[4] = 0.0; bad.append(("zero-norm", s))
+    s = variant(); s.extent[1, 0] = 0.0; bad.append(("extent", s))
+    s = variant(); s.ids[0] = 0xFFFFFFFF; bad.append(("reserved id", s))
+    for what, sc in bad:
+        with pytest.raises(farm.FarmError) as e:
+            _gpu.build_memory(sc)
+        assert e.value.status == -1, what
+
+
+def test_invalid_queries_rejected(farm):
+    import torch
+    from tests import _gpu
+    scene = _random_scene(40, 8, seed=11)
+    mem = _gpu.build_memory(scene)
+    ws = farm.Workspace(mem, 4, 40, 16)
+    qb = _random_queries(scene, 2, [1], seed=3)
+    target, anchors = _gpu.query_tensors(qb)
+    out = torch.empty((2, 40), dtype=torch.float32, device="cuda")
+    with pytest.raises(farm.FarmError):
+        farm.score_query(mem, ws, target, None, qb.rel_off, np.array([0, 7], np.int32), anchors, out)
+    with pytest.raises(farm.FarmError):  # nine relations
+        farm.score_query(mem, ws, target[:1], None, np.array([0, 9], np.int32), np.zeros(9, np.int32),
+                         torch.ones((9, 8), device="cuda"), out)
+    with pytest.raises(farm.FarmError):  # width mismatch
+        farm.score_query(mem, ws, torch.ones((2, 9), device="cuda"), None, qb.rel_off, qb.rel_pred,
+                         torch.ones((2, 9), device="cuda"), out)
+    oid = torch.empty((2, 4), dtype=torch.int32, device="cuda")
+    osc = torch.empty((2, 4), dtype=torch.float32, device="cuda")
+    with pytest.raises(farm.FarmError):
+        farm.query_topk(mem, ws, target, None, qb.rel_off, qb.rel_pred, anchors, 0, oid, osc)
+    # zero-norm query vector: reported by the status call, other rows unaffected
+    t2 = target.clone()
+    t2[1] = 0
+    farm.score_query(mem, ws, t2, None, qb.rel_off, qb.rel_pred, anchors, out)
+    with pytest.raises(farm.FarmError):
+        ws.status()
+    ws.status()  # cleared
