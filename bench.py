@@ -44,6 +44,23 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def recorded_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed counter record, or
+    None when there is none for this workload or the kernel's source file has
+    changed since the counters were taken (sha256 prefix mismatch)."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))["kernels"][kernel]
+    except (OSError, KeyError, ValueError):
+        return None
+    if rec.get("workload") != workload:
+        return None
+    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    if hashlib.sha256(src).hexdigest()[:16] != rec["sha256_prefix"]:
+        return None
+    return float(rec["bytes_per_launch"])
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -54,11 +71,29 @@ def parse():
     p.add_argument("--k", type=int, default=10)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=0, help="queries in the CPU-oracle sample (0 = auto)")
+    p.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                   help="only run one plain device copy of BYTES (reference for the HBM byte counters) and exit")
     return p.parse_args()
+
+
+def copy_calibration(nbytes):
+    """One device-to-device copy kernel of a known size: the byte counters of a
+    profiler pass over it give the factor between counter units and bytes."""
+    import torch
+    n = nbytes // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read": n * 4, "bytes_written": n * 4}}), flush=True)
 
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU layout is design-only "
               "in this build.", file=sys.stderr)
@@ -128,7 +163,7 @@ def main():
         achieved = flop_pair / avg_s / 1e12
         roofline = {"bound": "alu", "kernel": "k_pair_exhaustive", "achieved": round(achieved, 3),
                     "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
-                    "traffic": None, "pair_evals_per_launch": pairs_per_launch,
+                    "traffic": recorded_traffic("k_pair_exhaustive", cfg.name), "pair_evals_per_launch": pairs_per_launch,
                     "avg_launch_ms": round(avg_s * 1e3, 3)}
     else:
         avg_s = gemm_ms / max(gemm_n, 1) / 1e3
@@ -136,7 +171,8 @@ def main():
         achieved = flop / avg_s / 1e12
         peak = PEAK_MFMA_TFLOPS[args.form]
         roofline = {"bound": "mfma", "kernel": "k_sim_gemm_" + args.form, "achieved": round(achieved, 2),
-                    "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                    "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                    "traffic": recorded_traffic("k_sim_gemm_" + args.form, cfg.name),
                     "avg_launch_ms": round(avg_s * 1e3, 3)}
     phase_ms = {p: round(v[0] / max(v[1], 1), 3) for p, v in phases.items() if v[1]}
 
