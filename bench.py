@@ -67,7 +67,8 @@ def parse():
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="precision")
-    p.add_argument("--form", default="f32", choices=["f32"])
+    p.add_argument("--form", default="f32", choices=["f32", "bf16", "fp8"])
+    p.add_argument("--rescore-mult", type=int, default=4)
     p.add_argument("--k", type=int, default=10)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=0, help="queries in the CPU-oracle sample (0 = auto)")
@@ -113,7 +114,7 @@ def main():
     torch.cuda.set_device(dev)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     mem = farm.Memory(t(scene.desc), t(scene.center), t(scene.extent), t(scene.ids.view(np.int32)), t(scene.cls),
-                      scene.view_right)
+                      scene.view_right, flags=farm.FARM_BUILD_BF16 | farm.FARM_BUILD_FP8)
     ws = farm.Workspace(mem, qb.q, qb.r_tot, 64)
     target, anchors = t(qb.target), t(qb.rel_anchor)
     k = args.k
@@ -121,11 +122,12 @@ def main():
     osc = torch.empty((qb.q, k), dtype=torch.float32, device=dev)
     ot = torch.empty((qb.q, k, 8), dtype=torch.float32, device=dev)
     ob = torch.empty((qb.q, k, 8), dtype=torch.int32, device=dev)
-    dtype = {"f32": farm.F32}[args.form]
+    dtype = {"f32": farm.F32, "bf16": farm.BF16, "fp8": farm.FP8_E4M3}[args.form]
+    cert = torch.zeros((qb.q,), dtype=torch.int32, device=dev)
 
     def step():
         farm.query_topk(mem, ws, target, qb.target_cls, qb.rel_off, qb.rel_pred, anchors, k, oid, osc, ot, ob,
-                        dtype=dtype)
+                        dtype=dtype, rescore_mult=args.rescore_mult, certified=cert)
 
     for w in range(args.warmup):
         step()
@@ -149,12 +151,24 @@ def main():
     ws.set_timing(False)
     ws.status()
 
+    certified = int((cert.cpu().numpy() == 1).sum())
+    recall_exact = None
+    if dtype != farm.F32:
+        # Recall@K of this form against the exact FP32 path over the whole batch
+        xid = torch.empty_like(oid)
+        xsc = torch.empty_like(osc)
+        farm.query_topk(mem, ws, target, qb.target_cls, qb.rel_off, qb.rel_pred, anchors, k, xid, xsc)
+        torch.cuda.synchronize()
+        a, b = oid.cpu().numpy(), xid.cpu().numpy()
+        recall_exact = float(np.mean([len(set(a[i]) & set(b[i])) / k for i in range(qb.q)]))
+        log(f"[bench] recall@{k} vs exact FP32 path: {recall_exact:.5f}; certified {certified}/{qb.q}")
+
     qps = qb.q * args.steps / elapsed
     ms_step = elapsed / args.steps * 1e3
     # dominant kernel: the relational pass
     pair_ms, pair_n = phases["pair"]
     gemm_ms, gemm_n = phases["gemm"]
-    dominant = "pair" if pair_ms >= gemm_ms else "gemm"
+    dominant = max(("pair", "gemm"), key=lambda p: phases[p][0])
     n = scene.n
     pairs_per_launch = float(qb.r_tot) * n * (n - 1)
     flop_pair = sum(FLOP_PER_PAIR[int(p)] for p in qb.rel_pred) * float(n) * (n - 1)
@@ -170,7 +184,7 @@ def main():
         flop = 2.0 * (qb.q + qb.r_tot) * n * scene.d
         achieved = flop / avg_s / 1e12
         peak = PEAK_MFMA_TFLOPS[args.form]
-        roofline = {"bound": "mfma", "kernel": "k_sim_gemm_" + args.form, "achieved": round(achieved, 2),
+        roofline = {"bound": "mfma", "kernel": "k_sim_gemm<" + args.form + ">", "achieved": round(achieved, 2),
                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                     "traffic": recorded_traffic("k_sim_gemm_" + args.form, cfg.name),
                     "avg_launch_ms": round(avg_s * 1e3, 3)}
@@ -193,10 +207,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": {"f32": "f32", "bf16": "bf16 GEMM, f32 relational pass and rescoring",
+                  "fp8": "fp8-e4m3 GEMM, f32 relational pass and rescoring"}[args.form],
         "data": "synthetic (seeded scene generator; the paper's datasets are not used)",
         "config": {"workload": f"{cfg.name}: N={scene.n} objects, D={scene.d}, Q={qb.q} queries, "
-                               f"R~U{{{cfg.r_min}..{cfg.r_max}}} (R_tot={qb.r_tot}), K={k}, exhaustive FP32",
+                               f"R~U{{{cfg.r_min}..{cfg.r_max}}} (R_tot={qb.r_tot}), K={k}",
                    "form": args.form, "global_batch": qb.q, "parallelism": "none (1 GPU)"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
                        "what": "whole-batch latency of one step"},
@@ -204,6 +219,11 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "recall_at_10_vs_oracle": recall,
+        "recall_at_10_vs_exact_f32": recall_exact,
+        "certified_queries": certified,
+        "form": {"f32": "exhaustive FP32 (plain method)",
+                 "bf16": f"BF16 GEMM + exhaustive upper-bound pass + FP32 rescoring of top {args.rescore_mult}K",
+                 "fp8": f"FP8 GEMM + exhaustive upper-bound pass + FP32 rescoring of top {args.rescore_mult}K"}[args.form],
     }
     print(json.dumps(out), flush=True)
 

@@ -163,6 +163,8 @@ FARM_API farm_status farm_topk(const farm_memory* mem, farm_workspace* ws, const
 typedef struct {
   int32_t dtype;        /* farm_dtype of the similarity GEMM (FARM_F32 = exact path) */
   int32_t rescore_mult; /* reduced precision: rescore the top rescore_mult*k in FP32 (>= 1) */
+  int32_t* certified;   /* device [q] out or NULL: 1 when the returned set is provably
+                           the exact TopK (always 1 on the FP32 path), else 0 */
 } farm_score_opts;
 
 /*
@@ -178,9 +180,13 @@ typedef struct {
  *   out_anchor_id device [q][k][FARM_MAX_REL] uint32 b_r (FARM_NO_ID beyond R),
  *                 or NULL
  * With a reduced-precision dtype the similarity GEMM runs in BF16 or FP8
- * e4m3 (per-row scales) and the top rescore_mult*k candidates are rescored
- * in FP32 before the final TopK; the memory must have been built with the
- * matching FARM_BUILD_* flag.
+ * e4m3 (per-row scales); the relational pass then scores every object with an
+ * upper bound of its score (each similarity raised by a proven bound on its
+ * rounding error), the top rescore_mult*k objects by that bound are rescored
+ * in FP32 (exact target similarity; per relation, FP32 similarities for every
+ * anchor that could attain the maximum) and the TopK is taken among them.
+ * The memory must have been built with the matching FARM_BUILD_* flag and the
+ * workspace's max_k must cover rescore_mult*k.
  */
 FARM_API farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t q, int32_t d,
                             const float* target, const int32_t* target_cls, const int32_t* rel_off,

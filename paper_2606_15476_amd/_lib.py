@@ -35,7 +35,7 @@ class FarmError(RuntimeError):
 
 
 class ScoreOpts(ctypes.Structure):
-    _fields_ = [("dtype", ctypes.c_int32), ("rescore_mult", ctypes.c_int32)]
+    _fields_ = [("dtype", ctypes.c_int32), ("rescore_mult", ctypes.c_int32), ("certified", ctypes.c_void_p)]
 
 
 def lib_path() -> str:

@@ -92,14 +92,15 @@ size_t workspace_bytes_for(const farm_memory* mem, int32_t max_q, int32_t max_re
   size_t ld_s = (size_t)round_up(mem->n, kRowAlign);
   size_t b = 0;
   b += rows * mem->ldk * sizeof(float);                    // qn
-  if (mem->dn_bf16) b += rows * mem->ldk * sizeof(uint16_t);
-  if (mem->dn_fp8) b += rows * mem->ldk + rows * sizeof(float);
+  if (mem->dn_bf16) b += rows * mem->ldk * sizeof(uint16_t) + 2 * rows * sizeof(float);
+  if (mem->dn_fp8) b += rows * mem->ldk + 3 * rows * sizeof(float);
   b += rows * ld_s * sizeof(float);                         // sim
-  b += (size_t)max_q * ld_s * sizeof(float);                // scores
+  b += (size_t)max_q * ld_s * sizeof(float) * ((mem->dn_bf16 || mem->dn_fp8) ? 2 : 1);  // scores (+ bounds)
   b += (size_t)(2 * max_q + 1 + 2 * (size_t)max_rel) * sizeof(int32_t);
   b += sizeof(int);
-  b += 2 * (size_t)topk_candidate_capacity(mem->n, max_q, max_k) * (sizeof(uint64_t) + sizeof(int32_t));
-  b += (size_t)max_q * max_k * sizeof(int32_t);
+  b += 2 * (size_t)topk_candidate_capacity(mem->n, max_q, max_k + 1) * (sizeof(uint64_t) + sizeof(int32_t));
+  b += 2 * sizeof(float);
+  b += (size_t)max_q * max_k * (sizeof(int32_t) + sizeof(float) + kMaxRel * (sizeof(float) + sizeof(uint32_t)));
   return b;
 }
 
@@ -186,22 +187,57 @@ farm_status stage_meta(farm_workspace* ws, int32_t q, int32_t R, const int32_t* 
   return FARM_OK;
 }
 
-// Steps 2 and 3: normalised query rows and the FP32 similarity matrix.
-farm_status similarities_f32(const farm_memory* mem, farm_workspace* ws, int32_t q, int32_t R, const float* target,
-                             const float* rel_anchor, const MetaView& meta, hipStream_t s) {
+// Error-bound accumulation term of a reduced-precision similarity: FP32
+// accumulation of the GEMM and of the FP32 reference dot products (each at
+// most ldk * 2^-24 for unit vectors), with margin for the normalisation.
+float accumulation_bound(int32_t ldk) { return 2.02f * (float)ldk * 5.9604645e-8f + 1e-6f; }
+
+// Steps 2 and 3: normalised query rows and the similarity matrix in `dtype`.
+farm_status similarities(const farm_memory* mem, farm_workspace* ws, int32_t q, int32_t R, const float* target,
+                         const float* rel_anchor, const MetaView& meta, int32_t dtype, SimBound* bound,
+                         hipStream_t s) {
   const int32_t ldk = mem->ldk;
+  LowPrecRows lt, la;
+  if (dtype == FARM_BF16) {
+    lt.bf16 = ws->qn_bf16;
+    lt.err_bf16 = ws->qerr_bf16;
+    lt.nrm_bf16 = ws->qnrm_bf16;
+  } else if (dtype == FARM_FP8_E4M3) {
+    lt.fp8 = ws->qn_fp8;
+    lt.fp8_scale = ws->qn_scale;
+    lt.err_fp8 = ws->qerr_fp8;
+    lt.nrm_fp8 = ws->qnrm_fp8;
+  }
+  la = lt;
+  const int64_t off = (int64_t)q * ldk;
+  if (la.bf16) la.bf16 += off;
+  if (la.fp8) la.fp8 += off;
+  if (la.fp8_scale) la.fp8_scale += q;
+  if (la.err_bf16) { la.err_bf16 += q; la.nrm_bf16 += q; }
+  if (la.err_fp8) { la.err_fp8 += q; la.nrm_fp8 += q; }
   {
     PhaseTimer t(ws, s, FARM_PHASE_NORMALIZE);
-    FARM_HIP(launch_normalize_rows(target, q, mem->d, ldk, ws->qn, nullptr, nullptr, nullptr, ws->status, s),
-             "normalize targets");
-    FARM_HIP(launch_normalize_rows(rel_anchor, R, mem->d, ldk, ws->qn + (int64_t)q * ldk, nullptr, nullptr,
-                                   nullptr, ws->status, s),
+    FARM_HIP(launch_normalize_rows(target, q, mem->d, ldk, ws->qn, lt, ws->status, s), "normalize targets");
+    FARM_HIP(launch_normalize_rows(rel_anchor, R, mem->d, ldk, ws->qn + off, la, ws->status, s),
              "normalize anchors");
   }
   PhaseTimer t(ws, s, FARM_PHASE_GEMM);
-  FARM_HIP(launch_sim_gemm_f32(ws->qn, mem->dn, (int64_t)q + R, mem->n, ldk, ws->sim, ws->ld_s, meta.tcls, q,
-                               mem->cls, s),
-           "similarity GEMM");
+  *bound = SimBound{};
+  const int64_t rows = (int64_t)q + R;
+  if (dtype == FARM_F32) {
+    FARM_HIP(launch_sim_gemm_f32(ws->qn, mem->dn, rows, mem->n, ldk, ws->sim, ws->ld_s, meta.tcls, q, mem->cls, s),
+             "similarity GEMM");
+  } else if (dtype == FARM_BF16) {
+    FARM_HIP(launch_sim_gemm_bf16(ws->qn_bf16, mem->dn_bf16, rows, mem->n, ldk, ws->sim, ws->ld_s, meta.tcls, q,
+                                  mem->cls, s),
+             "BF16 similarity GEMM");
+    *bound = SimBound{ws->qnrm_bf16, ws->qerr_bf16, mem->err_bf16, mem->err_max, accumulation_bound(ldk)};
+  } else {
+    FARM_HIP(launch_sim_gemm_fp8(ws->qn_fp8, ws->qn_scale, mem->dn_fp8, mem->dn_scale, rows, mem->n, ldk, ws->sim,
+                                 ws->ld_s, meta.tcls, q, mem->cls, s),
+             "FP8 similarity GEMM");
+    *bound = SimBound{ws->qnrm_fp8, ws->qerr_fp8, mem->err_fp8, mem->err_max + 1, accumulation_bound(ldk)};
+  }
   return FARM_OK;
 }
 
@@ -251,12 +287,18 @@ farm_status farm_build_memory(int64_t n, int32_t d, const float* desc, const flo
     farm_status st = FARM_OK;
     const size_t nn = (size_t)n;
     if ((st = dalloc(mem->allocs, mem->bytes, &mem->dn, nn * mem->ldk, "descriptors"))) return fail(st);
-    if (flags & FARM_BUILD_BF16)
+    if (flags & FARM_BUILD_BF16) {
       if ((st = dalloc(mem->allocs, mem->bytes, &mem->dn_bf16, nn * mem->ldk, "BF16 descriptors"))) return fail(st);
+      if ((st = dalloc(mem->allocs, mem->bytes, &mem->err_bf16, nn, "BF16 error norms"))) return fail(st);
+      if ((st = dalloc(mem->allocs, mem->bytes, &mem->nrm_bf16, nn, "BF16 norms"))) return fail(st);
+    }
     if (flags & FARM_BUILD_FP8) {
       if ((st = dalloc(mem->allocs, mem->bytes, &mem->dn_fp8, nn * mem->ldk, "FP8 descriptors"))) return fail(st);
       if ((st = dalloc(mem->allocs, mem->bytes, &mem->dn_scale, nn, "FP8 scales"))) return fail(st);
+      if ((st = dalloc(mem->allocs, mem->bytes, &mem->err_fp8, nn, "FP8 error norms"))) return fail(st);
+      if ((st = dalloc(mem->allocs, mem->bytes, &mem->nrm_fp8, nn, "FP8 norms"))) return fail(st);
     }
+    if ((st = dalloc(mem->allocs, mem->bytes, &mem->err_max, 2, "error maxima"))) return fail(st);
     if ((st = dalloc(mem->allocs, mem->bytes, &mem->x, nn, "x"))) return fail(st);
     if ((st = dalloc(mem->allocs, mem->bytes, &mem->y, nn, "y"))) return fail(st);
     if ((st = dalloc(mem->allocs, mem->bytes, &mem->z, nn, "z"))) return fail(st);
@@ -281,9 +323,20 @@ farm_status farm_build_memory(int64_t n, int32_t d, const float* desc, const flo
     if ((e = hipMemsetAsync(d_flags, 0, sizeof(int), s)) != hipSuccess) return fail_tmp(hip_fail(e, "memset"));
     if ((e = launch_validate_memory(desc, center, extent, id, n, d, d_flags, table, tsize, s)) != hipSuccess)
       return fail_tmp(hip_fail(e, "validate"));
-    if ((e = launch_normalize_rows(desc, n, d, mem->ldk, mem->dn, mem->dn_bf16, mem->dn_fp8, mem->dn_scale, d_flags,
-                                   s)) != hipSuccess)
+    LowPrecRows lp;
+    lp.bf16 = mem->dn_bf16;
+    lp.err_bf16 = mem->err_bf16;
+    lp.nrm_bf16 = mem->nrm_bf16;
+    lp.fp8 = mem->dn_fp8;
+    lp.fp8_scale = mem->dn_scale;
+    lp.err_fp8 = mem->err_fp8;
+    lp.nrm_fp8 = mem->nrm_fp8;
+    if ((e = launch_normalize_rows(desc, n, d, mem->ldk, mem->dn, lp, d_flags, s)) != hipSuccess)
       return fail_tmp(hip_fail(e, "normalize descriptors"));
+    if (mem->err_bf16 && (e = launch_max_reduce(mem->err_bf16, n, mem->err_max, s)) != hipSuccess)
+      return fail_tmp(hip_fail(e, "error maximum"));
+    if (mem->err_fp8 && (e = launch_max_reduce(mem->err_fp8, n, mem->err_max + 1, s)) != hipSuccess)
+      return fail_tmp(hip_fail(e, "error maximum"));
     if ((e = launch_geometry(center, extent, n, view_right_x, view_right_y, mem->x, mem->y, mem->z, mem->hr_hi,
                              mem->hr_lo, mem->ext, s)) != hipSuccess)
       return fail_tmp(hip_fail(e, "geometry"));
@@ -366,23 +419,36 @@ farm_status farm_workspace_create(const farm_memory* mem, int32_t max_q, int32_t
     const size_t rows = (size_t)max_q + (size_t)max_rel;
     farm_status st;
     if ((st = dalloc(ws->allocs, ws->bytes, &ws->qn, rows * mem->ldk, "query vectors"))) return fail(st);
-    if (mem->dn_bf16 && (st = dalloc(ws->allocs, ws->bytes, &ws->qn_bf16, rows * mem->ldk, "BF16 query vectors")))
-      return fail(st);
+    if (mem->dn_bf16) {
+      if ((st = dalloc(ws->allocs, ws->bytes, &ws->qn_bf16, rows * mem->ldk, "BF16 query vectors"))) return fail(st);
+      if ((st = dalloc(ws->allocs, ws->bytes, &ws->qerr_bf16, rows, "BF16 query error norms"))) return fail(st);
+      if ((st = dalloc(ws->allocs, ws->bytes, &ws->qnrm_bf16, rows, "BF16 query norms"))) return fail(st);
+    }
     if (mem->dn_fp8) {
       if ((st = dalloc(ws->allocs, ws->bytes, &ws->qn_fp8, rows * mem->ldk, "FP8 query vectors"))) return fail(st);
       if ((st = dalloc(ws->allocs, ws->bytes, &ws->qn_scale, rows, "FP8 query scales"))) return fail(st);
+      if ((st = dalloc(ws->allocs, ws->bytes, &ws->qerr_fp8, rows, "FP8 query error norms"))) return fail(st);
+      if ((st = dalloc(ws->allocs, ws->bytes, &ws->qnrm_fp8, rows, "FP8 query norms"))) return fail(st);
     }
     if ((st = dalloc(ws->allocs, ws->bytes, &ws->sim, rows * ws->ld_s, "similarity matrix"))) return fail(st);
     if ((st = dalloc(ws->allocs, ws->bytes, &ws->scores, (size_t)max_q * ws->ld_s, "scores"))) return fail(st);
+    if ((mem->dn_bf16 || mem->dn_fp8) &&
+        (st = dalloc(ws->allocs, ws->bytes, &ws->scores_hi, (size_t)max_q * ws->ld_s, "score bounds")))
+      return fail(st);
     ws->meta_len = 2 * (int64_t)max_q + 1 + 2 * (int64_t)max_rel;
     if ((st = dalloc(ws->allocs, ws->bytes, &ws->d_meta, (size_t)ws->meta_len, "metadata"))) return fail(st);
     if ((st = dalloc(ws->allocs, ws->bytes, &ws->status, 1, "status"))) return fail(st);
-    ws->cand_cap = topk_candidate_capacity(mem->n, max_q, max_k);
+    ws->cand_cap = topk_candidate_capacity(mem->n, max_q, max_k + 1);
     for (int b = 0; b < 2; ++b) {
       if ((st = dalloc(ws->allocs, ws->bytes, &ws->cand_key[b], (size_t)ws->cand_cap, "TopK keys"))) return fail(st);
       if ((st = dalloc(ws->allocs, ws->bytes, &ws->cand_idx[b], (size_t)ws->cand_cap, "TopK indices"))) return fail(st);
     }
-    if ((st = dalloc(ws->allocs, ws->bytes, &ws->rs_idx, (size_t)max_q * max_k, "winner indices"))) return fail(st);
+    ws->max_k = max_k;
+    const size_t nk = (size_t)max_q * max_k;
+    if ((st = dalloc(ws->allocs, ws->bytes, &ws->rs_idx, nk, "winner indices"))) return fail(st);
+    if ((st = dalloc(ws->allocs, ws->bytes, &ws->rs_score, nk, "rescored scores"))) return fail(st);
+    if ((st = dalloc(ws->allocs, ws->bytes, &ws->rs_terms, nk * kMaxRel, "rescored terms"))) return fail(st);
+    if ((st = dalloc(ws->allocs, ws->bytes, &ws->rs_anchor, nk * kMaxRel, "rescored anchors"))) return fail(st);
     hipError_t e = hipHostMalloc((void**)&ws->h_meta, (size_t)ws->meta_len * sizeof(int32_t), hipHostMallocDefault);
     if (e != hipSuccess) { ws->h_meta = nullptr; return fail(hip_fail(e, "pinned metadata staging")); }
     e = hipEventCreateWithFlags(&ws->meta_done, hipEventDisableTiming);
@@ -479,9 +545,11 @@ farm_status farm_score_query(const farm_memory* mem, farm_workspace* ws, int32_t
     hipStream_t s = (hipStream_t)stream;
     MetaView meta;
     FARM_TRY(stage_meta(ws, q, R, target_cls, rel_off, rel_pred, s, &meta));
-    FARM_TRY(similarities_f32(mem, ws, q, R, target, rel_anchor, meta, s));
+    SimBound none;
+    FARM_TRY(similarities(mem, ws, q, R, target, rel_anchor, meta, FARM_F32, &none, s));
     PhaseTimer t(ws, s, FARM_PHASE_PAIR);
-    FARM_HIP(launch_pair_exhaustive(mem, ws->sim, ws->ld_s, q, meta, scores, mem->n, rel_terms, rel_anchor_id, s),
+    FARM_HIP(launch_pair_exhaustive(mem, ws->sim, ws->ld_s, q, meta, none, scores, mem->n, rel_terms, rel_anchor_id,
+                                    nullptr, s),
              "relational pass");
     return FARM_OK;
   } catch (...) {
@@ -498,10 +566,7 @@ farm_status farm_topk(const farm_memory* mem, farm_workspace* ws, const float* s
     if (k < 1 || k > FARM_MAX_K) { set_error("k = %d outside [1, %d]", k, FARM_MAX_K); return FARM_ERR_INVALID_ARG; }
     if (q == 0) return FARM_OK;
     if (!scores || !out_id || !out_score) { set_error("null pointer"); return FARM_ERR_INVALID_ARG; }
-    if ((int64_t)q * ((mem->n + 4095) / 4096) * k > ws->cand_cap) {
-      set_error("k = %d exceeds the workspace's max_k", k);
-      return FARM_ERR_INVALID_ARG;
-    }
+    if (k > ws->max_k) { set_error("k = %d exceeds the workspace's max_k %d", k, ws->max_k); return FARM_ERR_INVALID_ARG; }
     DeviceGuard g(mem->device);
     hipStream_t s = (hipStream_t)stream;
     uint64_t* key;
@@ -526,31 +591,66 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
     if (k < 1 || k > FARM_MAX_K) { set_error("k = %d outside [1, %d]", k, FARM_MAX_K); return FARM_ERR_INVALID_ARG; }
     if (q == 0) return FARM_OK;
     if (!out_id || !out_score) { set_error("null output pointer"); return FARM_ERR_INVALID_ARG; }
-    int32_t dtype = opts ? opts->dtype : FARM_F32;
-    if (dtype != FARM_F32) { set_error("dtype %d not supported by this build", dtype); return FARM_ERR_UNSUPPORTED; }
-    if ((int64_t)q * ((mem->n + 4095) / 4096) * k > ws->cand_cap) {
-      set_error("k = %d exceeds the workspace's max_k", k);
+    const int32_t dtype = opts ? opts->dtype : FARM_F32;
+    int32_t* certified = opts ? opts->certified : nullptr;
+    if (dtype != FARM_F32 && dtype != FARM_BF16 && dtype != FARM_FP8_E4M3) {
+      set_error("unknown dtype %d", dtype);
       return FARM_ERR_INVALID_ARG;
     }
+    if ((dtype == FARM_BF16 && !mem->dn_bf16) || (dtype == FARM_FP8_E4M3 && !mem->dn_fp8)) {
+      set_error("memory was built without the %s copy", dtype == FARM_BF16 ? "BF16" : "FP8");
+      return FARM_ERR_UNSUPPORTED;
+    }
+    int32_t c = k;  // candidates that leave the first TopK
+    if (dtype != FARM_F32) {
+      const int32_t mult = opts->rescore_mult;
+      if (mult < 1) { set_error("rescore_mult = %d must be >= 1", mult); return FARM_ERR_INVALID_ARG; }
+      if ((int64_t)mult * k > ws->max_k) {
+        set_error("rescore_mult * k = %lld exceeds the workspace's max_k %d", (long long)mult * k, ws->max_k);
+        return FARM_ERR_INVALID_ARG;
+      }
+      c = mult * k;
+    }
+    if (k > ws->max_k) { set_error("k = %d exceeds the workspace's max_k %d", k, ws->max_k); return FARM_ERR_INVALID_ARG; }
     DeviceGuard g(mem->device);
     hipStream_t s = (hipStream_t)stream;
     MetaView meta;
     FARM_TRY(stage_meta(ws, q, R, target_cls, rel_off, rel_pred, s, &meta));
-    FARM_TRY(similarities_f32(mem, ws, q, R, target, rel_anchor, meta, s));
+    SimBound bound;
+    FARM_TRY(similarities(mem, ws, q, R, target, rel_anchor, meta, dtype, &bound, s));
     {
       PhaseTimer t(ws, s, FARM_PHASE_PAIR);
-      FARM_HIP(launch_pair_exhaustive(mem, ws->sim, ws->ld_s, q, meta, ws->scores, ws->ld_s, nullptr, nullptr, s),
+      FARM_HIP(launch_pair_exhaustive(mem, ws->sim, ws->ld_s, q, meta, bound, ws->scores, ws->ld_s, nullptr, nullptr,
+                                      dtype == FARM_F32 ? nullptr : ws->scores_hi, s),
                "relational pass");
     }
     uint64_t* key;
     int32_t* idx;
     {
       PhaseTimer t(ws, s, FARM_PHASE_TOPK);
-      FARM_HIP(launch_topk(mem, ws, ws->scores, ws->ld_s, q, k, &key, &idx, s), "topk");
-      FARM_HIP(launch_topk_emit(key, idx, q, k, out_id, out_score, ws->rs_idx, s), "topk emit");
+      FARM_HIP(launch_topk(mem, ws, ws->scores, ws->ld_s, q, c, &key, &idx, s), "topk");
+      if (dtype == FARM_F32)
+        FARM_HIP(launch_topk_emit(key, idx, q, k, out_id, out_score, ws->rs_idx, s), "topk emit");
+      else
+        FARM_HIP(launch_topk_emit(key, idx, q, c, nullptr, nullptr, ws->rs_idx, s), "candidate emit");
     }
-    PhaseTimer t(ws, s, FARM_PHASE_EXPLAIN);
-    FARM_HIP(launch_explain(mem, ws->sim, ws->ld_s, q, meta, ws->rs_idx, k, out_terms, out_anchor_id, s), "explain");
+    if (dtype == FARM_F32) {
+      PhaseTimer t(ws, s, FARM_PHASE_EXPLAIN);
+      FARM_HIP(launch_explain(mem, ws->sim, ws->ld_s, q, meta, ws->rs_idx, k, out_terms, out_anchor_id, s), "explain");
+      if (certified) FARM_HIP(launch_fill_i32(certified, q, 1, s), "certificate");
+      return FARM_OK;
+    }
+    uint64_t* hi_key = nullptr;
+    int32_t* hi_idx = nullptr;
+    if (certified) {  // the c + 1 largest upper bounds (the first non-candidate among them bounds the rest)
+      PhaseTimer t(ws, s, FARM_PHASE_TOPK);
+      FARM_HIP(launch_topk(mem, ws, ws->scores_hi, ws->ld_s, q, c + 1, &hi_key, &hi_idx, s), "bound topk");
+    }
+    PhaseTimer t(ws, s, FARM_PHASE_RESCORE);
+    FARM_HIP(launch_rescore(mem, ws, ws->sim, ws->ld_s, q, meta, bound, ws->rs_idx, c, s), "rescore");
+    FARM_HIP(launch_rescore_select(ws, q, c, k, hi_key, hi_idx, mem->n, out_id, out_score, out_terms, out_anchor_id,
+                                   certified, s),
+             "rescore select");
     return FARM_OK;
   } catch (...) {
     set_error("unexpected host exception in farm_query_topk");

@@ -13,7 +13,7 @@
 namespace farm {
 
 constexpr int kMaxRel = FARM_MAX_REL;
-constexpr int kKPad = 32;          // descriptor rows are zero-padded to a multiple of this
+constexpr int kKPad = 128;         // descriptor rows are zero-padded to a multiple of this
 constexpr int kRowAlign = 64;      // similarity-matrix rows are padded to a multiple of this
 constexpr float kW = 0.5f;         // soft-blend weight of the relational factor
 constexpr float kClassFactor = 0.3f;
@@ -46,6 +46,12 @@ struct farm_memory {
   uint16_t* dn_bf16 = nullptr;  // [n][ldk] BF16 (RNE)
   uint8_t* dn_fp8 = nullptr;    // [n][ldk] OCP e4m3, scaled by 1/dn_scale
   float* dn_scale = nullptr;    // [n] per-row FP32 scale (amax / 448)
+  // reduced-precision error norms ||d~ - d||_2 and norms ||d~||_2 per row
+  float* err_bf16 = nullptr;
+  float* nrm_bf16 = nullptr;
+  float* err_fp8 = nullptr;
+  float* nrm_fp8 = nullptr;
+  float* err_max = nullptr;  // [2] max over rows of err_bf16, err_fp8
   // geometry, structure of arrays
   float* x = nullptr;
   float* y = nullptr;
@@ -68,8 +74,13 @@ struct farm_workspace {
   uint16_t* qn_bf16 = nullptr;
   uint8_t* qn_fp8 = nullptr;
   float* qn_scale = nullptr;
+  float* qerr_bf16 = nullptr;   // [rows] ||q~ - q||_2 and ||q~||_2 of the reduced-precision copies
+  float* qnrm_bf16 = nullptr;
+  float* qerr_fp8 = nullptr;
+  float* qnrm_fp8 = nullptr;
   float* sim = nullptr;       // [max_q + max_rel][ld_s] clamped similarities (target rows x kappa)
   float* scores = nullptr;    // [max_q][ld_s] composite scores (fused path)
+  float* scores_hi = nullptr; // [max_q][ld_s] upper bounds of the scores (reduced-precision form)
   int32_t* d_meta = nullptr;  // device copy of the metadata block below
   int32_t* h_meta = nullptr;  // pinned host staging of the metadata block
   int64_t meta_len = 0;       // int32 elements in the metadata block
@@ -80,8 +91,12 @@ struct farm_workspace {
   uint64_t* cand_key[2] = {nullptr, nullptr};
   int32_t* cand_idx[2] = {nullptr, nullptr};
   int64_t cand_cap = 0;       // elements per buffer
-  // rescoring buffers
-  int32_t* rs_idx = nullptr;  // [max_q][FARM_MAX_K * rescore]
+  int32_t max_k = 0;
+  // winners / rescoring candidates: object indices, FP32 scores, terms, bound anchors
+  int32_t* rs_idx = nullptr;     // [max_q][max_k]
+  float* rs_score = nullptr;     // [max_q][max_k]
+  float* rs_terms = nullptr;     // [max_q][max_k][FARM_MAX_REL]
+  uint32_t* rs_anchor = nullptr; // [max_q][max_k][FARM_MAX_REL]
   // optional phase timer: pending (start, stop) event pairs per phase
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -107,6 +122,30 @@ struct MetaView {
 
 namespace farm {
 
+// Outputs of row normalisation for the reduced-precision copies (any may be null).
+struct LowPrecRows {
+  uint16_t* bf16 = nullptr;
+  uint8_t* fp8 = nullptr;
+  float* fp8_scale = nullptr;
+  float* err_bf16 = nullptr;
+  float* nrm_bf16 = nullptr;
+  float* err_fp8 = nullptr;
+  float* nrm_fp8 = nullptr;
+};
+
+// Error bound of a reduced-precision similarity matrix, before the clamp and
+// the class factor:  |sim~(row, j) - sim(row, j)| <= q_nrm[row] * o_err[j] + q_err[row] + acc.
+// (Cauchy-Schwarz on q~.d~ - q.d = q~.(d~ - d) + (q~ - q).d with |d| <= 1, plus
+// FP32 accumulation of both the GEMM and the FP32 reference dot products.)
+// A null q_nrm means the matrix is the FP32 one (bound 0).
+struct SimBound {
+  const float* q_nrm = nullptr;
+  const float* q_err = nullptr;
+  const float* o_err = nullptr;
+  const float* o_err_max = nullptr;  // device scalar: max_j o_err[j]
+  float acc = 0.f;
+};
+
 void set_error(const char* fmt, ...);
 farm_status hip_fail(hipError_t e, const char* what);
 
@@ -115,8 +154,8 @@ hipError_t launch_validate_memory(const float* desc, const float* center, const 
                                   const uint32_t* id, int64_t n, int32_t d, int* flags,
                                   uint32_t* table, int64_t table_size, hipStream_t s);
 hipError_t launch_normalize_rows(const float* src, int64_t rows, int32_t d, int32_t ldk, float* dst_f32,
-                                 uint16_t* dst_bf16, uint8_t* dst_fp8, float* dst_scale, int* flags,
-                                 hipStream_t s);
+                                 const LowPrecRows& lp, int* flags, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_geometry(const float* center, const float* extent, int64_t n, float rx, float ry,
                            float* x, float* y, float* z, float* hr_hi, float* hr_lo, float* ext,
                            hipStream_t s);
@@ -134,14 +173,36 @@ hipError_t launch_sim_gemm_fp8(const uint8_t* a, const float* a_scale, const uin
                                hipStream_t s);
 
 // ---- pair.hip
+// With a SimBound (bound.q_nrm != null) the pass also writes scores_hi >= s:
+// the target similarity raised by its error bound and every relation term by
+// the largest similarity error bound of its row.
 hipError_t launch_pair_exhaustive(const farm_memory* mem, const float* sim, int64_t ld_s, int32_t q,
-                                  MetaView meta, float* scores, int64_t ld_out, float* rel_terms,
-                                  uint32_t* rel_anchor_id, hipStream_t s);
+                                  MetaView meta, const SimBound& bound, float* scores, int64_t ld_out,
+                                  float* rel_terms, uint32_t* rel_anchor_id, float* scores_hi, hipStream_t s);
 // ScoredCandidate breakdown for selected objects: t_r and b_r recomputed for
 // each (query, rank) entry of idx[q][k].
 hipError_t launch_explain(const farm_memory* mem, const float* sim, int64_t ld_s, int32_t q, MetaView meta,
                           const int32_t* idx, int32_t k, float* out_terms, uint32_t* out_anchor_id,
                           hipStream_t s);
+
+// ---- rescore.hip
+// FP32 scores of the candidates cand[q][c] (object indices, -1 = none): exact
+// target similarity and, per relation, the exact maximum over anchors, where
+// only anchors whose bounded value can reach the best lower bound get an FP32
+// dot product.  Writes rs_score[q][c], rs_terms/rs_anchor[q][c][8].
+hipError_t launch_rescore(const farm_memory* mem, const farm_workspace* ws, const float* sim, int64_t ld_s,
+                          int32_t q, MetaView meta, const SimBound& bound, const int32_t* cand, int32_t c,
+                          hipStream_t s);
+// Final TopK among rescored candidates; certified[q] (optional) = 1 when the
+// K-th rescored score exceeds, by the FP32 value tolerance, the largest upper
+// bound of any object outside the candidates, or every object was a
+// candidate.  hi_key/hi_idx [q][c + 1] are the top c + 1 objects by upper
+// bound: the first of them that is not a candidate carries that largest bound.
+hipError_t launch_rescore_select(const farm_workspace* ws, int32_t q, int32_t c, int32_t k,
+                                 const uint64_t* hi_key, const int32_t* hi_idx, int64_t n, uint32_t* out_id,
+                                 float* out_score, float* out_terms, uint32_t* out_anchor_id, int32_t* certified,
+                                 hipStream_t s);
+hipError_t launch_max_reduce(const float* v, int64_t n, float* out, hipStream_t s);
 
 // ---- topk.hip
 // Select the top k of each score row.  Writes (key, index) of the winners in

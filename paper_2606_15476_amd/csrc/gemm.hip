@@ -1,30 +1,39 @@
 // gemm.hip -- the descriptor/query similarity GEMM on MFMA.
 //
-//   sim[row][col] = kappa(row, col) * max(0, <qn_row, dn_col>)
+//   sim[row][col] = kappa(row, col) * max(0, sa[row] * sb[col] * <qn_row, dn_col>)
 //
 // qn (query vectors) and dn (object descriptors) are L2-normalised rows,
-// zero-padded to a multiple of 32 elements, so the contraction is an "NT"
-// GEMM with K contiguous in both operands.  The clamp at zero turns the
-// cosine into the unary score in [0, 1]; on target rows (row < n_cls_rows) the
-// soft class factor 0.3 multiplies objects whose known class differs from the
+// zero-padded to a multiple of 128 elements, so the contraction is an "NT"
+// GEMM with K contiguous in both operands.  The clamp at zero turns the cosine
+// into the unary score in [0, 1]; on target rows (row < n_cls_rows) the soft
+// class factor 0.3 multiplies objects whose known class differs from the
 // query's parsed class (Appendix "Retrieval Details", composite-scoring step).
+// FP8 rows carry per-row scales sa, sb (amax / 448); FP32 and BF16 have none.
 //
-// FP32 path: v_mfma_f32_32x32x2f32.  A 256-thread block computes a 128x128
-// tile; each of its four waves owns a 64x64 quadrant as 2x2 MFMA tiles of
-// 32x32.  K advances 32 at a time through LDS (rows padded by 4 floats so the
-// 16-byte fragment reads of 32 consecutive rows hit distinct banks); the next
-// K tile is fetched into registers while the current one is consumed.  Within
-// an 8-wide K slice, lane half h supplies elements 4h..4h+3 of the slice to
-// four consecutive MFMAs, a fixed permutation of the K order shared by both
-// operands (the sum is unchanged).
+// One kernel template serves the three operand types.  A 256-thread block
+// computes a 128x128 tile; each of its four waves owns a 64x64 quadrant as 2x2
+// MFMA tiles of 32x32.  K advances through LDS in slabs of 128 bytes per row
+// (32 FP32, 64 BF16 or 128 FP8 elements); rows are padded by 16 bytes so the
+// 16-byte fragment reads of 32 consecutive rows hit distinct banks, and the
+// next slab is fetched into registers while the current one is consumed.
+// Each 32-byte slice of a slab feeds the MFMA pipe from two lane halves of 16
+// bytes: four v_mfma_f32_32x32x2f32, one v_mfma_f32_32x32x16_bf16 or two
+// v_mfma_f32_32x32x16_fp8_fp8 per slice.  Lane half h supplies bytes 16h..16h+15
+// of the slice to both operands, a fixed permutation of the K order shared by
+// A and B (the sum is unchanged).
 #include "farm_internal.h"
 
 namespace farm {
 namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kBM = 128, kBN = 128, kBK = 32, kLda = kBK + 4;
+enum { kT32 = 0, kTBF16 = 1, kTFP8 = 2 };
+
+constexpr int kBM = 128, kBN = 128;
+constexpr int kSlab = 128;              // bytes of K per row per slab
+constexpr int kRowU4 = kSlab / 16 + 1;  // padded LDS row length in 16-byte units
 
 __device__ inline float class_factor(int64_t row, int64_t col, const int32_t* row_cls, int64_t n_cls_rows,
                                      const int32_t* col_cls) {
@@ -34,18 +43,16 @@ __device__ inline float class_factor(int64_t row, int64_t col, const int32_t* ro
   return (rc >= 0 && cc >= 0 && rc != cc) ? kClassFactor : 1.0f;
 }
 
-// Block index -> output tile, grouping consecutive launches of one XCD onto
-// neighbouring tiles.  Workgroups are dispatched round-robin over the 8 XCDs,
-// so block b runs on XCD b % 8; remapping makes each XCD sweep a contiguous
-// band of tiles that share operand rows in its own L2.
+// Block index -> output tile.  Workgroups are dispatched round-robin over the
+// 8 XCDs (block b runs on XCD b % 8); the remap gives each XCD a contiguous
+// band of tiles, swept column-major in groups of 8 tile rows so an object
+// block is reused by the query blocks of a group while it sits in that XCD's L2.
 __device__ inline void tile_of_block(int64_t& tm, int64_t& tn, int64_t tiles_m, int64_t tiles_n) {
   int64_t b = blockIdx.x;
   int64_t total = tiles_m * tiles_n;
   int64_t per_xcd = total / 8;
   int64_t lin = b;
   if (per_xcd > 0 && b < per_xcd * 8) lin = (b % 8) * per_xcd + b / 8;
-  // column-major sweep in groups of 8 tile rows (an object block is reused by
-  // the query blocks of a group while it is still in L2)
   const int64_t group = 8;
   int64_t gsize = group * tiles_n;
   int64_t g = lin / gsize;
@@ -56,13 +63,36 @@ __device__ inline void tile_of_block(int64_t& tm, int64_t& tn, int64_t tiles_m, 
   tn = in / gm;
 }
 
-__global__ __launch_bounds__(256) void k_sim_gemm_f32(const float* __restrict__ A, const float* __restrict__ B,
-                                                      int64_t M, int64_t N, int32_t ldk, float* __restrict__ C,
-                                                      int64_t ldc, const int32_t* __restrict__ row_cls,
-                                                      int64_t n_cls_rows, const int32_t* __restrict__ col_cls,
-                                                      int64_t tiles_m, int64_t tiles_n) {
-  __shared__ float As[kBM * kLda];
-  __shared__ float Bs[kBN * kLda];
+template <int T>
+__device__ inline void mfma_slice(floatx16& acc, const uint4& a, const uint4& b) {
+  if constexpr (T == kT32) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.x), __uint_as_float(b.x), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.y), __uint_as_float(b.y), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.z), __uint_as_float(b.z), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.w), __uint_as_float(b.w), acc, 0, 0, 0);
+  } else if constexpr (T == kTBF16) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), acc,
+                                                  0, 0, 0);
+  } else {
+    long a0 = (long)((uint64_t)a.x | ((uint64_t)a.y << 32));
+    long a1 = (long)((uint64_t)a.z | ((uint64_t)a.w << 32));
+    long b0 = (long)((uint64_t)b.x | ((uint64_t)b.y << 32));
+    long b1 = (long)((uint64_t)b.z | ((uint64_t)b.w << 32));
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a0, b0, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a1, b1, acc, 0, 0, 0);
+  }
+}
+
+template <int T>
+__global__ __launch_bounds__(256) void k_sim_gemm(const uint8_t* __restrict__ A, const uint8_t* __restrict__ B,
+                                                  int64_t M, int64_t N, int64_t ld_bytes, float* __restrict__ C,
+                                                  int64_t ldc, const float* __restrict__ a_scale,
+                                                  const float* __restrict__ b_scale,
+                                                  const int32_t* __restrict__ row_cls, int64_t n_cls_rows,
+                                                  const int32_t* __restrict__ col_cls, int64_t tiles_m,
+                                                  int64_t tiles_n) {
+  __shared__ uint4 As[kBM * kRowU4];
+  __shared__ uint4 Bs[kBN * kRowU4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   int64_t tm, tn;
@@ -77,50 +107,44 @@ __global__ __launch_bounds__(256) void k_sim_gemm_f32(const float* __restrict__ 
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
 
-  float4 ra[4], rb[4];
-  const int lr = tid >> 3, lc = (tid & 7) * 4;
-  auto gload = [&](int kt) {
+  uint4 ra[4], rb[4];
+  const int lr = tid >> 3, lc = tid & 7;
+  const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
+  auto gload = [&](int64_t kt) {
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       int64_t gm = m0 + lr + 32 * p, gn = n0 + lr + 32 * p;
-      ra[p] = gm < M ? *reinterpret_cast<const float4*>(A + gm * ldk + (int64_t)kt * kBK + lc)
-                     : make_float4(0.f, 0.f, 0.f, 0.f);
-      rb[p] = gn < N ? *reinterpret_cast<const float4*>(B + gn * ldk + (int64_t)kt * kBK + lc)
-                     : make_float4(0.f, 0.f, 0.f, 0.f);
+      ra[p] = gm < M ? *reinterpret_cast<const uint4*>(A + gm * ld_bytes + kt * kSlab + lc * 16) : zero;
+      rb[p] = gn < N ? *reinterpret_cast<const uint4*>(B + gn * ld_bytes + kt * kSlab + lc * 16) : zero;
     }
   };
   auto sstore = [&]() {
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
-      *reinterpret_cast<float4*>(&As[(lr + 32 * p) * kLda + lc]) = ra[p];
-      *reinterpret_cast<float4*>(&Bs[(lr + 32 * p) * kLda + lc]) = rb[p];
+      As[(lr + 32 * p) * kRowU4 + lc] = ra[p];
+      Bs[(lr + 32 * p) * kRowU4 + lc] = rb[p];
     }
   };
 
-  const int nk = ldk / kBK;
+  const int64_t nk = ld_bytes / kSlab;
   gload(0);
   sstore();
   __syncthreads();
   const int h = lane >> 5, r = lane & 31;
-  for (int kt = 0; kt < nk; ++kt) {
+  for (int64_t kt = 0; kt < nk; ++kt) {
     if (kt + 1 < nk) gload(kt + 1);
 #pragma unroll
-    for (int kk = 0; kk < kBK; kk += 8) {
-      float4 a[2], b[2];
+    for (int s = 0; s < 4; ++s) {
+      uint4 a[2], b[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        a[i] = *reinterpret_cast<const float4*>(&As[(wm * 64 + i * 32 + r) * kLda + kk + 4 * h]);
-        b[i] = *reinterpret_cast<const float4*>(&Bs[(wn * 64 + i * 32 + r) * kLda + kk + 4 * h]);
+        a[i] = As[(wm * 64 + i * 32 + r) * kRowU4 + 2 * s + h];
+        b[i] = Bs[(wn * 64 + i * 32 + r) * kRowU4 + 2 * s + h];
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].x, b[j].x, acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].y, b[j].y, acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].z, b[j].z, acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].w, b[j].w, acc[i][j], 0, 0, 0);
-        }
+        for (int j = 0; j < 2; ++j) mfma_slice<T>(acc[i][j], a[i], b[j]);
     }
     __syncthreads();
     if (kt + 1 < nk) {
@@ -134,16 +158,34 @@ __global__ __launch_bounds__(256) void k_sim_gemm_f32(const float* __restrict__ 
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 2; ++j) {
+      const int64_t col = n0 + wn * 64 + j * 32 + r;
+      const float sb = (T == kTFP8 && col < N) ? b_scale[col] : 1.0f;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        int64_t row = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-        int64_t col = n0 + wn * 64 + j * 32 + r;
+        const int64_t row = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
         if (row < M && col < N) {
-          float val = fmaxf(acc[i][j][v], 0.f);
+          float val = acc[i][j][v];
+          if (T == kTFP8) val = val * (a_scale[row] * sb);
+          val = fmaxf(val, 0.f);
           C[row * ldc + col] = val * class_factor(row, col, row_cls, n_cls_rows, col_cls);
         }
       }
+    }
+}
+
+template <int T>
+hipError_t launch_gemm(const void* a, const float* a_scale, const void* b, const float* b_scale, int64_t m, int64_t n,
+                       int32_t ldk, int elem_bytes, float* c, int64_t ldc, const int32_t* row_cls, int64_t n_cls_rows,
+                       const int32_t* col_cls, hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  const int64_t ld_bytes = (int64_t)ldk * elem_bytes;
+  if (ld_bytes % kSlab) return hipErrorInvalidValue;
+  int64_t tiles_m = (m + kBM - 1) / kBM, tiles_n = (n + kBN - 1) / kBN;
+  hipLaunchKernelGGL(k_sim_gemm<T>, dim3((unsigned)(tiles_m * tiles_n)), dim3(256), 0, s,
+                     static_cast<const uint8_t*>(a), static_cast<const uint8_t*>(b), m, n, ld_bytes, c, ldc, a_scale,
+                     b_scale, row_cls, n_cls_rows, col_cls, tiles_m, tiles_n);
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -151,22 +193,19 @@ __global__ __launch_bounds__(256) void k_sim_gemm_f32(const float* __restrict__ 
 hipError_t launch_sim_gemm_f32(const float* a, const float* b, int64_t m, int64_t n, int32_t ldk, float* c,
                                int64_t ldc, const int32_t* row_cls, int64_t n_cls_rows, const int32_t* col_cls,
                                hipStream_t s) {
-  if (m <= 0 || n <= 0) return hipSuccess;
-  if (ldk % kBK) return hipErrorInvalidValue;
-  int64_t tiles_m = (m + kBM - 1) / kBM, tiles_n = (n + kBN - 1) / kBN;
-  hipLaunchKernelGGL(k_sim_gemm_f32, dim3((unsigned)(tiles_m * tiles_n)), dim3(256), 0, s, a, b, m, n, ldk, c, ldc,
-                     row_cls, n_cls_rows, col_cls, tiles_m, tiles_n);
-  return hipGetLastError();
+  return launch_gemm<kT32>(a, nullptr, b, nullptr, m, n, ldk, 4, c, ldc, row_cls, n_cls_rows, col_cls, s);
 }
 
-hipError_t launch_sim_gemm_bf16(const uint16_t*, const uint16_t*, int64_t, int64_t, int32_t, float*, int64_t,
-                                const int32_t*, int64_t, const int32_t*, hipStream_t) {
-  return hipErrorNotSupported;
+hipError_t launch_sim_gemm_bf16(const uint16_t* a, const uint16_t* b, int64_t m, int64_t n, int32_t ldk, float* c,
+                                int64_t ldc, const int32_t* row_cls, int64_t n_cls_rows, const int32_t* col_cls,
+                                hipStream_t s) {
+  return launch_gemm<kTBF16>(a, nullptr, b, nullptr, m, n, ldk, 2, c, ldc, row_cls, n_cls_rows, col_cls, s);
 }
 
-hipError_t launch_sim_gemm_fp8(const uint8_t*, const float*, const uint8_t*, const float*, int64_t, int64_t,
-                               int32_t, float*, int64_t, const int32_t*, int64_t, const int32_t*, hipStream_t) {
-  return hipErrorNotSupported;
+hipError_t launch_sim_gemm_fp8(const uint8_t* a, const float* a_scale, const uint8_t* b, const float* b_scale,
+                               int64_t m, int64_t n, int32_t ldk, float* c, int64_t ldc, const int32_t* row_cls,
+                               int64_t n_cls_rows, const int32_t* col_cls, hipStream_t s) {
+  return launch_gemm<kTFP8>(a, a_scale, b, b_scale, m, n, ldk, 1, c, ldc, row_cls, n_cls_rows, col_cls, s);
 }
 
 }  // namespace farm

@@ -27,87 +27,10 @@
 #include <math.h>
 
 #include "farm_internal.h"
+#include "pair_math.h"
 
 namespace farm {
 namespace {
-
-enum Family { kFamNear = 0, kFamVert = 1, kFamLat = 2 };
-
-// (1/tau) * log2(e) with tau = 0.1 m
-constexpr float kInvTauLog2e = 14.426950408889634f;
-
-__device__ inline int family_of(int p) {
-  return p == FARM_NEAR ? kFamNear : (p == FARM_ABOVE || p == FARM_BELOW) ? kFamVert : kFamLat;
-}
-
-// exponent scale c such that P = 1 / (1 + 2^(offset * c))
-__device__ inline float sigmoid_scale(int p) {
-  return (p == FARM_ABOVE || p == FARM_RIGHT_OF) ? -kInvTauLog2e : kInvTauLog2e;
-}
-
-__device__ inline float rcp_approx(float v) { return __builtin_amdgcn_rcpf(v); }
-__device__ inline float exp2_approx(float v) { return __builtin_amdgcn_exp2f(v); }
-
-// Per-target coordinates, family-specific.
-struct Tgt {
-  float u0, u1, u2;
-};
-
-__device__ inline Tgt load_target(int fam, int64_t i, const float* x, const float* y, const float* z,
-                                  const float* hhi, const float* hlo) {
-  Tgt t{0.f, 0.f, 0.f};
-  if (fam == kFamNear) {
-    t.u0 = x[i]; t.u1 = y[i]; t.u2 = z[i];
-  } else if (fam == kFamVert) {
-    t.u0 = z[i];
-  } else {
-    t.u0 = hhi[i]; t.u1 = hlo[i];
-  }
-  return t;
-}
-
-// Anchor record: (value, coordinates).  Near stores log(a_j).
-__device__ inline float4 anchor_record(int fam, float a, int64_t j, const float* x, const float* y, const float* z,
-                                       const float* hhi, const float* hlo) {
-  // a = 0 maps to a large finite negative log so that such anchors still order by
-  // distance (any of them is a valid binding of a zero term).
-  if (fam == kFamNear) return make_float4(a > 0.f ? logf(a) : -1.0e30f, x[j], y[j], z[j]);
-  if (fam == kFamVert) return make_float4(a, z[j], 0.f, 0.f);
-  return make_float4(a, hhi[j], hlo[j], 0.f);
-}
-
-// Value of one (target, anchor) pair in the family's comparison domain:
-// log domain for Near, linear for the sigmoid families.
-template <int FAM>
-__device__ inline float pair_value(const Tgt& t, const float4& rec, float c) {
-  if (FAM == kFamNear) {
-    float dx = t.u0 - rec.y, dy = t.u1 - rec.z, dz = t.u2 - rec.w;
-    float d2 = dx * dx;
-    d2 = fmaf(dy, dy, d2);
-    d2 = fmaf(dz, dz, d2);
-    return fmaf(-2.0f, d2, rec.x);
-  } else if (FAM == kFamVert) {
-    float e = exp2_approx((t.u0 - rec.y) * c);
-    return rec.x * rcp_approx(1.0f + e);
-  } else {
-    float dh = (t.u0 - rec.y) + (t.u1 - rec.z);
-    float e = exp2_approx(dh * c);
-    return rec.x * rcp_approx(1.0f + e);
-  }
-}
-
-// Initial "best" in the comparison domain (below any attainable value).
-template <int FAM>
-__device__ inline float value_floor() {
-  return FAM == kFamNear ? -INFINITY : -1.0f;
-}
-
-// Linear relation term from the family-domain maximum.
-template <int FAM>
-__device__ inline float term_of(float best) {
-  if (FAM == kFamNear) return expf(best);
-  return best > 0.f ? best : 0.f;
-}
 
 constexpr int kThreads = 256;
 constexpr int kTpt = 2;                      // targets per thread
@@ -166,10 +89,11 @@ __device__ void relation_pass(const float* __restrict__ arow, int64_t n, int64_t
 
 template <bool WITH_ARG>
 __global__ __launch_bounds__(kThreads) void k_pair_exhaustive(
-    const float* __restrict__ sim, int64_t ld_s, int32_t q, MetaView meta, const float* __restrict__ x,
-    const float* __restrict__ y, const float* __restrict__ z, const float* __restrict__ hhi,
-    const float* __restrict__ hlo, const uint32_t* __restrict__ ids, int64_t n, float* __restrict__ scores,
-    int64_t ld_out, float* __restrict__ rel_terms, uint32_t* __restrict__ rel_anchor_id) {
+    const float* __restrict__ sim, int64_t ld_s, int32_t q, MetaView meta, SimBound bound,
+    const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
+    const float* __restrict__ hhi, const float* __restrict__ hlo, const uint32_t* __restrict__ ids,
+    const int32_t* __restrict__ cls, int64_t n, float* __restrict__ scores, int64_t ld_out,
+    float* __restrict__ rel_terms, uint32_t* __restrict__ rel_anchor_id, float* __restrict__ scores_hi) {
   __shared__ float4 rec[kChunk];
   __shared__ uint32_t rid[WITH_ARG ? kChunk : 1];
   const int32_t qq = blockIdx.y;
@@ -181,15 +105,19 @@ __global__ __launch_bounds__(kThreads) void k_pair_exhaustive(
     ti[u] = i < n ? i : n - 1;  // out-of-range lanes shadow the last target and do not store
   }
   const int r0 = meta.rel_off[qq], r1 = meta.rel_off[qq + 1];
-  float lsum[kTpt];
+  float lsum[kTpt], lsum_hi[kTpt];
 #pragma unroll
-  for (int u = 0; u < kTpt; ++u) lsum[u] = 0.f;
+  for (int u = 0; u < kTpt; ++u) lsum[u] = lsum_hi[u] = 0.f;
+  const bool bounded = bound.q_nrm != nullptr;
+  const float err_max = bounded ? *bound.o_err_max : 0.f;
 
   for (int r = r0; r < r1; ++r) {
     const int p = meta.rel_pred[r];
     const int fam = family_of(p);
     const float c = sigmoid_scale(p);
     const float* arow = sim + (int64_t)(q + r) * ld_s;
+    // largest similarity error of this relation row (upper-bound output only)
+    const float dmax = bounded ? fmaf(bound.q_nrm[q + r], err_max, bound.q_err[q + r] + bound.acc) : 0.f;
     Tgt t[kTpt];
 #pragma unroll
     for (int u = 0; u < kTpt; ++u) t[u] = load_target(fam, ti[u], x, y, z, hhi, hlo);
@@ -214,6 +142,10 @@ __global__ __launch_bounds__(kThreads) void k_pair_exhaustive(
         lsum[u] += logf(term[u]);
       }
     }
+    if (bounded) {
+#pragma unroll
+      for (int u = 0; u < kTpt; ++u) lsum_hi[u] += logf(fminf(1.0f, term[u] + dmax));
+    }
 #pragma unroll
     for (int u = 0; u < kTpt; ++u) {
       int64_t i = tile0 + threadIdx.x + u * kThreads;
@@ -228,9 +160,17 @@ __global__ __launch_bounds__(kThreads) void k_pair_exhaustive(
   for (int u = 0; u < kTpt; ++u) {
     int64_t i = tile0 + threadIdx.x + u * kThreads;
     if (i < n) {
-      float sem = sim[(int64_t)qq * ld_s + i];
-      float g = R > 0 ? expf(lsum[u] / (float)R) : 1.0f;
+      const float sem = sim[(int64_t)qq * ld_s + i];
+      const float g = R > 0 ? expf(lsum[u] / (float)R) : 1.0f;
       scores[(int64_t)qq * ld_out + i] = sem * ((1.0f - kW) + kW * g);
+      if (bounded) {  // s_hi: upper bounds of kappa * sim(i, q_t) and of every term
+        const int tc = meta.tcls[qq];
+        const float kappa = (tc >= 0 && cls && cls[i] >= 0 && cls[i] != tc) ? kClassFactor : 1.0f;
+        const float sem_hi =
+            fminf(kappa, sem + kappa * fmaf(bound.q_nrm[qq], bound.o_err[i], bound.q_err[qq] + bound.acc));
+        const float g_hi = R > 0 ? expf(lsum_hi[u] / (float)R) : 1.0f;
+        scores_hi[(int64_t)qq * ld_out + i] = sem_hi * ((1.0f - kW) + kW * g_hi) * (1.0f + 1e-6f);
+      }
     }
   }
 }
@@ -315,17 +255,19 @@ __global__ __launch_bounds__(256) void k_explain(const float* __restrict__ sim, 
 }  // namespace
 
 hipError_t launch_pair_exhaustive(const farm_memory* mem, const float* sim, int64_t ld_s, int32_t q, MetaView meta,
-                                  float* scores, int64_t ld_out, float* rel_terms, uint32_t* rel_anchor_id,
-                                  hipStream_t s) {
+                                  const SimBound& bound, float* scores, int64_t ld_out, float* rel_terms,
+                                  uint32_t* rel_anchor_id, float* scores_hi, hipStream_t s) {
   if (q <= 0) return hipSuccess;
   int64_t n = mem->n;
   dim3 grid((unsigned)((n + kTile - 1) / kTile), (unsigned)q);
   if (rel_anchor_id)
-    hipLaunchKernelGGL(k_pair_exhaustive<true>, grid, dim3(kThreads), 0, s, sim, ld_s, q, meta, mem->x, mem->y,
-                       mem->z, mem->hr_hi, mem->hr_lo, mem->id, n, scores, ld_out, rel_terms, rel_anchor_id);
+    hipLaunchKernelGGL(k_pair_exhaustive<true>, grid, dim3(kThreads), 0, s, sim, ld_s, q, meta, bound, mem->x, mem->y,
+                       mem->z, mem->hr_hi, mem->hr_lo, mem->id, mem->cls, n, scores, ld_out, rel_terms,
+                       rel_anchor_id, scores_hi);
   else
-    hipLaunchKernelGGL(k_pair_exhaustive<false>, grid, dim3(kThreads), 0, s, sim, ld_s, q, meta, mem->x, mem->y,
-                       mem->z, mem->hr_hi, mem->hr_lo, mem->id, n, scores, ld_out, rel_terms, rel_anchor_id);
+    hipLaunchKernelGGL(k_pair_exhaustive<false>, grid, dim3(kThreads), 0, s, sim, ld_s, q, meta, bound, mem->x,
+                       mem->y, mem->z, mem->hr_hi, mem->hr_lo, mem->id, mem->cls, n, scores, ld_out, rel_terms,
+                       rel_anchor_id, scores_hi);
   return hipGetLastError();
 }
 

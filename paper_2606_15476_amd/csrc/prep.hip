@@ -4,7 +4,7 @@
 //   positive extents, unique ids) in one pass plus a hash probe for ids.
 // * Row L2 normalisation into an FP32 master, with optional BF16 (round to
 //   nearest even) and OCP FP8 e4m3 (per-row scale amax/448, round to nearest
-//   even, saturating) copies; rows are zero-padded to a multiple of 32 so that
+//   even, saturating) copies; rows are zero-padded to a multiple of 128 so that
 //   the similarity GEMM never needs a K tail.
 // * Geometry in structure-of-arrays form, plus the lateral coordinate
 //   h = c . r (viewer right vector) as an unevaluated sum hi + lo of two floats
@@ -83,58 +83,101 @@ __device__ inline uint8_t fp8_e4m3_rne(float f) {
   return sign | (uint8_t)code;
 }
 
-// One block per row: L2 norm, then the FP32 / BF16 / FP8 copies.
+__device__ inline float bf16_to_float(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ inline float fp8_e4m3_to_float(uint8_t c) {
+  float sgn = (c & 0x80) ? -1.0f : 1.0f;
+  int e = (c >> 3) & 0xF, m = c & 7;
+  if (e == 0) return sgn * (float)m * 0.001953125f;  // m * 2^-9
+  return sgn * ldexpf(1.0f + (float)m * 0.125f, e - 7);
+}
+
+__device__ inline float block_sum(float v, float* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  float r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ inline float block_max(float v, float* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  float r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// One block per row: L2 norm, the FP32 copy, then the reduced-precision
+// copies with the 2-norms of their values and of their rounding errors
+// (accumulated in FP32 and rounded up by a relative 1e-3 margin; they feed an
+// error bound, never a score).
 __global__ __launch_bounds__(256) void k_normalize_rows(const float* __restrict__ src, int64_t rows, int32_t d,
-                                                        int32_t ldk, float* __restrict__ dst,
-                                                        uint16_t* __restrict__ dst_bf16,
-                                                        uint8_t* __restrict__ dst_fp8,
-                                                        float* __restrict__ dst_scale, int* __restrict__ flags) {
+                                                        int32_t ldk, float* __restrict__ dst, LowPrecRows lp,
+                                                        int* __restrict__ flags) {
   __shared__ float red[256];
-  __shared__ int bad_sh;
   int64_t row = blockIdx.x;
   const float* s = src + row * (int64_t)d;
   int tid = threadIdx.x;
-  if (tid == 0) bad_sh = 0;
-  __syncthreads();
-  float ss = 0.f, amax = 0.f;
-  bool bad = false;
+  float ss = 0.f;
+  int bad = 0;
   for (int k = tid; k < d; k += 256) {
     float v = s[k];
-    if (!isfinite(v)) bad = true;
+    if (!isfinite(v)) bad = 1;
     ss = fmaf(v, v, ss);
   }
-  if (bad) bad_sh = 1;
-  red[tid] = ss;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (tid < w) red[tid] += red[tid + w];
-    __syncthreads();
-  }
-  float nrm = sqrtf(red[0]);
+  float nbad = block_max((float)bad, red);
+  float nrm = sqrtf(block_sum(ss, red));
   bool zero = !(nrm > 0.f) || !isfinite(nrm);
-  if (tid == 0 && (bad_sh || zero)) atomicOr(flags, bad_sh ? kBadDesc : kZeroNorm);
+  if (tid == 0 && (nbad > 0.f || zero)) atomicOr(flags, nbad > 0.f ? kBadDesc : kZeroNorm);
   float inv = zero ? 0.f : 1.0f / nrm;
   float* o = dst + row * (int64_t)ldk;
+  float amax = 0.f, eb = 0.f, nb = 0.f;
   for (int k = tid; k < ldk; k += 256) {
-    float v = k < d ? s[k] * inv : 0.f;
-    if (zero) v = 0.f;
+    float v = (k < d && !zero) ? s[k] * inv : 0.f;
     o[k] = v;
     amax = fmaxf(amax, fabsf(v));
-    if (dst_bf16) dst_bf16[row * (int64_t)ldk + k] = bf16_rne(v);
+    if (lp.bf16) {
+      uint16_t b = bf16_rne(v);
+      lp.bf16[row * (int64_t)ldk + k] = b;
+      float r = bf16_to_float(b);
+      eb = fmaf(r - v, r - v, eb);
+      nb = fmaf(r, r, nb);
+    }
   }
-  if (!dst_fp8) return;
-  __syncthreads();
-  red[tid] = amax;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (tid < w) red[tid] = fmaxf(red[tid], red[tid + w]);
-    __syncthreads();
+  if (lp.bf16) {
+    float e2 = block_sum(eb, red), n2 = block_sum(nb, red);
+    if (tid == 0) {
+      if (lp.err_bf16) lp.err_bf16[row] = sqrtf(e2) * 1.001f + 1e-30f;
+      if (lp.nrm_bf16) lp.nrm_bf16[row] = sqrtf(n2) * 1.001f;
+    }
   }
-  float scale = red[0] > 0.f ? red[0] / kFp8Max : 1.0f;
-  if (tid == 0) dst_scale[row] = scale;
+  if (!lp.fp8) return;
+  __syncthreads();
+  float am = block_max(amax, red);
+  float scale = am > 0.f ? am / kFp8Max : 1.0f;
+  if (tid == 0) lp.fp8_scale[row] = scale;
+  float ef = 0.f, nf = 0.f;
   for (int k = tid; k < ldk; k += 256) {
     float v = o[k];
-    dst_fp8[row * (int64_t)ldk + k] = fp8_e4m3_rne(v / scale);
+    uint8_t c = fp8_e4m3_rne(v / scale);
+    lp.fp8[row * (int64_t)ldk + k] = c;
+    float r = fp8_e4m3_to_float(c) * scale;
+    ef = fmaf(r - v, r - v, ef);
+    nf = fmaf(r, r, nf);
+  }
+  float e2 = block_sum(ef, red), n2 = block_sum(nf, red);
+  if (tid == 0) {
+    if (lp.err_fp8) lp.err_fp8[row] = sqrtf(e2) * 1.001f + 1e-30f;
+    if (lp.nrm_fp8) lp.nrm_fp8[row] = sqrtf(n2) * 1.001f;
   }
 }
 
@@ -180,10 +223,16 @@ hipError_t launch_validate_memory(const float* desc, const float* center, const 
 }
 
 hipError_t launch_normalize_rows(const float* src, int64_t rows, int32_t d, int32_t ldk, float* dst_f32,
-                                 uint16_t* dst_bf16, uint8_t* dst_fp8, float* dst_scale, int* flags, hipStream_t s) {
+                                 const LowPrecRows& lp, int* flags, hipStream_t s) {
   if (rows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_normalize_rows, dim3((unsigned)rows), dim3(256), 0, s, src, rows, d, ldk, dst_f32, dst_bf16,
-                     dst_fp8, dst_scale, flags);
+  hipLaunchKernelGGL(k_normalize_rows, dim3((unsigned)rows), dim3(256), 0, s, src, rows, d, ldk, dst_f32, lp, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, reinterpret_cast<uint32_t*>(p),
+                     n, (uint32_t)v);
   return hipGetLastError();
 }
 

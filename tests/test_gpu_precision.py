@@ -1,0 +1,136 @@
+"""Reduced-precision form (BF16 / FP8-e4m3 similarity GEMM + FP32 rescoring).
+
+Checks, through the C ABI:
+  * every returned object's score, relation terms and bound anchors are the
+    exact FP32 ones (rescoring), against the FP64 oracle;
+  * every query the library certifies returns the exact TopK (oracle);
+  * Recall@10 against exact scoring (the FP32 path, itself oracle-checked) is
+    at least 0.99 over the whole batch, certified or not.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import CONFIGS, make_queries, make_scene
+from tests._parity import ABS, REL, assert_topk_valid, assert_values_close
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = {"bf16": 1, "fp8": 2}
+
+
+@pytest.fixture(scope="module")
+def farm():
+    import paper_2606_15476_amd as farm
+    return farm
+
+
+def _check_rows(scene, qb, rows, ids, sc, terms, anch, cert, oidx, osc, k):
+    idx_of = {int(v): i for i, v in enumerate(scene.ids)}
+    sub = qb.subset(rows)
+    # oracle scores + terms of every returned object
+    qsel = np.repeat(np.arange(len(rows)), k).astype(np.int32)
+    osel = np.array([idx_of[int(g)] for r in rows for g in ids[r]], np.int64)
+    ps, psem, pt, pb = oracle.score_pairs(scene, sub, qsel, osel)
+    assert_values_close(sc[rows].reshape(-1), ps, "rescored scores")
+    for m in range(len(qsel)):
+        row = rows[qsel[m]]
+        R = int(qb.rel_off[row + 1] - qb.rel_off[row])
+        rank = m % k
+        assert_values_close(terms[row, rank, :R], pt[m, :R], "rescored terms")
+        for e in range(R):
+            j = idx_of[int(anch[row, rank, e])]
+            v = oracle.binding_value(scene, int(qb.rel_pred[qb.rel_off[row] + e]), qb.rel_anchor[qb.rel_off[row] + e],
+                                     int(osel[m]), j)
+            assert abs(v - pt[m, e]) <= REL * pt[m, e] + ABS
+    n_cert = 0
+    for i, row in enumerate(rows):
+        if cert[row] != 1:
+            continue
+        n_cert += 1
+        o_ids = scene.ids[oidx[i][oidx[i] >= 0]]
+        o_sc = osc[i][oidx[i] >= 0]
+        known = {int(a): float(b) for a, b in zip(o_ids, o_sc)}
+        lut = {int(g): float(s) for g, s in zip(ids[row], ps[i * k:(i + 1) * k])}
+        assert_topk_valid(ids[row], sc[row], o_ids, o_sc, lambda g: known.get(g, lut.get(g)), k)
+    return n_cert
+
+
+def _recall(ids_a, ids_b, k):
+    return float(np.mean([len(set(map(int, a[:k])) & set(map(int, b[:k]))) / k for a, b in zip(ids_a, ids_b)]))
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+def test_precision_form_mid_all_queries(farm, dtype):
+    from tests import _gpu
+    cfg = CONFIGS["mid"]
+    scene = make_scene(cfg)
+    qb = make_queries(cfg, scene)
+    mem = _gpu.build_memory(scene, flags=farm.FARM_BUILD_BF16 | farm.FARM_BUILD_FP8)
+    ws = farm.Workspace(mem, qb.q, qb.r_tot, 64)
+    ids, sc, terms, anch, cert = _gpu.query_topk(mem, ws, qb, cfg.k, dtype=DTYPES[dtype], rescore_mult=4,
+                                                 with_cert=True)
+    exact = _gpu.query_topk(mem, ws, qb, cfg.k)
+    rows = list(range(qb.q))
+    oidx, osc, ot, ob, ns = oracle.topk_bounded(scene, qb, cfg.k + 8)
+    n_cert = _check_rows(scene, qb, rows, ids, sc, terms, anch, cert, oidx, osc, cfg.k)
+    rec = _recall(ids, exact[0], cfg.k)
+    print(f"[{dtype} mid] certified {n_cert}/{qb.q}, recall@10 vs exact {rec:.4f}", flush=True)
+    assert rec >= 0.99
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+def test_precision_form_full_size(farm, dtype):
+    """N = 20,000, 4,096 queries (the benchmark launch); recall over the whole batch against the
+    exact FP32 path; 12 sampled queries against the oracle."""
+    from tests import _gpu
+    cfg = CONFIGS["precision"]
+    scene = make_scene(cfg)
+    qb = make_queries(cfg, scene)
+    mem = _gpu.build_memory(scene, flags=farm.FARM_BUILD_BF16 | farm.FARM_BUILD_FP8)
+    ws = farm.Workspace(mem, qb.q, qb.r_tot, 64)
+    print(f"[{dtype} precision] n={scene.n} q={qb.q}", flush=True)
+    ids, sc, terms, anch, cert = _gpu.query_topk(mem, ws, qb, cfg.k, dtype=DTYPES[dtype], rescore_mult=4,
+                                                 with_cert=True)
+    exact = _gpu.query_topk(mem, ws, qb, cfg.k)
+    rec = _recall(ids, exact[0], cfg.k)
+    print(f"[{dtype} precision] certified {int((cert == 1).sum())}/{qb.q}, recall@10 vs exact {rec:.4f}", flush=True)
+    assert rec >= 0.99
+    # certified rows agree with the exact path's ids wherever the exact scores are well separated
+    rows = list(np.random.default_rng(11).choice(qb.q, size=12, replace=False))
+    oidx, osc, ot, ob, ns = oracle.topk_bounded(scene, qb.subset(rows), cfg.k + 6)
+    _check_rows(scene, qb, rows, ids, sc, terms, anch, cert, oidx, osc, cfg.k)
+
+
+def test_precision_form_small_scenes(farm):
+    """Fewer objects than candidates: everything is rescored and certified."""
+    from tests import _gpu
+    cfg = CONFIGS["tiny"]
+    scene = make_scene(cfg, n=30)
+    qb = make_queries(cfg, scene, q=5)
+    mem = _gpu.build_memory(scene, flags=farm.FARM_BUILD_BF16 | farm.FARM_BUILD_FP8)
+    ws = farm.Workspace(mem, qb.q, qb.r_tot, 64)
+    s64 = oracle.score(scene, qb)
+    for dt in DTYPES.values():
+        ids, sc, terms, anch, cert = _gpu.query_topk(mem, ws, qb, 10, dtype=dt, rescore_mult=4, with_cert=True)
+        assert np.all(cert == 1)
+        for qq in range(qb.q):
+            order = oracle.topk(s64[qq], scene.ids, 18)
+            by_id = {int(v): s64[qq, i] for i, v in enumerate(scene.ids)}
+            assert_topk_valid(ids[qq], sc[qq], scene.ids[order], s64[qq, order], lambda g: by_id[g], 10)
+
+
+def test_precision_form_requires_built_copy(farm):
+    from tests import _gpu
+    cfg = CONFIGS["tiny"]
+    scene = make_scene(cfg)
+    qb = make_queries(cfg, scene, q=2)
+    mem = _gpu.build_memory(scene)  # FP32 only
+    ws = farm.Workspace(mem, qb.q, qb.r_tot, 64)
+    with pytest.raises(farm.FarmError) as e:
+        _gpu.query_topk(mem, ws, qb, 10, dtype=1)
+    assert e.value.status == -4
+    with pytest.raises(farm.FarmError):  # rescore_mult * k beyond max_k
+        mem2 = _gpu.build_memory(scene, flags=farm.FARM_BUILD_BF16)
+        ws2 = farm.Workspace(mem2, qb.q, qb.r_tot, 16)
+        _gpu.query_topk(mem2, ws2, qb, 10, dtype=1, rescore_mult=4)
