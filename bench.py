@@ -69,6 +69,7 @@ def parse():
     p.add_argument("--workload", default="precision")
     p.add_argument("--form", default="f32", choices=["f32", "bf16", "fp8"])
     p.add_argument("--rescore-mult", type=int, default=4)
+    p.add_argument("--method", default="exhaustive", choices=["exhaustive", "bounded"])
     p.add_argument("--k", type=int, default=10)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=0, help="queries in the CPU-oracle sample (0 = auto)")
@@ -123,11 +124,12 @@ def main():
     ot = torch.empty((qb.q, k, 8), dtype=torch.float32, device=dev)
     ob = torch.empty((qb.q, k, 8), dtype=torch.int32, device=dev)
     dtype = {"f32": farm.F32, "bf16": farm.BF16, "fp8": farm.FP8_E4M3}[args.form]
+    method = {"exhaustive": farm.EXHAUSTIVE, "bounded": farm.BOUNDED}[args.method]
     cert = torch.zeros((qb.q,), dtype=torch.int32, device=dev)
 
     def step():
         farm.query_topk(mem, ws, target, qb.target_cls, qb.rel_off, qb.rel_pred, anchors, k, oid, osc, ot, ob,
-                        dtype=dtype, rescore_mult=args.rescore_mult, certified=cert)
+                        dtype=dtype, rescore_mult=args.rescore_mult, certified=cert, method=method)
 
     for w in range(args.warmup):
         step()
@@ -153,7 +155,7 @@ def main():
 
     certified = int((cert.cpu().numpy() == 1).sum())
     recall_exact = None
-    if dtype != farm.F32:
+    if dtype != farm.F32 or method != farm.EXHAUSTIVE:
         # Recall@K of this form against the exact FP32 path over the whole batch
         xid = torch.empty_like(oid)
         xsc = torch.empty_like(osc)
@@ -212,7 +214,7 @@ def main():
         "data": "synthetic (seeded scene generator; the paper's datasets are not used)",
         "config": {"workload": f"{cfg.name}: N={scene.n} objects, D={scene.d}, Q={qb.q} queries, "
                                f"R~U{{{cfg.r_min}..{cfg.r_max}}} (R_tot={qb.r_tot}), K={k}",
-                   "form": args.form, "global_batch": qb.q, "parallelism": "none (1 GPU)"},
+                   "form": args.form, "method": args.method, "global_batch": qb.q, "parallelism": "none (1 GPU)"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
                        "what": "whole-batch latency of one step"},
         "phase_ms": phase_ms,
@@ -221,11 +223,19 @@ def main():
         "recall_at_10_vs_oracle": recall,
         "recall_at_10_vs_exact_f32": recall_exact,
         "certified_queries": certified,
-        "form": {"f32": "exhaustive FP32 (plain method)",
-                 "bf16": f"BF16 GEMM + exhaustive upper-bound pass + FP32 rescoring of top {args.rescore_mult}K",
-                 "fp8": f"FP8 GEMM + exhaustive upper-bound pass + FP32 rescoring of top {args.rescore_mult}K"}[args.form],
+        "form": form_name(args),
     }
     print(json.dumps(out), flush=True)
+
+
+def form_name(args):
+    gemm = {"f32": "FP32", "bf16": "BF16", "fp8": "FP8-e4m3"}[args.form] + " similarity GEMM"
+    if args.method == "bounded":
+        return (gemm + " + exact bound-pruned TopK (objects whose s_sem bound can reach the K-th lower bound "
+                "scored in FP32 over every anchor)")
+    if args.form == "f32":
+        return "exhaustive FP32 (plain method: every object over every anchor)"
+    return gemm + f" + exhaustive estimate/upper-bound pass + FP32 rescoring of the top {args.rescore_mult}K"
 
 
 def cpu_baseline(scene, qb, oid, osc, k, sample):

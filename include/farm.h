@@ -159,12 +159,26 @@ FARM_API farm_status farm_score_query(const farm_memory* mem, farm_workspace* ws
 FARM_API farm_status farm_topk(const farm_memory* mem, farm_workspace* ws, const float* scores, int32_t q,
                       int32_t k, uint32_t* out_id, float* out_score, int32_t* out_index, void* stream);
 
+/* How the fused path finds the TopK. */
+typedef enum {
+  /* score every object over every anchor (the plain method); with a reduced
+     precision dtype, the top rescore_mult*k by estimate are rescored in FP32 */
+  FARM_METHOD_EXHAUSTIVE = 0,
+  /* exact bound-pruned TopK: the soft blend keeps each score in
+     [(1-w) s_sem, s_sem], so only objects whose s_sem upper bound reaches the
+     K-th largest lower bound (1-w) s_sem can enter the TopK; those (at most
+     2048 per query) are scored exactly in FP32 */
+  FARM_METHOD_BOUNDED = 1
+} farm_method;
+
 /* Options of the fused path. */
 typedef struct {
   int32_t dtype;        /* farm_dtype of the similarity GEMM (FARM_F32 = exact path) */
-  int32_t rescore_mult; /* reduced precision: rescore the top rescore_mult*k in FP32 (>= 1) */
+  int32_t method;       /* farm_method */
+  int32_t rescore_mult; /* EXHAUSTIVE with reduced precision: rescore the top rescore_mult*k (>= 1) */
+  int32_t reserved;     /* must be 0 */
   int32_t* certified;   /* device [q] out or NULL: 1 when the returned set is provably
-                           the exact TopK (always 1 on the FP32 path), else 0 */
+                           the exact TopK, else 0 */
 } farm_score_opts;
 
 /*

@@ -54,6 +54,11 @@ def _load():
         lib.farm_oracle_topk.argtypes = [i64, P, P, i32, P]
         lib.farm_oracle_binding_value.restype = ctypes.c_double
         lib.farm_oracle_binding_value.argtypes = [i64, ctypes.c_int, P, P, P, ctypes.c_int, P, i64, i64]
+        lib.farm_oracle_pair_features.restype = None
+        lib.farm_oracle_pair_features.argtypes = [P, P, P, i64, i64, P]
+        lib.farm_oracle_mlp.restype = ctypes.c_int
+        lib.farm_oracle_mlp.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, i64, P, P, P, P,
+                                        P, P, P, P, P, P, P]
         lib.farm_oracle_topk_bounded.restype = ctypes.c_int
         lib.farm_oracle_topk_bounded.argtypes = [i64, ctypes.c_int, P, P, P, P, P, i32, P, P, P, P, P,
                                                  i32, P, P, P, P, P]
@@ -190,3 +195,42 @@ def binding_value(scene, pred: int, anchor_vec, i: int, j: int) -> float:
     av, pa = _c(anchor_vec, np.float32)
     return float(lib.farm_oracle_binding_value(int(desc.shape[0]), int(desc.shape[1]), pd, pc, pv, int(pred), pa,
                                                int(i), int(j)))
+
+
+NPRED = 5
+NGEO = 12
+
+
+def pair_features(scene, o: int, a: int):
+    """The 12 relative-geometry features g(o, a) of the proposal network, FP64."""
+    lib = _load()
+    c, pc = _c(scene.center, np.float32)
+    e, pe = _c(scene.extent, np.float32)
+    r, pr = _c(scene.view_right, np.float32)
+    g = np.zeros(NGEO, np.float64)
+    lib.farm_oracle_pair_features(pc, pe, pr, int(o), int(a), g.ctypes.data_as(ctypes.c_void_p))
+    return g
+
+
+def mlp(weights: dict, X, pred, label, grads: bool = True):
+    """Loss (mean BCE-with-logits on the labelled predicate), logits [n,5] and,
+    with ``grads``, the FP64 gradients {name: array} of the proposal network.
+    weights: W1 [h,in], b1 [h], W2 [h,h], b2 [h], W3 [5,h], b3 [5]."""
+    lib = _load()
+    W = {k: np.ascontiguousarray(v, np.float64) for k, v in weights.items()}
+    h, inp = W["W1"].shape
+    Xa, px = _c(X, np.float64)
+    pa, pp = _c(pred, np.int32)
+    la, pl = _c(label, np.float64)
+    n = int(Xa.shape[0])
+    loss = ctypes.c_double()
+    logits = np.zeros((n, NPRED), np.float64)
+    g = {k: np.zeros_like(v) for k, v in W.items()} if grads else None
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    rc = lib.farm_oracle_mlp(inp, h, ptr(W["W1"]), ptr(W["b1"]), ptr(W["W2"]), ptr(W["b2"]), ptr(W["W3"]),
+                             ptr(W["b3"]), n, px, pp, pl, ctypes.byref(loss),
+                             *(ptr(g[k]) if grads else None for k in ("W1", "b1", "W2", "b2", "W3", "b3")),
+                             ptr(logits))
+    if rc:
+        raise ValueError(f"oracle mlp failed ({rc})")
+    return float(loss.value), logits, g

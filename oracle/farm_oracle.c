@@ -38,6 +38,7 @@
  * loops in the order of the definition.  OpenMP parallelises only the
  * independent outer loop over queries (or sampled targets).
  */
+#define _GNU_SOURCE
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -422,4 +423,115 @@ double farm_oracle_binding_value(int64_t n, int d, const float* desc, const floa
     free(u);
     free(v);
     return val;
+}
+
+/* ------------------------------------------------------------------------
+ * Learned anchor proposal network (test infrastructure for the GPU kernels).
+ * Not a construct of the paper: the anchor-candidate sets K_a of the
+ * query-time complexity analysis are produced here by a small network that
+ * ranks (target, anchor) pairs per predicate.
+ *
+ *   x  = [u_o ; u_a ; g(o, a)]                (2d + 12 inputs)
+ *   h1 = GELU(W1 x + b1),  h2 = GELU(W2 h1 + b2),  y = W3 h2 + b3   (5 logits)
+ *   GELU(v) = v/2 (1 + erf(v / sqrt 2))
+ *   loss = mean_s BCEwithLogits(y_s[p_s], label_s)
+ *        = mean_s [ max(y,0) - y*label + log(1 + exp(-|y|)) ]
+ *
+ * g(o, a) = [c_o - c_a (3), e_o (3), e_a (3), |c_o - c_a|, (c_o - c_a).r,
+ *            (z_o - e_o,z/2) - (z_a + e_a,z/2)]   (bottom of o minus top of a)
+ * Weights are row-major: W1 [h][in], W2 [h][h], W3 [5][h].
+ * ------------------------------------------------------------------------ */
+#define ORACLE_NPRED 5
+#define ORACLE_NGEO 12
+
+static double gelu(double v) { return 0.5 * v * (1.0 + erf(v / sqrt(2.0))); }
+static double gelu_grad(double v) {
+    return 0.5 * (1.0 + erf(v / sqrt(2.0))) + v * exp(-0.5 * v * v) / sqrt(2.0 * M_PI);
+}
+
+void farm_oracle_pair_features(const float* center, const float* extent, const float* right, int64_t o, int64_t a,
+                               double* g) {
+    double d[3];
+    for (int k = 0; k < 3; ++k) d[k] = (double)center[o * 3 + k] - (double)center[a * 3 + k];
+    for (int k = 0; k < 3; ++k) g[k] = d[k];
+    for (int k = 0; k < 3; ++k) g[3 + k] = extent[o * 3 + k];
+    for (int k = 0; k < 3; ++k) g[6 + k] = extent[a * 3 + k];
+    g[9] = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    g[10] = d[0] * (double)right[0] + d[1] * (double)right[1];
+    g[11] = ((double)center[o * 3 + 2] - 0.5 * (double)extent[o * 3 + 2]) -
+            ((double)center[a * 3 + 2] + 0.5 * (double)extent[a * 3 + 2]);
+}
+
+/*
+ * Loss and gradients over nsamp samples with inputs X [nsamp][in], predicate
+ * p_s and binary label_s.  Gradient outputs may be NULL; logits [nsamp][5]
+ * may be NULL.  Plain backpropagation, one sample at a time.
+ */
+int farm_oracle_mlp(int in, int h, const double* W1, const double* b1, const double* W2, const double* b2,
+                    const double* W3, const double* b3, int64_t nsamp, const double* X, const int32_t* pred,
+                    const double* label, double* loss, double* gW1, double* gb1, double* gW2, double* gb2,
+                    double* gW3, double* gb3, double* logits) {
+    double* z1 = (double*)malloc(sizeof(double) * h);
+    double* a1 = (double*)malloc(sizeof(double) * h);
+    double* z2 = (double*)malloc(sizeof(double) * h);
+    double* a2 = (double*)malloc(sizeof(double) * h);
+    double* d2 = (double*)malloc(sizeof(double) * h);
+    double* d1 = (double*)malloc(sizeof(double) * h);
+    if (!z1 || !a1 || !z2 || !a2 || !d2 || !d1) { free(z1); free(a1); free(z2); free(a2); free(d2); free(d1); return -2; }
+    if (gW1) memset(gW1, 0, sizeof(double) * (size_t)h * in);
+    if (gb1) memset(gb1, 0, sizeof(double) * h);
+    if (gW2) memset(gW2, 0, sizeof(double) * (size_t)h * h);
+    if (gb2) memset(gb2, 0, sizeof(double) * h);
+    if (gW3) memset(gW3, 0, sizeof(double) * ORACLE_NPRED * h);
+    if (gb3) memset(gb3, 0, sizeof(double) * ORACLE_NPRED);
+    double total = 0.0;
+    for (int64_t s = 0; s < nsamp; ++s) {
+        const double* x = X + s * in;
+        for (int j = 0; j < h; ++j) {
+            double acc = b1[j];
+            for (int k = 0; k < in; ++k) acc += W1[(size_t)j * in + k] * x[k];
+            z1[j] = acc;
+            a1[j] = gelu(acc);
+        }
+        for (int j = 0; j < h; ++j) {
+            double acc = b2[j];
+            for (int k = 0; k < h; ++k) acc += W2[(size_t)j * h + k] * a1[k];
+            z2[j] = acc;
+            a2[j] = gelu(acc);
+        }
+        double y[ORACLE_NPRED];
+        for (int c = 0; c < ORACLE_NPRED; ++c) {
+            double acc = b3[c];
+            for (int k = 0; k < h; ++k) acc += W3[(size_t)c * h + k] * a2[k];
+            y[c] = acc;
+            if (logits) logits[s * ORACLE_NPRED + c] = acc;
+        }
+        const int p = pred[s];
+        const double t = label[s], v = y[p];
+        total += (v > 0 ? v : 0.0) - v * t + log1p(exp(-fabs(v)));
+        if (!gW1 && !gb1 && !gW2 && !gb2 && !gW3 && !gb3) continue;
+        /* d loss / d y[p] = sigmoid(y[p]) - label, divided by nsamp (mean) */
+        const double dy = (1.0 / (1.0 + exp(-v)) - t) / (double)nsamp;
+        for (int k = 0; k < h; ++k) {
+            if (gW3) gW3[(size_t)p * h + k] += dy * a2[k];
+            d2[k] = dy * W3[(size_t)p * h + k] * gelu_grad(z2[k]);
+        }
+        if (gb3) gb3[p] += dy;
+        for (int j = 0; j < h; ++j) {
+            if (gb2) gb2[j] += d2[j];
+            if (gW2) for (int k = 0; k < h; ++k) gW2[(size_t)j * h + k] += d2[j] * a1[k];
+        }
+        for (int k = 0; k < h; ++k) {
+            double acc = 0.0;
+            for (int j = 0; j < h; ++j) acc += W2[(size_t)j * h + k] * d2[j];
+            d1[k] = acc * gelu_grad(z1[k]);
+        }
+        for (int j = 0; j < h; ++j) {
+            if (gb1) gb1[j] += d1[j];
+            if (gW1) for (int k = 0; k < in; ++k) gW1[(size_t)j * in + k] += d1[j] * x[k];
+        }
+    }
+    if (loss) *loss = total / (double)(nsamp > 0 ? nsamp : 1);
+    free(z1); free(a1); free(z2); free(a2); free(d2); free(d1);
+    return 0;
 }

@@ -100,7 +100,9 @@ size_t workspace_bytes_for(const farm_memory* mem, int32_t max_q, int32_t max_re
   b += sizeof(int);
   b += 2 * (size_t)topk_candidate_capacity(mem->n, max_q, max_k + 1) * (sizeof(uint64_t) + sizeof(int32_t));
   b += 2 * sizeof(float);
-  b += (size_t)max_q * max_k * (sizeof(int32_t) + sizeof(float) + kMaxRel * (sizeof(float) + sizeof(uint32_t)));
+  const size_t cap = (size_t)(max_k > kBoundCap ? max_k : kBoundCap);
+  b += (size_t)max_q * cap * (sizeof(int32_t) + sizeof(float) + kMaxRel * (sizeof(float) + sizeof(uint32_t)));
+  b += (size_t)max_q * sizeof(int32_t);
   return b;
 }
 
@@ -444,7 +446,9 @@ farm_status farm_workspace_create(const farm_memory* mem, int32_t max_q, int32_t
       if ((st = dalloc(ws->allocs, ws->bytes, &ws->cand_idx[b], (size_t)ws->cand_cap, "TopK indices"))) return fail(st);
     }
     ws->max_k = max_k;
-    const size_t nk = (size_t)max_q * max_k;
+    ws->rs_cap = max_k > kBoundCap ? max_k : kBoundCap;
+    const size_t nk = (size_t)max_q * ws->rs_cap;
+    if ((st = dalloc(ws->allocs, ws->bytes, &ws->cand_count, (size_t)max_q, "candidate counts"))) return fail(st);
     if ((st = dalloc(ws->allocs, ws->bytes, &ws->rs_idx, nk, "winner indices"))) return fail(st);
     if ((st = dalloc(ws->allocs, ws->bytes, &ws->rs_score, nk, "rescored scores"))) return fail(st);
     if ((st = dalloc(ws->allocs, ws->bytes, &ws->rs_terms, nk * kMaxRel, "rescored terms"))) return fail(st);
@@ -592,7 +596,13 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
     if (q == 0) return FARM_OK;
     if (!out_id || !out_score) { set_error("null output pointer"); return FARM_ERR_INVALID_ARG; }
     const int32_t dtype = opts ? opts->dtype : FARM_F32;
+    const int32_t method = opts ? opts->method : FARM_METHOD_EXHAUSTIVE;
     int32_t* certified = opts ? opts->certified : nullptr;
+    if (method != FARM_METHOD_EXHAUSTIVE && method != FARM_METHOD_BOUNDED) {
+      set_error("unknown method %d", method);
+      return FARM_ERR_INVALID_ARG;
+    }
+    if (opts && opts->reserved != 0) { set_error("reserved option field must be 0"); return FARM_ERR_INVALID_ARG; }
     if (dtype != FARM_F32 && dtype != FARM_BF16 && dtype != FARM_FP8_E4M3) {
       set_error("unknown dtype %d", dtype);
       return FARM_ERR_INVALID_ARG;
@@ -602,7 +612,7 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
       return FARM_ERR_UNSUPPORTED;
     }
     int32_t c = k;  // candidates that leave the first TopK
-    if (dtype != FARM_F32) {
+    if (dtype != FARM_F32 && method == FARM_METHOD_EXHAUSTIVE) {
       const int32_t mult = opts->rescore_mult;
       if (mult < 1) { set_error("rescore_mult = %d must be >= 1", mult); return FARM_ERR_INVALID_ARG; }
       if ((int64_t)mult * k > ws->max_k) {
@@ -618,6 +628,21 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
     FARM_TRY(stage_meta(ws, q, R, target_cls, rel_off, rel_pred, s, &meta));
     SimBound bound;
     FARM_TRY(similarities(mem, ws, q, R, target, rel_anchor, meta, dtype, &bound, s));
+    if (method == FARM_METHOD_BOUNDED) {
+      {
+        PhaseTimer t(ws, s, FARM_PHASE_TOPK);
+        FARM_HIP(launch_bound_candidates(mem, ws->sim, ws->ld_s, q, meta, bound, k, kBoundCap, ws->rs_idx,
+                                         ws->cand_count, certified, s),
+                 "bound candidates");
+      }
+      PhaseTimer t(ws, s, FARM_PHASE_RESCORE);
+      FARM_HIP(launch_rescore(mem, ws, ws->sim, ws->ld_s, q, meta, bound, ws->rs_idx, ws->cand_count, kBoundCap, s),
+               "candidate scoring");
+      FARM_HIP(launch_rescore_select(ws, q, kBoundCap, k, nullptr, nullptr, mem->n, out_id, out_score, out_terms,
+                                     out_anchor_id, nullptr, s),
+               "candidate select");
+      return FARM_OK;
+    }
     {
       PhaseTimer t(ws, s, FARM_PHASE_PAIR);
       FARM_HIP(launch_pair_exhaustive(mem, ws->sim, ws->ld_s, q, meta, bound, ws->scores, ws->ld_s, nullptr, nullptr,
@@ -647,7 +672,7 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
       FARM_HIP(launch_topk(mem, ws, ws->scores_hi, ws->ld_s, q, c + 1, &hi_key, &hi_idx, s), "bound topk");
     }
     PhaseTimer t(ws, s, FARM_PHASE_RESCORE);
-    FARM_HIP(launch_rescore(mem, ws, ws->sim, ws->ld_s, q, meta, bound, ws->rs_idx, c, s), "rescore");
+    FARM_HIP(launch_rescore(mem, ws, ws->sim, ws->ld_s, q, meta, bound, ws->rs_idx, nullptr, c, s), "rescore");
     FARM_HIP(launch_rescore_select(ws, q, c, k, hi_key, hi_idx, mem->n, out_id, out_score, out_terms, out_anchor_id,
                                    certified, s),
              "rescore select");

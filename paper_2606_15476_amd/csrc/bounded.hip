@@ -1,0 +1,150 @@
+// bounded.hip -- exact TopK without scoring every object.
+//
+// The soft blend keeps the spatial factor in [1 - w, 1] (Appendix "Retrieval
+// Details", "Why soft, not hard?"), so every object's score lies between
+// (1 - w) s_sem and s_sem.  Let L be the K-th largest lower bound
+// (1 - w) s_sem_lo over all objects: K objects score at least L, so an object
+// whose upper bound s_sem_hi is below L scores strictly below them and cannot
+// enter the TopK.  Only the remaining candidates are scored (rescore.hip);
+// the TopK among them is the exact TopK.  With FP32 similarities
+// s_sem_lo = s_sem_hi = s_sem; with BF16/FP8 similarities they are the
+// estimate minus/plus its proven error bound.
+//
+// One block per query: a 4-round radix select (8-bit digits, MSB first) finds
+// L on the IEEE bits of the non-negative lower bounds, then an ordered
+// compaction (per-thread contiguous chunks + block prefix scan) lists the
+// candidates in index order.  If more than `cap` objects survive, the list
+// keeps the `cap` largest upper bounds (a second radix select) and the query
+// is marked uncertified.
+#include <math.h>
+
+#include "farm_internal.h"
+
+namespace farm {
+namespace {
+
+constexpr int kThreads = 256;
+
+struct SemBounds {
+  float lo, hi;
+};
+
+__device__ inline SemBounds sem_bounds(const float* srow, int64_t i, int tc, const int32_t* cls, const SimBound& b,
+                                       int32_t qq) {
+  const float s = srow[i];
+  if (!b.q_nrm) return {s, s};
+  const float kappa = (tc >= 0 && cls && cls[i] >= 0 && cls[i] != tc) ? kClassFactor : 1.0f;
+  const float d = kappa * fmaf(b.q_nrm[qq], b.o_err[i], b.q_err[qq] + b.acc);
+  return {fmaxf(0.f, s - d), fminf(kappa, s + d)};
+}
+
+// K-th largest key among the values produced by `key(i)` (non-negative floats
+// as IEEE bits, or 0 for excluded entries).  All threads return the result.
+template <class KeyFn>
+__device__ uint32_t radix_select_kth(int64_t n, int64_t k, KeyFn key, uint32_t* hist, uint32_t* shared_word) {
+  uint32_t prefix = 0, mask = 0;
+  int64_t remaining = k;
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    for (int b = threadIdx.x; b < 256; b += kThreads) hist[b] = 0;
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < n; i += kThreads) {
+      const uint32_t u = key(i);
+      if ((u & mask) == prefix) atomicAdd(&hist[(u >> shift) & 0xFFu], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t acc = 0;
+      int bin = 255;
+      for (; bin > 0; --bin) {
+        if (acc + (int64_t)hist[bin] >= remaining) break;
+        acc += hist[bin];
+      }
+      remaining -= acc;
+      shared_word[0] = (uint32_t)bin;
+      shared_word[1] = (uint32_t)remaining;
+    }
+    __syncthreads();
+    prefix |= shared_word[0] << shift;
+    mask |= 0xFFu << shift;
+    remaining = shared_word[1];
+    __syncthreads();
+  }
+  return prefix;
+}
+
+__global__ __launch_bounds__(kThreads) void k_bound_candidates(const float* __restrict__ sim, int64_t ld_s, int64_t n,
+                                                               MetaView meta, SimBound bound,
+                                                               const int32_t* __restrict__ cls, int32_t k,
+                                                               int32_t cap, int32_t* __restrict__ cand,
+                                                               int32_t* __restrict__ count,
+                                                               int32_t* __restrict__ certified) {
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t word[2];
+  __shared__ int32_t scan[kThreads];
+  const int32_t qq = blockIdx.x;
+  const float* srow = sim + (int64_t)qq * ld_s;
+  const int tc = meta.tcls[qq];
+  // L: K-th largest lower bound (1 - w) s_sem_lo
+  float L = -INFINITY;
+  if (n > k) {
+    auto lo_key = [&](int64_t i) {
+      return __float_as_uint((1.0f - kW) * sem_bounds(srow, i, tc, cls, bound, qq).lo);
+    };
+    L = __uint_as_float(radix_select_kth(n, k, lo_key, hist, word));
+  }
+  // candidates: s_sem_hi >= L
+  const int64_t chunk = (n + kThreads - 1) / kThreads;
+  const int64_t i0 = threadIdx.x * chunk, i1 = i0 + chunk < n ? i0 + chunk : n;
+  auto pass = [&](float thresh, bool write) {
+    int32_t c = 0;
+    for (int64_t i = i0; i < i1; ++i) c += sem_bounds(srow, i, tc, cls, bound, qq).hi >= thresh;
+    scan[threadIdx.x] = c;
+    __syncthreads();
+    for (int off = 1; off < kThreads; off <<= 1) {  // inclusive Hillis-Steele scan
+      int32_t v = threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
+      __syncthreads();
+      scan[threadIdx.x] += v;
+      __syncthreads();
+    }
+    const int32_t total = scan[kThreads - 1];
+    if (write) {
+      int32_t pos = scan[threadIdx.x] - c;
+      for (int64_t i = i0; i < i1 && pos < cap; ++i)
+        if (sem_bounds(srow, i, tc, cls, bound, qq).hi >= thresh) cand[(int64_t)qq * cap + pos++] = (int32_t)i;
+    }
+    __syncthreads();
+    return total;
+  };
+  int32_t total = pass(L, false);
+  bool exact = true;
+  float thresh = L;
+  if (total > cap) {
+    // keep the cap largest upper bounds (ties at the threshold may exceed cap: truncated in index order)
+    auto hi_key = [&](int64_t i) {
+      const float h = sem_bounds(srow, i, tc, cls, bound, qq).hi;
+      return h >= L ? __float_as_uint(h) : 0u;
+    };
+    thresh = fmaxf(L, __uint_as_float(radix_select_kth(n, cap, hi_key, hist, word)));
+    exact = false;
+  }
+  total = pass(thresh, true);
+  total = total < cap ? total : cap;
+  for (int32_t c = total + threadIdx.x; c < cap; c += kThreads) cand[(int64_t)qq * cap + c] = -1;
+  if (threadIdx.x == 0) {
+    count[qq] = total;
+    if (certified) certified[qq] = exact ? 1 : 0;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_bound_candidates(const farm_memory* mem, const float* sim, int64_t ld_s, int32_t q, MetaView meta,
+                                   const SimBound& bound, int32_t k, int32_t cap, int32_t* cand, int32_t* count,
+                                   int32_t* certified, hipStream_t s) {
+  if (q <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bound_candidates, dim3((unsigned)q), dim3(kThreads), 0, s, sim, ld_s, mem->n, meta, bound,
+                     mem->cls, k, cap, cand, count, certified);
+  return hipGetLastError();
+}
+
+}  // namespace farm

@@ -18,6 +18,7 @@ constexpr int kRowAlign = 64;      // similarity-matrix rows are padded to a mul
 constexpr float kW = 0.5f;         // soft-blend weight of the relational factor
 constexpr float kClassFactor = 0.3f;
 constexpr float kFp8Max = 448.0f;  // largest finite OCP e4m3 value
+constexpr int32_t kBoundCap = 2048;  // candidates per query kept by the bound-pruned TopK
 
 // Validation flag bits raised by device-side checks.
 enum : int {
@@ -92,11 +93,13 @@ struct farm_workspace {
   int32_t* cand_idx[2] = {nullptr, nullptr};
   int64_t cand_cap = 0;       // elements per buffer
   int32_t max_k = 0;
+  int32_t rs_cap = 0;            // candidate slots per query: max(max_k, kBoundCap)
   // winners / rescoring candidates: object indices, FP32 scores, terms, bound anchors
-  int32_t* rs_idx = nullptr;     // [max_q][max_k]
-  float* rs_score = nullptr;     // [max_q][max_k]
-  float* rs_terms = nullptr;     // [max_q][max_k][FARM_MAX_REL]
-  uint32_t* rs_anchor = nullptr; // [max_q][max_k][FARM_MAX_REL]
+  int32_t* rs_idx = nullptr;     // [max_q][rs_cap]
+  float* rs_score = nullptr;     // [max_q][rs_cap]
+  float* rs_terms = nullptr;     // [max_q][rs_cap][FARM_MAX_REL]
+  uint32_t* rs_anchor = nullptr; // [max_q][rs_cap][FARM_MAX_REL]
+  int32_t* cand_count = nullptr; // [max_q]
   // optional phase timer: pending (start, stop) event pairs per phase
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -191,8 +194,17 @@ hipError_t launch_explain(const farm_memory* mem, const float* sim, int64_t ld_s
 // only anchors whose bounded value can reach the best lower bound get an FP32
 // dot product.  Writes rs_score[q][c], rs_terms/rs_anchor[q][c][8].
 hipError_t launch_rescore(const farm_memory* mem, const farm_workspace* ws, const float* sim, int64_t ld_s,
-                          int32_t q, MetaView meta, const SimBound& bound, const int32_t* cand, int32_t c,
-                          hipStream_t s);
+                          int32_t q, MetaView meta, const SimBound& bound, const int32_t* cand,
+                          const int32_t* cand_count, int32_t c, hipStream_t s);
+
+// ---- bounded.hip
+// Candidates of the exact bound-pruned TopK: per query every object whose
+// s_sem upper bound reaches the K-th largest lower bound (1 - w) s_sem_lo,
+// in index order, into cand[q][cap] (-1 padded), count[q]; certified[q] = 0
+// when more than cap objects qualified (the cap best upper bounds are kept).
+hipError_t launch_bound_candidates(const farm_memory* mem, const float* sim, int64_t ld_s, int32_t q, MetaView meta,
+                                   const SimBound& bound, int32_t k, int32_t cap, int32_t* cand, int32_t* count,
+                                   int32_t* certified, hipStream_t s);
 // Final TopK among rescored candidates; certified[q] (optional) = 1 when the
 // K-th rescored score exceeds, by the FP32 value tolerance, the largest upper
 // bound of any object outside the candidates, or every object was a

@@ -107,48 +107,51 @@ __global__ __launch_bounds__(256) void k_sim_gemm(const uint8_t* __restrict__ A,
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
 
-  uint4 ra[4], rb[4];
+  // Rows past the end of A or B are clamped to the last row: they only feed
+  // accumulator rows/columns that are never stored, and the loads stay
+  // unconditional so the next slab can be in flight under the MFMAs.
   const int lr = tid >> 3, lc = tid & 7;
-  const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
-  auto gload = [&](int64_t kt) {
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      int64_t gm = m0 + lr + 32 * p, gn = n0 + lr + 32 * p;
-      ra[p] = gm < M ? *reinterpret_cast<const uint4*>(A + gm * ld_bytes + kt * kSlab + lc * 16) : zero;
-      rb[p] = gn < N ? *reinterpret_cast<const uint4*>(B + gn * ld_bytes + kt * kSlab + lc * 16) : zero;
-    }
-  };
-  auto sstore = [&]() {
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      As[(lr + 32 * p) * kRowU4 + lc] = ra[p];
-      Bs[(lr + 32 * p) * kRowU4 + lc] = rb[p];
-    }
-  };
+  auto clamp_row = [](int64_t v, int64_t lim) { return v < lim ? v : lim - 1; };
+  const uint4* a0p = reinterpret_cast<const uint4*>(A + clamp_row(m0 + lr, M) * ld_bytes + lc * 16);
+  const uint4* a1p = reinterpret_cast<const uint4*>(A + clamp_row(m0 + lr + 32, M) * ld_bytes + lc * 16);
+  const uint4* a2p = reinterpret_cast<const uint4*>(A + clamp_row(m0 + lr + 64, M) * ld_bytes + lc * 16);
+  const uint4* a3p = reinterpret_cast<const uint4*>(A + clamp_row(m0 + lr + 96, M) * ld_bytes + lc * 16);
+  const uint4* b0p = reinterpret_cast<const uint4*>(B + clamp_row(n0 + lr, N) * ld_bytes + lc * 16);
+  const uint4* b1p = reinterpret_cast<const uint4*>(B + clamp_row(n0 + lr + 32, N) * ld_bytes + lc * 16);
+  const uint4* b2p = reinterpret_cast<const uint4*>(B + clamp_row(n0 + lr + 64, N) * ld_bytes + lc * 16);
+  const uint4* b3p = reinterpret_cast<const uint4*>(B + clamp_row(n0 + lr + 96, N) * ld_bytes + lc * 16);
+  constexpr int kStepU4 = kSlab / 16;  // one slab in 16-byte units
+  uint4 ra0 = a0p[0], ra1 = a1p[0], ra2 = a2p[0], ra3 = a3p[0];
+  uint4 rb0 = b0p[0], rb1 = b1p[0], rb2 = b2p[0], rb3 = b3p[0];
+  uint4* as = As + lr * kRowU4 + lc;
+  uint4* bs = Bs + lr * kRowU4 + lc;
+  as[0] = ra0; as[32 * kRowU4] = ra1; as[64 * kRowU4] = ra2; as[96 * kRowU4] = ra3;
+  bs[0] = rb0; bs[32 * kRowU4] = rb1; bs[64 * kRowU4] = rb2; bs[96 * kRowU4] = rb3;
+  __syncthreads();
 
   const int64_t nk = ld_bytes / kSlab;
-  gload(0);
-  sstore();
-  __syncthreads();
   const int h = lane >> 5, r = lane & 31;
   for (int64_t kt = 0; kt < nk; ++kt) {
-    if (kt + 1 < nk) gload(kt + 1);
+    const int64_t kn = (kt + 1 < nk ? kt + 1 : kt) * kStepU4;
+    ra0 = a0p[kn]; ra1 = a1p[kn]; ra2 = a2p[kn]; ra3 = a3p[kn];
+    rb0 = b0p[kn]; rb1 = b1p[kn]; rb2 = b2p[kn]; rb3 = b3p[kn];
+    // keep the next slab's loads in flight under this slab's MFMAs
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      uint4 a[2], b[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        a[i] = As[(wm * 64 + i * 32 + r) * kRowU4 + 2 * s + h];
-        b[i] = Bs[(wn * 64 + i * 32 + r) * kRowU4 + 2 * s + h];
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) mfma_slice<T>(acc[i][j], a[i], b[j]);
+      const uint4 a_0 = As[(wm * 64 + r) * kRowU4 + 2 * s + h];
+      const uint4 a_1 = As[(wm * 64 + 32 + r) * kRowU4 + 2 * s + h];
+      const uint4 b_0 = Bs[(wn * 64 + r) * kRowU4 + 2 * s + h];
+      const uint4 b_1 = Bs[(wn * 64 + 32 + r) * kRowU4 + 2 * s + h];
+      mfma_slice<T>(acc[0][0], a_0, b_0);
+      mfma_slice<T>(acc[0][1], a_0, b_1);
+      mfma_slice<T>(acc[1][0], a_1, b_0);
+      mfma_slice<T>(acc[1][1], a_1, b_1);
     }
     __syncthreads();
     if (kt + 1 < nk) {
-      sstore();
+      as[0] = ra0; as[32 * kRowU4] = ra1; as[64 * kRowU4] = ra2; as[96 * kRowU4] = ra3;
+      bs[0] = rb0; bs[32 * kRowU4] = rb1; bs[64 * kRowU4] = rb2; bs[96 * kRowU4] = rb3;
       __syncthreads();
     }
   }

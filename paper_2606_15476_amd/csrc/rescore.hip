@@ -127,88 +127,98 @@ __device__ void rescore_relation(const float* __restrict__ arow, const float* __
 __global__ __launch_bounds__(kRsThreads) void k_rescore(
     const float* __restrict__ sim, int64_t ld_s, int32_t q, MetaView meta, SimBound bound,
     const float* __restrict__ qn, const float* __restrict__ dn, int32_t ldk, const int32_t* __restrict__ cand,
-    int32_t C, const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
-    const float* __restrict__ hhi, const float* __restrict__ hlo, const uint32_t* __restrict__ ids,
-    const int32_t* __restrict__ cls, int64_t n, float* __restrict__ rs_score, float* __restrict__ rs_terms,
-    uint32_t* __restrict__ rs_anchor) {
+    const int32_t* __restrict__ cand_count, int32_t C, const float* __restrict__ x, const float* __restrict__ y,
+    const float* __restrict__ z, const float* __restrict__ hhi, const float* __restrict__ hlo,
+    const uint32_t* __restrict__ ids, const int32_t* __restrict__ cls, int64_t n, float* __restrict__ rs_score,
+    float* __restrict__ rs_terms, uint32_t* __restrict__ rs_anchor) {
   __shared__ float red_v[kRsThreads];
   __shared__ uint32_t red_id[kRsThreads];
   __shared__ int32_t surv[kWin];
   __shared__ int surv_n;
-  const int32_t qq = blockIdx.y, cc = blockIdx.x;
-  const int64_t slot = (int64_t)qq * C + cc;
-  const int64_t o = cand[slot];
+  const int32_t qq = blockIdx.y;
   const int tid = threadIdx.x;
   const int r0 = meta.rel_off[qq], r1 = meta.rel_off[qq + 1], R = r1 - r0;
-  if (o < 0) {
-    if (tid == 0) rs_score[slot] = -INFINITY;
-    if (tid < kMaxRel) {
+  const int32_t cnt = cand_count ? cand_count[qq] : C;
+  const bool bounded = bound.q_nrm != nullptr;
+  const float* qt = qn + (int64_t)qq * ldk;
+  const int tc = meta.tcls[qq];
+  for (int32_t cc = blockIdx.x; cc < cnt; cc += gridDim.x) {
+    const int64_t slot = (int64_t)qq * C + cc;
+    const int64_t o = cand[slot];
+    if (o < 0) {
+      if (tid == 0) rs_score[slot] = -INFINITY;
+      if (tid < kMaxRel) {
+        rs_terms[slot * kMaxRel + tid] = 0.f;
+        rs_anchor[slot * kMaxRel + tid] = FARM_NO_ID;
+      }
+      continue;
+    }
+    // target similarity: the FP32 GEMM's value, or an FP32 dot product when the
+    // similarity matrix is reduced-precision
+    float sem;
+    if (!bounded) {
+      sem = sim[(int64_t)qq * ld_s + o];
+    } else {
+      const float* dr = dn + o * ldk;
+      float part = 0.f;
+      for (int k = tid; k < ldk; k += kRsThreads) part = fmaf(qt[k], dr[k], part);
+      red_v[tid] = part;
+      __syncthreads();
+      for (int w = kRsThreads / 2; w > 0; w >>= 1) {
+        if (tid < w) red_v[tid] += red_v[tid + w];
+        __syncthreads();
+      }
+      const float dot = red_v[0];
+      __syncthreads();
+      const float kappa = (tc >= 0 && cls && cls[o] >= 0 && cls[o] != tc) ? kClassFactor : 1.0f;
+      sem = kappa * fmaxf(0.f, dot);
+    }
+    float lsum = 0.f;
+    for (int e = 0; e < R; ++e) {
+      const int r = r0 + e;
+      const int p = meta.rel_pred[r];
+      const float c = sigmoid_scale(p);
+      const float* arow = sim + (int64_t)(q + r) * ld_s;
+      const float* qrow = qn + (int64_t)(q + r) * ldk;
+      const float qnr = bounded ? bound.q_nrm[q + r] : 0.f;
+      const float qer = bounded ? bound.q_err[q + r] + bound.acc : 0.f;
+      float best;
+      uint32_t bid;
+      float term;
+      switch (family_of(p)) {
+        case kFamNear:
+          rescore_relation<kFamNear>(arow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, x, y, z, hhi,
+                                     hlo, ids, red_v, red_id, surv, &surv_n, best, bid);
+          term = term_of<kFamNear>(best);
+          lsum += best;
+          break;
+        case kFamVert:
+          rescore_relation<kFamVert>(arow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, x, y, z, hhi,
+                                     hlo, ids, red_v, red_id, surv, &surv_n, best, bid);
+          term = term_of<kFamVert>(best);
+          lsum += logf(term);
+          break;
+        default:
+          rescore_relation<kFamLat>(arow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, x, y, z, hhi,
+                                    hlo, ids, red_v, red_id, surv, &surv_n, best, bid);
+          term = term_of<kFamLat>(best);
+          lsum += logf(term);
+          break;
+      }
+      if (tid == 0) {
+        rs_terms[slot * kMaxRel + e] = term;
+        rs_anchor[slot * kMaxRel + e] = bid;
+      }
+    }
+    if (tid == 0) {
+      const float g = R > 0 ? expf(lsum / (float)R) : 1.0f;
+      rs_score[slot] = sem * ((1.0f - kW) + kW * g);
+    }
+    if (tid >= R && tid < kMaxRel) {
       rs_terms[slot * kMaxRel + tid] = 0.f;
       rs_anchor[slot * kMaxRel + tid] = FARM_NO_ID;
     }
-    return;
-  }
-  // exact target similarity
-  const float* qt = qn + (int64_t)qq * ldk;
-  const float* dr = dn + o * ldk;
-  float part = 0.f;
-  for (int k = tid; k < ldk; k += kRsThreads) part = fmaf(qt[k], dr[k], part);
-  red_v[tid] = part;
-  __syncthreads();
-  for (int w = kRsThreads / 2; w > 0; w >>= 1) {
-    if (tid < w) red_v[tid] += red_v[tid + w];
     __syncthreads();
-  }
-  const float dot = red_v[0];
-  __syncthreads();
-  const int tc = meta.tcls[qq];
-  const float kappa = (tc >= 0 && cls && cls[o] >= 0 && cls[o] != tc) ? kClassFactor : 1.0f;
-  const float sem = kappa * fmaxf(0.f, dot);
-  const bool bounded = bound.q_nrm != nullptr;
-  float lsum = 0.f;
-  for (int e = 0; e < R; ++e) {
-    const int r = r0 + e;
-    const int p = meta.rel_pred[r];
-    const float c = sigmoid_scale(p);
-    const float* arow = sim + (int64_t)(q + r) * ld_s;
-    const float* qrow = qn + (int64_t)(q + r) * ldk;
-    const float qnr = bounded ? bound.q_nrm[q + r] : 0.f;
-    const float qer = bounded ? bound.q_err[q + r] + bound.acc : 0.f;
-    float best;
-    uint32_t bid;
-    float term;
-    switch (family_of(p)) {
-      case kFamNear:
-        rescore_relation<kFamNear>(arow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, x, y, z, hhi, hlo,
-                                   ids, red_v, red_id, surv, &surv_n, best, bid);
-        term = term_of<kFamNear>(best);
-        lsum += best;
-        break;
-      case kFamVert:
-        rescore_relation<kFamVert>(arow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, x, y, z, hhi, hlo,
-                                   ids, red_v, red_id, surv, &surv_n, best, bid);
-        term = term_of<kFamVert>(best);
-        lsum += logf(term);
-        break;
-      default:
-        rescore_relation<kFamLat>(arow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, x, y, z, hhi, hlo,
-                                  ids, red_v, red_id, surv, &surv_n, best, bid);
-        term = term_of<kFamLat>(best);
-        lsum += logf(term);
-        break;
-    }
-    if (tid == 0) {
-      rs_terms[slot * kMaxRel + e] = term;
-      rs_anchor[slot * kMaxRel + e] = bid;
-    }
-  }
-  if (tid == 0) {
-    const float g = R > 0 ? expf(lsum / (float)R) : 1.0f;
-    rs_score[slot] = sem * ((1.0f - kW) + kW * g);
-  }
-  if (tid >= R && tid < kMaxRel) {
-    rs_terms[slot * kMaxRel + tid] = 0.f;
-    rs_anchor[slot * kMaxRel + tid] = FARM_NO_ID;
   }
 }
 
@@ -287,10 +297,13 @@ __global__ __launch_bounds__(256) void k_max_reduce(const float* __restrict__ v,
 }  // namespace
 
 hipError_t launch_rescore(const farm_memory* mem, const farm_workspace* ws, const float* sim, int64_t ld_s, int32_t q,
-                          MetaView meta, const SimBound& bound, const int32_t* cand, int32_t c, hipStream_t s) {
+                          MetaView meta, const SimBound& bound, const int32_t* cand, const int32_t* cand_count,
+                          int32_t c, hipStream_t s) {
   if (q <= 0 || c <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rescore, dim3((unsigned)c, (unsigned)q), dim3(kRsThreads), 0, s, sim, ld_s, q, meta, bound,
-                     ws->qn, mem->dn, mem->ldk, cand, c, mem->x, mem->y, mem->z, mem->hr_hi, mem->hr_lo, mem->id,
+  // with a device-side count the candidate slots are swept by a fixed number of blocks per query
+  const unsigned gx = cand_count ? (unsigned)(c < 64 ? c : 64) : (unsigned)c;
+  hipLaunchKernelGGL(k_rescore, dim3(gx, (unsigned)q), dim3(kRsThreads), 0, s, sim, ld_s, q, meta, bound, ws->qn,
+                     mem->dn, mem->ldk, cand, cand_count, c, mem->x, mem->y, mem->z, mem->hr_hi, mem->hr_lo, mem->id,
                      mem->cls, mem->n, ws->rs_score, ws->rs_terms, ws->rs_anchor);
   return hipGetLastError();
 }
