@@ -69,7 +69,10 @@ def parse():
     p.add_argument("--workload", default="precision")
     p.add_argument("--form", default="f32", choices=["f32", "bf16", "fp8"])
     p.add_argument("--rescore-mult", type=int, default=4)
-    p.add_argument("--method", default="exhaustive", choices=["exhaustive", "bounded"])
+    p.add_argument("--method", default="exhaustive", choices=["exhaustive", "bounded", "proposal"])
+    p.add_argument("--train-scenes", type=int, default=8, help="training scenes of the proposal network")
+    p.add_argument("--train-steps", type=int, default=600)
+    p.add_argument("--list-m", type=int, default=256, help="anchors per (object, predicate) list")
     p.add_argument("--k", type=int, default=10)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=0, help="queries in the CPU-oracle sample (0 = auto)")
@@ -124,8 +127,11 @@ def main():
     ot = torch.empty((qb.q, k, 8), dtype=torch.float32, device=dev)
     ob = torch.empty((qb.q, k, 8), dtype=torch.int32, device=dev)
     dtype = {"f32": farm.F32, "bf16": farm.BF16, "fp8": farm.FP8_E4M3}[args.form]
-    method = {"exhaustive": farm.EXHAUSTIVE, "bounded": farm.BOUNDED}[args.method]
+    method = {"exhaustive": farm.EXHAUSTIVE, "bounded": farm.BOUNDED, "proposal": farm.PROPOSAL}[args.method]
     cert = torch.zeros((qb.q,), dtype=torch.int32, device=dev)
+    proposal_info = None
+    if method == farm.PROPOSAL:
+        proposal_info = prepare_proposals(farm, cfg, mem, args)
 
     def step():
         farm.query_topk(mem, ws, target, qb.target_cls, qb.rel_off, qb.rel_pred, anchors, k, oid, osc, ot, ob,
@@ -138,6 +144,7 @@ def main():
     ws.status()
     ws.set_timing(True)
     ws.timings(reset=True)
+    ws.proposal_stats(reset=True)
     torch.cuda.synchronize()
     times = []
     t_start = time.perf_counter()
@@ -152,6 +159,11 @@ def main():
     phases = ws.timings(reset=True)
     ws.set_timing(False)
     ws.status()
+    if proposal_info is not None:
+        checked, fell = ws.proposal_stats(reset=True)
+        proposal_info["terms_per_step"] = checked // max(args.steps, 1)
+        proposal_info["fallback_rate"] = round(fell / max(checked, 1), 5)
+        log(f"[bench] proposal terms {checked}, fell back {fell}")
 
     certified = int((cert.cpu().numpy() == 1).sum())
     recall_exact = None
@@ -167,29 +179,7 @@ def main():
 
     qps = qb.q * args.steps / elapsed
     ms_step = elapsed / args.steps * 1e3
-    # dominant kernel: the relational pass
-    pair_ms, pair_n = phases["pair"]
-    gemm_ms, gemm_n = phases["gemm"]
-    dominant = max(("pair", "gemm"), key=lambda p: phases[p][0])
-    n = scene.n
-    pairs_per_launch = float(qb.r_tot) * n * (n - 1)
-    flop_pair = sum(FLOP_PER_PAIR[int(p)] for p in qb.rel_pred) * float(n) * (n - 1)
-    if dominant == "pair":
-        avg_s = pair_ms / max(pair_n, 1) / 1e3
-        achieved = flop_pair / avg_s / 1e12
-        roofline = {"bound": "alu", "kernel": "k_pair_exhaustive", "achieved": round(achieved, 3),
-                    "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
-                    "traffic": recorded_traffic("k_pair_exhaustive", cfg.name), "pair_evals_per_launch": pairs_per_launch,
-                    "avg_launch_ms": round(avg_s * 1e3, 3)}
-    else:
-        avg_s = gemm_ms / max(gemm_n, 1) / 1e3
-        flop = 2.0 * (qb.q + qb.r_tot) * n * scene.d
-        achieved = flop / avg_s / 1e12
-        peak = PEAK_MFMA_TFLOPS[args.form]
-        roofline = {"bound": "mfma", "kernel": "k_sim_gemm<" + args.form + ">", "achieved": round(achieved, 2),
-                    "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                    "traffic": recorded_traffic("k_sim_gemm_" + args.form, cfg.name),
-                    "avg_launch_ms": round(avg_s * 1e3, 3)}
+    roofline = dominant_roofline(phases, scene, qb, args, cfg, proposal_info)
     phase_ms = {p: round(v[0] / max(v[1], 1), 3) for p, v in phases.items() if v[1]}
 
     cpu = None
@@ -224,8 +214,89 @@ def main():
         "recall_at_10_vs_exact_f32": recall_exact,
         "certified_queries": certified,
         "form": form_name(args),
+        "proposal": proposal_info,
     }
     print(json.dumps(out), flush=True)
+
+
+def prepare_proposals(farm, cfg, mem, args):
+    """Train the proposal network on exhaustive bindings of training scenes of
+    the same generator (seeds 1000, 1001, ...), then build the lists of the
+    benchmark scene.  Outside the timed region, like farm_build_memory."""
+    import torch
+    from paper_2606_15476_amd import proposal
+    from synth import make_queries, make_scene
+    t0 = time.time()
+    data, keep = [], []
+    for i in range(args.train_scenes):
+        seed = 1000 + i
+        sc = make_scene(cfg, seed=seed)
+        qt = make_queries(cfg, sc, seed=seed, q=256)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+        m = farm.Memory(t(sc.desc), t(sc.center), t(sc.extent), t(sc.ids.view(np.int32)), t(sc.cls), sc.view_right)
+        w = farm.Workspace(m, qt.q, qt.r_tot, 16)
+        bind = proposal.exhaustive_bindings(m, w, t(qt.target), qt.target_cls, qt.rel_off, qt.rel_pred,
+                                            t(qt.rel_anchor))
+        o, a, p, y = proposal.sample_pairs(bind, sc.ids, qt.rel_pred, np.random.default_rng(seed), per_relation=96)
+        data.append((m, o, a, p, y))
+        keep.append(w)
+        log(f"[bench] training scene {seed}: {o.size} examples")
+    t_data = time.time() - t0
+    net = farm.ProposalNet(mem.d, max_batch=4096, seed=7)
+    t1 = time.time()
+    hist = proposal.train(net, data, steps=args.train_steps, batch=4096, lr=2e-3, weight_decay=1e-4)
+    t_train = time.time() - t1
+    log(f"[bench] trained {args.train_steps} steps in {t_train:.1f}s: loss {hist[0][1]:.4f} -> {hist[-1][1]:.4f}")
+    del data, keep
+    t2 = time.time()
+    farm.build_proposals(mem, net, args.list_m)
+    torch.cuda.synchronize()
+    t_build = time.time() - t2
+    log(f"[bench] proposal lists (M={args.list_m}) built in {t_build:.2f}s")
+    return {"train_scenes": args.train_scenes, "train_steps": args.train_steps, "loss_first": round(hist[0][1], 5),
+            "loss_last": round(hist[-1][1], 5), "label_s": round(t_data, 2), "train_s": round(t_train, 2),
+            "table_build_s": round(t_build, 3), "list_m": args.list_m}
+
+
+def dominant_roofline(phases, scene, qb, args, cfg, proposal_info):
+    """Roofline of the kernel behind the phase with the largest time."""
+    n, q, R = scene.n, qb.q, qb.r_tot
+    timed = {p: v for p, v in phases.items() if v[1]}
+    dominant = max(timed, key=lambda p: timed[p][0])
+    ms, launches = timed[dominant]
+    avg_s = ms / launches / 1e3
+    if dominant == "pair":
+        flop = sum(FLOP_PER_PAIR[int(p)] for p in qb.rel_pred) * float(n) * (n - 1)
+        achieved = flop / avg_s / 1e12
+        return {"bound": "alu", "kernel": "k_pair_exhaustive", "achieved": round(achieved, 3),
+                "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
+                "traffic": recorded_traffic("k_pair_exhaustive", cfg.name),
+                "pair_evals_per_launch": float(R) * n * (n - 1), "avg_launch_ms": round(avg_s * 1e3, 3)}
+    if dominant == "gemm":
+        flop = 2.0 * (q + R) * n * scene.d
+        achieved = flop / avg_s / 1e12
+        peak = PEAK_MFMA_TFLOPS[args.form]
+        return {"bound": "mfma", "kernel": "k_sim_gemm<" + args.form + ">", "achieved": round(achieved, 2),
+                "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                "traffic": recorded_traffic("k_sim_gemm_" + args.form, cfg.name), "avg_launch_ms": round(avg_s * 1e3, 3)}
+    if dominant == "topk":
+        # the candidate scan reads each target similarity row once (4 B per object and query)
+        kernel = "k_bound_candidates" if args.method in ("bounded", "proposal") else "k_topk_rows"
+        nbytes = 4.0 * q * n
+        achieved = nbytes / avg_s / 1e9
+        return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": recorded_traffic(kernel, cfg.name), "avg_launch_ms": round(avg_s * 1e3, 3)}
+    # rescoring / proposal pass: list entries (4 B index + 4 B cached value) and
+    # the gathered 4 B similarity of each entry, per evaluated term
+    terms = (proposal_info or {}).get("terms_per_step", 0)
+    m = (proposal_info or {}).get("list_m", 0)
+    nbytes = float(terms) * (m + 64) * 12.0
+    achieved = nbytes / avg_s / 1e9
+    return {"bound": "hbm", "kernel": "k_rescore", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": recorded_traffic("k_rescore", cfg.name), "avg_launch_ms": round(avg_s * 1e3, 3),
+            "phase": dominant}
 
 
 def form_name(args):
@@ -233,6 +304,9 @@ def form_name(args):
     if args.method == "bounded":
         return (gemm + " + exact bound-pruned TopK (objects whose s_sem bound can reach the K-th lower bound "
                 "scored in FP32 over every anchor)")
+    if args.method == "proposal":
+        return (gemm + f" + exact bound-pruned TopK whose candidates are scored over learned anchor lists "
+                f"(M={args.list_m}) and semantic anchor sets, certified, with full-scan fallback")
     if args.form == "f32":
         return "exhaustive FP32 (plain method: every object over every anchor)"
     return gemm + f" + exhaustive estimate/upper-bound pass + FP32 rescoring of the top {args.rescore_mult}K"

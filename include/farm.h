@@ -168,7 +168,12 @@ typedef enum {
      [(1-w) s_sem, s_sem], so only objects whose s_sem upper bound reaches the
      K-th largest lower bound (1-w) s_sem can enter the TopK; those (at most
      2048 per query) are scored exactly in FP32 */
-  FARM_METHOD_BOUNDED = 1
+  FARM_METHOD_BOUNDED = 1,
+  /* BOUNDED, with each candidate's relation terms taken over its learned
+     anchor list and the relation's semantic anchor set, certified against a
+     bound on every other anchor, else over all anchors (needs
+     farm_build_proposals); the result equals BOUNDED's */
+  FARM_METHOD_PROPOSAL = 2
 } farm_method;
 
 /* Options of the fused path. */
@@ -216,7 +221,8 @@ typedef enum {
   FARM_PHASE_TOPK = 3,      /* TopK selection */
   FARM_PHASE_RESCORE = 4,   /* reduced-precision candidates rescored in FP32 */
   FARM_PHASE_EXPLAIN = 5,   /* ScoredCandidate breakdown of the winners */
-  FARM_PHASE_COUNT = 6
+  FARM_PHASE_PROPOSE = 6,   /* semantic anchor sets of the proposal method */
+  FARM_PHASE_COUNT = 7
 } farm_phase;
 
 /*
@@ -229,6 +235,94 @@ typedef enum {
  */
 FARM_API farm_status farm_workspace_set_timing(farm_workspace* ws, int32_t enable);
 FARM_API farm_status farm_workspace_timings(farm_workspace* ws, double* ms, int64_t* count, int32_t reset);
+
+/* ------------------------------------------------------------------------
+ * Learned anchor proposal network.
+ *
+ * The query-time complexity analysis of the paper (Appendix "Robust
+ * Relational Retrieval Formulation") bounds the binding cost by the anchor
+ * candidate-set size K_a.  This network proposes, per (target, predicate), the
+ * anchors worth evaluating; exhaustive scoring stays the fallback and the judge
+ * of exactness (see farm_build_proposals).
+ *
+ *   x  = [u_o (dp) | u_a (dp) | g(o,a) / 4 m (12) | 0]     dp = d rounded up to 64
+ *   h1 = GELU(W1 x + b1), h2 = GELU(W2 h1 + b2), y = W3 h2 + b3 (5 logits,
+ *   one per farm_pred), GELU(v) = v/2 (1 + erf(v / sqrt 2))
+ *   g  = [c_o - c_a (3), e_o (3), e_a (3), |c_o - c_a|, (c_o - c_a).r,
+ *         bottom_o - top_a]
+ * FP32 master weights and AdamW moments (beta 0.9 / 0.999, eps 1e-8); GEMMs on
+ * BF16 copies with FP32 accumulation.  Weights are row-major:
+ * W1 [256][in_dim], b1 [256], W2 [256][256], b2 [256], W3 [5][256], b3 [5];
+ * in_dim = 2 dp + 64 (unused input columns hold zero weights).
+ * ------------------------------------------------------------------------ */
+#define FARM_MLP_HIDDEN 256
+
+typedef struct farm_mlp farm_mlp;
+
+/* d: descriptor width of the memories it will serve; max_batch: pairs per
+   call (1..2^22); seed: deterministic initialisation. */
+FARM_API farm_status farm_mlp_create(int32_t d, int32_t max_batch, uint64_t seed, farm_mlp** out);
+FARM_API farm_status farm_mlp_free(farm_mlp* mlp);
+FARM_API farm_status farm_mlp_shape(const farm_mlp* mlp, int32_t* in_dim, int32_t* hidden);
+/* host FP32 copies of the master weights / of the last step's gradients
+   (synchronising); any pointer may be NULL */
+FARM_API farm_status farm_mlp_get_weights(const farm_mlp* mlp, float* W1, float* b1, float* W2, float* b2,
+                                          float* W3, float* b3);
+FARM_API farm_status farm_mlp_get_grads(const farm_mlp* mlp, float* W1, float* b1, float* W2, float* b2,
+                                        float* W3, float* b3);
+FARM_API farm_status farm_mlp_set_weights(farm_mlp* mlp, const float* W1, const float* b1, const float* W2,
+                                          const float* b2, const float* W3, const float* b3);
+/* Network inputs of nb pairs (device o_idx, a_idx: object indices into mem)
+   as BF16 rows x_out [nb][in_dim] (device). */
+FARM_API farm_status farm_mlp_inputs(farm_mlp* mlp, const farm_memory* mem, int32_t nb, const int32_t* o_idx,
+                                     const int32_t* a_idx, uint16_t* x_out, void* stream);
+/* Logits [nb][5] (device) of nb pairs. */
+FARM_API farm_status farm_mlp_logits(farm_mlp* mlp, const farm_memory* mem, int32_t nb, const int32_t* o_idx,
+                                     const int32_t* a_idx, float* logits, void* stream);
+/* One training step on nb labelled pairs (device pred [nb] farm_pred,
+   label [nb] in {0,1}): forward, mean BCE-with-logits on the labelled
+   predicate, backward; with update != 0 an AdamW step (lr, decoupled
+   weight_decay on every parameter).  loss_out: device scalar or NULL. */
+FARM_API farm_status farm_mlp_step(farm_mlp* mlp, const farm_memory* mem, int32_t nb, const int32_t* o_idx,
+                                   const int32_t* a_idx, const int32_t* pred, const float* label, float lr,
+                                   float weight_decay, int32_t update, float* loss_out, void* stream);
+
+/*
+ * Proposal tables of a memory (method FARM_METHOD_PROPOSAL).  For every
+ * object o and predicate p the M anchors a != o with the largest logit y_p of
+ * the network on (o, a), their predicate values P_p(o, a), and the largest
+ * P_p(o, a) over the anchors left out.  This is the anchor candidate set K_a
+ * of the query-time complexity analysis (Appendix "Robust Relational Retrieval
+ * Formulation"), learned and query-independent; the exact maximum over all
+ * anchors remains the fallback whenever the tables cannot certify a term.
+ *   mem     memory to extend (owned tables replace earlier ones; the memory
+ *           must not be in use by another stream during the call)
+ *   mlp     network with the memory's descriptor width, same device
+ *   M       list length, 1..FARM_MAX_K (clamped to n - 1)
+ * Memory: n * M * 5 * 8 bytes + 5 n * 4 bytes, plus transient chunk buffers
+ * (up to 4 GiB for very large n).  Synchronises `stream`.
+ * Errors: INVALID_ARG (null, width/device mismatch, M out of range),
+ * UNSUPPORTED (n > 2^19), OOM, HIP.
+ */
+FARM_API farm_status farm_build_proposals(farm_memory* mem, farm_mlp* mlp, int32_t M, void* stream);
+
+/*
+ * Copy of the proposal tables (stream-ordered device-to-device copies):
+ *   m_out  host out: list length M (0 = no tables; nothing else is written)
+ *   idx    device [5][n][M] int32 anchor indices, or NULL
+ *   val    device [5][n][M] FP32 predicate values (Near: log P), or NULL
+ *   out    device [5][n] FP32 largest value outside each list, or NULL
+ */
+FARM_API farm_status farm_get_proposals(const farm_memory* mem, int32_t* m_out, int32_t* idx, float* val, float* out,
+                                        void* stream);
+
+/*
+ * Proposal certificate counters of a workspace since the last reset:
+ * stats[0] = (candidate, relation) terms evaluated by FARM_METHOD_PROPOSAL,
+ * stats[1] = those that fell back to the scan over all anchors.
+ * Synchronises `stream`; reset != 0 clears the counters afterwards.
+ */
+FARM_API farm_status farm_workspace_proposal_stats(farm_workspace* ws, int64_t* stats, int32_t reset, void* stream);
 
 /*
  * Synchronise `stream` and report whether any scoring call since the last

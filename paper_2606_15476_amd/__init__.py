@@ -15,13 +15,13 @@ import numpy as np
 
 from . import _lib
 from ._lib import (FARM_BUILD_BF16, FARM_BUILD_FP8, FARM_MAX_K, FARM_MAX_REL, FARM_NO_ID, F32, BF16, FP8_E4M3,
-                   EXHAUSTIVE, BOUNDED,
+                   EXHAUSTIVE, BOUNDED, PROPOSAL,
                    NEAR, ABOVE, BELOW, LEFT_OF, RIGHT_OF, FarmError, lib_path)
 
 __all__ = [
-    "Memory", "Workspace", "score_query", "topk", "query_topk", "workspace_estimate", "FarmError",
+    "Memory", "Workspace", "ProposalNet", "build_proposals", "get_proposals", "score_query", "topk", "query_topk", "workspace_estimate", "FarmError",
     "FARM_BUILD_BF16", "FARM_BUILD_FP8", "FARM_MAX_K", "FARM_MAX_REL", "FARM_NO_ID", "F32", "BF16",
-    "FP8_E4M3", "EXHAUSTIVE", "BOUNDED", "NEAR", "ABOVE", "BELOW", "LEFT_OF", "RIGHT_OF", "lib_path",
+    "FP8_E4M3", "EXHAUSTIVE", "BOUNDED", "PROPOSAL", "NEAR", "ABOVE", "BELOW", "LEFT_OF", "RIGHT_OF", "lib_path",
 ]
 
 
@@ -71,6 +71,7 @@ class Memory:
                                             _stream(stream), ctypes.byref(h)))
         self._h = h
         self.n, self.d, self.flags = n, d, int(flags)
+        self.device = desc.device
 
     @property
     def handle(self):
@@ -132,6 +133,12 @@ class Workspace:
     def status(self, stream=None):
         _lib.check(_lib.L.farm_workspace_status(self.handle, _stream(stream)))
 
+    def proposal_stats(self, reset: bool = False, stream=None) -> tuple:
+        """(terms evaluated, terms that fell back to the full anchor scan) of method PROPOSAL."""
+        out = (ctypes.c_int64 * 2)()
+        _lib.check(_lib.L.farm_workspace_proposal_stats(self.handle, out, 1 if reset else 0, _stream(stream)))
+        return int(out[0]), int(out[1])
+
     def close(self):
         if getattr(self, "_h", None) is not None:
             _lib.L.farm_workspace_free(self._h)
@@ -185,3 +192,89 @@ def query_topk(mem: Memory, ws: Workspace, target, target_cls, rel_off, rel_pred
                                       ctypes.byref(opts), int(k), _ptr(out_id), _ptr(out_score), _ptr(out_terms),
                                       _ptr(out_anchor_id), _stream(stream)))
     del tc, ro, rp
+
+
+def build_proposals(mem: Memory, net: "ProposalNet", m: int = 256, stream=None):
+    """farm_build_proposals: per-(object, predicate) anchor lists of length m from the network."""
+    _lib.check(_lib.L.farm_build_proposals(mem.handle, net.handle, int(m), _stream(stream)))
+
+
+def get_proposals(mem: Memory, stream=None):
+    """(M, idx [5,n,M] int32, val [5,n,M] float32, out [5,n] float32) device tensors, or (0, None, None, None)."""
+    import torch
+    m = ctypes.c_int32()
+    _lib.check(_lib.L.farm_get_proposals(mem.handle, ctypes.byref(m), None, None, None, _stream(stream)))
+    if m.value == 0:
+        return 0, None, None, None
+    n = mem.n
+    idx = torch.empty((5, n, m.value), dtype=torch.int32, device=mem.device)
+    val = torch.empty((5, n, m.value), dtype=torch.float32, device=mem.device)
+    out = torch.empty((5, n), dtype=torch.float32, device=mem.device)
+    _lib.check(_lib.L.farm_get_proposals(mem.handle, ctypes.byref(m), _ptr(idx), _ptr(val), _ptr(out),
+                                         _stream(stream)))
+    return m.value, idx, val, out
+
+
+class ProposalNet:
+    """The anchor proposal network (farm_mlp_*): BF16 GEMMs, FP32 masters, AdamW."""
+
+    PARAMS = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+    def __init__(self, d: int, max_batch: int = 8192, seed: int = 0):
+        h = ctypes.c_void_p()
+        _lib.check(_lib.L.farm_mlp_create(int(d), int(max_batch), int(seed), ctypes.byref(h)))
+        self._h = h
+        self.d, self.max_batch = int(d), int(max_batch)
+        ind, hid = ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(_lib.L.farm_mlp_shape(h, ctypes.byref(ind), ctypes.byref(hid)))
+        self.in_dim, self.hidden = int(ind.value), int(hid.value)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("network was freed")
+        return self._h
+
+    def _shapes(self):
+        h, i = self.hidden, self.in_dim
+        return {"W1": (h, i), "b1": (h,), "W2": (h, h), "b2": (h,), "W3": (5, h), "b3": (5,)}
+
+    def _io(self, fn, arrays):
+        ptrs = [arrays[k].ctypes.data_as(ctypes.c_void_p) for k in self.PARAMS]
+        _lib.check(fn(self.handle, *ptrs))
+        return arrays
+
+    def weights(self) -> dict:
+        return self._io(_lib.L.farm_mlp_get_weights, {k: np.zeros(v, np.float32) for k, v in self._shapes().items()})
+
+    def grads(self) -> dict:
+        return self._io(_lib.L.farm_mlp_get_grads, {k: np.zeros(v, np.float32) for k, v in self._shapes().items()})
+
+    def set_weights(self, w: dict):
+        arrays = {k: np.ascontiguousarray(w[k], np.float32).reshape(v) for k, v in self._shapes().items()}
+        self._io(_lib.L.farm_mlp_set_weights, arrays)
+
+    def inputs(self, mem: "Memory", o_idx, a_idx, out, stream=None):
+        _lib.check(_lib.L.farm_mlp_inputs(self.handle, mem.handle, int(o_idx.shape[0]), _ptr(o_idx), _ptr(a_idx),
+                                          _ptr(out), _stream(stream)))
+
+    def logits(self, mem: "Memory", o_idx, a_idx, out, stream=None):
+        _lib.check(_lib.L.farm_mlp_logits(self.handle, mem.handle, int(o_idx.shape[0]), _ptr(o_idx), _ptr(a_idx),
+                                          _ptr(out), _stream(stream)))
+
+    def step(self, mem: "Memory", o_idx, a_idx, pred, label, lr: float = 1e-3, weight_decay: float = 0.0,
+             update: bool = True, loss_out=None, stream=None):
+        _lib.check(_lib.L.farm_mlp_step(self.handle, mem.handle, int(o_idx.shape[0]), _ptr(o_idx), _ptr(a_idx),
+                                        _ptr(pred), _ptr(label), float(lr), float(weight_decay), 1 if update else 0,
+                                        _ptr(loss_out), _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.L.farm_mlp_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

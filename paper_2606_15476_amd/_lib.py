@@ -10,7 +10,7 @@ _PATH = os.path.join(_HERE, "libfarm.so")
 
 FARM_OK, FARM_ERR_INVALID_ARG, FARM_ERR_OOM, FARM_ERR_HIP, FARM_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 F32, BF16, FP8_E4M3 = 0, 1, 2
-EXHAUSTIVE, BOUNDED = 0, 1
+EXHAUSTIVE, BOUNDED, PROPOSAL = 0, 1, 2
 NEAR, ABOVE, BELOW, LEFT_OF, RIGHT_OF = 0, 1, 2, 3, 4
 FARM_MAX_REL = 8
 FARM_MAX_K = 1024
@@ -21,9 +21,12 @@ EXPORTS = (
     "farm_build_memory", "farm_free_memory", "farm_memory_info", "farm_workspace_create", "farm_workspace_free",
     "farm_workspace_bytes", "farm_workspace_estimate", "farm_score_query", "farm_topk", "farm_query_topk",
     "farm_workspace_status", "farm_last_error", "farm_version", "farm_workspace_set_timing",
-    "farm_workspace_timings",
+    "farm_workspace_timings", "farm_mlp_create", "farm_mlp_free", "farm_mlp_shape", "farm_mlp_get_weights",
+    "farm_mlp_get_grads", "farm_mlp_set_weights", "farm_mlp_inputs", "farm_mlp_logits", "farm_mlp_step",
+    "farm_build_proposals", "farm_workspace_proposal_stats", "farm_get_proposals",
 )
-PHASES = ("normalize", "gemm", "pair", "topk", "rescore", "explain")
+MLP_HIDDEN = 256
+PHASES = ("normalize", "gemm", "pair", "topk", "rescore", "explain", "propose")
 
 _STATUS = {FARM_ERR_INVALID_ARG: "invalid argument", FARM_ERR_OOM: "out of memory", FARM_ERR_HIP: "HIP error",
            FARM_ERR_UNSUPPORTED: "unsupported"}
@@ -62,6 +65,18 @@ def _declare(lib):
         "farm_workspace_status": [P, P],
         "farm_workspace_set_timing": [P, i32],
         "farm_workspace_timings": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32],
+        "farm_mlp_create": [i32, i32, ctypes.c_uint64, pp],
+        "farm_mlp_free": [P],
+        "farm_mlp_shape": [P, ctypes.POINTER(i32), ctypes.POINTER(i32)],
+        "farm_mlp_get_weights": [P, P, P, P, P, P, P],
+        "farm_mlp_get_grads": [P, P, P, P, P, P, P],
+        "farm_mlp_set_weights": [P, P, P, P, P, P, P],
+        "farm_mlp_inputs": [P, P, i32, P, P, P, P],
+        "farm_mlp_logits": [P, P, i32, P, P, P, P],
+        "farm_mlp_step": [P, P, i32, P, P, P, P, ctypes.c_float, ctypes.c_float, i32, P, P],
+        "farm_build_proposals": [P, P, i32, P],
+        "farm_workspace_proposal_stats": [P, ctypes.POINTER(i64), i32, P],
+        "farm_get_proposals": [P, ctypes.POINTER(i32), P, P, P, P],
         "farm_last_error": [],
         "farm_version": [],
     }

@@ -40,19 +40,6 @@ farm_status hip_fail(hipError_t e, const char* what) {
 
 namespace {
 
-struct DeviceGuard {
-  int prev = -1;
-  bool ok = true;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
-    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
-  }
-  ~DeviceGuard() {
-    int cur;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
-
 template <class T>
 farm_status dalloc(std::vector<void*>& allocs, size_t& bytes, T** p, size_t count, const char* what) {
   *p = nullptr;
@@ -95,6 +82,7 @@ size_t workspace_bytes_for(const farm_memory* mem, int32_t max_q, int32_t max_re
   if (mem->dn_bf16) b += rows * mem->ldk * sizeof(uint16_t) + 2 * rows * sizeof(float);
   if (mem->dn_fp8) b += rows * mem->ldk + 3 * rows * sizeof(float);
   b += rows * ld_s * sizeof(float);                         // sim
+  b += (size_t)(max_rel > 0 ? max_rel : 1) * ld_s * sizeof(float);  // log similarities
   b += (size_t)max_q * ld_s * sizeof(float) * ((mem->dn_bf16 || mem->dn_fp8) ? 2 : 1);  // scores (+ bounds)
   b += (size_t)(2 * max_q + 1 + 2 * (size_t)max_rel) * sizeof(int32_t);
   b += sizeof(int);
@@ -103,6 +91,9 @@ size_t workspace_bytes_for(const farm_memory* mem, int32_t max_q, int32_t max_re
   const size_t cap = (size_t)(max_k > kBoundCap ? max_k : kBoundCap);
   b += (size_t)max_q * cap * (sizeof(int32_t) + sizeof(float) + kMaxRel * (sizeof(float) + sizeof(uint32_t)));
   b += (size_t)max_q * sizeof(int32_t);
+  const size_t rel1 = (size_t)(max_rel > 0 ? max_rel : 1);
+  b += rel1 * (kSemMax * sizeof(int32_t) + sizeof(int32_t) + 2 * sizeof(float));  // semantic sets
+  b += 2 * sizeof(unsigned long long);
   return b;
 }
 
@@ -240,6 +231,7 @@ farm_status similarities(const farm_memory* mem, farm_workspace* ws, int32_t q, 
              "FP8 similarity GEMM");
     *bound = SimBound{ws->qnrm_fp8, ws->qerr_fp8, mem->err_fp8, mem->err_max + 1, accumulation_bound(ldk)};
   }
+  FARM_HIP(launch_log_rows(ws->sim + (int64_t)q * ws->ld_s, ws->ld_s, R, mem->n, ws->lsim, s), "log similarities");
   return FARM_OK;
 }
 
@@ -372,6 +364,7 @@ farm_status farm_free_memory(farm_memory* mem) {
   DeviceGuard g(mem->device);
   (void)hipDeviceSynchronize();
   free_all(mem->allocs);
+  free_all(mem->prop_allocs);
   delete mem;
   return FARM_OK;
 }
@@ -433,6 +426,9 @@ farm_status farm_workspace_create(const farm_memory* mem, int32_t max_q, int32_t
       if ((st = dalloc(ws->allocs, ws->bytes, &ws->qnrm_fp8, rows, "FP8 query norms"))) return fail(st);
     }
     if ((st = dalloc(ws->allocs, ws->bytes, &ws->sim, rows * ws->ld_s, "similarity matrix"))) return fail(st);
+    if ((st = dalloc(ws->allocs, ws->bytes, &ws->lsim, (size_t)(max_rel > 0 ? max_rel : 1) * ws->ld_s,
+                     "log similarities")))
+      return fail(st);
     if ((st = dalloc(ws->allocs, ws->bytes, &ws->scores, (size_t)max_q * ws->ld_s, "scores"))) return fail(st);
     if ((mem->dn_bf16 || mem->dn_fp8) &&
         (st = dalloc(ws->allocs, ws->bytes, &ws->scores_hi, (size_t)max_q * ws->ld_s, "score bounds")))
@@ -453,12 +449,21 @@ farm_status farm_workspace_create(const farm_memory* mem, int32_t max_q, int32_t
     if ((st = dalloc(ws->allocs, ws->bytes, &ws->rs_score, nk, "rescored scores"))) return fail(st);
     if ((st = dalloc(ws->allocs, ws->bytes, &ws->rs_terms, nk * kMaxRel, "rescored terms"))) return fail(st);
     if ((st = dalloc(ws->allocs, ws->bytes, &ws->rs_anchor, nk * kMaxRel, "rescored anchors"))) return fail(st);
+    const size_t rel1 = (size_t)(max_rel > 0 ? max_rel : 1);
+    if ((st = dalloc(ws->allocs, ws->bytes, &ws->sem_idx, rel1 * kSemMax, "semantic sets")) ||
+        (st = dalloc(ws->allocs, ws->bytes, &ws->sem_cnt, rel1, "semantic set sizes")) ||
+        (st = dalloc(ws->allocs, ws->bytes, &ws->sem_tau, rel1, "semantic bounds")) ||
+        (st = dalloc(ws->allocs, ws->bytes, &ws->sem_ltau, rel1, "semantic log bounds")) ||
+        (st = dalloc(ws->allocs, ws->bytes, &ws->prop_stats, 2, "proposal counters")))
+      return fail(st);
     hipError_t e = hipHostMalloc((void**)&ws->h_meta, (size_t)ws->meta_len * sizeof(int32_t), hipHostMallocDefault);
     if (e != hipSuccess) { ws->h_meta = nullptr; return fail(hip_fail(e, "pinned metadata staging")); }
     e = hipEventCreateWithFlags(&ws->meta_done, hipEventDisableTiming);
     if (e != hipSuccess) { ws->meta_done = nullptr; return fail(hip_fail(e, "event")); }
     e = hipMemset(ws->status, 0, sizeof(int));
     if (e != hipSuccess) return fail(hip_fail(e, "status clear"));
+    e = hipMemset(ws->prop_stats, 0, 2 * sizeof(unsigned long long));
+    if (e != hipSuccess) return fail(hip_fail(e, "counter clear"));
     *out = ws;
     return FARM_OK;
   } catch (...) {
@@ -519,6 +524,22 @@ farm_status farm_workspace_bytes(const farm_workspace* ws, size_t* bytes) {
   return FARM_OK;
 }
 
+farm_status farm_workspace_proposal_stats(farm_workspace* ws, int64_t* stats, int32_t reset, void* stream) {
+  if (!ws || !stats) { set_error("null workspace or output"); return FARM_ERR_INVALID_ARG; }
+  DeviceGuard g(ws->device);
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long h[2] = {0, 0};
+  FARM_HIP(hipMemcpyAsync(h, ws->prop_stats, sizeof(h), hipMemcpyDeviceToHost, s), "read counters");
+  FARM_HIP(hipStreamSynchronize(s), "counter synchronize");
+  stats[0] = (int64_t)h[0];
+  stats[1] = (int64_t)h[1];
+  if (reset) {
+    FARM_HIP(hipMemsetAsync(ws->prop_stats, 0, sizeof(h), s), "counter clear");
+    FARM_HIP(hipStreamSynchronize(s), "counter synchronize");
+  }
+  return FARM_OK;
+}
+
 farm_status farm_workspace_status(farm_workspace* ws, void* stream) {
   if (!ws) { set_error("null workspace"); return FARM_ERR_INVALID_ARG; }
   DeviceGuard g(ws->device);
@@ -552,7 +573,7 @@ farm_status farm_score_query(const farm_memory* mem, farm_workspace* ws, int32_t
     SimBound none;
     FARM_TRY(similarities(mem, ws, q, R, target, rel_anchor, meta, FARM_F32, &none, s));
     PhaseTimer t(ws, s, FARM_PHASE_PAIR);
-    FARM_HIP(launch_pair_exhaustive(mem, ws->sim, ws->ld_s, q, meta, none, scores, mem->n, rel_terms, rel_anchor_id,
+    FARM_HIP(launch_pair_exhaustive(mem, ws->sim, ws->lsim, ws->ld_s, q, meta, none, scores, mem->n, rel_terms, rel_anchor_id,
                                     nullptr, s),
              "relational pass");
     return FARM_OK;
@@ -598,9 +619,13 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
     const int32_t dtype = opts ? opts->dtype : FARM_F32;
     const int32_t method = opts ? opts->method : FARM_METHOD_EXHAUSTIVE;
     int32_t* certified = opts ? opts->certified : nullptr;
-    if (method != FARM_METHOD_EXHAUSTIVE && method != FARM_METHOD_BOUNDED) {
+    if (method != FARM_METHOD_EXHAUSTIVE && method != FARM_METHOD_BOUNDED && method != FARM_METHOD_PROPOSAL) {
       set_error("unknown method %d", method);
       return FARM_ERR_INVALID_ARG;
+    }
+    if (method == FARM_METHOD_PROPOSAL && mem->prop_m == 0 && mem->n >= 2) {
+      set_error("method PROPOSAL needs farm_build_proposals on this memory");
+      return FARM_ERR_UNSUPPORTED;
     }
     if (opts && opts->reserved != 0) { set_error("reserved option field must be 0"); return FARM_ERR_INVALID_ARG; }
     if (dtype != FARM_F32 && dtype != FARM_BF16 && dtype != FARM_FP8_E4M3) {
@@ -628,15 +653,32 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
     FARM_TRY(stage_meta(ws, q, R, target_cls, rel_off, rel_pred, s, &meta));
     SimBound bound;
     FARM_TRY(similarities(mem, ws, q, R, target, rel_anchor, meta, dtype, &bound, s));
-    if (method == FARM_METHOD_BOUNDED) {
+    if (method == FARM_METHOD_BOUNDED || method == FARM_METHOD_PROPOSAL) {
       {
         PhaseTimer t(ws, s, FARM_PHASE_TOPK);
         FARM_HIP(launch_bound_candidates(mem, ws->sim, ws->ld_s, q, meta, bound, k, kBoundCap, ws->rs_idx,
                                          ws->cand_count, certified, s),
                  "bound candidates");
       }
+      PropView pv;
+      if (method == FARM_METHOD_PROPOSAL && mem->prop_m > 0) {
+        PhaseTimer t(ws, s, FARM_PHASE_PROPOSE);
+        FARM_HIP(launch_semantic_sets(ws->sim, ws->lsim, ws->ld_s, q, R, mem->n, ws->sem_idx, ws->sem_cnt, ws->sem_tau,
+                                      ws->sem_ltau, s),
+                 "semantic sets");
+        pv.m = mem->prop_m;
+        pv.idx = mem->prop_idx;
+        pv.val = mem->prop_val;
+        pv.out = mem->prop_out;
+        pv.sem_idx = ws->sem_idx;
+        pv.sem_cnt = ws->sem_cnt;
+        pv.sem_tau = ws->sem_tau;
+        pv.sem_ltau = ws->sem_ltau;
+        pv.stats = ws->prop_stats;
+      }
       PhaseTimer t(ws, s, FARM_PHASE_RESCORE);
-      FARM_HIP(launch_rescore(mem, ws, ws->sim, ws->ld_s, q, meta, bound, ws->rs_idx, ws->cand_count, kBoundCap, s),
+      FARM_HIP(launch_rescore(mem, ws, ws->sim, ws->lsim, ws->ld_s, q, meta, bound, ws->rs_idx, ws->cand_count,
+                              kBoundCap, pv, s),
                "candidate scoring");
       FARM_HIP(launch_rescore_select(ws, q, kBoundCap, k, nullptr, nullptr, mem->n, out_id, out_score, out_terms,
                                      out_anchor_id, nullptr, s),
@@ -645,7 +687,7 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
     }
     {
       PhaseTimer t(ws, s, FARM_PHASE_PAIR);
-      FARM_HIP(launch_pair_exhaustive(mem, ws->sim, ws->ld_s, q, meta, bound, ws->scores, ws->ld_s, nullptr, nullptr,
+      FARM_HIP(launch_pair_exhaustive(mem, ws->sim, ws->lsim, ws->ld_s, q, meta, bound, ws->scores, ws->ld_s, nullptr, nullptr,
                                       dtype == FARM_F32 ? nullptr : ws->scores_hi, s),
                "relational pass");
     }
@@ -672,7 +714,8 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
       FARM_HIP(launch_topk(mem, ws, ws->scores_hi, ws->ld_s, q, c + 1, &hi_key, &hi_idx, s), "bound topk");
     }
     PhaseTimer t(ws, s, FARM_PHASE_RESCORE);
-    FARM_HIP(launch_rescore(mem, ws, ws->sim, ws->ld_s, q, meta, bound, ws->rs_idx, nullptr, c, s), "rescore");
+    FARM_HIP(launch_rescore(mem, ws, ws->sim, ws->lsim, ws->ld_s, q, meta, bound, ws->rs_idx, nullptr, c, PropView{}, s),
+             "rescore");
     FARM_HIP(launch_rescore_select(ws, q, c, k, hi_key, hi_idx, mem->n, out_id, out_score, out_terms, out_anchor_id,
                                    certified, s),
              "rescore select");

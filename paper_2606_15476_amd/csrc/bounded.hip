@@ -10,8 +10,9 @@
 // s_sem_lo = s_sem_hi = s_sem; with BF16/FP8 similarities they are the
 // estimate minus/plus its proven error bound.
 //
-// One block per query: a 4-round radix select (8-bit digits, MSB first) finds
-// L on the IEEE bits of the non-negative lower bounds, then an ordered
+// One block per query: L is found from per-thread sorted top-16 lists in
+// registers and K rounds of a block arg-max (K <= 16), or by a 4-round radix
+// select on the IEEE bits of the non-negative lower bounds (larger K); an ordered
 // compaction (per-thread contiguous chunks + block prefix scan) lists the
 // candidates in index order.  If more than `cap` objects survive, the list
 // keeps the `cap` largest upper bounds (a second radix select) and the query
@@ -72,6 +73,50 @@ __device__ uint32_t radix_select_kth(int64_t n, int64_t k, KeyFn key, uint32_t* 
   return prefix;
 }
 
+// K-th largest of the values lo(i), K <= kSmallK: each thread keeps its own
+// sorted top-kSmallK in registers (which must contain its share of the global
+// top K), then K rounds of a block arg-max pop the heads.
+constexpr int kSmallK = 16;
+
+template <class LoFn>
+__device__ float kth_largest_small(int64_t n, int k, LoFn lo, float* red_v, int* red_t) {
+  float top[kSmallK];
+#pragma unroll
+  for (int e = 0; e < kSmallK; ++e) top[e] = -INFINITY;
+  for (int64_t i = threadIdx.x; i < n; i += kThreads) {
+    const float v = lo(i);
+    if (v > top[kSmallK - 1]) {
+#pragma unroll
+      for (int e = kSmallK - 1; e > 0; --e) top[e] = v > top[e - 1] ? top[e - 1] : fmaxf(v, top[e]);
+      top[0] = fmaxf(top[0], v);
+    }
+  }
+  float kth = -INFINITY;
+  for (int round = 0; round < k; ++round) {
+    red_v[threadIdx.x] = top[0];
+    red_t[threadIdx.x] = threadIdx.x;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) {
+        const float a = red_v[threadIdx.x], b = red_v[threadIdx.x + w];
+        if (b > a || (b == a && red_t[threadIdx.x + w] < red_t[threadIdx.x])) {
+          red_v[threadIdx.x] = b;
+          red_t[threadIdx.x] = red_t[threadIdx.x + w];
+        }
+      }
+      __syncthreads();
+    }
+    kth = red_v[0];
+    if ((int)threadIdx.x == red_t[0]) {
+#pragma unroll
+      for (int e = 0; e < kSmallK - 1; ++e) top[e] = top[e + 1];
+      top[kSmallK - 1] = -INFINITY;
+    }
+    __syncthreads();
+  }
+  return kth;
+}
+
 __global__ __launch_bounds__(kThreads) void k_bound_candidates(const float* __restrict__ sim, int64_t ld_s, int64_t n,
                                                                MetaView meta, SimBound bound,
                                                                const int32_t* __restrict__ cls, int32_t k,
@@ -81,16 +126,22 @@ __global__ __launch_bounds__(kThreads) void k_bound_candidates(const float* __re
   __shared__ uint32_t hist[256];
   __shared__ uint32_t word[2];
   __shared__ int32_t scan[kThreads];
+  __shared__ float red_v[kThreads];
   const int32_t qq = blockIdx.x;
   const float* srow = sim + (int64_t)qq * ld_s;
   const int tc = meta.tcls[qq];
   // L: K-th largest lower bound (1 - w) s_sem_lo
   float L = -INFINITY;
   if (n > k) {
-    auto lo_key = [&](int64_t i) {
-      return __float_as_uint((1.0f - kW) * sem_bounds(srow, i, tc, cls, bound, qq).lo);
-    };
-    L = __uint_as_float(radix_select_kth(n, k, lo_key, hist, word));
+    if (k <= kSmallK) {
+      auto lo_val = [&](int64_t i) { return (1.0f - kW) * sem_bounds(srow, i, tc, cls, bound, qq).lo; };
+      L = kth_largest_small(n, k, lo_val, red_v, scan);
+    } else {
+      auto lo_key = [&](int64_t i) {
+        return __float_as_uint((1.0f - kW) * sem_bounds(srow, i, tc, cls, bound, qq).lo);
+      };
+      L = __uint_as_float(radix_select_kth(n, k, lo_key, hist, word));
+    }
   }
   // candidates: s_sem_hi >= L
   const int64_t chunk = (n + kThreads - 1) / kThreads;

@@ -19,6 +19,7 @@ constexpr float kW = 0.5f;         // soft-blend weight of the relational factor
 constexpr float kClassFactor = 0.3f;
 constexpr float kFp8Max = 448.0f;  // largest finite OCP e4m3 value
 constexpr int32_t kBoundCap = 2048;  // candidates per query kept by the bound-pruned TopK
+constexpr int32_t kSemMax = 64;      // semantic anchor set per relation in the proposal pass
 
 // Validation flag bits raised by device-side checks.
 enum : int {
@@ -62,6 +63,13 @@ struct farm_memory {
   float* ext = nullptr;    // [3][n] extents
   uint32_t* id = nullptr;
   int32_t* cls = nullptr;
+  // learned anchor proposals (farm_build_proposals): per predicate p and
+  // target o a list of M anchors (target-major: one target's list is contiguous)
+  int32_t prop_m = 0;
+  int32_t* prop_idx = nullptr;  // [5][n][M] anchor indices
+  float* prop_val = nullptr;    // [5][n][M] predicate value (Near: log P, others: P)
+  float* prop_out = nullptr;    // [5][n] largest predicate value over anchors left out (same domain)
+  std::vector<void*> prop_allocs;
   size_t bytes = 0;
   std::vector<void*> allocs;
 };
@@ -80,6 +88,7 @@ struct farm_workspace {
   float* qerr_fp8 = nullptr;
   float* qnrm_fp8 = nullptr;
   float* sim = nullptr;       // [max_q + max_rel][ld_s] clamped similarities (target rows x kappa)
+  float* lsim = nullptr;      // [max_rel][ld_s] log of the relation rows' similarities
   float* scores = nullptr;    // [max_q][ld_s] composite scores (fused path)
   float* scores_hi = nullptr; // [max_q][ld_s] upper bounds of the scores (reduced-precision form)
   int32_t* d_meta = nullptr;  // device copy of the metadata block below
@@ -100,6 +109,12 @@ struct farm_workspace {
   float* rs_terms = nullptr;     // [max_q][rs_cap][FARM_MAX_REL]
   uint32_t* rs_anchor = nullptr; // [max_q][rs_cap][FARM_MAX_REL]
   int32_t* cand_count = nullptr; // [max_q]
+  // proposal pass: semantic anchor set per relation, certificate counters
+  int32_t* sem_idx = nullptr;    // [max_rel][kSemMax]
+  int32_t* sem_cnt = nullptr;    // [max_rel]
+  float* sem_tau = nullptr;      // [max_rel] largest similarity of an anchor outside the set
+  float* sem_ltau = nullptr;     // [max_rel] largest log similarity outside the set
+  unsigned long long* prop_stats = nullptr;  // [2] (candidate, relation) pairs checked, pairs that fell back
   // optional phase timer: pending (start, stop) event pairs per phase
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -109,6 +124,42 @@ struct farm_workspace {
   int64_t phase_count[FARM_PHASE_COUNT] = {0};
   size_t bytes = 0;
   std::vector<void*> allocs;
+};
+
+// The anchor proposal network (mlp.hip): FP32 masters, BF16 copies, batch buffers.
+struct farm_mlp {
+  int device = 0;
+  int32_t d = 0, dp = 0, ldx = 0, h = 0, bmax = 0, bpad = 0;
+  int64_t step = 0;
+  // FP32 master parameters, gradients, AdamW moments: one block of floats
+  float* par = nullptr;
+  float* grad = nullptr;
+  float* m1 = nullptr;
+  float* m2 = nullptr;
+  int64_t n_par = 0;
+  float *W1, *b1, *W2, *b2, *W3, *b3;      // views into par
+  float *gW1, *gb1, *gW2, *gb2, *gW3, *gb3;  // views into grad
+  // BF16 copies used by the GEMMs; W3 rounded to BF16 values kept as floats
+  uint16_t* W1b = nullptr;   // [h][ldx]
+  uint16_t* W2b = nullptr;   // [h][h]
+  uint16_t* W2bT = nullptr;  // [h][h] transpose
+  float* W3r = nullptr;      // [5][h]
+  // batch activations
+  uint16_t* X = nullptr;     // [bpad][ldx]
+  uint16_t* XT = nullptr;    // [ldx][bpad]
+  float* Z1 = nullptr;       // [bpad][h]
+  float* Z2 = nullptr;
+  uint16_t* A1 = nullptr;    // [bpad][h]
+  uint16_t* A1T = nullptr;   // [h][bpad]
+  uint16_t* A2 = nullptr;
+  float* Y = nullptr;        // [bpad][5]
+  float* dY = nullptr;       // [bpad][5]
+  float* dA = nullptr;       // [bpad][h]
+  uint16_t* dZ = nullptr;    // [bpad][h]
+  uint16_t* dZT = nullptr;   // [h][bpad]
+  float* loss_part = nullptr;
+  std::vector<void*> allocs;
+  size_t bytes = 0;
 };
 
 // Metadata block layout (int32), written by the host per call:
@@ -149,6 +200,33 @@ struct SimBound {
   float acc = 0.f;
 };
 
+// Anchor proposals seen by the rescoring kernel; m == 0 means full anchor scans.
+struct PropView {
+  int32_t m = 0;
+  const int32_t* idx = nullptr;      // [5][n][m]
+  const float* val = nullptr;        // [5][n][m]
+  const float* out = nullptr;        // [5][n]
+  const int32_t* sem_idx = nullptr;  // [R][kSemMax]
+  const int32_t* sem_cnt = nullptr;  // [R]
+  const float* sem_tau = nullptr;    // [R]
+  const float* sem_ltau = nullptr;   // [R]
+  unsigned long long* stats = nullptr;
+};
+
+// Makes `dev` current for the guard's lifetime.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+  }
+  ~DeviceGuard() {
+    int cur;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
 void set_error(const char* fmt, ...);
 farm_status hip_fail(hipError_t e, const char* what);
 
@@ -175,12 +253,21 @@ hipError_t launch_sim_gemm_fp8(const uint8_t* a, const float* a_scale, const uin
                                const int32_t* row_cls, int64_t n_cls_rows, const int32_t* col_cls,
                                hipStream_t s);
 
+// Plain BF16 "NT" GEMM for the proposal network: C[m][n] = A[m][k] . B[n][k]^T
+// (+ bias[n]) in FP32, or BF16 GELU(A . B^T + bias) when gelu_bf16_out; k a
+// multiple of 64, leading dimensions in elements (rows 16-byte aligned).
+hipError_t launch_gemm_nt_bf16(const uint16_t* a, int64_t lda, const uint16_t* b, int64_t ldb, int64_t m, int64_t n,
+                               int64_t k, void* c, int64_t ldc, const float* bias, bool gelu_bf16_out, hipStream_t s);
+
 // ---- pair.hip
 // With a SimBound (bound.q_nrm != null) the pass also writes scores_hi >= s:
 // the target similarity raised by its error bound and every relation term by
 // the largest similarity error bound of its row.
-hipError_t launch_pair_exhaustive(const farm_memory* mem, const float* sim, int64_t ld_s, int32_t q,
-                                  MetaView meta, const SimBound& bound, float* scores, int64_t ld_out,
+// lsim[r][j] = log(sim[q + r][j]) of the relation rows (large negative for 0),
+// shared by the Near family of every relational kernel.
+hipError_t launch_log_rows(const float* sim, int64_t ld_s, int64_t rows, int64_t n, float* lsim, hipStream_t s);
+hipError_t launch_pair_exhaustive(const farm_memory* mem, const float* sim, const float* lsim, int64_t ld_s,
+                                  int32_t q, MetaView meta, const SimBound& bound, float* scores, int64_t ld_out,
                                   float* rel_terms, uint32_t* rel_anchor_id, float* scores_hi, hipStream_t s);
 // ScoredCandidate breakdown for selected objects: t_r and b_r recomputed for
 // each (query, rank) entry of idx[q][k].
@@ -193,9 +280,12 @@ hipError_t launch_explain(const farm_memory* mem, const float* sim, int64_t ld_s
 // target similarity and, per relation, the exact maximum over anchors, where
 // only anchors whose bounded value can reach the best lower bound get an FP32
 // dot product.  Writes rs_score[q][c], rs_terms/rs_anchor[q][c][8].
-hipError_t launch_rescore(const farm_memory* mem, const farm_workspace* ws, const float* sim, int64_t ld_s,
-                          int32_t q, MetaView meta, const SimBound& bound, const int32_t* cand,
-                          const int32_t* cand_count, int32_t c, hipStream_t s);
+// With proposals (prop.m > 0) each term is first taken over the target's
+// anchor list and the relation's semantic set; it is kept when it exceeds the
+// bound on every anchor outside both, else the anchors are scanned in full.
+hipError_t launch_rescore(const farm_memory* mem, const farm_workspace* ws, const float* sim, const float* lsim,
+                          int64_t ld_s, int32_t q, MetaView meta, const SimBound& bound, const int32_t* cand,
+                          const int32_t* cand_count, int32_t c, const PropView& prop, hipStream_t s);
 
 // ---- bounded.hip
 // Candidates of the exact bound-pruned TopK: per query every object whose
@@ -215,6 +305,13 @@ hipError_t launch_rescore_select(const farm_workspace* ws, int32_t q, int32_t c,
                                  float* out_score, float* out_terms, uint32_t* out_anchor_id, int32_t* certified,
                                  hipStream_t s);
 hipError_t launch_max_reduce(const float* v, int64_t n, float* out, hipStream_t s);
+
+// ---- proposal.hip
+// Per relation row: a semantic anchor set (at most kSemMax anchors with the
+// largest similarities), and the largest similarity and log similarity of the
+// anchors outside it.
+hipError_t launch_semantic_sets(const float* sim, const float* lsim, int64_t ld_s, int32_t q, int32_t R, int64_t n,
+                                int32_t* sem_idx, int32_t* sem_cnt, float* sem_tau, float* sem_ltau, hipStream_t s);
 
 // ---- topk.hip
 // Select the top k of each score row.  Writes (key, index) of the winners in

@@ -83,10 +83,23 @@ __device__ inline void mfma_slice(floatx16& acc, const uint4& a, const uint4& b)
   }
 }
 
-template <int T>
+// Epilogues: the similarity matrix (scales, clamp, class factor) or a plain
+// layer output C = acc + bias[col] in FP32, or BF16 GELU(acc + bias[col]).
+enum { kEpiSim = 0, kEpiBias = 1, kEpiGeluBf16 = 2 };
+
+__device__ inline float gelu_erf(float v) { return 0.5f * v * (1.0f + erff(v * 0.70710678118654752f)); }
+
+__device__ inline uint16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+template <int T, int EPI = kEpiSim>
 __global__ __launch_bounds__(256) void k_sim_gemm(const uint8_t* __restrict__ A, const uint8_t* __restrict__ B,
-                                                  int64_t M, int64_t N, int64_t ld_bytes, float* __restrict__ C,
-                                                  int64_t ldc, const float* __restrict__ a_scale,
+                                                  int64_t M, int64_t N, int64_t K_bytes, int64_t lda_bytes,
+                                                  int64_t ldb_bytes, void* __restrict__ Cv, int64_t ldc,
+                                                  const float* __restrict__ a_scale,
                                                   const float* __restrict__ b_scale,
                                                   const int32_t* __restrict__ row_cls, int64_t n_cls_rows,
                                                   const int32_t* __restrict__ col_cls, int64_t tiles_m,
@@ -112,14 +125,14 @@ __global__ __launch_bounds__(256) void k_sim_gemm(const uint8_t* __restrict__ A,
   // unconditional so the next slab can be in flight under the MFMAs.
   const int lr = tid >> 3, lc = tid & 7;
   auto clamp_row = [](int64_t v, int64_t lim) { return v < lim ? v : lim - 1; };
-  const uint4* a0p = reinterpret_cast<const uint4*>(A + clamp_row(m0 + lr, M) * ld_bytes + lc * 16);
-  const uint4* a1p = reinterpret_cast<const uint4*>(A + clamp_row(m0 + lr + 32, M) * ld_bytes + lc * 16);
-  const uint4* a2p = reinterpret_cast<const uint4*>(A + clamp_row(m0 + lr + 64, M) * ld_bytes + lc * 16);
-  const uint4* a3p = reinterpret_cast<const uint4*>(A + clamp_row(m0 + lr + 96, M) * ld_bytes + lc * 16);
-  const uint4* b0p = reinterpret_cast<const uint4*>(B + clamp_row(n0 + lr, N) * ld_bytes + lc * 16);
-  const uint4* b1p = reinterpret_cast<const uint4*>(B + clamp_row(n0 + lr + 32, N) * ld_bytes + lc * 16);
-  const uint4* b2p = reinterpret_cast<const uint4*>(B + clamp_row(n0 + lr + 64, N) * ld_bytes + lc * 16);
-  const uint4* b3p = reinterpret_cast<const uint4*>(B + clamp_row(n0 + lr + 96, N) * ld_bytes + lc * 16);
+  const uint4* a0p = reinterpret_cast<const uint4*>(A + clamp_row(m0 + lr, M) * lda_bytes + lc * 16);
+  const uint4* a1p = reinterpret_cast<const uint4*>(A + clamp_row(m0 + lr + 32, M) * lda_bytes + lc * 16);
+  const uint4* a2p = reinterpret_cast<const uint4*>(A + clamp_row(m0 + lr + 64, M) * lda_bytes + lc * 16);
+  const uint4* a3p = reinterpret_cast<const uint4*>(A + clamp_row(m0 + lr + 96, M) * lda_bytes + lc * 16);
+  const uint4* b0p = reinterpret_cast<const uint4*>(B + clamp_row(n0 + lr, N) * ldb_bytes + lc * 16);
+  const uint4* b1p = reinterpret_cast<const uint4*>(B + clamp_row(n0 + lr + 32, N) * ldb_bytes + lc * 16);
+  const uint4* b2p = reinterpret_cast<const uint4*>(B + clamp_row(n0 + lr + 64, N) * ldb_bytes + lc * 16);
+  const uint4* b3p = reinterpret_cast<const uint4*>(B + clamp_row(n0 + lr + 96, N) * ldb_bytes + lc * 16);
   constexpr int kStepU4 = kSlab / 16;  // one slab in 16-byte units
   uint4 ra0 = a0p[0], ra1 = a1p[0], ra2 = a2p[0], ra3 = a3p[0];
   uint4 rb0 = b0p[0], rb1 = b1p[0], rb2 = b2p[0], rb3 = b3p[0];
@@ -129,7 +142,7 @@ __global__ __launch_bounds__(256) void k_sim_gemm(const uint8_t* __restrict__ A,
   bs[0] = rb0; bs[32 * kRowU4] = rb1; bs[64 * kRowU4] = rb2; bs[96 * kRowU4] = rb3;
   __syncthreads();
 
-  const int64_t nk = ld_bytes / kSlab;
+  const int64_t nk = K_bytes / kSlab;
   const int h = lane >> 5, r = lane & 31;
   for (int64_t kt = 0; kt < nk; ++kt) {
     const int64_t kn = (kt + 1 < nk ? kt + 1 : kt) * kStepU4;
@@ -163,15 +176,21 @@ __global__ __launch_bounds__(256) void k_sim_gemm(const uint8_t* __restrict__ A,
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int64_t col = n0 + wn * 64 + j * 32 + r;
-      const float sb = (T == kTFP8 && col < N) ? b_scale[col] : 1.0f;
+      const float sb = (EPI == kEpiSim && T == kTFP8 && col < N) ? b_scale[col] : 1.0f;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int64_t row = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
         if (row < M && col < N) {
           float val = acc[i][j][v];
-          if (T == kTFP8) val = val * (a_scale[row] * sb);
-          val = fmaxf(val, 0.f);
-          C[row * ldc + col] = val * class_factor(row, col, row_cls, n_cls_rows, col_cls);
+          if constexpr (EPI == kEpiSim) {
+            if (T == kTFP8) val = val * (a_scale[row] * sb);
+            val = fmaxf(val, 0.f);
+            static_cast<float*>(Cv)[row * ldc + col] = val * class_factor(row, col, row_cls, n_cls_rows, col_cls);
+          } else if constexpr (EPI == kEpiBias) {
+            static_cast<float*>(Cv)[row * ldc + col] = val + (b_scale ? b_scale[col] : 0.f);
+          } else {
+            static_cast<uint16_t*>(Cv)[row * ldc + col] = to_bf16(gelu_erf(val + (b_scale ? b_scale[col] : 0.f)));
+          }
         }
       }
     }
@@ -185,9 +204,10 @@ hipError_t launch_gemm(const void* a, const float* a_scale, const void* b, const
   const int64_t ld_bytes = (int64_t)ldk * elem_bytes;
   if (ld_bytes % kSlab) return hipErrorInvalidValue;
   int64_t tiles_m = (m + kBM - 1) / kBM, tiles_n = (n + kBN - 1) / kBN;
-  hipLaunchKernelGGL(k_sim_gemm<T>, dim3((unsigned)(tiles_m * tiles_n)), dim3(256), 0, s,
-                     static_cast<const uint8_t*>(a), static_cast<const uint8_t*>(b), m, n, ld_bytes, c, ldc, a_scale,
-                     b_scale, row_cls, n_cls_rows, col_cls, tiles_m, tiles_n);
+  hipLaunchKernelGGL((k_sim_gemm<T, kEpiSim>), dim3((unsigned)(tiles_m * tiles_n)), dim3(256), 0, s,
+                     static_cast<const uint8_t*>(a), static_cast<const uint8_t*>(b), m, n, ld_bytes, ld_bytes,
+                     ld_bytes, static_cast<void*>(c), ldc, a_scale, b_scale, row_cls, n_cls_rows, col_cls, tiles_m,
+                     tiles_n);
   return hipGetLastError();
 }
 
@@ -209,6 +229,22 @@ hipError_t launch_sim_gemm_fp8(const uint8_t* a, const float* a_scale, const uin
                                int64_t m, int64_t n, int32_t ldk, float* c, int64_t ldc, const int32_t* row_cls,
                                int64_t n_cls_rows, const int32_t* col_cls, hipStream_t s) {
   return launch_gemm<kTFP8>(a, a_scale, b, b_scale, m, n, ldk, 1, c, ldc, row_cls, n_cls_rows, col_cls, s);
+}
+
+hipError_t launch_gemm_nt_bf16(const uint16_t* a, int64_t lda, const uint16_t* b, int64_t ldb, int64_t m, int64_t n,
+                               int64_t k, void* c, int64_t ldc, const float* bias, bool gelu_bf16_out, hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  if ((k * 2) % kSlab || (lda * 2) % 16 || (ldb * 2) % 16) return hipErrorInvalidValue;
+  int64_t tiles_m = (m + kBM - 1) / kBM, tiles_n = (n + kBN - 1) / kBN;
+  if (gelu_bf16_out)
+    hipLaunchKernelGGL((k_sim_gemm<kTBF16, kEpiGeluBf16>), dim3((unsigned)(tiles_m * tiles_n)), dim3(256), 0, s,
+                       reinterpret_cast<const uint8_t*>(a), reinterpret_cast<const uint8_t*>(b), m, n, k * 2, lda * 2,
+                       ldb * 2, c, ldc, nullptr, bias, nullptr, 0, nullptr, tiles_m, tiles_n);
+  else
+    hipLaunchKernelGGL((k_sim_gemm<kTBF16, kEpiBias>), dim3((unsigned)(tiles_m * tiles_n)), dim3(256), 0, s,
+                       reinterpret_cast<const uint8_t*>(a), reinterpret_cast<const uint8_t*>(b), m, n, k * 2, lda * 2,
+                       ldb * 2, c, ldc, nullptr, bias, nullptr, 0, nullptr, tiles_m, tiles_n);
+  return hipGetLastError();
 }
 
 }  // namespace farm

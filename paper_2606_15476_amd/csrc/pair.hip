@@ -48,10 +48,13 @@ __device__ inline void scan_chunk(const float4* __restrict__ rec, const uint32_t
       float v = pair_value<FAM>(t[u], r, c);
       if (SELF && j0 + jj == ti[u]) v = -INFINITY;
       if (WITH_ARG) {
-        uint32_t idj = rid[jj];
-        bool take = v > best[u] || (v == best[u] && idj < bid[u] && v != -INFINITY);
-        best[u] = take ? v : best[u];
-        bid[u] = take ? idj : bid[u];
+        if (v >= best[u] && v != -INFINITY) {  // ties are rare: read the id only then
+          uint32_t idj = rid[jj];
+          if (v > best[u] || idj < bid[u]) {
+            best[u] = v;
+            bid[u] = idj;
+          }
+        }
       } else {
         best[u] = fmaxf(best[u], v);
       }
@@ -60,7 +63,8 @@ __device__ inline void scan_chunk(const float4* __restrict__ rec, const uint32_t
 }
 
 template <int FAM, bool WITH_ARG>
-__device__ void relation_pass(const float* __restrict__ arow, int64_t n, int64_t tile0, const int64_t* ti,
+__device__ void relation_pass(const float* __restrict__ arow, const float* __restrict__ lrow, int64_t n,
+                              int64_t tile0, const int64_t* ti,
                               const Tgt* t, float c, const float* x, const float* y, const float* z,
                               const float* hhi, const float* hlo, const uint32_t* ids, float4* rec,
                               uint32_t* rid, float* best, uint32_t* bid) {
@@ -75,7 +79,7 @@ __device__ void relation_pass(const float* __restrict__ arow, int64_t n, int64_t
     __syncthreads();
     for (int jj = threadIdx.x; jj < cnt; jj += kThreads) {
       int64_t j = c0 + jj;
-      rec[jj] = anchor_record(FAM, arow[j], j, x, y, z, hhi, hlo);
+      rec[jj] = anchor_record_pre(FAM, arow[j], FAM == kFamNear ? lrow[j] : 0.f, j, x, y, z, hhi, hlo);
       if (WITH_ARG) rid[jj] = ids[j];
     }
     __syncthreads();
@@ -89,8 +93,8 @@ __device__ void relation_pass(const float* __restrict__ arow, int64_t n, int64_t
 
 template <bool WITH_ARG>
 __global__ __launch_bounds__(kThreads) void k_pair_exhaustive(
-    const float* __restrict__ sim, int64_t ld_s, int32_t q, MetaView meta, SimBound bound,
-    const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
+    const float* __restrict__ sim, const float* __restrict__ lsim, int64_t ld_s, int32_t q, MetaView meta,
+    SimBound bound, const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
     const float* __restrict__ hhi, const float* __restrict__ hlo, const uint32_t* __restrict__ ids,
     const int32_t* __restrict__ cls, int64_t n, float* __restrict__ scores, int64_t ld_out,
     float* __restrict__ rel_terms, uint32_t* __restrict__ rel_anchor_id, float* __restrict__ scores_hi) {
@@ -116,6 +120,7 @@ __global__ __launch_bounds__(kThreads) void k_pair_exhaustive(
     const int fam = family_of(p);
     const float c = sigmoid_scale(p);
     const float* arow = sim + (int64_t)(q + r) * ld_s;
+    const float* lrow = lsim + (int64_t)r * ld_s;
     // largest similarity error of this relation row (upper-bound output only)
     const float dmax = bounded ? fmaf(bound.q_nrm[q + r], err_max, bound.q_err[q + r] + bound.acc) : 0.f;
     Tgt t[kTpt];
@@ -125,7 +130,7 @@ __global__ __launch_bounds__(kThreads) void k_pair_exhaustive(
     uint32_t bid[kTpt];
     float term[kTpt];
     if (fam == kFamNear) {
-      relation_pass<kFamNear, WITH_ARG>(arow, n, tile0, ti, t, c, x, y, z, hhi, hlo, ids, rec, rid, best, bid);
+      relation_pass<kFamNear, WITH_ARG>(arow, lrow, n, tile0, ti, t, c, x, y, z, hhi, hlo, ids, rec, rid, best, bid);
 #pragma unroll
       for (int u = 0; u < kTpt; ++u) {
         term[u] = term_of<kFamNear>(best[u]);
@@ -133,9 +138,9 @@ __global__ __launch_bounds__(kThreads) void k_pair_exhaustive(
       }
     } else {
       if (fam == kFamVert)
-        relation_pass<kFamVert, WITH_ARG>(arow, n, tile0, ti, t, c, x, y, z, hhi, hlo, ids, rec, rid, best, bid);
+        relation_pass<kFamVert, WITH_ARG>(arow, lrow, n, tile0, ti, t, c, x, y, z, hhi, hlo, ids, rec, rid, best, bid);
       else
-        relation_pass<kFamLat, WITH_ARG>(arow, n, tile0, ti, t, c, x, y, z, hhi, hlo, ids, rec, rid, best, bid);
+        relation_pass<kFamLat, WITH_ARG>(arow, lrow, n, tile0, ti, t, c, x, y, z, hhi, hlo, ids, rec, rid, best, bid);
 #pragma unroll
       for (int u = 0; u < kTpt; ++u) {
         term[u] = term_of<kFamVert>(best[u]);
@@ -191,10 +196,12 @@ __device__ void explain_relation(const float* __restrict__ arow, int64_t n, int6
     if (j == i) continue;
     float4 r = anchor_record(FAM, arow[j], j, x, y, z, hhi, hlo);
     float v = pair_value<FAM>(t, r, c);
-    uint32_t idj = ids[j];
-    if (v > best || (v == best && idj < bid && v != -INFINITY)) {
-      best = v;
-      bid = idj;
+    if (v >= best && v != -INFINITY) {
+      uint32_t idj = ids[j];
+      if (v > best || idj < bid) {
+        best = v;
+        bid = idj;
+      }
     }
   }
   red_v[threadIdx.x] = best;
@@ -252,20 +259,35 @@ __global__ __launch_bounds__(256) void k_explain(const float* __restrict__ sim, 
   }
 }
 
+__global__ void k_log_rows(const float* __restrict__ sim, int64_t ld_s, int64_t rows, int64_t n,
+                           float* __restrict__ lsim) {
+  const int64_t r = blockIdx.y;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+    lsim[r * ld_s + j] = near_log(sim[r * ld_s + j]);
+}
+
 }  // namespace
 
-hipError_t launch_pair_exhaustive(const farm_memory* mem, const float* sim, int64_t ld_s, int32_t q, MetaView meta,
-                                  const SimBound& bound, float* scores, int64_t ld_out, float* rel_terms,
+hipError_t launch_log_rows(const float* sim, int64_t ld_s, int64_t rows, int64_t n, float* lsim, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  const unsigned gx = (unsigned)((n + 255) / 256 < 64 ? (n + 255) / 256 : 64);
+  hipLaunchKernelGGL(k_log_rows, dim3(gx, (unsigned)rows), dim3(256), 0, s, sim, ld_s, rows, n, lsim);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_exhaustive(const farm_memory* mem, const float* sim, const float* lsim, int64_t ld_s, int32_t q,
+                                  MetaView meta, const SimBound& bound, float* scores, int64_t ld_out, float* rel_terms,
                                   uint32_t* rel_anchor_id, float* scores_hi, hipStream_t s) {
   if (q <= 0) return hipSuccess;
   int64_t n = mem->n;
   dim3 grid((unsigned)((n + kTile - 1) / kTile), (unsigned)q);
   if (rel_anchor_id)
-    hipLaunchKernelGGL(k_pair_exhaustive<true>, grid, dim3(kThreads), 0, s, sim, ld_s, q, meta, bound, mem->x, mem->y,
+    hipLaunchKernelGGL(k_pair_exhaustive<true>, grid, dim3(kThreads), 0, s, sim, lsim, ld_s, q, meta, bound, mem->x,
+                       mem->y,
                        mem->z, mem->hr_hi, mem->hr_lo, mem->id, mem->cls, n, scores, ld_out, rel_terms,
                        rel_anchor_id, scores_hi);
   else
-    hipLaunchKernelGGL(k_pair_exhaustive<false>, grid, dim3(kThreads), 0, s, sim, ld_s, q, meta, bound, mem->x,
+    hipLaunchKernelGGL(k_pair_exhaustive<false>, grid, dim3(kThreads), 0, s, sim, lsim, ld_s, q, meta, bound, mem->x,
                        mem->y, mem->z, mem->hr_hi, mem->hr_lo, mem->id, mem->cls, n, scores, ld_out, rel_terms,
                        rel_anchor_id, scores_hi);
   return hipGetLastError();

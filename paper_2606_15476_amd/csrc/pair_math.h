@@ -53,12 +53,24 @@ __device__ inline Tgt load_target(int fam, int64_t i, const float* x, const floa
   return t;
 }
 
+// Log of a similarity as the Near family stores it (a = 0 maps to a large
+// finite negative number so such anchors still order by distance).
+__device__ inline float near_log(float a) { return a > 0.f ? logf(a) : -1.0e30f; }
+
 // Anchor record: (value, coordinates).  Near stores log(a_j).
 __device__ inline float4 anchor_record(int fam, float a, int64_t j, const float* x, const float* y, const float* z,
                                        const float* hhi, const float* hlo) {
   // a = 0 maps to a large finite negative log so that such anchors still order by
   // distance (any of them is a valid binding of a zero term).
-  if (fam == kFamNear) return make_float4(a > 0.f ? logf(a) : -1.0e30f, x[j], y[j], z[j]);
+  if (fam == kFamNear) return make_float4(near_log(a), x[j], y[j], z[j]);
+  if (fam == kFamVert) return make_float4(a, z[j], 0.f, 0.f);
+  return make_float4(a, hhi[j], hlo[j], 0.f);
+}
+
+// Anchor record from a precomputed log similarity (Near) or similarity.
+__device__ inline float4 anchor_record_pre(int fam, float a, float la, int64_t j, const float* x, const float* y,
+                                           const float* z, const float* hhi, const float* hlo) {
+  if (fam == kFamNear) return make_float4(la, x[j], y[j], z[j]);
   if (fam == kFamVert) return make_float4(a, z[j], 0.f, 0.f);
   return make_float4(a, hhi[j], hlo[j], 0.f);
 }

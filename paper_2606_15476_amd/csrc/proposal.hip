@@ -1,0 +1,383 @@
+// proposal.hip -- learned anchor proposals: table build and semantic sets.
+//
+// The star decomposition costs O(|Phi| K_t K_a) with K_a the anchor candidates
+// per relation (Appendix "Robust Relational Retrieval Formulation", query-time
+// complexity).  Here the exact pass over all anchors is replaced, for each
+// candidate target o and relation r, by the union of
+//   * a learned list L(o, p) of M anchors per (target, predicate), ranked by
+//     the proposal network's logit for p (query-independent, built once per
+//     scene, with the predicate value P(o, a) cached), and
+//   * the relation's semantic set S_r: the (at most 64) anchors with the
+//     largest similarity to the relation's anchor description, found per query.
+// Every anchor outside both has sim <= tau_r (the largest similarity outside
+// S_r) and P <= Pout(o, p) (the largest predicate value outside L(o, p),
+// computed exactly at build time), so its value is at most tau_r * Pout(o, p);
+// the rescoring kernel keeps the subset maximum when it is strictly larger and
+// scans all anchors otherwise.
+//
+// Table build (per chunk of targets, all anchors): the first layer is
+// factorised, W1 x = W1o u_o + W1a u_a + W1g g, with U = D W1o^T and V = D W1a^T
+// computed once per scene by MFMA GEMMs; per pair h1 = GELU(U_o + V_a + b1 +
+// W1g g(o, a)), h2 = GELU(W2 h1 + b2) (MFMA GEMM with the GELU epilogue),
+// logits from h2; a TopK per (predicate, target) row keeps the M largest.
+#include <math.h>
+
+#include <new>
+#include <vector>
+
+#include "farm_internal.h"
+#include "pair_math.h"
+#include "sort_util.h"
+
+namespace farm {
+namespace {
+
+constexpr int kNPred = 5;
+constexpr float kGeoScale = 0.25f;
+
+__device__ inline uint16_t bf16r(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ inline float from_bf16r(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ inline float gelu_f(float v) { return 0.5f * v * (1.0f + erff(v * 0.70710678118654752f)); }
+
+__device__ inline float geo_f(int f, int64_t o, int64_t a, const float* x, const float* y, const float* z,
+                              const float* ext, int64_t n, float rx, float ry) {
+  const float dx = x[o] - x[a], dy = y[o] - y[a], dz = z[o] - z[a];
+  float v;
+  switch (f) {
+    case 0: v = dx; break;
+    case 1: v = dy; break;
+    case 2: v = dz; break;
+    case 3: case 4: case 5: v = ext[(f - 3) * n + o]; break;
+    case 6: case 7: case 8: v = ext[(f - 6) * n + a]; break;
+    case 9: v = sqrtf(dx * dx + dy * dy + dz * dz); break;
+    case 10: v = dx * rx + dy * ry; break;
+    default: v = (z[o] - 0.5f * ext[2 * n + o]) - (z[a] + 0.5f * ext[2 * n + a]); break;
+  }
+  return v * kGeoScale;
+}
+
+__global__ void k_rows_to_bf16(const float* __restrict__ src, int64_t count, uint16_t* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = bf16r(src[i]);
+}
+
+// h1 of pair (t, a) for targets o_t = t0 + t: one block per pair, one thread per hidden unit
+__global__ void k_hidden1(const float* __restrict__ U, const float* __restrict__ V, const float* __restrict__ b1,
+                          const uint16_t* __restrict__ W1b, int32_t ldx, int32_t geo0, int64_t t0, int64_t n,
+                          const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
+                          const float* __restrict__ ext, float rx, float ry, uint16_t* __restrict__ A1) {
+  __shared__ float g[12];
+  const int64_t p = blockIdx.x;  // pair row = t * n + a
+  const int64_t t = p / n, a = p % n, o = t0 + t;
+  if (threadIdx.x < 12) g[threadIdx.x] = from_bf16r(bf16r(geo_f(threadIdx.x, o, a, x, y, z, ext, n, rx, ry)));
+  __syncthreads();
+  const int k = threadIdx.x;
+  float acc = U[o * FARM_MLP_HIDDEN + k] + V[a * FARM_MLP_HIDDEN + k] + b1[k];
+  const uint16_t* w = W1b + (int64_t)k * ldx + geo0;
+#pragma unroll
+  for (int f = 0; f < 12; ++f) acc = fmaf(from_bf16r(w[f]), g[f], acc);
+  A1[p * FARM_MLP_HIDDEN + k] = bf16r(gelu_f(acc));
+}
+
+// logits in predicate-major rows: L[p][t][a] (self pairs excluded with -inf)
+__global__ void k_head_rows(const uint16_t* __restrict__ A2, const float* __restrict__ W3r, const float* __restrict__ b3,
+                            int64_t t0, int64_t tc, int64_t n, float* __restrict__ L) {
+  const int64_t pr = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pr >= tc * n) return;
+  const int64_t t = pr / n, a = pr % n;
+  float acc[kNPred];
+#pragma unroll
+  for (int c = 0; c < kNPred; ++c) acc[c] = b3[c];
+  const uint16_t* row = A2 + pr * FARM_MLP_HIDDEN;
+  for (int k = 0; k < FARM_MLP_HIDDEN; ++k) {
+    const float v = from_bf16r(row[k]);
+#pragma unroll
+    for (int c = 0; c < kNPred; ++c) acc[c] = fmaf(v, W3r[c * FARM_MLP_HIDDEN + k], acc[c]);
+  }
+  const bool self = (t0 + t) == a;
+#pragma unroll
+  for (int c = 0; c < kNPred; ++c) L[((int64_t)c * tc + t) * n + a] = self ? -INFINITY : acc[c];
+}
+
+// Predicate value of (o, a) for predicate p in the family's comparison domain
+// (Near: log P; others: P), computed with the shared per-pair arithmetic.
+__device__ inline float pred_value(int p, int64_t o, int64_t a, const float* x, const float* y, const float* z,
+                                   const float* hhi, const float* hlo) {
+  const int fam = family_of(p);
+  const float c = sigmoid_scale(p);
+  const Tgt t = load_target(fam, o, x, y, z, hhi, hlo);
+  const float4 r = anchor_record_pre(fam, 1.0f, 0.0f, a, x, y, z, hhi, hlo);
+  if (fam == kFamNear) return pair_value<kFamNear>(t, r, c);
+  if (fam == kFamVert) return pair_value<kFamVert>(t, r, c);
+  return pair_value<kFamLat>(t, r, c);
+}
+
+// One block per (target t of the chunk, predicate): write the list (entries
+// that selection could not fill repeat a real anchor) and Pout.
+__global__ __launch_bounds__(256) void k_prop_finalize(const int32_t* __restrict__ top_idx, int32_t M, int64_t t0,
+                                                       int64_t tc, int64_t n, const float* __restrict__ x,
+                                                       const float* __restrict__ y, const float* __restrict__ z,
+                                                       const float* __restrict__ hhi, const float* __restrict__ hlo,
+                                                       int32_t* __restrict__ prop_idx, float* __restrict__ prop_val,
+                                                       float* __restrict__ prop_out) {
+  extern __shared__ uint32_t bits[];  // n bits: anchors on the list
+  __shared__ float red[256];
+  const int p = blockIdx.y;
+  const int64_t t = blockIdx.x, o = t0 + t;
+  const int64_t words = (n + 31) / 32;
+  for (int64_t w = threadIdx.x; w < words; w += blockDim.x) bits[w] = 0;
+  __syncthreads();
+  const int32_t* row = top_idx + ((int64_t)p * tc + t) * M;
+  const int64_t base = ((int64_t)p * n + o) * M;
+  for (int m = threadIdx.x; m < M; m += blockDim.x) {
+    int32_t a = row[m];
+    if (a < 0 || a >= n || a == o) a = o == 0 ? 1 : 0;
+    atomicOr(&bits[a >> 5], 1u << (a & 31));
+    prop_idx[base + m] = a;
+    prop_val[base + m] = pred_value(p, o, a, x, y, z, hhi, hlo);
+  }
+  __syncthreads();
+  float best = -INFINITY;
+  for (int64_t a = threadIdx.x; a < n; a += blockDim.x) {
+    if (a == o || (bits[a >> 5] >> (a & 31)) & 1u) continue;
+    best = fmaxf(best, pred_value(p, o, a, x, y, z, hhi, hlo));
+  }
+  red[threadIdx.x] = best;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) prop_out[(int64_t)p * n + o] = red[0];
+}
+
+// ---------------------------------------------------------------- query time
+// Semantic set of one relation row: tau = gamma * max_a sim with gamma in
+// 1/2, 3/4, 7/8, ... until at most kSemMax anchors exceed tau; the set is
+// their ordered compaction (truncated to kSemMax if ties at the maximum leave
+// more).  Then the largest similarity and log similarity of the anchors
+// outside the set, which bound every anchor the set leaves out.
+__global__ __launch_bounds__(256) void k_semantic_sets(const float* __restrict__ sim, const float* __restrict__ lsim,
+                                                       int64_t ld_s, int32_t q, int64_t n, int32_t* __restrict__ sem_idx,
+                                                       int32_t* __restrict__ sem_cnt, float* __restrict__ sem_tau,
+                                                       float* __restrict__ sem_ltau) {
+  __shared__ float red[256];
+  __shared__ float lred[256];
+  __shared__ int32_t scan[256];
+  const int32_t r = blockIdx.x;
+  const float* row = sim + (int64_t)(q + r) * ld_s;
+  const float* lrow = lsim + (int64_t)r * ld_s;
+  float mx = 0.f;
+  for (int64_t j = threadIdx.x; j < n; j += 256) mx = fmaxf(mx, row[j]);
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  const float amax = red[0];
+  __syncthreads();
+  const int64_t chunk = (n + 255) / 256;
+  const int64_t i0 = threadIdx.x * chunk < n ? threadIdx.x * chunk : n;
+  const int64_t i1 = i0 + chunk < n ? i0 + chunk : n;
+  auto count_above = [&](float tau) {
+    int32_t c = 0;
+    for (int64_t j = i0; j < i1; ++j) c += row[j] > tau;
+    scan[threadIdx.x] = c;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {  // inclusive scan
+      const int32_t v = (int)threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
+      __syncthreads();
+      scan[threadIdx.x] += v;
+      __syncthreads();
+    }
+    const int32_t total = scan[255];
+    return total;
+  };
+  float tau = 0.5f * amax, gap = 0.5f * amax;
+  int32_t total = count_above(tau);
+  for (int it = 0; it < 30 && total > kSemMax; ++it) {
+    __syncthreads();
+    gap *= 0.5f;
+    tau = amax - gap;
+    total = count_above(tau);
+  }
+  // scan[] holds the inclusive prefix counts for the settled tau
+  int32_t pos = threadIdx.x ? scan[threadIdx.x - 1] : 0;
+  float out = 0.f, lout = -INFINITY;
+  for (int64_t j = i0; j < i1; ++j) {
+    if (row[j] > tau && pos < kSemMax) {
+      sem_idx[(int64_t)r * kSemMax + pos++] = (int32_t)j;
+    } else {
+      out = fmaxf(out, row[j]);
+      lout = fmaxf(lout, lrow[j]);
+    }
+  }
+  __syncthreads();
+  red[threadIdx.x] = out;
+  lred[threadIdx.x] = lout;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+      lred[threadIdx.x] = fmaxf(lred[threadIdx.x], lred[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    sem_cnt[r] = total < kSemMax ? total : kSemMax;
+    sem_tau[r] = red[0];
+    sem_ltau[r] = lred[0];
+  }
+}
+
+inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t launch_semantic_sets(const float* sim, const float* lsim, int64_t ld_s, int32_t q, int32_t R, int64_t n,
+                                int32_t* sem_idx, int32_t* sem_cnt, float* sem_tau, float* sem_ltau, hipStream_t s) {
+  if (R <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_semantic_sets, dim3((unsigned)R), dim3(256), 0, s, sim, lsim, ld_s, q, n, sem_idx, sem_cnt,
+                     sem_tau, sem_ltau);
+  return hipGetLastError();
+}
+
+}  // namespace farm
+
+using namespace farm;
+
+extern "C" farm_status farm_build_proposals(farm_memory* mem, farm_mlp* mlp, int32_t M, void* stream) {
+  try {
+    if (!mem || !mlp) { set_error("null memory or network"); return FARM_ERR_INVALID_ARG; }
+    if (mlp->device != mem->device) { set_error("network and memory live on different devices"); return FARM_ERR_INVALID_ARG; }
+    if (mlp->d != mem->d) { set_error("network width %d != memory width %d", mlp->d, mem->d); return FARM_ERR_INVALID_ARG; }
+    if (M < 1 || M > FARM_MAX_K) { set_error("M = %d outside [1, %d]", M, FARM_MAX_K); return FARM_ERR_INVALID_ARG; }
+    const int64_t n = mem->n;
+    if (n > ((int64_t)1 << 19)) { set_error("proposal tables need n <= 2^19"); return FARM_ERR_UNSUPPORTED; }
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t H = FARM_MLP_HIDDEN;
+    DeviceGuard guard(mem->device);
+    // release an earlier table
+    if (hipStreamSynchronize(s) != hipSuccess) { set_error("synchronize failed"); return FARM_ERR_HIP; }
+    for (void* p : mem->prop_allocs) (void)hipFree(p);
+    mem->prop_allocs.clear();
+    mem->prop_m = 0;
+    mem->prop_idx = nullptr;
+    mem->prop_val = nullptr;
+    mem->prop_out = nullptr;
+    if (n < 2) return FARM_OK;  // no anchors: terms are zero without any table
+    if (M > n - 1) M = (int32_t)(n - 1);
+    std::vector<void*> tmp;
+    auto alloc = [&](std::vector<void*>& list, size_t bytes, void** p) -> bool {
+      if (hipMalloc(p, bytes ? bytes : 1) != hipSuccess) { (void)hipGetLastError(); return false; }
+      list.push_back(*p);
+      return true;
+    };
+    auto fail = [&](farm_status st, const char* what) {
+      (void)hipStreamSynchronize(s);
+      for (void* p : tmp) (void)hipFree(p);
+      for (void* p : mem->prop_allocs) (void)hipFree(p);
+      mem->prop_allocs.clear();
+      set_error("building proposals: %s", what);
+      return st;
+    };
+    int32_t* pidx;
+    float *pval, *pout;
+    if (!alloc(mem->prop_allocs, sizeof(int32_t) * kNPred * M * n, (void**)&pidx) ||
+        !alloc(mem->prop_allocs, sizeof(float) * kNPred * M * n, (void**)&pval) ||
+        !alloc(mem->prop_allocs, sizeof(float) * kNPred * n, (void**)&pout))
+      return fail(FARM_ERR_OOM, "table allocation");
+    // BF16 descriptors, U = D W1o^T, V = D W1a^T
+    const int64_t ldk = mem->ldk;
+    uint16_t* dnb = mem->dn_bf16;
+    float *U, *V;
+    if (!dnb && !alloc(tmp, sizeof(uint16_t) * n * ldk, (void**)&dnb)) return fail(FARM_ERR_OOM, "descriptor copy");
+    if (!alloc(tmp, sizeof(float) * n * H, (void**)&U) || !alloc(tmp, sizeof(float) * n * H, (void**)&V))
+      return fail(FARM_ERR_OOM, "first-layer factors");
+    hipError_t e;
+    if (!mem->dn_bf16) {
+      hipLaunchKernelGGL(k_rows_to_bf16, dim3(nblk(n * ldk)), dim3(256), 0, s, mem->dn, n * ldk, dnb);
+      if ((e = hipGetLastError()) != hipSuccess) return fail(FARM_ERR_HIP, "descriptor copy");
+    }
+    if ((e = launch_gemm_nt_bf16(dnb, ldk, mlp->W1b, mlp->ldx, n, H, mlp->dp, U, H, nullptr, false, s)) ||
+        (e = launch_gemm_nt_bf16(dnb, ldk, mlp->W1b + mlp->dp, mlp->ldx, n, H, mlp->dp, V, H, nullptr, false, s)))
+      return fail(FARM_ERR_HIP, "first-layer GEMMs");
+    // chunks of targets
+    // chunk of targets: at most 16, and at most 2^22 pairs (2 GiB of BF16 activations per buffer)
+    int64_t tc_max = ((int64_t)1 << 22) / n;
+    tc_max = tc_max < 1 ? 1 : tc_max > 16 ? 16 : tc_max;
+    if (tc_max > n) tc_max = n;
+    uint16_t *A1, *A2;
+    float* L;
+    if (!alloc(tmp, sizeof(uint16_t) * tc_max * n * H, (void**)&A1) ||
+        !alloc(tmp, sizeof(uint16_t) * tc_max * n * H, (void**)&A2) ||
+        !alloc(tmp, sizeof(float) * kNPred * tc_max * n, (void**)&L))
+      return fail(FARM_ERR_OOM, "chunk buffers");
+    // TopK candidate buffers in a scratch workspace
+    farm_workspace tw;
+    tw.mem = mem;
+    tw.cand_cap = topk_candidate_capacity(n, (int32_t)(kNPred * tc_max), M);
+    for (int b = 0; b < 2; ++b)
+      if (!alloc(tmp, sizeof(uint64_t) * tw.cand_cap, (void**)&tw.cand_key[b]) ||
+          !alloc(tmp, sizeof(int32_t) * tw.cand_cap, (void**)&tw.cand_idx[b]))
+        return fail(FARM_ERR_OOM, "selection buffers");
+    int32_t* top_idx;
+    if (!alloc(tmp, sizeof(int32_t) * kNPred * tc_max * M, (void**)&top_idx)) return fail(FARM_ERR_OOM, "lists");
+    const size_t bitmap = sizeof(uint32_t) * (size_t)((n + 31) / 32);
+    for (int64_t t0 = 0; t0 < n; t0 += tc_max) {
+      const int64_t tc = n - t0 < tc_max ? n - t0 : tc_max;
+      const int64_t pairs = tc * n;
+      hipLaunchKernelGGL(k_hidden1, dim3((unsigned)pairs), dim3((unsigned)H), 0, s, U, V, mlp->b1, mlp->W1b, mlp->ldx,
+                         2 * mlp->dp, t0, n, mem->x, mem->y, mem->z, mem->ext, mem->rx, mem->ry, A1);
+      if ((e = launch_gemm_nt_bf16(A1, H, mlp->W2b, H, pairs, H, H, A2, H, mlp->b2, true, s)))
+        return fail(FARM_ERR_HIP, "second layer");
+      hipLaunchKernelGGL(k_head_rows, dim3(nblk(pairs)), dim3(256), 0, s, A2, mlp->W3r, mlp->b3, t0, tc, n, L);
+      uint64_t* key;
+      int32_t* idx;
+      if ((e = launch_topk(mem, &tw, L, n, (int32_t)(kNPred * tc), M, &key, &idx, s)))
+        return fail(FARM_ERR_HIP, "list selection");
+      if ((e = launch_topk_emit(key, idx, (int32_t)(kNPred * tc), M, nullptr, nullptr, top_idx, s)))
+        return fail(FARM_ERR_HIP, "list emit");
+      hipLaunchKernelGGL(k_prop_finalize, dim3((unsigned)tc, kNPred), dim3(256), bitmap, s, top_idx, M, t0, tc, n,
+                         mem->x, mem->y, mem->z, mem->hr_hi, mem->hr_lo, pidx, pval, pout);
+      if ((e = hipGetLastError()) != hipSuccess) return fail(FARM_ERR_HIP, "finalize");
+    }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(FARM_ERR_HIP, "synchronize");
+    for (void* p : tmp) (void)hipFree(p);
+    mem->prop_idx = pidx;
+    mem->prop_val = pval;
+    mem->prop_out = pout;
+    mem->prop_m = M;
+    return FARM_OK;
+  } catch (...) {
+    set_error("unexpected host exception in farm_build_proposals");
+    return FARM_ERR_HIP;
+  }
+}
+
+extern "C" farm_status farm_get_proposals(const farm_memory* mem, int32_t* m_out, int32_t* idx, float* val, float* out,
+                                          void* stream) {
+  try {
+    if (!mem || !m_out) { set_error("null memory or m_out"); return FARM_ERR_INVALID_ARG; }
+    *m_out = mem->prop_m;
+    if (mem->prop_m == 0) return FARM_OK;
+    DeviceGuard guard(mem->device);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t entries = (size_t)kNPred * mem->n * mem->prop_m;
+    hipError_t e = hipSuccess;
+    if (idx && e == hipSuccess)
+      e = hipMemcpyAsync(idx, mem->prop_idx, entries * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+    if (val && e == hipSuccess) e = hipMemcpyAsync(val, mem->prop_val, entries * sizeof(float), hipMemcpyDeviceToDevice, s);
+    if (out && e == hipSuccess)
+      e = hipMemcpyAsync(out, mem->prop_out, (size_t)kNPred * mem->n * sizeof(float), hipMemcpyDeviceToDevice, s);
+    return e == hipSuccess ? FARM_OK : hip_fail(e, "copying proposal tables");
+  } catch (...) {
+    set_error("unexpected host exception in farm_get_proposals");
+    return FARM_ERR_HIP;
+  }
+}

@@ -17,6 +17,14 @@
 //           get an FP32 dot product (one wave per anchor), in windows of 2,048
 //           anchors so the survivor list never overflows LDS.  Without a bound
 //           (FP32 similarities) the maximum is taken directly.
+// With anchor proposals the maximum is first taken over the target's learned
+// anchor list and the relation's semantic set only (the same bound-and-survive
+// rule for reduced precision).  Every other anchor j has a similarity at most
+// tau (the largest one outside the semantic set, plus the error bound) and a
+// predicate value at most Pout(o, p) (the largest outside the list), so its
+// value is at most tau * Pout (log domain for Near).  A subset maximum strictly
+// above that is the exact term and binding; otherwise the anchors are scanned
+// in full (the fallback).
 // The per-pair arithmetic is the shared pair_math.h, so a rescored term equals
 // what the FP32 relational pass computes from the same similarity.
 #include <math.h>
@@ -54,29 +62,113 @@ __device__ inline bool better(float v, uint32_t id, float bv, uint32_t bid) {
   return v > bv || (v == bv && id < bid);
 }
 
+// max with the smallest-id tie-break; the id is read only when v reaches best
+__device__ inline void take_max(float v, int64_t j, const uint32_t* __restrict__ ids, float& best, uint32_t& bid) {
+  if (v >= best && v != -INFINITY) {
+    const uint32_t idj = ids[j];
+    if (v > best || idj < bid) {
+      best = v;
+      bid = idj;
+    }
+  }
+}
+
 template <int FAM>
-__device__ void rescore_relation(const float* __restrict__ arow, const float* __restrict__ qrow,
-                                 const float* __restrict__ dn, int32_t ldk, int64_t n, int64_t o, float c,
-                                 bool bounded, float qn, float qe, const float* __restrict__ o_err,
-                                 const float* x, const float* y, const float* z, const float* hhi, const float* hlo,
-                                 const uint32_t* __restrict__ ids, float* red_v, uint32_t* red_id, int32_t* surv,
-                                 int* surv_n, float& out_best, uint32_t& out_bid) {
+__device__ void rescore_relation(const float* __restrict__ arow, const float* __restrict__ lrow,
+                                 const float* __restrict__ qrow, const float* __restrict__ dn, int32_t ldk,
+                                 int64_t n, int64_t o, float c, bool bounded, float qn, float qe,
+                                 const float* __restrict__ o_err, const float* x, const float* y, const float* z,
+                                 const float* hhi, const float* hlo, const uint32_t* __restrict__ ids, float* red_v,
+                                 uint32_t* red_id, int32_t* surv, int* surv_n, const int32_t* __restrict__ lidx,
+                                 const float* __restrict__ lval, int M, const int32_t* __restrict__ sidx, int sn,
+                                 float cert, float& out_best, uint32_t& out_bid, bool& fell_back) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const Tgt t = load_target(FAM, o, x, y, z, hhi, hlo);
   float best = value_floor<FAM>();
   uint32_t bid = FARM_NO_ID;
+  fell_back = false;
+  if (M > 0) {
+    // value of subset entry e (list entries carry the cached predicate value)
+    auto entry = [&](int e, float a, float la) -> float {
+      if (e < M) return FAM == kFamNear ? la + lval[e] : a * lval[e];
+      return pair_value<FAM>(t, anchor_record_pre(FAM, a, la, e < M ? lidx[e] : sidx[e - M], x, y, z, hhi, hlo), c);
+    };
+    const int tot = M + sn;
+    if (!bounded) {
+      for (int e = tid; e < tot; e += kRsThreads) {
+        const int64_t j = e < M ? lidx[e] : sidx[e - M];
+        if (j == o) continue;
+        take_max(entry(e, arow[j], FAM == kFamNear ? lrow[j] : 0.f), j, ids, best, bid);
+      }
+    } else {
+      float lo = value_floor<FAM>();
+      for (int e = tid; e < tot; e += kRsThreads) {
+        const int64_t j = e < M ? lidx[e] : sidx[e - M];
+        if (j == o) continue;
+        const float a = fmaxf(0.f, arow[j] - fmaf(qn, o_err[j], qe));
+        lo = fmaxf(lo, entry(e, a, FAM == kFamNear ? near_log(a) : 0.f));
+      }
+      red_v[tid] = lo;
+      if (tid == 0) *surv_n = 0;
+      __syncthreads();
+      for (int w = kRsThreads / 2; w > 0; w >>= 1) {
+        if (tid < w) red_v[tid] = fmaxf(red_v[tid], red_v[tid + w]);
+        __syncthreads();
+      }
+      const float L = red_v[0] - (fabsf(red_v[0]) * 1e-6f + 1e-30f);
+      __syncthreads();
+      for (int e = tid; e < tot; e += kRsThreads) {
+        const int64_t j = e < M ? lidx[e] : sidx[e - M];
+        if (j == o) continue;
+        const float a = fminf(1.0f, arow[j] + fmaf(qn, o_err[j], qe));
+        if (entry(e, a, FAM == kFamNear ? near_log(a) : 0.f) >= L) surv[atomicAdd(surv_n, 1)] = e;
+      }
+      __syncthreads();
+      const int cnt = *surv_n;
+      for (int s = wave; s < cnt; s += kWaves) {
+        const int e = surv[s];
+        const int64_t j = e < M ? lidx[e] : sidx[e - M];
+        const float a = fmaxf(0.f, wave_dot(qrow, dn + j * ldk, ldk, lane));
+        take_max(entry(e, a, FAM == kFamNear ? near_log(a) : 0.f), j, ids, best, bid);
+      }
+      __syncthreads();
+    }
+    red_v[tid] = best;
+    red_id[tid] = bid;
+    __syncthreads();
+    for (int w = kRsThreads / 2; w > 0; w >>= 1) {
+      if (tid < w && better(red_v[tid + w], red_id[tid + w], red_v[tid], red_id[tid])) {
+        red_v[tid] = red_v[tid + w];
+        red_id[tid] = red_id[tid + w];
+      }
+      __syncthreads();
+    }
+    const float sb = red_v[0];
+    const uint32_t sid = red_id[0];
+    __syncthreads();
+    if (sb > cert) {
+      out_best = sb;
+      out_bid = sid;
+      return;
+    }
+    fell_back = true;
+    best = value_floor<FAM>();
+    bid = FARM_NO_ID;
+  }
   if (!bounded) {
+    // FP32 similarities: the maximum directly, with the relational pass's arithmetic
     for (int64_t j = tid; j < n; j += kRsThreads) {
       if (j == o) continue;
-      float v = pair_value<FAM>(t, anchor_record(FAM, arow[j], j, x, y, z, hhi, hlo), c);
-      if (better(v, ids[j], best, bid) && v != -INFINITY) { best = v; bid = ids[j]; }
+      const float v =
+          pair_value<FAM>(t, anchor_record_pre(FAM, arow[j], FAM == kFamNear ? lrow[j] : 0.f, j, x, y, z, hhi, hlo), c);
+      take_max(v, j, ids, best, bid);
     }
   } else {
-    // lower bound of the best exact value
+    // lower bound L of the best exact value, in the family's comparison domain
     float lo = value_floor<FAM>();
     for (int64_t j = tid; j < n; j += kRsThreads) {
       if (j == o) continue;
-      float a = fmaxf(0.f, arow[j] - fmaf(qn, o_err[j], qe));
+      const float a = fmaxf(0.f, arow[j] - fmaf(qn, o_err[j], qe));
       lo = fmaxf(lo, pair_value<FAM>(t, anchor_record(FAM, a, j, x, y, z, hhi, hlo), c));
     }
     red_v[tid] = lo;
@@ -85,8 +177,7 @@ __device__ void rescore_relation(const float* __restrict__ arow, const float* __
       if (tid < w) red_v[tid] = fmaxf(red_v[tid], red_v[tid + w]);
       __syncthreads();
     }
-    const float L = red_v[0];
-    const float Ls = L - (fabsf(L) * 1e-6f + 1e-30f);  // slack for rounding of the bounded values
+    const float L = red_v[0] - (fabsf(red_v[0]) * 1e-6f + 1e-30f);  // slack for rounding of the bounded values
     __syncthreads();
     for (int64_t w0 = 0; w0 < n; w0 += kWin) {
       if (tid == 0) *surv_n = 0;
@@ -94,17 +185,17 @@ __device__ void rescore_relation(const float* __restrict__ arow, const float* __
       const int64_t w1 = w0 + kWin < n ? w0 + kWin : n;
       for (int64_t j = w0 + tid; j < w1; j += kRsThreads) {
         if (j == o) continue;
-        float a = fminf(1.0f, arow[j] + fmaf(qn, o_err[j], qe));
-        float v = pair_value<FAM>(t, anchor_record(FAM, a, j, x, y, z, hhi, hlo), c);
-        if (v >= Ls) surv[atomicAdd(surv_n, 1)] = (int32_t)j;
+        const float a = fminf(1.0f, arow[j] + fmaf(qn, o_err[j], qe));
+        if (pair_value<FAM>(t, anchor_record(FAM, a, j, x, y, z, hhi, hlo), c) >= L)
+          surv[atomicAdd(surv_n, 1)] = (int32_t)j;
       }
       __syncthreads();
       const int cnt = *surv_n;
       for (int s = wave; s < cnt; s += kWaves) {
         const int64_t j = surv[s];
-        float a = fmaxf(0.f, wave_dot(qrow, dn + j * ldk, ldk, lane));
-        float v = pair_value<FAM>(t, anchor_record(FAM, a, j, x, y, z, hhi, hlo), c);
-        if (better(v, ids[j], best, bid) && v != -INFINITY) { best = v; bid = ids[j]; }
+        const float a = fmaxf(0.f, wave_dot(qrow, dn + j * ldk, ldk, lane));
+        const float v = pair_value<FAM>(t, anchor_record(FAM, a, j, x, y, z, hhi, hlo), c);
+        take_max(v, j, ids, best, bid);
       }
       __syncthreads();
     }
@@ -125,12 +216,13 @@ __device__ void rescore_relation(const float* __restrict__ arow, const float* __
 }
 
 __global__ __launch_bounds__(kRsThreads) void k_rescore(
-    const float* __restrict__ sim, int64_t ld_s, int32_t q, MetaView meta, SimBound bound,
-    const float* __restrict__ qn, const float* __restrict__ dn, int32_t ldk, const int32_t* __restrict__ cand,
+    const float* __restrict__ sim, const float* __restrict__ lsim, int64_t ld_s, int32_t q, MetaView meta,
+    SimBound bound, const float* __restrict__ qn, const float* __restrict__ dn, int32_t ldk,
+    const int32_t* __restrict__ cand,
     const int32_t* __restrict__ cand_count, int32_t C, const float* __restrict__ x, const float* __restrict__ y,
     const float* __restrict__ z, const float* __restrict__ hhi, const float* __restrict__ hlo,
     const uint32_t* __restrict__ ids, const int32_t* __restrict__ cls, int64_t n, float* __restrict__ rs_score,
-    float* __restrict__ rs_terms, uint32_t* __restrict__ rs_anchor) {
+    float* __restrict__ rs_terms, uint32_t* __restrict__ rs_anchor, PropView pv) {
   __shared__ float red_v[kRsThreads];
   __shared__ uint32_t red_id[kRsThreads];
   __shared__ int32_t surv[kWin];
@@ -179,28 +271,59 @@ __global__ __launch_bounds__(kRsThreads) void k_rescore(
       const int p = meta.rel_pred[r];
       const float c = sigmoid_scale(p);
       const float* arow = sim + (int64_t)(q + r) * ld_s;
+      const float* lrow = lsim + (int64_t)r * ld_s;
       const float* qrow = qn + (int64_t)(q + r) * ldk;
       const float qnr = bounded ? bound.q_nrm[q + r] : 0.f;
       const float qer = bounded ? bound.q_err[q + r] + bound.acc : 0.f;
       float best;
       uint32_t bid;
       float term;
+      bool fell_back;
+      // proposal subset of this (relation, candidate) and the bound on every anchor outside it
+      const int32_t* lidx = nullptr;
+      const float* lval = nullptr;
+      const int32_t* sidx = nullptr;
+      int sn = 0;
+      float cert = INFINITY;
+      if (pv.m > 0) {
+        const int64_t lo_ = ((int64_t)p * n + o) * pv.m;
+        lidx = pv.idx + lo_;
+        lval = pv.val + lo_;
+        sidx = pv.sem_idx + (int64_t)r * kSemMax;
+        sn = pv.sem_cnt[r];
+        const float pout = pv.out[(int64_t)p * n + o];
+        const bool near = family_of(p) == kFamNear;
+        if (!bounded) {
+          cert = near ? pv.sem_ltau[r] + pout : pv.sem_tau[r] * pout;
+        } else {
+          const float a_hi = pv.sem_tau[r] + fmaf(qnr, *bound.o_err_max, qer);
+          if (near) {
+            const float b = near_log(a_hi) + pout;
+            cert = b + fabsf(b) * 1e-6f;  // covers the rounding of the logarithm
+          } else {
+            cert = a_hi * pout;
+          }
+        }
+      }
       switch (family_of(p)) {
         case kFamNear:
-          rescore_relation<kFamNear>(arow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, x, y, z, hhi,
-                                     hlo, ids, red_v, red_id, surv, &surv_n, best, bid);
+          rescore_relation<kFamNear>(arow, lrow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, x, y, z, hhi,
+                                     hlo, ids, red_v, red_id, surv, &surv_n, lidx, lval, pv.m, sidx, sn, cert, best, bid,
+                                     fell_back);
           term = term_of<kFamNear>(best);
           lsum += best;
           break;
         case kFamVert:
-          rescore_relation<kFamVert>(arow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, x, y, z, hhi,
-                                     hlo, ids, red_v, red_id, surv, &surv_n, best, bid);
+          rescore_relation<kFamVert>(arow, lrow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, x, y, z, hhi,
+                                     hlo, ids, red_v, red_id, surv, &surv_n, lidx, lval, pv.m, sidx, sn, cert, best, bid,
+                                     fell_back);
           term = term_of<kFamVert>(best);
           lsum += logf(term);
           break;
         default:
-          rescore_relation<kFamLat>(arow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, x, y, z, hhi,
-                                    hlo, ids, red_v, red_id, surv, &surv_n, best, bid);
+          rescore_relation<kFamLat>(arow, lrow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, x, y, z, hhi,
+                                    hlo, ids, red_v, red_id, surv, &surv_n, lidx, lval, pv.m, sidx, sn, cert, best, bid,
+                                     fell_back);
           term = term_of<kFamLat>(best);
           lsum += logf(term);
           break;
@@ -208,6 +331,10 @@ __global__ __launch_bounds__(kRsThreads) void k_rescore(
       if (tid == 0) {
         rs_terms[slot * kMaxRel + e] = term;
         rs_anchor[slot * kMaxRel + e] = bid;
+        if (pv.stats) {
+          atomicAdd(&pv.stats[0], 1ull);
+          if (fell_back) atomicAdd(&pv.stats[1], 1ull);
+        }
       }
     }
     if (tid == 0) {
@@ -296,15 +423,15 @@ __global__ __launch_bounds__(256) void k_max_reduce(const float* __restrict__ v,
 
 }  // namespace
 
-hipError_t launch_rescore(const farm_memory* mem, const farm_workspace* ws, const float* sim, int64_t ld_s, int32_t q,
-                          MetaView meta, const SimBound& bound, const int32_t* cand, const int32_t* cand_count,
-                          int32_t c, hipStream_t s) {
+hipError_t launch_rescore(const farm_memory* mem, const farm_workspace* ws, const float* sim, const float* lsim,
+                          int64_t ld_s, int32_t q, MetaView meta, const SimBound& bound, const int32_t* cand,
+                          const int32_t* cand_count, int32_t c, const PropView& prop, hipStream_t s) {
   if (q <= 0 || c <= 0) return hipSuccess;
   // with a device-side count the candidate slots are swept by a fixed number of blocks per query
   const unsigned gx = cand_count ? (unsigned)(c < 64 ? c : 64) : (unsigned)c;
-  hipLaunchKernelGGL(k_rescore, dim3(gx, (unsigned)q), dim3(kRsThreads), 0, s, sim, ld_s, q, meta, bound, ws->qn,
+  hipLaunchKernelGGL(k_rescore, dim3(gx, (unsigned)q), dim3(kRsThreads), 0, s, sim, lsim, ld_s, q, meta, bound, ws->qn,
                      mem->dn, mem->ldk, cand, cand_count, c, mem->x, mem->y, mem->z, mem->hr_hi, mem->hr_lo, mem->id,
-                     mem->cls, mem->n, ws->rs_score, ws->rs_terms, ws->rs_anchor);
+                     mem->cls, mem->n, ws->rs_score, ws->rs_terms, ws->rs_anchor, prop);
   return hipGetLastError();
 }
 

@@ -1,0 +1,196 @@
+"""Learned anchor proposals (farm_build_proposals, FARM_METHOD_PROPOSAL).
+
+  * tables: every list holds M distinct anchors other than its target, the
+    cached predicate values equal the oracle's P_p(o, a), the stored bound is the
+    oracle's largest P_p(o, a) over the anchors left out, and a list is the top
+    M of the network's own logits;
+  * exactness: the proposal method returns the same ids, scores, terms and bound
+    anchors as the bound-pruned method (which is the exact TopK, tested against
+    the exhaustive path and the oracle elsewhere) for FP32, BF16 and FP8
+    similarities, with any network -- trained or not -- since uncertified terms
+    fall back to the scan over all anchors;
+  * gain: a network trained on the exhaustive pass's bindings certifies more
+    terms than the untrained network on a held-out scene of the same
+    generator, i.e. fewer full scans.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import CONFIGS, make_queries, make_scene
+
+pytestmark = pytest.mark.gpu
+
+REL, ABS = 1e-5, 4e-6
+
+
+@pytest.fixture(scope="module")
+def farm():
+    import paper_2606_15476_amd as farm
+    return farm
+
+
+def _tables(farm, mem):
+    m, idx, val, out = farm.get_proposals(mem)
+    return m, idx.cpu().numpy(), val.cpu().numpy(), out.cpu().numpy()
+
+
+def _p64(scene, p, o, a):
+    return oracle.predicate(p, scene.center[o], scene.center[a], scene.view_right)
+
+
+def test_tables_match_oracle(farm):
+    import torch
+    from tests import _gpu
+    scene = make_scene(CONFIGS["mid"], n=600, seed=11)
+    mem = _gpu.build_memory(scene)
+    net = farm.ProposalNet(scene.d, max_batch=4096, seed=5)
+    farm.build_proposals(mem, net, 48)
+    m, idx, val, out = _tables(farm, mem)
+    n = scene.n
+    assert m == 48 and idx.shape == (5, n, m)
+    rng = np.random.default_rng(0)
+    for o in rng.choice(n, 12, replace=False):
+        for p in range(5):
+            lst = idx[p, o]
+            assert np.all((lst >= 0) & (lst < n)) and np.all(lst != o)
+            assert len(set(lst.tolist())) == m
+            # cached values: log P for Near, P otherwise
+            for e, a in enumerate(lst):
+                v64 = _p64(scene, p, o, a)
+                got = np.exp(np.float64(val[p, o, e])) if p == farm.NEAR else np.float64(val[p, o, e])
+                assert abs(got - v64) <= REL * abs(v64) + ABS, (o, p, a, got, v64)
+            # bound over the anchors left out
+            rest = [a for a in range(n) if a != o and a not in set(lst.tolist())]
+            pout64 = max(_p64(scene, p, o, a) for a in rest)
+            got = np.exp(np.float64(out[p, o])) if p == farm.NEAR else np.float64(out[p, o])
+            assert abs(got - pout64) <= REL * abs(pout64) + ABS, (o, p, got, pout64)
+        # the lists are the network's top M (up to logit rounding of the factorised first layer)
+        o_t = torch.full((n,), int(o), dtype=torch.int32, device="cuda")
+        a_t = torch.arange(n, dtype=torch.int32, device="cuda")
+        lg = torch.empty((n, 5), dtype=torch.float32, device="cuda")
+        net.logits(mem, o_t, a_t, lg)
+        torch.cuda.synchronize()
+        lg = lg.cpu().numpy()
+        lg[o] = -np.inf
+        for p in range(5):
+            top = set(np.argsort(-lg[:, p], kind="stable")[:m].tolist())
+            overlap = len(top & set(idx[p, o].tolist())) / m
+            assert overlap >= 0.9, (o, p, overlap)
+
+
+def _compare(farm, mem, ws, qb, k, dtype):
+    from tests import _gpu
+    bd = _gpu.query_topk(mem, ws, qb, k, dtype=dtype, with_cert=True, method=farm.BOUNDED)
+    ws.proposal_stats(reset=True)
+    pr = _gpu.query_topk(mem, ws, qb, k, dtype=dtype, with_cert=True, method=farm.PROPOSAL)
+    checked, fell = ws.proposal_stats(reset=True)
+    for a, b in zip(pr, bd):
+        np.testing.assert_array_equal(a, b)
+    return checked, fell
+
+
+@pytest.mark.parametrize("dtype", [0, 1, 2], ids=["f32", "bf16", "fp8"])
+def test_proposal_equals_bounded_mid(farm, dtype):
+    from tests import _gpu
+    cfg = CONFIGS["mid"]
+    scene = make_scene(cfg)
+    qb = make_queries(cfg, scene)
+    mem = _gpu.build_memory(scene, flags=farm.FARM_BUILD_BF16 | farm.FARM_BUILD_FP8)
+    ws = farm.Workspace(mem, qb.q, qb.r_tot, 64)
+    net = farm.ProposalNet(scene.d, max_batch=4096, seed=1)
+    farm.build_proposals(mem, net, 256)
+    checked, fell = _compare(farm, mem, ws, qb, cfg.k, dtype)
+    print(f"[proposal mid dtype={dtype}] terms {checked}, fell back {fell}", flush=True)
+    assert checked > 0 and 0 <= fell <= checked
+
+
+def test_proposal_equals_bounded_full_size(farm):
+    from tests import _gpu
+    cfg = CONFIGS["precision"]
+    scene = make_scene(cfg)
+    qb = make_queries(cfg, scene)
+    mem = _gpu.build_memory(scene, flags=farm.FARM_BUILD_BF16)
+    ws = farm.Workspace(mem, qb.q, qb.r_tot, 64)
+    net = farm.ProposalNet(scene.d, max_batch=4096, seed=2)
+    farm.build_proposals(mem, net, 256)
+    for dtype in (0, 1):
+        checked, fell = _compare(farm, mem, ws, qb, cfg.k, dtype)
+        print(f"[proposal full dtype={dtype}] terms {checked}, fell back {fell}", flush=True)
+        assert checked > 0
+
+
+def test_small_scenes_and_errors(farm):
+    import torch
+    from tests import _gpu
+    from tests.test_gpu_parity import _random_queries, _random_scene
+    for n, d, m in ((1, 8, 4), (2, 8, 4), (7, 16, 64), (300, 40, 32)):
+        scene = _random_scene(n, d, seed=n)
+        qb = _random_queries(scene, 5, [0, 2, 3], seed=n + 1)
+        mem = _gpu.build_memory(scene, flags=farm.FARM_BUILD_BF16)
+        ws = farm.Workspace(mem, qb.q, qb.r_tot, 16)
+        with pytest.raises(farm.FarmError) if n >= 2 else _nullctx():
+            _gpu.query_topk(mem, ws, qb, 10, method=farm.PROPOSAL)
+        net = farm.ProposalNet(d, max_batch=256, seed=n)
+        farm.build_proposals(mem, net, m)
+        got_m = farm.get_proposals(mem)[0]
+        assert got_m == min(m, n - 1) if n >= 2 else got_m == 0
+        for dtype in (0, 1):
+            _compare(farm, mem, ws, qb, 10, dtype)
+    # width mismatch
+    scene = _random_scene(20, 16, seed=3)
+    mem = _gpu.build_memory(scene)
+    net = farm.ProposalNet(32, max_batch=64, seed=0)
+    with pytest.raises(farm.FarmError):
+        farm.build_proposals(mem, net, 8)
+    net16 = farm.ProposalNet(16, max_batch=64, seed=0)
+    for bad_m in (0, farm.FARM_MAX_K + 1):
+        with pytest.raises(farm.FarmError):
+            farm.build_proposals(mem, net16, bad_m)
+
+
+class _nullctx:
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        return False
+
+
+def test_trained_network_gain(farm):
+    """Training on exhaustive bindings lowers the fallback rate on a held-out scene."""
+    import time
+    from paper_2606_15476_amd import proposal
+    from tests import _gpu
+    cfg = CONFIGS["precision"]
+    n, q = 4000, 512
+    data = []
+    keep = []
+    for seed in (1000, 1001):
+        scene = make_scene(cfg, seed=seed, n=n)
+        qb = make_queries(cfg, scene, seed=seed, q=q)
+        mem = _gpu.build_memory(scene)
+        ws = farm.Workspace(mem, qb.q, qb.r_tot, 16)
+        target, anchors = _gpu.query_tensors(qb)
+        bind = proposal.exhaustive_bindings(mem, ws, target, qb.target_cls, qb.rel_off, qb.rel_pred, anchors)
+        o, a, p, y = proposal.sample_pairs(bind, scene.ids, qb.rel_pred, np.random.default_rng(seed),
+                                           per_relation=96, negatives=3)
+        data.append((mem, o, a, p, y))
+        keep.append(ws)
+    net = farm.ProposalNet(data[0][0].d, max_batch=4096, seed=7)
+    t0 = time.time()
+    hist = proposal.train(net, data, steps=400, batch=4096, lr=2e-3, weight_decay=1e-4)
+    print(f"[train] {time.time() - t0:.1f}s loss {hist[0][1]:.4f} -> {hist[-1][1]:.4f}", flush=True)
+    assert hist[-1][1] < hist[0][1]
+    # held-out scene: trained vs untrained lists
+    scene = make_scene(cfg, seed=2000, n=n)
+    qb = make_queries(cfg, scene, seed=2000, q=q)
+    mem = _gpu.build_memory(scene, flags=farm.FARM_BUILD_BF16)
+    ws = farm.Workspace(mem, qb.q, qb.r_tot, 16)
+    rates = {}
+    for name, nn_ in (("untrained", farm.ProposalNet(mem.d, max_batch=4096, seed=7)), ("trained", net)):
+        farm.build_proposals(mem, nn_, 256)
+        checked, fell = _compare(farm, mem, ws, qb, cfg.k, 0)
+        rates[name] = fell / max(checked, 1)
+        print(f"[gain] {name}: terms {checked}, fell back {fell} ({rates[name]:.3f})", flush=True)
+    assert rates["trained"] < rates["untrained"]
