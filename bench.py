@@ -76,6 +76,10 @@ def parse():
     p.add_argument("--k", type=int, default=10)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=0, help="queries in the CPU-oracle sample (0 = auto)")
+    p.add_argument("--serving", action="store_true",
+                   help="run the request loop over 16 resident scenes instead (p50/p99 latency per arrival rate)")
+    p.add_argument("--rates", default="500,2000,5000", help="Poisson arrival rates (requests/s) of --serving")
+    p.add_argument("--requests", type=int, default=3000, help="requests per rate of --serving")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                    help="only run one plain device copy of BYTES (reference for the HBM byte counters) and exit")
     return p.parse_args()
@@ -103,6 +107,9 @@ def main():
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU layout is design-only "
               "in this build.", file=sys.stderr)
         sys.exit(2)
+    if args.serving:
+        serving(args)
+        return
     import torch
 
     import paper_2606_15476_amd as farm
@@ -217,6 +224,73 @@ def main():
         "proposal": proposal_info,
     }
     print(json.dumps(out), flush=True)
+
+
+def serving(args):
+    """Poisson arrivals over 16 resident scenes (N log-uniform in [500, 20000],
+    the precision generator, seeds 3000-3015; arrivals seed 3100), uniform scene
+    choice, R ~ U{1..4}; each rate is served by the plain FP32 exhaustive form
+    and by the BF16 bound-pruned form.  Latency = completion seen by the host
+    minus the scheduled arrival time."""
+    import torch
+
+    import paper_2606_15476_amd as farm
+    from synth import CONFIGS, make_queries, make_scene
+    cfg = CONFIGS["precision"]
+    rng = np.random.default_rng(3100)
+    sizes = np.exp(rng.uniform(np.log(500), np.log(20000), 16)).astype(int)
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    scenes, pools = [], []
+    for i, n in enumerate(sizes):
+        sc = make_scene(cfg, seed=3000 + i, n=int(n))
+        qb = make_queries(cfg, sc, seed=3000 + i, q=64)
+        mem = farm.Memory(t(sc.desc), t(sc.center), t(sc.extent), t(sc.ids.view(np.int32)), t(sc.cls), sc.view_right,
+                          flags=farm.FARM_BUILD_BF16)
+        scenes.append(mem)
+        d = sc.d
+        pools.append([(qb.target[q], int(qb.target_cls[q]), qb.rel_pred[qb.rel_off[q]:qb.rel_off[q + 1]],
+                       qb.rel_anchor.reshape(-1, d)[qb.rel_off[q]:qb.rel_off[q + 1]]) for q in range(qb.q)])
+    log(f"[serve] 16 scenes, N = {sorted(int(x) for x in sizes)}")
+    forms = {"f32-exhaustive": (farm.F32, farm.EXHAUSTIVE), "bf16-bounded": (farm.BF16, farm.BOUNDED)}
+    results = []
+    for rate in [float(x) for x in args.rates.split(",")]:
+        gaps = rng.exponential(1.0 / rate, args.requests)
+        arrivals = np.cumsum(gaps)
+        picks = [(int(rng.integers(16)), int(rng.integers(64))) for _ in range(args.requests)]
+        for name, (dt, me) in forms.items():
+            sv = farm.Server(slots=4, max_batch_q=64, max_batch_rel=256, k=10, dtype=dt, method=me,
+                             hbm_budget=16 << 30)
+            for m in scenes:
+                sv.add_scene(m)
+            lat = {}
+            late = {}
+            t0 = time.perf_counter()
+            i = 0
+            while len(lat) < args.requests:
+                now = time.perf_counter() - t0
+                while i < args.requests and arrivals[i] <= now:
+                    s, q = picks[i]
+                    rid = sv.submit(s, *pools[s][q])
+                    late[rid] = (time.perf_counter() - t0) - arrivals[i]
+                    i += 1
+                sv.progress()
+                for rid, st, ce, ns, _, _ in sv.poll():
+                    lat[rid] = ns / 1e9 + late[rid]
+            wall = time.perf_counter() - t0
+            v = np.asarray(list(lat.values())) * 1e3
+            st = sv.stats()
+            sv.close()
+            row = {"rate": rate, "form": name, "p50_ms": round(float(np.percentile(v, 50)), 3),
+                   "p99_ms": round(float(np.percentile(v, 99)), 3), "served_per_s": round(args.requests / wall, 1),
+                   "batches": int(st["batches"]), "deferrals": int(st["deferrals"])}
+            log(f"[serve] {row}")
+            results.append(row)
+    print(json.dumps({"metric": "serving latency over 16 resident scenes", "unit": "ms", "n_gpus": 1,
+                      "config": {"workload": "16 scenes, N log-uniform [500, 20000], D=1152, R~U{1..4}, K=10, "
+                                             "Poisson arrivals", "slots": 4, "max_batch_q": 64,
+                                 "requests_per_rate": args.requests, "scene_sizes": sorted(int(x) for x in sizes)},
+                      "results": results}), flush=True)
 
 
 def prepare_proposals(farm, cfg, mem, args):

@@ -324,6 +324,68 @@ FARM_API farm_status farm_get_proposals(const farm_memory* mem, int32_t* m_out, 
  */
 FARM_API farm_status farm_workspace_proposal_stats(farm_workspace* ws, int64_t* stats, int32_t reset, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Request loop over resident scenes (serving).
+ *
+ * The paper answers one query at a time and reports its latency (Appendix on
+ * query latency); here many queries against several resident scenes are
+ * served together.  The loop is driven by the caller: farm_server_progress
+ * reaps finished batches and admits new ones, without blocking.
+ *   * continuous batching: a free slot takes the pending requests of one scene
+ *     (oldest first, up to max_batch_q queries and max_batch_rel relations);
+ *     slots run on their own streams, so batches of different scenes overlap;
+ *   * admission: each batch needs a workspace of its scene; idle ones are
+ *     reused, new ones are created while the workspaces held stay within
+ *     hbm_budget bytes (farm_workspace_estimate), idle workspaces of other
+ *     scenes are released to make room, and otherwise the requests wait;
+ *   * every request's result equals what it gets alone (rows are scored
+ *     independently of the batch they ride in).
+ * One server is used from one host thread.  Scenes must outlive the server.
+ * ------------------------------------------------------------------------ */
+typedef struct farm_server farm_server;
+
+typedef struct {
+  int32_t slots;          /* concurrent batches (1..64), one stream each */
+  int32_t max_batch_q;    /* queries per batch (>= 1) */
+  int32_t max_batch_rel;  /* relations per batch (0..8*max_batch_q) */
+  int32_t k;              /* TopK of every request (1..FARM_MAX_K) */
+  int32_t dtype;          /* farm_dtype of the similarity GEMM */
+  int32_t method;         /* farm_method */
+  size_t hbm_budget;      /* bytes of workspaces the server may hold */
+} farm_server_config;
+
+/* Errors: INVALID_ARG for a configuration outside the ranges above. */
+FARM_API farm_status farm_server_create(const farm_server_config* cfg, farm_server** out);
+/* Register a resident scene; all scenes share one descriptor width.  The
+   first scene allocates the slots' streams and staging buffers.
+   Errors: INVALID_ARG (width/device mismatch), UNSUPPORTED (the scene lacks
+   the dtype's copy or, for FARM_METHOD_PROPOSAL, its tables), OOM, HIP. */
+FARM_API farm_status farm_server_add_scene(farm_server* sv, const farm_memory* mem, int32_t* scene_out);
+/* Queue one request (host arrays, copied): target [d], target class (-1 =
+   none), r relations with predicates preds [r] and anchor vectors anchors
+   [r][d].  Validates on the host (finite, non-zero, predicates, r <= 8 and
+   <= max_batch_rel) so that a bad request never reaches a batch. */
+FARM_API farm_status farm_server_submit(farm_server* sv, int32_t scene, int32_t d, const float* target,
+                                        int32_t target_cls, int32_t r, const int32_t* preds, const float* anchors,
+                                        uint64_t* request_id);
+/* Cancel a pending or in-flight request; it completes with status 1 and the
+   other requests of its batch are unaffected. */
+FARM_API farm_status farm_server_cancel(farm_server* sv, uint64_t request_id);
+/* Reap finished batches, admit new ones.  busy_slots / pending: host out or NULL. */
+FARM_API farm_status farm_server_progress(farm_server* sv, int32_t* busy_slots, int32_t* pending);
+/* Completed requests in completion order, at most max_results (host arrays,
+   each may be NULL): request ids, status (0 done, 1 cancelled, 2 failed),
+   certified flag, latency from submit to the progress call that saw it
+   finish (ns), TopK ids [max_results][k] and scores. */
+FARM_API farm_status farm_server_poll(farm_server* sv, int32_t max_results, uint64_t* ids, int32_t* status,
+                                      int32_t* certified, int64_t* latency_ns, uint32_t* topk_ids,
+                                      float* topk_scores, int32_t* n_out);
+/* stats [5]: batches launched, admissions deferred, workspaces released to
+   make room, bytes held, workspaces held. */
+FARM_API farm_status farm_server_stats(const farm_server* sv, int64_t* stats);
+/* Waits for the slots' streams, frees the workspaces and buffers. */
+FARM_API farm_status farm_server_free(farm_server* sv);
+
 /*
  * Synchronise `stream` and report whether any scoring call since the last
  * check saw an invalid device input vector (FARM_ERR_INVALID_ARG) -- then

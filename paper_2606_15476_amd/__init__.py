@@ -19,7 +19,7 @@ from ._lib import (FARM_BUILD_BF16, FARM_BUILD_FP8, FARM_MAX_K, FARM_MAX_REL, FA
                    NEAR, ABOVE, BELOW, LEFT_OF, RIGHT_OF, FarmError, lib_path)
 
 __all__ = [
-    "Memory", "Workspace", "ProposalNet", "build_proposals", "get_proposals", "score_query", "topk", "query_topk", "workspace_estimate", "FarmError",
+    "Memory", "Workspace", "ProposalNet", "Server", "build_proposals", "get_proposals", "score_query", "topk", "query_topk", "workspace_estimate", "FarmError",
     "FARM_BUILD_BF16", "FARM_BUILD_FP8", "FARM_MAX_K", "FARM_MAX_REL", "FARM_NO_ID", "F32", "BF16",
     "FP8_E4M3", "EXHAUSTIVE", "BOUNDED", "PROPOSAL", "NEAR", "ABOVE", "BELOW", "LEFT_OF", "RIGHT_OF", "lib_path",
 ]
@@ -271,6 +271,85 @@ class ProposalNet:
     def close(self):
         if getattr(self, "_h", None) is not None:
             _lib.L.farm_mlp_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Request loop over resident scenes (farm_server_*): continuous batching,
+    HBM-budget admission, one stream per slot.  Driven by progress()."""
+
+    def __init__(self, slots: int = 4, max_batch_q: int = 64, max_batch_rel: int = 256, k: int = 10,
+                 dtype: int = F32, method: int = EXHAUSTIVE, hbm_budget: int = 8 << 30):
+        cfg = _lib.ServerConfig(int(slots), int(max_batch_q), int(max_batch_rel), int(k), int(dtype), int(method),
+                                int(hbm_budget))
+        h = ctypes.c_void_p()
+        _lib.check(_lib.L.farm_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self.k = int(k)
+        self.scenes = []
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("server was freed")
+        return self._h
+
+    def add_scene(self, mem: Memory) -> int:
+        idx = ctypes.c_int32()
+        _lib.check(_lib.L.farm_server_add_scene(self.handle, mem.handle, ctypes.byref(idx)))
+        self.scenes.append(mem)
+        return int(idx.value)
+
+    def submit(self, scene: int, target, target_cls: int, preds, anchors) -> int:
+        t = np.ascontiguousarray(target, dtype=np.float32).reshape(-1)
+        p = np.ascontiguousarray(np.asarray(preds, dtype=np.int32).reshape(-1))
+        a = np.ascontiguousarray(anchors, dtype=np.float32).reshape(-1)
+        rid = ctypes.c_uint64()
+        _lib.check(_lib.L.farm_server_submit(self.handle, int(scene), int(t.size), t.ctypes.data_as(ctypes.c_void_p),
+                                             int(target_cls), int(p.size), p.ctypes.data_as(ctypes.c_void_p),
+                                             a.ctypes.data_as(ctypes.c_void_p), ctypes.byref(rid)))
+        return int(rid.value)
+
+    def cancel(self, request_id: int):
+        _lib.check(_lib.L.farm_server_cancel(self.handle, ctypes.c_uint64(int(request_id))))
+
+    def progress(self) -> tuple:
+        """(busy slots, pending requests) after reaping and admitting."""
+        b, p = ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(_lib.L.farm_server_progress(self.handle, ctypes.byref(b), ctypes.byref(p)))
+        return int(b.value), int(p.value)
+
+    def poll(self, max_results: int = 1024) -> list:
+        """Completed requests: [(id, status, certified, latency_ns, ids[k] uint32, scores[k])]."""
+        m, k = int(max_results), self.k
+        ids = np.zeros(m, np.uint64)
+        st = np.zeros(m, np.int32)
+        ce = np.zeros(m, np.int32)
+        lat = np.zeros(m, np.int64)
+        tid = np.zeros((m, k), np.uint32)
+        tsc = np.zeros((m, k), np.float32)
+        n = ctypes.c_int32()
+        vp = lambda x: x.ctypes.data_as(ctypes.c_void_p)
+        _lib.check(_lib.L.farm_server_poll(self.handle, m, vp(ids), vp(st), vp(ce), vp(lat), vp(tid), vp(tsc),
+                                           ctypes.byref(n)))
+        return [(int(ids[i]), int(st[i]), int(ce[i]), int(lat[i]), tid[i].copy(), tsc[i].copy())
+                for i in range(n.value)]
+
+    def stats(self) -> dict:
+        out = (ctypes.c_int64 * 5)()
+        _lib.check(_lib.L.farm_server_stats(self.handle, out))
+        return {"batches": out[0], "deferrals": out[1], "evictions": out[2], "bytes_held": out[3],
+                "workspaces_held": out[4]}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.L.farm_server_free(self._h)
             self._h = None
 
     def __del__(self):

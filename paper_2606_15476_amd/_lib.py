@@ -24,6 +24,8 @@ EXPORTS = (
     "farm_workspace_timings", "farm_mlp_create", "farm_mlp_free", "farm_mlp_shape", "farm_mlp_get_weights",
     "farm_mlp_get_grads", "farm_mlp_set_weights", "farm_mlp_inputs", "farm_mlp_logits", "farm_mlp_step",
     "farm_build_proposals", "farm_workspace_proposal_stats", "farm_get_proposals",
+    "farm_server_create", "farm_server_add_scene", "farm_server_submit", "farm_server_cancel", "farm_server_progress",
+    "farm_server_poll", "farm_server_stats", "farm_server_free",
 )
 MLP_HIDDEN = 256
 PHASES = ("normalize", "gemm", "pair", "topk", "rescore", "explain", "propose")
@@ -36,6 +38,12 @@ class FarmError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{_STATUS.get(status, status)}: {message}")
         self.status = status
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("max_batch_q", ctypes.c_int32), ("max_batch_rel", ctypes.c_int32),
+                ("k", ctypes.c_int32), ("dtype", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_size_t)]
 
 
 class ScoreOpts(ctypes.Structure):
@@ -77,6 +85,14 @@ def _declare(lib):
         "farm_build_proposals": [P, P, i32, P],
         "farm_workspace_proposal_stats": [P, ctypes.POINTER(i64), i32, P],
         "farm_get_proposals": [P, ctypes.POINTER(i32), P, P, P, P],
+        "farm_server_create": [ctypes.POINTER(ServerConfig), pp],
+        "farm_server_add_scene": [P, P, ctypes.POINTER(i32)],
+        "farm_server_submit": [P, i32, i32, P, i32, i32, P, P, ctypes.POINTER(ctypes.c_uint64)],
+        "farm_server_cancel": [P, ctypes.c_uint64],
+        "farm_server_progress": [P, ctypes.POINTER(i32), ctypes.POINTER(i32)],
+        "farm_server_poll": [P, i32, P, P, P, P, P, P, ctypes.POINTER(i32)],
+        "farm_server_stats": [P, ctypes.POINTER(i64)],
+        "farm_server_free": [P],
         "farm_last_error": [],
         "farm_version": [],
     }

@@ -680,8 +680,8 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
       FARM_HIP(launch_rescore(mem, ws, ws->sim, ws->lsim, ws->ld_s, q, meta, bound, ws->rs_idx, ws->cand_count,
                               kBoundCap, pv, s),
                "candidate scoring");
-      FARM_HIP(launch_rescore_select(ws, q, kBoundCap, k, nullptr, nullptr, mem->n, out_id, out_score, out_terms,
-                                     out_anchor_id, nullptr, s),
+      FARM_HIP(launch_rescore_select(ws, q, kBoundCap, k, nullptr, nullptr, ws->cand_count, mem->n, out_id, out_score,
+                                     out_terms, out_anchor_id, nullptr, s),
                "candidate select");
       return FARM_OK;
     }
@@ -716,8 +716,8 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
     PhaseTimer t(ws, s, FARM_PHASE_RESCORE);
     FARM_HIP(launch_rescore(mem, ws, ws->sim, ws->lsim, ws->ld_s, q, meta, bound, ws->rs_idx, nullptr, c, PropView{}, s),
              "rescore");
-    FARM_HIP(launch_rescore_select(ws, q, c, k, hi_key, hi_idx, mem->n, out_id, out_score, out_terms, out_anchor_id,
-                                   certified, s),
+    FARM_HIP(launch_rescore_select(ws, q, c, k, hi_key, hi_idx, nullptr, mem->n, out_id, out_score, out_terms,
+                                   out_anchor_id, certified, s),
              "rescore select");
     return FARM_OK;
   } catch (...) {

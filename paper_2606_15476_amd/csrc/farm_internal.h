@@ -300,10 +300,11 @@ hipError_t launch_bound_candidates(const farm_memory* mem, const float* sim, int
 // bound of any object outside the candidates, or every object was a
 // candidate.  hi_key/hi_idx [q][c + 1] are the top c + 1 objects by upper
 // bound: the first of them that is not a candidate carries that largest bound.
+// cand_count (optional): per query, the number of filled candidate slots.
 hipError_t launch_rescore_select(const farm_workspace* ws, int32_t q, int32_t c, int32_t k,
-                                 const uint64_t* hi_key, const int32_t* hi_idx, int64_t n, uint32_t* out_id,
-                                 float* out_score, float* out_terms, uint32_t* out_anchor_id, int32_t* certified,
-                                 hipStream_t s);
+                                 const uint64_t* hi_key, const int32_t* hi_idx, const int32_t* cand_count, int64_t n,
+                                 uint32_t* out_id, float* out_score, float* out_terms, uint32_t* out_anchor_id,
+                                 int32_t* certified, hipStream_t s);
 hipError_t launch_max_reduce(const float* v, int64_t n, float* out, hipStream_t s);
 
 // ---- proposal.hip

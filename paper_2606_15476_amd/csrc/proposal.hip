@@ -156,82 +156,72 @@ __global__ __launch_bounds__(256) void k_prop_finalize(const int32_t* __restrict
 }
 
 // ---------------------------------------------------------------- query time
-// Semantic set of one relation row: tau = gamma * max_a sim with gamma in
-// 1/2, 3/4, 7/8, ... until at most kSemMax anchors exceed tau; the set is
-// their ordered compaction (truncated to kSemMax if ties at the maximum leave
-// more).  Then the largest similarity and log similarity of the anchors
-// outside the set, which bound every anchor the set leaves out.
-__global__ __launch_bounds__(256) void k_semantic_sets(const float* __restrict__ sim, const float* __restrict__ lsim,
-                                                       int64_t ld_s, int32_t q, int64_t n, int32_t* __restrict__ sem_idx,
-                                                       int32_t* __restrict__ sem_cnt, float* __restrict__ sem_tau,
-                                                       float* __restrict__ sem_ltau) {
-  __shared__ float red[256];
-  __shared__ float lred[256];
-  __shared__ int32_t scan[256];
-  const int32_t r = blockIdx.x;
+// Semantic set of one relation row, one wave per row: tau = gamma * max_a sim
+// with gamma in 1/2, 3/4, 7/8, ... until at most kSemMax anchors exceed tau;
+// the set is their ordered compaction (ballots; truncated to kSemMax if ties
+// at the maximum leave more).  Then the largest similarity and log similarity
+// of the anchors outside the set, which bound every anchor the set leaves out.
+constexpr int kSemWaves = 4;
+
+__device__ inline float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+  return v;
+}
+
+__global__ __launch_bounds__(64 * kSemWaves) void k_semantic_sets(const float* __restrict__ sim,
+                                                                  const float* __restrict__ lsim, int64_t ld_s,
+                                                                  int32_t q, int32_t R, int64_t n,
+                                                                  int32_t* __restrict__ sem_idx,
+                                                                  int32_t* __restrict__ sem_cnt,
+                                                                  float* __restrict__ sem_tau,
+                                                                  float* __restrict__ sem_ltau) {
+  const int lane = threadIdx.x & 63;
+  const int32_t r = blockIdx.x * kSemWaves + (threadIdx.x >> 6);
+  if (r >= R) return;  // the whole wave leaves; no block barrier follows
   const float* row = sim + (int64_t)(q + r) * ld_s;
   const float* lrow = lsim + (int64_t)r * ld_s;
   float mx = 0.f;
-  for (int64_t j = threadIdx.x; j < n; j += 256) mx = fmaxf(mx, row[j]);
-  red[threadIdx.x] = mx;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
-    __syncthreads();
-  }
-  const float amax = red[0];
-  __syncthreads();
-  const int64_t chunk = (n + 255) / 256;
-  const int64_t i0 = threadIdx.x * chunk < n ? threadIdx.x * chunk : n;
-  const int64_t i1 = i0 + chunk < n ? i0 + chunk : n;
+  for (int64_t j = lane; j < n; j += 64) mx = fmaxf(mx, row[j]);
+  const float amax = wave_max(mx);
   auto count_above = [&](float tau) {
     int32_t c = 0;
-    for (int64_t j = i0; j < i1; ++j) c += row[j] > tau;
-    scan[threadIdx.x] = c;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {  // inclusive scan
-      const int32_t v = (int)threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
-      __syncthreads();
-      scan[threadIdx.x] += v;
-      __syncthreads();
+    for (int64_t base = 0; base < n; base += 64) {
+      const int64_t j = base + lane;
+      c += __popcll(__ballot(j < n && row[j] > tau));
     }
-    const int32_t total = scan[255];
-    return total;
+    return c;
   };
   float tau = 0.5f * amax, gap = 0.5f * amax;
   int32_t total = count_above(tau);
   for (int it = 0; it < 30 && total > kSemMax; ++it) {
-    __syncthreads();
     gap *= 0.5f;
     tau = amax - gap;
     total = count_above(tau);
   }
-  // scan[] holds the inclusive prefix counts for the settled tau
-  int32_t pos = threadIdx.x ? scan[threadIdx.x - 1] : 0;
+  const uint64_t below = (1ull << lane) - 1ull;
+  int32_t pos = 0;
   float out = 0.f, lout = -INFINITY;
-  for (int64_t j = i0; j < i1; ++j) {
-    if (row[j] > tau && pos < kSemMax) {
-      sem_idx[(int64_t)r * kSemMax + pos++] = (int32_t)j;
-    } else {
+  for (int64_t base = 0; base < n; base += 64) {
+    const int64_t j = base + lane;
+    const bool valid = j < n;
+    const bool above = valid && row[j] > tau;
+    const uint64_t mask = __ballot(above);
+    const int32_t my = pos + __popcll(mask & below);
+    if (above && my < kSemMax) {
+      sem_idx[(int64_t)r * kSemMax + my] = (int32_t)j;
+    } else if (valid) {
       out = fmaxf(out, row[j]);
       lout = fmaxf(lout, lrow[j]);
     }
+    pos += __popcll(mask);
   }
-  __syncthreads();
-  red[threadIdx.x] = out;
-  lred[threadIdx.x] = lout;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
-      lred[threadIdx.x] = fmaxf(lred[threadIdx.x], lred[threadIdx.x + w]);
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
+  out = wave_max(out);
+  lout = wave_max(lout);
+  if (lane == 0) {
     sem_cnt[r] = total < kSemMax ? total : kSemMax;
-    sem_tau[r] = red[0];
-    sem_ltau[r] = lred[0];
+    sem_tau[r] = out;
+    sem_ltau[r] = lout;
   }
 }
 
@@ -242,8 +232,8 @@ inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t
 hipError_t launch_semantic_sets(const float* sim, const float* lsim, int64_t ld_s, int32_t q, int32_t R, int64_t n,
                                 int32_t* sem_idx, int32_t* sem_cnt, float* sem_tau, float* sem_ltau, hipStream_t s) {
   if (R <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_semantic_sets, dim3((unsigned)R), dim3(256), 0, s, sim, lsim, ld_s, q, n, sem_idx, sem_cnt,
-                     sem_tau, sem_ltau);
+  hipLaunchKernelGGL(k_semantic_sets, dim3((unsigned)((R + kSemWaves - 1) / kSemWaves)), dim3(64 * kSemWaves), 0, s,
+                     sim, lsim, ld_s, q, R, n, sem_idx, sem_cnt, sem_tau, sem_ltau);
   return hipGetLastError();
 }
 

@@ -355,7 +355,8 @@ __global__ __launch_bounds__(256) void k_rescore_select(const float* __restrict_
                                                         const uint32_t* __restrict__ rs_anchor,
                                                         const uint32_t* __restrict__ ids, int32_t C, int32_t k,
                                                         const uint64_t* __restrict__ hi_key,
-                                                        const int32_t* __restrict__ hi_idx, int64_t n,
+                                                        const int32_t* __restrict__ hi_idx,
+                                                        const int32_t* __restrict__ cand_count, int64_t n,
                                                         uint32_t* __restrict__ out_id, float* __restrict__ out_score,
                                                         float* __restrict__ out_terms,
                                                         uint32_t* __restrict__ out_anchor,
@@ -364,9 +365,11 @@ __global__ __launch_bounds__(256) void k_rescore_select(const float* __restrict_
   __shared__ int32_t slot[kSortMax];
   __shared__ int32_t first_out;
   const int32_t qq = blockIdx.x;
-  const int P = pow2_at_least(C);
+  // slots at or beyond the query's candidate count hold nothing
+  const int32_t used = cand_count ? (cand_count[qq] < C ? cand_count[qq] : C) : C;
+  const int P = pow2_at_least(used > 0 ? used : 1);
   for (int e = threadIdx.x; e < P; e += blockDim.x) {
-    int32_t o = e < C ? rs_idx[(int64_t)qq * C + e] : -1;
+    int32_t o = e < used ? rs_idx[(int64_t)qq * C + e] : -1;
     keys[e] = o >= 0 ? make_key(rs_score[(int64_t)qq * C + e], ids[o]) : 0;
     slot[e] = o >= 0 ? e : -1;
   }
@@ -436,13 +439,14 @@ hipError_t launch_rescore(const farm_memory* mem, const farm_workspace* ws, cons
 }
 
 hipError_t launch_rescore_select(const farm_workspace* ws, int32_t q, int32_t c, int32_t k, const uint64_t* hi_key,
-                                 const int32_t* hi_idx, int64_t n, uint32_t* out_id, float* out_score,
-                                 float* out_terms, uint32_t* out_anchor_id, int32_t* certified, hipStream_t s) {
+                                 const int32_t* hi_idx, const int32_t* cand_count, int64_t n, uint32_t* out_id,
+                                 float* out_score, float* out_terms, uint32_t* out_anchor_id, int32_t* certified,
+                                 hipStream_t s) {
   if (q <= 0) return hipSuccess;
   if (c > kSortMax) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_rescore_select, dim3((unsigned)q), dim3(256), 0, s, ws->rs_score, ws->rs_idx, ws->rs_terms,
-                     ws->rs_anchor, ws->mem->id, c, k, hi_key, hi_idx, n, out_id, out_score, out_terms, out_anchor_id,
-                     certified);
+                     ws->rs_anchor, ws->mem->id, c, k, hi_key, hi_idx, cand_count, n, out_id, out_score, out_terms,
+                     out_anchor_id, certified);
   return hipGetLastError();
 }
 
