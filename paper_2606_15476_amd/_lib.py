@@ -108,6 +108,11 @@ def load(path: str | None = None):
     if not os.path.exists(path):
         raise ImportError(f"libfarm.so not built at {path}; run `python paper_2606_15476_amd/build.py` "
                           "(the HIP library is required: there is no fallback)")
+    # torch ships its own HIP runtime under the same soname (libamdhip64.so.7).
+    # Loading torch first makes libfarm bind to that one instance; loading
+    # libfarm first would bring in a second HIP/HSA runtime, and the second one
+    # to initialise in the process finds no device.
+    import torch  # noqa: F401
     return _declare(ctypes.CDLL(path))
 
 

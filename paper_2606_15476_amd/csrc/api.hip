@@ -92,7 +92,7 @@ size_t workspace_bytes_for(const farm_memory* mem, int32_t max_q, int32_t max_re
   b += (size_t)max_q * cap * (sizeof(int32_t) + sizeof(float) + kMaxRel * (sizeof(float) + sizeof(uint32_t)));
   b += (size_t)max_q * sizeof(int32_t);
   const size_t rel1 = (size_t)(max_rel > 0 ? max_rel : 1);
-  b += rel1 * (kSemMax * sizeof(int32_t) + sizeof(int32_t) + 2 * sizeof(float));  // semantic sets
+  b += rel1 * (kSemMax * sizeof(int32_t) + sizeof(int32_t) + sizeof(float));  // semantic sets
   b += 2 * sizeof(unsigned long long);
   return b;
 }
@@ -186,9 +186,11 @@ farm_status stage_meta(farm_workspace* ws, int32_t q, int32_t R, const int32_t* 
 float accumulation_bound(int32_t ldk) { return 2.02f * (float)ldk * 5.9604645e-8f + 1e-6f; }
 
 // Steps 2 and 3: normalised query rows and the similarity matrix in `dtype`.
+// need_log: also write lsim (the exhaustive relational pass stages it; the
+// candidate methods take logarithms of the few similarities they gather).
 farm_status similarities(const farm_memory* mem, farm_workspace* ws, int32_t q, int32_t R, const float* target,
                          const float* rel_anchor, const MetaView& meta, int32_t dtype, SimBound* bound,
-                         hipStream_t s) {
+                         bool need_log, hipStream_t s) {
   const int32_t ldk = mem->ldk;
   LowPrecRows lt, la;
   if (dtype == FARM_BF16) {
@@ -231,7 +233,8 @@ farm_status similarities(const farm_memory* mem, farm_workspace* ws, int32_t q, 
              "FP8 similarity GEMM");
     *bound = SimBound{ws->qnrm_fp8, ws->qerr_fp8, mem->err_fp8, mem->err_max + 1, accumulation_bound(ldk)};
   }
-  FARM_HIP(launch_log_rows(ws->sim + (int64_t)q * ws->ld_s, ws->ld_s, R, mem->n, ws->lsim, s), "log similarities");
+  if (need_log)
+    FARM_HIP(launch_log_rows(ws->sim + (int64_t)q * ws->ld_s, ws->ld_s, R, mem->n, ws->lsim, s), "log similarities");
   return FARM_OK;
 }
 
@@ -453,7 +456,6 @@ farm_status farm_workspace_create(const farm_memory* mem, int32_t max_q, int32_t
     if ((st = dalloc(ws->allocs, ws->bytes, &ws->sem_idx, rel1 * kSemMax, "semantic sets")) ||
         (st = dalloc(ws->allocs, ws->bytes, &ws->sem_cnt, rel1, "semantic set sizes")) ||
         (st = dalloc(ws->allocs, ws->bytes, &ws->sem_tau, rel1, "semantic bounds")) ||
-        (st = dalloc(ws->allocs, ws->bytes, &ws->sem_ltau, rel1, "semantic log bounds")) ||
         (st = dalloc(ws->allocs, ws->bytes, &ws->prop_stats, 2, "proposal counters")))
       return fail(st);
     hipError_t e = hipHostMalloc((void**)&ws->h_meta, (size_t)ws->meta_len * sizeof(int32_t), hipHostMallocDefault);
@@ -571,7 +573,7 @@ farm_status farm_score_query(const farm_memory* mem, farm_workspace* ws, int32_t
     MetaView meta;
     FARM_TRY(stage_meta(ws, q, R, target_cls, rel_off, rel_pred, s, &meta));
     SimBound none;
-    FARM_TRY(similarities(mem, ws, q, R, target, rel_anchor, meta, FARM_F32, &none, s));
+    FARM_TRY(similarities(mem, ws, q, R, target, rel_anchor, meta, FARM_F32, &none, true, s));
     PhaseTimer t(ws, s, FARM_PHASE_PAIR);
     FARM_HIP(launch_pair_exhaustive(mem, ws->sim, ws->lsim, ws->ld_s, q, meta, none, scores, mem->n, rel_terms, rel_anchor_id,
                                     nullptr, s),
@@ -652,7 +654,7 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
     MetaView meta;
     FARM_TRY(stage_meta(ws, q, R, target_cls, rel_off, rel_pred, s, &meta));
     SimBound bound;
-    FARM_TRY(similarities(mem, ws, q, R, target, rel_anchor, meta, dtype, &bound, s));
+    FARM_TRY(similarities(mem, ws, q, R, target, rel_anchor, meta, dtype, &bound, method == FARM_METHOD_EXHAUSTIVE, s));
     if (method == FARM_METHOD_BOUNDED || method == FARM_METHOD_PROPOSAL) {
       {
         PhaseTimer t(ws, s, FARM_PHASE_TOPK);
@@ -663,8 +665,7 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
       PropView pv;
       if (method == FARM_METHOD_PROPOSAL && mem->prop_m > 0) {
         PhaseTimer t(ws, s, FARM_PHASE_PROPOSE);
-        FARM_HIP(launch_semantic_sets(ws->sim, ws->lsim, ws->ld_s, q, R, mem->n, ws->sem_idx, ws->sem_cnt, ws->sem_tau,
-                                      ws->sem_ltau, s),
+        FARM_HIP(launch_semantic_sets(ws->sim, ws->ld_s, q, R, mem->n, ws->sem_idx, ws->sem_cnt, ws->sem_tau, s),
                  "semantic sets");
         pv.m = mem->prop_m;
         pv.idx = mem->prop_idx;
@@ -673,12 +674,11 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
         pv.sem_idx = ws->sem_idx;
         pv.sem_cnt = ws->sem_cnt;
         pv.sem_tau = ws->sem_tau;
-        pv.sem_ltau = ws->sem_ltau;
         pv.stats = ws->prop_stats;
       }
       PhaseTimer t(ws, s, FARM_PHASE_RESCORE);
-      FARM_HIP(launch_rescore(mem, ws, ws->sim, ws->lsim, ws->ld_s, q, meta, bound, ws->rs_idx, ws->cand_count,
-                              kBoundCap, pv, s),
+      FARM_HIP(launch_rescore(mem, ws, ws->sim, ws->ld_s, q, meta, bound, ws->rs_idx, ws->cand_count, kBoundCap, pv,
+                              s),
                "candidate scoring");
       FARM_HIP(launch_rescore_select(ws, q, kBoundCap, k, nullptr, nullptr, ws->cand_count, mem->n, out_id, out_score,
                                      out_terms, out_anchor_id, nullptr, s),
@@ -714,7 +714,7 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
       FARM_HIP(launch_topk(mem, ws, ws->scores_hi, ws->ld_s, q, c + 1, &hi_key, &hi_idx, s), "bound topk");
     }
     PhaseTimer t(ws, s, FARM_PHASE_RESCORE);
-    FARM_HIP(launch_rescore(mem, ws, ws->sim, ws->lsim, ws->ld_s, q, meta, bound, ws->rs_idx, nullptr, c, PropView{}, s),
+    FARM_HIP(launch_rescore(mem, ws, ws->sim, ws->ld_s, q, meta, bound, ws->rs_idx, nullptr, c, PropView{}, s),
              "rescore");
     FARM_HIP(launch_rescore_select(ws, q, c, k, hi_key, hi_idx, nullptr, mem->n, out_id, out_score, out_terms,
                                    out_anchor_id, certified, s),

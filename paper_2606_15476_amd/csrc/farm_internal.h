@@ -113,7 +113,6 @@ struct farm_workspace {
   int32_t* sem_idx = nullptr;    // [max_rel][kSemMax]
   int32_t* sem_cnt = nullptr;    // [max_rel]
   float* sem_tau = nullptr;      // [max_rel] largest similarity of an anchor outside the set
-  float* sem_ltau = nullptr;     // [max_rel] largest log similarity outside the set
   unsigned long long* prop_stats = nullptr;  // [2] (candidate, relation) pairs checked, pairs that fell back
   // optional phase timer: pending (start, stop) event pairs per phase
   bool timing = false;
@@ -209,7 +208,6 @@ struct PropView {
   const int32_t* sem_idx = nullptr;  // [R][kSemMax]
   const int32_t* sem_cnt = nullptr;  // [R]
   const float* sem_tau = nullptr;    // [R]
-  const float* sem_ltau = nullptr;   // [R]
   unsigned long long* stats = nullptr;
 };
 
@@ -283,9 +281,9 @@ hipError_t launch_explain(const farm_memory* mem, const float* sim, int64_t ld_s
 // With proposals (prop.m > 0) each term is first taken over the target's
 // anchor list and the relation's semantic set; it is kept when it exceeds the
 // bound on every anchor outside both, else the anchors are scanned in full.
-hipError_t launch_rescore(const farm_memory* mem, const farm_workspace* ws, const float* sim, const float* lsim,
-                          int64_t ld_s, int32_t q, MetaView meta, const SimBound& bound, const int32_t* cand,
-                          const int32_t* cand_count, int32_t c, const PropView& prop, hipStream_t s);
+hipError_t launch_rescore(const farm_memory* mem, const farm_workspace* ws, const float* sim, int64_t ld_s, int32_t q,
+                          MetaView meta, const SimBound& bound, const int32_t* cand, const int32_t* cand_count,
+                          int32_t c, const PropView& prop, hipStream_t s);
 
 // ---- bounded.hip
 // Candidates of the exact bound-pruned TopK: per query every object whose
@@ -309,10 +307,9 @@ hipError_t launch_max_reduce(const float* v, int64_t n, float* out, hipStream_t 
 
 // ---- proposal.hip
 // Per relation row: a semantic anchor set (at most kSemMax anchors with the
-// largest similarities), and the largest similarity and log similarity of the
-// anchors outside it.
-hipError_t launch_semantic_sets(const float* sim, const float* lsim, int64_t ld_s, int32_t q, int32_t R, int64_t n,
-                                int32_t* sem_idx, int32_t* sem_cnt, float* sem_tau, float* sem_ltau, hipStream_t s);
+// largest similarities) and the largest similarity of the anchors outside it.
+hipError_t launch_semantic_sets(const float* sim, int64_t ld_s, int32_t q, int32_t R, int64_t n, int32_t* sem_idx,
+                                int32_t* sem_cnt, float* sem_tau, hipStream_t s);
 
 // ---- topk.hip
 // Select the top k of each score row.  Writes (key, index) of the winners in

@@ -159,8 +159,8 @@ __global__ __launch_bounds__(256) void k_prop_finalize(const int32_t* __restrict
 // Semantic set of one relation row, one wave per row: tau = gamma * max_a sim
 // with gamma in 1/2, 3/4, 7/8, ... until at most kSemMax anchors exceed tau;
 // the set is their ordered compaction (ballots; truncated to kSemMax if ties
-// at the maximum leave more).  Then the largest similarity and log similarity
-// of the anchors outside the set, which bound every anchor the set leaves out.
+// at the maximum leave more).  Then the largest similarity of the anchors
+// outside the set, which bounds every anchor the set leaves out.
 constexpr int kSemWaves = 4;
 
 __device__ inline float wave_max(float v) {
@@ -169,18 +169,15 @@ __device__ inline float wave_max(float v) {
   return v;
 }
 
-__global__ __launch_bounds__(64 * kSemWaves) void k_semantic_sets(const float* __restrict__ sim,
-                                                                  const float* __restrict__ lsim, int64_t ld_s,
+__global__ __launch_bounds__(64 * kSemWaves) void k_semantic_sets(const float* __restrict__ sim, int64_t ld_s,
                                                                   int32_t q, int32_t R, int64_t n,
                                                                   int32_t* __restrict__ sem_idx,
                                                                   int32_t* __restrict__ sem_cnt,
-                                                                  float* __restrict__ sem_tau,
-                                                                  float* __restrict__ sem_ltau) {
+                                                                  float* __restrict__ sem_tau) {
   const int lane = threadIdx.x & 63;
   const int32_t r = blockIdx.x * kSemWaves + (threadIdx.x >> 6);
   if (r >= R) return;  // the whole wave leaves; no block barrier follows
   const float* row = sim + (int64_t)(q + r) * ld_s;
-  const float* lrow = lsim + (int64_t)r * ld_s;
   float mx = 0.f;
   for (int64_t j = lane; j < n; j += 64) mx = fmaxf(mx, row[j]);
   const float amax = wave_max(mx);
@@ -201,7 +198,7 @@ __global__ __launch_bounds__(64 * kSemWaves) void k_semantic_sets(const float* _
   }
   const uint64_t below = (1ull << lane) - 1ull;
   int32_t pos = 0;
-  float out = 0.f, lout = -INFINITY;
+  float out = 0.f;
   for (int64_t base = 0; base < n; base += 64) {
     const int64_t j = base + lane;
     const bool valid = j < n;
@@ -212,16 +209,13 @@ __global__ __launch_bounds__(64 * kSemWaves) void k_semantic_sets(const float* _
       sem_idx[(int64_t)r * kSemMax + my] = (int32_t)j;
     } else if (valid) {
       out = fmaxf(out, row[j]);
-      lout = fmaxf(lout, lrow[j]);
     }
     pos += __popcll(mask);
   }
   out = wave_max(out);
-  lout = wave_max(lout);
   if (lane == 0) {
     sem_cnt[r] = total < kSemMax ? total : kSemMax;
     sem_tau[r] = out;
-    sem_ltau[r] = lout;
   }
 }
 
@@ -229,11 +223,11 @@ inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t
 
 }  // namespace
 
-hipError_t launch_semantic_sets(const float* sim, const float* lsim, int64_t ld_s, int32_t q, int32_t R, int64_t n,
-                                int32_t* sem_idx, int32_t* sem_cnt, float* sem_tau, float* sem_ltau, hipStream_t s) {
+hipError_t launch_semantic_sets(const float* sim, int64_t ld_s, int32_t q, int32_t R, int64_t n, int32_t* sem_idx,
+                                int32_t* sem_cnt, float* sem_tau, hipStream_t s) {
   if (R <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_semantic_sets, dim3((unsigned)((R + kSemWaves - 1) / kSemWaves)), dim3(64 * kSemWaves), 0, s,
-                     sim, lsim, ld_s, q, R, n, sem_idx, sem_cnt, sem_tau, sem_ltau);
+                     sim, ld_s, q, R, n, sem_idx, sem_cnt, sem_tau);
   return hipGetLastError();
 }
 

@@ -8,15 +8,16 @@
 // ("certified") whenever the K-th rescored score exceeds the largest s_hi of
 // any object outside the candidates.
 //
-// Rescoring one candidate o (one block per (candidate, query)):
-//   s_sem:  FP32 dot of the normalised target and descriptor rows (block sum),
-//           clamp, class factor;
+// Rescoring one candidate o: one wave per (candidate, relation) term, then
+// one wave per candidate for the composite.
+//   s_sem:  the FP32 GEMM's value, or an FP32 dot of the normalised target and
+//           descriptor rows when the GEMM ran in reduced precision;
 //   t_r:    with a similarity bound |a~_j - a_j| <= delta_j, the best value is
 //           at least L = max_j (a~_j - delta_j)+ * P(o, j); only anchors with
 //           min(1, a~_j + delta_j) * P(o, j) >= L can reach it, so only those
-//           get an FP32 dot product (one wave per anchor), in windows of 2,048
-//           anchors so the survivor list never overflows LDS.  Without a bound
-//           (FP32 similarities) the maximum is taken directly.
+//           get an FP32 dot product (the wave iterates over the ballot of
+//           survivors).  Without a bound (FP32 similarities) the maximum is
+//           taken directly.
 // With anchor proposals the maximum is first taken over the target's learned
 // anchor list and the relation's semantic set only (the same bound-and-survive
 // rule for reduced precision).  Every other anchor j has a similarity at most
@@ -35,10 +36,6 @@
 
 namespace farm {
 namespace {
-
-constexpr int kRsThreads = 256;
-constexpr int kWaves = kRsThreads / 64;
-constexpr int kWin = 2048;
 
 __device__ inline float wave_sum(float v) {
 #pragma unroll
@@ -73,82 +70,104 @@ __device__ inline void take_max(float v, int64_t j, const uint32_t* __restrict__
   }
 }
 
+// Wave-wide arg-max with the smallest-id tie-break; every lane gets the result.
+__device__ inline void wave_argmax(float& best, uint32_t& bid) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const float v = __shfl_xor(best, off);
+    const uint32_t id = (uint32_t)__shfl_xor((int)bid, off);
+    if (better(v, id, best, bid)) {
+      best = v;
+      bid = id;
+    }
+  }
+}
+
+__device__ inline float wave_max_f(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+  return v;
+}
+
+// Geometry of the memory, passed by value.
+struct Geo {
+  const float *x, *y, *z, *hhi, *hlo;
+  const uint32_t* ids;
+};
+
+// Anchors of one term: the list of the target (lidx/lval, M entries) and the
+// relation's semantic set (sidx, sn entries); M == 0 means none.
+struct Subset {
+  const int32_t* lidx;
+  const float* lval;
+  int M;
+  const int32_t* sidx;
+  int sn;
+  float cert;  // bound on the value of every anchor outside the subset (family domain)
+};
+
+// One relation term of target o, computed by one wave.  Returns the
+// family-domain maximum (log for Near) and its anchor id.
 template <int FAM>
-__device__ void rescore_relation(const float* __restrict__ arow, const float* __restrict__ lrow,
-                                 const float* __restrict__ qrow, const float* __restrict__ dn, int32_t ldk,
-                                 int64_t n, int64_t o, float c, bool bounded, float qn, float qe,
-                                 const float* __restrict__ o_err, const float* x, const float* y, const float* z,
-                                 const float* hhi, const float* hlo, const uint32_t* __restrict__ ids, float* red_v,
-                                 uint32_t* red_id, int32_t* surv, int* surv_n, const int32_t* __restrict__ lidx,
-                                 const float* __restrict__ lval, int M, const int32_t* __restrict__ sidx, int sn,
-                                 float cert, float& out_best, uint32_t& out_bid, bool& fell_back) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const Tgt t = load_target(FAM, o, x, y, z, hhi, hlo);
+__device__ void term_wave(const float* __restrict__ arow, const float* __restrict__ qrow, const float* __restrict__ dn, int32_t ldk, int64_t n,
+                          int64_t o, float c, bool bounded, float qn, float qe, const float* __restrict__ o_err,
+                          const Geo& g, const Subset& sub, int lane, float& out_best, uint32_t& out_bid,
+                          bool& fell_back) {
+  const Tgt t = load_target(FAM, o, g.x, g.y, g.z, g.hhi, g.hlo);
   float best = value_floor<FAM>();
   uint32_t bid = FARM_NO_ID;
   fell_back = false;
-  if (M > 0) {
-    // value of subset entry e (list entries carry the cached predicate value)
-    auto entry = [&](int e, float a, float la) -> float {
-      if (e < M) return FAM == kFamNear ? la + lval[e] : a * lval[e];
-      return pair_value<FAM>(t, anchor_record_pre(FAM, a, la, e < M ? lidx[e] : sidx[e - M], x, y, z, hhi, hlo), c);
+  if (sub.M > 0) {
+    const int tot = sub.M + sub.sn;
+    auto anchor_of = [&](int e) -> int64_t { return e < sub.M ? sub.lidx[e] : sub.sidx[e - sub.M]; };
+    // list entries carry the cached predicate value; semantic-set entries are evaluated
+    auto entry = [&](int e, int64_t j, float a, float la) -> float {
+      if (e < sub.M) return FAM == kFamNear ? la + sub.lval[e] : a * sub.lval[e];
+      return pair_value<FAM>(t, anchor_record_pre(FAM, a, la, j, g.x, g.y, g.z, g.hhi, g.hlo), c);
     };
-    const int tot = M + sn;
     if (!bounded) {
-      for (int e = tid; e < tot; e += kRsThreads) {
-        const int64_t j = e < M ? lidx[e] : sidx[e - M];
+      for (int e = lane; e < tot; e += 64) {
+        const int64_t j = anchor_of(e);
         if (j == o) continue;
-        take_max(entry(e, arow[j], FAM == kFamNear ? lrow[j] : 0.f), j, ids, best, bid);
+        const float a = arow[j];
+        take_max(entry(e, j, a, FAM == kFamNear ? near_log(a) : 0.f), j, g.ids, best, bid);
       }
     } else {
       float lo = value_floor<FAM>();
-      for (int e = tid; e < tot; e += kRsThreads) {
-        const int64_t j = e < M ? lidx[e] : sidx[e - M];
+      for (int e = lane; e < tot; e += 64) {
+        const int64_t j = anchor_of(e);
         if (j == o) continue;
         const float a = fmaxf(0.f, arow[j] - fmaf(qn, o_err[j], qe));
-        lo = fmaxf(lo, entry(e, a, FAM == kFamNear ? near_log(a) : 0.f));
+        lo = fmaxf(lo, entry(e, j, a, FAM == kFamNear ? near_log(a) : 0.f));
       }
-      red_v[tid] = lo;
-      if (tid == 0) *surv_n = 0;
-      __syncthreads();
-      for (int w = kRsThreads / 2; w > 0; w >>= 1) {
-        if (tid < w) red_v[tid] = fmaxf(red_v[tid], red_v[tid + w]);
-        __syncthreads();
+      lo = wave_max_f(lo);
+      const float L = lo - (fabsf(lo) * 1e-6f + 1e-30f);  // slack for rounding of the bounded values
+      for (int base = 0; base < tot; base += 64) {
+        const int e = base + lane;
+        bool f = false;
+        int64_t j = -1;
+        if (e < tot) {
+          j = anchor_of(e);
+          if (j != o) {
+            const float a = fminf(1.0f, arow[j] + fmaf(qn, o_err[j], qe));
+            f = entry(e, j, a, FAM == kFamNear ? near_log(a) : 0.f) >= L;
+          }
+        }
+        uint64_t mask = __ballot(f);
+        while (mask) {
+          const int src = __ffsll((unsigned long long)mask) - 1;
+          mask &= mask - 1;
+          const int e2 = base + src;
+          const int64_t j2 = anchor_of(e2);
+          const float a = fmaxf(0.f, wave_dot(qrow, dn + j2 * ldk, ldk, lane));
+          take_max(entry(e2, j2, a, FAM == kFamNear ? near_log(a) : 0.f), j2, g.ids, best, bid);
+        }
       }
-      const float L = red_v[0] - (fabsf(red_v[0]) * 1e-6f + 1e-30f);
-      __syncthreads();
-      for (int e = tid; e < tot; e += kRsThreads) {
-        const int64_t j = e < M ? lidx[e] : sidx[e - M];
-        if (j == o) continue;
-        const float a = fminf(1.0f, arow[j] + fmaf(qn, o_err[j], qe));
-        if (entry(e, a, FAM == kFamNear ? near_log(a) : 0.f) >= L) surv[atomicAdd(surv_n, 1)] = e;
-      }
-      __syncthreads();
-      const int cnt = *surv_n;
-      for (int s = wave; s < cnt; s += kWaves) {
-        const int e = surv[s];
-        const int64_t j = e < M ? lidx[e] : sidx[e - M];
-        const float a = fmaxf(0.f, wave_dot(qrow, dn + j * ldk, ldk, lane));
-        take_max(entry(e, a, FAM == kFamNear ? near_log(a) : 0.f), j, ids, best, bid);
-      }
-      __syncthreads();
     }
-    red_v[tid] = best;
-    red_id[tid] = bid;
-    __syncthreads();
-    for (int w = kRsThreads / 2; w > 0; w >>= 1) {
-      if (tid < w && better(red_v[tid + w], red_id[tid + w], red_v[tid], red_id[tid])) {
-        red_v[tid] = red_v[tid + w];
-        red_id[tid] = red_id[tid + w];
-      }
-      __syncthreads();
-    }
-    const float sb = red_v[0];
-    const uint32_t sid = red_id[0];
-    __syncthreads();
-    if (sb > cert) {
-      out_best = sb;
-      out_bid = sid;
+    wave_argmax(best, bid);
+    if (best > sub.cert) {
+      out_best = best;
+      out_bid = bid;
       return;
     }
     fell_back = true;
@@ -157,195 +176,179 @@ __device__ void rescore_relation(const float* __restrict__ arow, const float* __
   }
   if (!bounded) {
     // FP32 similarities: the maximum directly, with the relational pass's arithmetic
-    for (int64_t j = tid; j < n; j += kRsThreads) {
+    for (int64_t j = lane; j < n; j += 64) {
       if (j == o) continue;
-      const float v =
-          pair_value<FAM>(t, anchor_record_pre(FAM, arow[j], FAM == kFamNear ? lrow[j] : 0.f, j, x, y, z, hhi, hlo), c);
-      take_max(v, j, ids, best, bid);
+      const float v = pair_value<FAM>(t, anchor_record(FAM, arow[j], j, g.x, g.y, g.z, g.hhi, g.hlo), c);
+      take_max(v, j, g.ids, best, bid);
     }
   } else {
-    // lower bound L of the best exact value, in the family's comparison domain
     float lo = value_floor<FAM>();
-    for (int64_t j = tid; j < n; j += kRsThreads) {
+    for (int64_t j = lane; j < n; j += 64) {
       if (j == o) continue;
       const float a = fmaxf(0.f, arow[j] - fmaf(qn, o_err[j], qe));
-      lo = fmaxf(lo, pair_value<FAM>(t, anchor_record(FAM, a, j, x, y, z, hhi, hlo), c));
+      lo = fmaxf(lo, pair_value<FAM>(t, anchor_record(FAM, a, j, g.x, g.y, g.z, g.hhi, g.hlo), c));
     }
-    red_v[tid] = lo;
-    __syncthreads();
-    for (int w = kRsThreads / 2; w > 0; w >>= 1) {
-      if (tid < w) red_v[tid] = fmaxf(red_v[tid], red_v[tid + w]);
-      __syncthreads();
-    }
-    const float L = red_v[0] - (fabsf(red_v[0]) * 1e-6f + 1e-30f);  // slack for rounding of the bounded values
-    __syncthreads();
-    for (int64_t w0 = 0; w0 < n; w0 += kWin) {
-      if (tid == 0) *surv_n = 0;
-      __syncthreads();
-      const int64_t w1 = w0 + kWin < n ? w0 + kWin : n;
-      for (int64_t j = w0 + tid; j < w1; j += kRsThreads) {
-        if (j == o) continue;
+    lo = wave_max_f(lo);
+    const float L = lo - (fabsf(lo) * 1e-6f + 1e-30f);
+    for (int64_t base = 0; base < n; base += 64) {
+      const int64_t j = base + lane;
+      bool f = false;
+      if (j < n && j != o) {
         const float a = fminf(1.0f, arow[j] + fmaf(qn, o_err[j], qe));
-        if (pair_value<FAM>(t, anchor_record(FAM, a, j, x, y, z, hhi, hlo), c) >= L)
-          surv[atomicAdd(surv_n, 1)] = (int32_t)j;
+        f = pair_value<FAM>(t, anchor_record(FAM, a, j, g.x, g.y, g.z, g.hhi, g.hlo), c) >= L;
       }
-      __syncthreads();
-      const int cnt = *surv_n;
-      for (int s = wave; s < cnt; s += kWaves) {
-        const int64_t j = surv[s];
-        const float a = fmaxf(0.f, wave_dot(qrow, dn + j * ldk, ldk, lane));
-        const float v = pair_value<FAM>(t, anchor_record(FAM, a, j, x, y, z, hhi, hlo), c);
-        take_max(v, j, ids, best, bid);
+      uint64_t mask = __ballot(f);
+      while (mask) {
+        const int src = __ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1;
+        const int64_t j2 = base + src;
+        const float a = fmaxf(0.f, wave_dot(qrow, dn + j2 * ldk, ldk, lane));
+        take_max(pair_value<FAM>(t, anchor_record(FAM, a, j2, g.x, g.y, g.z, g.hhi, g.hlo), c), j2, g.ids, best,
+                 bid);
       }
-      __syncthreads();
     }
   }
-  red_v[tid] = best;
-  red_id[tid] = bid;
-  __syncthreads();
-  for (int w = kRsThreads / 2; w > 0; w >>= 1) {
-    if (tid < w && better(red_v[tid + w], red_id[tid + w], red_v[tid], red_id[tid])) {
-      red_v[tid] = red_v[tid + w];
-      red_id[tid] = red_id[tid + w];
-    }
-    __syncthreads();
-  }
-  out_best = red_v[0];
-  out_bid = red_id[0];
-  __syncthreads();
+  wave_argmax(best, bid);
+  out_best = best;
+  out_bid = bid;
 }
 
-__global__ __launch_bounds__(kRsThreads) void k_rescore(
-    const float* __restrict__ sim, const float* __restrict__ lsim, int64_t ld_s, int32_t q, MetaView meta,
-    SimBound bound, const float* __restrict__ qn, const float* __restrict__ dn, int32_t ldk,
-    const int32_t* __restrict__ cand,
-    const int32_t* __restrict__ cand_count, int32_t C, const float* __restrict__ x, const float* __restrict__ y,
-    const float* __restrict__ z, const float* __restrict__ hhi, const float* __restrict__ hlo,
-    const uint32_t* __restrict__ ids, const int32_t* __restrict__ cls, int64_t n, float* __restrict__ rs_score,
+constexpr int kTermWaves = 4;       // waves per block
+constexpr int kTermBlocksX = 8;     // blocks per query: 32 waves sweep a query's terms
+
+// One wave per (candidate, relation) term.  Writes the family-domain maximum
+// (Near: log of the term; others: the term) into rs_terms and the bound
+// anchor into rs_anchor; k_rescore_combine turns them into scores.
+__global__ __launch_bounds__(64 * kTermWaves) void k_rescore_terms(
+    const float* __restrict__ sim, int64_t ld_s, int32_t q, MetaView meta, SimBound bound,
+    const float* __restrict__ qn, const float* __restrict__ dn, int32_t ldk, const int32_t* __restrict__ cand,
+    const int32_t* __restrict__ cand_count, int32_t C, Geo g, int64_t n,
     float* __restrict__ rs_terms, uint32_t* __restrict__ rs_anchor, PropView pv) {
-  __shared__ float red_v[kRsThreads];
-  __shared__ uint32_t red_id[kRsThreads];
-  __shared__ int32_t surv[kWin];
-  __shared__ int surv_n;
+  const int lane = threadIdx.x & 63;
   const int32_t qq = blockIdx.y;
-  const int tid = threadIdx.x;
-  const int r0 = meta.rel_off[qq], r1 = meta.rel_off[qq + 1], R = r1 - r0;
-  const int32_t cnt = cand_count ? cand_count[qq] : C;
+  const int r0 = meta.rel_off[qq], R = meta.rel_off[qq + 1] - r0;
+  if (R == 0) return;
+  const int32_t cnt = cand_count ? (cand_count[qq] < C ? cand_count[qq] : C) : C;
+  const int64_t terms = (int64_t)cnt * R;
+  const int stride = kTermBlocksX * kTermWaves;
   const bool bounded = bound.q_nrm != nullptr;
-  const float* qt = qn + (int64_t)qq * ldk;
+  const float err_max = bounded ? *bound.o_err_max : 0.f;
+  unsigned long long checked = 0, fell = 0;
+  for (int64_t tix = blockIdx.x * kTermWaves + (threadIdx.x >> 6); tix < terms; tix += stride) {
+    const int32_t cc = (int32_t)(tix / R);
+    const int e = (int)(tix % R);
+    const int64_t slot = (int64_t)qq * C + cc;
+    const int64_t o = cand[slot];
+    if (o < 0) continue;
+    const int r = r0 + e;
+    const int p = meta.rel_pred[r];
+    const float c = sigmoid_scale(p);
+    const float* arow = sim + (int64_t)(q + r) * ld_s;
+    const float* qrow = qn + (int64_t)(q + r) * ldk;
+    const float qnr = bounded ? bound.q_nrm[q + r] : 0.f;
+    const float qer = bounded ? bound.q_err[q + r] + bound.acc : 0.f;
+    Subset sub{nullptr, nullptr, 0, nullptr, 0, INFINITY};
+    if (pv.m > 0) {
+      const int64_t off = ((int64_t)p * n + o) * pv.m;
+      sub.lidx = pv.idx + off;
+      sub.lval = pv.val + off;
+      sub.M = pv.m;
+      sub.sidx = pv.sem_idx + (int64_t)r * kSemMax;
+      sub.sn = pv.sem_cnt[r];
+      const float pout = pv.out[(int64_t)p * n + o];
+      // every anchor outside the subset has similarity <= a_hi and predicate value <= pout
+      const float a_hi = bounded ? pv.sem_tau[r] + fmaf(qnr, err_max, qer) : pv.sem_tau[r];
+      if (family_of(p) == kFamNear) {
+        const float b = near_log(a_hi) + pout;
+        sub.cert = b + fabsf(b) * 1e-6f;  // covers the rounding of the logarithm
+      } else {
+        sub.cert = a_hi * pout;
+      }
+    }
+    float best;
+    uint32_t bid;
+    bool fb;
+    switch (family_of(p)) {
+      case kFamNear:
+        term_wave<kFamNear>(arow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, g, sub, lane, best,
+                            bid, fb);
+        break;
+      case kFamVert:
+        term_wave<kFamVert>(arow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, g, sub, lane, best,
+                            bid, fb);
+        break;
+      default:
+        term_wave<kFamLat>(arow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, g, sub, lane, best,
+                           bid, fb);
+        break;
+    }
+    if (lane == 0) {
+      rs_terms[slot * kMaxRel + e] = best;
+      rs_anchor[slot * kMaxRel + e] = bid;
+    }
+    checked += 1;
+    fell += fb ? 1 : 0;
+  }
+  if (pv.stats && lane == 0 && checked) {
+    atomicAdd(&pv.stats[0], checked);
+    if (fell) atomicAdd(&pv.stats[1], fell);
+  }
+}
+
+// Composite score of every candidate from its family-domain maxima: one wave
+// per candidate.  The target similarity is the FP32 GEMM's value, or an FP32
+// dot product when the similarity matrix is reduced-precision.  Terms become
+// linear; slots past the query's R get 0 and FARM_NO_ID.
+__global__ __launch_bounds__(256) void k_rescore_combine(
+    const float* __restrict__ sim, int64_t ld_s, int32_t q, MetaView meta, SimBound bound, const float* __restrict__ qn,
+    const float* __restrict__ dn, int32_t ldk, const int32_t* __restrict__ cand, const int32_t* __restrict__ cand_count,
+    int32_t C, const int32_t* __restrict__ cls, float* __restrict__ rs_score, float* __restrict__ rs_terms,
+    uint32_t* __restrict__ rs_anchor) {
+  const int lane = threadIdx.x & 63;
+  const int32_t qq = blockIdx.y;
+  const int32_t cnt = cand_count ? (cand_count[qq] < C ? cand_count[qq] : C) : C;
+  const int r0 = meta.rel_off[qq], R = meta.rel_off[qq + 1] - r0;
+  const bool bounded = bound.q_nrm != nullptr;
   const int tc = meta.tcls[qq];
-  for (int32_t cc = blockIdx.x; cc < cnt; cc += gridDim.x) {
+  for (int32_t cc = blockIdx.x * 4 + (threadIdx.x >> 6); cc < cnt; cc += gridDim.x * 4) {
     const int64_t slot = (int64_t)qq * C + cc;
     const int64_t o = cand[slot];
     if (o < 0) {
-      if (tid == 0) rs_score[slot] = -INFINITY;
-      if (tid < kMaxRel) {
-        rs_terms[slot * kMaxRel + tid] = 0.f;
-        rs_anchor[slot * kMaxRel + tid] = FARM_NO_ID;
+      if (lane == 0) rs_score[slot] = -INFINITY;
+      if (lane < kMaxRel) {
+        rs_terms[slot * kMaxRel + lane] = 0.f;
+        rs_anchor[slot * kMaxRel + lane] = FARM_NO_ID;
       }
       continue;
     }
-    // target similarity: the FP32 GEMM's value, or an FP32 dot product when the
-    // similarity matrix is reduced-precision
     float sem;
     if (!bounded) {
       sem = sim[(int64_t)qq * ld_s + o];
     } else {
-      const float* dr = dn + o * ldk;
-      float part = 0.f;
-      for (int k = tid; k < ldk; k += kRsThreads) part = fmaf(qt[k], dr[k], part);
-      red_v[tid] = part;
-      __syncthreads();
-      for (int w = kRsThreads / 2; w > 0; w >>= 1) {
-        if (tid < w) red_v[tid] += red_v[tid + w];
-        __syncthreads();
-      }
-      const float dot = red_v[0];
-      __syncthreads();
+      const float dot = wave_dot(qn + (int64_t)qq * ldk, dn + o * ldk, ldk, lane);
       const float kappa = (tc >= 0 && cls && cls[o] >= 0 && cls[o] != tc) ? kClassFactor : 1.0f;
       sem = kappa * fmaxf(0.f, dot);
     }
-    float lsum = 0.f;
-    for (int e = 0; e < R; ++e) {
-      const int r = r0 + e;
-      const int p = meta.rel_pred[r];
-      const float c = sigmoid_scale(p);
-      const float* arow = sim + (int64_t)(q + r) * ld_s;
-      const float* lrow = lsim + (int64_t)r * ld_s;
-      const float* qrow = qn + (int64_t)(q + r) * ldk;
-      const float qnr = bounded ? bound.q_nrm[q + r] : 0.f;
-      const float qer = bounded ? bound.q_err[q + r] + bound.acc : 0.f;
-      float best;
-      uint32_t bid;
-      float term;
-      bool fell_back;
-      // proposal subset of this (relation, candidate) and the bound on every anchor outside it
-      const int32_t* lidx = nullptr;
-      const float* lval = nullptr;
-      const int32_t* sidx = nullptr;
-      int sn = 0;
-      float cert = INFINITY;
-      if (pv.m > 0) {
-        const int64_t lo_ = ((int64_t)p * n + o) * pv.m;
-        lidx = pv.idx + lo_;
-        lval = pv.val + lo_;
-        sidx = pv.sem_idx + (int64_t)r * kSemMax;
-        sn = pv.sem_cnt[r];
-        const float pout = pv.out[(int64_t)p * n + o];
-        const bool near = family_of(p) == kFamNear;
-        if (!bounded) {
-          cert = near ? pv.sem_ltau[r] + pout : pv.sem_tau[r] * pout;
+    if (lane == 0) {
+      float lsum = 0.f;
+      for (int e = 0; e < R; ++e) {
+        const float v = rs_terms[slot * kMaxRel + e];
+        if (family_of(meta.rel_pred[r0 + e]) == kFamNear) {
+          lsum += v;
+          rs_terms[slot * kMaxRel + e] = term_of<kFamNear>(v);
         } else {
-          const float a_hi = pv.sem_tau[r] + fmaf(qnr, *bound.o_err_max, qer);
-          if (near) {
-            const float b = near_log(a_hi) + pout;
-            cert = b + fabsf(b) * 1e-6f;  // covers the rounding of the logarithm
-          } else {
-            cert = a_hi * pout;
-          }
+          const float term = term_of<kFamVert>(v);
+          lsum += logf(term);
+          rs_terms[slot * kMaxRel + e] = term;
         }
       }
-      switch (family_of(p)) {
-        case kFamNear:
-          rescore_relation<kFamNear>(arow, lrow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, x, y, z, hhi,
-                                     hlo, ids, red_v, red_id, surv, &surv_n, lidx, lval, pv.m, sidx, sn, cert, best, bid,
-                                     fell_back);
-          term = term_of<kFamNear>(best);
-          lsum += best;
-          break;
-        case kFamVert:
-          rescore_relation<kFamVert>(arow, lrow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, x, y, z, hhi,
-                                     hlo, ids, red_v, red_id, surv, &surv_n, lidx, lval, pv.m, sidx, sn, cert, best, bid,
-                                     fell_back);
-          term = term_of<kFamVert>(best);
-          lsum += logf(term);
-          break;
-        default:
-          rescore_relation<kFamLat>(arow, lrow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, x, y, z, hhi,
-                                    hlo, ids, red_v, red_id, surv, &surv_n, lidx, lval, pv.m, sidx, sn, cert, best, bid,
-                                     fell_back);
-          term = term_of<kFamLat>(best);
-          lsum += logf(term);
-          break;
-      }
-      if (tid == 0) {
-        rs_terms[slot * kMaxRel + e] = term;
-        rs_anchor[slot * kMaxRel + e] = bid;
-        if (pv.stats) {
-          atomicAdd(&pv.stats[0], 1ull);
-          if (fell_back) atomicAdd(&pv.stats[1], 1ull);
-        }
+      const float gm = R > 0 ? expf(lsum / (float)R) : 1.0f;
+      rs_score[slot] = sem * ((1.0f - kW) + kW * gm);
+      for (int e = R; e < kMaxRel; ++e) {
+        rs_terms[slot * kMaxRel + e] = 0.f;
+        rs_anchor[slot * kMaxRel + e] = FARM_NO_ID;
       }
     }
-    if (tid == 0) {
-      const float g = R > 0 ? expf(lsum / (float)R) : 1.0f;
-      rs_score[slot] = sem * ((1.0f - kW) + kW * g);
-    }
-    if (tid >= R && tid < kMaxRel) {
-      rs_terms[slot * kMaxRel + tid] = 0.f;
-      rs_anchor[slot * kMaxRel + tid] = FARM_NO_ID;
-    }
-    __syncthreads();
   }
 }
 
@@ -426,15 +429,19 @@ __global__ __launch_bounds__(256) void k_max_reduce(const float* __restrict__ v,
 
 }  // namespace
 
-hipError_t launch_rescore(const farm_memory* mem, const farm_workspace* ws, const float* sim, const float* lsim,
-                          int64_t ld_s, int32_t q, MetaView meta, const SimBound& bound, const int32_t* cand,
-                          const int32_t* cand_count, int32_t c, const PropView& prop, hipStream_t s) {
+hipError_t launch_rescore(const farm_memory* mem, const farm_workspace* ws, const float* sim, int64_t ld_s, int32_t q,
+                          MetaView meta, const SimBound& bound, const int32_t* cand, const int32_t* cand_count,
+                          int32_t c, const PropView& prop, hipStream_t s) {
   if (q <= 0 || c <= 0) return hipSuccess;
-  // with a device-side count the candidate slots are swept by a fixed number of blocks per query
-  const unsigned gx = cand_count ? (unsigned)(c < 64 ? c : 64) : (unsigned)c;
-  hipLaunchKernelGGL(k_rescore, dim3(gx, (unsigned)q), dim3(kRsThreads), 0, s, sim, lsim, ld_s, q, meta, bound, ws->qn,
-                     mem->dn, mem->ldk, cand, cand_count, c, mem->x, mem->y, mem->z, mem->hr_hi, mem->hr_lo, mem->id,
-                     mem->cls, mem->n, ws->rs_score, ws->rs_terms, ws->rs_anchor, prop);
+  const Geo g{mem->x, mem->y, mem->z, mem->hr_hi, mem->hr_lo, mem->id};
+  hipLaunchKernelGGL(k_rescore_terms, dim3(kTermBlocksX, (unsigned)q), dim3(64 * kTermWaves), 0, s, sim, ld_s, q,
+                     meta, bound, ws->qn, mem->dn, mem->ldk, cand, cand_count, c, g, mem->n, ws->rs_terms,
+                     ws->rs_anchor, prop);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const unsigned gx = (unsigned)((c + 3) / 4 < 16 ? (c + 3) / 4 : 16);
+  hipLaunchKernelGGL(k_rescore_combine, dim3(gx, (unsigned)q), dim3(256), 0, s, sim, ld_s, q, meta, bound, ws->qn,
+                     mem->dn, mem->ldk, cand, cand_count, c, mem->cls, ws->rs_score, ws->rs_terms, ws->rs_anchor);
   return hipGetLastError();
 }
 
