@@ -302,7 +302,7 @@ FARM_API farm_status farm_mlp_step(farm_mlp* mlp, const farm_memory* mem, int32_
  * Memory: n * M * 5 * 8 bytes + 5 n * 4 bytes, plus transient chunk buffers
  * (up to 4 GiB for very large n).  Synchronises `stream`.
  * Errors: INVALID_ARG (null, width/device mismatch, M out of range),
- * UNSUPPORTED (n > 2^19), OOM, HIP.
+ * UNSUPPORTED (n > 500,000), OOM, HIP.
  */
 FARM_API farm_status farm_build_proposals(farm_memory* mem, farm_mlp* mlp, int32_t M, void* stream);
 

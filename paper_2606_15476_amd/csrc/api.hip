@@ -92,7 +92,7 @@ size_t workspace_bytes_for(const farm_memory* mem, int32_t max_q, int32_t max_re
   b += (size_t)max_q * cap * (sizeof(int32_t) + sizeof(float) + kMaxRel * (sizeof(float) + sizeof(uint32_t)));
   b += (size_t)max_q * sizeof(int32_t);
   const size_t rel1 = (size_t)(max_rel > 0 ? max_rel : 1);
-  b += rel1 * (kSemMax * sizeof(int32_t) + sizeof(int32_t) + sizeof(float));  // semantic sets
+  b += rel1 * (kSemMax * (sizeof(int32_t) + sizeof(float)) + sizeof(int32_t) + sizeof(float));  // semantic sets
   b += 2 * sizeof(unsigned long long);
   return b;
 }
@@ -456,6 +456,7 @@ farm_status farm_workspace_create(const farm_memory* mem, int32_t max_q, int32_t
     if ((st = dalloc(ws->allocs, ws->bytes, &ws->sem_idx, rel1 * kSemMax, "semantic sets")) ||
         (st = dalloc(ws->allocs, ws->bytes, &ws->sem_cnt, rel1, "semantic set sizes")) ||
         (st = dalloc(ws->allocs, ws->bytes, &ws->sem_tau, rel1, "semantic bounds")) ||
+        (st = dalloc(ws->allocs, ws->bytes, &ws->sem_sim, rel1 * kSemMax, "semantic similarities")) ||
         (st = dalloc(ws->allocs, ws->bytes, &ws->prop_stats, 2, "proposal counters")))
       return fail(st);
     hipError_t e = hipHostMalloc((void**)&ws->h_meta, (size_t)ws->meta_len * sizeof(int32_t), hipHostMallocDefault);
@@ -667,6 +668,7 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
         PhaseTimer t(ws, s, FARM_PHASE_PROPOSE);
         FARM_HIP(launch_semantic_sets(ws->sim, ws->ld_s, q, R, mem->n, ws->sem_idx, ws->sem_cnt, ws->sem_tau, s),
                  "semantic sets");
+        if (dtype != FARM_F32) FARM_HIP(launch_semantic_exact(mem, ws, q, R, s), "semantic similarities");
         pv.m = mem->prop_m;
         pv.idx = mem->prop_idx;
         pv.val = mem->prop_val;
@@ -674,6 +676,7 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
         pv.sem_idx = ws->sem_idx;
         pv.sem_cnt = ws->sem_cnt;
         pv.sem_tau = ws->sem_tau;
+        pv.sem_sim = dtype != FARM_F32 ? ws->sem_sim : nullptr;
         pv.stats = ws->prop_stats;
       }
       PhaseTimer t(ws, s, FARM_PHASE_RESCORE);

@@ -113,6 +113,7 @@ struct farm_workspace {
   int32_t* sem_idx = nullptr;    // [max_rel][kSemMax]
   int32_t* sem_cnt = nullptr;    // [max_rel]
   float* sem_tau = nullptr;      // [max_rel] largest similarity of an anchor outside the set
+  float* sem_sim = nullptr;      // [max_rel][kSemMax] FP32 similarity of each set member (reduced precision)
   unsigned long long* prop_stats = nullptr;  // [2] (candidate, relation) pairs checked, pairs that fell back
   // optional phase timer: pending (start, stop) event pairs per phase
   bool timing = false;
@@ -208,6 +209,7 @@ struct PropView {
   const int32_t* sem_idx = nullptr;  // [R][kSemMax]
   const int32_t* sem_cnt = nullptr;  // [R]
   const float* sem_tau = nullptr;    // [R]
+  const float* sem_sim = nullptr;    // [R][kSemMax] exact similarities of the set, or null (FP32 matrix)
   unsigned long long* stats = nullptr;
 };
 
@@ -304,6 +306,10 @@ hipError_t launch_rescore_select(const farm_workspace* ws, int32_t q, int32_t c,
                                  uint32_t* out_id, float* out_score, float* out_terms, uint32_t* out_anchor_id,
                                  int32_t* certified, hipStream_t s);
 hipError_t launch_max_reduce(const float* v, int64_t n, float* out, hipStream_t s);
+// FP32 similarity max(0, q.d) of every semantic-set member (reduced-precision
+// matrices), with the rescoring kernel's own dot product so that the values
+// are the ones a full scan would compute.
+hipError_t launch_semantic_exact(const farm_memory* mem, const farm_workspace* ws, int32_t q, int32_t R, hipStream_t s);
 
 // ---- proposal.hip
 // Per relation row: a semantic anchor set (at most kSemMax anchors with the

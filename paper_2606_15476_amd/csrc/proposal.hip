@@ -242,7 +242,8 @@ extern "C" farm_status farm_build_proposals(farm_memory* mem, farm_mlp* mlp, int
     if (mlp->d != mem->d) { set_error("network width %d != memory width %d", mlp->d, mem->d); return FARM_ERR_INVALID_ARG; }
     if (M < 1 || M > FARM_MAX_K) { set_error("M = %d outside [1, %d]", M, FARM_MAX_K); return FARM_ERR_INVALID_ARG; }
     const int64_t n = mem->n;
-    if (n > ((int64_t)1 << 19)) { set_error("proposal tables need n <= 2^19"); return FARM_ERR_UNSUPPORTED; }
+    // the per-target bitmap of listed anchors lives in LDS (n / 8 bytes, at most 62.5 KiB)
+    if (n > 500000) { set_error("proposal tables need n <= 500000"); return FARM_ERR_UNSUPPORTED; }
     hipStream_t s = (hipStream_t)stream;
     const int64_t H = FARM_MLP_HIDDEN;
     DeviceGuard guard(mem->device);

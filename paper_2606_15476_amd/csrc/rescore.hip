@@ -103,7 +103,8 @@ struct Subset {
   int M;
   const int32_t* sidx;
   int sn;
-  float cert;  // bound on the value of every anchor outside the subset (family domain)
+  const float* ssim;  // exact similarities of the semantic set (reduced precision), or null
+  float cert;         // bound on the value of every anchor outside the subset (family domain)
 };
 
 // One relation term of target o, computed by one wave.  Returns the
@@ -133,8 +134,16 @@ __device__ void term_wave(const float* __restrict__ arow, const float* __restric
         take_max(entry(e, j, a, FAM == kFamNear ? near_log(a) : 0.f), j, g.ids, best, bid);
       }
     } else {
-      float lo = value_floor<FAM>();
-      for (int e = lane; e < tot; e += 64) {
+      // semantic-set members carry their exact similarity: exact values at once
+      for (int e = sub.M + lane; e < tot; e += 64) {
+        const int64_t j = anchor_of(e);
+        if (j == o) continue;
+        const float a = sub.ssim[e - sub.M];
+        take_max(entry(e, j, a, FAM == kFamNear ? near_log(a) : 0.f), j, g.ids, best, bid);
+      }
+      // list entries: bounds from the reduced-precision similarity
+      float lo = best;
+      for (int e = lane; e < sub.M; e += 64) {
         const int64_t j = anchor_of(e);
         if (j == o) continue;
         const float a = fmaxf(0.f, arow[j] - fmaf(qn, o_err[j], qe));
@@ -142,11 +151,11 @@ __device__ void term_wave(const float* __restrict__ arow, const float* __restric
       }
       lo = wave_max_f(lo);
       const float L = lo - (fabsf(lo) * 1e-6f + 1e-30f);  // slack for rounding of the bounded values
-      for (int base = 0; base < tot; base += 64) {
+      for (int base = 0; base < sub.M; base += 64) {
         const int e = base + lane;
         bool f = false;
         int64_t j = -1;
-        if (e < tot) {
+        if (e < sub.M) {
           j = anchor_of(e);
           if (j != o) {
             const float a = fminf(1.0f, arow[j] + fmaf(qn, o_err[j], qe));
@@ -247,7 +256,7 @@ __global__ __launch_bounds__(64 * kTermWaves) void k_rescore_terms(
     const float* qrow = qn + (int64_t)(q + r) * ldk;
     const float qnr = bounded ? bound.q_nrm[q + r] : 0.f;
     const float qer = bounded ? bound.q_err[q + r] + bound.acc : 0.f;
-    Subset sub{nullptr, nullptr, 0, nullptr, 0, INFINITY};
+    Subset sub{nullptr, nullptr, 0, nullptr, 0, nullptr, INFINITY};
     if (pv.m > 0) {
       const int64_t off = ((int64_t)p * n + o) * pv.m;
       sub.lidx = pv.idx + off;
@@ -255,6 +264,7 @@ __global__ __launch_bounds__(64 * kTermWaves) void k_rescore_terms(
       sub.M = pv.m;
       sub.sidx = pv.sem_idx + (int64_t)r * kSemMax;
       sub.sn = pv.sem_cnt[r];
+      sub.ssim = pv.sem_sim ? pv.sem_sim + (int64_t)r * kSemMax : nullptr;
       const float pout = pv.out[(int64_t)p * n + o];
       // every anchor outside the subset has similarity <= a_hi and predicate value <= pout
       const float a_hi = bounded ? pv.sem_tau[r] + fmaf(qnr, err_max, qer) : pv.sem_tau[r];
@@ -414,6 +424,21 @@ __global__ __launch_bounds__(256) void k_rescore_select(const float* __restrict_
   }
 }
 
+// One wave per (relation, semantic-set member): max(0, FP32 dot).
+__global__ __launch_bounds__(256) void k_semantic_exact(const float* __restrict__ qn, const float* __restrict__ dn,
+                                                        int32_t ldk, int32_t q, int32_t R,
+                                                        const int32_t* __restrict__ sem_idx,
+                                                        const int32_t* __restrict__ sem_cnt,
+                                                        float* __restrict__ sem_sim) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int32_t r = (int32_t)(w / kSemMax), e = (int32_t)(w % kSemMax);
+  if (r >= R || e >= sem_cnt[r]) return;  // whole waves leave
+  const int64_t j = sem_idx[(int64_t)r * kSemMax + e];
+  const float a = fmaxf(0.f, wave_dot(qn + (int64_t)(q + r) * ldk, dn + j * ldk, ldk, lane));
+  if (lane == 0) sem_sim[(int64_t)r * kSemMax + e] = a;
+}
+
 __global__ __launch_bounds__(256) void k_max_reduce(const float* __restrict__ v, int64_t n, float* __restrict__ out) {
   __shared__ float red[256];
   float m = 0.f;
@@ -454,6 +479,15 @@ hipError_t launch_rescore_select(const farm_workspace* ws, int32_t q, int32_t c,
   hipLaunchKernelGGL(k_rescore_select, dim3((unsigned)q), dim3(256), 0, s, ws->rs_score, ws->rs_idx, ws->rs_terms,
                      ws->rs_anchor, ws->mem->id, c, k, hi_key, hi_idx, cand_count, n, out_id, out_score, out_terms,
                      out_anchor_id, certified);
+  return hipGetLastError();
+}
+
+hipError_t launch_semantic_exact(const farm_memory* mem, const farm_workspace* ws, int32_t q, int32_t R,
+                                 hipStream_t s) {
+  if (R <= 0) return hipSuccess;
+  const int64_t waves = (int64_t)R * kSemMax;
+  hipLaunchKernelGGL(k_semantic_exact, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, ws->qn, mem->dn, mem->ldk, q,
+                     R, ws->sem_idx, ws->sem_cnt, ws->sem_sim);
   return hipGetLastError();
 }
 
