@@ -1,18 +1,24 @@
 """Benchmark of the relational retrieval hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload precision] [--form f32]
-                    [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload precision]
+                    [--form bf16|f32|fp8] [--method proposal|bounded|exhaustive]
+                    [--no-cpu-baseline] [--serving]
 
-One step = one pass of the whole hot path over one batch resident in HBM:
-query normalisation, similarity GEMM, relational pass (relation terms +
-composite), TopK and the ScoredCandidate breakdown of the winners
-(farm_query_topk), for the 4,096-query batch of the N = 20,000 scene.  The
-scene is built once (farm_build_memory) outside the timed region.
+One step = one farm_query_topk call over the 4,096-query batch of the
+N = 20,000 scene, inputs resident in HBM: query normalisation, similarity GEMM,
+TopK candidates, relation terms, composite scores, TopK and the
+ScoredCandidate breakdown of the winners.  Default form: BF16 similarity GEMM
+with the exact bound-pruned TopK whose candidates are scored over the learned
+anchor lists (certified, full-scan fallback).  The scene is built once
+(farm_build_memory), and the proposal network is trained on training scenes of
+the same generator and its lists built (farm_build_proposals), all outside the
+timed region.
 
 Prints ONE JSON line with the throughput (queries/s), batch latency
 percentiles, the roofline of the dominant kernel (timed live with the
 library's HIP-event phase timer on the launch stream) and the CPU oracle
-timed on a bounded sample of the same workload.
+timed on a bounded sample of the same workload.  --serving instead runs the
+request loop over 16 resident scenes and prints p50/p99 latency per rate.
 """
 from __future__ import annotations
 
@@ -67,9 +73,9 @@ def parse():
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="precision")
-    p.add_argument("--form", default="f32", choices=["f32", "bf16", "fp8"])
+    p.add_argument("--form", default="bf16", choices=["f32", "bf16", "fp8"])
     p.add_argument("--rescore-mult", type=int, default=4)
-    p.add_argument("--method", default="exhaustive", choices=["exhaustive", "bounded", "proposal"])
+    p.add_argument("--method", default="proposal", choices=["exhaustive", "bounded", "proposal"])
     p.add_argument("--train-scenes", type=int, default=8, help="training scenes of the proposal network")
     p.add_argument("--train-steps", type=int, default=600)
     p.add_argument("--list-m", type=int, default=256, help="anchors per (object, predicate) list")
@@ -167,9 +173,11 @@ def main():
     ws.set_timing(False)
     ws.status()
     if proposal_info is not None:
-        checked, fell = ws.proposal_stats(reset=True)
+        checked, fell, dots, fb_dots = ws.proposal_stats(reset=True)
         proposal_info["terms_per_step"] = checked // max(args.steps, 1)
         proposal_info["fallback_rate"] = round(fell / max(checked, 1), 5)
+        proposal_info["fp32_dots_per_step"] = dots // max(args.steps, 1)
+        proposal_info["fallback_fp32_dots_per_step"] = fb_dots // max(args.steps, 1)
         log(f"[bench] proposal terms {checked}, fell back {fell}")
 
     certified = int((cert.cpu().numpy() == 1).sum())
@@ -361,16 +369,33 @@ def dominant_roofline(phases, scene, qb, args, cfg, proposal_info):
         return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                 "traffic": recorded_traffic(kernel, cfg.name), "avg_launch_ms": round(avg_s * 1e3, 3)}
-    # rescoring / proposal pass: list entries (4 B index + 4 B cached value) and
-    # the gathered 4 B similarity of each entry, per evaluated term
-    terms = (proposal_info or {}).get("terms_per_step", 0)
-    m = (proposal_info or {}).get("list_m", 0)
-    nbytes = float(terms) * (m + 64) * 12.0
-    achieved = nbytes / avg_s / 1e9
-    return {"bound": "hbm", "kernel": "k_rescore", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-            "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-            "traffic": recorded_traffic("k_rescore", cfg.name), "avg_launch_ms": round(avg_s * 1e3, 3),
-            "phase": dominant}
+    if dominant == "propose":
+        # semantic sets: each relation similarity row read once (4 B per anchor)
+        nbytes = 4.0 * R * n
+        achieved = nbytes / avg_s / 1e9
+        return {"bound": "hbm", "kernel": "k_semantic_sets", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": recorded_traffic("k_semantic_sets", cfg.name), "avg_launch_ms": round(avg_s * 1e3, 3)}
+    info = proposal_info or {}
+    terms, m, dots = info.get("terms_per_step", 0), info.get("list_m", 0), info.get("fp32_dots_per_step", 0)
+    if dominant == "rescore" and info:
+        # proposal terms: per term the list (4 B index + 4 B cached value + 4 B gathered
+        # similarity per entry) and the semantic set (4 B index + 4 B similarity per
+        # member, at most 64); per FP32 dot product one descriptor row (4 B x D)
+        nbytes = float(terms) * (m * 12.0 + 64 * 8.0) + float(dots) * 4.0 * scene.d
+        achieved = nbytes / avg_s / 1e9
+        return {"bound": "hbm", "kernel": "k_rescore_terms<subset>", "achieved": round(achieved, 1),
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": recorded_traffic("k_rescore_terms", cfg.name), "avg_launch_ms": round(avg_s * 1e3, 3),
+                "algorithmic_bytes_per_launch": nbytes}
+    # full anchor scans of candidate terms: pair evaluations on the ALU
+    per_pair = float(np.mean([FLOP_PER_PAIR[int(p)] for p in qb.rel_pred])) if R else 0.0
+    n_terms = float(info.get("fallback_rate", 0.0) * terms) if dominant == "fallback" else float("nan")
+    flop = n_terms * n * per_pair
+    achieved = flop / avg_s / 1e12
+    return {"bound": "alu", "kernel": f"k_rescore_terms ({dominant})", "achieved": round(achieved, 3),
+            "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
+            "traffic": None, "avg_launch_ms": round(avg_s * 1e3, 3)}
 
 
 def form_name(args):

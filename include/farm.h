@@ -219,10 +219,12 @@ typedef enum {
   FARM_PHASE_GEMM = 1,      /* similarity GEMM */
   FARM_PHASE_PAIR = 2,      /* relational pass (relation terms + composite) */
   FARM_PHASE_TOPK = 3,      /* TopK selection */
-  FARM_PHASE_RESCORE = 4,   /* reduced-precision candidates rescored in FP32 */
+  FARM_PHASE_RESCORE = 4,   /* candidate relation terms (one kernel) */
   FARM_PHASE_EXPLAIN = 5,   /* ScoredCandidate breakdown of the winners */
   FARM_PHASE_PROPOSE = 6,   /* semantic anchor sets of the proposal method */
-  FARM_PHASE_COUNT = 7
+  FARM_PHASE_FALLBACK = 7,  /* full anchor scans of the terms the proposals could not certify */
+  FARM_PHASE_SELECT = 8,    /* candidate composite scores and final TopK */
+  FARM_PHASE_COUNT = 9
 } farm_phase;
 
 /*
@@ -317,9 +319,12 @@ FARM_API farm_status farm_get_proposals(const farm_memory* mem, int32_t* m_out, 
                                         void* stream);
 
 /*
- * Proposal certificate counters of a workspace since the last reset:
+ * Candidate-scoring counters of a workspace since the last reset (host [4]):
  * stats[0] = (candidate, relation) terms evaluated by FARM_METHOD_PROPOSAL,
- * stats[1] = those that fell back to the scan over all anchors.
+ * stats[1] = those that fell back to the scan over all anchors,
+ * stats[2], stats[3] = FP32 dot products taken, in the proposal pass and in
+ *            the fallback scans, for anchors whose reduced-precision bound
+ *            could not be resolved.
  * Synchronises `stream`; reset != 0 clears the counters afterwards.
  */
 FARM_API farm_status farm_workspace_proposal_stats(farm_workspace* ws, int64_t* stats, int32_t reset, void* stream);

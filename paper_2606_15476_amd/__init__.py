@@ -134,10 +134,11 @@ class Workspace:
         _lib.check(_lib.L.farm_workspace_status(self.handle, _stream(stream)))
 
     def proposal_stats(self, reset: bool = False, stream=None) -> tuple:
-        """(terms evaluated, terms that fell back to the full anchor scan) of method PROPOSAL."""
-        out = (ctypes.c_int64 * 2)()
+        """(terms evaluated, terms that fell back to the full anchor scan, FP32 dot products in the
+        proposal pass, FP32 dot products in the fallback scans) under method PROPOSAL."""
+        out = (ctypes.c_int64 * 4)()
         _lib.check(_lib.L.farm_workspace_proposal_stats(self.handle, out, 1 if reset else 0, _stream(stream)))
-        return int(out[0]), int(out[1])
+        return tuple(int(v) for v in out)
 
     def close(self):
         if getattr(self, "_h", None) is not None:

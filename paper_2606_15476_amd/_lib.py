@@ -28,7 +28,7 @@ EXPORTS = (
     "farm_server_poll", "farm_server_stats", "farm_server_free",
 )
 MLP_HIDDEN = 256
-PHASES = ("normalize", "gemm", "pair", "topk", "rescore", "explain", "propose")
+PHASES = ("normalize", "gemm", "pair", "topk", "rescore", "explain", "propose", "fallback", "select")
 
 _STATUS = {FARM_ERR_INVALID_ARG: "invalid argument", FARM_ERR_OOM: "out of memory", FARM_ERR_HIP: "HIP error",
            FARM_ERR_UNSUPPORTED: "unsupported"}

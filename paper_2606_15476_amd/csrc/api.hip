@@ -93,7 +93,8 @@ size_t workspace_bytes_for(const farm_memory* mem, int32_t max_q, int32_t max_re
   b += (size_t)max_q * sizeof(int32_t);
   const size_t rel1 = (size_t)(max_rel > 0 ? max_rel : 1);
   b += rel1 * (kSemMax * (sizeof(int32_t) + sizeof(float)) + sizeof(int32_t) + sizeof(float));  // semantic sets
-  b += 2 * sizeof(unsigned long long);
+  b += 4 * sizeof(unsigned long long);
+  b += (size_t)fallback_cap(max_q) * sizeof(unsigned long long) + sizeof(uint32_t);  // fallback worklist
   return b;
 }
 
@@ -457,15 +458,18 @@ farm_status farm_workspace_create(const farm_memory* mem, int32_t max_q, int32_t
         (st = dalloc(ws->allocs, ws->bytes, &ws->sem_cnt, rel1, "semantic set sizes")) ||
         (st = dalloc(ws->allocs, ws->bytes, &ws->sem_tau, rel1, "semantic bounds")) ||
         (st = dalloc(ws->allocs, ws->bytes, &ws->sem_sim, rel1 * kSemMax, "semantic similarities")) ||
-        (st = dalloc(ws->allocs, ws->bytes, &ws->prop_stats, 2, "proposal counters")))
+        (st = dalloc(ws->allocs, ws->bytes, &ws->prop_stats, 4, "proposal counters")) ||
+        (st = dalloc(ws->allocs, ws->bytes, &ws->fb_list, (size_t)fallback_cap(max_q), "fallback worklist")) ||
+        (st = dalloc(ws->allocs, ws->bytes, &ws->fb_count, 1, "fallback count")))
       return fail(st);
+    ws->fb_cap = fallback_cap(max_q);
     hipError_t e = hipHostMalloc((void**)&ws->h_meta, (size_t)ws->meta_len * sizeof(int32_t), hipHostMallocDefault);
     if (e != hipSuccess) { ws->h_meta = nullptr; return fail(hip_fail(e, "pinned metadata staging")); }
     e = hipEventCreateWithFlags(&ws->meta_done, hipEventDisableTiming);
     if (e != hipSuccess) { ws->meta_done = nullptr; return fail(hip_fail(e, "event")); }
     e = hipMemset(ws->status, 0, sizeof(int));
     if (e != hipSuccess) return fail(hip_fail(e, "status clear"));
-    e = hipMemset(ws->prop_stats, 0, 2 * sizeof(unsigned long long));
+    e = hipMemset(ws->prop_stats, 0, 4 * sizeof(unsigned long long));
     if (e != hipSuccess) return fail(hip_fail(e, "counter clear"));
     *out = ws;
     return FARM_OK;
@@ -531,11 +535,10 @@ farm_status farm_workspace_proposal_stats(farm_workspace* ws, int64_t* stats, in
   if (!ws || !stats) { set_error("null workspace or output"); return FARM_ERR_INVALID_ARG; }
   DeviceGuard g(ws->device);
   hipStream_t s = (hipStream_t)stream;
-  unsigned long long h[2] = {0, 0};
+  unsigned long long h[4] = {0, 0, 0, 0};
   FARM_HIP(hipMemcpyAsync(h, ws->prop_stats, sizeof(h), hipMemcpyDeviceToHost, s), "read counters");
   FARM_HIP(hipStreamSynchronize(s), "counter synchronize");
-  stats[0] = (int64_t)h[0];
-  stats[1] = (int64_t)h[1];
+  for (int i = 0; i < 4; ++i) stats[i] = (int64_t)h[i];
   if (reset) {
     FARM_HIP(hipMemsetAsync(ws->prop_stats, 0, sizeof(h), s), "counter clear");
     FARM_HIP(hipStreamSynchronize(s), "counter synchronize");
@@ -678,11 +681,26 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
         pv.sem_tau = ws->sem_tau;
         pv.sem_sim = dtype != FARM_F32 ? ws->sem_sim : nullptr;
         pv.stats = ws->prop_stats;
+        pv.fb_list = ws->fb_list;
+        pv.fb_count = ws->fb_count;
+        pv.fb_cap = ws->fb_cap;
       }
-      PhaseTimer t(ws, s, FARM_PHASE_RESCORE);
-      FARM_HIP(launch_rescore(mem, ws, ws->sim, ws->ld_s, q, meta, bound, ws->rs_idx, ws->cand_count, kBoundCap, pv,
-                              s),
-               "candidate scoring");
+      {
+        PhaseTimer t(ws, s, FARM_PHASE_RESCORE);
+        FARM_HIP(launch_rescore_terms(mem, ws, ws->sim, ws->ld_s, q, meta, bound, ws->rs_idx, ws->cand_count,
+                                      kBoundCap, pv, false, s),
+                 "candidate terms");
+      }
+      if (pv.m > 0) {
+        PhaseTimer t(ws, s, FARM_PHASE_FALLBACK);
+        FARM_HIP(launch_rescore_terms(mem, ws, ws->sim, ws->ld_s, q, meta, bound, ws->rs_idx, ws->cand_count,
+                                      kBoundCap, pv, true, s),
+                 "fallback terms");
+      }
+      PhaseTimer t(ws, s, FARM_PHASE_SELECT);
+      FARM_HIP(launch_rescore_combine(mem, ws, ws->sim, ws->ld_s, q, meta, bound, ws->rs_idx, ws->cand_count,
+                                      kBoundCap, s),
+               "candidate scores");
       FARM_HIP(launch_rescore_select(ws, q, kBoundCap, k, nullptr, nullptr, ws->cand_count, mem->n, out_id, out_score,
                                      out_terms, out_anchor_id, nullptr, s),
                "candidate select");
@@ -716,9 +734,15 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
       PhaseTimer t(ws, s, FARM_PHASE_TOPK);
       FARM_HIP(launch_topk(mem, ws, ws->scores_hi, ws->ld_s, q, c + 1, &hi_key, &hi_idx, s), "bound topk");
     }
-    PhaseTimer t(ws, s, FARM_PHASE_RESCORE);
-    FARM_HIP(launch_rescore(mem, ws, ws->sim, ws->ld_s, q, meta, bound, ws->rs_idx, nullptr, c, PropView{}, s),
-             "rescore");
+    {
+      PhaseTimer t(ws, s, FARM_PHASE_RESCORE);
+      FARM_HIP(launch_rescore_terms(mem, ws, ws->sim, ws->ld_s, q, meta, bound, ws->rs_idx, nullptr, c, PropView{},
+                                    false, s),
+               "rescore terms");
+    }
+    PhaseTimer t(ws, s, FARM_PHASE_SELECT);
+    FARM_HIP(launch_rescore_combine(mem, ws, ws->sim, ws->ld_s, q, meta, bound, ws->rs_idx, nullptr, c, s),
+             "rescore scores");
     FARM_HIP(launch_rescore_select(ws, q, c, k, hi_key, hi_idx, nullptr, mem->n, out_id, out_score, out_terms,
                                    out_anchor_id, certified, s),
              "rescore select");

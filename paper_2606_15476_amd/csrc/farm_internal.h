@@ -20,6 +20,12 @@ constexpr float kClassFactor = 0.3f;
 constexpr float kFp8Max = 448.0f;  // largest finite OCP e4m3 value
 constexpr int32_t kBoundCap = 2048;  // candidates per query kept by the bound-pruned TopK
 constexpr int32_t kSemMax = 64;      // semantic anchor set per relation in the proposal pass
+// Uncertified terms listed for the block-wide fallback scan (more are still
+// found and scanned by a sweep over the terms).
+inline int64_t fallback_cap(int32_t max_q) {
+  const int64_t c = (int64_t)max_q * 256 + 1024;
+  return c < (1 << 20) ? c : (1 << 20);
+}
 
 // Validation flag bits raised by device-side checks.
 enum : int {
@@ -114,7 +120,10 @@ struct farm_workspace {
   int32_t* sem_cnt = nullptr;    // [max_rel]
   float* sem_tau = nullptr;      // [max_rel] largest similarity of an anchor outside the set
   float* sem_sim = nullptr;      // [max_rel][kSemMax] FP32 similarity of each set member (reduced precision)
-  unsigned long long* prop_stats = nullptr;  // [2] (candidate, relation) pairs checked, pairs that fell back
+  unsigned long long* prop_stats = nullptr;  // [4] terms checked, fell back, FP32 dots (subset, fallback)
+  unsigned long long* fb_list = nullptr;     // [fb_cap] terms the proposals could not certify: query << 32 | term
+  uint32_t* fb_count = nullptr;              // [1]
+  int64_t fb_cap = 0;
   // optional phase timer: pending (start, stop) event pairs per phase
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -211,6 +220,9 @@ struct PropView {
   const float* sem_tau = nullptr;    // [R]
   const float* sem_sim = nullptr;    // [R][kSemMax] exact similarities of the set, or null (FP32 matrix)
   unsigned long long* stats = nullptr;
+  unsigned long long* fb_list = nullptr;  // worklist of uncertified terms (query << 32 | term index)
+  uint32_t* fb_count = nullptr;
+  int64_t fb_cap = 0;
 };
 
 // Makes `dev` current for the guard's lifetime.
@@ -280,12 +292,21 @@ hipError_t launch_explain(const farm_memory* mem, const float* sim, int64_t ld_s
 // target similarity and, per relation, the exact maximum over anchors, where
 // only anchors whose bounded value can reach the best lower bound get an FP32
 // dot product.  Writes rs_score[q][c], rs_terms/rs_anchor[q][c][8].
-// With proposals (prop.m > 0) each term is first taken over the target's
-// anchor list and the relation's semantic set; it is kept when it exceeds the
-// bound on every anchor outside both, else the anchors are scanned in full.
-hipError_t launch_rescore(const farm_memory* mem, const farm_workspace* ws, const float* sim, int64_t ld_s, int32_t q,
-                          MetaView meta, const SimBound& bound, const int32_t* cand, const int32_t* cand_count,
-                          int32_t c, const PropView& prop, hipStream_t s);
+// Candidate scoring in two steps.  launch_rescore_terms: every (candidate,
+// relation) term into rs_terms / rs_anchor in the family's domain.  With
+// proposals (prop.m > 0) a first pass takes each term over the target's anchor
+// list and the relation's semantic set and keeps it when it exceeds the bound
+// on every anchor outside both; the second pass (fallback_pass) scans all
+// anchors for the others.  Without proposals one pass scans all anchors.
+// launch_rescore_combine: s_sem (FP32 dot for reduced precision) and the
+// composite into rs_score, linear terms into rs_terms.
+hipError_t launch_rescore_terms(const farm_memory* mem, const farm_workspace* ws, const float* sim, int64_t ld_s,
+                                int32_t q, MetaView meta, const SimBound& bound, const int32_t* cand,
+                                const int32_t* cand_count, int32_t c, const PropView& prop, bool fallback_pass,
+                                hipStream_t s);
+hipError_t launch_rescore_combine(const farm_memory* mem, const farm_workspace* ws, const float* sim, int64_t ld_s,
+                                  int32_t q, MetaView meta, const SimBound& bound, const int32_t* cand,
+                                  const int32_t* cand_count, int32_t c, hipStream_t s);
 
 // ---- bounded.hip
 // Candidates of the exact bound-pruned TopK: per query every object whose

@@ -181,6 +181,29 @@ __global__ __launch_bounds__(64 * kSemWaves) void k_semantic_sets(const float* _
   float mx = 0.f;
   for (int64_t j = lane; j < n; j += 64) mx = fmaxf(mx, row[j]);
   const float amax = wave_max(mx);
+  const uint64_t below = (1ull << lane) - 1ull;
+  // one pass: ordered compaction of the anchors above tau (first kSemMax kept),
+  // their count, and the largest similarity of the anchors left out
+  float out = 0.f;
+  auto compact = [&](float tau) {
+    int32_t pos = 0;
+    out = 0.f;
+    for (int64_t base = 0; base < n; base += 64) {
+      const int64_t j = base + lane;
+      const bool valid = j < n;
+      const float v = valid ? row[j] : 0.f;
+      const bool above = valid && v > tau;
+      const uint64_t mask = __ballot(above);
+      const int32_t my = pos + __popcll(mask & below);
+      if (above && my < kSemMax) {
+        sem_idx[(int64_t)r * kSemMax + my] = (int32_t)j;
+      } else if (valid) {
+        out = fmaxf(out, v);
+      }
+      pos += __popcll(mask);
+    }
+    return pos;
+  };
   auto count_above = [&](float tau) {
     int32_t c = 0;
     for (int64_t base = 0; base < n; base += 64) {
@@ -190,27 +213,14 @@ __global__ __launch_bounds__(64 * kSemWaves) void k_semantic_sets(const float* _
     return c;
   };
   float tau = 0.5f * amax, gap = 0.5f * amax;
-  int32_t total = count_above(tau);
-  for (int it = 0; it < 30 && total > kSemMax; ++it) {
-    gap *= 0.5f;
-    tau = amax - gap;
-    total = count_above(tau);
-  }
-  const uint64_t below = (1ull << lane) - 1ull;
-  int32_t pos = 0;
-  float out = 0.f;
-  for (int64_t base = 0; base < n; base += 64) {
-    const int64_t j = base + lane;
-    const bool valid = j < n;
-    const bool above = valid && row[j] > tau;
-    const uint64_t mask = __ballot(above);
-    const int32_t my = pos + __popcll(mask & below);
-    if (above && my < kSemMax) {
-      sem_idx[(int64_t)r * kSemMax + my] = (int32_t)j;
-    } else if (valid) {
-      out = fmaxf(out, row[j]);
+  int32_t total = compact(tau);  // usually final: few anchors reach half the best similarity
+  if (total > kSemMax) {
+    for (int it = 0; it < 30 && total > kSemMax; ++it) {
+      gap *= 0.5f;
+      tau = amax - gap;
+      total = count_above(tau);
     }
-    pos += __popcll(mask);
+    total = compact(tau);
   }
   out = wave_max(out);
   if (lane == 0) {

@@ -70,6 +70,17 @@ __device__ inline void take_max(float v, int64_t j, const uint32_t* __restrict__
   }
 }
 
+// max with the smallest-id tie-break that remembers the anchor's index; the
+// ids are read only to break exact ties (resolve with the index at the end)
+__device__ inline void take_max_j(float v, int64_t j, const uint32_t* __restrict__ ids, float& best, int64_t& bj) {
+  if (v > best) {
+    best = v;
+    bj = j;
+  } else if (v == best && bj >= 0 && j != bj && ids[j] < ids[bj]) {
+    bj = j;
+  }
+}
+
 // Wave-wide arg-max with the smallest-id tie-break; every lane gets the result.
 __device__ inline void wave_argmax(float& best, uint32_t& bid) {
 #pragma unroll
@@ -107,81 +118,29 @@ struct Subset {
   float cert;         // bound on the value of every anchor outside the subset (family domain)
 };
 
-// One relation term of target o, computed by one wave.  Returns the
-// family-domain maximum (log for Near) and its anchor id.
+// The exact maximum over every anchor of one relation term of target o, by
+// one wave.  Returns the family-domain maximum (log for Near) and its anchor id.
+// With reduced precision, members of the relation's semantic set (sidx, sn;
+// exact similarities ssim, may be null) start the maximum at their exact
+// values and never need a dot product of their own.
 template <int FAM>
-__device__ void term_wave(const float* __restrict__ arow, const float* __restrict__ qrow, const float* __restrict__ dn, int32_t ldk, int64_t n,
-                          int64_t o, float c, bool bounded, float qn, float qe, const float* __restrict__ o_err,
-                          const Geo& g, const Subset& sub, int lane, float& out_best, uint32_t& out_bid,
-                          bool& fell_back) {
+__device__ void full_term(const float* __restrict__ arow, const float* __restrict__ qrow,
+                          const float* __restrict__ dn, int32_t ldk, int64_t n, int64_t o, float c, bool bounded,
+                          float qn, float qe, const float* __restrict__ o_err, const Geo& g, int lane,
+                          const int32_t* __restrict__ sidx, int sn, const float* __restrict__ ssim,
+                          float& out_best, uint32_t& out_bid, uint32_t& dots) {
   const Tgt t = load_target(FAM, o, g.x, g.y, g.z, g.hhi, g.hlo);
   float best = value_floor<FAM>();
   uint32_t bid = FARM_NO_ID;
-  fell_back = false;
-  if (sub.M > 0) {
-    const int tot = sub.M + sub.sn;
-    auto anchor_of = [&](int e) -> int64_t { return e < sub.M ? sub.lidx[e] : sub.sidx[e - sub.M]; };
-    // list entries carry the cached predicate value; semantic-set entries are evaluated
-    auto entry = [&](int e, int64_t j, float a, float la) -> float {
-      if (e < sub.M) return FAM == kFamNear ? la + sub.lval[e] : a * sub.lval[e];
-      return pair_value<FAM>(t, anchor_record_pre(FAM, a, la, j, g.x, g.y, g.z, g.hhi, g.hlo), c);
-    };
-    if (!bounded) {
-      for (int e = lane; e < tot; e += 64) {
-        const int64_t j = anchor_of(e);
-        if (j == o) continue;
-        const float a = arow[j];
-        take_max(entry(e, j, a, FAM == kFamNear ? near_log(a) : 0.f), j, g.ids, best, bid);
-      }
-    } else {
-      // semantic-set members carry their exact similarity: exact values at once
-      for (int e = sub.M + lane; e < tot; e += 64) {
-        const int64_t j = anchor_of(e);
-        if (j == o) continue;
-        const float a = sub.ssim[e - sub.M];
-        take_max(entry(e, j, a, FAM == kFamNear ? near_log(a) : 0.f), j, g.ids, best, bid);
-      }
-      // list entries: bounds from the reduced-precision similarity
-      float lo = best;
-      for (int e = lane; e < sub.M; e += 64) {
-        const int64_t j = anchor_of(e);
-        if (j == o) continue;
-        const float a = fmaxf(0.f, arow[j] - fmaf(qn, o_err[j], qe));
-        lo = fmaxf(lo, entry(e, j, a, FAM == kFamNear ? near_log(a) : 0.f));
-      }
-      lo = wave_max_f(lo);
-      const float L = lo - (fabsf(lo) * 1e-6f + 1e-30f);  // slack for rounding of the bounded values
-      for (int base = 0; base < sub.M; base += 64) {
-        const int e = base + lane;
-        bool f = false;
-        int64_t j = -1;
-        if (e < sub.M) {
-          j = anchor_of(e);
-          if (j != o) {
-            const float a = fminf(1.0f, arow[j] + fmaf(qn, o_err[j], qe));
-            f = entry(e, j, a, FAM == kFamNear ? near_log(a) : 0.f) >= L;
-          }
-        }
-        uint64_t mask = __ballot(f);
-        while (mask) {
-          const int src = __ffsll((unsigned long long)mask) - 1;
-          mask &= mask - 1;
-          const int e2 = base + src;
-          const int64_t j2 = anchor_of(e2);
-          const float a = fmaxf(0.f, wave_dot(qrow, dn + j2 * ldk, ldk, lane));
-          take_max(entry(e2, j2, a, FAM == kFamNear ? near_log(a) : 0.f), j2, g.ids, best, bid);
-        }
-      }
+  // lane e < sn holds semantic-set member e (for the membership ballot below)
+  int64_t my_member = -1;
+  if (bounded && ssim && lane < sn) {
+    my_member = sidx[lane];
+    if (my_member != o) {
+      const float a = ssim[lane];
+      take_max(pair_value<FAM>(t, anchor_record(FAM, a, my_member, g.x, g.y, g.z, g.hhi, g.hlo), c), my_member,
+               g.ids, best, bid);
     }
-    wave_argmax(best, bid);
-    if (best > sub.cert) {
-      out_best = best;
-      out_bid = bid;
-      return;
-    }
-    fell_back = true;
-    best = value_floor<FAM>();
-    bid = FARM_NO_ID;
   }
   if (!bounded) {
     // FP32 similarities: the maximum directly, with the relational pass's arithmetic
@@ -191,14 +150,14 @@ __device__ void term_wave(const float* __restrict__ arow, const float* __restric
       take_max(v, j, g.ids, best, bid);
     }
   } else {
-    float lo = value_floor<FAM>();
+    float lo = best;  // exact values of the semantic-set members are lower bounds too
     for (int64_t j = lane; j < n; j += 64) {
       if (j == o) continue;
       const float a = fmaxf(0.f, arow[j] - fmaf(qn, o_err[j], qe));
       lo = fmaxf(lo, pair_value<FAM>(t, anchor_record(FAM, a, j, g.x, g.y, g.z, g.hhi, g.hlo), c));
     }
     lo = wave_max_f(lo);
-    const float L = lo - (fabsf(lo) * 1e-6f + 1e-30f);
+    const float L = lo - (fabsf(lo) * 1e-6f + 1e-30f);  // slack for rounding of the bounded values
     for (int64_t base = 0; base < n; base += 64) {
       const int64_t j = base + lane;
       bool f = false;
@@ -211,7 +170,9 @@ __device__ void term_wave(const float* __restrict__ arow, const float* __restric
         const int src = __ffsll((unsigned long long)mask) - 1;
         mask &= mask - 1;
         const int64_t j2 = base + src;
+        if (__ballot(my_member == j2)) continue;  // a semantic-set member: its exact value is in already
         const float a = fmaxf(0.f, wave_dot(qrow, dn + j2 * ldk, ldk, lane));
+        ++dots;
         take_max(pair_value<FAM>(t, anchor_record(FAM, a, j2, g.x, g.y, g.z, g.hhi, g.hlo), c), j2, g.ids, best,
                  bid);
       }
@@ -222,12 +183,118 @@ __device__ void term_wave(const float* __restrict__ arow, const float* __restric
   out_bid = bid;
 }
 
-constexpr int kTermWaves = 4;       // waves per block
-constexpr int kTermBlocksX = 8;     // blocks per query: 32 waves sweep a query's terms
+// The maximum over the subset (the target's list and the relation's semantic
+// set) by one wave; true when it certifies the term (strictly above the bound
+// on every other anchor).
+template <int FAM>
+__device__ bool subset_term(const float* arow, const float* __restrict__ qrow, const float* __restrict__ dn,
+                            int32_t ldk, int64_t o, float c, bool bounded, float qn, float qe,
+                            const float* __restrict__ o_err, float qd_uniform, const Geo& g, const Subset& sub,
+                            int lane, float& out_best, uint32_t& out_bid, uint32_t& dots) {
+  const Tgt t = load_target(FAM, o, g.x, g.y, g.z, g.hhi, g.hlo);
+  float best = value_floor<FAM>();
+  int64_t bj = -1;
+  const int tot = sub.M + sub.sn;
+  auto anchor_of = [&](int e) -> int64_t { return e < sub.M ? sub.lidx[e] : sub.sidx[e - sub.M]; };
+  // list entries carry the cached predicate value; semantic-set entries are evaluated
+  auto entry = [&](int e, int64_t j, float a, float la) -> float {
+    if (e < sub.M) return FAM == kFamNear ? la + sub.lval[e] : a * sub.lval[e];
+    return pair_value<FAM>(t, anchor_record_pre(FAM, a, la, j, g.x, g.y, g.z, g.hhi, g.hlo), c);
+  };
+  // similarity error bound of anchor j (per anchor, or one bound for all)
+  auto delta = [&](int64_t j) { return o_err ? fmaf(qn, o_err[j], qe) : qd_uniform; };
+  if (!bounded) {
+    for (int e = lane; e < tot; e += 64) {
+      const int64_t j = anchor_of(e);
+      if (j == o) continue;
+      const float a = arow[j];
+      take_max_j(entry(e, j, a, FAM == kFamNear ? near_log(a) : 0.f), j, g.ids, best, bj);
+    }
+  } else {
+    // semantic-set members carry their exact similarity: exact values at once
+    for (int e = sub.M + lane; e < tot; e += 64) {
+      const int64_t j = anchor_of(e);
+      if (j == o) continue;
+      const float a = sub.ssim[e - sub.M];
+      take_max_j(entry(e, j, a, FAM == kFamNear ? near_log(a) : 0.f), j, g.ids, best, bj);
+    }
+    // list entries: bounds from the reduced-precision similarity
+    float lo = best;
+    for (int e = lane; e < sub.M; e += 64) {
+      const int64_t j = anchor_of(e);
+      if (j == o) continue;
+      const float a = fmaxf(0.f, arow[j] - delta(j));
+      lo = fmaxf(lo, entry(e, j, a, FAM == kFamNear ? near_log(a) : 0.f));
+    }
+    lo = wave_max_f(lo);
+    const float L = lo - (fabsf(lo) * 1e-6f + 1e-30f);  // slack for rounding of the bounded values
+    for (int base = 0; base < sub.M; base += 64) {
+      const int e = base + lane;
+      bool f = false;
+      if (e < sub.M) {
+        const int64_t j = anchor_of(e);
+        if (j != o) {
+          const float a = fminf(1.0f, arow[j] + delta(j));
+          f = entry(e, j, a, FAM == kFamNear ? near_log(a) : 0.f) >= L;
+        }
+      }
+      uint64_t mask = __ballot(f);
+      while (mask) {
+        const int src = __ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1;
+        const int e2 = base + src;
+        const int64_t j2 = anchor_of(e2);
+        const float a = fmaxf(0.f, wave_dot(qrow, dn + j2 * ldk, ldk, lane));
+        ++dots;
+        take_max_j(entry(e2, j2, a, FAM == kFamNear ? near_log(a) : 0.f), j2, g.ids, best, bj);
+      }
+    }
+  }
+  uint32_t bid = bj >= 0 ? g.ids[bj] : FARM_NO_ID;
+  wave_argmax(best, bid);
+  out_best = best;
+  out_bid = bid;
+  return best > sub.cert;
+}
+
+// Proposal subset of term (candidate o, relation r) and the bound on every
+// anchor outside it.
+__device__ inline Subset make_subset(const PropView& pv, int r, int p, int64_t o, int64_t n, bool bounded, float qnr,
+                                     float qer, float err_max) {
+  Subset sub;
+  const int64_t off = ((int64_t)p * n + o) * pv.m;
+  sub.lidx = pv.idx + off;
+  sub.lval = pv.val + off;
+  sub.M = pv.m;
+  sub.sidx = pv.sem_idx + (int64_t)r * kSemMax;
+  sub.sn = pv.sem_cnt[r];
+  sub.ssim = pv.sem_sim ? pv.sem_sim + (int64_t)r * kSemMax : nullptr;
+  const float pout = pv.out[(int64_t)p * n + o];
+  // every anchor outside the subset has similarity <= a_hi and predicate value <= pout
+  const float a_hi = bounded ? pv.sem_tau[r] + fmaf(qnr, err_max, qer) : pv.sem_tau[r];
+  if (family_of(p) == kFamNear) {
+    const float b = near_log(a_hi) + pout;
+    sub.cert = b + fabsf(b) * 1e-6f;  // covers the rounding of the logarithm
+  } else {
+    sub.cert = a_hi * pout;
+  }
+  return sub;
+}
+
+constexpr int kTermWaves = 4;    // waves per block
+constexpr int kTermBlocksX = 8;  // blocks per query: 32 waves sweep a query's terms
+
+enum { kTermsFull = 0, kTermsSubset = 1, kTermsFallback = 2 };
 
 // One wave per (candidate, relation) term.  Writes the family-domain maximum
 // (Near: log of the term; others: the term) into rs_terms and the bound
 // anchor into rs_anchor; k_rescore_combine turns them into scores.
+//   kTermsFull:     every term over all anchors;
+//   kTermsSubset:   every term over its proposal subset; a term the subset
+//                   cannot certify is marked NaN;
+//   kTermsFallback: the NaN-marked terms over all anchors (a wave tests 64
+//                   terms with one ballot).
+template <int MODE, bool BOUNDED>
 __global__ __launch_bounds__(64 * kTermWaves) void k_rescore_terms(
     const float* __restrict__ sim, int64_t ld_s, int32_t q, MetaView meta, SimBound bound,
     const float* __restrict__ qn, const float* __restrict__ dn, int32_t ldk, const int32_t* __restrict__ cand,
@@ -239,70 +306,264 @@ __global__ __launch_bounds__(64 * kTermWaves) void k_rescore_terms(
   if (R == 0) return;
   const int32_t cnt = cand_count ? (cand_count[qq] < C ? cand_count[qq] : C) : C;
   const int64_t terms = (int64_t)cnt * R;
+  const int wave = blockIdx.x * kTermWaves + (threadIdx.x >> 6);
   const int stride = kTermBlocksX * kTermWaves;
-  const bool bounded = bound.q_nrm != nullptr;
+  constexpr bool bounded = BOUNDED;  // reduced-precision similarities with an error bound
   const float err_max = bounded ? *bound.o_err_max : 0.f;
   unsigned long long checked = 0, fell = 0;
-  for (int64_t tix = blockIdx.x * kTermWaves + (threadIdx.x >> 6); tix < terms; tix += stride) {
+  uint32_t dots = 0;
+  auto term_args = [&](int64_t tix, int64_t& slot, int& e, int64_t& o) {
     const int32_t cc = (int32_t)(tix / R);
-    const int e = (int)(tix % R);
-    const int64_t slot = (int64_t)qq * C + cc;
-    const int64_t o = cand[slot];
-    if (o < 0) continue;
+    e = (int)(tix % R);
+    slot = (int64_t)qq * C + cc;
+    o = cand[slot];
+  };
+  auto full = [&](int64_t slot, int e, int64_t o) {
     const int r = r0 + e;
+    const int32_t* sidx = pv.sem_idx ? pv.sem_idx + (int64_t)r * kSemMax : nullptr;
+    const int sn = pv.sem_idx ? pv.sem_cnt[r] : 0;
+    const float* ssim = pv.sem_sim ? pv.sem_sim + (int64_t)r * kSemMax : nullptr;
     const int p = meta.rel_pred[r];
     const float c = sigmoid_scale(p);
     const float* arow = sim + (int64_t)(q + r) * ld_s;
     const float* qrow = qn + (int64_t)(q + r) * ldk;
     const float qnr = bounded ? bound.q_nrm[q + r] : 0.f;
     const float qer = bounded ? bound.q_err[q + r] + bound.acc : 0.f;
-    Subset sub{nullptr, nullptr, 0, nullptr, 0, nullptr, INFINITY};
-    if (pv.m > 0) {
-      const int64_t off = ((int64_t)p * n + o) * pv.m;
-      sub.lidx = pv.idx + off;
-      sub.lval = pv.val + off;
-      sub.M = pv.m;
-      sub.sidx = pv.sem_idx + (int64_t)r * kSemMax;
-      sub.sn = pv.sem_cnt[r];
-      sub.ssim = pv.sem_sim ? pv.sem_sim + (int64_t)r * kSemMax : nullptr;
-      const float pout = pv.out[(int64_t)p * n + o];
-      // every anchor outside the subset has similarity <= a_hi and predicate value <= pout
-      const float a_hi = bounded ? pv.sem_tau[r] + fmaf(qnr, err_max, qer) : pv.sem_tau[r];
-      if (family_of(p) == kFamNear) {
-        const float b = near_log(a_hi) + pout;
-        sub.cert = b + fabsf(b) * 1e-6f;  // covers the rounding of the logarithm
-      } else {
-        sub.cert = a_hi * pout;
-      }
-    }
     float best;
     uint32_t bid;
-    bool fb;
     switch (family_of(p)) {
       case kFamNear:
-        term_wave<kFamNear>(arow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, g, sub, lane, best,
-                            bid, fb);
+        full_term<kFamNear>(arow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, g, lane, sidx, sn, ssim,
+                             best, bid, dots);
         break;
       case kFamVert:
-        term_wave<kFamVert>(arow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, g, sub, lane, best,
-                            bid, fb);
+        full_term<kFamVert>(arow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, g, lane, sidx, sn, ssim,
+                             best, bid, dots);
         break;
       default:
-        term_wave<kFamLat>(arow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, g, sub, lane, best,
-                           bid, fb);
+        full_term<kFamLat>(arow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, g, lane, sidx, sn, ssim,
+                             best, bid, dots);
         break;
     }
     if (lane == 0) {
       rs_terms[slot * kMaxRel + e] = best;
       rs_anchor[slot * kMaxRel + e] = bid;
     }
-    checked += 1;
-    fell += fb ? 1 : 0;
+  };
+  if (MODE == kTermsFallback) {
+    for (int64_t base = (int64_t)wave * 64; base < terms; base += (int64_t)stride * 64) {
+      const int64_t tix = base + lane;
+      bool marked = false;
+      if (tix < terms) {
+        int64_t slot, o;
+        int e;
+        term_args(tix, slot, e, o);
+        marked = o >= 0 && isnan(rs_terms[slot * kMaxRel + e]);
+      }
+      uint64_t mask = __ballot(marked);
+      while (mask) {
+        const int src = __ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1;
+        int64_t slot, o;
+        int e;
+        term_args(base + src, slot, e, o);
+        full(slot, e, o);
+      }
+    }
+  } else {
+    for (int64_t tix = wave; tix < terms; tix += stride) {
+      int64_t slot, o;
+      int e;
+      term_args(tix, slot, e, o);
+      if (o < 0) continue;
+      if (MODE == kTermsFull) {
+        full(slot, e, o);
+        continue;
+      }
+      const int r = r0 + e;
+      const int p = meta.rel_pred[r];
+      const float c = sigmoid_scale(p);
+      const float* arow = sim + (int64_t)(q + r) * ld_s;
+      const float* qrow = qn + (int64_t)(q + r) * ldk;
+      const float qnr = bounded ? bound.q_nrm[q + r] : 0.f;
+      const float qer = bounded ? bound.q_err[q + r] + bound.acc : 0.f;
+      const Subset sub = make_subset(pv, r, p, o, n, bounded, qnr, qer, err_max);
+      float best;
+      uint32_t bid;
+      bool ok;
+      switch (family_of(p)) {
+        case kFamNear:
+          ok = subset_term<kFamNear>(arow, qrow, dn, ldk, o, c, bounded, qnr, qer, bound.o_err, 0.f, g, sub, lane, best,
+                                     bid, dots);
+          break;
+        case kFamVert:
+          ok = subset_term<kFamVert>(arow, qrow, dn, ldk, o, c, bounded, qnr, qer, bound.o_err, 0.f, g, sub, lane, best,
+                                     bid, dots);
+          break;
+        default:
+          ok = subset_term<kFamLat>(arow, qrow, dn, ldk, o, c, bounded, qnr, qer, bound.o_err, 0.f, g, sub, lane, best,
+                                    bid, dots);
+          break;
+      }
+      if (lane == 0) {
+        rs_terms[slot * kMaxRel + e] = ok ? best : NAN;  // NaN: scanned in full by the fallback pass
+        rs_anchor[slot * kMaxRel + e] = bid;
+        if (!ok && pv.fb_list) {
+          const uint32_t pos = atomicAdd(pv.fb_count, 1u);
+          if (pos < pv.fb_cap) pv.fb_list[pos] = ((unsigned long long)qq << 32) | (unsigned long long)tix;
+        }
+      }
+      checked += 1;
+      fell += ok ? 0 : 1;
+    }
   }
-  if (pv.stats && lane == 0 && checked) {
-    atomicAdd(&pv.stats[0], checked);
+  if (pv.stats && lane == 0 && (checked || dots)) {
+    if (checked) atomicAdd(&pv.stats[0], checked);
     if (fell) atomicAdd(&pv.stats[1], fell);
+    if (dots) atomicAdd(&pv.stats[MODE == kTermsSubset ? 2 : 3], (unsigned long long)dots);
   }
+}
+
+constexpr int kFbThreads = 256;
+
+// Block-wide arg-max (smallest id on ties) of per-thread (best, bid).
+__device__ inline void block_argmax(float& best, uint32_t& bid, float* sv, uint32_t* sid) {
+  wave_argmax(best, bid);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    sv[w] = best;
+    sid[w] = bid;
+  }
+  __syncthreads();
+  best = sv[0];
+  bid = sid[0];
+  for (int i = 1; i < kFbThreads / 64; ++i)
+    if (better(sv[i], sid[i], best, bid)) {
+      best = sv[i];
+      bid = sid[i];
+    }
+}
+
+// The exact maximum over every anchor of one term by a whole block (the
+// block-wide form of full_term, same per-pair arithmetic and survivors rule).
+template <int FAM, bool BOUNDED>
+__device__ void full_term_block(const float* __restrict__ arow, const float* __restrict__ qrow,
+                                const float* __restrict__ dn, int32_t ldk, int64_t n, int64_t o, float c, float qn,
+                                float qe, const float* __restrict__ o_err, const Geo& g,
+                                const int32_t* __restrict__ sidx, int sn, const float* __restrict__ ssim, float* sv,
+                                uint32_t* sid, float& out_best, uint32_t& out_bid, uint32_t& dots) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const Tgt t = load_target(FAM, o, g.x, g.y, g.z, g.hhi, g.hlo);
+  float best = value_floor<FAM>();
+  uint32_t bid = FARM_NO_ID;
+  int64_t my_member = -1;  // lane e < sn of every wave holds semantic-set member e
+  if (BOUNDED && ssim && lane < sn) {
+    my_member = sidx[lane];
+    if (w == 0 && my_member != o) {
+      const float a = ssim[lane];
+      take_max(pair_value<FAM>(t, anchor_record(FAM, a, my_member, g.x, g.y, g.z, g.hhi, g.hlo), c), my_member,
+               g.ids, best, bid);
+    }
+  }
+  if (!BOUNDED) {
+    for (int64_t j = tid; j < n; j += kFbThreads) {
+      if (j == o) continue;
+      take_max(pair_value<FAM>(t, anchor_record(FAM, arow[j], j, g.x, g.y, g.z, g.hhi, g.hlo), c), j, g.ids, best,
+               bid);
+    }
+  } else {
+    float lo = best;
+    for (int64_t j = tid; j < n; j += kFbThreads) {
+      if (j == o) continue;
+      const float a = fmaxf(0.f, arow[j] - fmaf(qn, o_err[j], qe));
+      lo = fmaxf(lo, pair_value<FAM>(t, anchor_record(FAM, a, j, g.x, g.y, g.z, g.hhi, g.hlo), c));
+    }
+    lo = wave_max_f(lo);
+    __syncthreads();
+    if (lane == 0) sv[w] = lo;
+    __syncthreads();
+    for (int i = 0; i < kFbThreads / 64; ++i) lo = fmaxf(lo, sv[i]);
+    const float L = lo - (fabsf(lo) * 1e-6f + 1e-30f);  // slack for rounding of the bounded values
+    // each wave resolves the survivors of its own 64-anchor chunks
+    for (int64_t base = (int64_t)w * 64; base < n; base += kFbThreads) {
+      const int64_t j = base + lane;
+      bool f = false;
+      if (j < n && j != o) {
+        const float a = fminf(1.0f, arow[j] + fmaf(qn, o_err[j], qe));
+        f = pair_value<FAM>(t, anchor_record(FAM, a, j, g.x, g.y, g.z, g.hhi, g.hlo), c) >= L;
+      }
+      uint64_t mask = __ballot(f);
+      while (mask) {
+        const int src = __ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1;
+        const int64_t j2 = base + src;
+        if (__ballot(my_member == j2)) continue;  // a semantic-set member: its exact value is in already
+        const float a = fmaxf(0.f, wave_dot(qrow, dn + j2 * ldk, ldk, lane));
+        ++dots;
+        take_max(pair_value<FAM>(t, anchor_record(FAM, a, j2, g.x, g.y, g.z, g.hhi, g.hlo), c), j2, g.ids, best,
+                 bid);
+      }
+    }
+  }
+  block_argmax(best, bid, sv, sid);
+  out_best = best;
+  out_bid = bid;
+}
+
+// One block per listed uncertified term (grid-stride over the worklist).
+template <bool BOUNDED>
+__global__ __launch_bounds__(kFbThreads) void k_rescore_fallback(
+    const float* __restrict__ sim, int64_t ld_s, int32_t q, MetaView meta, SimBound bound,
+    const float* __restrict__ qn, const float* __restrict__ dn, int32_t ldk, const int32_t* __restrict__ cand,
+    int32_t C, Geo g, int64_t n, float* __restrict__ rs_terms, uint32_t* __restrict__ rs_anchor, PropView pv) {
+  __shared__ float sv[kFbThreads / 64];
+  __shared__ uint32_t sid[kFbThreads / 64];
+  const uint32_t listed = *pv.fb_count;
+  const int64_t count = listed < pv.fb_cap ? (int64_t)listed : pv.fb_cap;
+  uint32_t dots = 0;
+  for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
+    const unsigned long long item = pv.fb_list[i];
+    const int32_t qq = (int32_t)(item >> 32);
+    const int64_t tix = (int64_t)(item & 0xFFFFFFFFull);
+    const int r0 = meta.rel_off[qq], R = meta.rel_off[qq + 1] - r0;
+    const int32_t cc = (int32_t)(tix / R);
+    const int e = (int)(tix % R);
+    const int64_t slot = (int64_t)qq * C + cc;
+    const int64_t o = cand[slot];
+    const int r = r0 + e;
+    const int p = meta.rel_pred[r];
+    const float c = sigmoid_scale(p);
+    const float* arow = sim + (int64_t)(q + r) * ld_s;
+    const float* qrow = qn + (int64_t)(q + r) * ldk;
+    const float qnr = BOUNDED ? bound.q_nrm[q + r] : 0.f;
+    const float qer = BOUNDED ? bound.q_err[q + r] + bound.acc : 0.f;
+    const int32_t* sidx = pv.sem_idx + (int64_t)r * kSemMax;
+    const int sn = pv.sem_cnt[r];
+    const float* ssim = pv.sem_sim ? pv.sem_sim + (int64_t)r * kSemMax : nullptr;
+    float best;
+    uint32_t bid;
+    switch (family_of(p)) {
+      case kFamNear:
+        full_term_block<kFamNear, BOUNDED>(arow, qrow, dn, ldk, n, o, c, qnr, qer, bound.o_err, g, sidx, sn, ssim, sv,
+                                           sid, best, bid, dots);
+        break;
+      case kFamVert:
+        full_term_block<kFamVert, BOUNDED>(arow, qrow, dn, ldk, n, o, c, qnr, qer, bound.o_err, g, sidx, sn, ssim, sv,
+                                           sid, best, bid, dots);
+        break;
+      default:
+        full_term_block<kFamLat, BOUNDED>(arow, qrow, dn, ldk, n, o, c, qnr, qer, bound.o_err, g, sidx, sn, ssim, sv,
+                                          sid, best, bid, dots);
+        break;
+    }
+    if (threadIdx.x == 0) {
+      rs_terms[slot * kMaxRel + e] = best;
+      rs_anchor[slot * kMaxRel + e] = bid;
+    }
+    __syncthreads();
+  }
+  if (pv.stats && (threadIdx.x & 63) == 0 && dots) atomicAdd(&pv.stats[3], (unsigned long long)dots);
 }
 
 // Composite score of every candidate from its family-domain maxima: one wave
@@ -454,16 +715,52 @@ __global__ __launch_bounds__(256) void k_max_reduce(const float* __restrict__ v,
 
 }  // namespace
 
-hipError_t launch_rescore(const farm_memory* mem, const farm_workspace* ws, const float* sim, int64_t ld_s, int32_t q,
-                          MetaView meta, const SimBound& bound, const int32_t* cand, const int32_t* cand_count,
-                          int32_t c, const PropView& prop, hipStream_t s) {
+hipError_t launch_rescore_terms(const farm_memory* mem, const farm_workspace* ws, const float* sim, int64_t ld_s,
+                                int32_t q, MetaView meta, const SimBound& bound, const int32_t* cand,
+                                const int32_t* cand_count, int32_t c, const PropView& prop, bool fallback_pass,
+                                hipStream_t s) {
   if (q <= 0 || c <= 0) return hipSuccess;
   const Geo g{mem->x, mem->y, mem->z, mem->hr_hi, mem->hr_lo, mem->id};
-  hipLaunchKernelGGL(k_rescore_terms, dim3(kTermBlocksX, (unsigned)q), dim3(64 * kTermWaves), 0, s, sim, ld_s, q,
-                     meta, bound, ws->qn, mem->dn, mem->ldk, cand, cand_count, c, g, mem->n, ws->rs_terms,
-                     ws->rs_anchor, prop);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  const dim3 grid(kTermBlocksX, (unsigned)q), block(64 * kTermWaves);
+#define FARM_TERMS(MODE, B)                                                                                      \
+  hipLaunchKernelGGL((k_rescore_terms<MODE, B>), grid, block, 0, s, sim, ld_s, q, meta, bound, ws->qn, mem->dn, \
+                     mem->ldk, cand, cand_count, c, g, mem->n, ws->rs_terms, ws->rs_anchor, prop)
+  const bool bounded = bound.q_nrm != nullptr;
+  const int mode = prop.m > 0 ? (fallback_pass ? kTermsFallback : kTermsSubset) : kTermsFull;
+  if (mode == kTermsFull && fallback_pass) return hipSuccess;
+  if (mode == kTermsSubset && prop.fb_count) {
+    hipError_t e = launch_fill_i32(reinterpret_cast<int32_t*>(prop.fb_count), 1, 0, s);
+    if (e != hipSuccess) return e;
+  }
+  if (mode == kTermsFallback && prop.fb_list) {
+    // listed terms, one block each; then the sweep below finds any the list could not hold
+    const unsigned blocks = 2048;
+    if (bounded)
+      hipLaunchKernelGGL((k_rescore_fallback<true>), dim3(blocks), dim3(kFbThreads), 0, s, sim, ld_s, q, meta, bound,
+                         ws->qn, mem->dn, mem->ldk, cand, c, g, mem->n, ws->rs_terms, ws->rs_anchor, prop);
+    else
+      hipLaunchKernelGGL((k_rescore_fallback<false>), dim3(blocks), dim3(kFbThreads), 0, s, sim, ld_s, q, meta, bound,
+                         ws->qn, mem->dn, mem->ldk, cand, c, g, mem->n, ws->rs_terms, ws->rs_anchor, prop);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (bounded) {
+    if (mode == kTermsSubset) FARM_TERMS(kTermsSubset, true);
+    else if (mode == kTermsFallback) FARM_TERMS(kTermsFallback, true);
+    else FARM_TERMS(kTermsFull, true);
+  } else {
+    if (mode == kTermsSubset) FARM_TERMS(kTermsSubset, false);
+    else if (mode == kTermsFallback) FARM_TERMS(kTermsFallback, false);
+    else FARM_TERMS(kTermsFull, false);
+  }
+#undef FARM_TERMS
+  return hipGetLastError();
+}
+
+hipError_t launch_rescore_combine(const farm_memory* mem, const farm_workspace* ws, const float* sim, int64_t ld_s,
+                                  int32_t q, MetaView meta, const SimBound& bound, const int32_t* cand,
+                                  const int32_t* cand_count, int32_t c, hipStream_t s) {
+  if (q <= 0 || c <= 0) return hipSuccess;
   const unsigned gx = (unsigned)((c + 3) / 4 < 16 ? (c + 3) / 4 : 16);
   hipLaunchKernelGGL(k_rescore_combine, dim3(gx, (unsigned)q), dim3(256), 0, s, sim, ld_s, q, meta, bound, ws->qn,
                      mem->dn, mem->ldk, cand, cand_count, c, mem->cls, ws->rs_score, ws->rs_terms, ws->rs_anchor);
