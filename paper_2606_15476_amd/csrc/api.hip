@@ -684,6 +684,7 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
         pv.fb_list = ws->fb_list;
         pv.fb_count = ws->fb_count;
         pv.fb_cap = ws->fb_cap;
+        pv.rel_total = R;
       }
       {
         PhaseTimer t(ws, s, FARM_PHASE_RESCORE);

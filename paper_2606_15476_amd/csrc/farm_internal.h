@@ -223,6 +223,7 @@ struct PropView {
   unsigned long long* fb_list = nullptr;  // worklist of uncertified terms (query << 32 | term index)
   uint32_t* fb_count = nullptr;
   int64_t fb_cap = 0;
+  int32_t rel_total = 0;  // relation rows of the call (one LDS-staged block each)
 };
 
 // Makes `dev` current for the guard's lifetime.

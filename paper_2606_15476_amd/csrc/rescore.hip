@@ -424,6 +424,83 @@ __global__ __launch_bounds__(64 * kTermWaves) void k_rescore_terms(
   }
 }
 
+// Proposal pass with the relation's similarity row staged in LDS: one block
+// per relation row serves every candidate of its query, so the list entries'
+// similarity gathers hit LDS instead of L2.  List bounds use the largest
+// descriptor error (no per-anchor gather); the exact values are unchanged.
+constexpr int kLdsThreads = 512;
+
+template <bool BOUNDED>
+__global__ __launch_bounds__(kLdsThreads) void k_rescore_subset_lds(
+    const float* __restrict__ sim, int64_t ld_s, int32_t q, MetaView meta, SimBound bound,
+    const float* __restrict__ qn, const float* __restrict__ dn, int32_t ldk, const int32_t* __restrict__ cand,
+    const int32_t* __restrict__ cand_count, int32_t C, Geo g, int64_t n, float* __restrict__ rs_terms,
+    uint32_t* __restrict__ rs_anchor, PropView pv) {
+  extern __shared__ float srow[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int32_t r = blockIdx.x;
+  const int32_t qq = meta.rel_query[r];
+  const int r0 = meta.rel_off[qq], R = meta.rel_off[qq + 1] - r0;
+  const int e = r - r0;
+  const float* arow = sim + (int64_t)(q + r) * ld_s;
+  // stage the row (rows start 256-byte aligned)
+  const int64_t n4 = n >> 2;
+  const float4* a4 = reinterpret_cast<const float4*>(arow);
+  float4* s4 = reinterpret_cast<float4*>(srow);
+  for (int64_t i = threadIdx.x; i < n4; i += kLdsThreads) s4[i] = a4[i];
+  for (int64_t j = (n4 << 2) + threadIdx.x; j < n; j += kLdsThreads) srow[j] = arow[j];
+  __syncthreads();
+  const int32_t cnt = cand_count ? (cand_count[qq] < C ? cand_count[qq] : C) : C;
+  const int p = meta.rel_pred[r];
+  const float c = sigmoid_scale(p);
+  const float* qrow = qn + (int64_t)(q + r) * ldk;
+  const float qnr = BOUNDED ? bound.q_nrm[q + r] : 0.f;
+  const float qer = BOUNDED ? bound.q_err[q + r] + bound.acc : 0.f;
+  const float err_max = BOUNDED ? *bound.o_err_max : 0.f;
+  const float qd = BOUNDED ? fmaf(qnr, err_max, qer) : 0.f;
+  unsigned long long checked = 0, fell = 0;
+  uint32_t dots = 0;
+  for (int32_t cc = wave; cc < cnt; cc += kLdsThreads / 64) {
+    const int64_t slot = (int64_t)qq * C + cc;
+    const int64_t o = cand[slot];
+    if (o < 0) continue;
+    const Subset sub = make_subset(pv, r, p, o, n, BOUNDED, qnr, qer, err_max);
+    float best;
+    uint32_t bid;
+    bool ok;
+    switch (family_of(p)) {
+      case kFamNear:
+        ok = subset_term<kFamNear>(srow, qrow, dn, ldk, o, c, BOUNDED, qnr, qer, nullptr, qd, g, sub, lane, best, bid,
+                                   dots);
+        break;
+      case kFamVert:
+        ok = subset_term<kFamVert>(srow, qrow, dn, ldk, o, c, BOUNDED, qnr, qer, nullptr, qd, g, sub, lane, best, bid,
+                                   dots);
+        break;
+      default:
+        ok = subset_term<kFamLat>(srow, qrow, dn, ldk, o, c, BOUNDED, qnr, qer, nullptr, qd, g, sub, lane, best, bid,
+                                  dots);
+        break;
+    }
+    if (lane == 0) {
+      rs_terms[slot * kMaxRel + e] = ok ? best : NAN;  // NaN: scanned in full by the fallback pass
+      rs_anchor[slot * kMaxRel + e] = bid;
+      if (!ok && pv.fb_list) {
+        const uint32_t pos = atomicAdd(pv.fb_count, 1u);
+        if (pos < pv.fb_cap)
+          pv.fb_list[pos] = ((unsigned long long)qq << 32) | (unsigned long long)((int64_t)cc * R + e);
+      }
+    }
+    checked += 1;
+    fell += ok ? 0 : 1;
+  }
+  if (pv.stats && lane == 0 && (checked || dots)) {
+    if (checked) atomicAdd(&pv.stats[0], checked);
+    if (fell) atomicAdd(&pv.stats[1], fell);
+    if (dots) atomicAdd(&pv.stats[2], (unsigned long long)dots);
+  }
+}
+
 constexpr int kFbThreads = 256;
 
 // Block-wide arg-max (smallest id on ties) of per-thread (best, bid).
@@ -715,6 +792,31 @@ __global__ __launch_bounds__(256) void k_max_reduce(const float* __restrict__ v,
 
 }  // namespace
 
+// Whether a similarity row of `bytes` can be staged in LDS by the proposal
+// pass on `device` (raises the kernel's dynamic LDS limit once as needed).
+bool lds_row_fits(int device, size_t bytes, bool bounded) {
+  static int limit[64] = {0};
+  static size_t granted[2][64] = {{0}};
+  if (device < 0 || device >= 64) return false;
+  if (limit[device] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) v = -1;
+    limit[device] = v > 0 ? v : -1;
+  }
+  if (limit[device] < 0 || bytes > (size_t)limit[device]) return false;
+  size_t& g = granted[bounded ? 1 : 0][device];
+  if (bytes > 65536 && bytes > g) {
+    const void* fn = bounded ? reinterpret_cast<const void*>(&k_rescore_subset_lds<true>)
+                             : reinterpret_cast<const void*>(&k_rescore_subset_lds<false>);
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    g = bytes;
+  }
+  return true;
+}
+
 hipError_t launch_rescore_terms(const farm_memory* mem, const farm_workspace* ws, const float* sim, int64_t ld_s,
                                 int32_t q, MetaView meta, const SimBound& bound, const int32_t* cand,
                                 const int32_t* cand_count, int32_t c, const PropView& prop, bool fallback_pass,
@@ -743,6 +845,22 @@ hipError_t launch_rescore_terms(const farm_memory* mem, const farm_workspace* ws
                          ws->qn, mem->dn, mem->ldk, cand, c, g, mem->n, ws->rs_terms, ws->rs_anchor, prop);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+  }
+  if (mode == kTermsSubset) {
+    const size_t lds = (size_t)round_up(mem->n, 4) * sizeof(float);
+    if (lds_row_fits(mem->device, lds, bounded)) {
+      const int32_t R = prop.rel_total;
+      if (R <= 0) return hipSuccess;
+      if (bounded)
+        hipLaunchKernelGGL((k_rescore_subset_lds<true>), dim3((unsigned)R), dim3(kLdsThreads), lds, s, sim, ld_s, q,
+                           meta, bound, ws->qn, mem->dn, mem->ldk, cand, cand_count, c, g, mem->n, ws->rs_terms,
+                           ws->rs_anchor, prop);
+      else
+        hipLaunchKernelGGL((k_rescore_subset_lds<false>), dim3((unsigned)R), dim3(kLdsThreads), lds, s, sim, ld_s, q,
+                           meta, bound, ws->qn, mem->dn, mem->ldk, cand, cand_count, c, g, mem->n, ws->rs_terms,
+                           ws->rs_anchor, prop);
+      return hipGetLastError();
+    }
   }
   if (bounded) {
     if (mode == kTermsSubset) FARM_TERMS(kTermsSubset, true);
