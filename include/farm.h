@@ -176,12 +176,20 @@ typedef enum {
   FARM_METHOD_PROPOSAL = 2
 } farm_method;
 
+/* Option bits of farm_score_opts.flags. */
+typedef enum {
+  /* FARM_METHOD_PROPOSAL: run the proposal pass on similarities gathered from
+     global memory even when a similarity row fits in LDS (the form used
+     for scenes too large to stage); results are identical */
+  FARM_OPT_GLOBAL_PROPOSAL_PASS = 1
+} farm_opt_flags;
+
 /* Options of the fused path. */
 typedef struct {
   int32_t dtype;        /* farm_dtype of the similarity GEMM (FARM_F32 = exact path) */
   int32_t method;       /* farm_method */
   int32_t rescore_mult; /* EXHAUSTIVE with reduced precision: rescore the top rescore_mult*k (>= 1) */
-  int32_t reserved;     /* must be 0 */
+  int32_t flags;        /* farm_opt_flags bits (0 = defaults) */
   int32_t* certified;   /* device [q] out or NULL: 1 when the returned set is provably
                            the exact TopK, else 0 */
 } farm_score_opts;

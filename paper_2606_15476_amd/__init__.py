@@ -15,13 +15,13 @@ import numpy as np
 
 from . import _lib
 from ._lib import (FARM_BUILD_BF16, FARM_BUILD_FP8, FARM_MAX_K, FARM_MAX_REL, FARM_NO_ID, F32, BF16, FP8_E4M3,
-                   EXHAUSTIVE, BOUNDED, PROPOSAL,
+                   EXHAUSTIVE, BOUNDED, PROPOSAL, OPT_GLOBAL_PROPOSAL_PASS,
                    NEAR, ABOVE, BELOW, LEFT_OF, RIGHT_OF, FarmError, lib_path)
 
 __all__ = [
     "Memory", "Workspace", "ProposalNet", "Server", "build_proposals", "get_proposals", "score_query", "topk", "query_topk", "workspace_estimate", "FarmError",
     "FARM_BUILD_BF16", "FARM_BUILD_FP8", "FARM_MAX_K", "FARM_MAX_REL", "FARM_NO_ID", "F32", "BF16",
-    "FP8_E4M3", "EXHAUSTIVE", "BOUNDED", "PROPOSAL", "NEAR", "ABOVE", "BELOW", "LEFT_OF", "RIGHT_OF", "lib_path",
+    "FP8_E4M3", "EXHAUSTIVE", "BOUNDED", "PROPOSAL", "OPT_GLOBAL_PROPOSAL_PASS", "NEAR", "ABOVE", "BELOW", "LEFT_OF", "RIGHT_OF", "lib_path",
 ]
 
 
@@ -180,14 +180,14 @@ def topk(mem: Memory, ws: Workspace, scores, k: int, out_id, out_score, out_inde
 
 def query_topk(mem: Memory, ws: Workspace, target, target_cls, rel_off, rel_pred, rel_anchor, k: int, out_id,
                out_score, out_terms=None, out_anchor_id=None, dtype: int = F32, rescore_mult: int = 4,
-               certified=None, method: int = EXHAUSTIVE, stream=None):
+               certified=None, method: int = EXHAUSTIVE, flags: int = 0, stream=None):
     """farm_query_topk: fused scoring + TopK + ScoredCandidate breakdown."""
     tc, ptc = _host_i32(target_cls)
     ro, pro = _host_i32(rel_off)
     rp, prp = _host_i32(rel_pred)
     q, d = int(target.shape[0]), int(target.shape[1])
     cp = _ptr(certified)
-    opts = _lib.ScoreOpts(int(dtype), int(method), int(rescore_mult), 0, cp.value if cp is not None else None)
+    opts = _lib.ScoreOpts(int(dtype), int(method), int(rescore_mult), int(flags), cp.value if cp is not None else None)
     _lib.check(_lib.L.farm_query_topk(mem.handle, ws.handle, q, d, _ptr(target), ptc, pro, prp,
                                       _ptr(rel_anchor) if rel_anchor is not None and rel_anchor.numel() else None,
                                       ctypes.byref(opts), int(k), _ptr(out_id), _ptr(out_score), _ptr(out_terms),

@@ -11,6 +11,7 @@ _PATH = os.path.join(_HERE, "libfarm.so")
 FARM_OK, FARM_ERR_INVALID_ARG, FARM_ERR_OOM, FARM_ERR_HIP, FARM_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 F32, BF16, FP8_E4M3 = 0, 1, 2
 EXHAUSTIVE, BOUNDED, PROPOSAL = 0, 1, 2
+OPT_GLOBAL_PROPOSAL_PASS = 1
 NEAR, ABOVE, BELOW, LEFT_OF, RIGHT_OF = 0, 1, 2, 3, 4
 FARM_MAX_REL = 8
 FARM_MAX_K = 1024
@@ -48,7 +49,7 @@ class ServerConfig(ctypes.Structure):
 
 class ScoreOpts(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int32), ("method", ctypes.c_int32), ("rescore_mult", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("certified", ctypes.c_void_p)]
+                ("flags", ctypes.c_int32), ("certified", ctypes.c_void_p)]
 
 
 def lib_path() -> str:

@@ -633,7 +633,11 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
       set_error("method PROPOSAL needs farm_build_proposals on this memory");
       return FARM_ERR_UNSUPPORTED;
     }
-    if (opts && opts->reserved != 0) { set_error("reserved option field must be 0"); return FARM_ERR_INVALID_ARG; }
+    const int32_t opt_flags = opts ? opts->flags : 0;
+    if (opt_flags & ~FARM_OPT_GLOBAL_PROPOSAL_PASS) {
+      set_error("unknown option flags 0x%x", opt_flags);
+      return FARM_ERR_INVALID_ARG;
+    }
     if (dtype != FARM_F32 && dtype != FARM_BF16 && dtype != FARM_FP8_E4M3) {
       set_error("unknown dtype %d", dtype);
       return FARM_ERR_INVALID_ARG;
@@ -668,10 +672,14 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
       }
       PropView pv;
       if (method == FARM_METHOD_PROPOSAL && mem->prop_m > 0) {
-        PhaseTimer t(ws, s, FARM_PHASE_PROPOSE);
-        FARM_HIP(launch_semantic_sets(ws->sim, ws->ld_s, q, R, mem->n, ws->sem_idx, ws->sem_cnt, ws->sem_tau, s),
-                 "semantic sets");
-        if (dtype != FARM_F32) FARM_HIP(launch_semantic_exact(mem, ws, q, R, s), "semantic similarities");
+        const bool in_lds = !(opt_flags & FARM_OPT_GLOBAL_PROPOSAL_PASS) && proposal_pass_in_lds(mem, dtype != FARM_F32);
+        if (!in_lds) {
+          // the LDS-staged pass selects the semantic sets itself; otherwise a scan per relation row
+          PhaseTimer t(ws, s, FARM_PHASE_PROPOSE);
+          FARM_HIP(launch_semantic_sets(ws->sim, ws->ld_s, q, R, mem->n, ws->sem_idx, ws->sem_cnt, ws->sem_tau, s),
+                   "semantic sets");
+          if (dtype != FARM_F32) FARM_HIP(launch_semantic_exact(mem, ws, q, R, s), "semantic similarities");
+        }
         pv.m = mem->prop_m;
         pv.idx = mem->prop_idx;
         pv.val = mem->prop_val;
@@ -685,6 +693,11 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
         pv.fb_count = ws->fb_count;
         pv.fb_cap = ws->fb_cap;
         pv.rel_total = R;
+        pv.in_lds = in_lds;
+        pv.sem_idx_out = ws->sem_idx;
+        pv.sem_cnt_out = ws->sem_cnt;
+        pv.sem_tau_out = ws->sem_tau;
+        pv.sem_sim_out = ws->sem_sim;
       }
       {
         PhaseTimer t(ws, s, FARM_PHASE_RESCORE);

@@ -224,7 +224,17 @@ struct PropView {
   uint32_t* fb_count = nullptr;
   int64_t fb_cap = 0;
   int32_t rel_total = 0;  // relation rows of the call (one LDS-staged block each)
+  bool in_lds = false;    // run the proposal pass with the rows staged in LDS
+  // where the LDS-staged pass publishes the semantic sets it selects
+  int32_t* sem_idx_out = nullptr;
+  int32_t* sem_cnt_out = nullptr;
+  float* sem_tau_out = nullptr;
+  float* sem_sim_out = nullptr;
 };
+
+// Whether the proposal pass stages similarity rows of this memory in LDS
+// (and then selects the semantic sets itself).
+bool proposal_pass_in_lds(const farm_memory* mem, bool bounded);
 
 // Makes `dev` current for the guard's lifetime.
 struct DeviceGuard {

@@ -426,9 +426,25 @@ __global__ __launch_bounds__(64 * kTermWaves) void k_rescore_terms(
 
 // Proposal pass with the relation's similarity row staged in LDS: one block
 // per relation row serves every candidate of its query, so the list entries'
-// similarity gathers hit LDS instead of L2.  List bounds use the largest
-// descriptor error (no per-anchor gather); the exact values are unchanged.
+// similarity gathers hit LDS instead of L2.  The block also selects the
+// relation's semantic set from the staged row (threshold gamma * max with
+// gamma in 1/2, 3/4, 7/8, ... until at most kSemMax anchors exceed it; the
+// largest similarity outside bounds the rest), takes the members' exact FP32
+// similarities for reduced precision, and publishes the set for the fallback
+// scans.  List bounds use the largest descriptor error (no per-anchor
+// gather); the exact values are unchanged.
 constexpr int kLdsThreads = 512;
+constexpr int kLdsWaves = kLdsThreads / 64;
+
+__device__ inline float block_max_lds(float v, float* red) {
+  v = wave_max_f(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float m = red[0];
+  for (int i = 1; i < kLdsWaves; ++i) m = fmaxf(m, red[i]);
+  return m;
+}
 
 template <bool BOUNDED>
 __global__ __launch_bounds__(kLdsThreads) void k_rescore_subset_lds(
@@ -437,6 +453,10 @@ __global__ __launch_bounds__(kLdsThreads) void k_rescore_subset_lds(
     const int32_t* __restrict__ cand_count, int32_t C, Geo g, int64_t n, float* __restrict__ rs_terms,
     uint32_t* __restrict__ rs_anchor, PropView pv) {
   extern __shared__ float srow[];
+  __shared__ float red[kLdsWaves];
+  __shared__ int32_t set_idx[kSemMax];
+  __shared__ float set_sim[kSemMax];
+  __shared__ int32_t set_n;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int32_t r = blockIdx.x;
   const int32_t qq = meta.rel_query[r];
@@ -447,24 +467,100 @@ __global__ __launch_bounds__(kLdsThreads) void k_rescore_subset_lds(
   const int64_t n4 = n >> 2;
   const float4* a4 = reinterpret_cast<const float4*>(arow);
   float4* s4 = reinterpret_cast<float4*>(srow);
-  for (int64_t i = threadIdx.x; i < n4; i += kLdsThreads) s4[i] = a4[i];
-  for (int64_t j = (n4 << 2) + threadIdx.x; j < n; j += kLdsThreads) srow[j] = arow[j];
+  float mx = 0.f;
+  for (int64_t i = threadIdx.x; i < n4; i += kLdsThreads) {
+    const float4 v = a4[i];
+    s4[i] = v;
+    mx = fmaxf(fmaxf(mx, fmaxf(v.x, v.y)), fmaxf(v.z, v.w));
+  }
+  for (int64_t j = (n4 << 2) + threadIdx.x; j < n; j += kLdsThreads) {
+    srow[j] = arow[j];
+    mx = fmaxf(mx, arow[j]);
+  }
+  const float amax = block_max_lds(mx, red);  // synchronises: the row is staged
+  // semantic set: count above tau, refine tau while more than kSemMax exceed it
+  auto count_above = [&](float tau) {
+    int32_t c = 0;
+    for (int64_t j = threadIdx.x; j < n; j += kLdsThreads) c += srow[j] > tau;
+    // block sum through the wave sums
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    __syncthreads();
+    if (lane == 0) red[wave] = __int_as_float(c);
+    __syncthreads();
+    int32_t t = 0;
+    for (int i = 0; i < kLdsWaves; ++i) t += __float_as_int(red[i]);
+    return t;
+  };
+  float tau = 0.5f * amax, gap = 0.5f * amax;
+  int32_t total = count_above(tau);
+  for (int it = 0; it < 30 && total > kSemMax; ++it) {
+    gap *= 0.5f;
+    tau = amax - gap;
+    total = count_above(tau);
+  }
+  if (threadIdx.x == 0) set_n = 0;
   __syncthreads();
+  float out = 0.f;
+  for (int64_t j = threadIdx.x; j < n; j += kLdsThreads) {
+    const float v = srow[j];
+    bool member = false;
+    if (v > tau) {
+      const int32_t pos = atomicAdd(&set_n, 1);
+      if (pos < kSemMax) {
+        set_idx[pos] = (int32_t)j;
+        member = true;
+      }
+    }
+    if (!member) out = fmaxf(out, v);
+  }
+  const float tau_out = block_max_lds(out, red);  // synchronises: the set is complete
+  const int sn = set_n < kSemMax ? set_n : kSemMax;
+  const float* qrow = qn + (int64_t)(q + r) * ldk;
+  if (BOUNDED) {
+    for (int m = wave; m < sn; m += kLdsWaves) {
+      const float a = fmaxf(0.f, wave_dot(qrow, dn + (int64_t)set_idx[m] * ldk, ldk, lane));
+      if (lane == 0) set_sim[m] = a;
+    }
+  }
+  __syncthreads();
+  // publish the set for the fallback scans
+  if ((int)threadIdx.x < sn) {
+    pv.sem_idx_out[(int64_t)r * kSemMax + threadIdx.x] = set_idx[threadIdx.x];
+    if (BOUNDED) pv.sem_sim_out[(int64_t)r * kSemMax + threadIdx.x] = set_sim[threadIdx.x];
+  }
+  if (threadIdx.x == 0) {
+    pv.sem_cnt_out[r] = sn;
+    pv.sem_tau_out[r] = tau_out;
+  }
   const int32_t cnt = cand_count ? (cand_count[qq] < C ? cand_count[qq] : C) : C;
   const int p = meta.rel_pred[r];
   const float c = sigmoid_scale(p);
-  const float* qrow = qn + (int64_t)(q + r) * ldk;
   const float qnr = BOUNDED ? bound.q_nrm[q + r] : 0.f;
   const float qer = BOUNDED ? bound.q_err[q + r] + bound.acc : 0.f;
   const float err_max = BOUNDED ? *bound.o_err_max : 0.f;
   const float qd = BOUNDED ? fmaf(qnr, err_max, qer) : 0.f;
   unsigned long long checked = 0, fell = 0;
   uint32_t dots = 0;
-  for (int32_t cc = wave; cc < cnt; cc += kLdsThreads / 64) {
+  for (int32_t cc = wave; cc < cnt; cc += kLdsWaves) {
     const int64_t slot = (int64_t)qq * C + cc;
     const int64_t o = cand[slot];
     if (o < 0) continue;
-    const Subset sub = make_subset(pv, r, p, o, n, BOUNDED, qnr, qer, err_max);
+    Subset sub;
+    const int64_t off = ((int64_t)p * n + o) * pv.m;
+    sub.lidx = pv.idx + off;
+    sub.lval = pv.val + off;
+    sub.M = pv.m;
+    sub.sidx = set_idx;
+    sub.sn = sn;
+    sub.ssim = BOUNDED ? set_sim : nullptr;
+    const float pout = pv.out[(int64_t)p * n + o];
+    const float a_hi = BOUNDED ? tau_out + qd : tau_out;
+    if (family_of(p) == kFamNear) {
+      const float b = near_log(a_hi) + pout;
+      sub.cert = b + fabsf(b) * 1e-6f;  // covers the rounding of the logarithm
+    } else {
+      sub.cert = a_hi * pout;
+    }
     float best;
     uint32_t bid;
     bool ok;
@@ -803,7 +899,7 @@ bool lds_row_fits(int device, size_t bytes, bool bounded) {
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) v = -1;
     limit[device] = v > 0 ? v : -1;
   }
-  if (limit[device] < 0 || bytes > (size_t)limit[device]) return false;
+  if (limit[device] < 0 || bytes + 1024 > (size_t)limit[device]) return false;
   size_t& g = granted[bounded ? 1 : 0][device];
   if (bytes > 65536 && bytes > g) {
     const void* fn = bounded ? reinterpret_cast<const void*>(&k_rescore_subset_lds<true>)
@@ -815,6 +911,10 @@ bool lds_row_fits(int device, size_t bytes, bool bounded) {
     g = bytes;
   }
   return true;
+}
+
+bool proposal_pass_in_lds(const farm_memory* mem, bool bounded) {
+  return lds_row_fits(mem->device, (size_t)round_up(mem->n, 4) * sizeof(float), bounded);
 }
 
 hipError_t launch_rescore_terms(const farm_memory* mem, const farm_workspace* ws, const float* sim, int64_t ld_s,
@@ -848,7 +948,7 @@ hipError_t launch_rescore_terms(const farm_memory* mem, const farm_workspace* ws
   }
   if (mode == kTermsSubset) {
     const size_t lds = (size_t)round_up(mem->n, 4) * sizeof(float);
-    if (lds_row_fits(mem->device, lds, bounded)) {
+    if (prop.in_lds) {
       const int32_t R = prop.rel_total;
       if (R <= 0) return hipSuccess;
       if (bounded)

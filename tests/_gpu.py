@@ -56,7 +56,7 @@ def score_full(mem, ws, qb, terms=True):
     return s, t, b
 
 
-def query_topk(mem, ws, qb, k, dtype=0, rescore_mult=4, with_cert=False, method=0):
+def query_topk(mem, ws, qb, k, dtype=0, rescore_mult=4, with_cert=False, method=0, flags=0):
     """(ids [q,k] uint32, scores [q,k], terms [q,k,8], anchor ids [q,k,8] uint32[, certified [q]]) as numpy."""
     import torch
     import paper_2606_15476_amd as farm
@@ -68,7 +68,7 @@ def query_topk(mem, ws, qb, k, dtype=0, rescore_mult=4, with_cert=False, method=
     ob = torch.empty((q, k, 8), dtype=torch.int32, device=device())
     cert = torch.full((q,), -1, dtype=torch.int32, device=device())
     farm.query_topk(mem, ws, target, qb.target_cls, qb.rel_off, qb.rel_pred, anchors, k, oid, osc, ot, ob,
-                    dtype=dtype, rescore_mult=rescore_mult, certified=cert, method=method)
+                    dtype=dtype, rescore_mult=rescore_mult, certified=cert, method=method, flags=flags)
     torch.cuda.synchronize()
     out = (oid.cpu().numpy().view(np.uint32), osc.cpu().numpy(), ot.cpu().numpy(), ob.cpu().numpy().view(np.uint32))
     return out + (cert.cpu().numpy(),) if with_cert else out

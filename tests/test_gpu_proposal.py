@@ -80,12 +80,18 @@ def test_tables_match_oracle(farm):
 
 
 def _compare(farm, mem, ws, qb, k, dtype):
+    """PROPOSAL (LDS-staged and global-memory forms of its pass) against BOUNDED."""
     from tests import _gpu
     bd = _gpu.query_topk(mem, ws, qb, k, dtype=dtype, with_cert=True, method=farm.BOUNDED)
     ws.proposal_stats(reset=True)
     pr = _gpu.query_topk(mem, ws, qb, k, dtype=dtype, with_cert=True, method=farm.PROPOSAL)
     checked, fell = ws.proposal_stats(reset=True)[:2]
     for a, b in zip(pr, bd):
+        np.testing.assert_array_equal(a, b)
+    pg = _gpu.query_topk(mem, ws, qb, k, dtype=dtype, with_cert=True, method=farm.PROPOSAL,
+                         flags=farm.OPT_GLOBAL_PROPOSAL_PASS)
+    ws.proposal_stats(reset=True)
+    for a, b in zip(pg, bd):
         np.testing.assert_array_equal(a, b)
     return checked, fell
 
