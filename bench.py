@@ -70,8 +70,8 @@ def recorded_traffic(kernel: str, workload: str):
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=3)
-    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--workload", default="precision")
     p.add_argument("--form", default="bf16", choices=["f32", "bf16", "fp8"])
     p.add_argument("--rescore-mult", type=int, default=4)
@@ -261,6 +261,13 @@ def serving(args):
                        qb.rel_anchor.reshape(-1, d)[qb.rel_off[q]:qb.rel_off[q + 1]]) for q in range(qb.q)])
     log(f"[serve] 16 scenes, N = {sorted(int(x) for x in sizes)}")
     forms = {"f32-exhaustive": (farm.F32, farm.EXHAUSTIVE), "bf16-bounded": (farm.BF16, farm.BOUNDED)}
+    if args.train_scenes > 0:
+        # the learned-proposal form: one network trained on training scenes of the generator, lists per scene
+        net = train_network(farm, cfg, args)
+        for m in scenes:
+            farm.build_proposals(m, net, args.list_m)
+        torch.cuda.synchronize()
+        forms["bf16-proposal"] = (farm.BF16, farm.PROPOSAL)
     results = []
     for rate in [float(x) for x in args.rates.split(",")]:
         gaps = rng.exponential(1.0 / rate, args.requests)
@@ -301,10 +308,9 @@ def serving(args):
                       "results": results}), flush=True)
 
 
-def prepare_proposals(farm, cfg, mem, args):
-    """Train the proposal network on exhaustive bindings of training scenes of
-    the same generator (seeds 1000, 1001, ...), then build the lists of the
-    benchmark scene.  Outside the timed region, like farm_build_memory."""
+def train_network(farm, cfg, args):
+    """The proposal network trained on exhaustive bindings of training scenes of
+    the generator (seeds 1000, 1001, ...)."""
     import torch
     from paper_2606_15476_amd import proposal
     from synth import make_queries, make_scene
@@ -324,19 +330,30 @@ def prepare_proposals(farm, cfg, mem, args):
         keep.append(w)
         log(f"[bench] training scene {seed}: {o.size} examples")
     t_data = time.time() - t0
-    net = farm.ProposalNet(mem.d, max_batch=4096, seed=7)
+    net = farm.ProposalNet(cfg.d, max_batch=4096, seed=7)
     t1 = time.time()
     hist = proposal.train(net, data, steps=args.train_steps, batch=4096, lr=2e-3, weight_decay=1e-4)
     t_train = time.time() - t1
     log(f"[bench] trained {args.train_steps} steps in {t_train:.1f}s: loss {hist[0][1]:.4f} -> {hist[-1][1]:.4f}")
-    del data, keep
+    net.history, net.label_s, net.train_s = hist, t_data, t_train
+    return net
+
+
+def prepare_proposals(farm, cfg, mem, args):
+    """Train the proposal network, then build the lists of the benchmark scene.
+    Outside the timed region, like farm_build_memory."""
+    import torch
+    net = train_network(farm, cfg, args)
+    hist = net.history
     t2 = time.time()
     farm.build_proposals(mem, net, args.list_m)
     torch.cuda.synchronize()
     t_build = time.time() - t2
     log(f"[bench] proposal lists (M={args.list_m}) built in {t_build:.2f}s")
-    return {"train_scenes": args.train_scenes, "train_steps": args.train_steps, "loss_first": round(hist[0][1], 5),
-            "loss_last": round(hist[-1][1], 5), "label_s": round(t_data, 2), "train_s": round(t_train, 2),
+    dtype = {"f32": farm.F32, "bf16": farm.BF16, "fp8": farm.FP8_E4M3}[args.form]
+    return {"pass_in_lds": mem.proposal_pass_in_lds(dtype),
+            "train_scenes": args.train_scenes, "train_steps": args.train_steps, "loss_first": round(hist[0][1], 5),
+            "loss_last": round(hist[-1][1], 5), "label_s": round(net.label_s, 2), "train_s": round(net.train_s, 2),
             "table_build_s": round(t_build, 3), "list_m": args.list_m}
 
 
@@ -379,14 +396,15 @@ def dominant_roofline(phases, scene, qb, args, cfg, proposal_info):
     info = proposal_info or {}
     terms, m, dots = info.get("terms_per_step", 0), info.get("list_m", 0), info.get("fp32_dots_per_step", 0)
     if dominant == "rescore" and info:
+        kernel = "k_rescore_subset_lds" if info.get("pass_in_lds") else "k_rescore_terms<subset>"
         # proposal terms: per term the list (4 B index + 4 B cached value + 4 B gathered
         # similarity per entry) and the semantic set (4 B index + 4 B similarity per
         # member, at most 64); per FP32 dot product one descriptor row (4 B x D)
         nbytes = float(terms) * (m * 12.0 + 64 * 8.0) + float(dots) * 4.0 * scene.d
         achieved = nbytes / avg_s / 1e9
-        return {"bound": "hbm", "kernel": "k_rescore_terms<subset>", "achieved": round(achieved, 1),
+        return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                "traffic": recorded_traffic("k_rescore_terms", cfg.name), "avg_launch_ms": round(avg_s * 1e3, 3),
+                "traffic": recorded_traffic(kernel, cfg.name), "avg_launch_ms": round(avg_s * 1e3, 3),
                 "algorithmic_bytes_per_launch": nbytes}
     # full anchor scans of candidate terms: pair evaluations on the ALU
     per_pair = float(np.mean([FLOP_PER_PAIR[int(p)] for p in qb.rel_pred])) if R else 0.0

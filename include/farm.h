@@ -327,6 +327,14 @@ FARM_API farm_status farm_get_proposals(const farm_memory* mem, int32_t* m_out, 
                                         void* stream);
 
 /*
+ * Which form FARM_METHOD_PROPOSAL uses on this memory for a similarity dtype:
+ * *in_lds = 1 when each relation's similarity row is staged in LDS (one block
+ * per row, the semantic set selected in the same kernel), 0 when the pass
+ * gathers similarities from global memory (rows too large for LDS).
+ */
+FARM_API farm_status farm_proposal_pass_form(const farm_memory* mem, int32_t dtype, int32_t* in_lds);
+
+/*
  * Candidate-scoring counters of a workspace since the last reset (host [4]):
  * stats[0] = (candidate, relation) terms evaluated by FARM_METHOD_PROPOSAL,
  * stats[1] = those that fell back to the scan over all anchors,

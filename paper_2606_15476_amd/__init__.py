@@ -85,6 +85,12 @@ class Memory:
         _lib.check(_lib.L.farm_memory_info(self.handle, None, None, ctypes.byref(b)))
         return int(b.value)
 
+    def proposal_pass_in_lds(self, dtype: int = F32) -> bool:
+        """Whether FARM_METHOD_PROPOSAL stages similarity rows in LDS on this memory."""
+        v = ctypes.c_int32()
+        _lib.check(_lib.L.farm_proposal_pass_form(self.handle, int(dtype), ctypes.byref(v)))
+        return bool(v.value)
+
     def close(self):
         if getattr(self, "_h", None) is not None:
             _lib.L.farm_free_memory(self._h)

@@ -24,7 +24,7 @@ EXPORTS = (
     "farm_workspace_status", "farm_last_error", "farm_version", "farm_workspace_set_timing",
     "farm_workspace_timings", "farm_mlp_create", "farm_mlp_free", "farm_mlp_shape", "farm_mlp_get_weights",
     "farm_mlp_get_grads", "farm_mlp_set_weights", "farm_mlp_inputs", "farm_mlp_logits", "farm_mlp_step",
-    "farm_build_proposals", "farm_workspace_proposal_stats", "farm_get_proposals",
+    "farm_build_proposals", "farm_workspace_proposal_stats", "farm_get_proposals", "farm_proposal_pass_form",
     "farm_server_create", "farm_server_add_scene", "farm_server_submit", "farm_server_cancel", "farm_server_progress",
     "farm_server_poll", "farm_server_stats", "farm_server_free",
 )
@@ -86,6 +86,7 @@ def _declare(lib):
         "farm_build_proposals": [P, P, i32, P],
         "farm_workspace_proposal_stats": [P, ctypes.POINTER(i64), i32, P],
         "farm_get_proposals": [P, ctypes.POINTER(i32), P, P, P, P],
+        "farm_proposal_pass_form": [P, i32, ctypes.POINTER(i32)],
         "farm_server_create": [ctypes.POINTER(ServerConfig), pp],
         "farm_server_add_scene": [P, P, ctypes.POINTER(i32)],
         "farm_server_submit": [P, i32, i32, P, i32, i32, P, P, ctypes.POINTER(ctypes.c_uint64)],

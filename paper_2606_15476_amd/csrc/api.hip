@@ -531,6 +531,13 @@ farm_status farm_workspace_bytes(const farm_workspace* ws, size_t* bytes) {
   return FARM_OK;
 }
 
+farm_status farm_proposal_pass_form(const farm_memory* mem, int32_t dtype, int32_t* in_lds) {
+  if (!mem || !in_lds) { set_error("null memory or output"); return FARM_ERR_INVALID_ARG; }
+  DeviceGuard g(mem->device);
+  *in_lds = proposal_pass_in_lds(mem, dtype != FARM_F32) ? 1 : 0;
+  return FARM_OK;
+}
+
 farm_status farm_workspace_proposal_stats(farm_workspace* ws, int64_t* stats, int32_t reset, void* stream) {
   if (!ws || !stats) { set_error("null workspace or output"); return FARM_ERR_INVALID_ARG; }
   DeviceGuard g(ws->device);

@@ -167,6 +167,7 @@ struct farm_mlp {
   uint16_t* dZ = nullptr;    // [bpad][h]
   uint16_t* dZT = nullptr;   // [h][bpad]
   float* loss_part = nullptr;
+  float* red_part = nullptr;  // partial sums of the chunked batch reductions
   std::vector<void*> allocs;
   size_t bytes = 0;
 };

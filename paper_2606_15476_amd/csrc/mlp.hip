@@ -140,19 +140,51 @@ __global__ void k_sum_parts(const float* __restrict__ part, int32_t nparts, int3
   *out = s / (float)nb;
 }
 
-// gW3[c][k] = sum_b dY[b][c] A2[b][k]; gb3[c] = sum_b dY[b][c]
-__global__ void k_head_grad(const float* __restrict__ dY, const uint16_t* __restrict__ A2, int32_t nb, int32_t h,
-                            float* __restrict__ gW3, float* __restrict__ gb3) {
+// Batch reductions run in two deterministic stages: chunks of kRedRows rows
+// give partial sums (one thread per output column and chunk), then the
+// partials are added in chunk order.
+constexpr int kRedRows = 128;
+
+// partial gW3[c][k] (k < h) and gb3[c] (k == h) over rows of chunk blockIdx.y
+__global__ void k_head_grad_part(const float* __restrict__ dY, const uint16_t* __restrict__ A2, int32_t nb,
+                                 int32_t h, float* __restrict__ part) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= kNPred * (h + 1)) return;
+  const int cols = kNPred * (h + 1);
+  if (t >= cols) return;
   const int c = t / (h + 1), k = t % (h + 1);
+  const int64_t b0 = (int64_t)blockIdx.y * kRedRows, b1 = b0 + kRedRows < nb ? b0 + kRedRows : nb;
   float acc = 0.f;
-  if (k < h) {
-    for (int64_t b = 0; b < nb; ++b) acc = fmaf(dY[b * kNPred + c], from_bf16(A2[b * h + k]), acc);
-    gW3[c * h + k] = acc;
+  if (k < h)
+    for (int64_t b = b0; b < b1; ++b) acc = fmaf(dY[b * kNPred + c], from_bf16(A2[b * h + k]), acc);
+  else
+    for (int64_t b = b0; b < b1; ++b) acc += dY[b * kNPred + c];
+  part[(int64_t)blockIdx.y * cols + t] = acc;
+}
+
+// partial column sums of dZ over rows of chunk blockIdx.y
+__global__ void k_colsum_part(const uint16_t* __restrict__ dZ, int32_t nb, int32_t h, float* __restrict__ part) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= h) return;
+  const int64_t b0 = (int64_t)blockIdx.y * kRedRows, b1 = b0 + kRedRows < nb ? b0 + kRedRows : nb;
+  float acc = 0.f;
+  for (int64_t b = b0; b < b1; ++b) acc += from_bf16(dZ[b * h + k]);
+  part[(int64_t)blockIdx.y * h + k] = acc;
+}
+
+// out[t] = sum over chunks of part[chunk][t], in chunk order; the head's
+// columns are split into gW3 ([c][h]) and gb3 ([c]) when w3 is set
+__global__ void k_sum_chunks(const float* __restrict__ part, int32_t chunks, int32_t cols, int32_t h, bool w3,
+                             float* __restrict__ out, float* __restrict__ out_b) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cols) return;
+  float acc = 0.f;
+  for (int i = 0; i < chunks; ++i) acc += part[(int64_t)i * cols + t];
+  if (!w3) {
+    out[t] = acc;
   } else {
-    for (int64_t b = 0; b < nb; ++b) acc += dY[b * kNPred + c];
-    gb3[c] = acc;
+    const int c = t / (h + 1), k = t % (h + 1);
+    if (k < h) out[c * h + k] = acc;
+    else out_b[c] = acc;
   }
 }
 
@@ -173,15 +205,6 @@ __global__ void k_gelu_back(const float* __restrict__ dA, const float* __restric
                             uint16_t* __restrict__ dZ) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < total) dZ[i] = bf16(dA[i] * gelu_grad(Z[i]));
-}
-
-// column sums over nb rows (bias gradients)
-__global__ void k_colsum(const uint16_t* __restrict__ dZ, int32_t nb, int32_t h, float* __restrict__ out) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= h) return;
-  float acc = 0.f;
-  for (int64_t b = 0; b < nb; ++b) acc += from_bf16(dZ[b * h + k]);
-  out[k] = acc;
 }
 
 __global__ void k_adamw(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
@@ -275,7 +298,8 @@ farm_status alloc_mlp(farm_mlp* m) {
             take(&m->X, B * ldx) && take(&m->XT, ldx * B) && take(&m->Z1, B * h) && take(&m->Z2, B * h) &&
             take(&m->A1, B * h) && take(&m->A1T, h * B) && take(&m->A2, B * h) && take(&m->Y, B * kNPred) &&
             take(&m->dY, B * kNPred) && take(&m->dA, B * h) && take(&m->dZ, B * h) && take(&m->dZT, h * B) &&
-            take(&m->loss_part, B / 256 + 1);
+            take(&m->loss_part, B / 256 + 1) &&
+            take(&m->red_part, (B / kRedRows + 1) * (kNPred * (h + 1)));
   if (!ok) {
     (void)hipGetLastError();
     return FARM_ERR_OOM;
@@ -450,14 +474,20 @@ farm_status farm_mlp_step(farm_mlp* m, const farm_memory* mem, int32_t nb, const
     hipLaunchKernelGGL(k_bce, dim3(nparts), dim3(256), 0, s, m->Y, pred, label, nb, m->dY, m->loss_part);
     if (loss_out) hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, m->loss_part, (int32_t)nparts, nb, loss_out);
     // head
-    hipLaunchKernelGGL(k_head_grad, dim3(blocks(kNPred * (h + 1))), dim3(256), 0, s, m->dY, m->A2, nb, (int32_t)h,
-                       m->gW3, m->gb3);
+    const unsigned chunks = (unsigned)((nb + kRedRows - 1) / kRedRows);
+    const int32_t head_cols = kNPred * (int32_t)(h + 1);
+    hipLaunchKernelGGL(k_head_grad_part, dim3(blocks(head_cols), chunks), dim3(256), 0, s, m->dY, m->A2, nb,
+                       (int32_t)h, m->red_part);
+    hipLaunchKernelGGL(k_sum_chunks, dim3(blocks(head_cols)), dim3(256), 0, s, m->red_part, (int32_t)chunks,
+                       head_cols, (int32_t)h, true, m->gW3, m->gb3);
     hipLaunchKernelGGL(k_head_back, dim3(blocks((int64_t)nb * h)), dim3(256), 0, s, m->dY, m->W3r, m->Z2, nb,
                        (int32_t)h, m->dZ);
     if (nbp > nb)
       hipLaunchKernelGGL(k_zero_u16, dim3(blocks((nbp - nb) * h)), dim3(256), 0, s, m->dZ + nb * h, (nbp - nb) * h);
     // layer 2
-    hipLaunchKernelGGL(k_colsum, dim3(blocks(h)), dim3(256), 0, s, m->dZ, nb, (int32_t)h, m->gb2);
+    hipLaunchKernelGGL(k_colsum_part, dim3(blocks(h), chunks), dim3(256), 0, s, m->dZ, nb, (int32_t)h, m->red_part);
+    hipLaunchKernelGGL(k_sum_chunks, dim3(blocks(h)), dim3(256), 0, s, m->red_part, (int32_t)chunks, (int32_t)h,
+                       (int32_t)h, false, m->gb2, nullptr);
     hipLaunchKernelGGL(k_transpose_u16, dim3(blocks(h, 32), blocks(nbp, 32)), dim3(32, 8), 0, s, m->dZ, nbp, h, h,
                        m->dZT, nbp);
     hipLaunchKernelGGL(k_transpose_u16, dim3(blocks(h, 32), blocks(nbp, 32)), dim3(32, 8), 0, s, m->A1, nbp, h, h,
@@ -469,7 +499,9 @@ farm_status farm_mlp_step(farm_mlp* m, const farm_memory* mem, int32_t nb, const
     // layer 1
     hipLaunchKernelGGL(k_gelu_back, dim3(blocks((int64_t)nb * h)), dim3(256), 0, s, m->dA, m->Z1, (int64_t)nb * h,
                        m->dZ);
-    hipLaunchKernelGGL(k_colsum, dim3(blocks(h)), dim3(256), 0, s, m->dZ, nb, (int32_t)h, m->gb1);
+    hipLaunchKernelGGL(k_colsum_part, dim3(blocks(h), chunks), dim3(256), 0, s, m->dZ, nb, (int32_t)h, m->red_part);
+    hipLaunchKernelGGL(k_sum_chunks, dim3(blocks(h)), dim3(256), 0, s, m->red_part, (int32_t)chunks, (int32_t)h,
+                       (int32_t)h, false, m->gb1, nullptr);
     hipLaunchKernelGGL(k_transpose_u16, dim3(blocks(h, 32), blocks(nbp, 32)), dim3(32, 8), 0, s, m->dZ, nbp, h, h,
                        m->dZT, nbp);
     hipLaunchKernelGGL(k_transpose_u16, dim3(blocks(ldx, 32), blocks(nbp, 32)), dim3(32, 8), 0, s, m->X, nbp, ldx,

@@ -218,35 +218,48 @@ __device__ bool subset_term(const float* arow, const float* __restrict__ qrow, c
       const float a = sub.ssim[e - sub.M];
       take_max_j(entry(e, j, a, FAM == kFamNear ? near_log(a) : 0.f), j, g.ids, best, bj);
     }
-    // list entries: bounds from the reduced-precision similarity
+    // list entries: lower and upper bounds from the reduced-precision
+    // similarity, a~ -+ delta; only entries whose upper bound reaches the best
+    // lower bound L (the semantic set's exact values included) can be the
+    // maximum, and each of those needs an FP32 dot product.
+    auto value_at = [&](int e, int64_t j, float a) { return entry(e, j, a, FAM == kFamNear ? near_log(a) : 0.f); };
+    auto upper = [&](int e, int64_t j) { return value_at(e, j, fminf(1.0f, arow[j] + delta(j))); };
     float lo = best;
     for (int e = lane; e < sub.M; e += 64) {
       const int64_t j = anchor_of(e);
       if (j == o) continue;
-      const float a = fmaxf(0.f, arow[j] - delta(j));
-      lo = fmaxf(lo, entry(e, j, a, FAM == kFamNear ? near_log(a) : 0.f));
+      lo = fmaxf(lo, value_at(e, j, fmaxf(0.f, arow[j] - delta(j))));
     }
     lo = wave_max_f(lo);
     const float L = lo - (fabsf(lo) * 1e-6f + 1e-30f);  // slack for rounding of the bounded values
+    // survivors in index order; each exact value raises B, and a survivor
+    // whose upper bound has fallen below B (beyond the rounding slack, so ties
+    // are still resolved exactly) is skipped without its dot product
+    float B = wave_max_f(best);
     for (int base = 0; base < sub.M; base += 64) {
       const int e = base + lane;
+      float u = -INFINITY;
       bool f = false;
       if (e < sub.M) {
         const int64_t j = anchor_of(e);
         if (j != o) {
-          const float a = fminf(1.0f, arow[j] + delta(j));
-          f = entry(e, j, a, FAM == kFamNear ? near_log(a) : 0.f) >= L;
+          u = upper(e, j);
+          f = u >= L;
         }
       }
       uint64_t mask = __ballot(f);
       while (mask) {
         const int src = __ffsll((unsigned long long)mask) - 1;
         mask &= mask - 1;
+        const float us = __shfl(u, src);
+        if (us < B - (fabsf(B) * 1e-6f + 1e-30f)) continue;
         const int e2 = base + src;
         const int64_t j2 = anchor_of(e2);
         const float a = fmaxf(0.f, wave_dot(qrow, dn + j2 * ldk, ldk, lane));
         ++dots;
-        take_max_j(entry(e2, j2, a, FAM == kFamNear ? near_log(a) : 0.f), j2, g.ids, best, bj);
+        const float v = value_at(e2, j2, a);
+        take_max_j(v, j2, g.ids, best, bj);
+        B = fmaxf(B, v);
       }
     }
   }
