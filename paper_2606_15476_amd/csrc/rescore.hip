@@ -55,6 +55,28 @@ __device__ inline float wave_dot(const float* __restrict__ a, const float* __res
   return wave_sum(acc);
 }
 
+// NN dot products against the same row `a`, interleaved for memory-level
+// parallelism; each one with exactly wave_dot's arithmetic (same per-lane
+// order, same reduction tree), so the values are bit-identical.
+template <int NN>
+__device__ inline void wave_dots(const float* __restrict__ a, const float* const (&b)[NN], int32_t ldk, int lane,
+                                 float (&out)[NN]) {
+  float acc[NN];
+#pragma unroll
+  for (int u = 0; u < NN; ++u) acc[u] = 0.f;
+  for (int k = 2 * lane; k < ldk; k += 128) {
+    const float2 x = *reinterpret_cast<const float2*>(a + k);
+#pragma unroll
+    for (int u = 0; u < NN; ++u) {
+      const float2 y = *reinterpret_cast<const float2*>(b[u] + k);
+      acc[u] = fmaf(x.x, y.x, acc[u]);
+      acc[u] = fmaf(x.y, y.y, acc[u]);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NN; ++u) out[u] = wave_sum(acc[u]);
+}
+
 __device__ inline bool better(float v, uint32_t id, float bv, uint32_t bid) {
   return v > bv || (v == bv && id < bid);
 }
@@ -530,9 +552,17 @@ __global__ __launch_bounds__(kLdsThreads) void k_rescore_subset_lds(
   const int sn = set_n < kSemMax ? set_n : kSemMax;
   const float* qrow = qn + (int64_t)(q + r) * ldk;
   if (BOUNDED) {
-    for (int m = wave; m < sn; m += kLdsWaves) {
-      const float a = fmaxf(0.f, wave_dot(qrow, dn + (int64_t)set_idx[m] * ldk, ldk, lane));
-      if (lane == 0) set_sim[m] = a;
+    // four members per wave at a time (members past the set repeat the last one and are dropped)
+    for (int m0 = 4 * wave; m0 < sn; m0 += 4 * kLdsWaves) {
+      const float* rows[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) rows[u] = dn + (int64_t)set_idx[m0 + u < sn ? m0 + u : sn - 1] * ldk;
+      float d[4];
+      wave_dots<4>(qrow, rows, ldk, lane, d);
+      if (lane == 0)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (m0 + u < sn) set_sim[m0 + u] = fmaxf(0.f, d[u]);
     }
   }
   __syncthreads();
