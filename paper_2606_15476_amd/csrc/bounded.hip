@@ -10,13 +10,13 @@
 // s_sem_lo = s_sem_hi = s_sem; with BF16/FP8 similarities they are the
 // estimate minus/plus its proven error bound.
 //
-// One block per query: L is found from per-thread sorted top-16 lists in
-// registers and K rounds of a block arg-max (K <= 16), or by a 4-round radix
-// select on the IEEE bits of the non-negative lower bounds (larger K); an ordered
-// compaction (per-thread contiguous chunks + block prefix scan) lists the
-// candidates in index order.  If more than `cap` objects survive, the list
-// keeps the `cap` largest upper bounds (a second radix select) and the query
-// is marked uncertified.
+// One block per query: L is found from per-thread sorted top-16 lists and K
+// rounds of a block arg-max (K <= 16), or by a 4-round radix select on the
+// IEEE bits of the non-negative lower bounds (larger K), and the candidates
+// are compacted (an LDS counter for K <= 16, an ordered block scan
+// otherwise).  If more than `cap` objects survive, the list keeps the `cap`
+// largest upper bounds (a second radix select) and the query is marked
+// uncertified.
 #include <math.h>
 
 #include "farm_internal.h"
@@ -188,21 +188,24 @@ __global__ __launch_bounds__(kThreads) void k_bound_candidates(const float* __re
 }
 
 
-// Wave-per-query form for K <= kSmallK (the common case): no block barriers;
-// every pass reads the similarity row with unit-stride lanes (coalesced), the
-// K-th lower bound comes from per-lane sorted top-K lists and K rounds of a
-// wave arg-max, and the ordered compaction uses ballots: the position of an
-// object is the number of qualifying objects before it in index order.
-constexpr int kWavesPerBlock = 4;
-
-__global__ __launch_bounds__(64 * kWavesPerBlock) void k_bound_candidates_wave(
-    const float* __restrict__ sim, int64_t ld_s, int64_t n, int32_t q, MetaView meta, SimBound bound,
+// Block-per-query form for K <= kSmallK: four waves share a query's row (more
+// loads in flight than one wave), per-thread sorted top-K lists and K rounds
+// of a block arg-max give L, and the candidates are compacted through an LDS
+// counter (one atomic per wave and 64 objects; their order is immaterial, the
+// final selection sorts by score and id).  More than `cap` candidates: the
+// `cap` largest upper bounds are kept (radix select) and the query is marked
+// uncertified.
+__global__ __launch_bounds__(kThreads) void k_bound_candidates_block(
+    const float* __restrict__ sim, int64_t ld_s, int64_t n, MetaView meta, SimBound bound,
     const int32_t* __restrict__ cls, int32_t k, int32_t cap, int32_t* __restrict__ cand, int32_t* __restrict__ count,
     int32_t* __restrict__ certified) {
-  __shared__ uint32_t hist_all[kWavesPerBlock][256];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int32_t qq = blockIdx.x * kWavesPerBlock + w;
-  if (qq >= q) return;  // the whole wave leaves; no block barrier follows
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t word[2];
+  __shared__ float wv[kThreads / 64];
+  __shared__ int32_t wt[kThreads / 64];
+  __shared__ int32_t filled;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int32_t qq = blockIdx.x;
   const float* srow = sim + (int64_t)qq * ld_s;
   const int tc = meta.tcls[qq];
   float L = -INFINITY;
@@ -210,7 +213,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_bound_candidates_wave(
     float top[kSmallK];
 #pragma unroll
     for (int e = 0; e < kSmallK; ++e) top[e] = -INFINITY;
-    for (int64_t i = lane; i < n; i += 64) {
+    for (int64_t i = tid; i < n; i += kThreads) {
       const float v = (1.0f - kW) * sem_bounds(srow, i, tc, cls, bound, qq).lo;
       if (v > top[kSmallK - 1]) {
 #pragma unroll
@@ -219,73 +222,68 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_bound_candidates_wave(
       }
     }
     for (int round = 0; round < k; ++round) {
+      // largest head in each wave (lowest lane on ties), then across the waves (lowest thread)
       float m = top[0];
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
       const uint64_t holders = __ballot(top[0] == m);
-      const int winner = __ffsll((unsigned long long)holders) - 1;
-      if (lane == winner) {
+      if (lane == 0) {
+        wv[w] = m;
+        wt[w] = w * 64 + __ffsll((unsigned long long)holders) - 1;
+      }
+      __syncthreads();
+      float bm = wv[0];
+      int bt = wt[0];
+      for (int i = 1; i < kThreads / 64; ++i)
+        if (wv[i] > bm) {
+          bm = wv[i];
+          bt = wt[i];
+        }
+      if (tid == bt) {
 #pragma unroll
         for (int e = 0; e < kSmallK - 1; ++e) top[e] = top[e + 1];
         top[kSmallK - 1] = -INFINITY;
       }
-      L = m;
+      L = bm;
+      __syncthreads();
     }
   }
   const uint64_t below = (1ull << lane) - 1ull;
-  auto compact = [&](float thresh, bool write) {
-    int32_t total = 0;
-    for (int64_t base = 0; base < n; base += 64) {
+  auto compact = [&](float thresh) {
+    if (tid == 0) filled = 0;
+    __syncthreads();
+    for (int64_t base = (int64_t)w * 64; base < n; base += kThreads) {
       const int64_t i = base + lane;
       const bool f = i < n && sem_bounds(srow, i, tc, cls, bound, qq).hi >= thresh;
       const uint64_t mask = __ballot(f);
-      if (write && f) {
-        const int32_t pos = total + __popcll(mask & below);
+      if (!mask) continue;
+      int32_t first = 0;
+      if (lane == 0) first = atomicAdd(&filled, (int32_t)__popcll(mask));
+      first = __shfl(first, 0);
+      if (f) {
+        const int32_t pos = first + __popcll(mask & below);
         if (pos < cap) cand[(int64_t)qq * cap + pos] = (int32_t)i;
       }
-      total += __popcll(mask);
     }
-    return total;
+    __syncthreads();
+    return filled;
   };
-  int32_t total = compact(L, true);
+  int32_t total = compact(L);
   bool exact = true;
   if (total > cap) {
-    // keep the cap largest upper bounds: radix select of the cap-th largest on this wave's histogram
-    uint32_t* hist = hist_all[w];
-    uint32_t prefix = 0, mask = 0;
-    int64_t remaining = cap;
-    for (int shift = 24; shift >= 0; shift -= 8) {
-      for (int b = lane; b < 256; b += 64) hist[b] = 0;
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      for (int64_t i = lane; i < n; i += 64) {
-        const float h = sem_bounds(srow, i, tc, cls, bound, qq).hi;
-        const uint32_t u = h >= L ? __float_as_uint(h) : 0u;
-        if ((u & mask) == prefix) atomicAdd(&hist[(u >> shift) & 0xFFu], 1u);
-      }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      int bin = 255;
-      int64_t acc = 0;
-      for (; bin > 0; --bin) {
-        if (acc + (int64_t)hist[bin] >= remaining) break;
-        acc += hist[bin];
-      }
-      remaining -= acc;
-      prefix |= (uint32_t)bin << shift;
-      mask |= 0xFFu << shift;
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-    }
-    total = compact(fmaxf(L, __uint_as_float(prefix)), true);
+    auto hi_key = [&](int64_t i) {
+      const float h = sem_bounds(srow, i, tc, cls, bound, qq).hi;
+      return h >= L ? __float_as_uint(h) : 0u;
+    };
+    const float thresh = fmaxf(L, __uint_as_float(radix_select_kth(n, cap, hi_key, hist, word)));
+    total = compact(thresh);
     exact = false;
   }
-  if (lane == 0) {
+  if (tid == 0) {
     count[qq] = total < cap ? total : cap;
     if (certified) certified[qq] = exact ? 1 : 0;
   }
 }
-
 }  // namespace
 
 hipError_t launch_bound_candidates(const farm_memory* mem, const float* sim, int64_t ld_s, int32_t q, MetaView meta,
@@ -293,9 +291,8 @@ hipError_t launch_bound_candidates(const farm_memory* mem, const float* sim, int
                                    int32_t* certified, hipStream_t s) {
   if (q <= 0) return hipSuccess;
   if (k <= kSmallK) {
-    const unsigned blocks = (unsigned)((q + kWavesPerBlock - 1) / kWavesPerBlock);
-    hipLaunchKernelGGL(k_bound_candidates_wave, dim3(blocks), dim3(64 * kWavesPerBlock), 0, s, sim, ld_s, mem->n, q,
-                       meta, bound, mem->cls, k, cap, cand, count, certified);
+    hipLaunchKernelGGL(k_bound_candidates_block, dim3((unsigned)q), dim3(kThreads), 0, s, sim, ld_s, mem->n, meta,
+                       bound, mem->cls, k, cap, cand, count, certified);
   } else {
     hipLaunchKernelGGL(k_bound_candidates, dim3((unsigned)q), dim3(kThreads), 0, s, sim, ld_s, mem->n, meta, bound,
                        mem->cls, k, cap, cand, count, certified);
