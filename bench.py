@@ -396,11 +396,13 @@ def dominant_roofline(phases, scene, qb, args, cfg, proposal_info):
     info = proposal_info or {}
     terms, m, dots = info.get("terms_per_step", 0), info.get("list_m", 0), info.get("fp32_dots_per_step", 0)
     if dominant == "rescore" and info:
-        kernel = "k_rescore_subset_lds" if info.get("pass_in_lds") else "k_rescore_terms<subset>"
-        # proposal terms: per term the list (4 B index + 4 B cached value + 4 B gathered
-        # similarity per entry) and the semantic set (4 B index + 4 B similarity per
-        # member, at most 64); per FP32 dot product one descriptor row (4 B x D)
-        nbytes = float(terms) * (m * 12.0 + 64 * 8.0) + float(dots) * 4.0 * scene.d
+        in_lds = bool(info.get("pass_in_lds"))
+        kernel = "k_rescore_subset_lds" if in_lds else "k_rescore_terms<subset>"
+        # proposal pass: each relation's similarity row once (4 B per object); per term the
+        # list (4 B index + 4 B cached value per entry; + a 4 B similarity gather from global
+        # memory when the row is not staged in LDS); per FP32 dot product (semantic-set
+        # members and bound survivors) one descriptor row (4 B x D)
+        nbytes = (4.0 * R * n + float(terms) * m * (8.0 if in_lds else 12.0) + float(dots) * 4.0 * scene.d)
         achieved = nbytes / avg_s / 1e9
         return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),

@@ -492,6 +492,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_rescore_subset_lds(
   __shared__ int32_t set_idx[kSemMax];
   __shared__ float set_sim[kSemMax];
   __shared__ int32_t set_n;
+  __shared__ unsigned long long wave_cnt[kLdsWaves][3];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int32_t r = blockIdx.x;
   const int32_t qq = meta.rel_query[r];
@@ -551,6 +552,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_rescore_subset_lds(
   const float tau_out = block_max_lds(out, red);  // synchronises: the set is complete
   const int sn = set_n < kSemMax ? set_n : kSemMax;
   const float* qrow = qn + (int64_t)(q + r) * ldk;
+  uint32_t dots = 0;  // FP32 dot products of this wave
   if (BOUNDED) {
     // four members per wave at a time (members past the set repeat the last one and are dropped)
     for (int m0 = 4 * wave; m0 < sn; m0 += 4 * kLdsWaves) {
@@ -563,6 +565,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_rescore_subset_lds(
 #pragma unroll
         for (int u = 0; u < 4; ++u)
           if (m0 + u < sn) set_sim[m0 + u] = fmaxf(0.f, d[u]);
+      dots += (uint32_t)(sn - m0 < 4 ? sn - m0 : 4);  // counted with the wave's other dot products
     }
   }
   __syncthreads();
@@ -583,7 +586,6 @@ __global__ __launch_bounds__(kLdsThreads) void k_rescore_subset_lds(
   const float err_max = BOUNDED ? *bound.o_err_max : 0.f;
   const float qd = BOUNDED ? fmaf(qnr, err_max, qer) : 0.f;
   unsigned long long checked = 0, fell = 0;
-  uint32_t dots = 0;
   for (int32_t cc = wave; cc < cnt; cc += kLdsWaves) {
     const int64_t slot = (int64_t)qq * C + cc;
     const int64_t o = cand[slot];
@@ -633,10 +635,18 @@ __global__ __launch_bounds__(kLdsThreads) void k_rescore_subset_lds(
     checked += 1;
     fell += ok ? 0 : 1;
   }
-  if (pv.stats && lane == 0 && (checked || dots)) {
-    if (checked) atomicAdd(&pv.stats[0], checked);
-    if (fell) atomicAdd(&pv.stats[1], fell);
-    if (dots) atomicAdd(&pv.stats[2], (unsigned long long)dots);
+  // counters: summed over the block's waves, then one atomic each per block
+  __syncthreads();
+  if (lane == 0) {
+    wave_cnt[wave][0] = checked;
+    wave_cnt[wave][1] = fell;
+    wave_cnt[wave][2] = dots;
+  }
+  __syncthreads();
+  if (pv.stats && threadIdx.x < 3) {
+    unsigned long long t = 0;
+    for (int i = 0; i < kLdsWaves; ++i) t += wave_cnt[i][threadIdx.x];
+    if (t) atomicAdd(&pv.stats[threadIdx.x], t);
   }
 }
 
@@ -797,14 +807,30 @@ __global__ __launch_bounds__(256) void k_rescore_combine(
   const int r0 = meta.rel_off[qq], R = meta.rel_off[qq + 1] - r0;
   const bool bounded = bound.q_nrm != nullptr;
   const int tc = meta.tcls[qq];
-  for (int32_t cc = blockIdx.x * 4 + (threadIdx.x >> 6); cc < cnt; cc += gridDim.x * 4) {
-    const int64_t slot = (int64_t)qq * C + cc;
-    const int64_t o = cand[slot];
+  // four candidates per wave: their target dot products interleaved, then one lane each for the composite
+  for (int32_t c0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 4; c0 < cnt; c0 += gridDim.x * 16) {
+    int64_t o4[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) o4[u] = c0 + u < cnt ? cand[(int64_t)qq * C + c0 + u] : -1;
+    float dot4[4] = {0.f, 0.f, 0.f, 0.f};
+    if (bounded) {
+      const float* rows[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) rows[u] = dn + (o4[u] >= 0 ? o4[u] : 0) * ldk;
+      wave_dots<4>(qn + (int64_t)qq * ldk, rows, ldk, lane, dot4);
+    }
+    if (lane >= 4 || c0 + lane >= cnt) continue;
+    float dot = dot4[0];
+#pragma unroll
+    for (int u = 1; u < 4; ++u)
+      if (lane == u) dot = dot4[u];
+    const int64_t slot = (int64_t)qq * C + c0 + lane;
+    const int64_t o = o4[0] * (lane == 0) + o4[1] * (lane == 1) + o4[2] * (lane == 2) + o4[3] * (lane == 3);
     if (o < 0) {
-      if (lane == 0) rs_score[slot] = -INFINITY;
-      if (lane < kMaxRel) {
-        rs_terms[slot * kMaxRel + lane] = 0.f;
-        rs_anchor[slot * kMaxRel + lane] = FARM_NO_ID;
+      rs_score[slot] = -INFINITY;
+      for (int e = 0; e < kMaxRel; ++e) {
+        rs_terms[slot * kMaxRel + e] = 0.f;
+        rs_anchor[slot * kMaxRel + e] = FARM_NO_ID;
       }
       continue;
     }
@@ -812,29 +838,26 @@ __global__ __launch_bounds__(256) void k_rescore_combine(
     if (!bounded) {
       sem = sim[(int64_t)qq * ld_s + o];
     } else {
-      const float dot = wave_dot(qn + (int64_t)qq * ldk, dn + o * ldk, ldk, lane);
       const float kappa = (tc >= 0 && cls && cls[o] >= 0 && cls[o] != tc) ? kClassFactor : 1.0f;
       sem = kappa * fmaxf(0.f, dot);
     }
-    if (lane == 0) {
-      float lsum = 0.f;
-      for (int e = 0; e < R; ++e) {
-        const float v = rs_terms[slot * kMaxRel + e];
-        if (family_of(meta.rel_pred[r0 + e]) == kFamNear) {
-          lsum += v;
-          rs_terms[slot * kMaxRel + e] = term_of<kFamNear>(v);
-        } else {
-          const float term = term_of<kFamVert>(v);
-          lsum += logf(term);
-          rs_terms[slot * kMaxRel + e] = term;
-        }
+    float lsum = 0.f;
+    for (int e = 0; e < R; ++e) {
+      const float v = rs_terms[slot * kMaxRel + e];
+      if (family_of(meta.rel_pred[r0 + e]) == kFamNear) {
+        lsum += v;
+        rs_terms[slot * kMaxRel + e] = term_of<kFamNear>(v);
+      } else {
+        const float term = term_of<kFamVert>(v);
+        lsum += logf(term);
+        rs_terms[slot * kMaxRel + e] = term;
       }
-      const float gm = R > 0 ? expf(lsum / (float)R) : 1.0f;
-      rs_score[slot] = sem * ((1.0f - kW) + kW * gm);
-      for (int e = R; e < kMaxRel; ++e) {
-        rs_terms[slot * kMaxRel + e] = 0.f;
-        rs_anchor[slot * kMaxRel + e] = FARM_NO_ID;
-      }
+    }
+    const float gm = R > 0 ? expf(lsum / (float)R) : 1.0f;
+    rs_score[slot] = sem * ((1.0f - kW) + kW * gm);
+    for (int e = R; e < kMaxRel; ++e) {
+      rs_terms[slot * kMaxRel + e] = 0.f;
+      rs_anchor[slot * kMaxRel + e] = FARM_NO_ID;
     }
   }
 }
@@ -1022,7 +1045,7 @@ hipError_t launch_rescore_combine(const farm_memory* mem, const farm_workspace* 
                                   int32_t q, MetaView meta, const SimBound& bound, const int32_t* cand,
                                   const int32_t* cand_count, int32_t c, hipStream_t s) {
   if (q <= 0 || c <= 0) return hipSuccess;
-  const unsigned gx = (unsigned)((c + 3) / 4 < 16 ? (c + 3) / 4 : 16);
+  const unsigned gx = (unsigned)((c + 15) / 16 < 8 ? (c + 15) / 16 : 8);
   hipLaunchKernelGGL(k_rescore_combine, dim3(gx, (unsigned)q), dim3(256), 0, s, sim, ld_s, q, meta, bound, ws->qn,
                      mem->dn, mem->ldk, cand, cand_count, c, mem->cls, ws->rs_score, ws->rs_terms, ws->rs_anchor);
   return hipGetLastError();
