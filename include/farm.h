@@ -214,6 +214,16 @@ typedef struct {
  * anchor that could attain the maximum) and the TopK is taken among them.
  * The memory must have been built with the matching FARM_BUILD_* flag and the
  * workspace's max_k must cover rescore_mult*k.
+ * With FARM_METHOD_BOUNDED / FARM_METHOD_PROPOSAL the candidates (objects
+ * whose score can still reach the TopK, at most 2048 per query) are scored
+ * exactly -- FP32 similarities, or for a reduced-precision dtype FP32 dot
+ * products wherever the error bound leaves the maximum open -- so the result
+ * is the exact TopK whenever certified[q] = 1; certified[q] = 0 only when more
+ * than 2048 objects qualified (then the 2048 with the largest upper bounds
+ * were scored).  PROPOSAL returns the same records as BOUNDED, bit for bit.
+ * Errors: INVALID_ARG (shapes, pointers, k, unknown dtype/method/flag bits,
+ * host metadata), UNSUPPORTED (missing reduced-precision copy; PROPOSAL
+ * without farm_build_proposals), HIP.
  */
 FARM_API farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t q, int32_t d,
                             const float* target, const int32_t* target_cls, const int32_t* rel_off,

@@ -87,3 +87,48 @@ def test_bounded_small_and_ragged(farm):
                 order = oracle.topk(s64[qq], scene.ids, min(n, 18))
                 by_id = {int(v): s64[qq, i] for i, v in enumerate(scene.ids)}
                 assert_topk_valid(ids[qq], sc[qq], scene.ids[order], s64[qq, order], lambda g: by_id[g], 10)
+
+
+@pytest.mark.parametrize("k", [1, 16, 17, 64, 300])
+def test_bounded_and_proposal_k_range(farm, k):
+    """Both K forms of the candidate scan (per-thread top-16 lists for K <= 16, radix select above) against
+    the exhaustive FP32 path: same ids and bit-identical scores for FP32 similarities."""
+    from tests import _gpu
+    cfg = CONFIGS["mid"]
+    scene = make_scene(cfg, n=1500, seed=21)
+    qb = make_queries(cfg, scene, seed=22, q=48)
+    mem = _gpu.build_memory(scene, flags=farm.FARM_BUILD_BF16)
+    ws = farm.Workspace(mem, qb.q, qb.r_tot, 512)
+    ex = _gpu.query_topk(mem, ws, qb, k)
+    bd = _gpu.query_topk(mem, ws, qb, k, with_cert=True, method=farm.BOUNDED)
+    assert np.all(bd[4] == 1)
+    np.testing.assert_array_equal(bd[0], ex[0])
+    np.testing.assert_array_equal(bd[1], ex[1])
+    net = farm.ProposalNet(scene.d, max_batch=256, seed=4)
+    farm.build_proposals(mem, net, 64)
+    pr = _gpu.query_topk(mem, ws, qb, k, with_cert=True, method=farm.PROPOSAL)
+    for a, b in zip(pr, bd):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_bounded_candidate_overflow_is_reported(farm):
+    """More than 2,048 objects that can reach the TopK (identical descriptors): the query is reported
+    uncertified, and the answer is still a valid ranking of scored objects."""
+    from tests import _gpu
+    from tests.test_gpu_parity import _random_queries, _random_scene
+    scene = _random_scene(3000, 32, seed=8)
+    scene.desc[:] = scene.desc[0]
+    if scene.cls is not None:
+        scene.cls[:] = -1  # no class factor: every object has the same s_sem
+    qb = _random_queries(scene, 4, [0, 1, 2], seed=9)
+    mem = _gpu.build_memory(scene)
+    ws = farm.Workspace(mem, qb.q, qb.r_tot, 16)
+    ids, sc, terms, anch, cert = _gpu.query_topk(mem, ws, qb, 10, with_cert=True, method=farm.BOUNDED)
+    assert np.all(cert == 0)
+    s_full = _gpu.score_full(mem, ws, qb, terms=False)
+    idx_of = {int(v): i for i, v in enumerate(scene.ids)}
+    for qq in range(qb.q):
+        assert np.all(np.diff(sc[qq]) <= 0)
+        for rank in range(10):
+            i = idx_of[int(ids[qq, rank])]
+            assert sc[qq, rank] == s_full[qq, i]  # each returned score is that object's exact score

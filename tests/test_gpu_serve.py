@@ -68,8 +68,13 @@ def _run(farm, scenes, reqs, cancel=(), timeout=60.0, **cfg):
     return [res[i] for i in ids], stats
 
 
-@pytest.mark.parametrize("dtype,method", [(0, 0), (1, 1)], ids=["f32-exhaustive", "bf16-bounded"])
+@pytest.mark.parametrize("dtype,method", [(0, 0), (1, 1), (1, 2)], ids=["f32-exhaustive", "bf16-bounded",
+                                                                         "bf16-proposal"])
 def test_alone_equals_mix(farm, scenes, dtype, method):
+    if method == farm.PROPOSAL:
+        net = farm.ProposalNet(scenes[0][0].d, max_batch=256, seed=3)
+        for _, _, mem in scenes:
+            farm.build_proposals(mem, net, 64)
     reqs = _requests(scenes)
     alone = []
     for r in reqs:
