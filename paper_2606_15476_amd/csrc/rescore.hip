@@ -208,8 +208,32 @@ __device__ void full_term(const float* __restrict__ arow, const float* __restric
 // The maximum over the subset (the target's list and the relation's semantic
 // set) by one wave; true when it certifies the term (strictly above the bound
 // on every other anchor).
-template <int FAM>
-__device__ bool subset_term(const float* arow, const float* __restrict__ qrow, const float* __restrict__ dn,
+// Similarity row of the proposal pass: FP32 values (global memory or LDS), or
+// BF16 roundings of a reduced-precision GEMM's values staged in LDS, whose
+// rounding (at most 2^-9 relative, round to nearest even) is folded into
+// the bounds (2^-7 relative, with margin).
+struct RowF32 {
+  const float* p;
+  __device__ float get(int64_t j) const { return p[j]; }
+  __device__ float lo(int64_t j, float d) const { return fmaxf(0.f, p[j] - d); }
+  __device__ float hi(int64_t j, float d) const { return fminf(1.0f, p[j] + d); }
+};
+constexpr float kBf16Margin = 1.0f / 128.0f;
+__device__ inline float bf16_value(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ inline uint16_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+struct RowBF16 {
+  const uint16_t* p;
+  __device__ float get(int64_t j) const { return bf16_value(p[j]); }
+  __device__ float lo(int64_t j, float d) const { return fmaxf(0.f, bf16_value(p[j]) * (1.0f - kBf16Margin) - d); }
+  __device__ float hi(int64_t j, float d) const { return fminf(1.0f, bf16_value(p[j]) * (1.0f + kBf16Margin) + d); }
+};
+
+template <int FAM, class Row = RowF32>
+__device__ bool subset_term(Row arow, const float* __restrict__ qrow, const float* __restrict__ dn,
                             int32_t ldk, int64_t o, float c, bool bounded, float qn, float qe,
                             const float* __restrict__ o_err, float qd_uniform, const Geo& g, const Subset& sub,
                             int lane, float& out_best, uint32_t& out_bid, uint32_t& dots) {
@@ -229,7 +253,7 @@ __device__ bool subset_term(const float* arow, const float* __restrict__ qrow, c
     for (int e = lane; e < tot; e += 64) {
       const int64_t j = anchor_of(e);
       if (j == o) continue;
-      const float a = arow[j];
+      const float a = arow.get(j);
       take_max_j(entry(e, j, a, FAM == kFamNear ? near_log(a) : 0.f), j, g.ids, best, bj);
     }
   } else {
@@ -245,12 +269,12 @@ __device__ bool subset_term(const float* arow, const float* __restrict__ qrow, c
     // lower bound L (the semantic set's exact values included) can be the
     // maximum, and each of those needs an FP32 dot product.
     auto value_at = [&](int e, int64_t j, float a) { return entry(e, j, a, FAM == kFamNear ? near_log(a) : 0.f); };
-    auto upper = [&](int e, int64_t j) { return value_at(e, j, fminf(1.0f, arow[j] + delta(j))); };
+    auto upper = [&](int e, int64_t j) { return value_at(e, j, arow.hi(j, delta(j))); };
     float lo = best;
     for (int e = lane; e < sub.M; e += 64) {
       const int64_t j = anchor_of(e);
       if (j == o) continue;
-      lo = fmaxf(lo, value_at(e, j, fmaxf(0.f, arow[j] - delta(j))));
+      lo = fmaxf(lo, value_at(e, j, arow.lo(j, delta(j))));
     }
     lo = wave_max_f(lo);
     const float L = lo - (fabsf(lo) * 1e-6f + 1e-30f);  // slack for rounding of the bounded values
@@ -428,15 +452,15 @@ __global__ __launch_bounds__(64 * kTermWaves) void k_rescore_terms(
       bool ok;
       switch (family_of(p)) {
         case kFamNear:
-          ok = subset_term<kFamNear>(arow, qrow, dn, ldk, o, c, bounded, qnr, qer, bound.o_err, 0.f, g, sub, lane, best,
+          ok = subset_term<kFamNear>(RowF32{arow}, qrow, dn, ldk, o, c, bounded, qnr, qer, bound.o_err, 0.f, g, sub, lane, best,
                                      bid, dots);
           break;
         case kFamVert:
-          ok = subset_term<kFamVert>(arow, qrow, dn, ldk, o, c, bounded, qnr, qer, bound.o_err, 0.f, g, sub, lane, best,
+          ok = subset_term<kFamVert>(RowF32{arow}, qrow, dn, ldk, o, c, bounded, qnr, qer, bound.o_err, 0.f, g, sub, lane, best,
                                      bid, dots);
           break;
         default:
-          ok = subset_term<kFamLat>(arow, qrow, dn, ldk, o, c, bounded, qnr, qer, bound.o_err, 0.f, g, sub, lane, best,
+          ok = subset_term<kFamLat>(RowF32{arow}, qrow, dn, ldk, o, c, bounded, qnr, qer, bound.o_err, 0.f, g, sub, lane, best,
                                     bid, dots);
           break;
       }
@@ -487,7 +511,11 @@ __global__ __launch_bounds__(kLdsThreads) void k_rescore_subset_lds(
     const float* __restrict__ qn, const float* __restrict__ dn, int32_t ldk, const int32_t* __restrict__ cand,
     const int32_t* __restrict__ cand_count, int32_t C, Geo g, int64_t n, float* __restrict__ rs_terms,
     uint32_t* __restrict__ rs_anchor, PropView pv) {
+  // FP32 row (exact similarities) or, for a reduced-precision GEMM whose values
+  // only feed bounds, its BF16 rounding (half the LDS, more blocks per CU)
   extern __shared__ float srow[];
+  uint16_t* srow16 = reinterpret_cast<uint16_t*>(srow);
+  auto staged = [&](int64_t j) { return BOUNDED ? bf16_value(srow16[j]) : srow[j]; };
   __shared__ float red[kLdsWaves];
   __shared__ int32_t set_idx[kSemMax];
   __shared__ float set_sim[kSemMax];
@@ -506,18 +534,28 @@ __global__ __launch_bounds__(kLdsThreads) void k_rescore_subset_lds(
   float mx = 0.f;
   for (int64_t i = threadIdx.x; i < n4; i += kLdsThreads) {
     const float4 v = a4[i];
-    s4[i] = v;
+    if (BOUNDED) {
+      ushort4 h;
+      h.x = bf16_rne(v.x);
+      h.y = bf16_rne(v.y);
+      h.z = bf16_rne(v.z);
+      h.w = bf16_rne(v.w);
+      reinterpret_cast<ushort4*>(srow16)[i] = h;
+    } else {
+      s4[i] = v;
+    }
     mx = fmaxf(fmaxf(mx, fmaxf(v.x, v.y)), fmaxf(v.z, v.w));
   }
   for (int64_t j = (n4 << 2) + threadIdx.x; j < n; j += kLdsThreads) {
-    srow[j] = arow[j];
+    if (BOUNDED) srow16[j] = bf16_rne(arow[j]);
+    else srow[j] = arow[j];
     mx = fmaxf(mx, arow[j]);
   }
   const float amax = block_max_lds(mx, red);  // synchronises: the row is staged
   // semantic set: count above tau, refine tau while more than kSemMax exceed it
   auto count_above = [&](float tau) {
     int32_t c = 0;
-    for (int64_t j = threadIdx.x; j < n; j += kLdsThreads) c += srow[j] > tau;
+    for (int64_t j = threadIdx.x; j < n; j += kLdsThreads) c += staged(j) > tau;
     // block sum through the wave sums
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
     __syncthreads();
@@ -538,7 +576,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_rescore_subset_lds(
   __syncthreads();
   float out = 0.f;
   for (int64_t j = threadIdx.x; j < n; j += kLdsThreads) {
-    const float v = srow[j];
+    const float v = staged(j);
     bool member = false;
     if (v > tau) {
       const int32_t pos = atomicAdd(&set_n, 1);
@@ -549,7 +587,8 @@ __global__ __launch_bounds__(kLdsThreads) void k_rescore_subset_lds(
     }
     if (!member) out = fmaxf(out, v);
   }
-  const float tau_out = block_max_lds(out, red);  // synchronises: the set is complete
+  // largest similarity outside the set (a staged BF16 value bounds its source within the margin)
+  const float tau_out = block_max_lds(out, red) * (BOUNDED ? 1.0f + kBf16Margin : 1.0f);  // synchronises
   const int sn = set_n < kSemMax ? set_n : kSemMax;
   const float* qrow = qn + (int64_t)(q + r) * ldk;
   uint32_t dots = 0;  // FP32 dot products of this wave
@@ -611,16 +650,28 @@ __global__ __launch_bounds__(kLdsThreads) void k_rescore_subset_lds(
     bool ok;
     switch (family_of(p)) {
       case kFamNear:
-        ok = subset_term<kFamNear>(srow, qrow, dn, ldk, o, c, BOUNDED, qnr, qer, nullptr, qd, g, sub, lane, best, bid,
-                                   dots);
+        if constexpr (BOUNDED)
+          ok = subset_term<kFamNear>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, g, sub, lane,
+                                     best, bid, dots);
+        else
+          ok = subset_term<kFamNear>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, g, sub, lane,
+                                     best, bid, dots);
         break;
       case kFamVert:
-        ok = subset_term<kFamVert>(srow, qrow, dn, ldk, o, c, BOUNDED, qnr, qer, nullptr, qd, g, sub, lane, best, bid,
-                                   dots);
+        if constexpr (BOUNDED)
+          ok = subset_term<kFamVert>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, g, sub, lane,
+                                     best, bid, dots);
+        else
+          ok = subset_term<kFamVert>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, g, sub, lane,
+                                     best, bid, dots);
         break;
       default:
-        ok = subset_term<kFamLat>(srow, qrow, dn, ldk, o, c, BOUNDED, qnr, qer, nullptr, qd, g, sub, lane, best, bid,
-                                  dots);
+        if constexpr (BOUNDED)
+          ok = subset_term<kFamLat>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, g, sub, lane,
+                                     best, bid, dots);
+        else
+          ok = subset_term<kFamLat>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, g, sub, lane,
+                                     best, bid, dots);
         break;
     }
     if (lane == 0) {
@@ -980,7 +1031,8 @@ bool lds_row_fits(int device, size_t bytes, bool bounded) {
 }
 
 bool proposal_pass_in_lds(const farm_memory* mem, bool bounded) {
-  return lds_row_fits(mem->device, (size_t)round_up(mem->n, 4) * sizeof(float), bounded);
+  return lds_row_fits(mem->device, (size_t)round_up(mem->n, 4) * (bounded ? sizeof(uint16_t) : sizeof(float)),
+                      bounded);
 }
 
 hipError_t launch_rescore_terms(const farm_memory* mem, const farm_workspace* ws, const float* sim, int64_t ld_s,
@@ -1013,7 +1065,7 @@ hipError_t launch_rescore_terms(const farm_memory* mem, const farm_workspace* ws
     if (e != hipSuccess) return e;
   }
   if (mode == kTermsSubset) {
-    const size_t lds = (size_t)round_up(mem->n, 4) * sizeof(float);
+    const size_t lds = (size_t)round_up(mem->n, 4) * (bounded ? sizeof(uint16_t) : sizeof(float));
     if (prop.in_lds) {
       const int32_t R = prop.rel_total;
       if (R <= 0) return hipSuccess;
