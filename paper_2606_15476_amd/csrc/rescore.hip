@@ -44,11 +44,28 @@ __device__ inline float wave_sum(float v) {
 }
 
 // FP32 dot product of two zero-padded rows (ldk a multiple of 128) by one wave.
+// Lane l accumulates elements 2l, 2l+1 of every 128-element slab, in slab
+// order; the loads of four slabs are issued before their FMAs so that one
+// memory round trip covers four slabs (the arithmetic order is unchanged).
 __device__ inline float wave_dot(const float* __restrict__ a, const float* __restrict__ b, int32_t ldk, int lane) {
   float acc = 0.f;
-  for (int k = 2 * lane; k < ldk; k += 128) {
-    float2 x = *reinterpret_cast<const float2*>(a + k);
-    float2 y = *reinterpret_cast<const float2*>(b + k);
+  int k = 2 * lane;
+  for (; k + 128 < ldk; k += 2 * 128) {
+    float2 x[2], y[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      x[u] = *reinterpret_cast<const float2*>(a + k + 128 * u);
+      y[u] = *reinterpret_cast<const float2*>(b + k + 128 * u);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      acc = fmaf(x[u].x, y[u].x, acc);
+      acc = fmaf(x[u].y, y[u].y, acc);
+    }
+  }
+  for (; k < ldk; k += 128) {
+    const float2 x = *reinterpret_cast<const float2*>(a + k);
+    const float2 y = *reinterpret_cast<const float2*>(b + k);
     acc = fmaf(x.x, y.x, acc);
     acc = fmaf(x.y, y.y, acc);
   }
@@ -232,11 +249,100 @@ struct RowBF16 {
   __device__ float hi(int64_t j, float d) const { return fminf(1.0f, bf16_value(p[j]) * (1.0f + kBf16Margin) + d); }
 };
 
-template <int FAM, class Row = RowF32>
-__device__ bool subset_term(Row arow, const float* __restrict__ qrow, const float* __restrict__ dn,
-                            int32_t ldk, int64_t o, float c, bool bounded, float qn, float qe,
-                            const float* __restrict__ o_err, float qd_uniform, const Geo& g, const Subset& sub,
-                            int lane, float& out_best, uint32_t& out_bid, uint32_t& dots) {
+// subset_term for lists of at most 256 entries, a multiple of 4: each lane
+// holds list entries 4l..4l+3 (one 16-byte load of ids, one of cached
+// predicate values) and semantic-set member l, all loaded before the first
+// use, so one memory round trip serves the whole subset.  Same values, bounds
+// and survivor rule as the general form.
+constexpr int kRegEntries = 4;
+static_assert(kSemMax <= 64, "one semantic-set member per lane");
+template <int FAM, class Row>
+__device__ bool subset_term_reg(Row arow, const float* __restrict__ qrow, const float* __restrict__ dn,
+                                int32_t ldk, int64_t o, float c, bool bounded, float qn, float qe,
+                                const float* __restrict__ o_err, float qd_uniform, const Geo& g, const Subset& sub,
+                                int lane, float& out_best, uint32_t& out_bid, uint32_t& dots) {
+  const Tgt t = load_target(FAM, o, g.x, g.y, g.z, g.hhi, g.hlo);
+  const int e0 = kRegEntries * lane;
+  int4 j4 = make_int4(-1, -1, -1, -1);
+  float4 p4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (e0 < sub.M) {
+    j4 = *reinterpret_cast<const int4*>(sub.lidx + e0);
+    p4 = *reinterpret_cast<const float4*>(sub.lval + e0);
+  }
+  const int32_t jl[kRegEntries] = {j4.x, j4.y, j4.z, j4.w};
+  const float pl[kRegEntries] = {p4.x, p4.y, p4.z, p4.w};
+  // list value from a similarity: cached predicate value times it (log domain for Near)
+  auto list_value = [&](float a, float p) { return FAM == kFamNear ? near_log(a) + p : a * p; };
+  auto delta = [&](int64_t j) { return o_err ? fmaf(qn, o_err[j], qe) : qd_uniform; };
+  float best = value_floor<FAM>();
+  int64_t bj = -1;
+  // semantic-set member of this lane: exact similarity (carried, or the FP32 row)
+  if (lane < sub.sn) {
+    const int64_t js = sub.sidx[lane];
+    if (js != o) {
+      const float a = bounded ? sub.ssim[lane] : arow.get(js);
+      best = pair_value<FAM>(t, anchor_record_pre(FAM, a, FAM == kFamNear ? near_log(a) : 0.f, js, g.x, g.y, g.z,
+                                                  g.hhi, g.hlo), c);
+      bj = js;
+    }
+  }
+  if (!bounded) {
+#pragma unroll
+    for (int k = 0; k < kRegEntries; ++k) {
+      const int64_t j = jl[k];
+      if (j < 0 || j == o) continue;
+      take_max_j(list_value(arow.get(j), pl[k]), j, g.ids, best, bj);
+    }
+  } else {
+    float lo = best;
+#pragma unroll
+    for (int k = 0; k < kRegEntries; ++k) {
+      const int64_t j = jl[k];
+      if (j < 0 || j == o) continue;
+      lo = fmaxf(lo, list_value(arow.lo(j, delta(j)), pl[k]));
+    }
+    lo = wave_max_f(lo);
+    const float L = lo - (fabsf(lo) * 1e-6f + 1e-30f);  // slack for rounding of the bounded values
+    uint32_t surv = 0;  // entries of this lane whose upper bound reaches L
+#pragma unroll
+    for (int k = 0; k < kRegEntries; ++k) {
+      const int64_t j = jl[k];
+      if (j < 0 || j == o) continue;
+      surv |= (list_value(arow.hi(j, delta(j)), pl[k]) >= L ? 1u : 0u) << k;
+    }
+    float B = wave_max_f(best);
+    // survivors: the entry is re-read (one uniform load) so that nothing of
+    // the register-held list stays live across the dot products
+#pragma unroll
+    for (int k = 0; k < kRegEntries; ++k) {
+      uint64_t mask = __ballot((surv >> k) & 1u);
+      while (mask) {
+        const int src = __ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1;
+        const int e2 = kRegEntries * src + k;
+        const int64_t j2 = sub.lidx[e2];
+        const float p2 = sub.lval[e2];
+        if (list_value(arow.hi(j2, delta(j2)), p2) < B - (fabsf(B) * 1e-6f + 1e-30f)) continue;
+        const float a = fmaxf(0.f, wave_dot(qrow, dn + j2 * ldk, ldk, lane));
+        ++dots;
+        const float v = list_value(a, p2);
+        take_max_j(v, j2, g.ids, best, bj);
+        B = fmaxf(B, v);
+      }
+    }
+  }
+  uint32_t bid = bj >= 0 ? g.ids[bj] : FARM_NO_ID;
+  wave_argmax(best, bid);
+  out_best = best;
+  out_bid = bid;
+  return best > sub.cert;
+}
+
+template <int FAM, class Row>
+__device__ bool subset_term_gen(Row arow, const float* __restrict__ qrow, const float* __restrict__ dn,
+                                int32_t ldk, int64_t o, float c, bool bounded, float qn, float qe,
+                                const float* __restrict__ o_err, float qd_uniform, const Geo& g, const Subset& sub,
+                                int lane, float& out_best, uint32_t& out_bid, uint32_t& dots) {
   const Tgt t = load_target(FAM, o, g.x, g.y, g.z, g.hhi, g.hlo);
   float best = value_floor<FAM>();
   int64_t bj = -1;
@@ -314,6 +420,36 @@ __device__ bool subset_term(Row arow, const float* __restrict__ qrow, const floa
   out_best = best;
   out_bid = bid;
   return best > sub.cert;
+}
+
+// Lists of at most 256 entries (a multiple of 4) take the register form.
+__device__ inline bool reg_list(int M) { return (M & (kRegEntries - 1)) == 0 && M <= 64 * kRegEntries; }
+
+template <int FAM, class Row = RowF32>
+__device__ bool subset_term(Row arow, const float* __restrict__ qrow, const float* __restrict__ dn,
+                            int32_t ldk, int64_t o, float c, bool bounded, float qn, float qe,
+                            const float* __restrict__ o_err, float qd_uniform, const Geo& g, const Subset& sub,
+                            int lane, float& out_best, uint32_t& out_bid, uint32_t& dots) {
+  if (reg_list(sub.M))
+    return subset_term_reg<FAM>(arow, qrow, dn, ldk, o, c, bounded, qn, qe, o_err, qd_uniform, g, sub, lane,
+                                out_best, out_bid, dots);
+  return subset_term_gen<FAM>(arow, qrow, dn, ldk, o, c, bounded, qn, qe, o_err, qd_uniform, g, sub, lane, out_best,
+                              out_bid, dots);
+}
+
+// The form fixed at compile time (one form per kernel keeps its register count down).
+template <bool REG, int FAM, class Row>
+__device__ inline bool subset_term_sel(Row arow, const float* __restrict__ qrow, const float* __restrict__ dn,
+                                       int32_t ldk, int64_t o, float c, bool bounded, float qn, float qe,
+                                       const float* __restrict__ o_err, float qd_uniform, const Geo& g,
+                                       const Subset& sub, int lane, float& out_best, uint32_t& out_bid,
+                                       uint32_t& dots) {
+  if constexpr (REG)
+    return subset_term_reg<FAM>(arow, qrow, dn, ldk, o, c, bounded, qn, qe, o_err, qd_uniform, g, sub, lane,
+                                out_best, out_bid, dots);
+  else
+    return subset_term_gen<FAM>(arow, qrow, dn, ldk, o, c, bounded, qn, qe, o_err, qd_uniform, g, sub, lane,
+                                out_best, out_bid, dots);
 }
 
 // Proposal subset of term (candidate o, relation r) and the bound on every
@@ -505,8 +641,8 @@ __device__ inline float block_max_lds(float v, float* red) {
   return m;
 }
 
-template <bool BOUNDED>
-__global__ __launch_bounds__(kLdsThreads) void k_rescore_subset_lds(
+template <bool BOUNDED, bool REG>
+__global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_rescore_subset_lds(
     const float* __restrict__ sim, int64_t ld_s, int32_t q, MetaView meta, SimBound bound,
     const float* __restrict__ qn, const float* __restrict__ dn, int32_t ldk, const int32_t* __restrict__ cand,
     const int32_t* __restrict__ cand_count, int32_t C, Geo g, int64_t n, float* __restrict__ rs_terms,
@@ -651,26 +787,26 @@ __global__ __launch_bounds__(kLdsThreads) void k_rescore_subset_lds(
     switch (family_of(p)) {
       case kFamNear:
         if constexpr (BOUNDED)
-          ok = subset_term<kFamNear>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, g, sub, lane,
+          ok = subset_term_sel<REG, kFamNear>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, g, sub, lane,
                                      best, bid, dots);
         else
-          ok = subset_term<kFamNear>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, g, sub, lane,
+          ok = subset_term_sel<REG, kFamNear>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, g, sub, lane,
                                      best, bid, dots);
         break;
       case kFamVert:
         if constexpr (BOUNDED)
-          ok = subset_term<kFamVert>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, g, sub, lane,
+          ok = subset_term_sel<REG, kFamVert>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, g, sub, lane,
                                      best, bid, dots);
         else
-          ok = subset_term<kFamVert>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, g, sub, lane,
+          ok = subset_term_sel<REG, kFamVert>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, g, sub, lane,
                                      best, bid, dots);
         break;
       default:
         if constexpr (BOUNDED)
-          ok = subset_term<kFamLat>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, g, sub, lane,
+          ok = subset_term_sel<REG, kFamLat>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, g, sub, lane,
                                      best, bid, dots);
         else
-          ok = subset_term<kFamLat>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, g, sub, lane,
+          ok = subset_term_sel<REG, kFamLat>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, g, sub, lane,
                                      best, bid, dots);
         break;
     }
@@ -1019,12 +1155,15 @@ bool lds_row_fits(int device, size_t bytes, bool bounded) {
   if (limit[device] < 0 || bytes + 1024 > (size_t)limit[device]) return false;
   size_t& g = granted[bounded ? 1 : 0][device];
   if (bytes > 65536 && bytes > g) {
-    const void* fn = bounded ? reinterpret_cast<const void*>(&k_rescore_subset_lds<true>)
-                             : reinterpret_cast<const void*>(&k_rescore_subset_lds<false>);
-    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      return false;
-    }
+    const void* fn[2] = {bounded ? reinterpret_cast<const void*>(&k_rescore_subset_lds<true, false>)
+                                 : reinterpret_cast<const void*>(&k_rescore_subset_lds<false, false>),
+                         bounded ? reinterpret_cast<const void*>(&k_rescore_subset_lds<true, true>)
+                                 : reinterpret_cast<const void*>(&k_rescore_subset_lds<false, true>)};
+    for (const void* f : fn)
+      if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+      }
     g = bytes;
   }
   return true;
@@ -1069,14 +1208,19 @@ hipError_t launch_rescore_terms(const farm_memory* mem, const farm_workspace* ws
     if (prop.in_lds) {
       const int32_t R = prop.rel_total;
       if (R <= 0) return hipSuccess;
-      if (bounded)
-        hipLaunchKernelGGL((k_rescore_subset_lds<true>), dim3((unsigned)R), dim3(kLdsThreads), lds, s, sim, ld_s, q,
-                           meta, bound, ws->qn, mem->dn, mem->ldk, cand, cand_count, c, g, mem->n, ws->rs_terms,
-                           ws->rs_anchor, prop);
-      else
-        hipLaunchKernelGGL((k_rescore_subset_lds<false>), dim3((unsigned)R), dim3(kLdsThreads), lds, s, sim, ld_s, q,
-                           meta, bound, ws->qn, mem->dn, mem->ldk, cand, cand_count, c, g, mem->n, ws->rs_terms,
-                           ws->rs_anchor, prop);
+#define FARM_LDS(B, REG)                                                                                        \
+  hipLaunchKernelGGL((k_rescore_subset_lds<B, REG>), dim3((unsigned)R), dim3(kLdsThreads), lds, s, sim, ld_s, q, \
+                     meta, bound, ws->qn, mem->dn, mem->ldk, cand, cand_count, c, g, mem->n, ws->rs_terms,        \
+                     ws->rs_anchor, prop)
+      const bool reg = (prop.m & (kRegEntries - 1)) == 0 && prop.m <= 64 * kRegEntries;
+      if (bounded) {
+        if (reg) FARM_LDS(true, true);
+        else FARM_LDS(true, false);
+      } else {
+        if (reg) FARM_LDS(false, true);
+        else FARM_LDS(false, false);
+      }
+#undef FARM_LDS
       return hipGetLastError();
     }
   }

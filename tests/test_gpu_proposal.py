@@ -96,8 +96,10 @@ def _compare(farm, mem, ws, qb, k, dtype):
     return checked, fell
 
 
+@pytest.mark.parametrize("m", [256, 300, 254], ids=["m256", "m300", "m254"])
 @pytest.mark.parametrize("dtype", [0, 1, 2], ids=["f32", "bf16", "fp8"])
-def test_proposal_equals_bounded_mid(farm, dtype):
+def test_proposal_equals_bounded_mid(farm, dtype, m):
+    """Lists of at most 256 entries in multiples of 4 take the register form, others the general one."""
     from tests import _gpu
     cfg = CONFIGS["mid"]
     scene = make_scene(cfg)
@@ -105,9 +107,10 @@ def test_proposal_equals_bounded_mid(farm, dtype):
     mem = _gpu.build_memory(scene, flags=farm.FARM_BUILD_BF16 | farm.FARM_BUILD_FP8)
     ws = farm.Workspace(mem, qb.q, qb.r_tot, 64)
     net = farm.ProposalNet(scene.d, max_batch=4096, seed=1)
-    farm.build_proposals(mem, net, 256)
+    farm.build_proposals(mem, net, m)
+    assert farm.get_proposals(mem)[0] == m
     checked, fell = _compare(farm, mem, ws, qb, cfg.k, dtype)
-    print(f"[proposal mid dtype={dtype}] terms {checked}, fell back {fell}", flush=True)
+    print(f"[proposal mid dtype={dtype} m={m}] terms {checked}, fell back {fell}", flush=True)
     assert checked > 0 and 0 <= fell <= checked
 
 
