@@ -74,14 +74,34 @@ __device__ inline float wave_dot(const float* __restrict__ a, const float* __res
 
 // NN dot products against the same row `a`, interleaved for memory-level
 // parallelism; each one with exactly wave_dot's arithmetic (same per-lane
-// order, same reduction tree), so the values are bit-identical.
-template <int NN>
+// order, same reduction tree), so the values are bit-identical.  SLABS slabs
+// of loads are issued ahead of their FMAs (more registers, fewer round trips).
+template <int NN, int SLABS = 1>
 __device__ inline void wave_dots(const float* __restrict__ a, const float* const (&b)[NN], int32_t ldk, int lane,
                                  float (&out)[NN]) {
   float acc[NN];
 #pragma unroll
   for (int u = 0; u < NN; ++u) acc[u] = 0.f;
-  for (int k = 2 * lane; k < ldk; k += 128) {
+  int k = 2 * lane;
+  if constexpr (SLABS > 1) {
+    for (; k + (SLABS - 1) * 128 < ldk; k += SLABS * 128) {
+      float2 x[SLABS], y[SLABS][NN];
+#pragma unroll
+      for (int s = 0; s < SLABS; ++s) {
+        x[s] = *reinterpret_cast<const float2*>(a + k + 128 * s);
+#pragma unroll
+        for (int u = 0; u < NN; ++u) y[s][u] = *reinterpret_cast<const float2*>(b[u] + k + 128 * s);
+      }
+#pragma unroll
+      for (int s = 0; s < SLABS; ++s)
+#pragma unroll
+        for (int u = 0; u < NN; ++u) {
+          acc[u] = fmaf(x[s].x, y[s][u].x, acc[u]);
+          acc[u] = fmaf(x[s].y, y[s][u].y, acc[u]);
+        }
+    }
+  }
+  for (; k < ldk; k += 128) {
     const float2 x = *reinterpret_cast<const float2*>(a + k);
 #pragma unroll
     for (int u = 0; u < NN; ++u) {
@@ -112,6 +132,15 @@ __device__ inline void take_max(float v, int64_t j, const uint32_t* __restrict__
 // max with the smallest-id tie-break that remembers the anchor's index; the
 // ids are read only to break exact ties (resolve with the index at the end)
 __device__ inline void take_max_j(float v, int64_t j, const uint32_t* __restrict__ ids, float& best, int64_t& bj) {
+  if (v > best) {
+    best = v;
+    bj = j;
+  } else if (v == best && bj >= 0 && j != bj && ids[j] < ids[bj]) {
+    bj = j;
+  }
+}
+__device__ inline void take_max_j32(float v, int32_t j, const uint32_t* __restrict__ ids, float& best,
+                                    int32_t& bj) {
   if (v > best) {
     best = v;
     bj = j;
@@ -155,7 +184,24 @@ struct Subset {
   int sn;
   const float* ssim;  // exact similarities of the semantic set (reduced precision), or null
   float cert;         // bound on the value of every anchor outside the subset (family domain)
+  const float4* sgeo = nullptr;  // the set's anchor coordinates (geo_of layout), or null: read from Geo
 };
+
+// An anchor's coordinates as its family uses them: Near (x, y, z), Above/Below
+// (z), Left/Right (h hi, h lo).
+template <int FAM>
+__device__ inline float4 geo_of(int64_t j, const Geo& g) {
+  if (FAM == kFamNear) return make_float4(g.x[j], g.y[j], g.z[j], 0.f);
+  if (FAM == kFamVert) return make_float4(g.z[j], 0.f, 0.f, 0.f);
+  return make_float4(g.hhi[j], g.hlo[j], 0.f, 0.f);
+}
+// anchor record (as anchor_record_pre) from such coordinates
+template <int FAM>
+__device__ inline float4 record_of(float a, float la, const float4& c) {
+  if (FAM == kFamNear) return make_float4(la, c.x, c.y, c.z);
+  if (FAM == kFamVert) return make_float4(a, c.x, 0.f, 0.f);
+  return make_float4(a, c.x, c.y, 0.f);
+}
 
 // The exact maximum over every anchor of one relation term of target o, by
 // one wave.  Returns the family-domain maximum (log for Near) and its anchor id.
@@ -256,33 +302,47 @@ struct RowBF16 {
 // and survivor rule as the general form.
 constexpr int kRegEntries = 4;
 static_assert(kSemMax <= 64, "one semantic-set member per lane");
+struct RegList {
+  int4 j;    // anchor ids of list entries 4l..4l+3 (-1: none)
+  float4 p;  // their cached predicate values
+};
+__device__ inline RegList load_reg_list(const int32_t* __restrict__ lidx, const float* __restrict__ lval, int M,
+                                        int lane) {
+  RegList l{make_int4(-1, -1, -1, -1), make_float4(0.f, 0.f, 0.f, 0.f)};
+  const int e0 = kRegEntries * lane;
+  if (e0 < M) {
+    l.j = *reinterpret_cast<const int4*>(lidx + e0);
+    l.p = *reinterpret_cast<const float4*>(lval + e0);
+  }
+  return l;
+}
+
 template <int FAM, class Row>
 __device__ bool subset_term_reg(Row arow, const float* __restrict__ qrow, const float* __restrict__ dn,
                                 int32_t ldk, int64_t o, float c, bool bounded, float qn, float qe,
                                 const float* __restrict__ o_err, float qd_uniform, const Geo& g, const Subset& sub,
-                                int lane, float& out_best, uint32_t& out_bid, uint32_t& dots) {
-  const Tgt t = load_target(FAM, o, g.x, g.y, g.z, g.hhi, g.hlo);
-  const int e0 = kRegEntries * lane;
-  int4 j4 = make_int4(-1, -1, -1, -1);
-  float4 p4 = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (e0 < sub.M) {
-    j4 = *reinterpret_cast<const int4*>(sub.lidx + e0);
-    p4 = *reinterpret_cast<const float4*>(sub.lval + e0);
-  }
+                                const Tgt& t, const RegList& lst, int lane, float& out_best, uint32_t& out_bid,
+                                uint32_t& dots) {
+  const int4 j4 = lst.j;
+  const float4 p4 = lst.p;
   const int32_t jl[kRegEntries] = {j4.x, j4.y, j4.z, j4.w};
   const float pl[kRegEntries] = {p4.x, p4.y, p4.z, p4.w};
   // list value from a similarity: cached predicate value times it (log domain for Near)
   auto list_value = [&](float a, float p) { return FAM == kFamNear ? near_log(a) + p : a * p; };
   auto delta = [&](int64_t j) { return o_err ? fmaf(qn, o_err[j], qe) : qd_uniform; };
   float best = value_floor<FAM>();
-  int64_t bj = -1;
+  int32_t bj = -1;  // anchor index of best
   // semantic-set member of this lane: exact similarity (carried, or the FP32 row)
-  if (lane < sub.sn) {
-    const int64_t js = sub.sidx[lane];
+  // (the member's data are re-read per term, not held across a caller's loop
+  // of terms: an opaque copy of the lane index keeps them from being hoisted)
+  int sl = lane;
+  asm volatile("" : "+v"(sl));
+  if (sl < sub.sn) {
+    const int32_t js = sub.sidx[sl];
     if (js != o) {
-      const float a = bounded ? sub.ssim[lane] : arow.get(js);
-      best = pair_value<FAM>(t, anchor_record_pre(FAM, a, FAM == kFamNear ? near_log(a) : 0.f, js, g.x, g.y, g.z,
-                                                  g.hhi, g.hlo), c);
+      const float a = bounded ? sub.ssim[sl] : arow.get(js);
+      const float4 cs = sub.sgeo ? sub.sgeo[sl] : geo_of<FAM>(js, g);
+      best = pair_value<FAM>(t, record_of<FAM>(a, FAM == kFamNear ? near_log(a) : 0.f, cs), c);
       bj = js;
     }
   }
@@ -291,7 +351,7 @@ __device__ bool subset_term_reg(Row arow, const float* __restrict__ qrow, const 
     for (int k = 0; k < kRegEntries; ++k) {
       const int64_t j = jl[k];
       if (j < 0 || j == o) continue;
-      take_max_j(list_value(arow.get(j), pl[k]), j, g.ids, best, bj);
+      take_max_j32(list_value(arow.get(j), pl[k]), (int32_t)j, g.ids, best, bj);
     }
   } else {
     float lo = best;
@@ -320,13 +380,13 @@ __device__ bool subset_term_reg(Row arow, const float* __restrict__ qrow, const 
         const int src = __ffsll((unsigned long long)mask) - 1;
         mask &= mask - 1;
         const int e2 = kRegEntries * src + k;
-        const int64_t j2 = sub.lidx[e2];
+        const int32_t j2 = sub.lidx[e2];
         const float p2 = sub.lval[e2];
         if (list_value(arow.hi(j2, delta(j2)), p2) < B - (fabsf(B) * 1e-6f + 1e-30f)) continue;
-        const float a = fmaxf(0.f, wave_dot(qrow, dn + j2 * ldk, ldk, lane));
+        const float a = fmaxf(0.f, wave_dot(qrow, dn + (int64_t)j2 * ldk, ldk, lane));
         ++dots;
         const float v = list_value(a, p2);
-        take_max_j(v, j2, g.ids, best, bj);
+        take_max_j32(v, j2, g.ids, best, bj);
         B = fmaxf(B, v);
       }
     }
@@ -431,8 +491,9 @@ __device__ bool subset_term(Row arow, const float* __restrict__ qrow, const floa
                             const float* __restrict__ o_err, float qd_uniform, const Geo& g, const Subset& sub,
                             int lane, float& out_best, uint32_t& out_bid, uint32_t& dots) {
   if (reg_list(sub.M))
-    return subset_term_reg<FAM>(arow, qrow, dn, ldk, o, c, bounded, qn, qe, o_err, qd_uniform, g, sub, lane,
-                                out_best, out_bid, dots);
+    return subset_term_reg<FAM>(arow, qrow, dn, ldk, o, c, bounded, qn, qe, o_err, qd_uniform, g, sub,
+                                load_target(FAM, o, g.x, g.y, g.z, g.hhi, g.hlo),
+                                load_reg_list(sub.lidx, sub.lval, sub.M, lane), lane, out_best, out_bid, dots);
   return subset_term_gen<FAM>(arow, qrow, dn, ldk, o, c, bounded, qn, qe, o_err, qd_uniform, g, sub, lane, out_best,
                               out_bid, dots);
 }
@@ -442,10 +503,10 @@ template <bool REG, int FAM, class Row>
 __device__ inline bool subset_term_sel(Row arow, const float* __restrict__ qrow, const float* __restrict__ dn,
                                        int32_t ldk, int64_t o, float c, bool bounded, float qn, float qe,
                                        const float* __restrict__ o_err, float qd_uniform, const Geo& g,
-                                       const Subset& sub, int lane, float& out_best, uint32_t& out_bid,
-                                       uint32_t& dots) {
+                                       const Subset& sub, const Tgt& t, const RegList& lst, int lane,
+                                       float& out_best, uint32_t& out_bid, uint32_t& dots) {
   if constexpr (REG)
-    return subset_term_reg<FAM>(arow, qrow, dn, ldk, o, c, bounded, qn, qe, o_err, qd_uniform, g, sub, lane,
+    return subset_term_reg<FAM>(arow, qrow, dn, ldk, o, c, bounded, qn, qe, o_err, qd_uniform, g, sub, t, lst, lane,
                                 out_best, out_bid, dots);
   else
     return subset_term_gen<FAM>(arow, qrow, dn, ldk, o, c, bounded, qn, qe, o_err, qd_uniform, g, sub, lane,
@@ -641,6 +702,9 @@ __device__ inline float block_max_lds(float v, float* red) {
   return m;
 }
 
+constexpr int kStageLoads = 8;  // row staging: float4 loads per thread in flight
+constexpr int kCandLds = 256;   // candidates whose id, coordinates and outside bound are staged in LDS
+
 template <bool BOUNDED, bool REG>
 __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_rescore_subset_lds(
     const float* __restrict__ sim, int64_t ld_s, int32_t q, MetaView meta, SimBound bound,
@@ -655,6 +719,10 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
   __shared__ float red[kLdsWaves];
   __shared__ int32_t set_idx[kSemMax];
   __shared__ float set_sim[kSemMax];
+  __shared__ float4 set_geo[kSemMax];
+  __shared__ int32_t c_id[kCandLds];
+  __shared__ float4 c_geo[kCandLds];
+  __shared__ float c_pout[kCandLds];
   __shared__ int32_t set_n;
   __shared__ unsigned long long wave_cnt[kLdsWaves][3];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -668,19 +736,30 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
   const float4* a4 = reinterpret_cast<const float4*>(arow);
   float4* s4 = reinterpret_cast<float4*>(srow);
   float mx = 0.f;
-  for (int64_t i = threadIdx.x; i < n4; i += kLdsThreads) {
-    const float4 v = a4[i];
-    if (BOUNDED) {
-      ushort4 h;
-      h.x = bf16_rne(v.x);
-      h.y = bf16_rne(v.y);
-      h.z = bf16_rne(v.z);
-      h.w = bf16_rne(v.w);
-      reinterpret_cast<ushort4*>(srow16)[i] = h;
-    } else {
-      s4[i] = v;
+  // kStageLoads loads per thread in flight before the first use
+  for (int64_t base = threadIdx.x; base < n4; base += kStageLoads * kLdsThreads) {
+    float4 v[kStageLoads];
+#pragma unroll
+    for (int u = 0; u < kStageLoads; ++u) {
+      const int64_t i = base + (int64_t)u * kLdsThreads;
+      v[u] = i < n4 ? a4[i] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    mx = fmaxf(fmaxf(mx, fmaxf(v.x, v.y)), fmaxf(v.z, v.w));
+#pragma unroll
+    for (int u = 0; u < kStageLoads; ++u) {
+      const int64_t i = base + (int64_t)u * kLdsThreads;
+      if (i >= n4) break;
+      if (BOUNDED) {
+        ushort4 h;
+        h.x = bf16_rne(v[u].x);
+        h.y = bf16_rne(v[u].y);
+        h.z = bf16_rne(v[u].z);
+        h.w = bf16_rne(v[u].w);
+        reinterpret_cast<ushort4*>(srow16)[i] = h;
+      } else {
+        s4[i] = v[u];
+      }
+      mx = fmaxf(fmaxf(mx, fmaxf(v[u].x, v[u].y)), fmaxf(v[u].z, v[u].w));
+    }
   }
   for (int64_t j = (n4 << 2) + threadIdx.x; j < n; j += kLdsThreads) {
     if (BOUNDED) srow16[j] = bf16_rne(arow[j]);
@@ -727,6 +806,24 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
   const float tau_out = block_max_lds(out, red) * (BOUNDED ? 1.0f + kBf16Margin : 1.0f);  // synchronises
   const int sn = set_n < kSemMax ? set_n : kSemMax;
   const float* qrow = qn + (int64_t)(q + r) * ldk;
+  const int p = meta.rel_pred[r];
+  const int fam = family_of(p);
+  const int32_t cnt = cand_count ? (cand_count[qq] < C ? cand_count[qq] : C) : C;
+  // the set's anchor coordinates and the first kCandLds candidates (id, own
+  // coordinates, bound on the predicate outside the list), read once for all
+  // of the relation's terms
+  auto coords = [&](int64_t j) {
+    return fam == kFamNear ? geo_of<kFamNear>(j, g) : fam == kFamVert ? geo_of<kFamVert>(j, g) : geo_of<kFamLat>(j, g);
+  };
+  if ((int)threadIdx.x < sn) set_geo[threadIdx.x] = coords(set_idx[threadIdx.x]);
+  for (int32_t i = threadIdx.x; i < cnt && i < kCandLds; i += kLdsThreads) {
+    const int32_t o = cand[(int64_t)qq * C + i];
+    c_id[i] = o;
+    if (o >= 0) {
+      c_geo[i] = coords(o);
+      c_pout[i] = pv.out[(int64_t)p * n + o];
+    }
+  }
   uint32_t dots = 0;  // FP32 dot products of this wave
   if (BOUNDED) {
     // four members per wave at a time (members past the set repeat the last one and are dropped)
@@ -735,7 +832,7 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
 #pragma unroll
       for (int u = 0; u < 4; ++u) rows[u] = dn + (int64_t)set_idx[m0 + u < sn ? m0 + u : sn - 1] * ldk;
       float d[4];
-      wave_dots<4>(qrow, rows, ldk, lane, d);
+      wave_dots<4, 3>(qrow, rows, ldk, lane, d);
       if (lane == 0)
 #pragma unroll
         for (int u = 0; u < 4; ++u)
@@ -753,18 +850,51 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
     pv.sem_cnt_out[r] = sn;
     pv.sem_tau_out[r] = tau_out;
   }
-  const int32_t cnt = cand_count ? (cand_count[qq] < C ? cand_count[qq] : C) : C;
-  const int p = meta.rel_pred[r];
   const float c = sigmoid_scale(p);
   const float qnr = BOUNDED ? bound.q_nrm[q + r] : 0.f;
   const float qer = BOUNDED ? bound.q_err[q + r] + bound.acc : 0.f;
   const float err_max = BOUNDED ? *bound.o_err_max : 0.f;
   const float qd = BOUNDED ? fmaf(qnr, err_max, qer) : 0.f;
   unsigned long long checked = 0, fell = 0;
+  // this wave's terms are candidates wave, wave + kLdsWaves, ...
+  // (wave-uniform values are moved to scalar registers: fewer vector registers)
+  auto uni = [](float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); };
+  auto o_of = [&](int32_t cc) -> int64_t {
+    if (cc >= cnt) return -1;
+    return __builtin_amdgcn_readfirstlane(cc < kCandLds ? c_id[cc] : cand[(int64_t)qq * C + cc]);
+  };
+  // register form: the next term's list ids are loaded while the current
+  // term is evaluated (its predicate values at the start of its turn)
+  auto ids_of = [&](int64_t o) {
+    int4 j = make_int4(-1, -1, -1, -1);
+    if (kRegEntries * lane < pv.m)
+      j = *reinterpret_cast<const int4*>(pv.idx + ((int64_t)p * n + o) * pv.m + kRegEntries * lane);
+    return j;
+  };
+  int64_t o_nx = o_of(wave);
+  int4 j_nx = make_int4(-1, -1, -1, -1);
+  if (REG && o_nx >= 0) j_nx = ids_of(o_nx);
   for (int32_t cc = wave; cc < cnt; cc += kLdsWaves) {
     const int64_t slot = (int64_t)qq * C + cc;
-    const int64_t o = cand[slot];
+    const int64_t o = REG ? o_nx : o_of(cc);
+    RegList lst{j_nx, make_float4(0.f, 0.f, 0.f, 0.f)};
+    if (REG && o >= 0 && kRegEntries * lane < pv.m)
+      lst.p = *reinterpret_cast<const float4*>(pv.val + ((int64_t)p * n + o) * pv.m + kRegEntries * lane);
+    if (REG) {
+      o_nx = o_of(cc + kLdsWaves);
+      if (o_nx >= 0) j_nx = ids_of(o_nx);
+    }
     if (o < 0) continue;
+    Tgt t;
+    float pout;
+    if (cc < kCandLds) {
+      const float4 tc = c_geo[cc];
+      t = Tgt{uni(tc.x), uni(tc.y), uni(tc.z)};
+      pout = uni(c_pout[cc]);
+    } else {
+      t = load_target(fam, o, g.x, g.y, g.z, g.hhi, g.hlo);
+      pout = pv.out[(int64_t)p * n + o];
+    }
     Subset sub;
     const int64_t off = ((int64_t)p * n + o) * pv.m;
     sub.lidx = pv.idx + off;
@@ -773,7 +903,7 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
     sub.sidx = set_idx;
     sub.sn = sn;
     sub.ssim = BOUNDED ? set_sim : nullptr;
-    const float pout = pv.out[(int64_t)p * n + o];
+    sub.sgeo = set_geo;
     const float a_hi = BOUNDED ? tau_out + qd : tau_out;
     if (family_of(p) == kFamNear) {
       const float b = near_log(a_hi) + pout;
@@ -787,26 +917,26 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
     switch (family_of(p)) {
       case kFamNear:
         if constexpr (BOUNDED)
-          ok = subset_term_sel<REG, kFamNear>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, g, sub, lane,
+          ok = subset_term_sel<REG, kFamNear>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, g, sub, t, lst, lane,
                                      best, bid, dots);
         else
-          ok = subset_term_sel<REG, kFamNear>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, g, sub, lane,
+          ok = subset_term_sel<REG, kFamNear>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, g, sub, t, lst, lane,
                                      best, bid, dots);
         break;
       case kFamVert:
         if constexpr (BOUNDED)
-          ok = subset_term_sel<REG, kFamVert>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, g, sub, lane,
+          ok = subset_term_sel<REG, kFamVert>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, g, sub, t, lst, lane,
                                      best, bid, dots);
         else
-          ok = subset_term_sel<REG, kFamVert>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, g, sub, lane,
+          ok = subset_term_sel<REG, kFamVert>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, g, sub, t, lst, lane,
                                      best, bid, dots);
         break;
       default:
         if constexpr (BOUNDED)
-          ok = subset_term_sel<REG, kFamLat>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, g, sub, lane,
+          ok = subset_term_sel<REG, kFamLat>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, g, sub, t, lst, lane,
                                      best, bid, dots);
         else
-          ok = subset_term_sel<REG, kFamLat>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, g, sub, lane,
+          ok = subset_term_sel<REG, kFamLat>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, g, sub, t, lst, lane,
                                      best, bid, dots);
         break;
     }
@@ -1004,7 +1134,7 @@ __global__ __launch_bounds__(256) void k_rescore_combine(
       const float* rows[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) rows[u] = dn + (o4[u] >= 0 ? o4[u] : 0) * ldk;
-      wave_dots<4>(qn + (int64_t)qq * ldk, rows, ldk, lane, dot4);
+      wave_dots<4, 3>(qn + (int64_t)qq * ldk, rows, ldk, lane, dot4);
     }
     if (lane >= 4 || c0 + lane >= cnt) continue;
     float dot = dot4[0];
@@ -1152,13 +1282,26 @@ bool lds_row_fits(int device, size_t bytes, bool bounded) {
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) v = -1;
     limit[device] = v > 0 ? v : -1;
   }
-  if (limit[device] < 0 || bytes + 1024 > (size_t)limit[device]) return false;
+  const void* fn[2] = {bounded ? reinterpret_cast<const void*>(&k_rescore_subset_lds<true, false>)
+                               : reinterpret_cast<const void*>(&k_rescore_subset_lds<false, false>),
+                       bounded ? reinterpret_cast<const void*>(&k_rescore_subset_lds<true, true>)
+                               : reinterpret_cast<const void*>(&k_rescore_subset_lds<false, true>)};
+  // the kernels' own (static) LDS comes on top of the row
+  static size_t stat[2] = {0, 0};
+  size_t& st = stat[bounded ? 1 : 0];
+  if (st == 0) {
+    for (const void* f : fn) {
+      hipFuncAttributes fa;
+      if (hipFuncGetAttributes(&fa, f) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+      }
+      st = fa.sharedSizeBytes > st ? fa.sharedSizeBytes : st;
+    }
+  }
+  if (limit[device] < 0 || bytes + st > (size_t)limit[device]) return false;
   size_t& g = granted[bounded ? 1 : 0][device];
   if (bytes > 65536 && bytes > g) {
-    const void* fn[2] = {bounded ? reinterpret_cast<const void*>(&k_rescore_subset_lds<true, false>)
-                                 : reinterpret_cast<const void*>(&k_rescore_subset_lds<false, false>),
-                         bounded ? reinterpret_cast<const void*>(&k_rescore_subset_lds<true, true>)
-                                 : reinterpret_cast<const void*>(&k_rescore_subset_lds<false, true>)};
     for (const void* f : fn)
       if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) {
         (void)hipGetLastError();
