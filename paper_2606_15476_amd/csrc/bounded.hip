@@ -41,14 +41,14 @@ __device__ inline SemBounds sem_bounds(const float* srow, int64_t i, int tc, con
 
 // K-th largest key among the values produced by `key(i)` (non-negative floats
 // as IEEE bits, or 0 for excluded entries).  All threads return the result.
-template <class KeyFn>
+template <int NT = kThreads, class KeyFn>
 __device__ uint32_t radix_select_kth(int64_t n, int64_t k, KeyFn key, uint32_t* hist, uint32_t* shared_word) {
   uint32_t prefix = 0, mask = 0;
   int64_t remaining = k;
   for (int shift = 24; shift >= 0; shift -= 8) {
-    for (int b = threadIdx.x; b < 256; b += kThreads) hist[b] = 0;
+    for (int b = threadIdx.x; b < 256; b += NT) hist[b] = 0;
     __syncthreads();
-    for (int64_t i = threadIdx.x; i < n; i += kThreads) {
+    for (int64_t i = threadIdx.x; i < n; i += NT) {
       const uint32_t u = key(i);
       if ((u & mask) == prefix) atomicAdd(&hist[(u >> shift) & 0xFFu], 1u);
     }
@@ -284,13 +284,199 @@ __global__ __launch_bounds__(kThreads) void k_bound_candidates_block(
     if (certified) certified[qq] = exact ? 1 : 0;
   }
 }
+
+// Block-per-query form for K <= kSmallK that reads the row once: the first
+// pass feeds the per-thread top-K lists with the lower bounds (16-byte loads,
+// kCandLoads per thread in flight) and keeps every upper bound, rounded up to
+// BF16, in LDS; the compaction then tests the LDS copy and confirms an object
+// with its exact upper bound only when the rounded one reaches the threshold.
+// Same candidates, certificate and overflow rule as k_bound_candidates_block.
+constexpr int kCandThreads = 512;
+constexpr int kCandLoads = 4;
+
+__device__ inline uint16_t bf16_round_up(float f) {  // f >= 0: the smallest BF16 value >= f
+  return (uint16_t)((__float_as_uint(f) + 0xFFFFu) >> 16);
+}
+
+__global__ __launch_bounds__(kCandThreads) void k_bound_candidates_lds(
+    const float* __restrict__ sim, int64_t ld_s, int64_t n, MetaView meta, SimBound bound,
+    const int32_t* __restrict__ cls, int32_t k, int32_t cap, int32_t* __restrict__ cand, int32_t* __restrict__ count,
+    int32_t* __restrict__ certified) {
+  extern __shared__ uint16_t hup[];  // upper bounds, rounded up to BF16
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t word[2];
+  __shared__ float wv[kCandThreads / 64];
+  __shared__ int32_t wt[kCandThreads / 64];
+  __shared__ int32_t filled;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int32_t qq = blockIdx.x;
+  const float* srow = sim + (int64_t)qq * ld_s;
+  const int tc = meta.tcls[qq];
+  const bool bnd = bound.q_nrm != nullptr;
+  const float qn = bnd ? bound.q_nrm[qq] : 0.f;
+  const float qe = bnd ? bound.q_err[qq] + bound.acc : 0.f;
+  float top[kSmallK];
+#pragma unroll
+  for (int e = 0; e < kSmallK; ++e) top[e] = -INFINITY;
+  // lower bound into the top list, upper bound into LDS (sem_bounds' arithmetic)
+  auto visit = [&](int64_t i, float sv, int32_t cv, float ev) {
+    float lo = sv, hi = sv;
+    if (bnd) {
+      const float kappa = (tc >= 0 && cv >= 0 && cv != tc) ? kClassFactor : 1.0f;
+      const float d = kappa * fmaf(qn, ev, qe);
+      lo = fmaxf(0.f, sv - d);
+      hi = fminf(kappa, sv + d);
+    }
+    hup[i] = bf16_round_up(hi);
+    const float v = (1.0f - kW) * lo;
+    if (v > top[kSmallK - 1]) {
+#pragma unroll
+      for (int e = kSmallK - 1; e > 0; --e) top[e] = v > top[e - 1] ? top[e - 1] : fmaxf(v, top[e]);
+      top[0] = fmaxf(top[0], v);
+    }
+  };
+  const int64_t n4 = n >> 2;
+  const float4* s4 = reinterpret_cast<const float4*>(srow);
+  const float4* e4 = reinterpret_cast<const float4*>(bound.o_err);
+  const int4* c4 = reinterpret_cast<const int4*>(cls);
+  for (int64_t b = tid; b < n4; b += (int64_t)kCandThreads * kCandLoads) {
+    float4 sv[kCandLoads], ev[kCandLoads];
+    int4 cv[kCandLoads];
+#pragma unroll
+    for (int u = 0; u < kCandLoads; ++u) {
+      const int64_t i = b + (int64_t)u * kCandThreads;
+      sv[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+      ev[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+      cv[u] = make_int4(-1, -1, -1, -1);
+      if (i < n4) {
+        sv[u] = s4[i];
+        if (bnd) {
+          ev[u] = e4[i];
+          if (cls) cv[u] = c4[i];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kCandLoads; ++u) {
+      const int64_t i = b + (int64_t)u * kCandThreads;
+      if (i >= n4) break;
+      visit(4 * i, sv[u].x, cv[u].x, ev[u].x);
+      visit(4 * i + 1, sv[u].y, cv[u].y, ev[u].y);
+      visit(4 * i + 2, sv[u].z, cv[u].z, ev[u].z);
+      visit(4 * i + 3, sv[u].w, cv[u].w, ev[u].w);
+    }
+  }
+  for (int64_t i = 4 * n4 + tid; i < n; i += kCandThreads)
+    visit(i, srow[i], cls ? cls[i] : -1, bnd ? bound.o_err[i] : 0.f);
+  float L = -INFINITY;
+  if (n > k) {
+    for (int round = 0; round < k; ++round) {
+      // largest head in each wave (lowest lane on ties), then across the waves (lowest thread)
+      float m = top[0];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+      const uint64_t holders = __ballot(top[0] == m);
+      if (lane == 0) {
+        wv[w] = m;
+        wt[w] = w * 64 + __ffsll((unsigned long long)holders) - 1;
+      }
+      __syncthreads();
+      float bm = wv[0];
+      int bt = wt[0];
+      for (int i = 1; i < kCandThreads / 64; ++i)
+        if (wv[i] > bm) {
+          bm = wv[i];
+          bt = wt[i];
+        }
+      if (tid == bt) {
+#pragma unroll
+        for (int e = 0; e < kSmallK - 1; ++e) top[e] = top[e + 1];
+        top[kSmallK - 1] = -INFINITY;
+      }
+      L = bm;
+      __syncthreads();
+    }
+  }
+  const uint64_t below = (1ull << lane) - 1ull;
+  auto compact = [&](float thresh) {
+    if (tid == 0) filled = 0;
+    __syncthreads();  // also publishes the LDS upper bounds
+    for (int64_t base = (int64_t)w * 64; base < n; base += kCandThreads) {
+      const int64_t i = base + lane;
+      bool f = i < n && __uint_as_float((uint32_t)hup[i] << 16) >= thresh;
+      if (f) f = sem_bounds(srow, i, tc, cls, bound, qq).hi >= thresh;
+      const uint64_t mask = __ballot(f);
+      if (!mask) continue;
+      int32_t first = 0;
+      if (lane == 0) first = atomicAdd(&filled, (int32_t)__popcll(mask));
+      first = __shfl(first, 0);
+      if (f) {
+        const int32_t pos = first + __popcll(mask & below);
+        if (pos < cap) cand[(int64_t)qq * cap + pos] = (int32_t)i;
+      }
+    }
+    __syncthreads();
+    return filled;
+  };
+  int32_t total = compact(L);
+  bool exact = true;
+  if (total > cap) {
+    auto hi_key = [&](int64_t i) {
+      const float h = sem_bounds(srow, i, tc, cls, bound, qq).hi;
+      return h >= L ? __float_as_uint(h) : 0u;
+    };
+    const float thresh = fmaxf(L, __uint_as_float(radix_select_kth<kCandThreads>(n, cap, hi_key, hist, word)));
+    total = compact(thresh);
+    exact = false;
+  }
+  if (tid == 0) {
+    count[qq] = total < cap ? total : cap;
+    if (certified) certified[qq] = exact ? 1 : 0;
+  }
+}
+
+// Dynamic LDS of k_bound_candidates_lds for n objects fits on `device`
+// (raises the kernel's limit once as needed).
+bool cand_lds_fits(int device, size_t bytes) {
+  static int limit[64] = {0};
+  static size_t granted[64] = {0};
+  static size_t stat = 0;
+  if (device < 0 || device >= 64) return false;
+  if (limit[device] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) v = -1;
+    limit[device] = v > 0 ? v : -1;
+  }
+  const void* fn = reinterpret_cast<const void*>(&k_bound_candidates_lds);
+  if (stat == 0) {
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, fn) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    stat = fa.sharedSizeBytes;
+  }
+  if (limit[device] < 0 || bytes + stat > (size_t)limit[device]) return false;
+  if (bytes > 65536 && bytes > granted[device]) {
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    granted[device] = bytes;
+  }
+  return true;
+}
 }  // namespace
 
 hipError_t launch_bound_candidates(const farm_memory* mem, const float* sim, int64_t ld_s, int32_t q, MetaView meta,
                                    const SimBound& bound, int32_t k, int32_t cap, int32_t* cand, int32_t* count,
                                    int32_t* certified, hipStream_t s) {
   if (q <= 0) return hipSuccess;
-  if (k <= kSmallK) {
+  const size_t lds = (size_t)round_up(mem->n, 4) * sizeof(uint16_t);
+  if (k <= kSmallK && cand_lds_fits(mem->device, lds)) {
+    hipLaunchKernelGGL(k_bound_candidates_lds, dim3((unsigned)q), dim3(kCandThreads), lds, s, sim, ld_s, mem->n, meta,
+                       bound, mem->cls, k, cap, cand, count, certified);
+  } else if (k <= kSmallK) {
     hipLaunchKernelGGL(k_bound_candidates_block, dim3((unsigned)q), dim3(kThreads), 0, s, sim, ld_s, mem->n, meta,
                        bound, mem->cls, k, cap, cand, count, certified);
   } else {
