@@ -96,7 +96,7 @@ __device__ inline uint16_t to_bf16(float f) {
 }
 
 template <int T, int EPI = kEpiSim>
-__global__ __launch_bounds__(256) void k_sim_gemm(const uint8_t* __restrict__ A, const uint8_t* __restrict__ B,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_sim_gemm(const uint8_t* __restrict__ A, const uint8_t* __restrict__ B,
                                                   int64_t M, int64_t N, int64_t K_bytes, int64_t lda_bytes,
                                                   int64_t ldb_bytes, void* __restrict__ Cv, int64_t ldc,
                                                   const float* __restrict__ a_scale,
@@ -106,11 +106,41 @@ __global__ __launch_bounds__(256) void k_sim_gemm(const uint8_t* __restrict__ A,
                                                   int64_t tiles_n) {
   __shared__ uint4 As[kBM * kRowU4];
   __shared__ uint4 Bs[kBN * kRowU4];
+  // epilogue inputs of the tile's rows (first kBM) and columns: class ids and
+  // FP8 scales of the similarity epilogue, the bias of the layer epilogues.
+  // They are read here, before any store of the block: a load issued after
+  // the stores would wait for all of them (loads and stores share one
+  // in-order counter).
+  __shared__ int32_t e_cls[kBM + kBN];
+  __shared__ float e_val[kBM + kBN];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   int64_t tm, tn;
   tile_of_block(tm, tn, tiles_m, tiles_n);
   const int64_t m0 = tm * kBM, n0 = tn * kBN;
+  {
+    int32_t ec = -1;
+    float ev = EPI == kEpiSim ? 1.0f : 0.0f;
+    if (tid < kBM) {
+      const int64_t row = m0 + tid;
+      if (EPI == kEpiSim && row < M) {
+        if (row < n_cls_rows && col_cls) ec = row_cls[row];
+        if (T == kTFP8) ev = a_scale[row];
+      }
+    } else {
+      const int64_t col = n0 + tid - kBM;
+      if (col < N) {
+        if (EPI == kEpiSim) {
+          if (col_cls) ec = col_cls[col];
+          if (T == kTFP8) ev = b_scale[col];
+        } else if (b_scale) {
+          ev = b_scale[col];
+        }
+      }
+    }
+    e_cls[tid] = ec;
+    e_val[tid] = ev;
+  }
 
   floatx16 acc[2][2];
 #pragma unroll
@@ -175,21 +205,26 @@ __global__ __launch_bounds__(256) void k_sim_gemm(const uint8_t* __restrict__ A,
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const int64_t col = n0 + wn * 64 + j * 32 + r;
-      const float sb = (EPI == kEpiSim && T == kTFP8 && col < N) ? b_scale[col] : 1.0f;
+      const int cl = wn * 64 + j * 32 + r;
+      const int64_t col = n0 + cl;
+      const int32_t cc = e_cls[kBM + cl];
+      const float cv = e_val[kBM + cl];  // FP8 column scale, or the bias
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int64_t row = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        const int rl = wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        const int64_t row = m0 + rl;
         if (row < M && col < N) {
           float val = acc[i][j][v];
           if constexpr (EPI == kEpiSim) {
-            if (T == kTFP8) val = val * (a_scale[row] * sb);
+            if (T == kTFP8) val = val * (e_val[rl] * cv);
             val = fmaxf(val, 0.f);
-            static_cast<float*>(Cv)[row * ldc + col] = val * class_factor(row, col, row_cls, n_cls_rows, col_cls);
+            const int32_t rc = e_cls[rl];
+            static_cast<float*>(Cv)[row * ldc + col] =
+                val * ((rc >= 0 && cc >= 0 && rc != cc) ? kClassFactor : 1.0f);
           } else if constexpr (EPI == kEpiBias) {
-            static_cast<float*>(Cv)[row * ldc + col] = val + (b_scale ? b_scale[col] : 0.f);
+            static_cast<float*>(Cv)[row * ldc + col] = val + cv;
           } else {
-            static_cast<uint16_t*>(Cv)[row * ldc + col] = to_bf16(gelu_erf(val + (b_scale ? b_scale[col] : 0.f)));
+            static_cast<uint16_t*>(Cv)[row * ldc + col] = to_bf16(gelu_erf(val + cv));
           }
         }
       }
