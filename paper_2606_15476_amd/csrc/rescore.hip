@@ -988,14 +988,27 @@ __device__ inline void block_argmax(float& best, uint32_t& bid, float* sv, uint3
     }
 }
 
+// Smallest BF16 value >= f (round toward +inf; f finite or -inf).
+__device__ inline uint16_t bf16_ceil(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (uint16_t)(f >= 0.f ? (u + 0xFFFFu) >> 16 : u >> 16);
+}
+
+constexpr int kFbLoads = 4;       // anchors per thread whose loads are in flight together
+constexpr int kFbLds = 20480;     // anchors whose upper values are kept in LDS (40 KB)
+
 // The exact maximum over every anchor of one term by a whole block (the
 // block-wide form of full_term, same per-pair arithmetic and survivors rule).
+// Loads are issued kFbLoads anchors at a time.  Reduced precision: the first
+// pass takes the lower values and keeps each anchor's upper value, rounded up
+// to BF16, in LDS (the first kFbLds anchors; the rest are recomputed), and the
+// survivors are the anchors whose kept upper value reaches the best lower one.
 template <int FAM, bool BOUNDED>
 __device__ void full_term_block(const float* __restrict__ arow, const float* __restrict__ qrow,
                                 const float* __restrict__ dn, int32_t ldk, int64_t n, int64_t o, float c, float qn,
                                 float qe, const float* __restrict__ o_err, const Geo& g,
                                 const int32_t* __restrict__ sidx, int sn, const float* __restrict__ ssim, float* sv,
-                                uint32_t* sid, float& out_best, uint32_t& out_bid, uint32_t& dots) {
+                                uint32_t* sid, uint16_t* hup, float& out_best, uint32_t& out_bid, uint32_t& dots) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const Tgt t = load_target(FAM, o, g.x, g.y, g.z, g.hhi, g.hlo);
   float best = value_floor<FAM>();
@@ -1009,21 +1022,57 @@ __device__ void full_term_block(const float* __restrict__ arow, const float* __r
                g.ids, best, bid);
     }
   }
+  auto value = [&](float a, const float4& cj) {
+    return pair_value<FAM>(t, record_of<FAM>(a, FAM == kFamNear ? near_log(a) : 0.f, cj), c);
+  };
   if (!BOUNDED) {
-    for (int64_t j = tid; j < n; j += kFbThreads) {
-      if (j == o) continue;
-      take_max(pair_value<FAM>(t, anchor_record(FAM, arow[j], j, g.x, g.y, g.z, g.hhi, g.hlo), c), j, g.ids, best,
-               bid);
+    for (int64_t b0 = tid; b0 < n; b0 += (int64_t)kFbThreads * kFbLoads) {
+      float av[kFbLoads];
+      float4 cv[kFbLoads];
+#pragma unroll
+      for (int u = 0; u < kFbLoads; ++u) {
+        const int64_t j = b0 + (int64_t)u * kFbThreads;
+        const int64_t jj = j < n ? j : n - 1;
+        av[u] = arow[jj];
+        cv[u] = geo_of<FAM>(jj, g);
+      }
+#pragma unroll
+      for (int u = 0; u < kFbLoads; ++u) {
+        const int64_t j = b0 + (int64_t)u * kFbThreads;
+        if (j < n && j != o) take_max(value(av[u], cv[u]), j, g.ids, best, bid);
+      }
     }
   } else {
     float lo = best;
-    for (int64_t j = tid; j < n; j += kFbThreads) {
-      if (j == o) continue;
-      const float a = fmaxf(0.f, arow[j] - fmaf(qn, o_err[j], qe));
-      lo = fmaxf(lo, pair_value<FAM>(t, anchor_record(FAM, a, j, g.x, g.y, g.z, g.hhi, g.hlo), c));
+    // lower and upper values of anchor j from its loaded similarity, error and coordinates
+    auto bounds = [&](int64_t j, float a, float e, const float4& cj, float& vlo, float& vhi) {
+      const float d = fmaf(qn, e, qe);
+      vlo = value(fmaxf(0.f, a - d), cj);
+      vhi = value(fminf(1.0f, a + d), cj);
+    };
+    for (int64_t b0 = tid; b0 < n; b0 += (int64_t)kFbThreads * kFbLoads) {
+      float av[kFbLoads], ev[kFbLoads];
+      float4 cv[kFbLoads];
+#pragma unroll
+      for (int u = 0; u < kFbLoads; ++u) {
+        const int64_t j = b0 + (int64_t)u * kFbThreads;
+        const int64_t jj = j < n ? j : n - 1;
+        av[u] = arow[jj];
+        ev[u] = o_err[jj];
+        cv[u] = geo_of<FAM>(jj, g);
+      }
+#pragma unroll
+      for (int u = 0; u < kFbLoads; ++u) {
+        const int64_t j = b0 + (int64_t)u * kFbThreads;
+        if (j >= n) break;
+        float vlo = -INFINITY, vhi = -INFINITY;
+        if (j != o) bounds(j, av[u], ev[u], cv[u], vlo, vhi);
+        lo = fmaxf(lo, vlo);
+        if (j < kFbLds) hup[j] = bf16_ceil(vhi);
+      }
     }
     lo = wave_max_f(lo);
-    __syncthreads();
+    __syncthreads();  // also publishes the kept upper values
     if (lane == 0) sv[w] = lo;
     __syncthreads();
     for (int i = 0; i < kFbThreads / 64; ++i) lo = fmaxf(lo, sv[i]);
@@ -1033,8 +1082,13 @@ __device__ void full_term_block(const float* __restrict__ arow, const float* __r
       const int64_t j = base + lane;
       bool f = false;
       if (j < n && j != o) {
-        const float a = fminf(1.0f, arow[j] + fmaf(qn, o_err[j], qe));
-        f = pair_value<FAM>(t, anchor_record(FAM, a, j, g.x, g.y, g.z, g.hhi, g.hlo), c) >= L;
+        if (j < kFbLds) {
+          f = __uint_as_float((uint32_t)hup[j] << 16) >= L;
+        } else {
+          float vlo, vhi;
+          bounds(j, arow[j], o_err[j], geo_of<FAM>(j, g), vlo, vhi);
+          f = vhi >= L;
+        }
       }
       uint64_t mask = __ballot(f);
       while (mask) {
@@ -1062,6 +1116,7 @@ __global__ __launch_bounds__(kFbThreads) void k_rescore_fallback(
     int32_t C, Geo g, int64_t n, float* __restrict__ rs_terms, uint32_t* __restrict__ rs_anchor, PropView pv) {
   __shared__ float sv[kFbThreads / 64];
   __shared__ uint32_t sid[kFbThreads / 64];
+  __shared__ uint16_t hup[BOUNDED ? kFbLds : 1];
   const uint32_t listed = *pv.fb_count;
   const int64_t count = listed < pv.fb_cap ? (int64_t)listed : pv.fb_cap;
   uint32_t dots = 0;
@@ -1089,15 +1144,15 @@ __global__ __launch_bounds__(kFbThreads) void k_rescore_fallback(
     switch (family_of(p)) {
       case kFamNear:
         full_term_block<kFamNear, BOUNDED>(arow, qrow, dn, ldk, n, o, c, qnr, qer, bound.o_err, g, sidx, sn, ssim, sv,
-                                           sid, best, bid, dots);
+                                           sid, hup, best, bid, dots);
         break;
       case kFamVert:
         full_term_block<kFamVert, BOUNDED>(arow, qrow, dn, ldk, n, o, c, qnr, qer, bound.o_err, g, sidx, sn, ssim, sv,
-                                           sid, best, bid, dots);
+                                           sid, hup, best, bid, dots);
         break;
       default:
         full_term_block<kFamLat, BOUNDED>(arow, qrow, dn, ldk, n, o, c, qnr, qer, bound.o_err, g, sidx, sn, ssim, sv,
-                                          sid, best, bid, dots);
+                                          sid, hup, best, bid, dots);
         break;
     }
     if (threadIdx.x == 0) {
