@@ -1439,7 +1439,9 @@ hipError_t launch_rescore_combine(const farm_memory* mem, const farm_workspace* 
                                   int32_t q, MetaView meta, const SimBound& bound, const int32_t* cand,
                                   const int32_t* cand_count, int32_t c, hipStream_t s) {
   if (q <= 0 || c <= 0) return hipSuccess;
-  const unsigned gx = (unsigned)((c + 15) / 16 < 8 ? (c + 15) / 16 : 8);
+  // two blocks (32 candidates per sweep) per query: more blocks than that mostly find no work, and
+  // dispatching them costs more than the loop they save
+  const unsigned gx = (unsigned)((c + 15) / 16 < 2 ? (c + 15) / 16 : 2);
   hipLaunchKernelGGL(k_rescore_combine, dim3(gx, (unsigned)q), dim3(256), 0, s, sim, ld_s, q, meta, bound, ws->qn,
                      mem->dn, mem->ldk, cand, cand_count, c, mem->cls, ws->rs_score, ws->rs_terms, ws->rs_anchor);
   return hipGetLastError();
