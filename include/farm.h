@@ -346,11 +346,12 @@ FARM_API farm_status farm_proposal_pass_form(const farm_memory* mem, int32_t dty
 
 /*
  * Candidate-scoring counters of a workspace since the last reset (host [4]):
- * stats[0] = (candidate, relation) terms evaluated by FARM_METHOD_PROPOSAL,
+ * stats[0] = (candidate, relation) terms evaluated by FARM_METHOD_PROPOSAL
+ *            (by FARM_METHOD_BOUNDED: terms scanned over all anchors),
  * stats[1] = those that fell back to the scan over all anchors,
  * stats[2], stats[3] = FP32 dot products taken, in the proposal pass and in
- *            the fallback scans, for anchors whose reduced-precision bound
- *            could not be resolved.
+ *            the scans over all anchors, for anchors whose reduced-precision
+ *            bound could not be resolved.
  * Synchronises `stream`; reset != 0 clears the counters afterwards.
  */
 FARM_API farm_status farm_workspace_proposal_stats(farm_workspace* ws, int64_t* stats, int32_t reset, void* stream);

@@ -678,6 +678,7 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
                  "bound candidates");
       }
       PropView pv;
+      pv.stats = ws->prop_stats;  // term and dot counters (full scans of BOUNDED too)
       if (method == FARM_METHOD_PROPOSAL && mem->prop_m > 0) {
         const bool in_lds = !(opt_flags & FARM_OPT_GLOBAL_PROPOSAL_PASS) && proposal_pass_in_lds(mem, dtype != FARM_F32);
         if (!in_lds) {

@@ -634,6 +634,7 @@ __global__ __launch_bounds__(64 * kTermWaves) void k_rescore_terms(
       if (o < 0) continue;
       if (MODE == kTermsFull) {
         full(slot, e, o);
+        checked += 1;
         continue;
       }
       const int r = r0 + e;

@@ -31,10 +31,19 @@ def test_roofline_of_each_phase_kind():
     cases = {"gemm": ("mfma", "k_sim_gemm<bf16>"), "pair": ("alu", "k_pair_exhaustive"),
              "topk": ("hbm", "k_bound_candidates"), "rescore": ("hbm", "k_rescore_subset_lds"),
              "propose": ("hbm", "k_semantic_sets")}
-    for phase, (bound, kernel) in cases.items():
-        phases = {p: (1e-4, 1) for p in ("normalize", "gemm", "pair", "topk", "rescore", "propose")}
+
+    class Bounded:
+        form, method = "bf16", "bounded"
+
+    runs = [(Args, info, phase, want) for phase, want in cases.items()]
+    # full anchor scans: the proposal method's fallback and the bound-pruned method's candidate terms
+    runs.append((Args, dict(info, terms_per_step=10**7, fallback_rate=0.5), "fallback",
+                 ("alu", "k_rescore_fallback")))
+    runs.append((Bounded, {"full_scan_terms_per_step": 10**7}, "rescore", ("alu", "k_rescore_terms<full>")))
+    for a, inf, phase, (bound, kernel) in runs:
+        phases = {p: (1e-4, 1) for p in ("normalize", "gemm", "pair", "topk", "rescore", "propose", "fallback")}
         phases[phase] = (1e-3, 1)
-        r = bench.dominant_roofline(phases, scene, qb, Args, cfg, info)
+        r = bench.dominant_roofline(phases, scene, qb, a, cfg, inf)
         assert r["bound"] == bound and r["kernel"].startswith(kernel), (phase, r)
         assert 0.0 < r["frac"] == round(r["achieved"] / r["peak"], 4)
-        json.dumps(r)
+        json.dumps(r, allow_nan=False)
