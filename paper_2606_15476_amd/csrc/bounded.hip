@@ -286,13 +286,18 @@ __global__ __launch_bounds__(kThreads) void k_bound_candidates_block(
 }
 
 // Block-per-query form for K <= kSmallK that reads the row once: the first
-// pass feeds the per-thread top-K lists with the lower bounds (16-byte loads,
-// kCandLoads per thread in flight) and keeps every upper bound, rounded up to
-// BF16, in LDS; the compaction then tests the LDS copy and confirms an object
-// with its exact upper bound only when the rounded one reaches the threshold.
-// Same candidates, certificate and overflow rule as k_bound_candidates_block.
+// pass keeps each thread's two largest lower bounds (16-byte loads, kCandLoads
+// per thread in flight) and every upper bound, rounded up to BF16, in LDS; the
+// compaction tests the LDS copy and confirms an object with its exact upper
+// bound only where the rounded one reaches the threshold.  The threshold is the
+// K-th largest of the threads' kept values: they belong to distinct objects,
+// so it never exceeds the K-th largest lower bound over all objects and the
+// pruning stays exact; it falls below that only when three of the K largest
+// share a thread, which admits a few more candidates.  Same certificate and
+// overflow rule as k_bound_candidates_block.
 constexpr int kCandThreads = 512;
 constexpr int kCandLoads = 4;
+constexpr int kCandKeep = 2;
 
 __device__ inline uint16_t bf16_round_up(float f) {  // f >= 0: the smallest BF16 value >= f
   return (uint16_t)((__float_as_uint(f) + 0xFFFFu) >> 16);
@@ -315,10 +320,10 @@ __global__ __launch_bounds__(kCandThreads) void k_bound_candidates_lds(
   const bool bnd = bound.q_nrm != nullptr;
   const float qn = bnd ? bound.q_nrm[qq] : 0.f;
   const float qe = bnd ? bound.q_err[qq] + bound.acc : 0.f;
-  float top[kSmallK];
+  float top[kCandKeep];
 #pragma unroll
-  for (int e = 0; e < kSmallK; ++e) top[e] = -INFINITY;
-  // lower bound into the top list, upper bound into LDS (sem_bounds' arithmetic)
+  for (int e = 0; e < kCandKeep; ++e) top[e] = -INFINITY;
+  // lower bound into the kept pair, upper bound into LDS (sem_bounds' arithmetic)
   auto visit = [&](int64_t i, float sv, int32_t cv, float ev) {
     float lo = sv, hi = sv;
     if (bnd) {
@@ -329,11 +334,8 @@ __global__ __launch_bounds__(kCandThreads) void k_bound_candidates_lds(
     }
     hup[i] = bf16_round_up(hi);
     const float v = (1.0f - kW) * lo;
-    if (v > top[kSmallK - 1]) {
-#pragma unroll
-      for (int e = kSmallK - 1; e > 0; --e) top[e] = v > top[e - 1] ? top[e - 1] : fmaxf(v, top[e]);
-      top[0] = fmaxf(top[0], v);
-    }
+    top[1] = fmaxf(top[1], fminf(v, top[0]));
+    top[0] = fmaxf(top[0], v);
   };
   const int64_t n4 = n >> 2;
   const float4* s4 = reinterpret_cast<const float4*>(srow);
@@ -389,9 +391,8 @@ __global__ __launch_bounds__(kCandThreads) void k_bound_candidates_lds(
           bt = wt[i];
         }
       if (tid == bt) {
-#pragma unroll
-        for (int e = 0; e < kSmallK - 1; ++e) top[e] = top[e + 1];
-        top[kSmallK - 1] = -INFINITY;
+        top[0] = top[1];
+        top[1] = -INFINITY;
       }
       L = bm;
       __syncthreads();
