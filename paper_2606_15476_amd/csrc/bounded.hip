@@ -298,6 +298,7 @@ __global__ __launch_bounds__(kThreads) void k_bound_candidates_block(
 constexpr int kCandThreads = 512;
 constexpr int kCandLoads = 4;
 constexpr int kCandKeep = 2;
+constexpr int kPreCap = 2048;  // objects listed by the LDS test before their exact bounds are read
 
 __device__ inline uint16_t bf16_round_up(float f) {  // f >= 0: the smallest BF16 value >= f
   return (uint16_t)((__float_as_uint(f) + 0xFFFFu) >> 16);
@@ -313,6 +314,8 @@ __global__ __launch_bounds__(kCandThreads) void k_bound_candidates_lds(
   __shared__ float wv[kCandThreads / 64];
   __shared__ int32_t wt[kCandThreads / 64];
   __shared__ int32_t filled;
+  __shared__ int32_t pre[kPreCap];  // objects whose rounded upper bound reaches the threshold
+  __shared__ int32_t pre_n;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int32_t qq = blockIdx.x;
   const float* srow = sim + (int64_t)qq * ld_s;
@@ -399,21 +402,55 @@ __global__ __launch_bounds__(kCandThreads) void k_bound_candidates_lds(
     }
   }
   const uint64_t below = (1ull << lane) - 1ull;
+  // appends the objects of this wave with f set to the candidate list
+  auto append = [&](bool f, int64_t i) {
+    const uint64_t mask = __ballot(f);
+    if (!mask) return;
+    int32_t first = 0;
+    if (lane == 0) first = atomicAdd(&filled, (int32_t)__popcll(mask));
+    first = __shfl(first, 0);
+    if (f) {
+      const int32_t pos = first + __popcll(mask & below);
+      if (pos < cap) cand[(int64_t)qq * cap + pos] = (int32_t)i;
+    }
+  };
+  // Two steps: the LDS test alone lists the objects whose rounded upper bound
+  // reaches the threshold, then their exact bounds are read all at once (no
+  // load waits behind a candidate store or behind another object's test).
   auto compact = [&](float thresh) {
-    if (tid == 0) filled = 0;
+    if (tid == 0) {
+      filled = 0;
+      pre_n = 0;
+    }
     __syncthreads();  // also publishes the LDS upper bounds
     for (int64_t base = (int64_t)w * 64; base < n; base += kCandThreads) {
       const int64_t i = base + lane;
-      bool f = i < n && __uint_as_float((uint32_t)hup[i] << 16) >= thresh;
-      if (f) f = sem_bounds(srow, i, tc, cls, bound, qq).hi >= thresh;
+      const bool f = i < n && __uint_as_float((uint32_t)hup[i] << 16) >= thresh;
       const uint64_t mask = __ballot(f);
       if (!mask) continue;
       int32_t first = 0;
-      if (lane == 0) first = atomicAdd(&filled, (int32_t)__popcll(mask));
+      if (lane == 0) first = atomicAdd(&pre_n, (int32_t)__popcll(mask));
       first = __shfl(first, 0);
       if (f) {
         const int32_t pos = first + __popcll(mask & below);
-        if (pos < cap) cand[(int64_t)qq * cap + pos] = (int32_t)i;
+        if (pos < kPreCap) pre[pos] = (int32_t)i;
+      }
+    }
+    __syncthreads();
+    const int32_t np = pre_n;
+    if (np <= kPreCap) {
+      for (int32_t base = w * 64; base < np; base += kCandThreads) {
+        const int32_t t = base + lane;
+        const int64_t i = t < np ? pre[t] : 0;
+        append(t < np && sem_bounds(srow, i, tc, cls, bound, qq).hi >= thresh, i);
+      }
+    } else {
+      // more than kPreCap: test and confirm in one sweep
+      for (int64_t base = (int64_t)w * 64; base < n; base += kCandThreads) {
+        const int64_t i = base + lane;
+        bool f = i < n && __uint_as_float((uint32_t)hup[i] << 16) >= thresh;
+        if (f) f = sem_bounds(srow, i, tc, cls, bound, qq).hi >= thresh;
+        append(f, i);
       }
     }
     __syncthreads();
