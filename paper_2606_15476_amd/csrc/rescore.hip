@@ -968,7 +968,7 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
   }
 }
 
-constexpr int kFbThreads = 256;
+constexpr int kFbThreads = 512;
 
 // Block-wide arg-max (smallest id on ties) of per-thread (best, bid).
 __device__ inline void block_argmax(float& best, uint32_t& bid, float* sv, uint32_t* sid) {
