@@ -92,90 +92,77 @@ __device__ inline float fp8_e4m3_to_float(uint8_t c) {
   return sgn * ldexpf(1.0f + (float)m * 0.125f, e - 7);
 }
 
-__device__ inline float block_sum(float v, float* red) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  float r = red[0];
-  __syncthreads();
-  return r;
+__device__ inline float wave_sum_f(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ inline float wave_max_f(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
 }
 
-__device__ inline float block_max(float v, float* red) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
-    __syncthreads();
-  }
-  float r = red[0];
-  __syncthreads();
-  return r;
-}
-
-// One block per row: L2 norm, the FP32 copy, then the reduced-precision
-// copies with the 2-norms of their values and of their rounding errors
-// (accumulated in FP32 and rounded up by a relative 1e-3 margin; they feed an
-// error bound, never a score).
-__global__ __launch_bounds__(256) void k_normalize_rows(const float* __restrict__ src, int64_t rows, int32_t d,
-                                                        int32_t ldk, float* __restrict__ dst, LowPrecRows lp,
-                                                        int* __restrict__ flags) {
-  __shared__ float red[256];
-  int64_t row = blockIdx.x;
+// One wave per row (four rows per block, shuffle reductions): L2 norm, the
+// FP32 copy, then the reduced-precision copies with the 2-norms of their
+// values and of their rounding errors (accumulated in FP32 and rounded up by a
+// relative 1e-3 margin; they feed an error bound, never a score).
+constexpr int kNormRows = 4;
+__global__ __launch_bounds__(64 * kNormRows) void k_normalize_rows(const float* __restrict__ src, int64_t rows,
+                                                                   int32_t d, int32_t ldk, float* __restrict__ dst,
+                                                                   LowPrecRows lp, int* __restrict__ flags) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * kNormRows + (threadIdx.x >> 6);
+  if (row >= rows) return;
   const float* s = src + row * (int64_t)d;
-  int tid = threadIdx.x;
   float ss = 0.f;
   int bad = 0;
-  for (int k = tid; k < d; k += 256) {
-    float v = s[k];
+  for (int k = lane; k < d; k += 64) {
+    const float v = s[k];
     if (!isfinite(v)) bad = 1;
     ss = fmaf(v, v, ss);
   }
-  float nbad = block_max((float)bad, red);
-  float nrm = sqrtf(block_sum(ss, red));
-  bool zero = !(nrm > 0.f) || !isfinite(nrm);
-  if (tid == 0 && (nbad > 0.f || zero)) atomicOr(flags, nbad > 0.f ? kBadDesc : kZeroNorm);
-  float inv = zero ? 0.f : 1.0f / nrm;
+  const bool anybad = __ballot(bad) != 0;
+  const float nrm = sqrtf(wave_sum_f(ss));
+  const bool zero = !(nrm > 0.f) || !isfinite(nrm);
+  if (lane == 0 && (anybad || zero)) atomicOr(flags, anybad ? kBadDesc : kZeroNorm);
+  const float inv = zero ? 0.f : 1.0f / nrm;
   float* o = dst + row * (int64_t)ldk;
   float amax = 0.f, eb = 0.f, nb = 0.f;
-  for (int k = tid; k < ldk; k += 256) {
-    float v = (k < d && !zero) ? s[k] * inv : 0.f;
+  for (int k = lane; k < ldk; k += 64) {
+    const float v = (k < d && !zero) ? s[k] * inv : 0.f;
     o[k] = v;
     amax = fmaxf(amax, fabsf(v));
     if (lp.bf16) {
-      uint16_t b = bf16_rne(v);
+      const uint16_t b = bf16_rne(v);
       lp.bf16[row * (int64_t)ldk + k] = b;
-      float r = bf16_to_float(b);
+      const float r = bf16_to_float(b);
       eb = fmaf(r - v, r - v, eb);
       nb = fmaf(r, r, nb);
     }
   }
   if (lp.bf16) {
-    float e2 = block_sum(eb, red), n2 = block_sum(nb, red);
-    if (tid == 0) {
+    const float e2 = wave_sum_f(eb), n2 = wave_sum_f(nb);
+    if (lane == 0) {
       if (lp.err_bf16) lp.err_bf16[row] = sqrtf(e2) * 1.001f + 1e-30f;
       if (lp.nrm_bf16) lp.nrm_bf16[row] = sqrtf(n2) * 1.001f;
     }
   }
   if (!lp.fp8) return;
-  __syncthreads();
-  float am = block_max(amax, red);
-  float scale = am > 0.f ? am / kFp8Max : 1.0f;
-  if (tid == 0) lp.fp8_scale[row] = scale;
+  const float am = wave_max_f(amax);
+  const float scale = am > 0.f ? am / kFp8Max : 1.0f;
+  if (lane == 0) lp.fp8_scale[row] = scale;
   float ef = 0.f, nf = 0.f;
-  for (int k = tid; k < ldk; k += 256) {
-    float v = o[k];
-    uint8_t c = fp8_e4m3_rne(v / scale);
+  for (int k = lane; k < ldk; k += 64) {
+    const float v = (k < d && !zero) ? s[k] * inv : 0.f;
+    const uint8_t c = fp8_e4m3_rne(v / scale);
     lp.fp8[row * (int64_t)ldk + k] = c;
-    float r = fp8_e4m3_to_float(c) * scale;
+    const float r = fp8_e4m3_to_float(c) * scale;
     ef = fmaf(r - v, r - v, ef);
     nf = fmaf(r, r, nf);
   }
-  float e2 = block_sum(ef, red), n2 = block_sum(nf, red);
-  if (tid == 0) {
+  const float e2 = wave_sum_f(ef), n2 = wave_sum_f(nf);
+  if (lane == 0) {
     if (lp.err_fp8) lp.err_fp8[row] = sqrtf(e2) * 1.001f + 1e-30f;
     if (lp.nrm_fp8) lp.nrm_fp8[row] = sqrtf(n2) * 1.001f;
   }
@@ -225,7 +212,8 @@ hipError_t launch_validate_memory(const float* desc, const float* center, const 
 hipError_t launch_normalize_rows(const float* src, int64_t rows, int32_t d, int32_t ldk, float* dst_f32,
                                  const LowPrecRows& lp, int* flags, hipStream_t s) {
   if (rows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_normalize_rows, dim3((unsigned)rows), dim3(256), 0, s, src, rows, d, ldk, dst_f32, lp, flags);
+  hipLaunchKernelGGL(k_normalize_rows, dim3((unsigned)((rows + kNormRows - 1) / kNormRows)), dim3(64 * kNormRows), 0, s,
+                     src, rows, d, ldk, dst_f32, lp, flags);
   return hipGetLastError();
 }
 
