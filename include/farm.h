@@ -19,11 +19,17 @@
  *   s(i)     = s_sem(i) * (0.5 + 0.5 * (prod_r t_r(i))^(1/R))   (1 if R = 0)
  *   TopK     = first min(K, n) objects by (s desc, id asc)
  *
- *   predicates, D = c_i - c_j (target minus anchor box center), sig = logistic:
- *   FARM_NEAR      exp(-|D|^2 / (2 * 0.5^2))
- *   FARM_ABOVE     sig(D_z / 0.1)            FARM_BELOW    sig(-D_z / 0.1)
- *   FARM_RIGHT_OF  sig((D_x r_x + D_y r_y) / 0.1)
- *   FARM_LEFT_OF   sig(-(D_x r_x + D_y r_y) / 0.1)
+ *   predicates, D = c_i - c_j (target minus anchor box center), sig = logistic,
+ *   r = the scene's viewer right axis, f = (-r_y, r_x) its viewing direction
+ *   (Appendix "Retrieval Details": closed-form evaluators; one viewer frame
+ *   per scene stands in for the stored camera views):
+ *   FARM_NEAR        exp(-|D|^2 / (2 * 0.5^2))
+ *   FARM_NEXT_TO     exp(-|D|^2 / (2 * 1.0^2))
+ *   FARM_ABOVE       sig(D_z / 0.1)            FARM_BELOW    sig(-D_z / 0.1)
+ *   FARM_RIGHT_OF    sig((D_x r_x + D_y r_y) / 0.1)
+ *   FARM_LEFT_OF     sig(-(D_x r_x + D_y r_y) / 0.1)
+ *   FARM_IN_FRONT_OF sig(-(D_x f_x + D_y f_y) / 0.1)   (nearer the viewer)
+ *   FARM_BEHIND      sig((D_x f_x + D_y f_y) / 0.1)
  *
  * Conventions shared by every entry point:
  *   - Every function returns a farm_status; farm_last_error() gives a message
@@ -65,7 +71,18 @@ typedef enum {
 
 typedef enum { FARM_F32 = 0, FARM_BF16 = 1, FARM_FP8_E4M3 = 2 } farm_dtype;
 
-typedef enum { FARM_NEAR = 0, FARM_ABOVE = 1, FARM_BELOW = 2, FARM_LEFT_OF = 3, FARM_RIGHT_OF = 4 } farm_pred;
+typedef enum {
+  FARM_NEAR = 0,
+  FARM_ABOVE = 1,
+  FARM_BELOW = 2,
+  FARM_LEFT_OF = 3,
+  FARM_RIGHT_OF = 4,
+  FARM_NEXT_TO = 5,
+  FARM_IN_FRONT_OF = 6,
+  FARM_BEHIND = 7
+} farm_pred;
+#define FARM_NUM_PRED 8         /* predicate ids 0 .. FARM_NUM_PRED - 1 */
+#define FARM_NUM_PROP_PRED 5    /* learned anchor lists cover ids 0 .. 4 */
 
 #define FARM_MAX_REL 8          /* relations per query */
 #define FARM_MAX_K 1024         /* TopK size */
@@ -220,7 +237,9 @@ typedef struct {
  * products wherever the error bound leaves the maximum open -- so the result
  * is the exact TopK whenever certified[q] = 1; certified[q] = 0 only when more
  * than 2048 objects qualified (then the 2048 with the largest upper bounds
- * were scored).  PROPOSAL returns the same records as BOUNDED, bit for bit.
+ * were scored).  PROPOSAL returns the same records as BOUNDED, bit for bit;
+ * its tables cover predicates 0..FARM_NUM_PROP_PRED-1, and terms of the other
+ * predicates are scanned over all anchors.
  * Errors: INVALID_ARG (shapes, pointers, k, unknown dtype/method/flag bits,
  * host metadata), UNSUPPORTED (missing reduced-precision copy; PROPOSAL
  * without farm_build_proposals), HIP.
@@ -309,7 +328,8 @@ FARM_API farm_status farm_mlp_step(farm_mlp* mlp, const farm_memory* mem, int32_
 
 /*
  * Proposal tables of a memory (method FARM_METHOD_PROPOSAL).  For every
- * object o and predicate p the M anchors a != o with the largest logit y_p of
+ * object o and predicate p < FARM_NUM_PROP_PRED (the network's five outputs:
+ * Near, Above, Below, LeftOf, RightOf) the M anchors a != o with the largest logit y_p of
  * the network on (o, a), their predicate values P_p(o, a), and the largest
  * P_p(o, a) over the anchors left out.  This is the anchor candidate set K_a
  * of the query-time complexity analysis (Appendix "Robust Relational Retrieval

@@ -38,19 +38,28 @@ def _sigmoid(x):
 
 
 def soft_relation(pred, ci, cj, right):
-    """The five closed-form soft predicates, written from their definitions."""
+    """The eight closed-form soft predicates, written from their definitions."""
     dx, dy, dz = (float(ci[0]) - float(cj[0]), float(ci[1]) - float(cj[1]), float(ci[2]) - float(cj[2]))
     if pred == 0:  # near: Gaussian on centroid distance, sigma 0.5 m
         return math.exp(-(dx * dx + dy * dy + dz * dz) / (2 * 0.25))
+    if pred == 5:  # next to: the same Gaussian with sigma 1 m
+        return math.exp(-(dx * dx + dy * dy + dz * dz) / 2.0)
     if pred == 1:  # above: sigmoid of the vertical offset, temperature 0.1 m
         return _sigmoid(dz / 0.1)
     if pred == 2:  # below
         return _sigmoid(-dz / 0.1)
-    lateral = dx * float(right[0]) + dy * float(right[1])
+    rx, ry = float(right[0]), float(right[1])
+    lateral = dx * rx + dy * ry
     if pred == 4:  # right of
         return _sigmoid(lateral / 0.1)
     if pred == 3:  # left of
         return _sigmoid(-lateral / 0.1)
+    # viewing direction: the right axis turned a quarter turn counter-clockwise
+    depth = dx * (-ry) + dy * rx
+    if pred == 6:  # in front of: nearer the viewer than the anchor
+        return _sigmoid(-depth / 0.1)
+    if pred == 7:  # behind
+        return _sigmoid(depth / 0.1)
     raise ValueError(pred)
 
 

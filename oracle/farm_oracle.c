@@ -47,26 +47,41 @@
 #define ORACLE_W 0.5
 #define ORACLE_CLASS_FACTOR 0.3
 #define ORACLE_NEAR_SIGMA 0.5
+#define ORACLE_NEXT_TO_SIGMA 1.0
 #define ORACLE_TAU 0.1
 #define ORACLE_MAX_REL 8
 #define ORACLE_NO_ID 0xFFFFFFFFu
 
-enum { P_NEAR = 0, P_ABOVE = 1, P_BELOW = 2, P_LEFT_OF = 3, P_RIGHT_OF = 4 };
+enum { P_NEAR = 0, P_ABOVE = 1, P_BELOW = 2, P_LEFT_OF = 3, P_RIGHT_OF = 4, P_NEXT_TO = 5, P_IN_FRONT_OF = 6,
+       P_BEHIND = 7, P_COUNT = 8 };
 
 static double logistic(double u) { return 1.0 / (1.0 + exp(-u)); }
 
-/* Soft predicate P_p(i, j) for target center ci and anchor center cj. */
+/* Soft predicate P_p(i, j) for target center ci and anchor center cj
+ * (Appendix "Retrieval Details", closed-form evaluators): Near and NextTo are
+ * Gaussians of the centroid distance (sigma 0.5 m and 1.0 m); Above/Below a
+ * logistic of the vertical offset; LeftOf/RightOf a logistic of the offset
+ * along the viewer's right axis r, InFrontOf/Behind of the offset along its
+ * viewing direction f = (-r_y, r_x) (in front = nearer the viewer), one viewer
+ * frame per scene standing in for the stored camera views; temperature 0.1 m. */
 double oracle_predicate(int p, const double* ci, const double* cj, const double* right) {
     double dx = ci[0] - cj[0], dy = ci[1] - cj[1], dz = ci[2] - cj[2];
+    double depth = dx * -right[1] + dy * right[0];  /* offset along f */
     switch (p) {
     case P_NEAR: {
         double d2 = dx * dx + dy * dy + dz * dz;
         return exp(-d2 / (2.0 * ORACLE_NEAR_SIGMA * ORACLE_NEAR_SIGMA));
     }
+    case P_NEXT_TO: {
+        double d2 = dx * dx + dy * dy + dz * dz;
+        return exp(-d2 / (2.0 * ORACLE_NEXT_TO_SIGMA * ORACLE_NEXT_TO_SIGMA));
+    }
     case P_ABOVE: return logistic(dz / ORACLE_TAU);
     case P_BELOW: return logistic(-dz / ORACLE_TAU);
     case P_RIGHT_OF: return logistic((dx * right[0] + dy * right[1]) / ORACLE_TAU);
     case P_LEFT_OF: return logistic(-(dx * right[0] + dy * right[1]) / ORACLE_TAU);
+    case P_IN_FRONT_OF: return logistic(-depth / ORACLE_TAU);
+    case P_BEHIND: return logistic(depth / ORACLE_TAU);
     default: return NAN;
     }
 }
@@ -193,7 +208,7 @@ static int check_query_meta(int32_t q, const int32_t* rel_off, const int32_t* re
         int r = rel_off[k + 1] - rel_off[k];
         if (r < 0 || r > ORACLE_MAX_REL) return -1;
         for (int rr = rel_off[k]; rr < rel_off[k + 1]; ++rr)
-            if (rel_pred[rr] < 0 || rel_pred[rr] > 4) return -1;
+            if (rel_pred[rr] < 0 || rel_pred[rr] >= P_COUNT) return -1;
     }
     return 0;
 }

@@ -26,6 +26,8 @@ import numpy as np
 
 # Predicate ids, in the order the C ABI uses.
 NEAR, ABOVE, BELOW, LEFT_OF, RIGHT_OF = 0, 1, 2, 3, 4
+NEXT_TO, IN_FRONT_OF, BEHIND = 5, 6, 7
+ALL_PREDS = tuple(range(8))
 PRED_NAMES = ("near", "above", "below", "left_of", "right_of")
 NUM_PRED = 5
 
@@ -182,15 +184,20 @@ def _plant_anchor(rng, scene: Scene, o: int, pred: int, c64: np.ndarray, r64: np
     d = c64 - c64[o]
     dist = np.sqrt((d * d).sum(axis=1))
     dist[o] = np.inf
-    if pred == NEAR:
+    if pred in (NEAR, NEXT_TO):
         ok = np.isfinite(dist)
     elif pred in (ABOVE, BELOW):
         # Target above the anchor: anchor lies at least 0.3 m lower.
         side = -d[:, 2] if pred == ABOVE else d[:, 2]
         ok = side > 0.3
-    else:
+    elif pred in (LEFT_OF, RIGHT_OF):
         lateral = -(d[:, 0] * r64[0] + d[:, 1] * r64[1])  # (target - anchor) . right
         side = lateral if pred == RIGHT_OF else -lateral
+        ok = side > 0.3
+    else:
+        # viewing direction (-r_y, r_x); in front = the anchor lies at least 0.3 m farther away
+        farther = d[:, 0] * -r64[1] + d[:, 1] * r64[0]  # (anchor - target) . forward
+        side = farther if pred == IN_FRONT_OF else -farther
         ok = side > 0.3
     ok &= np.isfinite(dist)
     if not ok.any():
@@ -201,14 +208,16 @@ def _plant_anchor(rng, scene: Scene, o: int, pred: int, c64: np.ndarray, r64: np
 
 def make_queries(cfg: Config, scene: Scene, seed: int | None = None, q: int | None = None,
                  r_min: int | None = None, r_max: int | None = None,
-                 with_class: bool = True) -> QueryBatch:
+                 with_class: bool = True, preds=None) -> QueryBatch:
     """Draw a query batch against ``scene``.
 
     Each query picks a planted target object, uses a noisy copy of its category
     centroid as the target embedding, and draws R relations; each relation has
     a uniformly drawn predicate and the anchor embedding of a noisy centroid of
-    a geometrically suitable anchor object's category.
+    a geometrically suitable anchor object's category.  ``preds`` lists the
+    predicate ids to draw from (default: the first five, Near..RightOf).
     """
+    pool = tuple(range(NUM_PRED)) if preds is None else tuple(int(p) for p in preds)
     seed = cfg.seed if seed is None else seed
     q = cfg.q if q is None else q
     r_min = cfg.r_min if r_min is None else r_min
@@ -227,7 +236,7 @@ def make_queries(cfg: Config, scene: Scene, seed: int | None = None, q: int | No
         r = int(rng.integers(r_min, r_max + 1))
         for _ in range(r):
             for _attempt in range(16):
-                p = int(rng.integers(0, NUM_PRED))
+                p = pool[int(rng.integers(0, len(pool)))]
                 j = _plant_anchor(rng, scene, o, p, c64, r64) if n > 1 else -1
                 if j >= 0:
                     break

@@ -14,8 +14,8 @@ import pytest
 
 import oracle
 from oracle.brute import brute_scores
-from synth import (ABOVE, BELOW, LEFT_OF, NEAR, RIGHT_OF, CONFIGS, QueryBatch, Scene,
-                   make_queries, make_scene)
+from synth import (ABOVE, ALL_PREDS, BEHIND, BELOW, IN_FRONT_OF, LEFT_OF, NEAR, NEXT_TO, RIGHT_OF, CONFIGS,
+                   QueryBatch, Scene, make_queries, make_scene)
 from tests import _golden
 
 LN3_TENTH = 0.1 * math.log(3.0)
@@ -84,6 +84,46 @@ def test_left_right_translation_invariant():
         assert v1 == pytest.approx(v0, abs=1e-6)
 
 
+def test_next_to_closed_form_and_scale():
+    r = [1.0, 0.0]
+    assert oracle.predicate(NEXT_TO, [0, 0, 0], [0, 0, 0], r) == 1.0
+    # |D| = 1 m = sigma  ->  exp(-1/2); |D| = 2 m -> exp(-2)
+    assert oracle.predicate(NEXT_TO, [0, 0, 0], [1.0, 0, 0], r) == pytest.approx(math.exp(-0.5), rel=1e-15)
+    assert oracle.predicate(NEXT_TO, [1, 2, 3], [1, 4, 3], r) == pytest.approx(math.exp(-2.0), rel=1e-15)
+    # a Gaussian twice as wide as Near: NextTo(a, b) = Near(a/2, b/2) (halving is exact in FP32)
+    rng = np.random.default_rng(6)
+    for _ in range(30):
+        a, b = rng.uniform(-3, 3, 3).astype(np.float32), rng.uniform(-3, 3, 3).astype(np.float32)
+        assert oracle.predicate(NEXT_TO, a, b, r) == pytest.approx(oracle.predicate(NEAR, a / 2, b / 2, r),
+                                                                    rel=1e-14)
+        assert oracle.predicate(NEXT_TO, a, b, r) >= oracle.predicate(NEAR, a, b, r)
+
+
+def test_front_behind_duality_and_viewer():
+    rng = np.random.default_rng(7)
+    for _ in range(50):
+        yaw = rng.uniform(0, 2 * math.pi)
+        r = np.array([math.sin(yaw), -math.cos(yaw)], np.float32)
+        a, b = rng.uniform(-5, 5, 3).astype(np.float32), rng.uniform(-5, 5, 3).astype(np.float32)
+        fr = oracle.predicate(IN_FRONT_OF, a, b, r)
+        bh = oracle.predicate(BEHIND, a, b, r)
+        assert fr + bh == pytest.approx(1.0, abs=1e-15)
+        assert fr == pytest.approx(oracle.predicate(BEHIND, b, a, r), abs=1e-15)
+        # the viewing direction is the right axis turned a quarter turn counter-clockwise:
+        # depth relations are side relations of a viewer turned to face the old right
+        r_turned = np.array([-r[1], r[0]], np.float32)
+        assert fr == pytest.approx(oracle.predicate(LEFT_OF, a, b, r_turned), abs=1e-15)
+        assert bh == pytest.approx(oracle.predicate(RIGHT_OF, a, b, r_turned), abs=1e-15)
+        # height plays no part
+        a2 = a.copy()
+        a2[2] += 3.0
+        assert oracle.predicate(BEHIND, a2, b, r) == pytest.approx(bh, abs=1e-15)
+    # closed form: viewer right (0, -1) looks along +x; a target 0.1 ln 3 nearer than the anchor
+    r = np.array([0.0, -1.0], np.float32)
+    assert oracle.predicate(IN_FRONT_OF, [-LN3_TENTH, 0, 0], [0, 0, 0], r) == pytest.approx(0.75, abs=2e-8)
+    assert oracle.predicate(BEHIND, [-LN3_TENTH, 0, 0], [0, 0, 0], r) == pytest.approx(0.25, abs=2e-8)
+
+
 # ---------------------------------------------------------------- hand scenes
 @pytest.mark.parametrize("path", _golden.all_paths(), ids=lambda p: p.rsplit("/", 1)[-1])
 def test_golden_scenes(path):
@@ -112,7 +152,7 @@ def test_golden_scenes_brute_force(path):
 
 
 # ---------------------------------------------------------------- brute force
-def _tiny(seed, n, r, q=3, d=6, n_cat=3):
+def _tiny(seed, n, r, q=3, d=6, n_cat=3, npred=5):
     cfg = CONFIGS["tiny"]
     rng = np.random.default_rng(seed)
     cent = rng.standard_normal((n_cat, d))
@@ -127,7 +167,7 @@ def _tiny(seed, n, r, q=3, d=6, n_cat=3):
     preds = []
     for _ in range(q):
         for _ in range(r):
-            preds.append(int(rng.integers(0, 5)))
+            preds.append(int(rng.integers(0, npred)))
         offs.append(len(preds))
     qb = QueryBatch(target=rng.standard_normal((q, d)).astype(np.float32),
                     target_cls=rng.integers(-1, n_cat, q).astype(np.int32),
@@ -141,6 +181,15 @@ def _tiny(seed, n, r, q=3, d=6, n_cat=3):
 def test_star_decomposition_equals_joint_enumeration(n, r):
     for seed in range(3):
         scene, qb = _tiny(seed * 31 + n * 7 + r, n, r)
+        s = oracle.score(scene, qb)
+        bs = np.asarray(brute_scores(scene, qb))
+        np.testing.assert_allclose(s, bs, rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("n,r", [(2, 1), (5, 2), (7, 3)])
+def test_star_decomposition_all_predicates(n, r):
+    for seed in range(3):
+        scene, qb = _tiny(seed * 17 + n * 5 + r, n, r, npred=len(ALL_PREDS))
         s = oracle.score(scene, qb)
         bs = np.asarray(brute_scores(scene, qb))
         np.testing.assert_allclose(s, bs, rtol=1e-12, atol=1e-14)
