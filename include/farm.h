@@ -321,7 +321,9 @@ FARM_API farm_status farm_mlp_logits(farm_mlp* mlp, const farm_memory* mem, int3
 /* One training step on nb labelled pairs (device pred [nb] farm_pred,
    label [nb] in {0,1}): forward, mean BCE-with-logits on the labelled
    predicate, backward; with update != 0 an AdamW step (lr, decoupled
-   weight_decay on every parameter).  loss_out: device scalar or NULL. */
+   weight_decay on every parameter).  loss_out: device scalar or NULL.
+   Pairs whose predicate has no output (id outside 0..FARM_NUM_PROP_PRED-1)
+   add nothing to the loss or the gradients (they still count in nb). */
 FARM_API farm_status farm_mlp_step(farm_mlp* mlp, const farm_memory* mem, int32_t nb, const int32_t* o_idx,
                                    const int32_t* a_idx, const int32_t* pred, const float* label, float lr,
                                    float weight_decay, int32_t update, float* loss_out, void* stream);

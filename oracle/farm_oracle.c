@@ -424,7 +424,7 @@ int farm_oracle_topk_bounded(int64_t n, int d, const float* desc, const float* c
  */
 double farm_oracle_binding_value(int64_t n, int d, const float* desc, const float* center, const float* right,
                                  int p, const float* anchor, int64_t i, int64_t j) {
-    if (i < 0 || j < 0 || i >= n || j >= n || p < 0 || p > 4) return NAN;
+    if (i < 0 || j < 0 || i >= n || j >= n || p < 0 || p >= P_COUNT) return NAN;
     double* u = (double*)malloc(sizeof(double) * (size_t)d);
     double* v = (double*)malloc(sizeof(double) * (size_t)d);
     if (!u || !v) { free(u); free(v); return NAN; }

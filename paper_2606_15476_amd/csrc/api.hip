@@ -119,7 +119,7 @@ farm_status check_queries(const farm_memory* mem, const farm_workspace* ws, int3
   if (R > ws->max_rel) { set_error("%d relations exceed the workspace's %d", R, ws->max_rel); return FARM_ERR_INVALID_ARG; }
   if (R > 0 && (!rel_pred || !rel_anchor)) { set_error("null rel_pred or rel_anchor"); return FARM_ERR_INVALID_ARG; }
   for (int32_t r = 0; r < R; ++r)
-    if (rel_pred[r] < FARM_NEAR || rel_pred[r] > FARM_RIGHT_OF) {
+    if (rel_pred[r] < 0 || rel_pred[r] >= FARM_NUM_PRED) {
       set_error("relation %d has predicate id %d", r, rel_pred[r]);
       return FARM_ERR_INVALID_ARG;
     }
@@ -300,8 +300,8 @@ farm_status farm_build_memory(int64_t n, int32_t d, const float* desc, const flo
     if ((st = dalloc(mem->allocs, mem->bytes, &mem->x, nn, "x"))) return fail(st);
     if ((st = dalloc(mem->allocs, mem->bytes, &mem->y, nn, "y"))) return fail(st);
     if ((st = dalloc(mem->allocs, mem->bytes, &mem->z, nn, "z"))) return fail(st);
-    if ((st = dalloc(mem->allocs, mem->bytes, &mem->hr_hi, nn, "lateral hi"))) return fail(st);
-    if ((st = dalloc(mem->allocs, mem->bytes, &mem->hr_lo, nn, "lateral lo"))) return fail(st);
+    if ((st = dalloc(mem->allocs, mem->bytes, &mem->hr_hi, 2 * nn, "lateral/depth hi"))) return fail(st);
+    if ((st = dalloc(mem->allocs, mem->bytes, &mem->hr_lo, 2 * nn, "lateral/depth lo"))) return fail(st);
     if ((st = dalloc(mem->allocs, mem->bytes, &mem->ext, nn * 3, "extents"))) return fail(st);
     if ((st = dalloc(mem->allocs, mem->bytes, &mem->id, nn, "ids"))) return fail(st);
     if (cls)

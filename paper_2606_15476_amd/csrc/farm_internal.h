@@ -64,7 +64,9 @@ struct farm_memory {
   float* x = nullptr;
   float* y = nullptr;
   float* z = nullptr;
-  float* hr_hi = nullptr;  // lateral coordinate c . r as an unevaluated sum hi + lo
+  // [2][n]: lateral coordinate c . r (first n), then depth c . f along the
+  // viewing direction f = (-r_y, r_x), each as an unevaluated sum hi + lo
+  float* hr_hi = nullptr;
   float* hr_lo = nullptr;
   float* ext = nullptr;    // [3][n] extents
   uint32_t* id = nullptr;

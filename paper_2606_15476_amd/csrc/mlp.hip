@@ -120,9 +120,13 @@ __global__ void k_bce(const float* __restrict__ Y, const int32_t* __restrict__ p
   float l = 0.f;
   if (b < nb) {
     const int p = pred[b];
-    const float t = label[b], v = Y[b * kNPred + p];
-    l = fmaxf(v, 0.f) - v * t + log1pf(expf(-fabsf(v)));
-    for (int c = 0; c < kNPred; ++c) dY[b * kNPred + c] = c == p ? (1.0f / (1.0f + expf(-v)) - t) / (float)nb : 0.f;
+    if (p >= 0 && p < kNPred) {  // a pair of a predicate without an output contributes nothing
+      const float t = label[b], v = Y[b * kNPred + p];
+      l = fmaxf(v, 0.f) - v * t + log1pf(expf(-fabsf(v)));
+      for (int c = 0; c < kNPred; ++c) dY[b * kNPred + c] = c == p ? (1.0f / (1.0f + expf(-v)) - t) / (float)nb : 0.f;
+    } else {
+      for (int c = 0; c < kNPred; ++c) dY[b * kNPred + c] = 0.f;
+    }
   }
   red[threadIdx.x] = l;
   __syncthreads();

@@ -123,14 +123,17 @@ __global__ __launch_bounds__(kThreads) void k_pair_exhaustive(
     const float* lrow = lsim + (int64_t)r * ld_s;
     // largest similarity error of this relation row (upper-bound output only)
     const float dmax = bounded ? fmaf(bound.q_nrm[q + r], err_max, bound.q_err[q + r] + bound.acc) : 0.f;
+    // InFrontOf/Behind measure along the viewing direction: the depth pair follows the lateral one
+    const float* rhi = hhi + (is_depth(p) ? n : 0);
+    const float* rlo = hlo + (is_depth(p) ? n : 0);
     Tgt t[kTpt];
 #pragma unroll
-    for (int u = 0; u < kTpt; ++u) t[u] = load_target(fam, ti[u], x, y, z, hhi, hlo);
+    for (int u = 0; u < kTpt; ++u) t[u] = load_target(fam, ti[u], x, y, z, rhi, rlo);
     float best[kTpt];
     uint32_t bid[kTpt];
     float term[kTpt];
     if (fam == kFamNear) {
-      relation_pass<kFamNear, WITH_ARG>(arow, lrow, n, tile0, ti, t, c, x, y, z, hhi, hlo, ids, rec, rid, best, bid);
+      relation_pass<kFamNear, WITH_ARG>(arow, lrow, n, tile0, ti, t, c, x, y, z, rhi, rlo, ids, rec, rid, best, bid);
 #pragma unroll
       for (int u = 0; u < kTpt; ++u) {
         term[u] = term_of<kFamNear>(best[u]);
@@ -138,9 +141,9 @@ __global__ __launch_bounds__(kThreads) void k_pair_exhaustive(
       }
     } else {
       if (fam == kFamVert)
-        relation_pass<kFamVert, WITH_ARG>(arow, lrow, n, tile0, ti, t, c, x, y, z, hhi, hlo, ids, rec, rid, best, bid);
+        relation_pass<kFamVert, WITH_ARG>(arow, lrow, n, tile0, ti, t, c, x, y, z, rhi, rlo, ids, rec, rid, best, bid);
       else
-        relation_pass<kFamLat, WITH_ARG>(arow, lrow, n, tile0, ti, t, c, x, y, z, hhi, hlo, ids, rec, rid, best, bid);
+        relation_pass<kFamLat, WITH_ARG>(arow, lrow, n, tile0, ti, t, c, x, y, z, rhi, rlo, ids, rec, rid, best, bid);
 #pragma unroll
       for (int u = 0; u < kTpt; ++u) {
         term[u] = term_of<kFamVert>(best[u]);
@@ -246,10 +249,12 @@ __global__ __launch_bounds__(256) void k_explain(const float* __restrict__ sim, 
       const int p = meta.rel_pred[r];
       const float* arow = sim + (int64_t)(q + r) * ld_s;
       const float c = sigmoid_scale(p);
+      const float* rhi = hhi + (is_depth(p) ? n : 0);  // depth pair of InFrontOf/Behind
+      const float* rlo = hlo + (is_depth(p) ? n : 0);
       switch (family_of(p)) {
-        case kFamNear: explain_relation<kFamNear>(arow, n, i, c, x, y, z, hhi, hlo, ids, red_v, red_id, tv, b); break;
-        case kFamVert: explain_relation<kFamVert>(arow, n, i, c, x, y, z, hhi, hlo, ids, red_v, red_id, tv, b); break;
-        default: explain_relation<kFamLat>(arow, n, i, c, x, y, z, hhi, hlo, ids, red_v, red_id, tv, b); break;
+        case kFamNear: explain_relation<kFamNear>(arow, n, i, c, x, y, z, rhi, rlo, ids, red_v, red_id, tv, b); break;
+        case kFamVert: explain_relation<kFamVert>(arow, n, i, c, x, y, z, rhi, rlo, ids, red_v, red_id, tv, b); break;
+        default: explain_relation<kFamLat>(arow, n, i, c, x, y, z, rhi, rlo, ids, red_v, red_id, tv, b); break;
       }
     }
     if (threadIdx.x == 0) {

@@ -3,11 +3,14 @@
 // produce identical values for identical inputs.
 //
 // Forms (algebraically equal to the definitions of the soft predicates):
-//   Near:        log(a_j) - 2 |c_i - c_j|^2 is compared in the log domain
-//                (no transcendental per pair); t = exp(max).
+//   Near/NextTo: log(a_j) + c |c_i - c_j|^2 with c = -1/(2 sigma^2) (-2 for
+//                Near, -1/2 for NextTo) is compared in the log domain (no
+//                transcendental per pair); t = exp(max).
 //   Above/Below: P = 1 / (1 + 2^(dz * c)), c = -+(1/tau) log2(e), dz = z_i - z_j.
 //   Left/Right:  the same sigmoid of the lateral offset dh = h_i - h_j, with h
-//                kept as an unevaluated float pair hi + lo.
+//                kept as an unevaluated float pair hi + lo; InFrontOf/Behind
+//                the same with the offset along the viewing direction (the
+//                "lateral" coordinate pair of those predicates is the depth).
 // Offsets are differences of coordinates before any scaling, so argument
 // errors are relative to the offset, not to the distance from the origin.
 #pragma once
@@ -24,12 +27,20 @@ enum Family { kFamNear = 0, kFamVert = 1, kFamLat = 2 };
 constexpr float kInvTauLog2e = 14.426950408889634f;
 
 __device__ inline int family_of(int p) {
-  return p == FARM_NEAR ? kFamNear : (p == FARM_ABOVE || p == FARM_BELOW) ? kFamVert : kFamLat;
+  return (p == FARM_NEAR || p == FARM_NEXT_TO) ? kFamNear : (p == FARM_ABOVE || p == FARM_BELOW) ? kFamVert : kFamLat;
 }
 
-// exponent scale c such that P = 1 / (1 + 2^(offset * c))
+// Predicates of the Left/Right family measured along the viewing direction
+// (their coordinate pair is the depth, not the lateral offset).
+__device__ inline bool is_depth(int p) { return p == FARM_IN_FRONT_OF || p == FARM_BEHIND; }
+
+// Per-predicate constant of pair_value: for the sigmoid families the exponent
+// scale c with P = 1 / (1 + 2^(offset * c)); for Near/NextTo the log-domain
+// coefficient -1/(2 sigma^2) of the squared distance.
 __device__ inline float sigmoid_scale(int p) {
-  return (p == FARM_ABOVE || p == FARM_RIGHT_OF) ? -kInvTauLog2e : kInvTauLog2e;
+  if (p == FARM_NEAR) return -2.0f;     // sigma 0.5 m
+  if (p == FARM_NEXT_TO) return -0.5f;  // sigma 1.0 m
+  return (p == FARM_ABOVE || p == FARM_RIGHT_OF || p == FARM_BEHIND) ? -kInvTauLog2e : kInvTauLog2e;
 }
 
 __device__ inline float rcp_approx(float v) { return __builtin_amdgcn_rcpf(v); }
@@ -84,7 +95,7 @@ __device__ inline float pair_value(const Tgt& t, const float4& rec, float c) {
     float d2 = dx * dx;
     d2 = fmaf(dy, dy, d2);
     d2 = fmaf(dz, dz, d2);
-    return fmaf(-2.0f, d2, rec.x);
+    return fmaf(c, d2, rec.x);
   } else if (FAM == kFamVert) {
     float e = exp2_approx((t.u0 - rec.y) * c);
     return rec.x * rcp_approx(1.0f + e);

@@ -168,8 +168,10 @@ __global__ __launch_bounds__(64 * kNormRows) void k_normalize_rows(const float* 
   }
 }
 
-// Error-free transformations (Knuth two-sum, FMA two-product).
+// Error-free transformations (Knuth two-sum, FMA two-product).  They rely on
+// every product and sum being rounded on its own: no contraction into FMAs.
 __device__ inline void two_sum(float a, float b, float& s, float& e) {
+#pragma clang fp contract(off)
   s = a + b;
   float bb = s - a;
   e = (a - (s - bb)) + (b - bb);
@@ -184,15 +186,20 @@ __global__ void k_geometry(const float* __restrict__ center, const float* __rest
   x[i] = cx;
   y[i] = cy;
   z[i] = cz;
-  float p1 = cx * rx, e1 = fmaf(cx, rx, -p1);
-  float p2 = cy * ry, e2 = fmaf(cy, ry, -p2);
-  float s, e3;
-  two_sum(p1, p2, s, e3);
-  float lo = e1 + e2 + e3;
-  float hi;
-  two_sum(s, lo, hi, lo);
-  hhi[i] = hi;
-  hlo[i] = lo;
+  // c . u as an unevaluated pair hi + lo (FMA two-products, two-sums), for the
+  // right axis u = r (entries 0..n-1) and the viewing direction u = (-r_y, r_x)
+  // (entries n..2n-1)
+  auto dot2 = [&](float ux, float uy, float& hi, float& lo) {
+#pragma clang fp contract(off)
+    float p1 = cx * ux, e1 = fmaf(cx, ux, -p1);
+    float p2 = cy * uy, e2 = fmaf(cy, uy, -p2);
+    float s, e3;
+    two_sum(p1, p2, s, e3);
+    lo = e1 + e2 + e3;
+    two_sum(s, lo, hi, lo);
+  };
+  dot2(rx, ry, hhi[i], hlo[i]);
+  dot2(-ry, rx, hhi[n + i], hlo[n + i]);
   for (int k = 0; k < 3; ++k) ext[k * n + i] = extent[i * 3 + k];
 }
 

@@ -170,9 +170,23 @@ __device__ inline float wave_max_f(float v) {
 
 // Geometry of the memory, passed by value.
 struct Geo {
-  const float *x, *y, *z, *hhi, *hlo;
+  const float *x, *y, *z, *hhi, *hlo;  // hhi/hlo: [2][n], lateral then depth pairs
   const uint32_t* ids;
 };
+
+// The coordinates predicate p uses: InFrontOf/Behind take the depth pair
+// (entries n..2n-1) where the other Left/Right-family predicates take the lateral one.
+__device__ inline Geo geo_for(const Geo& g, int p, int64_t n) {
+  Geo r = g;
+  if (is_depth(p)) {
+    r.hhi += n;
+    r.hlo += n;
+  }
+  return r;
+}
+
+// Learned anchor lists exist for predicates 0..FARM_NUM_PROP_PRED-1 only.
+__device__ inline bool has_lists(int p) { return p < FARM_NUM_PROP_PRED; }
 
 // Anchors of one term: the list of the target (lidx/lval, M entries) and the
 // relation's semantic set (sidx, sn entries); M == 0 means none.
@@ -581,6 +595,7 @@ __global__ __launch_bounds__(64 * kTermWaves) void k_rescore_terms(
     const float* ssim = pv.sem_sim ? pv.sem_sim + (int64_t)r * kSemMax : nullptr;
     const int p = meta.rel_pred[r];
     const float c = sigmoid_scale(p);
+    const Geo gp = geo_for(g, p, n);
     const float* arow = sim + (int64_t)(q + r) * ld_s;
     const float* qrow = qn + (int64_t)(q + r) * ldk;
     const float qnr = bounded ? bound.q_nrm[q + r] : 0.f;
@@ -589,15 +604,15 @@ __global__ __launch_bounds__(64 * kTermWaves) void k_rescore_terms(
     uint32_t bid;
     switch (family_of(p)) {
       case kFamNear:
-        full_term<kFamNear>(arow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, g, lane, sidx, sn, ssim,
+        full_term<kFamNear>(arow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, gp, lane, sidx, sn, ssim,
                              best, bid, dots);
         break;
       case kFamVert:
-        full_term<kFamVert>(arow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, g, lane, sidx, sn, ssim,
+        full_term<kFamVert>(arow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, gp, lane, sidx, sn, ssim,
                              best, bid, dots);
         break;
       default:
-        full_term<kFamLat>(arow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, g, lane, sidx, sn, ssim,
+        full_term<kFamLat>(arow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, gp, lane, sidx, sn, ssim,
                              best, bid, dots);
         break;
     }
@@ -640,27 +655,30 @@ __global__ __launch_bounds__(64 * kTermWaves) void k_rescore_terms(
       const int r = r0 + e;
       const int p = meta.rel_pred[r];
       const float c = sigmoid_scale(p);
+      const Geo gp = geo_for(g, p, n);
       const float* arow = sim + (int64_t)(q + r) * ld_s;
       const float* qrow = qn + (int64_t)(q + r) * ldk;
       const float qnr = bounded ? bound.q_nrm[q + r] : 0.f;
       const float qer = bounded ? bound.q_err[q + r] + bound.acc : 0.f;
+      float best = 0.f;
+      uint32_t bid = FARM_NO_ID;
+      bool ok = false;  // a predicate without lists is left to the fallback
+      if (has_lists(p)) {
       const Subset sub = make_subset(pv, r, p, o, n, bounded, qnr, qer, err_max);
-      float best;
-      uint32_t bid;
-      bool ok;
       switch (family_of(p)) {
         case kFamNear:
-          ok = subset_term<kFamNear>(RowF32{arow}, qrow, dn, ldk, o, c, bounded, qnr, qer, bound.o_err, 0.f, g, sub, lane, best,
+          ok = subset_term<kFamNear>(RowF32{arow}, qrow, dn, ldk, o, c, bounded, qnr, qer, bound.o_err, 0.f, gp, sub, lane, best,
                                      bid, dots);
           break;
         case kFamVert:
-          ok = subset_term<kFamVert>(RowF32{arow}, qrow, dn, ldk, o, c, bounded, qnr, qer, bound.o_err, 0.f, g, sub, lane, best,
+          ok = subset_term<kFamVert>(RowF32{arow}, qrow, dn, ldk, o, c, bounded, qnr, qer, bound.o_err, 0.f, gp, sub, lane, best,
                                      bid, dots);
           break;
         default:
-          ok = subset_term<kFamLat>(RowF32{arow}, qrow, dn, ldk, o, c, bounded, qnr, qer, bound.o_err, 0.f, g, sub, lane, best,
+          ok = subset_term<kFamLat>(RowF32{arow}, qrow, dn, ldk, o, c, bounded, qnr, qer, bound.o_err, 0.f, gp, sub, lane, best,
                                     bid, dots);
           break;
+      }
       }
       if (lane == 0) {
         rs_terms[slot * kMaxRel + e] = ok ? best : NAN;  // NaN: scanned in full by the fallback pass
@@ -809,12 +827,15 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
   const float* qrow = qn + (int64_t)(q + r) * ldk;
   const int p = meta.rel_pred[r];
   const int fam = family_of(p);
+  const Geo gp = geo_for(g, p, n);
+  const bool tab = has_lists(p);  // without lists every term goes to the fallback
   const int32_t cnt = cand_count ? (cand_count[qq] < C ? cand_count[qq] : C) : C;
   // the set's anchor coordinates and the first kCandLds candidates (id, own
   // coordinates, bound on the predicate outside the list), read once for all
   // of the relation's terms
   auto coords = [&](int64_t j) {
-    return fam == kFamNear ? geo_of<kFamNear>(j, g) : fam == kFamVert ? geo_of<kFamVert>(j, g) : geo_of<kFamLat>(j, g);
+    return fam == kFamNear ? geo_of<kFamNear>(j, gp) : fam == kFamVert ? geo_of<kFamVert>(j, gp)
+                                                       : geo_of<kFamLat>(j, gp);
   };
   if ((int)threadIdx.x < sn) set_geo[threadIdx.x] = coords(set_idx[threadIdx.x]);
   for (int32_t i = threadIdx.x; i < cnt && i < kCandLds; i += kLdsThreads) {
@@ -822,7 +843,7 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
     c_id[i] = o;
     if (o >= 0) {
       c_geo[i] = coords(o);
-      c_pout[i] = pv.out[(int64_t)p * n + o];
+      c_pout[i] = tab ? pv.out[(int64_t)p * n + o] : 0.f;
     }
   }
   uint32_t dots = 0;  // FP32 dot products of this wave
@@ -874,16 +895,16 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
   };
   int64_t o_nx = o_of(wave);
   int4 j_nx = make_int4(-1, -1, -1, -1);
-  if (REG && o_nx >= 0) j_nx = ids_of(o_nx);
+  if (REG && tab && o_nx >= 0) j_nx = ids_of(o_nx);
   for (int32_t cc = wave; cc < cnt; cc += kLdsWaves) {
     const int64_t slot = (int64_t)qq * C + cc;
     const int64_t o = REG ? o_nx : o_of(cc);
     RegList lst{j_nx, make_float4(0.f, 0.f, 0.f, 0.f)};
-    if (REG && o >= 0 && kRegEntries * lane < pv.m)
+    if (REG && tab && o >= 0 && kRegEntries * lane < pv.m)
       lst.p = *reinterpret_cast<const float4*>(pv.val + ((int64_t)p * n + o) * pv.m + kRegEntries * lane);
     if (REG) {
       o_nx = o_of(cc + kLdsWaves);
-      if (o_nx >= 0) j_nx = ids_of(o_nx);
+      if (tab && o_nx >= 0) j_nx = ids_of(o_nx);
     }
     if (o < 0) continue;
     Tgt t;
@@ -893,8 +914,8 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
       t = Tgt{uni(tc.x), uni(tc.y), uni(tc.z)};
       pout = uni(c_pout[cc]);
     } else {
-      t = load_target(fam, o, g.x, g.y, g.z, g.hhi, g.hlo);
-      pout = pv.out[(int64_t)p * n + o];
+      t = load_target(fam, o, gp.x, gp.y, gp.z, gp.hhi, gp.hlo);
+      pout = tab ? pv.out[(int64_t)p * n + o] : 0.f;
     }
     Subset sub;
     const int64_t off = ((int64_t)p * n + o) * pv.m;
@@ -912,32 +933,32 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
     } else {
       sub.cert = a_hi * pout;
     }
-    float best;
-    uint32_t bid;
-    bool ok;
-    switch (family_of(p)) {
+    float best = 0.f;
+    uint32_t bid = FARM_NO_ID;
+    bool ok = false;
+    if (tab) switch (family_of(p)) {
       case kFamNear:
         if constexpr (BOUNDED)
-          ok = subset_term_sel<REG, kFamNear>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, g, sub, t, lst, lane,
+          ok = subset_term_sel<REG, kFamNear>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
                                      best, bid, dots);
         else
-          ok = subset_term_sel<REG, kFamNear>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, g, sub, t, lst, lane,
+          ok = subset_term_sel<REG, kFamNear>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
                                      best, bid, dots);
         break;
       case kFamVert:
         if constexpr (BOUNDED)
-          ok = subset_term_sel<REG, kFamVert>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, g, sub, t, lst, lane,
+          ok = subset_term_sel<REG, kFamVert>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
                                      best, bid, dots);
         else
-          ok = subset_term_sel<REG, kFamVert>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, g, sub, t, lst, lane,
+          ok = subset_term_sel<REG, kFamVert>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
                                      best, bid, dots);
         break;
       default:
         if constexpr (BOUNDED)
-          ok = subset_term_sel<REG, kFamLat>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, g, sub, t, lst, lane,
+          ok = subset_term_sel<REG, kFamLat>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
                                      best, bid, dots);
         else
-          ok = subset_term_sel<REG, kFamLat>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, g, sub, t, lst, lane,
+          ok = subset_term_sel<REG, kFamLat>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
                                      best, bid, dots);
         break;
     }
@@ -1133,6 +1154,7 @@ __global__ __launch_bounds__(kFbThreads) void k_rescore_fallback(
     const int r = r0 + e;
     const int p = meta.rel_pred[r];
     const float c = sigmoid_scale(p);
+    const Geo gp = geo_for(g, p, n);
     const float* arow = sim + (int64_t)(q + r) * ld_s;
     const float* qrow = qn + (int64_t)(q + r) * ldk;
     const float qnr = BOUNDED ? bound.q_nrm[q + r] : 0.f;
@@ -1144,15 +1166,15 @@ __global__ __launch_bounds__(kFbThreads) void k_rescore_fallback(
     uint32_t bid;
     switch (family_of(p)) {
       case kFamNear:
-        full_term_block<kFamNear, BOUNDED>(arow, qrow, dn, ldk, n, o, c, qnr, qer, bound.o_err, g, sidx, sn, ssim, sv,
+        full_term_block<kFamNear, BOUNDED>(arow, qrow, dn, ldk, n, o, c, qnr, qer, bound.o_err, gp, sidx, sn, ssim, sv,
                                            sid, hup, best, bid, dots);
         break;
       case kFamVert:
-        full_term_block<kFamVert, BOUNDED>(arow, qrow, dn, ldk, n, o, c, qnr, qer, bound.o_err, g, sidx, sn, ssim, sv,
+        full_term_block<kFamVert, BOUNDED>(arow, qrow, dn, ldk, n, o, c, qnr, qer, bound.o_err, gp, sidx, sn, ssim, sv,
                                            sid, hup, best, bid, dots);
         break;
       default:
-        full_term_block<kFamLat, BOUNDED>(arow, qrow, dn, ldk, n, o, c, qnr, qer, bound.o_err, g, sidx, sn, ssim, sv,
+        full_term_block<kFamLat, BOUNDED>(arow, qrow, dn, ldk, n, o, c, qnr, qer, bound.o_err, gp, sidx, sn, ssim, sv,
                                           sid, hup, best, bid, dots);
         break;
     }

@@ -19,7 +19,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import FARM_NO_ID, Memory, ProposalNet, Workspace, score_query
+from . import FARM_NO_ID, NUM_PROP_PRED, Memory, ProposalNet, Workspace, score_query
 
 
 def exhaustive_bindings(mem: Memory, ws: Workspace, target, target_cls, rel_off, rel_pred, anchors, stream=None):
@@ -42,12 +42,16 @@ def sample_pairs(bind_ids: np.ndarray, ids: np.ndarray, rel_pred: np.ndarray, rn
 
     For each relation row, `per_relation` targets o drawn uniformly give one
     positive (o, b_r(o)) each and `negatives` pairs (o, a) with a drawn
-    uniformly (a != o; labelled 1 if it happens to be b_r(o))."""
+    uniformly (a != o; labelled 1 if it happens to be b_r(o)).  Rows of
+    predicates the network has no output for (ids >= NUM_PROP_PRED) are
+    skipped: their terms are scanned over all anchors."""
     R, n = bind_ids.shape
     order = np.argsort(ids)
     sorted_ids = ids[order]
     o_all, a_all, p_all, y_all = [], [], [], []
     for r in range(R):
+        if int(rel_pred[r]) >= NUM_PROP_PRED:
+            continue
         o = rng.integers(0, n, per_relation)
         b = bind_ids[r, o]
         keep = b != FARM_NO_ID

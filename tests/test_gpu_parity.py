@@ -117,6 +117,18 @@ def test_mid_config_subset_full_parity(farm):
             assert np.all(anch[qq, rank, r1 - r0:] == 0xFFFFFFFF)
 
 
+def test_all_eight_predicates_full_parity(farm):
+    """NextTo, InFrontOf and Behind beside the first five: full score matrix,
+    per-relation terms and bindings, TopK and breakdown against the oracle."""
+    import synth
+    cfg = CONFIGS["mid"]
+    scene = make_scene(cfg, seed=21)
+    qb = make_queries(cfg, scene, seed=22, q=48, preds=synth.ALL_PREDS)
+    assert set(np.unique(qb.rel_pred)) == set(synth.ALL_PREDS)
+    mem, ws, s64 = _check_full(farm, scene, qb, "mid/all predicates")
+    _topk_against_full(farm, mem, ws, scene, qb, s64, cfg.k, "mid/all predicates")
+
+
 def test_mid_config_topk_all_queries(farm):
     from tests import _gpu
     cfg = CONFIGS["mid"]
@@ -324,7 +336,7 @@ def test_invalid_queries_rejected(farm):
     target, anchors = _gpu.query_tensors(qb)
     out = torch.empty((2, 40), dtype=torch.float32, device="cuda")
     with pytest.raises(farm.FarmError):
-        farm.score_query(mem, ws, target, None, qb.rel_off, np.array([0, 7], np.int32), anchors, out)
+        farm.score_query(mem, ws, target, None, qb.rel_off, np.array([0, farm.NUM_PRED], np.int32), anchors, out)
     with pytest.raises(farm.FarmError):  # nine relations
         farm.score_query(mem, ws, target[:1], None, np.array([0, 9], np.int32), np.zeros(9, np.int32),
                          torch.ones((9, 8), device="cuda"), out)

@@ -114,6 +114,32 @@ def test_proposal_equals_bounded_mid(farm, dtype, m):
     assert checked > 0 and 0 <= fell <= checked
 
 
+@pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "bf16"])
+def test_predicates_without_lists(farm, dtype):
+    """Relations of NextTo/InFrontOf/Behind (no learned lists) are scanned in
+    full; results stay bit-identical to BOUNDED, which equals the exact TopK."""
+    import synth
+    from tests import _gpu
+    cfg = CONFIGS["mid"]
+    scene = make_scene(cfg, seed=23)
+    qb = make_queries(cfg, scene, seed=24, q=64, preds=synth.ALL_PREDS)
+    mem = _gpu.build_memory(scene, flags=farm.FARM_BUILD_BF16)
+    ws = farm.Workspace(mem, qb.q, qb.r_tot, 64)
+    net = farm.ProposalNet(scene.d, max_batch=4096, seed=5)
+    farm.build_proposals(mem, net, 64)
+    checked, fell = _compare(farm, mem, ws, qb, cfg.k, dtype)
+    # and BOUNDED (hence PROPOSAL) is the exact TopK of the oracle
+    from tests.test_gpu_parity import _check_bounded
+    ids, sc, _, _, cert = _gpu.query_topk(mem, ws, qb, cfg.k, dtype=dtype, with_cert=True, method=farm.BOUNDED)
+    assert np.all(cert == 1)
+    oidx, osc, ot, ob, ns = oracle.topk_bounded(scene, qb, cfg.k + 8)
+    _check_bounded(scene, qb, ids, sc, oidx, osc, cfg.k)
+    unlisted = int(np.sum(qb.rel_pred >= farm.NUM_PROP_PRED))
+    print(f"[proposal all predicates dtype={dtype}] terms {checked}, fell back {fell}, unlisted relations "
+          f"{unlisted}", flush=True)
+    assert unlisted > 0 and fell > 0
+
+
 def test_proposal_equals_bounded_full_size(farm):
     from tests import _gpu
     cfg = CONFIGS["precision"]

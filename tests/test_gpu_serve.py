@@ -152,7 +152,7 @@ def test_invalid_requests_rejected(farm, scenes):
     bad = [
         (0, np.zeros(d, np.float32), -1, [0], np.ones((1, d), np.float32)),          # zero target
         (0, np.full(d, np.nan, np.float32), -1, [0], np.ones((1, d), np.float32)),   # NaN target
-        (0, good_t, -1, [7], np.ones((1, d), np.float32)),                           # bad predicate
+        (0, good_t, -1, [farm.NUM_PRED], np.ones((1, d), np.float32)),               # bad predicate
         (0, good_t, -1, [0] * 9, np.ones((9, d), np.float32)),                       # R > 8
         (5, good_t, -1, [0], np.ones((1, d), np.float32)),                           # unknown scene
         (0, good_t[: d - 1], -1, [0], np.ones((1, d - 1), np.float32)),              # width
