@@ -43,7 +43,7 @@ PEAK_MFMA_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
 # counted on the definition (offsets, squares/products, scaling by 1/tau or
 # 1/(2 sigma^2), exp, 1 + e, reciprocal, times the anchor similarity, max);
 # a transcendental counts as one operation.
-FLOP_PER_PAIR = {0: 12, 1: 7, 2: 7, 3: 11, 4: 11}
+FLOP_PER_PAIR = {0: 12, 1: 7, 2: 7, 3: 11, 4: 11, 5: 12, 6: 11, 7: 11}
 
 
 def log(msg):
@@ -80,6 +80,9 @@ def parse():
     p.add_argument("--train-steps", type=int, default=600)
     p.add_argument("--list-m", type=int, default=256, help="anchors per (object, predicate) list")
     p.add_argument("--k", type=int, default=10)
+    p.add_argument("--preds", default="five", choices=["five", "all"],
+                   help="predicates the queries draw from: the workload's five (Near..RightOf) or all eight "
+                        "(+ NextTo, InFrontOf, Behind)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=0, help="queries in the CPU-oracle sample (0 = auto)")
     p.add_argument("--serving", action="store_true",
@@ -124,7 +127,7 @@ def main():
     cfg = CONFIGS[args.workload]
     t0 = time.time()
     scene = make_scene(cfg)
-    qb = make_queries(cfg, scene)
+    qb = make_queries(cfg, scene, preds=None if args.preds == "five" else tuple(range(8)))
     log(f"[bench] generated {cfg.name}: n={scene.n} d={scene.d} q={qb.q} R={qb.r_tot} in {time.time() - t0:.1f}s")
 
     dev = torch.device("cuda:0")
@@ -224,7 +227,8 @@ def main():
         "data": "synthetic (seeded scene generator; the paper's datasets are not used)",
         "config": {"workload": f"{cfg.name}: N={scene.n} objects, D={scene.d}, Q={qb.q} queries, "
                                f"R~U{{{cfg.r_min}..{cfg.r_max}}} (R_tot={qb.r_tot}), K={k}",
-                   "form": args.form, "method": args.method, "global_batch": qb.q, "parallelism": "none (1 GPU)"},
+                   "form": args.form, "method": args.method, "global_batch": qb.q, "parallelism": "none (1 GPU)",
+                   "predicates": "Near, Above, Below, LeftOf, RightOf" if args.preds == "five" else "all eight"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
                        "what": "whole-batch latency of one step"},
         "phase_ms": phase_ms,
@@ -324,7 +328,7 @@ def train_network(farm, cfg, args):
     for i in range(args.train_scenes):
         seed = 1000 + i
         sc = make_scene(cfg, seed=seed)
-        qt = make_queries(cfg, sc, seed=seed, q=256)
+        qt = make_queries(cfg, sc, seed=seed, q=256, preds=None if args.preds == "five" else tuple(range(8)))
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
         m = farm.Memory(t(sc.desc), t(sc.center), t(sc.extent), t(sc.ids.view(np.int32)), t(sc.cls), sc.view_right)
         w = farm.Workspace(m, qt.q, qt.r_tot, 16)

@@ -82,7 +82,7 @@ typedef enum {
   FARM_BEHIND = 7
 } farm_pred;
 #define FARM_NUM_PRED 8         /* predicate ids 0 .. FARM_NUM_PRED - 1 */
-#define FARM_NUM_PROP_PRED 5    /* learned anchor lists cover ids 0 .. 4 */
+#define FARM_NUM_PROP_PRED 8    /* predicates with learned anchor lists (network outputs) */
 
 #define FARM_MAX_REL 8          /* relations per query */
 #define FARM_MAX_K 1024         /* TopK size */
@@ -285,13 +285,13 @@ FARM_API farm_status farm_workspace_timings(farm_workspace* ws, double* ms, int6
  * of exactness (see farm_build_proposals).
  *
  *   x  = [u_o (dp) | u_a (dp) | g(o,a) / 4 m (12) | 0]     dp = d rounded up to 64
- *   h1 = GELU(W1 x + b1), h2 = GELU(W2 h1 + b2), y = W3 h2 + b3 (5 logits,
+ *   h1 = GELU(W1 x + b1), h2 = GELU(W2 h1 + b2), y = W3 h2 + b3 (8 logits,
  *   one per farm_pred), GELU(v) = v/2 (1 + erf(v / sqrt 2))
  *   g  = [c_o - c_a (3), e_o (3), e_a (3), |c_o - c_a|, (c_o - c_a).r,
  *         bottom_o - top_a]
  * FP32 master weights and AdamW moments (beta 0.9 / 0.999, eps 1e-8); GEMMs on
  * BF16 copies with FP32 accumulation.  Weights are row-major:
- * W1 [256][in_dim], b1 [256], W2 [256][256], b2 [256], W3 [5][256], b3 [5];
+ * W1 [256][in_dim], b1 [256], W2 [256][256], b2 [256], W3 [8][256], b3 [8];
  * in_dim = 2 dp + 64 (unused input columns hold zero weights).
  * ------------------------------------------------------------------------ */
 #define FARM_MLP_HIDDEN 256
@@ -315,7 +315,7 @@ FARM_API farm_status farm_mlp_set_weights(farm_mlp* mlp, const float* W1, const 
    as BF16 rows x_out [nb][in_dim] (device). */
 FARM_API farm_status farm_mlp_inputs(farm_mlp* mlp, const farm_memory* mem, int32_t nb, const int32_t* o_idx,
                                      const int32_t* a_idx, uint16_t* x_out, void* stream);
-/* Logits [nb][5] (device) of nb pairs. */
+/* Logits [nb][FARM_NUM_PROP_PRED] (device) of nb pairs. */
 FARM_API farm_status farm_mlp_logits(farm_mlp* mlp, const farm_memory* mem, int32_t nb, const int32_t* o_idx,
                                      const int32_t* a_idx, float* logits, void* stream);
 /* One training step on nb labelled pairs (device pred [nb] farm_pred,
@@ -330,8 +330,8 @@ FARM_API farm_status farm_mlp_step(farm_mlp* mlp, const farm_memory* mem, int32_
 
 /*
  * Proposal tables of a memory (method FARM_METHOD_PROPOSAL).  For every
- * object o and predicate p < FARM_NUM_PROP_PRED (the network's five outputs:
- * Near, Above, Below, LeftOf, RightOf) the M anchors a != o with the largest logit y_p of
+ * object o and predicate p < FARM_NUM_PROP_PRED (one network output per
+ * predicate) the M anchors a != o with the largest logit y_p of
  * the network on (o, a), their predicate values P_p(o, a), and the largest
  * P_p(o, a) over the anchors left out.  This is the anchor candidate set K_a
  * of the query-time complexity analysis (Appendix "Robust Relational Retrieval
@@ -341,7 +341,7 @@ FARM_API farm_status farm_mlp_step(farm_mlp* mlp, const farm_memory* mem, int32_
  *           must not be in use by another stream during the call)
  *   mlp     network with the memory's descriptor width, same device
  *   M       list length, 1..FARM_MAX_K (clamped to n - 1)
- * Memory: n * M * 5 * 8 bytes + 5 n * 4 bytes, plus transient chunk buffers
+ * Memory: n * M * 8 * 8 bytes + 8 n * 4 bytes, plus transient chunk buffers
  * (up to 4 GiB for very large n).  Synchronises `stream`.
  * Errors: INVALID_ARG (null, width/device mismatch, M out of range),
  * UNSUPPORTED (n > 500,000), OOM, HIP.
@@ -351,9 +351,9 @@ FARM_API farm_status farm_build_proposals(farm_memory* mem, farm_mlp* mlp, int32
 /*
  * Copy of the proposal tables (stream-ordered device-to-device copies):
  *   m_out  host out: list length M (0 = no tables; nothing else is written)
- *   idx    device [5][n][M] int32 anchor indices, or NULL
- *   val    device [5][n][M] FP32 predicate values (Near: log P), or NULL
- *   out    device [5][n] FP32 largest value outside each list, or NULL
+ *   idx    device [8][n][M] int32 anchor indices, or NULL
+ *   val    device [8][n][M] FP32 predicate values (Near/NextTo: log P), or NULL
+ *   out    device [8][n] FP32 largest value outside each list, or NULL
  */
 FARM_API farm_status farm_get_proposals(const farm_memory* mem, int32_t* m_out, int32_t* idx, float* val, float* out,
                                         void* stream);

@@ -197,7 +197,7 @@ def binding_value(scene, pred: int, anchor_vec, i: int, j: int) -> float:
                                                int(i), int(j)))
 
 
-NPRED = 5
+NPRED = 8
 NGEO = 12
 
 
@@ -215,7 +215,7 @@ def pair_features(scene, o: int, a: int):
 def mlp(weights: dict, X, pred, label, grads: bool = True):
     """Loss (mean BCE-with-logits on the labelled predicate), logits [n,5] and,
     with ``grads``, the FP64 gradients {name: array} of the proposal network.
-    weights: W1 [h,in], b1 [h], W2 [h,h], b2 [h], W3 [5,h], b3 [5]."""
+    weights: W1 [h,in], b1 [h], W2 [h,h], b2 [h], W3 [8,h], b3 [8]."""
     lib = _load()
     W = {k: np.ascontiguousarray(v, np.float64) for k, v in weights.items()}
     h, inp = W["W1"].shape

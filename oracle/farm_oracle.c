@@ -447,16 +447,16 @@ double farm_oracle_binding_value(int64_t n, int d, const float* desc, const floa
  * ranks (target, anchor) pairs per predicate.
  *
  *   x  = [u_o ; u_a ; g(o, a)]                (2d + 12 inputs)
- *   h1 = GELU(W1 x + b1),  h2 = GELU(W2 h1 + b2),  y = W3 h2 + b3   (5 logits)
+ *   h1 = GELU(W1 x + b1),  h2 = GELU(W2 h1 + b2),  y = W3 h2 + b3   (8 logits)
  *   GELU(v) = v/2 (1 + erf(v / sqrt 2))
  *   loss = mean_s BCEwithLogits(y_s[p_s], label_s)
  *        = mean_s [ max(y,0) - y*label + log(1 + exp(-|y|)) ]
  *
  * g(o, a) = [c_o - c_a (3), e_o (3), e_a (3), |c_o - c_a|, (c_o - c_a).r,
  *            (z_o - e_o,z/2) - (z_a + e_a,z/2)]   (bottom of o minus top of a)
- * Weights are row-major: W1 [h][in], W2 [h][h], W3 [5][h].
+ * Weights are row-major: W1 [h][in], W2 [h][h], W3 [8][h] (one output per predicate).
  * ------------------------------------------------------------------------ */
-#define ORACLE_NPRED 5
+#define ORACLE_NPRED 8
 #define ORACLE_NGEO 12
 
 static double gelu(double v) { return 0.5 * v * (1.0 + erf(v / sqrt(2.0))); }
@@ -479,7 +479,7 @@ void farm_oracle_pair_features(const float* center, const float* extent, const f
 
 /*
  * Loss and gradients over nsamp samples with inputs X [nsamp][in], predicate
- * p_s and binary label_s.  Gradient outputs may be NULL; logits [nsamp][5]
+ * p_s and binary label_s.  Gradient outputs may be NULL; logits [nsamp][8]
  * may be NULL.  Plain backpropagation, one sample at a time.
  */
 int farm_oracle_mlp(int in, int h, const double* W1, const double* b1, const double* W2, const double* b2,

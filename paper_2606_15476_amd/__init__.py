@@ -209,16 +209,17 @@ def build_proposals(mem: Memory, net: "ProposalNet", m: int = 256, stream=None):
 
 
 def get_proposals(mem: Memory, stream=None):
-    """(M, idx [5,n,M] int32, val [5,n,M] float32, out [5,n] float32) device tensors, or (0, None, None, None)."""
+    """(M, idx [P,n,M] int32, val [P,n,M] float32, out [P,n] float32) device tensors (P = NUM_PROP_PRED), or
+    (0, None, None, None)."""
     import torch
     m = ctypes.c_int32()
     _lib.check(_lib.L.farm_get_proposals(mem.handle, ctypes.byref(m), None, None, None, _stream(stream)))
     if m.value == 0:
         return 0, None, None, None
     n = mem.n
-    idx = torch.empty((5, n, m.value), dtype=torch.int32, device=mem.device)
-    val = torch.empty((5, n, m.value), dtype=torch.float32, device=mem.device)
-    out = torch.empty((5, n), dtype=torch.float32, device=mem.device)
+    idx = torch.empty((NUM_PROP_PRED, n, m.value), dtype=torch.int32, device=mem.device)
+    val = torch.empty((NUM_PROP_PRED, n, m.value), dtype=torch.float32, device=mem.device)
+    out = torch.empty((NUM_PROP_PRED, n), dtype=torch.float32, device=mem.device)
     _lib.check(_lib.L.farm_get_proposals(mem.handle, ctypes.byref(m), _ptr(idx), _ptr(val), _ptr(out),
                                          _stream(stream)))
     return m.value, idx, val, out
@@ -246,7 +247,7 @@ class ProposalNet:
 
     def _shapes(self):
         h, i = self.hidden, self.in_dim
-        return {"W1": (h, i), "b1": (h,), "W2": (h, h), "b2": (h,), "W3": (5, h), "b3": (5,)}
+        return {"W1": (h, i), "b1": (h,), "W2": (h, h), "b2": (h,), "W3": (NUM_PROP_PRED, h), "b3": (NUM_PROP_PRED,)}
 
     def _io(self, fn, arrays):
         ptrs = [arrays[k].ctypes.data_as(ctypes.c_void_p) for k in self.PARAMS]

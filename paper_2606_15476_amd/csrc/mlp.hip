@@ -25,7 +25,7 @@
 namespace farm {
 namespace {
 
-constexpr int kNPred = 5;
+constexpr int kNPred = FARM_NUM_PROP_PRED;  // one output per predicate
 constexpr float kGeoScale = 0.25f;  // geometry features in units of 4 m
 
 __device__ inline uint16_t bf16(float f) {

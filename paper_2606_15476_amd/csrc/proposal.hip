@@ -32,7 +32,7 @@
 namespace farm {
 namespace {
 
-constexpr int kNPred = 5;
+constexpr int kNPred = FARM_NUM_PROP_PRED;  // one list per predicate
 constexpr float kGeoScale = 0.25f;
 
 __device__ inline uint16_t bf16r(float f) {
@@ -104,7 +104,8 @@ __global__ void k_head_rows(const uint16_t* __restrict__ A2, const float* __rest
 }
 
 // Predicate value of (o, a) for predicate p in the family's comparison domain
-// (Near: log P; others: P), computed with the shared per-pair arithmetic.
+// (Near/NextTo: log P; others: P), computed with the shared per-pair arithmetic
+// (hhi/hlo: the coordinate pair of p's family, lateral or depth).
 __device__ inline float pred_value(int p, int64_t o, int64_t a, const float* x, const float* y, const float* z,
                                    const float* hhi, const float* hlo) {
   const int fam = family_of(p);
@@ -129,6 +130,9 @@ __global__ __launch_bounds__(256) void k_prop_finalize(const int32_t* __restrict
   const int p = blockIdx.y;
   const int64_t t = blockIdx.x, o = t0 + t;
   const int64_t words = (n + 31) / 32;
+  // InFrontOf/Behind use the depth pair stored after the lateral one
+  hhi += is_depth(p) ? n : 0;
+  hlo += is_depth(p) ? n : 0;
   for (int64_t w = threadIdx.x; w < words; w += blockDim.x) bits[w] = 0;
   __syncthreads();
   const int32_t* row = top_idx + ((int64_t)p * tc + t) * M;

@@ -48,32 +48,33 @@ def test_tables_match_oracle(farm):
     farm.build_proposals(mem, net, 48)
     m, idx, val, out = _tables(farm, mem)
     n = scene.n
-    assert m == 48 and idx.shape == (5, n, m)
+    assert m == 48 and idx.shape == (farm.NUM_PROP_PRED, n, m)
     rng = np.random.default_rng(0)
     for o in rng.choice(n, 12, replace=False):
-        for p in range(5):
+        for p in range(farm.NUM_PROP_PRED):
             lst = idx[p, o]
             assert np.all((lst >= 0) & (lst < n)) and np.all(lst != o)
             assert len(set(lst.tolist())) == m
-            # cached values: log P for Near, P otherwise
+            # cached values: log P for the Gaussians (Near, NextTo), P otherwise
+            log_domain = p in (farm.NEAR, farm.NEXT_TO)
             for e, a in enumerate(lst):
                 v64 = _p64(scene, p, o, a)
-                got = np.exp(np.float64(val[p, o, e])) if p == farm.NEAR else np.float64(val[p, o, e])
+                got = np.exp(np.float64(val[p, o, e])) if log_domain else np.float64(val[p, o, e])
                 assert abs(got - v64) <= REL * abs(v64) + ABS, (o, p, a, got, v64)
             # bound over the anchors left out
             rest = [a for a in range(n) if a != o and a not in set(lst.tolist())]
             pout64 = max(_p64(scene, p, o, a) for a in rest)
-            got = np.exp(np.float64(out[p, o])) if p == farm.NEAR else np.float64(out[p, o])
+            got = np.exp(np.float64(out[p, o])) if log_domain else np.float64(out[p, o])
             assert abs(got - pout64) <= REL * abs(pout64) + ABS, (o, p, got, pout64)
         # the lists are the network's top M (up to logit rounding of the factorised first layer)
         o_t = torch.full((n,), int(o), dtype=torch.int32, device="cuda")
         a_t = torch.arange(n, dtype=torch.int32, device="cuda")
-        lg = torch.empty((n, 5), dtype=torch.float32, device="cuda")
+        lg = torch.empty((n, farm.NUM_PROP_PRED), dtype=torch.float32, device="cuda")
         net.logits(mem, o_t, a_t, lg)
         torch.cuda.synchronize()
         lg = lg.cpu().numpy()
         lg[o] = -np.inf
-        for p in range(5):
+        for p in range(farm.NUM_PROP_PRED):
             top = set(np.argsort(-lg[:, p], kind="stable")[:m].tolist())
             overlap = len(top & set(idx[p, o].tolist())) / m
             assert overlap >= 0.9, (o, p, overlap)
@@ -115,9 +116,10 @@ def test_proposal_equals_bounded_mid(farm, dtype, m):
 
 
 @pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "bf16"])
-def test_predicates_without_lists(farm, dtype):
-    """Relations of NextTo/InFrontOf/Behind (no learned lists) are scanned in
-    full; results stay bit-identical to BOUNDED, which equals the exact TopK."""
+def test_all_eight_predicates(farm, dtype):
+    """Lists for NextTo/InFrontOf/Behind too (their depth coordinates, NextTo's
+    log domain); results stay bit-identical to BOUNDED, which equals the exact
+    TopK."""
     import synth
     from tests import _gpu
     cfg = CONFIGS["mid"]
@@ -134,10 +136,8 @@ def test_predicates_without_lists(farm, dtype):
     assert np.all(cert == 1)
     oidx, osc, ot, ob, ns = oracle.topk_bounded(scene, qb, cfg.k + 8)
     _check_bounded(scene, qb, ids, sc, oidx, osc, cfg.k)
-    unlisted = int(np.sum(qb.rel_pred >= farm.NUM_PROP_PRED))
-    print(f"[proposal all predicates dtype={dtype}] terms {checked}, fell back {fell}, unlisted relations "
-          f"{unlisted}", flush=True)
-    assert unlisted > 0 and fell > 0
+    print(f"[proposal all predicates dtype={dtype}] terms {checked}, fell back {fell}", flush=True)
+    assert checked > 0 and fell < checked
 
 
 def test_proposal_equals_bounded_full_size(farm):

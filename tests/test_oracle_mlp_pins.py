@@ -9,38 +9,42 @@ import pytest
 import oracle
 from synth import Scene
 
+NP = oracle.NPRED  # one network output per predicate
+
 
 def _weights(rng, inp, h, scale=0.3):
     return {"W1": rng.standard_normal((h, inp)) * scale, "b1": rng.standard_normal(h) * 0.1,
             "W2": rng.standard_normal((h, h)) * scale, "b2": rng.standard_normal(h) * 0.1,
-            "W3": rng.standard_normal((5, h)) * scale, "b3": rng.standard_normal(5) * 0.1}
+            "W3": rng.standard_normal((NP, h)) * scale, "b3": rng.standard_normal(NP) * 0.1}
 
 
 def test_zero_network_closed_forms():
     """All weights zero: y = b3, so the loss is the BCE of a constant logit."""
     inp, h = 7, 4
     W = {k: np.zeros_like(v) for k, v in _weights(np.random.default_rng(0), inp, h).items()}
-    W["b3"] = np.array([0.0, 1.0, -2.0, 0.5, 3.0])
-    X = np.ones((4, inp))
-    pred = np.array([0, 1, 2, 4], np.int32)
-    lab = np.array([1.0, 0.0, 1.0, 1.0])
+    W["b3"] = np.array([0.0, 1.0, -2.0, 0.5, 3.0, -1.0, 0.25, 2.0])
+    X = np.ones((6, inp))
+    pred = np.array([0, 1, 2, 4, 5, 7], np.int32)
+    lab = np.array([1.0, 0.0, 1.0, 1.0, 0.0, 1.0])
     loss, logits, g = oracle.mlp(W, X, pred, lab)
     sp = lambda v: math.log1p(math.exp(v))  # softplus
-    want = (math.log(2.0) + sp(1.0) + sp(2.0) + sp(-3.0)) / 4.0  # BCE(y, t) = softplus(y) - t y
+    # BCE(y, t) = softplus(y) - t y
+    want = (math.log(2.0) + sp(1.0) + sp(2.0) + sp(-3.0) + sp(-1.0) + sp(-2.0)) / 6.0
     assert loss == pytest.approx(want, rel=1e-14)
-    np.testing.assert_array_equal(logits, np.tile(W["b3"], (4, 1)))
+    np.testing.assert_array_equal(logits, np.tile(W["b3"], (6, 1)))
     # d loss / d b3[p] = mean over samples with that predicate of sigmoid(y) - label
     sig = lambda v: 1 / (1 + math.exp(-v))
-    assert g["b3"][0] == pytest.approx((sig(0.0) - 1) / 4)
-    assert g["b3"][1] == pytest.approx(sig(1.0) / 4)
-    assert g["b3"][3] == 0.0
+    assert g["b3"][0] == pytest.approx((sig(0.0) - 1) / 6)
+    assert g["b3"][1] == pytest.approx(sig(1.0) / 6)
+    assert g["b3"][5] == pytest.approx(sig(-1.0) / 6)
+    assert g["b3"][3] == 0.0 and g["b3"][6] == 0.0
 
 
 def test_gelu_values_through_a_one_unit_network():
     """h = 1, identity-like weights expose GELU(z) in the logit: y = GELU(GELU(z))."""
     inp, h = 1, 1
     W = {"W1": np.array([[1.0]]), "b1": np.zeros(1), "W2": np.array([[1.0]]), "b2": np.zeros(1),
-         "W3": np.ones((5, 1)), "b3": np.zeros(5)}
+         "W3": np.ones((NP, 1)), "b3": np.zeros(NP)}
     gelu = lambda v: 0.5 * v * (1 + math.erf(v / math.sqrt(2)))
     for z, g1 in ((0.0, 0.0), (1.0, 0.8413447460685429), (-1.0, -0.15865525393145707)):
         assert gelu(z) == pytest.approx(g1, abs=1e-15)
@@ -67,7 +71,7 @@ def test_gradients_match_central_differences():
     inp, h, n = 2 * 8 + 12, 16, 9
     W = _weights(rng, inp, h)
     X = rng.standard_normal((n, inp))
-    pred = rng.integers(0, 5, n).astype(np.int32)
+    pred = rng.integers(0, NP, n).astype(np.int32)
     lab = rng.integers(0, 2, n).astype(np.float64)
     loss, _, g = oracle.mlp(W, X, pred, lab)
     eps = 1e-6
