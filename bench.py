@@ -2,7 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload precision]
                     [--form bf16|f32|fp8] [--method proposal|bounded|exhaustive]
-                    [--no-cpu-baseline] [--serving]
+                    [--no-cpu-baseline] [--serving] [--latency] [--preds five|all]
 
 One step = one farm_query_topk call over the 4,096-query batch of the
 N = 20,000 scene, inputs resident in HBM: query normalisation, similarity GEMM,
@@ -18,7 +18,8 @@ Prints ONE JSON line with the throughput (queries/s), batch latency
 percentiles, the roofline of the dominant kernel (timed live with the
 library's HIP-event phase timer on the launch stream) and the CPU oracle
 timed on a bounded sample of the same workload.  --serving instead runs the
-request loop over 16 resident scenes and prints p50/p99 latency per rate.
+request loop over 16 resident scenes and prints p50/p99 latency per rate;
+--latency the closed-loop batch-1 latency per scene size.
 """
 from __future__ import annotations
 
@@ -89,6 +90,8 @@ def parse():
                    help="run the request loop over 16 resident scenes instead (p50/p99 latency per arrival rate)")
     p.add_argument("--rates", default="500,2000,5000", help="Poisson arrival rates (requests/s) of --serving")
     p.add_argument("--requests", type=int, default=3000, help="requests per rate of --serving")
+    p.add_argument("--latency", action="store_true",
+                   help="closed-loop batch-1 latency per scene size instead (one query at a time, p50/p99)")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                    help="only run one plain device copy of BYTES (reference for the HBM byte counters) and exit")
     return p.parse_args()
@@ -118,6 +121,9 @@ def main():
         sys.exit(2)
     if args.serving:
         serving(args)
+        return
+    if args.latency:
+        latency(args)
         return
     import torch
 
@@ -314,6 +320,59 @@ def serving(args):
                       "config": {"workload": "16 scenes, N log-uniform [500, 20000], D=1152, R~U{1..4}, K=10, "
                                              "Poisson arrivals", "slots": 4, "max_batch_q": 64,
                                  "requests_per_rate": args.requests, "scene_sizes": sorted(int(x) for x in sizes)},
+                      "results": results}), flush=True)
+
+
+def latency(args):
+    """Closed-loop batch-1 latency: one query at a time (submit, wait for the
+    result, next) on precision-generator scenes of N = 1k, 5k and 20k objects,
+    for the plain FP32 exhaustive form and the BF16 learned-proposal form;
+    latency = host wall time of one farm_query_topk call plus its
+    synchronisation.  256 queries per scene after 16 untimed ones."""
+    import torch
+
+    import paper_2606_15476_amd as farm
+    from synth import CONFIGS, make_queries, make_scene
+    cfg = CONFIGS["precision"]
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    net = train_network(farm, cfg, args) if args.train_scenes > 0 else None
+    results = []
+    for n in (1000, 5000, 20000):
+        sc = make_scene(cfg, seed=4000 + n, n=n)
+        qb = make_queries(cfg, sc, seed=4100 + n, q=272)
+        mem = farm.Memory(t(sc.desc), t(sc.center), t(sc.extent), t(sc.ids.view(np.int32)), t(sc.cls), sc.view_right,
+                          flags=farm.FARM_BUILD_BF16)
+        forms = {"f32-exhaustive": (farm.F32, farm.EXHAUSTIVE)}
+        if net is not None:
+            farm.build_proposals(mem, net, args.list_m)
+            forms["bf16-proposal"] = (farm.BF16, farm.PROPOSAL)
+        ws = farm.Workspace(mem, 1, farm.FARM_MAX_REL, 64)
+        d = sc.d
+        queries = []
+        for q in range(qb.q):
+            r0, r1 = int(qb.rel_off[q]), int(qb.rel_off[q + 1])
+            queries.append((t(qb.target[q:q + 1]), qb.target_cls[q:q + 1], np.array([0, r1 - r0], np.int32),
+                            qb.rel_pred[r0:r1], t(qb.rel_anchor.reshape(-1, d)[r0:r1])))
+        oid = torch.empty((1, args.k), dtype=torch.int32, device=dev)
+        osc = torch.empty((1, args.k), dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+        for name, (dt, me) in forms.items():
+            lat = []
+            for i, (tg, tc, ro, rp, an) in enumerate(queries):
+                a = time.perf_counter()
+                farm.query_topk(mem, ws, tg, tc, ro, rp, an, args.k, oid, osc, dtype=dt, method=me)
+                torch.cuda.synchronize()
+                if i >= 16:
+                    lat.append(time.perf_counter() - a)
+            v = np.asarray(lat) * 1e3
+            row = {"n": n, "form": name, "p50_ms": round(float(np.percentile(v, 50)), 3),
+                   "p99_ms": round(float(np.percentile(v, 99)), 3), "queries": len(lat)}
+            log(f"[latency] {row}")
+            results.append(row)
+    print(json.dumps({"metric": "closed-loop batch-1 query latency", "unit": "ms", "n_gpus": 1,
+                      "config": {"workload": "precision generator, N in {1000, 5000, 20000}, D=1152, R~U{1..4}, "
+                                             "K=10, one query per call"},
                       "results": results}), flush=True)
 
 
