@@ -518,9 +518,20 @@ def cpu_baseline(scene, qb, oid, osc, k, sample):
     ids = oid[:m].cpu().numpy().view(np.uint32)
     hits = [len(set(int(x) for x in ids[i]) & set(int(x) for x in scene.ids[order[i]])) / k for i in range(m)]
     log(f"[bench] cpu baseline: {secs:.1f}s, recall@{k} on the sample {np.mean(hits):.4f}")
+    # the first query alone: the oracle parallelises over queries, so one thread does all of it
+    a = time.perf_counter()
+    oracle.score(scene, qb.subset(range(1)))
+    secs1 = time.perf_counter() - a
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    log(f"[bench] cpu baseline, one thread: {secs1:.1f}s for one query")
     return ({"value": round(m / secs, 4), "unit": "queries/s", "cores": min(threads, m), "kind": "oracle",
              "sample": f"first {m} queries of the batch, full exhaustive FP64 scoring of all {scene.n} objects + TopK",
-             "seconds": round(secs, 2)},
+             "seconds": round(secs, 2), "one_thread_seconds_per_query": round(secs1, 2), "cpu": model},
             {"value": float(np.mean(hits)), "queries": m, "what": "|TopK_gpu & TopK_oracle| / K on the CPU sample"})
 
 
