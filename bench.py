@@ -44,7 +44,7 @@ PEAK_MFMA_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
 # counted on the definition (offsets, squares/products, scaling by 1/tau or
 # 1/(2 sigma^2), exp, 1 + e, reciprocal, times the anchor similarity, max);
 # a transcendental counts as one operation.
-FLOP_PER_PAIR = {0: 12, 1: 7, 2: 7, 3: 11, 4: 11, 5: 12, 6: 11, 7: 11}
+FLOP_PER_PAIR = {0: 12, 1: 7, 2: 7, 3: 11, 4: 11, 5: 12, 6: 11, 7: 11, 8: 12}
 
 
 def log(msg):
@@ -128,12 +128,12 @@ def main():
     import torch
 
     import paper_2606_15476_amd as farm
-    from synth import CONFIGS, make_queries, make_scene
+    from synth import ALL_PREDS, CONFIGS, make_queries, make_scene
 
     cfg = CONFIGS[args.workload]
     t0 = time.time()
     scene = make_scene(cfg)
-    qb = make_queries(cfg, scene, preds=None if args.preds == "five" else tuple(range(8)))
+    qb = make_queries(cfg, scene, preds=None if args.preds == "five" else ALL_PREDS)
     log(f"[bench] generated {cfg.name}: n={scene.n} d={scene.d} q={qb.q} R={qb.r_tot} in {time.time() - t0:.1f}s")
 
     dev = torch.device("cuda:0")
@@ -234,7 +234,7 @@ def main():
         "config": {"workload": f"{cfg.name}: N={scene.n} objects, D={scene.d}, Q={qb.q} queries, "
                                f"R~U{{{cfg.r_min}..{cfg.r_max}}} (R_tot={qb.r_tot}), K={k}",
                    "form": args.form, "method": args.method, "global_batch": qb.q, "parallelism": "none (1 GPU)",
-                   "predicates": "Near, Above, Below, LeftOf, RightOf" if args.preds == "five" else "all eight"},
+                   "predicates": "Near, Above, Below, LeftOf, RightOf" if args.preds == "five" else "all nine"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
                        "what": "whole-batch latency of one step"},
         "phase_ms": phase_ms,
@@ -258,7 +258,7 @@ def serving(args):
     import torch
 
     import paper_2606_15476_amd as farm
-    from synth import CONFIGS, make_queries, make_scene
+    from synth import ALL_PREDS, CONFIGS, make_queries, make_scene
     cfg = CONFIGS["precision"]
     rng = np.random.default_rng(3100)
     sizes = np.exp(rng.uniform(np.log(500), np.log(20000), 16)).astype(int)
@@ -332,7 +332,7 @@ def latency(args):
     import torch
 
     import paper_2606_15476_amd as farm
-    from synth import CONFIGS, make_queries, make_scene
+    from synth import ALL_PREDS, CONFIGS, make_queries, make_scene
     cfg = CONFIGS["precision"]
     dev = torch.device("cuda:0")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
@@ -381,13 +381,13 @@ def train_network(farm, cfg, args):
     the generator (seeds 1000, 1001, ...)."""
     import torch
     from paper_2606_15476_amd import proposal
-    from synth import make_queries, make_scene
+    from synth import ALL_PREDS, make_queries, make_scene
     t0 = time.time()
     data, keep = [], []
     for i in range(args.train_scenes):
         seed = 1000 + i
         sc = make_scene(cfg, seed=seed)
-        qt = make_queries(cfg, sc, seed=seed, q=256, preds=None if args.preds == "five" else tuple(range(8)))
+        qt = make_queries(cfg, sc, seed=seed, q=256, preds=None if args.preds == "five" else ALL_PREDS)
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
         m = farm.Memory(t(sc.desc), t(sc.center), t(sc.extent), t(sc.ids.view(np.int32)), t(sc.cls), sc.view_right)
         w = farm.Workspace(m, qt.q, qt.r_tot, 16)

@@ -44,23 +44,23 @@ def _load():
         P = ctypes.c_void_p
         i64, i32 = ctypes.c_int64, ctypes.c_int32
         lib.farm_oracle_predicate.restype = ctypes.c_double
-        lib.farm_oracle_predicate.argtypes = [ctypes.c_int, P, P, P]
+        lib.farm_oracle_predicate.argtypes = [ctypes.c_int, P, P, P, P, P]
         lib.farm_oracle_score.restype = ctypes.c_int
-        lib.farm_oracle_score.argtypes = [i64, ctypes.c_int, P, P, P, P, P, i32, P, P, P, P, P, P, P, P, P]
+        lib.farm_oracle_score.argtypes = [i64, ctypes.c_int, P, P, P, P, P, P, i32, P, P, P, P, P, P, P, P, P]
         lib.farm_oracle_score_pairs.restype = ctypes.c_int
-        lib.farm_oracle_score_pairs.argtypes = [i64, ctypes.c_int, P, P, P, P, P, i32, P, P, P, P, P,
+        lib.farm_oracle_score_pairs.argtypes = [i64, ctypes.c_int, P, P, P, P, P, P, i32, P, P, P, P, P,
                                                 i64, P, P, P, P, P, P]
         lib.farm_oracle_topk.restype = ctypes.c_int
         lib.farm_oracle_topk.argtypes = [i64, P, P, i32, P]
         lib.farm_oracle_binding_value.restype = ctypes.c_double
-        lib.farm_oracle_binding_value.argtypes = [i64, ctypes.c_int, P, P, P, ctypes.c_int, P, i64, i64]
+        lib.farm_oracle_binding_value.argtypes = [i64, ctypes.c_int, P, P, P, P, ctypes.c_int, P, i64, i64]
         lib.farm_oracle_pair_features.restype = None
         lib.farm_oracle_pair_features.argtypes = [P, P, P, i64, i64, P]
         lib.farm_oracle_mlp.restype = ctypes.c_int
         lib.farm_oracle_mlp.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, i64, P, P, P, P,
                                         P, P, P, P, P, P, P]
         lib.farm_oracle_topk_bounded.restype = ctypes.c_int
-        lib.farm_oracle_topk_bounded.argtypes = [i64, ctypes.c_int, P, P, P, P, P, i32, P, P, P, P, P,
+        lib.farm_oracle_topk_bounded.argtypes = [i64, ctypes.c_int, P, P, P, P, P, P, i32, P, P, P, P, P,
                                                  i32, P, P, P, P, P]
         _lib = lib
     return _lib
@@ -79,26 +79,30 @@ def set_threads(n: int | None):
         os.environ["OMP_NUM_THREADS"] = str(int(n))
 
 
-def predicate(p: int, ci, cj, right) -> float:
-    """P_p(i, j) in FP64 for float32 centers and viewer right vector."""
+def predicate(p: int, ci, cj, right, ei=(0.0, 0.0, 0.0), ej=(0.0, 0.0, 0.0)) -> float:
+    """P_p(i, j) in FP64 for float32 centers, full extents (used by On only) and
+    viewer right vector."""
     lib = _load()
     a, pa = _c(ci, np.float32)
     b, pb = _c(cj, np.float32)
+    ea, pea = _c(ei, np.float32)
+    eb, peb = _c(ej, np.float32)
     r, pr = _c(right, np.float32)
-    return float(lib.farm_oracle_predicate(int(p), pa, pb, pr))
+    return float(lib.farm_oracle_predicate(int(p), pa, pb, pea, peb, pr))
 
 
 def _scene_args(scene):
     desc, pd = _c(scene.desc, np.float32)
     cen, pc = _c(scene.center, np.float32)
+    ext, pe = _c(scene.extent, np.float32)
     ids, pi = _c(scene.ids, np.uint32)
     if scene.cls is None:
         cls, pk = None, None
     else:
         cls, pk = _c(scene.cls, np.int32)
     vr, pv = _c(scene.view_right, np.float32)
-    keep = (desc, cen, ids, cls, vr)
-    return keep, [int(desc.shape[0]), int(desc.shape[1]), pd, pc, pi, pk, pv]
+    keep = (desc, cen, ext, ids, cls, vr)
+    return keep, [int(desc.shape[0]), int(desc.shape[1]), pd, pc, pe, pi, pk, pv]
 
 
 def _query_args(qb):
@@ -191,13 +195,15 @@ def binding_value(scene, pred: int, anchor_vec, i: int, j: int) -> float:
     lib = _load()
     desc, pd = _c(scene.desc, np.float32)
     cen, pc = _c(scene.center, np.float32)
+    ext, pe = _c(scene.extent, np.float32)
     vr, pv = _c(scene.view_right, np.float32)
     av, pa = _c(anchor_vec, np.float32)
-    return float(lib.farm_oracle_binding_value(int(desc.shape[0]), int(desc.shape[1]), pd, pc, pv, int(pred), pa,
-                                               int(i), int(j)))
+    return float(lib.farm_oracle_binding_value(int(desc.shape[0]), int(desc.shape[1]), pd, pc, pe, pv, int(pred),
+                                               pa, int(i), int(j)))
 
 
-NPRED = 8
+NUM_PRED = 9   # predicates the scorer evaluates (ids 0..8, On = 8)
+NPRED = 8      # proposal-network outputs (predicates 0..7)
 NGEO = 12
 
 

@@ -37,9 +37,17 @@ def _sigmoid(x):
     return 1.0 / (1.0 + math.exp(-x))
 
 
-def soft_relation(pred, ci, cj, right):
-    """The eight closed-form soft predicates, written from their definitions."""
+def soft_relation(pred, ci, cj, right, ei=(0.0, 0.0, 0.0), ej=(0.0, 0.0, 0.0)):
+    """The nine closed-form soft predicates, written from their definitions
+    (ei, ej: full box extents of target and anchor, used by On only)."""
     dx, dy, dz = (float(ci[0]) - float(cj[0]), float(ci[1]) - float(cj[1]), float(ci[2]) - float(cj[2]))
+    if pred == 8:  # on: gate on the horizontal distance (sigma 0.4 m) times a band on the
+        # gap between the target's bottom face and the anchor's top face (sigma 0.1 m)
+        bottom_i = float(ci[2]) - float(ei[2]) / 2.0
+        top_j = float(cj[2]) + float(ej[2]) / 2.0
+        gate = math.exp(-(dx * dx + dy * dy) / (2 * 0.4 * 0.4))
+        band = math.exp(-((bottom_i - top_j) ** 2) / (2 * 0.1 * 0.1))
+        return gate * band
     if pred == 0:  # near: Gaussian on centroid distance, sigma 0.5 m
         return math.exp(-(dx * dx + dy * dy + dz * dz) / (2 * 0.25))
     if pred == 5:  # next to: the same Gaussian with sigma 1 m
@@ -89,7 +97,8 @@ def brute_scores(scene, qb):
             for binding in itertools.product(others, repeat=len(rels)):
                 prod = 1.0
                 for (pred, qr), j in zip(rels, binding):
-                    prod *= _sim(units[j], qr) * soft_relation(pred, scene.center[e], scene.center[j], scene.view_right)
+                    prod *= _sim(units[j], qr) * soft_relation(pred, scene.center[e], scene.center[j], scene.view_right,
+                                                               scene.extent[e], scene.extent[j])
                 v = s_sem * ((1 - W) + W * prod ** (1.0 / len(rels)))
                 if best is None or v > best:
                     best = v

@@ -30,9 +30,15 @@
  *   NEAR     = exp(-|D|^2 / (2 * 0.5^2))          (Gaussian, sigma = 0.5 m)
  *   ABOVE    = sig(D_z / 0.1),  BELOW = sig(-D_z / 0.1)
  *   RIGHT_OF = sig((D_x r_x + D_y r_y) / 0.1),  LEFT_OF = sig(-(...) / 0.1)
- * where (r_x, r_y) is the scene viewer's right vector.  The temperatures
- * (0.1 m), the Gaussian's normalisation, the clamp at zero and the viewer
- * convention are readings where the paper is silent.
+ *   NEXT_TO  = exp(-|D|^2 / (2 * 1.0^2))
+ *   IN_FRONT_OF = sig(-(D_x f_x + D_y f_y) / 0.1),  BEHIND = sig(+(...) / 0.1)
+ *   ON       = exp(-(D_x^2 + D_y^2) / (2 * 0.4^2)) * exp(-g^2 / (2 * 0.1^2)),
+ *              g = (c_i,z - e_i,z / 2) - (c_j,z + e_j,z / 2)
+ * where (r_x, r_y) is the scene viewer's right vector, f = (-r_y, r_x) its
+ * viewing direction and e the full box extents.  The temperatures
+ * (0.1 m), the Gaussian's normalisation, the clamp at zero, the viewer
+ * convention and On's Gaussian gate and band with their widths are readings
+ * where the paper is silent.
  *
  * Everything is computed in double precision from the float inputs, with plain
  * loops in the order of the definition.  OpenMP parallelises only the
@@ -49,22 +55,28 @@
 #define ORACLE_NEAR_SIGMA 0.5
 #define ORACLE_NEXT_TO_SIGMA 1.0
 #define ORACLE_TAU 0.1
+#define ORACLE_ON_SIGMA_H 0.4
+#define ORACLE_ON_SIGMA_V 0.1
 #define ORACLE_MAX_REL 8
 #define ORACLE_NO_ID 0xFFFFFFFFu
 
 enum { P_NEAR = 0, P_ABOVE = 1, P_BELOW = 2, P_LEFT_OF = 3, P_RIGHT_OF = 4, P_NEXT_TO = 5, P_IN_FRONT_OF = 6,
-       P_BEHIND = 7, P_COUNT = 8 };
+       P_BEHIND = 7, P_ON = 8, P_COUNT = 9 };
 
 static double logistic(double u) { return 1.0 / (1.0 + exp(-u)); }
 
-/* Soft predicate P_p(i, j) for target center ci and anchor center cj
- * (Appendix "Retrieval Details", closed-form evaluators): Near and NextTo are
- * Gaussians of the centroid distance (sigma 0.5 m and 1.0 m); Above/Below a
- * logistic of the vertical offset; LeftOf/RightOf a logistic of the offset
- * along the viewer's right axis r, InFrontOf/Behind of the offset along its
- * viewing direction f = (-r_y, r_x) (in front = nearer the viewer), one viewer
- * frame per scene standing in for the stored camera views; temperature 0.1 m. */
-double oracle_predicate(int p, const double* ci, const double* cj, const double* right) {
+/* Soft predicate P_p(i, j) for target center ci and anchor center cj, full
+ * box extents ei and ej (Appendix "Retrieval Details", closed-form
+ * evaluators): Near and NextTo are Gaussians of the centroid distance (sigma
+ * 0.5 m and 1.0 m); Above/Below a logistic of the vertical offset;
+ * LeftOf/RightOf a logistic of the offset along the viewer's right axis r,
+ * InFrontOf/Behind of the offset along its viewing direction f = (-r_y, r_x)
+ * (in front = nearer the viewer), one viewer frame per scene standing in for
+ * the stored camera views; temperature 0.1 m.  On is a gate on the horizontal
+ * center distance times a band on the vertical gap between the target's bottom
+ * face and the anchor's top face, both Gaussians (sigma 0.4 m and 0.1 m). */
+double oracle_predicate(int p, const double* ci, const double* cj, const double* ei, const double* ej,
+                        const double* right) {
     double dx = ci[0] - cj[0], dy = ci[1] - cj[1], dz = ci[2] - cj[2];
     double depth = dx * -right[1] + dy * right[0];  /* offset along f */
     switch (p) {
@@ -82,14 +94,23 @@ double oracle_predicate(int p, const double* ci, const double* cj, const double*
     case P_LEFT_OF: return logistic(-(dx * right[0] + dy * right[1]) / ORACLE_TAU);
     case P_IN_FRONT_OF: return logistic(-depth / ORACLE_TAU);
     case P_BEHIND: return logistic(depth / ORACLE_TAU);
+    case P_ON: {
+        double h2 = dx * dx + dy * dy;
+        double gap = (ci[2] - 0.5 * ei[2]) - (cj[2] + 0.5 * ej[2]);  /* bottom of i minus top of j */
+        double gate = exp(-h2 / (2.0 * ORACLE_ON_SIGMA_H * ORACLE_ON_SIGMA_H));
+        double band = exp(-gap * gap / (2.0 * ORACLE_ON_SIGMA_V * ORACLE_ON_SIGMA_V));
+        return gate * band;
+    }
     default: return NAN;
     }
 }
 
 /* Exported wrapper so tests can pin single predicate values. */
-double farm_oracle_predicate(int p, const float* ci, const float* cj, const float* right) {
+double farm_oracle_predicate(int p, const float* ci, const float* cj, const float* ei, const float* ej,
+                             const float* right) {
     double a[3] = {ci[0], ci[1], ci[2]}, b[3] = {cj[0], cj[1], cj[2]}, r[2] = {right[0], right[1]};
-    return oracle_predicate(p, a, b, r);
+    double ea[3] = {ei[0], ei[1], ei[2]}, eb[3] = {ej[0], ej[1], ej[2]};
+    return oracle_predicate(p, a, b, ea, eb, r);
 }
 
 static void unit_vector(const float* v, int d, double* out) {
@@ -110,21 +131,24 @@ typedef struct {
     int d;
     double* u;        /* [n][d] normalised descriptors */
     double* c;        /* [n][3] centers */
+    double* e;        /* [n][3] full extents */
     const uint32_t* id;
     const int32_t* cls;
     double right[2];
 } scene64;
 
 static int scene_init(scene64* s, int64_t n, int d, const float* desc, const float* center,
-                      const uint32_t* id, const int32_t* cls, const float* right) {
+                      const float* extent, const uint32_t* id, const int32_t* cls, const float* right) {
     s->n = n;
     s->d = d;
     s->u = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * (size_t)d);
     s->c = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * 3);
-    if (!s->u || !s->c) return -2;
+    s->e = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * 3);
+    if (!s->u || !s->c || !s->e) return -2;
     for (int64_t i = 0; i < n; ++i) {
         unit_vector(desc + (size_t)i * d, d, s->u + (size_t)i * d);
         for (int k = 0; k < 3; ++k) s->c[i * 3 + k] = center[i * 3 + k];
+        for (int k = 0; k < 3; ++k) s->e[i * 3 + k] = extent[i * 3 + k];
     }
     s->id = id;
     s->cls = cls;
@@ -136,6 +160,7 @@ static int scene_init(scene64* s, int64_t n, int d, const float* desc, const flo
 static void scene_free(scene64* s) {
     free(s->u);
     free(s->c);
+    free(s->e);
 }
 
 /* Per-query state: normalised target, anchor similarities per relation. */
@@ -181,7 +206,8 @@ static void relation_term(const scene64* s, const query64* qs, int rr, int64_t i
     const double* a = qs->asim + (size_t)rr * s->n;
     for (int64_t j = 0; j < s->n; ++j) {
         if (j == i) continue;
-        double v = a[j] * oracle_predicate(qs->pred[rr], s->c + i * 3, s->c + j * 3, s->right);
+        double v = a[j] * oracle_predicate(qs->pred[rr], s->c + i * 3, s->c + j * 3, s->e + i * 3, s->e + j * 3,
+                                            s->right);
         if (v > best || (v == best && s->id[j] < best_id)) {
             best = v;
             best_id = s->id[j];
@@ -221,14 +247,14 @@ static int check_query_meta(int32_t q, const int32_t* rel_off, const int32_t* re
  *   rel_anchor_id[r_tot][n] b_r (may be NULL)
  * Returns 0, -1 on invalid metadata, -2 on allocation failure.
  */
-int farm_oracle_score(int64_t n, int d, const float* desc, const float* center, const uint32_t* id,
-                      const int32_t* cls, const float* right, int32_t q, const float* target,
+int farm_oracle_score(int64_t n, int d, const float* desc, const float* center, const float* extent,
+                      const uint32_t* id, const int32_t* cls, const float* right, int32_t q, const float* target,
                       const int32_t* target_cls, const int32_t* rel_off, const int32_t* rel_pred,
                       const float* rel_anchor, double* scores, double* sem, double* rel_terms,
                       uint32_t* rel_anchor_id) {
     if (check_query_meta(q, rel_off, rel_pred)) return -1;
     scene64 s;
-    if (scene_init(&s, n, d, desc, center, id, cls, right)) { scene_free(&s); return -2; }
+    if (scene_init(&s, n, d, desc, center, extent, id, cls, right)) { scene_free(&s); return -2; }
     int err = 0;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int32_t k = 0; k < q; ++k) {
@@ -264,8 +290,8 @@ int farm_oracle_score(int64_t n, int d, const float* desc, const float* center, 
  * (qsel[m], osel[m]); each costs O(R * N) after the query's similarities.
  * rel_terms/rel_anchor_id, when not NULL, are [m][8] (unused slots = 0 / NO_ID).
  */
-int farm_oracle_score_pairs(int64_t n, int d, const float* desc, const float* center, const uint32_t* id,
-                            const int32_t* cls, const float* right, int32_t q, const float* target,
+int farm_oracle_score_pairs(int64_t n, int d, const float* desc, const float* center, const float* extent,
+                            const uint32_t* id, const int32_t* cls, const float* right, int32_t q, const float* target,
                             const int32_t* target_cls, const int32_t* rel_off, const int32_t* rel_pred,
                             const float* rel_anchor, int64_t m, const int32_t* qsel, const int64_t* osel,
                             double* out, double* out_sem, double* rel_terms, uint32_t* rel_anchor_id) {
@@ -273,7 +299,7 @@ int farm_oracle_score_pairs(int64_t n, int d, const float* desc, const float* ce
     for (int64_t p = 0; p < m; ++p)
         if (qsel[p] < 0 || qsel[p] >= q || osel[p] < 0 || osel[p] >= n) return -1;
     scene64 s;
-    if (scene_init(&s, n, d, desc, center, id, cls, right)) { scene_free(&s); return -2; }
+    if (scene_init(&s, n, d, desc, center, extent, id, cls, right)) { scene_free(&s); return -2; }
     int err = 0;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int32_t k = 0; k < q; ++k) {
@@ -346,14 +372,14 @@ int farm_oracle_topk(int64_t n, const double* scores, const uint32_t* id, int32_
  *   out_idx[q][k] object indices (-1 padding), out_score[q][k],
  *   n_scored[q]   how many objects were scored exactly (may be NULL).
  */
-int farm_oracle_topk_bounded(int64_t n, int d, const float* desc, const float* center, const uint32_t* id,
-                             const int32_t* cls, const float* right, int32_t q, const float* target,
+int farm_oracle_topk_bounded(int64_t n, int d, const float* desc, const float* center, const float* extent,
+                             const uint32_t* id, const int32_t* cls, const float* right, int32_t q, const float* target,
                              const int32_t* target_cls, const int32_t* rel_off, const int32_t* rel_pred,
                              const float* rel_anchor, int32_t k, int64_t* out_idx, double* out_score,
                              double* out_terms, uint32_t* out_anchor_id, int64_t* n_scored) {
     if (check_query_meta(q, rel_off, rel_pred) || k < 1) return -1;
     scene64 s;
-    if (scene_init(&s, n, d, desc, center, id, cls, right)) { scene_free(&s); return -2; }
+    if (scene_init(&s, n, d, desc, center, extent, id, cls, right)) { scene_free(&s); return -2; }
     int err = 0;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int32_t qq = 0; qq < q; ++qq) {
@@ -422,7 +448,8 @@ int farm_oracle_topk_bounded(int64_t n, int d, const float* desc, const float* c
  * Value of one binding: sim(j, q_r) * P_p(i, j) in FP64 -- used to check that
  * an anchor chosen by another implementation attains the relation term.
  */
-double farm_oracle_binding_value(int64_t n, int d, const float* desc, const float* center, const float* right,
+double farm_oracle_binding_value(int64_t n, int d, const float* desc, const float* center, const float* extent,
+                                 const float* right,
                                  int p, const float* anchor, int64_t i, int64_t j) {
     if (i < 0 || j < 0 || i >= n || j >= n || p < 0 || p >= P_COUNT) return NAN;
     double* u = (double*)malloc(sizeof(double) * (size_t)d);
@@ -433,8 +460,10 @@ double farm_oracle_binding_value(int64_t n, int d, const float* desc, const floa
     double a = clamped_cosine(u, v, d);
     double ci[3] = {center[i * 3], center[i * 3 + 1], center[i * 3 + 2]};
     double cj[3] = {center[j * 3], center[j * 3 + 1], center[j * 3 + 2]};
+    double ei[3] = {extent[i * 3], extent[i * 3 + 1], extent[i * 3 + 2]};
+    double ej[3] = {extent[j * 3], extent[j * 3 + 1], extent[j * 3 + 2]};
     double r[2] = {right[0], right[1]};
-    double val = a * oracle_predicate(p, ci, cj, r);
+    double val = a * oracle_predicate(p, ci, cj, ei, ej, r);
     free(u);
     free(v);
     return val;

@@ -26,10 +26,10 @@ import numpy as np
 
 # Predicate ids, in the order the C ABI uses.
 NEAR, ABOVE, BELOW, LEFT_OF, RIGHT_OF = 0, 1, 2, 3, 4
-NEXT_TO, IN_FRONT_OF, BEHIND = 5, 6, 7
-ALL_PREDS = tuple(range(8))
-PRED_NAMES = ("near", "above", "below", "left_of", "right_of")
-NUM_PRED = 5
+NEXT_TO, IN_FRONT_OF, BEHIND, ON = 5, 6, 7, 8
+ALL_PREDS = tuple(range(9))
+DEFAULT_PREDS = (NEAR, ABOVE, BELOW, LEFT_OF, RIGHT_OF)  # the pool query batches draw from by default
+PRED_NAMES = ("near", "above", "below", "left_of", "right_of", "next_to", "in_front_of", "behind", "on")
 
 
 @dataclasses.dataclass
@@ -186,6 +186,11 @@ def _plant_anchor(rng, scene: Scene, o: int, pred: int, c64: np.ndarray, r64: np
     dist[o] = np.inf
     if pred in (NEAR, NEXT_TO):
         ok = np.isfinite(dist)
+    elif pred == ON:
+        # the horizontally nearest object whose center lies at least 0.3 m lower
+        ok = -d[:, 2] > 0.3
+        dist = np.sqrt(d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1])
+        dist[o] = np.inf
     elif pred in (ABOVE, BELOW):
         # Target above the anchor: anchor lies at least 0.3 m lower.
         side = -d[:, 2] if pred == ABOVE else d[:, 2]
@@ -215,9 +220,9 @@ def make_queries(cfg: Config, scene: Scene, seed: int | None = None, q: int | No
     centroid as the target embedding, and draws R relations; each relation has
     a uniformly drawn predicate and the anchor embedding of a noisy centroid of
     a geometrically suitable anchor object's category.  ``preds`` lists the
-    predicate ids to draw from (default: the first five, Near..RightOf).
+    predicate ids to draw from (default: ``DEFAULT_PREDS``, Near..RightOf).
     """
-    pool = tuple(range(NUM_PRED)) if preds is None else tuple(int(p) for p in preds)
+    pool = DEFAULT_PREDS if preds is None else tuple(int(p) for p in preds)
     seed = cfg.seed if seed is None else seed
     q = cfg.q if q is None else q
     r_min = cfg.r_min if r_min is None else r_min

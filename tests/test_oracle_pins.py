@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 from oracle.brute import brute_scores
-from synth import (ABOVE, ALL_PREDS, BEHIND, BELOW, IN_FRONT_OF, LEFT_OF, NEAR, NEXT_TO, RIGHT_OF, CONFIGS,
+from synth import (ABOVE, ALL_PREDS, BEHIND, BELOW, IN_FRONT_OF, LEFT_OF, NEAR, NEXT_TO, ON, RIGHT_OF, CONFIGS,
                    QueryBatch, Scene, make_queries, make_scene)
 from tests import _golden
 
@@ -124,6 +124,52 @@ def test_front_behind_duality_and_viewer():
     assert oracle.predicate(BEHIND, [-LN3_TENTH, 0, 0], [0, 0, 0], r) == pytest.approx(0.25, abs=2e-8)
 
 
+
+def test_on_closed_form_gate_and_band():
+    """On: a gate on the horizontal center distance (sigma 0.4 m) times a band
+    on the gap between the target's bottom face and the anchor's top face
+    (sigma 0.1 m).  Inputs are exact in FP32, so the values are exact."""
+    r = [1.0, 0.0]
+    cup, table = [0.3, 0.3, 0.5], [2.0, 2.0, 1.0]   # full extents
+    # a cup resting centred on a table: bottom 1.25 - 0.25 = 1.0 = top 0.5 + 0.5
+    assert oracle.predicate(ON, [0, 0, 1.25], [0, 0, 0.5], r, cup, table) == 1.0
+    # 0.5 m off centre: exp(-0.25 / (2 * 0.16))
+    assert oracle.predicate(ON, [0.5, 0, 1.25], [0, 0, 0.5], r, cup, table) == pytest.approx(
+        math.exp(-0.78125), rel=1e-15)
+    # hovering 0.25 m above or sunk 0.25 m into the table: exp(-0.0625 / (2 * 0.01))
+    for zc in (1.5, 1.0):
+        assert oracle.predicate(ON, [0, 0, zc], [0, 0, 0.5], r, cup, table) == pytest.approx(
+            math.exp(-3.125), rel=1e-14)
+    # both at once multiply
+    assert oracle.predicate(ON, [0, 0.5, 1.5], [0, 0, 0.5], r, cup, table) == pytest.approx(
+        math.exp(-0.78125 - 3.125), rel=1e-14)
+    # roles swapped (the table "on" the cup): the table's bottom 0 is 1.5 m below the cup's top
+    assert oracle.predicate(ON, [0, 0, 0.5], [0, 0, 1.25], r, table, cup) == pytest.approx(
+        math.exp(-1.5 ** 2 / 0.02), rel=1e-12)
+    # a taller cup raises its own center, not the contact: same value when the center moves with it
+    assert oracle.predicate(ON, [0, 0, 1.5], [0, 0, 0.5], r, [0.3, 0.3, 1.0], table) == 1.0
+    rng = np.random.default_rng(8)
+    for _ in range(40):
+        a, b = rng.uniform(-3, 3, 3).astype(np.float32), rng.uniform(-3, 3, 3).astype(np.float32)
+        ea, eb = rng.uniform(0.1, 2, 3).astype(np.float32), rng.uniform(0.1, 2, 3).astype(np.float32)
+        v = oracle.predicate(ON, a, b, r, ea, eb)
+        assert 0.0 <= v <= 1.0
+        # neither the viewer nor the horizontal extents play a part
+        yaw = rng.uniform(0, 2 * math.pi)
+        r2 = np.array([math.sin(yaw), -math.cos(yaw)], np.float32)
+        ea2, eb2 = ea.copy(), eb.copy()
+        ea2[:2] *= 3
+        eb2[:2] /= 2
+        assert oracle.predicate(ON, a, b, r2, ea2, eb2) == v
+        # gate: the horizontal part is Near's Gaussian at sigma 0.4 = 0.8 * 0.5 on a flattened pair
+        # (scaling by 1.25 is not exact in FP32, hence the tolerance)
+        fa, fb = np.array([a[0], a[1], 0], np.float32), np.array([b[0], b[1], 0], np.float32)
+        gate = oracle.predicate(NEAR, fa * np.float32(1.25), fb * np.float32(1.25), r)
+        # band: with the horizontal offset removed only the band remains
+        band = oracle.predicate(ON, np.array([b[0], b[1], a[2]], np.float32), b, r, ea, eb)
+        assert v == pytest.approx(gate * band, rel=1e-5, abs=1e-300)
+
+
 # ---------------------------------------------------------------- hand scenes
 @pytest.mark.parametrize("path", _golden.all_paths(), ids=lambda p: p.rsplit("/", 1)[-1])
 def test_golden_scenes(path):
@@ -159,8 +205,11 @@ def _tiny(seed, n, r, q=3, d=6, n_cat=3, npred=5):
     cent /= np.linalg.norm(cent, axis=1, keepdims=True)
     cls = rng.integers(0, n_cat, n).astype(np.int32)
     desc = cent[cls] + 0.4 * rng.standard_normal((n, d))
+    # extents from a stream of their own (the other draws keep their values); they
+    # matter to On only
+    ext = np.random.default_rng(seed + 1000).uniform(0.2, 1.5, (n, 3)).astype(np.float32)
     scene = Scene(desc=desc.astype(np.float32), center=rng.uniform(0, 2, (n, 3)).astype(np.float32),
-                  extent=np.ones((n, 3), np.float32), ids=rng.permutation(100)[:n].astype(np.uint32) + 1,
+                  extent=ext, ids=rng.permutation(100)[:n].astype(np.uint32) + 1,
                   cls=cls, view_right=np.array([math.cos(seed), math.sin(seed)], np.float32),
                   centroids=cent.astype(np.float32))
     offs = [0]

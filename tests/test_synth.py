@@ -121,7 +121,7 @@ def test_query_statistics_match_config(name):
     counts = np.diff(qb.rel_off)
     assert qb.rel_off[0] == 0 and qb.rel_off[-1] == qb.r_tot
     assert counts.min() >= cfg.r_min and counts.max() <= cfg.r_max
-    assert set(np.unique(qb.rel_pred)) <= set(range(synth.NUM_PRED))
+    assert set(np.unique(qb.rel_pred)) <= set(synth.DEFAULT_PREDS)
     np.testing.assert_allclose(np.linalg.norm(qb.target, axis=1), 1.0, atol=1e-5)
     np.testing.assert_allclose(np.linalg.norm(qb.rel_anchor, axis=1), 1.0, atol=1e-5)
     # the target class is the planted object's category
@@ -131,7 +131,7 @@ def test_query_statistics_match_config(name):
 
 
 def test_predicate_pool_and_planting_rule():
-    """With the full pool all eight predicates appear, and every planted
+    """With the full pool all nine predicates appear, and every planted
     anchor category belongs to an object that lies on the named side of the
     target (so the query describes something true of the scene)."""
     cfg = synth.MID
@@ -148,6 +148,8 @@ def test_predicate_pool_and_planting_rule():
             d = c - c[o]
             if p in (synth.NEAR, synth.NEXT_TO):
                 ok = np.ones(s.n, bool)
+            elif p == synth.ON:
+                ok = -d[:, 2] > 0.3
             elif p == synth.ABOVE:
                 ok = -d[:, 2] > 0.3
             elif p == synth.BELOW:
