@@ -203,7 +203,7 @@ def binding_value(scene, pred: int, anchor_vec, i: int, j: int) -> float:
 
 
 NUM_PRED = 9   # predicates the scorer evaluates (ids 0..8, On = 8)
-NPRED = 8      # proposal-network outputs (predicates 0..7)
+NPRED = 9      # proposal-network outputs, one per predicate
 NGEO = 12
 
 
@@ -219,12 +219,16 @@ def pair_features(scene, o: int, a: int):
 
 
 def mlp(weights: dict, X, pred, label, grads: bool = True):
-    """Loss (mean BCE-with-logits on the labelled predicate), logits [n,5] and,
+    """Loss (mean BCE-with-logits on the labelled predicate), logits [n,9] and,
     with ``grads``, the FP64 gradients {name: array} of the proposal network.
-    weights: W1 [h,in], b1 [h], W2 [h,h], b2 [h], W3 [8,h], b3 [8]."""
+    weights: W1 [h,in], b1 [h], W2 [h,h], b2 [h], W3 [9,h], b3 [9]."""
     lib = _load()
     W = {k: np.ascontiguousarray(v, np.float64) for k, v in weights.items()}
     h, inp = W["W1"].shape
+    want = {"W1": (h, inp), "b1": (h,), "W2": (h, h), "b2": (h,), "W3": (NPRED, h), "b3": (NPRED,)}
+    for k, shape in want.items():
+        if W[k].shape != shape:
+            raise ValueError(f"oracle mlp: {k} has shape {W[k].shape}, expected {shape}")
     Xa, px = _c(X, np.float64)
     pa, pp = _c(pred, np.int32)
     la, pl = _c(label, np.float64)

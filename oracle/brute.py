@@ -41,12 +41,12 @@ def soft_relation(pred, ci, cj, right, ei=(0.0, 0.0, 0.0), ej=(0.0, 0.0, 0.0)):
     """The nine closed-form soft predicates, written from their definitions
     (ei, ej: full box extents of target and anchor, used by On only)."""
     dx, dy, dz = (float(ci[0]) - float(cj[0]), float(ci[1]) - float(cj[1]), float(ci[2]) - float(cj[2]))
-    if pred == 8:  # on: gate on the horizontal distance (sigma 0.4 m) times a band on the
-        # gap between the target's bottom face and the anchor's top face (sigma 0.1 m)
+    if pred == 8:  # on: gate on the horizontal distance (sigma 0.5 m) times a band on the
+        # gap between the target's bottom face and the anchor's top face (sigma 0.125 m)
         bottom_i = float(ci[2]) - float(ei[2]) / 2.0
         top_j = float(cj[2]) + float(ej[2]) / 2.0
-        gate = math.exp(-(dx * dx + dy * dy) / (2 * 0.4 * 0.4))
-        band = math.exp(-((bottom_i - top_j) ** 2) / (2 * 0.1 * 0.1))
+        gate = math.exp(-(dx * dx + dy * dy) / (2 * 0.5 * 0.5))
+        band = math.exp(-((bottom_i - top_j) ** 2) / (2 * 0.125 * 0.125))
         return gate * band
     if pred == 0:  # near: Gaussian on centroid distance, sigma 0.5 m
         return math.exp(-(dx * dx + dy * dy + dz * dz) / (2 * 0.25))

@@ -32,7 +32,7 @@
  *   RIGHT_OF = sig((D_x r_x + D_y r_y) / 0.1),  LEFT_OF = sig(-(...) / 0.1)
  *   NEXT_TO  = exp(-|D|^2 / (2 * 1.0^2))
  *   IN_FRONT_OF = sig(-(D_x f_x + D_y f_y) / 0.1),  BEHIND = sig(+(...) / 0.1)
- *   ON       = exp(-(D_x^2 + D_y^2) / (2 * 0.4^2)) * exp(-g^2 / (2 * 0.1^2)),
+ *   ON       = exp(-(D_x^2 + D_y^2) / (2 * 0.5^2)) * exp(-g^2 / (2 * 0.125^2)),
  *              g = (c_i,z - e_i,z / 2) - (c_j,z + e_j,z / 2)
  * where (r_x, r_y) is the scene viewer's right vector, f = (-r_y, r_x) its
  * viewing direction and e the full box extents.  The temperatures
@@ -55,8 +55,8 @@
 #define ORACLE_NEAR_SIGMA 0.5
 #define ORACLE_NEXT_TO_SIGMA 1.0
 #define ORACLE_TAU 0.1
-#define ORACLE_ON_SIGMA_H 0.4
-#define ORACLE_ON_SIGMA_V 0.1
+#define ORACLE_ON_SIGMA_H 0.5
+#define ORACLE_ON_SIGMA_V 0.125
 #define ORACLE_MAX_REL 8
 #define ORACLE_NO_ID 0xFFFFFFFFu
 
@@ -74,7 +74,7 @@ static double logistic(double u) { return 1.0 / (1.0 + exp(-u)); }
  * (in front = nearer the viewer), one viewer frame per scene standing in for
  * the stored camera views; temperature 0.1 m.  On is a gate on the horizontal
  * center distance times a band on the vertical gap between the target's bottom
- * face and the anchor's top face, both Gaussians (sigma 0.4 m and 0.1 m). */
+ * face and the anchor's top face, both Gaussians (sigma 0.5 m and 0.125 m). */
 double oracle_predicate(int p, const double* ci, const double* cj, const double* ei, const double* ej,
                         const double* right) {
     double dx = ci[0] - cj[0], dy = ci[1] - cj[1], dz = ci[2] - cj[2];
@@ -476,16 +476,16 @@ double farm_oracle_binding_value(int64_t n, int d, const float* desc, const floa
  * ranks (target, anchor) pairs per predicate.
  *
  *   x  = [u_o ; u_a ; g(o, a)]                (2d + 12 inputs)
- *   h1 = GELU(W1 x + b1),  h2 = GELU(W2 h1 + b2),  y = W3 h2 + b3   (8 logits)
+ *   h1 = GELU(W1 x + b1),  h2 = GELU(W2 h1 + b2),  y = W3 h2 + b3   (9 logits)
  *   GELU(v) = v/2 (1 + erf(v / sqrt 2))
  *   loss = mean_s BCEwithLogits(y_s[p_s], label_s)
  *        = mean_s [ max(y,0) - y*label + log(1 + exp(-|y|)) ]
  *
  * g(o, a) = [c_o - c_a (3), e_o (3), e_a (3), |c_o - c_a|, (c_o - c_a).r,
  *            (z_o - e_o,z/2) - (z_a + e_a,z/2)]   (bottom of o minus top of a)
- * Weights are row-major: W1 [h][in], W2 [h][h], W3 [8][h] (one output per predicate).
+ * Weights are row-major: W1 [h][in], W2 [h][h], W3 [9][h] (one output per predicate).
  * ------------------------------------------------------------------------ */
-#define ORACLE_NPRED 8
+#define ORACLE_NPRED 9
 #define ORACLE_NGEO 12
 
 static double gelu(double v) { return 0.5 * v * (1.0 + erf(v / sqrt(2.0))); }
@@ -508,7 +508,7 @@ void farm_oracle_pair_features(const float* center, const float* extent, const f
 
 /*
  * Loss and gradients over nsamp samples with inputs X [nsamp][in], predicate
- * p_s and binary label_s.  Gradient outputs may be NULL; logits [nsamp][8]
+ * p_s and binary label_s.  Gradient outputs may be NULL; logits [nsamp][9]
  * may be NULL.  Plain backpropagation, one sample at a time.
  */
 int farm_oracle_mlp(int in, int h, const double* W1, const double* b1, const double* W2, const double* b2,

@@ -22,14 +22,14 @@ def test_zero_network_closed_forms():
     """All weights zero: y = b3, so the loss is the BCE of a constant logit."""
     inp, h = 7, 4
     W = {k: np.zeros_like(v) for k, v in _weights(np.random.default_rng(0), inp, h).items()}
-    W["b3"] = np.array([0.0, 1.0, -2.0, 0.5, 3.0, -1.0, 0.25, 2.0])
+    W["b3"] = np.array([0.0, 1.0, -2.0, 0.5, 3.0, -1.0, 0.25, 2.0, -0.5])
     X = np.ones((6, inp))
-    pred = np.array([0, 1, 2, 4, 5, 7], np.int32)
+    pred = np.array([0, 1, 2, 4, 5, 8], np.int32)
     lab = np.array([1.0, 0.0, 1.0, 1.0, 0.0, 1.0])
     loss, logits, g = oracle.mlp(W, X, pred, lab)
     sp = lambda v: math.log1p(math.exp(v))  # softplus
     # BCE(y, t) = softplus(y) - t y
-    want = (math.log(2.0) + sp(1.0) + sp(2.0) + sp(-3.0) + sp(-1.0) + sp(-2.0)) / 6.0
+    want = (math.log(2.0) + sp(1.0) + sp(2.0) + sp(-3.0) + sp(-1.0) + sp(0.5)) / 6.0
     assert loss == pytest.approx(want, rel=1e-14)
     np.testing.assert_array_equal(logits, np.tile(W["b3"], (6, 1)))
     # d loss / d b3[p] = mean over samples with that predicate of sigmoid(y) - label
@@ -37,7 +37,8 @@ def test_zero_network_closed_forms():
     assert g["b3"][0] == pytest.approx((sig(0.0) - 1) / 6)
     assert g["b3"][1] == pytest.approx(sig(1.0) / 6)
     assert g["b3"][5] == pytest.approx(sig(-1.0) / 6)
-    assert g["b3"][3] == 0.0 and g["b3"][6] == 0.0
+    assert g["b3"][8] == pytest.approx((sig(-0.5) - 1) / 6)
+    assert g["b3"][3] == 0.0 and g["b3"][6] == 0.0 and g["b3"][7] == 0.0
 
 
 def test_gelu_values_through_a_one_unit_network():

@@ -126,26 +126,26 @@ def test_front_behind_duality_and_viewer():
 
 
 def test_on_closed_form_gate_and_band():
-    """On: a gate on the horizontal center distance (sigma 0.4 m) times a band
+    """On: a gate on the horizontal center distance (sigma 0.5 m) times a band
     on the gap between the target's bottom face and the anchor's top face
-    (sigma 0.1 m).  Inputs are exact in FP32, so the values are exact."""
+    (sigma 0.125 m).  Inputs are exact in FP32, so the values are exact."""
     r = [1.0, 0.0]
     cup, table = [0.3, 0.3, 0.5], [2.0, 2.0, 1.0]   # full extents
     # a cup resting centred on a table: bottom 1.25 - 0.25 = 1.0 = top 0.5 + 0.5
     assert oracle.predicate(ON, [0, 0, 1.25], [0, 0, 0.5], r, cup, table) == 1.0
-    # 0.5 m off centre: exp(-0.25 / (2 * 0.16))
+    # 0.5 m off centre: exp(-0.25 / (2 * 0.25))
     assert oracle.predicate(ON, [0.5, 0, 1.25], [0, 0, 0.5], r, cup, table) == pytest.approx(
-        math.exp(-0.78125), rel=1e-15)
-    # hovering 0.25 m above or sunk 0.25 m into the table: exp(-0.0625 / (2 * 0.01))
+        math.exp(-0.5), rel=1e-15)
+    # hovering 0.25 m above or sunk 0.25 m into the table: exp(-0.0625 / (2 * 0.015625))
     for zc in (1.5, 1.0):
         assert oracle.predicate(ON, [0, 0, zc], [0, 0, 0.5], r, cup, table) == pytest.approx(
-            math.exp(-3.125), rel=1e-14)
+            math.exp(-2.0), rel=1e-14)
     # both at once multiply
     assert oracle.predicate(ON, [0, 0.5, 1.5], [0, 0, 0.5], r, cup, table) == pytest.approx(
-        math.exp(-0.78125 - 3.125), rel=1e-14)
+        math.exp(-2.5), rel=1e-14)
     # roles swapped (the table "on" the cup): the table's bottom 0 is 1.5 m below the cup's top
     assert oracle.predicate(ON, [0, 0, 0.5], [0, 0, 1.25], r, table, cup) == pytest.approx(
-        math.exp(-1.5 ** 2 / 0.02), rel=1e-12)
+        math.exp(-72.0), rel=1e-12)
     # a taller cup raises its own center, not the contact: same value when the center moves with it
     assert oracle.predicate(ON, [0, 0, 1.5], [0, 0, 0.5], r, [0.3, 0.3, 1.0], table) == 1.0
     rng = np.random.default_rng(8)
@@ -161,13 +161,12 @@ def test_on_closed_form_gate_and_band():
         ea2[:2] *= 3
         eb2[:2] /= 2
         assert oracle.predicate(ON, a, b, r2, ea2, eb2) == v
-        # gate: the horizontal part is Near's Gaussian at sigma 0.4 = 0.8 * 0.5 on a flattened pair
-        # (scaling by 1.25 is not exact in FP32, hence the tolerance)
+        # gate: the horizontal part is Near's Gaussian (same width) on the pair flattened to the ground
         fa, fb = np.array([a[0], a[1], 0], np.float32), np.array([b[0], b[1], 0], np.float32)
-        gate = oracle.predicate(NEAR, fa * np.float32(1.25), fb * np.float32(1.25), r)
+        gate = oracle.predicate(NEAR, fa, fb, r)
         # band: with the horizontal offset removed only the band remains
         band = oracle.predicate(ON, np.array([b[0], b[1], a[2]], np.float32), b, r, ea, eb)
-        assert v == pytest.approx(gate * band, rel=1e-5, abs=1e-300)
+        assert v == pytest.approx(gate * band, rel=1e-14, abs=1e-300)
 
 
 # ---------------------------------------------------------------- hand scenes
