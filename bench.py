@@ -82,8 +82,8 @@ def parse():
     p.add_argument("--list-m", type=int, default=256, help="anchors per (object, predicate) list")
     p.add_argument("--k", type=int, default=10)
     p.add_argument("--preds", default="five", choices=["five", "all"],
-                   help="predicates the queries draw from: the workload's five (Near..RightOf) or all eight "
-                        "(+ NextTo, InFrontOf, Behind)")
+                   help="predicates the queries draw from: the workload's five (Near..RightOf) or all nine "
+                        "(+ NextTo, InFrontOf, Behind, On)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=0, help="queries in the CPU-oracle sample (0 = auto)")
     p.add_argument("--serving", action="store_true",

@@ -14,7 +14,7 @@
  *   sim(i,v) = max(0, cos(desc_i, v))
  *   s_sem(i) = kappa_i * sim(i, q_t)      kappa_i = 0.3 if both classes are
  *                                          known (>= 0) and differ, else 1
- *   t_r(i)   = max_{j != i} sim(j, q_r) * P_{p_r}(c_i, c_j)
+ *   t_r(i)   = max_{j != i} sim(j, q_r) * P_{p_r}(i, j)
  *   b_r(i)   = id of the maximising anchor (smallest id on ties)
  *   s(i)     = s_sem(i) * (0.5 + 0.5 * (prod_r t_r(i))^(1/R))   (1 if R = 0)
  *   TopK     = first min(K, n) objects by (s desc, id asc)
@@ -30,6 +30,10 @@
  *   FARM_LEFT_OF     sig(-(D_x r_x + D_y r_y) / 0.1)
  *   FARM_IN_FRONT_OF sig(-(D_x f_x + D_y f_y) / 0.1)   (nearer the viewer)
  *   FARM_BEHIND      sig((D_x f_x + D_y f_y) / 0.1)
+ *   FARM_ON          exp(-(D_x^2 + D_y^2) / (2 * 0.5^2)) * exp(-g^2 / (2 * 0.125^2))
+ *                    g = (c_i,z - e_i,z / 2) - (c_j,z + e_j,z / 2): the target's
+ *                    bottom face minus the anchor's top face (e = full extents);
+ *                    a horizontal gate times a vertical band
  *
  * Conventions shared by every entry point:
  *   - Every function returns a farm_status; farm_last_error() gives a message
@@ -79,10 +83,11 @@ typedef enum {
   FARM_RIGHT_OF = 4,
   FARM_NEXT_TO = 5,
   FARM_IN_FRONT_OF = 6,
-  FARM_BEHIND = 7
+  FARM_BEHIND = 7,
+  FARM_ON = 8
 } farm_pred;
-#define FARM_NUM_PRED 8         /* predicate ids 0 .. FARM_NUM_PRED - 1 */
-#define FARM_NUM_PROP_PRED 8    /* predicates with learned anchor lists (network outputs) */
+#define FARM_NUM_PRED 9         /* predicate ids 0 .. FARM_NUM_PRED - 1 */
+#define FARM_NUM_PROP_PRED 9    /* predicates with learned anchor lists (network outputs): all */
 
 #define FARM_MAX_REL 8          /* relations per query */
 #define FARM_MAX_K 1024         /* TopK size */
@@ -285,13 +290,13 @@ FARM_API farm_status farm_workspace_timings(farm_workspace* ws, double* ms, int6
  * of exactness (see farm_build_proposals).
  *
  *   x  = [u_o (dp) | u_a (dp) | g(o,a) / 4 m (12) | 0]     dp = d rounded up to 64
- *   h1 = GELU(W1 x + b1), h2 = GELU(W2 h1 + b2), y = W3 h2 + b3 (8 logits,
- *   one per farm_pred), GELU(v) = v/2 (1 + erf(v / sqrt 2))
+ *   h1 = GELU(W1 x + b1), h2 = GELU(W2 h1 + b2), y = W3 h2 + b3 (P = FARM_NUM_PROP_PRED
+ *   logits, one per farm_pred), GELU(v) = v/2 (1 + erf(v / sqrt 2))
  *   g  = [c_o - c_a (3), e_o (3), e_a (3), |c_o - c_a|, (c_o - c_a).r,
  *         bottom_o - top_a]
  * FP32 master weights and AdamW moments (beta 0.9 / 0.999, eps 1e-8); GEMMs on
  * BF16 copies with FP32 accumulation.  Weights are row-major:
- * W1 [256][in_dim], b1 [256], W2 [256][256], b2 [256], W3 [8][256], b3 [8];
+ * W1 [256][in_dim], b1 [256], W2 [256][256], b2 [256], W3 [P][256], b3 [P];
  * in_dim = 2 dp + 64 (unused input columns hold zero weights).
  * ------------------------------------------------------------------------ */
 #define FARM_MLP_HIDDEN 256
@@ -341,7 +346,7 @@ FARM_API farm_status farm_mlp_step(farm_mlp* mlp, const farm_memory* mem, int32_
  *           must not be in use by another stream during the call)
  *   mlp     network with the memory's descriptor width, same device
  *   M       list length, 1..FARM_MAX_K (clamped to n - 1)
- * Memory: n * M * 8 * 8 bytes + 8 n * 4 bytes, plus transient chunk buffers
+ * Memory: n * M * P * 8 bytes + P n * 4 bytes (P = FARM_NUM_PROP_PRED), plus transient chunk buffers
  * (up to 4 GiB for very large n).  Synchronises `stream`.
  * Errors: INVALID_ARG (null, width/device mismatch, M out of range),
  * UNSUPPORTED (n > 500,000), OOM, HIP.
@@ -351,9 +356,9 @@ FARM_API farm_status farm_build_proposals(farm_memory* mem, farm_mlp* mlp, int32
 /*
  * Copy of the proposal tables (stream-ordered device-to-device copies):
  *   m_out  host out: list length M (0 = no tables; nothing else is written)
- *   idx    device [8][n][M] int32 anchor indices, or NULL
- *   val    device [8][n][M] FP32 predicate values (Near/NextTo: log P), or NULL
- *   out    device [8][n] FP32 largest value outside each list, or NULL
+ *   idx    device [P][n][M] int32 anchor indices (P = FARM_NUM_PROP_PRED), or NULL
+ *   val    device [P][n][M] FP32 predicate values (Near/NextTo/On: log P), or NULL
+ *   out    device [P][n] FP32 largest value outside each list, or NULL
  */
 FARM_API farm_status farm_get_proposals(const farm_memory* mem, int32_t* m_out, int32_t* idx, float* val, float* out,
                                         void* stream);

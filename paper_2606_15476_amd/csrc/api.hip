@@ -303,6 +303,7 @@ farm_status farm_build_memory(int64_t n, int32_t d, const float* desc, const flo
     if ((st = dalloc(mem->allocs, mem->bytes, &mem->hr_hi, 2 * nn, "lateral/depth hi"))) return fail(st);
     if ((st = dalloc(mem->allocs, mem->bytes, &mem->hr_lo, 2 * nn, "lateral/depth lo"))) return fail(st);
     if ((st = dalloc(mem->allocs, mem->bytes, &mem->ext, nn * 3, "extents"))) return fail(st);
+    if ((st = dalloc(mem->allocs, mem->bytes, &mem->vz, 2 * nn, "bottom/top faces"))) return fail(st);
     if ((st = dalloc(mem->allocs, mem->bytes, &mem->id, nn, "ids"))) return fail(st);
     if (cls)
       if ((st = dalloc(mem->allocs, mem->bytes, &mem->cls, nn, "classes"))) return fail(st);
@@ -335,8 +336,8 @@ farm_status farm_build_memory(int64_t n, int32_t d, const float* desc, const flo
       return fail_tmp(hip_fail(e, "error maximum"));
     if (mem->err_fp8 && (e = launch_max_reduce(mem->err_fp8, n, mem->err_max + 1, s)) != hipSuccess)
       return fail_tmp(hip_fail(e, "error maximum"));
-    if ((e = launch_geometry(center, extent, n, view_right_x, view_right_y, mem->x, mem->y, mem->z, mem->hr_hi,
-                             mem->hr_lo, mem->ext, s)) != hipSuccess)
+    if ((e = launch_geometry(center, extent, n, view_right_x, view_right_y, mem->vz, mem->x, mem->y, mem->z,
+                             mem->hr_hi, mem->hr_lo, mem->ext, s)) != hipSuccess)
       return fail_tmp(hip_fail(e, "geometry"));
     if ((e = hipMemcpyAsync(mem->id, id, nn * sizeof(uint32_t), hipMemcpyDeviceToDevice, s)) != hipSuccess)
       return fail_tmp(hip_fail(e, "copy ids"));

@@ -69,6 +69,11 @@ struct farm_memory {
   float* hr_hi = nullptr;
   float* hr_lo = nullptr;
   float* ext = nullptr;    // [3][n] extents
+  // [2][n]: On's vertical coordinates, 4 * bottom face (first n) and 4 * top
+  // face (z -+ extent_z / 2); the factor 4 = sigma_h / sigma_v (0.5 m / 0.125 m)
+  // turns On's exponent into Near's form with a single coefficient (a power of
+  // two, so exact)
+  float* vz = nullptr;
   uint32_t* id = nullptr;
   int32_t* cls = nullptr;
   // learned anchor proposals (farm_build_proposals): per predicate p and
@@ -263,7 +268,7 @@ hipError_t launch_validate_memory(const float* desc, const float* center, const 
 hipError_t launch_normalize_rows(const float* src, int64_t rows, int32_t d, int32_t ldk, float* dst_f32,
                                  const LowPrecRows& lp, int* flags, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
-hipError_t launch_geometry(const float* center, const float* extent, int64_t n, float rx, float ry,
+hipError_t launch_geometry(const float* center, const float* extent, int64_t n, float rx, float ry, float* vz,
                            float* x, float* y, float* z, float* hr_hi, float* hr_lo, float* ext,
                            hipStream_t s);
 

@@ -95,8 +95,9 @@ template <bool WITH_ARG>
 __global__ __launch_bounds__(kThreads) void k_pair_exhaustive(
     const float* __restrict__ sim, const float* __restrict__ lsim, int64_t ld_s, int32_t q, MetaView meta,
     SimBound bound, const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
-    const float* __restrict__ hhi, const float* __restrict__ hlo, const uint32_t* __restrict__ ids,
-    const int32_t* __restrict__ cls, int64_t n, float* __restrict__ scores, int64_t ld_out,
+    const float* __restrict__ vz, const float* __restrict__ hhi, const float* __restrict__ hlo,
+    const uint32_t* __restrict__ ids, const int32_t* __restrict__ cls, int64_t n, float* __restrict__ scores,
+    int64_t ld_out,
     float* __restrict__ rel_terms, uint32_t* __restrict__ rel_anchor_id, float* __restrict__ scores_hi) {
   __shared__ float4 rec[kChunk];
   __shared__ uint32_t rid[WITH_ARG ? kChunk : 1];
@@ -126,14 +127,16 @@ __global__ __launch_bounds__(kThreads) void k_pair_exhaustive(
     // InFrontOf/Behind measure along the viewing direction: the depth pair follows the lateral one
     const float* rhi = hhi + (is_depth(p) ? n : 0);
     const float* rlo = hlo + (is_depth(p) ? n : 0);
+    const ZPair zp = z_for(p, z, vz, n);  // On: the target's bottom and the anchors' top faces
     Tgt t[kTpt];
 #pragma unroll
-    for (int u = 0; u < kTpt; ++u) t[u] = load_target(fam, ti[u], x, y, z, rhi, rlo);
+    for (int u = 0; u < kTpt; ++u) t[u] = load_target(fam, ti[u], x, y, zp.tgt, rhi, rlo);
     float best[kTpt];
     uint32_t bid[kTpt];
     float term[kTpt];
     if (fam == kFamNear) {
-      relation_pass<kFamNear, WITH_ARG>(arow, lrow, n, tile0, ti, t, c, x, y, z, rhi, rlo, ids, rec, rid, best, bid);
+      relation_pass<kFamNear, WITH_ARG>(arow, lrow, n, tile0, ti, t, c, x, y, zp.anc, rhi, rlo, ids, rec, rid, best,
+                                        bid);
 #pragma unroll
       for (int u = 0; u < kTpt; ++u) {
         term[u] = term_of<kFamNear>(best[u]);
@@ -189,15 +192,15 @@ __global__ __launch_bounds__(kThreads) void k_pair_exhaustive(
 // pass above (identical values), reducing (value, id) across the block.
 template <int FAM>
 __device__ void explain_relation(const float* __restrict__ arow, int64_t n, int64_t i, float c, const float* x,
-                                 const float* y, const float* z, const float* hhi, const float* hlo,
+                                 const float* y, ZPair zp, const float* hhi, const float* hlo,
                                  const uint32_t* ids, float* red_v, uint32_t* red_id, float& out_t,
                                  uint32_t& out_b) {
-  Tgt t = load_target(FAM, i, x, y, z, hhi, hlo);
+  Tgt t = load_target(FAM, i, x, y, zp.tgt, hhi, hlo);
   float best = value_floor<FAM>();
   uint32_t bid = FARM_NO_ID;
   for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
     if (j == i) continue;
-    float4 r = anchor_record(FAM, arow[j], j, x, y, z, hhi, hlo);
+    float4 r = anchor_record(FAM, arow[j], j, x, y, zp.anc, hhi, hlo);
     float v = pair_value<FAM>(t, r, c);
     if (v >= best && v != -INFINITY) {
       uint32_t idj = ids[j];
@@ -231,7 +234,8 @@ __device__ void explain_relation(const float* __restrict__ arow, int64_t n, int6
 __global__ __launch_bounds__(256) void k_explain(const float* __restrict__ sim, int64_t ld_s, int32_t q,
                                                  MetaView meta, const int32_t* __restrict__ idx, int32_t k,
                                                  const float* __restrict__ x, const float* __restrict__ y,
-                                                 const float* __restrict__ z, const float* __restrict__ hhi,
+                                                 const float* __restrict__ z, const float* __restrict__ vz,
+                                                 const float* __restrict__ hhi,
                                                  const float* __restrict__ hlo, const uint32_t* __restrict__ ids,
                                                  int64_t n, float* __restrict__ out_terms,
                                                  uint32_t* __restrict__ out_anchor_id) {
@@ -251,10 +255,11 @@ __global__ __launch_bounds__(256) void k_explain(const float* __restrict__ sim, 
       const float c = sigmoid_scale(p);
       const float* rhi = hhi + (is_depth(p) ? n : 0);  // depth pair of InFrontOf/Behind
       const float* rlo = hlo + (is_depth(p) ? n : 0);
+      const ZPair zp = z_for(p, z, vz, n);  // On: bottom/top faces
       switch (family_of(p)) {
-        case kFamNear: explain_relation<kFamNear>(arow, n, i, c, x, y, z, rhi, rlo, ids, red_v, red_id, tv, b); break;
-        case kFamVert: explain_relation<kFamVert>(arow, n, i, c, x, y, z, rhi, rlo, ids, red_v, red_id, tv, b); break;
-        default: explain_relation<kFamLat>(arow, n, i, c, x, y, z, rhi, rlo, ids, red_v, red_id, tv, b); break;
+        case kFamNear: explain_relation<kFamNear>(arow, n, i, c, x, y, zp, rhi, rlo, ids, red_v, red_id, tv, b); break;
+        case kFamVert: explain_relation<kFamVert>(arow, n, i, c, x, y, zp, rhi, rlo, ids, red_v, red_id, tv, b); break;
+        default: explain_relation<kFamLat>(arow, n, i, c, x, y, zp, rhi, rlo, ids, red_v, red_id, tv, b); break;
       }
     }
     if (threadIdx.x == 0) {
@@ -288,13 +293,12 @@ hipError_t launch_pair_exhaustive(const farm_memory* mem, const float* sim, cons
   dim3 grid((unsigned)((n + kTile - 1) / kTile), (unsigned)q);
   if (rel_anchor_id)
     hipLaunchKernelGGL(k_pair_exhaustive<true>, grid, dim3(kThreads), 0, s, sim, lsim, ld_s, q, meta, bound, mem->x,
-                       mem->y,
-                       mem->z, mem->hr_hi, mem->hr_lo, mem->id, mem->cls, n, scores, ld_out, rel_terms,
-                       rel_anchor_id, scores_hi);
+                       mem->y, mem->z, mem->vz, mem->hr_hi, mem->hr_lo, mem->id, mem->cls, n, scores, ld_out,
+                       rel_terms, rel_anchor_id, scores_hi);
   else
     hipLaunchKernelGGL(k_pair_exhaustive<false>, grid, dim3(kThreads), 0, s, sim, lsim, ld_s, q, meta, bound, mem->x,
-                       mem->y, mem->z, mem->hr_hi, mem->hr_lo, mem->id, mem->cls, n, scores, ld_out, rel_terms,
-                       rel_anchor_id, scores_hi);
+                       mem->y, mem->z, mem->vz, mem->hr_hi, mem->hr_lo, mem->id, mem->cls, n, scores, ld_out,
+                       rel_terms, rel_anchor_id, scores_hi);
   return hipGetLastError();
 }
 
@@ -302,7 +306,7 @@ hipError_t launch_explain(const farm_memory* mem, const float* sim, int64_t ld_s
                           const int32_t* idx, int32_t k, float* out_terms, uint32_t* out_anchor_id, hipStream_t s) {
   if (q <= 0 || k <= 0 || (!out_terms && !out_anchor_id)) return hipSuccess;
   dim3 grid((unsigned)k, (unsigned)q);
-  hipLaunchKernelGGL(k_explain, grid, dim3(256), 0, s, sim, ld_s, q, meta, idx, k, mem->x, mem->y, mem->z,
+  hipLaunchKernelGGL(k_explain, grid, dim3(256), 0, s, sim, ld_s, q, meta, idx, k, mem->x, mem->y, mem->z, mem->vz,
                      mem->hr_hi, mem->hr_lo, mem->id, mem->n, out_terms, out_anchor_id);
   return hipGetLastError();
 }

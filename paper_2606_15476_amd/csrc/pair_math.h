@@ -6,6 +6,14 @@
 //   Near/NextTo: log(a_j) + c |c_i - c_j|^2 with c = -1/(2 sigma^2) (-2 for
 //                Near, -1/2 for NextTo) is compared in the log domain (no
 //                transcendental per pair); t = exp(max).
+//   On:          the same form: the gate's and the band's exponents add up to
+//                c (dx^2 + dy^2 + (4 g)^2) with c = -1/(2 * 0.5^2) = -2 and g
+//                the gap between the target's bottom and the anchor's top,
+//                since the band's width 0.125 m is a quarter of the gate's; the
+//                vertical coordinate is 4 * bottom for the target and 4 * top
+//                for the anchor instead of the center.
+// Every Near-family coefficient is a power of two, so c * d2 is exact and a
+// cached c * d2 plus log(a) rounds as fmaf(c, d2, log a) does.
 //   Above/Below: P = 1 / (1 + 2^(dz * c)), c = -+(1/tau) log2(e), dz = z_i - z_j.
 //   Left/Right:  the same sigmoid of the lateral offset dh = h_i - h_j, with h
 //                kept as an unevaluated float pair hi + lo; InFrontOf/Behind
@@ -27,7 +35,9 @@ enum Family { kFamNear = 0, kFamVert = 1, kFamLat = 2 };
 constexpr float kInvTauLog2e = 14.426950408889634f;
 
 __device__ inline int family_of(int p) {
-  return (p == FARM_NEAR || p == FARM_NEXT_TO) ? kFamNear : (p == FARM_ABOVE || p == FARM_BELOW) ? kFamVert : kFamLat;
+  return (p == FARM_NEAR || p == FARM_NEXT_TO || p == FARM_ON) ? kFamNear
+         : (p == FARM_ABOVE || p == FARM_BELOW)                ? kFamVert
+                                                               : kFamLat;
 }
 
 // Predicates of the Left/Right family measured along the viewing direction
@@ -40,11 +50,23 @@ __device__ inline bool is_depth(int p) { return p == FARM_IN_FRONT_OF || p == FA
 __device__ inline float sigmoid_scale(int p) {
   if (p == FARM_NEAR) return -2.0f;     // sigma 0.5 m
   if (p == FARM_NEXT_TO) return -0.5f;  // sigma 1.0 m
+  if (p == FARM_ON) return -2.0f;       // gate sigma 0.5 m (band 0.125 m through the scaled coordinate)
   return (p == FARM_ABOVE || p == FARM_RIGHT_OF || p == FARM_BEHIND) ? -kInvTauLog2e : kInvTauLog2e;
 }
 
 __device__ inline float rcp_approx(float v) { return __builtin_amdgcn_rcpf(v); }
 __device__ inline float exp2_approx(float v) { return __builtin_amdgcn_exp2f(v); }
+
+// The vertical coordinates of the Near family for predicate p: the target's
+// and the anchor's.  On compares the target's bottom face with the anchor's
+// top face (vz: [2][n], both scaled by 4); the others the box centers.
+struct ZPair {
+  const float* tgt;
+  const float* anc;
+};
+__device__ inline ZPair z_for(int p, const float* z, const float* vz, int64_t n) {
+  return p == FARM_ON ? ZPair{vz, vz + n} : ZPair{z, z};
+}
 
 // Per-target coordinates, family-specific.
 struct Tgt {

@@ -179,7 +179,8 @@ __device__ inline void two_sum(float a, float b, float& s, float& e) {
 
 __global__ void k_geometry(const float* __restrict__ center, const float* __restrict__ extent, int64_t n, float rx,
                            float ry, float* __restrict__ x, float* __restrict__ y, float* __restrict__ z,
-                           float* __restrict__ hhi, float* __restrict__ hlo, float* __restrict__ ext) {
+                           float* __restrict__ hhi, float* __restrict__ hlo, float* __restrict__ ext,
+                           float* __restrict__ vz) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   float cx = center[i * 3 + 0], cy = center[i * 3 + 1], cz = center[i * 3 + 2];
@@ -201,6 +202,10 @@ __global__ void k_geometry(const float* __restrict__ center, const float* __rest
   dot2(rx, ry, hhi[i], hlo[i]);
   dot2(-ry, rx, hhi[n + i], hlo[n + i]);
   for (int k = 0; k < 3; ++k) ext[k * n + i] = extent[i * 3 + k];
+  // bottom and top faces, scaled by 4 (exact): one rounding each, as z -+ e/2
+  const float half = 0.5f * extent[i * 3 + 2];
+  vz[i] = 4.0f * (cz - half);
+  vz[n + i] = 4.0f * (cz + half);
 }
 
 }  // namespace
@@ -231,11 +236,11 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_geometry(const float* center, const float* extent, int64_t n, float rx, float ry, float* x,
-                           float* y, float* z, float* hr_hi, float* hr_lo, float* ext, hipStream_t s) {
+hipError_t launch_geometry(const float* center, const float* extent, int64_t n, float rx, float ry, float* vz,
+                           float* x, float* y, float* z, float* hr_hi, float* hr_lo, float* ext, hipStream_t s) {
   int64_t blocks = (n + 255) / 256;
   hipLaunchKernelGGL(k_geometry, dim3((unsigned)blocks), dim3(256), 0, s, center, extent, n, rx, ry, x, y, z, hr_hi,
-                     hr_lo, ext);
+                     hr_lo, ext, vz);
   return hipGetLastError();
 }
 

@@ -104,14 +104,15 @@ __global__ void k_head_rows(const uint16_t* __restrict__ A2, const float* __rest
 }
 
 // Predicate value of (o, a) for predicate p in the family's comparison domain
-// (Near/NextTo: log P; others: P), computed with the shared per-pair arithmetic
-// (hhi/hlo: the coordinate pair of p's family, lateral or depth).
-__device__ inline float pred_value(int p, int64_t o, int64_t a, const float* x, const float* y, const float* z,
+// (Near/NextTo/On: log P; others: P), computed with the shared per-pair
+// arithmetic (hhi/hlo: the coordinate pair of p's family, lateral or depth;
+// zp: the target's and the anchor's vertical coordinates).
+__device__ inline float pred_value(int p, int64_t o, int64_t a, const float* x, const float* y, ZPair zp,
                                    const float* hhi, const float* hlo) {
   const int fam = family_of(p);
   const float c = sigmoid_scale(p);
-  const Tgt t = load_target(fam, o, x, y, z, hhi, hlo);
-  const float4 r = anchor_record_pre(fam, 1.0f, 0.0f, a, x, y, z, hhi, hlo);
+  const Tgt t = load_target(fam, o, x, y, zp.tgt, hhi, hlo);
+  const float4 r = anchor_record_pre(fam, 1.0f, 0.0f, a, x, y, zp.anc, hhi, hlo);
   if (fam == kFamNear) return pair_value<kFamNear>(t, r, c);
   if (fam == kFamVert) return pair_value<kFamVert>(t, r, c);
   return pair_value<kFamLat>(t, r, c);
@@ -122,6 +123,7 @@ __device__ inline float pred_value(int p, int64_t o, int64_t a, const float* x, 
 __global__ __launch_bounds__(256) void k_prop_finalize(const int32_t* __restrict__ top_idx, int32_t M, int64_t t0,
                                                        int64_t tc, int64_t n, const float* __restrict__ x,
                                                        const float* __restrict__ y, const float* __restrict__ z,
+                                                       const float* __restrict__ vz,
                                                        const float* __restrict__ hhi, const float* __restrict__ hlo,
                                                        int32_t* __restrict__ prop_idx, float* __restrict__ prop_val,
                                                        float* __restrict__ prop_out) {
@@ -133,6 +135,7 @@ __global__ __launch_bounds__(256) void k_prop_finalize(const int32_t* __restrict
   // InFrontOf/Behind use the depth pair stored after the lateral one
   hhi += is_depth(p) ? n : 0;
   hlo += is_depth(p) ? n : 0;
+  const ZPair zp = z_for(p, z, vz, n);  // On: the target's bottom and the anchors' top faces
   for (int64_t w = threadIdx.x; w < words; w += blockDim.x) bits[w] = 0;
   __syncthreads();
   const int32_t* row = top_idx + ((int64_t)p * tc + t) * M;
@@ -142,13 +145,13 @@ __global__ __launch_bounds__(256) void k_prop_finalize(const int32_t* __restrict
     if (a < 0 || a >= n || a == o) a = o == 0 ? 1 : 0;
     atomicOr(&bits[a >> 5], 1u << (a & 31));
     prop_idx[base + m] = a;
-    prop_val[base + m] = pred_value(p, o, a, x, y, z, hhi, hlo);
+    prop_val[base + m] = pred_value(p, o, a, x, y, zp, hhi, hlo);
   }
   __syncthreads();
   float best = -INFINITY;
   for (int64_t a = threadIdx.x; a < n; a += blockDim.x) {
     if (a == o || (bits[a >> 5] >> (a & 31)) & 1u) continue;
-    best = fmaxf(best, pred_value(p, o, a, x, y, z, hhi, hlo));
+    best = fmaxf(best, pred_value(p, o, a, x, y, zp, hhi, hlo));
   }
   red[threadIdx.x] = best;
   __syncthreads();
@@ -343,7 +346,7 @@ extern "C" farm_status farm_build_proposals(farm_memory* mem, farm_mlp* mlp, int
       if ((e = launch_topk_emit(key, idx, (int32_t)(kNPred * tc), M, nullptr, nullptr, top_idx, s)))
         return fail(FARM_ERR_HIP, "list emit");
       hipLaunchKernelGGL(k_prop_finalize, dim3((unsigned)tc, kNPred), dim3(256), bitmap, s, top_idx, M, t0, tc, n,
-                         mem->x, mem->y, mem->z, mem->hr_hi, mem->hr_lo, pidx, pval, pout);
+                         mem->x, mem->y, mem->z, mem->vz, mem->hr_hi, mem->hr_lo, pidx, pval, pout);
       if ((e = hipGetLastError()) != hipSuccess) return fail(FARM_ERR_HIP, "finalize");
     }
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(FARM_ERR_HIP, "synchronize");

@@ -168,20 +168,26 @@ __device__ inline float wave_max_f(float v) {
   return v;
 }
 
-// Geometry of the memory, passed by value.
+// Geometry of the memory, passed by value.  z is the targets' vertical
+// coordinate and za the anchors' (the same array except for On).
 struct Geo {
-  const float *x, *y, *z, *hhi, *hlo;  // hhi/hlo: [2][n], lateral then depth pairs
+  const float *x, *y, *z, *za, *hhi, *hlo;  // hhi/hlo: [2][n], lateral then depth pairs
   const uint32_t* ids;
+  const float* vz;  // [2][n]: 4 * bottom face, 4 * top face (On)
 };
 
 // The coordinates predicate p uses: InFrontOf/Behind take the depth pair
-// (entries n..2n-1) where the other Left/Right-family predicates take the lateral one.
+// (entries n..2n-1) where the other Left/Right-family predicates take the
+// lateral one; On takes the target's bottom and the anchor's top face.
 __device__ inline Geo geo_for(const Geo& g, int p, int64_t n) {
   Geo r = g;
   if (is_depth(p)) {
     r.hhi += n;
     r.hlo += n;
   }
+  const ZPair zp = z_for(p, g.z, g.vz, n);
+  r.z = zp.tgt;
+  r.za = zp.anc;
   return r;
 }
 
@@ -205,8 +211,8 @@ struct Subset {
 // (z), Left/Right (h hi, h lo).
 template <int FAM>
 __device__ inline float4 geo_of(int64_t j, const Geo& g) {
-  if (FAM == kFamNear) return make_float4(g.x[j], g.y[j], g.z[j], 0.f);
-  if (FAM == kFamVert) return make_float4(g.z[j], 0.f, 0.f, 0.f);
+  if (FAM == kFamNear) return make_float4(g.x[j], g.y[j], g.za[j], 0.f);
+  if (FAM == kFamVert) return make_float4(g.za[j], 0.f, 0.f, 0.f);
   return make_float4(g.hhi[j], g.hlo[j], 0.f, 0.f);
 }
 // anchor record (as anchor_record_pre) from such coordinates
@@ -237,7 +243,7 @@ __device__ void full_term(const float* __restrict__ arow, const float* __restric
     my_member = sidx[lane];
     if (my_member != o) {
       const float a = ssim[lane];
-      take_max(pair_value<FAM>(t, anchor_record(FAM, a, my_member, g.x, g.y, g.z, g.hhi, g.hlo), c), my_member,
+      take_max(pair_value<FAM>(t, anchor_record(FAM, a, my_member, g.x, g.y, g.za, g.hhi, g.hlo), c), my_member,
                g.ids, best, bid);
     }
   }
@@ -245,7 +251,7 @@ __device__ void full_term(const float* __restrict__ arow, const float* __restric
     // FP32 similarities: the maximum directly, with the relational pass's arithmetic
     for (int64_t j = lane; j < n; j += 64) {
       if (j == o) continue;
-      const float v = pair_value<FAM>(t, anchor_record(FAM, arow[j], j, g.x, g.y, g.z, g.hhi, g.hlo), c);
+      const float v = pair_value<FAM>(t, anchor_record(FAM, arow[j], j, g.x, g.y, g.za, g.hhi, g.hlo), c);
       take_max(v, j, g.ids, best, bid);
     }
   } else {
@@ -253,7 +259,7 @@ __device__ void full_term(const float* __restrict__ arow, const float* __restric
     for (int64_t j = lane; j < n; j += 64) {
       if (j == o) continue;
       const float a = fmaxf(0.f, arow[j] - fmaf(qn, o_err[j], qe));
-      lo = fmaxf(lo, pair_value<FAM>(t, anchor_record(FAM, a, j, g.x, g.y, g.z, g.hhi, g.hlo), c));
+      lo = fmaxf(lo, pair_value<FAM>(t, anchor_record(FAM, a, j, g.x, g.y, g.za, g.hhi, g.hlo), c));
     }
     lo = wave_max_f(lo);
     const float L = lo - (fabsf(lo) * 1e-6f + 1e-30f);  // slack for rounding of the bounded values
@@ -262,7 +268,7 @@ __device__ void full_term(const float* __restrict__ arow, const float* __restric
       bool f = false;
       if (j < n && j != o) {
         const float a = fminf(1.0f, arow[j] + fmaf(qn, o_err[j], qe));
-        f = pair_value<FAM>(t, anchor_record(FAM, a, j, g.x, g.y, g.z, g.hhi, g.hlo), c) >= L;
+        f = pair_value<FAM>(t, anchor_record(FAM, a, j, g.x, g.y, g.za, g.hhi, g.hlo), c) >= L;
       }
       uint64_t mask = __ballot(f);
       while (mask) {
@@ -272,7 +278,7 @@ __device__ void full_term(const float* __restrict__ arow, const float* __restric
         if (__ballot(my_member == j2)) continue;  // a semantic-set member: its exact value is in already
         const float a = fmaxf(0.f, wave_dot(qrow, dn + j2 * ldk, ldk, lane));
         ++dots;
-        take_max(pair_value<FAM>(t, anchor_record(FAM, a, j2, g.x, g.y, g.z, g.hhi, g.hlo), c), j2, g.ids, best,
+        take_max(pair_value<FAM>(t, anchor_record(FAM, a, j2, g.x, g.y, g.za, g.hhi, g.hlo), c), j2, g.ids, best,
                  bid);
       }
     }
@@ -425,7 +431,7 @@ __device__ bool subset_term_gen(Row arow, const float* __restrict__ qrow, const 
   // list entries carry the cached predicate value; semantic-set entries are evaluated
   auto entry = [&](int e, int64_t j, float a, float la) -> float {
     if (e < sub.M) return FAM == kFamNear ? la + sub.lval[e] : a * sub.lval[e];
-    return pair_value<FAM>(t, anchor_record_pre(FAM, a, la, j, g.x, g.y, g.z, g.hhi, g.hlo), c);
+    return pair_value<FAM>(t, anchor_record_pre(FAM, a, la, j, g.x, g.y, g.za, g.hhi, g.hlo), c);
   };
   // similarity error bound of anchor j (per anchor, or one bound for all)
   auto delta = [&](int64_t j) { return o_err ? fmaf(qn, o_err[j], qe) : qd_uniform; };
@@ -833,16 +839,20 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
   // the set's anchor coordinates and the first kCandLds candidates (id, own
   // coordinates, bound on the predicate outside the list), read once for all
   // of the relation's terms
-  auto coords = [&](int64_t j) {
-    return fam == kFamNear ? geo_of<kFamNear>(j, gp) : fam == kFamVert ? geo_of<kFamVert>(j, gp)
-                                                       : geo_of<kFamLat>(j, gp);
+  auto coords = [&](int64_t j, const Geo& gg) {
+    return fam == kFamNear ? geo_of<kFamNear>(j, gg) : fam == kFamVert ? geo_of<kFamVert>(j, gg)
+                                                       : geo_of<kFamLat>(j, gg);
   };
-  if ((int)threadIdx.x < sn) set_geo[threadIdx.x] = coords(set_idx[threadIdx.x]);
+  // candidates are targets: their vertical coordinate is z, not the anchors' za
+  // (they differ for On: bottom and top faces); same layout as load_target
+  Geo gt = gp;
+  gt.za = gp.z;
+  if ((int)threadIdx.x < sn) set_geo[threadIdx.x] = coords(set_idx[threadIdx.x], gp);
   for (int32_t i = threadIdx.x; i < cnt && i < kCandLds; i += kLdsThreads) {
     const int32_t o = cand[(int64_t)qq * C + i];
     c_id[i] = o;
     if (o >= 0) {
-      c_geo[i] = coords(o);
+      c_geo[i] = coords(o, gt);
       c_pout[i] = tab ? pv.out[(int64_t)p * n + o] : 0.f;
     }
   }
@@ -1040,7 +1050,7 @@ __device__ void full_term_block(const float* __restrict__ arow, const float* __r
     my_member = sidx[lane];
     if (w == 0 && my_member != o) {
       const float a = ssim[lane];
-      take_max(pair_value<FAM>(t, anchor_record(FAM, a, my_member, g.x, g.y, g.z, g.hhi, g.hlo), c), my_member,
+      take_max(pair_value<FAM>(t, anchor_record(FAM, a, my_member, g.x, g.y, g.za, g.hhi, g.hlo), c), my_member,
                g.ids, best, bid);
     }
   }
@@ -1120,7 +1130,7 @@ __device__ void full_term_block(const float* __restrict__ arow, const float* __r
         if (__ballot(my_member == j2)) continue;  // a semantic-set member: its exact value is in already
         const float a = fmaxf(0.f, wave_dot(qrow, dn + j2 * ldk, ldk, lane));
         ++dots;
-        take_max(pair_value<FAM>(t, anchor_record(FAM, a, j2, g.x, g.y, g.z, g.hhi, g.hlo), c), j2, g.ids, best,
+        take_max(pair_value<FAM>(t, anchor_record(FAM, a, j2, g.x, g.y, g.za, g.hhi, g.hlo), c), j2, g.ids, best,
                  bid);
       }
     }
@@ -1400,7 +1410,7 @@ hipError_t launch_rescore_terms(const farm_memory* mem, const farm_workspace* ws
                                 const int32_t* cand_count, int32_t c, const PropView& prop, bool fallback_pass,
                                 hipStream_t s) {
   if (q <= 0 || c <= 0) return hipSuccess;
-  const Geo g{mem->x, mem->y, mem->z, mem->hr_hi, mem->hr_lo, mem->id};
+  const Geo g{mem->x, mem->y, mem->z, mem->z, mem->hr_hi, mem->hr_lo, mem->id, mem->vz};
   const dim3 grid(kTermBlocksX, (unsigned)q), block(64 * kTermWaves);
 #define FARM_TERMS(MODE, B)                                                                                      \
   hipLaunchKernelGGL((k_rescore_terms<MODE, B>), grid, block, 0, s, sim, ld_s, q, meta, bound, ws->qn, mem->dn, \

@@ -117,9 +117,10 @@ def test_mid_config_subset_full_parity(farm):
             assert np.all(anch[qq, rank, r1 - r0:] == 0xFFFFFFFF)
 
 
-def test_all_eight_predicates_full_parity(farm):
-    """NextTo, InFrontOf and Behind beside the first five: full score matrix,
-    per-relation terms and bindings, TopK and breakdown against the oracle."""
+def test_all_predicates_full_parity(farm):
+    """NextTo, InFrontOf, Behind and On beside the first five: full score
+    matrix, per-relation terms and bindings, TopK and breakdown against the
+    oracle."""
     import synth
     cfg = CONFIGS["mid"]
     scene = make_scene(cfg, seed=21)

@@ -36,7 +36,7 @@ def _tables(farm, mem):
 
 
 def _p64(scene, p, o, a):
-    return oracle.predicate(p, scene.center[o], scene.center[a], scene.view_right)
+    return oracle.predicate(p, scene.center[o], scene.center[a], scene.view_right, scene.extent[o], scene.extent[a])
 
 
 def test_tables_match_oracle(farm):
@@ -55,8 +55,8 @@ def test_tables_match_oracle(farm):
             lst = idx[p, o]
             assert np.all((lst >= 0) & (lst < n)) and np.all(lst != o)
             assert len(set(lst.tolist())) == m
-            # cached values: log P for the Gaussians (Near, NextTo), P otherwise
-            log_domain = p in (farm.NEAR, farm.NEXT_TO)
+            # cached values: log P for the Gaussians (Near, NextTo, On), P otherwise
+            log_domain = p in (farm.NEAR, farm.NEXT_TO, farm.ON)
             for e, a in enumerate(lst):
                 v64 = _p64(scene, p, o, a)
                 got = np.exp(np.float64(val[p, o, e])) if log_domain else np.float64(val[p, o, e])
@@ -116,10 +116,10 @@ def test_proposal_equals_bounded_mid(farm, dtype, m):
 
 
 @pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "bf16"])
-def test_all_eight_predicates(farm, dtype):
-    """Lists for NextTo/InFrontOf/Behind too (their depth coordinates, NextTo's
-    log domain); results stay bit-identical to BOUNDED, which equals the exact
-    TopK."""
+def test_all_predicates(farm, dtype):
+    """Lists for NextTo/InFrontOf/Behind/On too (their depth coordinates, the
+    log domain of NextTo and On, On's bottom/top faces); results stay
+    bit-identical to BOUNDED, which equals the exact TopK."""
     import synth
     from tests import _gpu
     cfg = CONFIGS["mid"]
