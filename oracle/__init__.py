@@ -53,7 +53,8 @@ def _load():
         lib.farm_oracle_topk.restype = ctypes.c_int
         lib.farm_oracle_topk.argtypes = [i64, P, P, i32, P]
         lib.farm_oracle_binding_value.restype = ctypes.c_double
-        lib.farm_oracle_binding_value.argtypes = [i64, ctypes.c_int, P, P, P, P, ctypes.c_int, P, i64, i64]
+        lib.farm_oracle_binding_value.argtypes = [i64, ctypes.c_int, P, P, P, P, P, P, i32, ctypes.c_int, P, i64,
+                                                  i64]
         lib.farm_oracle_pair_features.restype = None
         lib.farm_oracle_pair_features.argtypes = [P, P, P, i64, i64, P]
         lib.farm_oracle_mlp.restype = ctypes.c_int
@@ -190,19 +191,25 @@ def topk_bounded(scene, qb, k: int):
     return idx, sc, t, b, ns
 
 
-def binding_value(scene, pred: int, anchor_vec, i: int, j: int) -> float:
-    """sim(j, q_r) * P_pred(i, j) in FP64 for one candidate binding."""
+def binding_value(scene, pred: int, anchor_vec, i: int, j: int, target_cls: int = -1) -> float:
+    """sim(j, q_r) * P_pred(i, j) in FP64 for one candidate binding (target_cls:
+    the query's parsed class, which fixes the candidate set of Closest/Farthest)."""
     lib = _load()
     desc, pd = _c(scene.desc, np.float32)
     cen, pc = _c(scene.center, np.float32)
     ext, pe = _c(scene.extent, np.float32)
+    ids, pi = _c(scene.ids, np.uint32)
+    if scene.cls is None:
+        cls, pk = None, None
+    else:
+        cls, pk = _c(scene.cls, np.int32)
     vr, pv = _c(scene.view_right, np.float32)
     av, pa = _c(anchor_vec, np.float32)
-    return float(lib.farm_oracle_binding_value(int(desc.shape[0]), int(desc.shape[1]), pd, pc, pe, pv, int(pred),
-                                               pa, int(i), int(j)))
+    return float(lib.farm_oracle_binding_value(int(desc.shape[0]), int(desc.shape[1]), pd, pc, pe, pi, pk, pv,
+                                               int(target_cls), int(pred), pa, int(i), int(j)))
 
 
-NUM_PRED = 9   # predicates the scorer evaluates (ids 0..8, On = 8)
+NUM_PRED = 11  # predicates the scorer evaluates (ids 0..10: On = 8, Closest = 9, Farthest = 10)
 NPRED = 9      # proposal-network outputs, one per predicate
 NGEO = 12
 

@@ -12,13 +12,16 @@ Appendix "Retrieval Details", composite-scoring step:
 
 Each relation's term folds the anchor's own description match sim(a, q_r)
 into the relational score (the anchor's unary predicate and the relation share
-the anchor variable).  Pure Python on math.* in double precision; it shares no
-code with ``farm_oracle.c`` and costs O(N^(R+1)) -- use N <= 16, R <= 3.
+the anchor variable).  Pure Python on math.* in double precision (the rank of
+Closest/Farthest is decided in FP32, see ``rank_relation``); it shares no code
+with ``farm_oracle.c`` and costs O(N^(R+1)) -- use N <= 16, R <= 3.
 """
 from __future__ import annotations
 
 import itertools
 import math
+
+import numpy as np
 
 W = 0.5
 CLASS_FACTOR = 0.3
@@ -71,6 +74,36 @@ def soft_relation(pred, ci, cj, right, ei=(0.0, 0.0, 0.0), ej=(0.0, 0.0, 0.0)):
     raise ValueError(pred)
 
 
+def rank_relation(pred, scene, tcls, i, j):
+    """Closest (9) / Farthest (10): 1 / (|rank - r*| + 1), the rank of target i
+    among the query's candidates (objects of class tcls; all objects without a
+    class) by distance to anchor j, nearer first, equal distances by id.  The
+    distances are compared in FP32 in the order ((dx*dx + dy*dy) + dz*dz), as
+    the scorers decide the rank."""
+    c = scene.center.astype(np.float32)
+
+    def d2(a, b):
+        dx, dy, dz = c[a, 0] - c[b, 0], c[a, 1] - c[b, 1], c[a, 2] - c[b, 2]
+        s = dx * dx
+        s = s + dy * dy
+        return s + dz * dz
+
+    dij = d2(i, j)
+    nearer = m = 0
+    for k in range(scene.desc.shape[0]):
+        if k in (i, j):
+            continue
+        if tcls >= 0 and scene.cls is not None and int(scene.cls[k]) != tcls:
+            continue
+        m += 1
+        dk = d2(k, j)
+        if dk < dij or (dk == dij and int(scene.ids[k]) < int(scene.ids[i])):
+            nearer += 1
+    rank = nearer + 1
+    rstar = 1 if pred == 9 else m + 1
+    return 1.0 / (abs(rank - rstar) + 1)
+
+
 def brute_scores(scene, qb):
     """Scores [q][n] by enumerating all anchor bindings (list of lists of floats)."""
     n = scene.desc.shape[0]
@@ -97,8 +130,12 @@ def brute_scores(scene, qb):
             for binding in itertools.product(others, repeat=len(rels)):
                 prod = 1.0
                 for (pred, qr), j in zip(rels, binding):
-                    prod *= _sim(units[j], qr) * soft_relation(pred, scene.center[e], scene.center[j], scene.view_right,
-                                                               scene.extent[e], scene.extent[j])
+                    if pred in (9, 10):
+                        pv = rank_relation(pred, scene, tcls, e, j)
+                    else:
+                        pv = soft_relation(pred, scene.center[e], scene.center[j], scene.view_right,
+                                           scene.extent[e], scene.extent[j])
+                    prod *= _sim(units[j], qr) * pv
                 v = s_sem * ((1 - W) + W * prod ** (1.0 / len(rels)))
                 if best is None or v > best:
                     best = v

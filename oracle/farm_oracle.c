@@ -34,6 +34,8 @@
  *   IN_FRONT_OF = sig(-(D_x f_x + D_y f_y) / 0.1),  BEHIND = sig(+(...) / 0.1)
  *   ON       = exp(-(D_x^2 + D_y^2) / (2 * 0.5^2)) * exp(-g^2 / (2 * 0.125^2)),
  *              g = (c_i,z - e_i,z / 2) - (c_j,z + e_j,z / 2)
+ *   CLOSEST  = 1 / rank,  FARTHEST = 1 / (last rank - rank + 1): the rank of i
+ *              among the query's candidates by distance to j (see rank_value)
  * where (r_x, r_y) is the scene viewer's right vector, f = (-r_y, r_x) its
  * viewing direction and e the full box extents.  The temperatures
  * (0.1 m), the Gaussian's normalisation, the clamp at zero, the viewer
@@ -61,7 +63,7 @@
 #define ORACLE_NO_ID 0xFFFFFFFFu
 
 enum { P_NEAR = 0, P_ABOVE = 1, P_BELOW = 2, P_LEFT_OF = 3, P_RIGHT_OF = 4, P_NEXT_TO = 5, P_IN_FRONT_OF = 6,
-       P_BEHIND = 7, P_ON = 8, P_COUNT = 9 };
+       P_BEHIND = 7, P_ON = 8, P_CLOSEST = 9, P_FARTHEST = 10, P_COUNT = 11 };
 
 static double logistic(double u) { return 1.0 / (1.0 + exp(-u)); }
 
@@ -132,6 +134,7 @@ typedef struct {
     double* u;        /* [n][d] normalised descriptors */
     double* c;        /* [n][3] centers */
     double* e;        /* [n][3] full extents */
+    const float* cf;  /* [n][3] centers as given (FP32), for the rank predicates */
     const uint32_t* id;
     const int32_t* cls;
     double right[2];
@@ -150,6 +153,7 @@ static int scene_init(scene64* s, int64_t n, int d, const float* desc, const flo
         for (int k = 0; k < 3; ++k) s->c[i * 3 + k] = center[i * 3 + k];
         for (int k = 0; k < 3; ++k) s->e[i * 3 + k] = extent[i * 3 + k];
     }
+    s->cf = center;
     s->id = id;
     s->cls = cls;
     s->right[0] = right[0];
@@ -166,6 +170,7 @@ static void scene_free(scene64* s) {
 /* Per-query state: normalised target, anchor similarities per relation. */
 typedef struct {
     int r;                      /* number of relations */
+    int32_t tcls;               /* parsed target class (-1: none) */
     int pred[ORACLE_MAX_REL];
     double* sem;                /* [n]  s_sem(i) */
     double* asim;               /* [r][n] sim(j, q_r) */
@@ -176,6 +181,7 @@ static int query_init(query64* qs, const scene64* s, const float* target, int32_
     int64_t n = s->n;
     int d = s->d;
     qs->r = r;
+    qs->tcls = tcls;
     qs->sem = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     qs->asim = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * (size_t)(r > 0 ? r : 1));
     double* v = (double*)malloc(sizeof(double) * (size_t)d);
@@ -199,15 +205,55 @@ static void query_free(query64* qs) {
     free(qs->asim);
 }
 
+/* Closest / Farthest (Appendix "Retrieval Details": a rank within the
+ * candidate set, scored 1 / (|rank - r*| + 1)).  Readings: the candidate set C
+ * holds the objects of the query's parsed target class (every object when the
+ * query or the scene has no class); for target i and anchor j the rank is one
+ * plus the number of other candidates c (c != i, c != j) nearer to j than i,
+ * equal distances ordered by object id; r* = 1 for Closest and the last rank,
+ * |C minus i and j| + 1, for Farthest.  The rank is an integer decided by
+ * comparing distances, so it is decided in FP32 in one fixed order, the
+ * precision the GPU uses: ((dx*dx + dy*dy) + dz*dz) of FP32 center
+ * differences (this file is compiled without contraction). */
+static float dist2_f32(const float* c, int64_t a, int64_t b) {
+    float dx = c[a * 3] - c[b * 3];
+    float dy = c[a * 3 + 1] - c[b * 3 + 1];
+    float dz = c[a * 3 + 2] - c[b * 3 + 2];
+    float d2 = dx * dx;
+    d2 = d2 + dy * dy;
+    d2 = d2 + dz * dz;
+    return d2;
+}
+
+static int is_rank_pred(int p) { return p == P_CLOSEST || p == P_FARTHEST; }
+
+static double rank_value(const scene64* s, int32_t tcls, int p, int64_t i, int64_t j) {
+    float dij = dist2_f32(s->cf, i, j);
+    int64_t nearer = 0, m = 0;
+    for (int64_t c = 0; c < s->n; ++c) {
+        if (c == i || c == j) continue;
+        if (tcls >= 0 && s->cls && s->cls[c] != tcls) continue;
+        ++m;
+        float dc = dist2_f32(s->cf, c, j);
+        if (dc < dij || (dc == dij && s->id[c] < s->id[i])) ++nearer;
+    }
+    int64_t rank = nearer + 1;
+    int64_t rstar = p == P_CLOSEST ? 1 : m + 1;
+    int64_t off = rank > rstar ? rank - rstar : rstar - rank;
+    return 1.0 / (double)(off + 1);
+}
+
 /* t_r(i) and b_r(i): exhaustive maximum over anchors j != i. */
 static void relation_term(const scene64* s, const query64* qs, int rr, int64_t i, double* t, uint32_t* b) {
     double best = -1.0;
     uint32_t best_id = ORACLE_NO_ID;
     const double* a = qs->asim + (size_t)rr * s->n;
+    const int p = qs->pred[rr];
     for (int64_t j = 0; j < s->n; ++j) {
         if (j == i) continue;
-        double v = a[j] * oracle_predicate(qs->pred[rr], s->c + i * 3, s->c + j * 3, s->e + i * 3, s->e + j * 3,
-                                            s->right);
+        double v = a[j] * (is_rank_pred(p) ? rank_value(s, qs->tcls, p, i, j)
+                                           : oracle_predicate(p, s->c + i * 3, s->c + j * 3, s->e + i * 3,
+                                                              s->e + j * 3, s->right));
         if (v > best || (v == best && s->id[j] < best_id)) {
             best = v;
             best_id = s->id[j];
@@ -449,7 +495,7 @@ int farm_oracle_topk_bounded(int64_t n, int d, const float* desc, const float* c
  * an anchor chosen by another implementation attains the relation term.
  */
 double farm_oracle_binding_value(int64_t n, int d, const float* desc, const float* center, const float* extent,
-                                 const float* right,
+                                 const uint32_t* id, const int32_t* cls, const float* right, int32_t tcls,
                                  int p, const float* anchor, int64_t i, int64_t j) {
     if (i < 0 || j < 0 || i >= n || j >= n || p < 0 || p >= P_COUNT) return NAN;
     double* u = (double*)malloc(sizeof(double) * (size_t)d);
@@ -463,7 +509,18 @@ double farm_oracle_binding_value(int64_t n, int d, const float* desc, const floa
     double ei[3] = {extent[i * 3], extent[i * 3 + 1], extent[i * 3 + 2]};
     double ej[3] = {extent[j * 3], extent[j * 3 + 1], extent[j * 3 + 2]};
     double r[2] = {right[0], right[1]};
-    double val = a * oracle_predicate(p, ci, cj, ei, ej, r);
+    double val;
+    if (is_rank_pred(p)) {
+        scene64 s0;
+        memset(&s0, 0, sizeof(s0));
+        s0.n = n;
+        s0.cf = center;
+        s0.id = id;
+        s0.cls = cls;
+        val = a * rank_value(&s0, tcls, p, i, j);
+    } else {
+        val = a * oracle_predicate(p, ci, cj, ei, ej, r);
+    }
     free(u);
     free(v);
     return val;

@@ -27,9 +27,13 @@ import numpy as np
 # Predicate ids, in the order the C ABI uses.
 NEAR, ABOVE, BELOW, LEFT_OF, RIGHT_OF = 0, 1, 2, 3, 4
 NEXT_TO, IN_FRONT_OF, BEHIND, ON = 5, 6, 7, 8
-ALL_PREDS = tuple(range(9))
+CLOSEST, FARTHEST = 9, 10
+ALL_PREDS = tuple(range(9))                 # the pairwise predicates
+RANK_PREDS = (CLOSEST, FARTHEST)            # rank within the query's candidate set
+EVERY_PRED = ALL_PREDS + RANK_PREDS
 DEFAULT_PREDS = (NEAR, ABOVE, BELOW, LEFT_OF, RIGHT_OF)  # the pool query batches draw from by default
-PRED_NAMES = ("near", "above", "below", "left_of", "right_of", "next_to", "in_front_of", "behind", "on")
+PRED_NAMES = ("near", "above", "below", "left_of", "right_of", "next_to", "in_front_of", "behind", "on", "closest",
+              "farthest")
 
 
 @dataclasses.dataclass
@@ -184,8 +188,11 @@ def _plant_anchor(rng, scene: Scene, o: int, pred: int, c64: np.ndarray, r64: np
     d = c64 - c64[o]
     dist = np.sqrt((d * d).sum(axis=1))
     dist[o] = np.inf
-    if pred in (NEAR, NEXT_TO):
+    if pred in (NEAR, NEXT_TO, CLOSEST):
         ok = np.isfinite(dist)
+    elif pred == FARTHEST:
+        ok = np.isfinite(dist)
+        dist = np.where(ok, -dist, np.inf)  # the farthest object
     elif pred == ON:
         # the horizontally nearest object whose center lies at least 0.3 m lower
         ok = -d[:, 2] > 0.3

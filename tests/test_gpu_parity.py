@@ -49,7 +49,9 @@ def _check_full(farm, scene, qb, label):
                     continue
                 j = idx_of[int(b[r, i])]
                 assert j != i
-                v = oracle.binding_value(scene, int(qb.rel_pred[r]), qb.rel_anchor[r], int(i), j)
+                qq = int(np.searchsorted(qb.rel_off, r, side="right")) - 1
+                v = oracle.binding_value(scene, int(qb.rel_pred[r]), qb.rel_anchor[r], int(i), j,
+                                         int(qb.target_cls[qq]))
                 assert abs(v - t64[r, i]) <= REL * t64[r, i] + ABS, (label, r, i)
     return mem, ws, s64
 

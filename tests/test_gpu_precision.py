@@ -41,7 +41,7 @@ def _check_rows(scene, qb, rows, ids, sc, terms, anch, cert, oidx, osc, k):
         for e in range(R):
             j = idx_of[int(anch[row, rank, e])]
             v = oracle.binding_value(scene, int(qb.rel_pred[qb.rel_off[row] + e]), qb.rel_anchor[qb.rel_off[row] + e],
-                                     int(osel[m]), j)
+                                     int(osel[m]), j, int(qb.target_cls[row]))
             assert abs(v - pt[m, e]) <= REL * pt[m, e] + ABS
     n_cert = 0
     for i, row in enumerate(rows):

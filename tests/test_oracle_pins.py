@@ -14,7 +14,8 @@ import pytest
 
 import oracle
 from oracle.brute import brute_scores
-from synth import (ABOVE, ALL_PREDS, BEHIND, BELOW, IN_FRONT_OF, LEFT_OF, NEAR, NEXT_TO, ON, RIGHT_OF, CONFIGS,
+from synth import (ABOVE, ALL_PREDS, BEHIND, BELOW, CLOSEST, EVERY_PRED, FARTHEST, IN_FRONT_OF, LEFT_OF, NEAR,
+                   NEXT_TO, ON, RIGHT_OF, CONFIGS,
                    QueryBatch, Scene, make_queries, make_scene)
 from tests import _golden
 
@@ -169,6 +170,72 @@ def test_on_closed_form_gate_and_band():
         assert v == pytest.approx(gate * band, rel=1e-14, abs=1e-300)
 
 
+
+def _rank_scene():
+    """Three chairs (class 1) on the x axis at 1, 2 and 3 m from a package
+    (class 2) at the origin, a lamp (class 3) at 1.5 m, a fourth chair at
+    -2 m (as far from the package as the second chair, with a larger id)."""
+    d = 4
+    e = np.eye(d, dtype=np.float32)
+    desc = np.stack([e[0], e[0], e[0], e[1], e[2], e[0]])
+    center = np.array([[1, 0, 0], [2, 0, 0], [3, 0, 0], [0, 0, 0], [1.5, 0, 0], [-2, 0, 0]], np.float32)
+    scene = Scene(desc=desc, center=center, extent=np.full((6, 3), 0.5, np.float32),
+                  ids=np.array([10, 20, 30, 40, 50, 60], np.uint32), cls=np.array([1, 1, 1, 2, 3, 1], np.int32),
+                  view_right=np.array([1, 0], np.float32), centroids=np.zeros((1, d), np.float32))
+    return scene, e
+
+
+def _one_query(e, pred, tcls):
+    return QueryBatch(target=e[0][None], target_cls=np.array([tcls], np.int32), rel_off=np.array([0, 1], np.int32),
+                      rel_pred=np.array([pred], np.int32), rel_anchor=e[1][None], planted=np.zeros(1, np.int64))
+
+
+def test_closest_farthest_hand_scene():
+    """Closest / Farthest: 1 / (|rank - r*| + 1), the rank of the target among
+    the query's candidates (its class) by distance to the anchor; only the
+    package matches the anchor description, so t = P(chair, package)."""
+    scene, e = _rank_scene()
+    _, _, t, b = oracle.score(scene, _one_query(e, CLOSEST, 1), terms=True)
+    # chairs at 1, 2, 3 m and -2 m (same distance as 2 m, larger id: after it)
+    np.testing.assert_allclose(t[0, [0, 1, 2, 5]], [1.0, 1 / 2, 1 / 4, 1 / 3], rtol=0, atol=0)
+    assert set(b[0, [0, 1, 2, 5]]) == {40}
+    # Farthest: r* is the last rank among the other chairs (3 of them): 4
+    _, _, t, b = oracle.score(scene, _one_query(e, FARTHEST, 1), terms=True)
+    np.testing.assert_allclose(t[0, [0, 1, 2, 5]], [1 / 4, 1 / 3, 1.0, 1 / 2], rtol=0, atol=0)
+    # without a class every object is a candidate: the lamp (1.5 m) now precedes the 2 m chair
+    _, _, t, _ = oracle.score(scene, _one_query(e, CLOSEST, -1), terms=True)
+    np.testing.assert_allclose(t[0, [0, 1, 2, 5]], [1.0, 1 / 3, 1 / 5, 1 / 4], rtol=0, atol=0)
+    # the composite: s = s_sem (1/2 + t/2) with s_sem = 1 for every chair
+    s = oracle.score(scene, _one_query(e, CLOSEST, 1))
+    np.testing.assert_allclose(s[0, [0, 1, 2, 5]], [1.0, 0.75, 0.625, 2 / 3], rtol=1e-15)
+
+
+def test_rank_values_are_a_permutation():
+    """For one anchor, the Closest values over the candidates are 1, 1/2, ...,
+    1/|C| each once, and Farthest takes them in reverse order of distance."""
+    cfg = CONFIGS["mid"]
+    scene = make_scene(cfg, n=150, seed=41)
+    rng = np.random.default_rng(42)
+    for _ in range(6):
+        tc = int(scene.cls[rng.integers(0, scene.n)])
+        cand = np.flatnonzero(scene.cls == tc)
+        j = int(rng.integers(0, scene.n))
+        members = [int(c) for c in cand if c != j]
+        anchor = scene.desc[j]
+        vals_c, vals_f, dist = [], [], []
+        u = anchor.astype(np.float64) / np.linalg.norm(anchor.astype(np.float64))
+        a = float(u @ u)  # the anchor's own similarity (1 up to rounding)
+        for i in members:
+            vals_c.append(oracle.binding_value(scene, CLOSEST, anchor, i, j, tc) / a)
+            vals_f.append(oracle.binding_value(scene, FARTHEST, anchor, i, j, tc) / a)
+            dist.append(float(np.sum((scene.center[i].astype(np.float64) - scene.center[j]) ** 2)))
+        m = len(members)
+        np.testing.assert_allclose(sorted(vals_c, reverse=True), [1 / (k + 1) for k in range(m)], rtol=1e-12)
+        order = np.argsort(dist, kind="stable")
+        np.testing.assert_allclose(np.asarray(vals_c)[order], [1 / (k + 1) for k in range(m)], rtol=1e-12)
+        np.testing.assert_allclose(np.asarray(vals_f)[order], [1 / (m - k) for k in range(m)], rtol=1e-12)
+
+
 # ---------------------------------------------------------------- hand scenes
 @pytest.mark.parametrize("path", _golden.all_paths(), ids=lambda p: p.rsplit("/", 1)[-1])
 def test_golden_scenes(path):
@@ -237,7 +304,7 @@ def test_star_decomposition_equals_joint_enumeration(n, r):
 @pytest.mark.parametrize("n,r", [(2, 1), (5, 2), (7, 3)])
 def test_star_decomposition_all_predicates(n, r):
     for seed in range(3):
-        scene, qb = _tiny(seed * 17 + n * 5 + r, n, r, npred=len(ALL_PREDS))
+        scene, qb = _tiny(seed * 17 + n * 5 + r, n, r, npred=len(EVERY_PRED))
         s = oracle.score(scene, qb)
         bs = np.asarray(brute_scores(scene, qb))
         np.testing.assert_allclose(s, bs, rtol=1e-12, atol=1e-14)
