@@ -34,6 +34,15 @@
  *                    g = (c_i,z - e_i,z / 2) - (c_j,z + e_j,z / 2): the target's
  *                    bottom face minus the anchor's top face (e = full extents);
  *                    a horizontal gate times a vertical band
+ *   FARM_CLOSEST     1 / rank             FARM_FARTHEST  1 / (m + 2 - rank)
+ *                    rank of i among the query's candidates (objects of its
+ *                    target class; all objects without a class), by distance
+ *                    to j: 1 + #{c in C, c != i, j : |c_c - c_j| < |c_i - c_j|,
+ *                    equal distances by id}, m = |C minus i and j|; distances
+ *                    compared as FP32 ((dx*dx + dy*dy) + dz*dz).  A rank within
+ *                    the candidate set, scored 1 / (|rank - r*| + 1).  Cost
+ *                    O(N) per evaluated anchor: meant for small scenes or few
+ *                    such relations
  *
  * Conventions shared by every entry point:
  *   - Every function returns a farm_status; farm_last_error() gives a message
@@ -84,10 +93,12 @@ typedef enum {
   FARM_NEXT_TO = 5,
   FARM_IN_FRONT_OF = 6,
   FARM_BEHIND = 7,
-  FARM_ON = 8
+  FARM_ON = 8,
+  FARM_CLOSEST = 9,
+  FARM_FARTHEST = 10
 } farm_pred;
-#define FARM_NUM_PRED 9         /* predicate ids 0 .. FARM_NUM_PRED - 1 */
-#define FARM_NUM_PROP_PRED 9    /* predicates with learned anchor lists (network outputs): all */
+#define FARM_NUM_PRED 11        /* predicate ids 0 .. FARM_NUM_PRED - 1 */
+#define FARM_NUM_PROP_PRED 9    /* predicates with learned anchor lists (network outputs): 0 .. 8 */
 
 #define FARM_MAX_REL 8          /* relations per query */
 #define FARM_MAX_K 1024         /* TopK size */

@@ -170,7 +170,11 @@ farm_status stage_meta(farm_workspace* ws, int32_t q, int32_t R, const int32_t* 
   int32_t* rq = h + 2 * q + 1 + R;
   for (int32_t k = 0; k < q; ++k)
     for (int32_t r = rel_off[k]; r < rel_off[k + 1]; ++r) rq[r] = k;
-  size_t len = (size_t)(2 * q + 1 + 2 * R);
+  int32_t* rk = h + 2 * q + 1 + 2 * R;  // rows of the rank predicates
+  int32_t nrank = 0;
+  for (int32_t r = 0; r < R; ++r)
+    if (rel_pred[r] == FARM_CLOSEST || rel_pred[r] == FARM_FARTHEST) rk[nrank++] = r;
+  size_t len = (size_t)(2 * q + 1 + 2 * R + nrank);
   FARM_HIP(hipMemcpyAsync(ws->d_meta, h, len * sizeof(int32_t), hipMemcpyHostToDevice, s), "metadata copy");
   FARM_HIP(hipEventRecord(ws->meta_done, s), "metadata event");
   ws->meta_pending = true;
@@ -178,6 +182,8 @@ farm_status stage_meta(farm_workspace* ws, int32_t q, int32_t R, const int32_t* 
   view->rel_off = ws->d_meta + q;
   view->rel_pred = ws->d_meta + 2 * q + 1;
   view->rel_query = ws->d_meta + 2 * q + 1 + R;
+  view->rank_rows = ws->d_meta + 2 * q + 1 + 2 * R;
+  view->rank_n = nrank;
   return FARM_OK;
 }
 
@@ -438,7 +444,7 @@ farm_status farm_workspace_create(const farm_memory* mem, int32_t max_q, int32_t
     if ((mem->dn_bf16 || mem->dn_fp8) &&
         (st = dalloc(ws->allocs, ws->bytes, &ws->scores_hi, (size_t)max_q * ws->ld_s, "score bounds")))
       return fail(st);
-    ws->meta_len = 2 * (int64_t)max_q + 1 + 2 * (int64_t)max_rel;
+    ws->meta_len = 2 * (int64_t)max_q + 1 + 3 * (int64_t)max_rel;
     if ((st = dalloc(ws->allocs, ws->bytes, &ws->d_meta, (size_t)ws->meta_len, "metadata"))) return fail(st);
     if ((st = dalloc(ws->allocs, ws->bytes, &ws->status, 1, "status"))) return fail(st);
     ws->cand_cap = topk_candidate_capacity(mem->n, max_q, max_k + 1);

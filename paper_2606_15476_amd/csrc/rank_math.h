@@ -1,0 +1,105 @@
+// rank_math.h -- Closest / Farthest: a rank within the query's candidate set
+// (Appendix "Retrieval Details", predicate evaluation: score 1 / (|rank - r*| + 1)).
+//
+// The candidate set C holds the objects of the query's parsed target class
+// (every object when the query or the memory has no classes).  For target o
+// and anchor a, rank = 1 + the number of candidates c (c != o, c != a) nearer
+// to a than o, equal distances ordered by object id; r* = 1 for Closest and
+// the last rank, m + 1 with m = |C minus o and a|, for Farthest.  The rank is
+// an integer decided by distance comparisons, so it is decided in one fixed
+// FP32 order: ((dx*dx + dy*dy) + dz*dz) of FP32 center differences, without
+// contraction.
+//
+// The term t = max_{a != o} sim(a) * P(o, a) is taken by one wave: anchors
+// whose similarity (or its upper bound) is below the best value so far are
+// skipped, since P <= 1; the others get their rank from a wave-wide count
+// over the objects.  Cost: O(N) per anchor evaluated.
+#pragma once
+
+#include <math.h>
+
+#include "farm_internal.h"
+
+namespace farm {
+
+__device__ inline bool is_rank(int p) { return p == FARM_CLOSEST || p == FARM_FARTHEST; }
+
+struct RankCtx {
+  const float *x, *y, *z;
+  const uint32_t* ids;
+  const int32_t* cls;  // object classes, or null
+  int32_t tc;          // the query's parsed target class (-1: none)
+  int64_t n;
+  bool closest;
+};
+
+__device__ inline float rank_d2(float ax, float ay, float az, float bx, float by, float bz) {
+#pragma clang fp contract(off)
+  const float dx = ax - bx, dy = ay - by, dz = az - bz;
+  float s = dx * dx;
+  s = s + dy * dy;
+  s = s + dz * dz;
+  return s;
+}
+
+__device__ inline int wave_sum_i(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// P(o, a) by one wave (every lane returns the same value).
+__device__ inline float rank_pred_wave(const RankCtx& k, int64_t o, int64_t a, int lane) {
+  const float ax = k.x[a], ay = k.y[a], az = k.z[a];
+  const float doa = rank_d2(k.x[o], k.y[o], k.z[o], ax, ay, az);
+  const uint32_t ido = k.ids[o];
+  const bool filter = k.tc >= 0 && k.cls != nullptr;
+  int nearer = 0, m = 0;
+  for (int64_t c = lane; c < k.n; c += 64) {
+    if (c == o || c == a) continue;
+    if (filter && k.cls[c] != k.tc) continue;
+    ++m;
+    const float dc = rank_d2(k.x[c], k.y[c], k.z[c], ax, ay, az);
+    nearer += (dc < doa || (dc == doa && k.ids[c] < ido)) ? 1 : 0;
+  }
+  nearer = wave_sum_i(nearer);
+  m = wave_sum_i(m);
+  const int rank = nearer + 1;
+  const int rstar = k.closest ? 1 : m + 1;
+  const int off = rank > rstar ? rank - rstar : rstar - rank;
+  return 1.0f / (float)(off + 1);
+}
+
+// t and the binding anchor's id for target o by one wave.  hi_of(a): an upper
+// bound of sim(a) (lane-local); exact_of(a): sim(a), called by the whole wave
+// with a uniform a (it may be a wave-wide dot product).  best is -1 when no
+// anchor exists (n = 1); the caller clamps.
+template <class HiOf, class ExactOf>
+__device__ void rank_term_wave(const RankCtx& k, int64_t o, int lane, HiOf hi_of, ExactOf exact_of, float& out_best,
+                               uint32_t& out_bid) {
+  float best = -1.0f;
+  uint32_t bid = FARM_NO_ID;
+  for (int64_t a0 = 0; a0 < k.n; a0 += 64) {
+    const int64_t a = a0 + lane;
+    const float h = (a < k.n && a != o) ? hi_of(a) : -INFINITY;
+    uint64_t mask = __ballot(h >= best);
+    while (mask) {
+      const int src = __ffsll((unsigned long long)mask) - 1;
+      mask &= mask - 1;
+      if (__shfl(h, src) < best) continue;  // the best grew meanwhile
+      const int64_t aa = a0 + src;
+      const float s = exact_of(aa);
+      if (s < best) continue;
+      const float v = s * rank_pred_wave(k, o, aa, lane);
+      const uint32_t ida = k.ids[aa];
+      if (v > best || (v == best && ida < bid)) {
+        best = v;
+        bid = ida;
+      }
+    }
+  }
+  out_best = best;
+  out_bid = bid;
+}
+
+}  // namespace farm

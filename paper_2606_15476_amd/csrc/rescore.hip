@@ -32,6 +32,7 @@
 
 #include "farm_internal.h"
 #include "pair_math.h"
+#include "rank_math.h"
 #include "sort_util.h"
 
 namespace farm {
@@ -173,7 +174,8 @@ __device__ inline float wave_max_f(float v) {
 struct Geo {
   const float *x, *y, *z, *za, *hhi, *hlo;  // hhi/hlo: [2][n], lateral then depth pairs
   const uint32_t* ids;
-  const float* vz;  // [2][n]: 4 * bottom face, 4 * top face (On)
+  const float* vz;     // [2][n]: 4 * bottom face, 4 * top face (On)
+  const int32_t* cls;  // object classes or null (the candidate set of Closest/Farthest)
 };
 
 // The coordinates predicate p uses: InFrontOf/Behind take the depth pair
@@ -562,6 +564,28 @@ constexpr int kTermBlocksX = 8;  // blocks per query: 32 waves sweep a query's t
 
 enum { kTermsFull = 0, kTermsSubset = 1, kTermsFallback = 2 };
 
+// Closest/Farthest term of target o by one wave (rank_math.h).  Reduced
+// precision: an anchor whose upper bound (BF16/FP8 value + error bound)
+// reaches the best value so far gets its exact FP32 similarity (wave dot).
+__device__ inline void rank_term(const Geo& g, int32_t tc, int p, const float* __restrict__ arow,
+                                 const float* __restrict__ qrow, const float* __restrict__ dn, int32_t ldk, int64_t n,
+                                 int64_t o, bool bounded, float qnr, float qer, const float* __restrict__ o_err,
+                                 int lane, float& best, uint32_t& bid, uint32_t& dots) {
+  const RankCtx k{g.x, g.y, g.z, g.ids, g.cls, tc, n, p == FARM_CLOSEST};
+  if (!bounded) {
+    rank_term_wave(
+        k, o, lane, [&](int64_t a) { return arow[a]; }, [&](int64_t a) { return arow[a]; }, best, bid);
+  } else {
+    rank_term_wave(
+        k, o, lane, [&](int64_t a) { return arow[a] + fmaf(qnr, o_err[a], qer); },
+        [&](int64_t a) {
+          ++dots;
+          return fmaxf(0.f, wave_dot(qrow, dn + a * ldk, ldk, lane));
+        },
+        best, bid);
+  }
+}
+
 // One wave per (candidate, relation) term.  Writes the family-domain maximum
 // (Near: log of the term; others: the term) into rs_terms and the bound
 // anchor into rs_anchor; k_rescore_combine turns them into scores.
@@ -608,6 +632,9 @@ __global__ __launch_bounds__(64 * kTermWaves) void k_rescore_terms(
     const float qer = bounded ? bound.q_err[q + r] + bound.acc : 0.f;
     float best;
     uint32_t bid;
+    if (is_rank(p)) {
+      rank_term(gp, meta.tcls[qq], p, arow, qrow, dn, ldk, n, o, bounded, qnr, qer, bound.o_err, lane, best, bid, dots);
+    } else
     switch (family_of(p)) {
       case kFamNear:
         full_term<kFamNear>(arow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, gp, lane, sidx, sn, ssim,
@@ -1172,8 +1199,13 @@ __global__ __launch_bounds__(kFbThreads) void k_rescore_fallback(
     const int32_t* sidx = pv.sem_idx + (int64_t)r * kSemMax;
     const int sn = pv.sem_cnt[r];
     const float* ssim = pv.sem_sim ? pv.sem_sim + (int64_t)r * kSemMax : nullptr;
-    float best;
-    uint32_t bid;
+    float best = 0.f;
+    uint32_t bid = FARM_NO_ID;
+    if (is_rank(p)) {  // one wave takes the term
+      if (threadIdx.x < 64)
+        rank_term(gp, meta.tcls[qq], p, arow, qrow, dn, ldk, n, o, BOUNDED, qnr, qer, bound.o_err, (int)threadIdx.x,
+                  best, bid, dots);
+    } else
     switch (family_of(p)) {
       case kFamNear:
         full_term_block<kFamNear, BOUNDED>(arow, qrow, dn, ldk, n, o, c, qnr, qer, bound.o_err, gp, sidx, sn, ssim, sv,
@@ -1410,7 +1442,7 @@ hipError_t launch_rescore_terms(const farm_memory* mem, const farm_workspace* ws
                                 const int32_t* cand_count, int32_t c, const PropView& prop, bool fallback_pass,
                                 hipStream_t s) {
   if (q <= 0 || c <= 0) return hipSuccess;
-  const Geo g{mem->x, mem->y, mem->z, mem->z, mem->hr_hi, mem->hr_lo, mem->id, mem->vz};
+  const Geo g{mem->x, mem->y, mem->z, mem->z, mem->hr_hi, mem->hr_lo, mem->id, mem->vz, mem->cls};
   const dim3 grid(kTermBlocksX, (unsigned)q), block(64 * kTermWaves);
 #define FARM_TERMS(MODE, B)                                                                                      \
   hipLaunchKernelGGL((k_rescore_terms<MODE, B>), grid, block, 0, s, sim, ld_s, q, meta, bound, ws->qn, mem->dn, \

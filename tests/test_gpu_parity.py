@@ -132,6 +132,54 @@ def test_all_predicates_full_parity(farm):
     _topk_against_full(farm, mem, ws, scene, qb, s64, cfg.k, "mid/all predicates")
 
 
+def _rank_world(seed, n=700, q=24):
+    """A mid-config scene and queries drawing from every predicate, Closest and
+    Farthest included; every third query has no class (every object is then a
+    candidate of the rank predicates)."""
+    import synth
+    cfg = CONFIGS["mid"]
+    scene = make_scene(cfg, n=n, seed=seed)
+    qb = make_queries(cfg, scene, seed=seed + 1, q=q, preds=synth.EVERY_PRED)
+    qb.target_cls[::3] = -1
+    assert set(synth.RANK_PREDS) <= set(np.unique(qb.rel_pred).tolist())
+    return cfg, scene, qb
+
+
+def test_rank_predicates_full_parity(farm):
+    """Closest/Farthest (rank within the candidate set) beside the pairwise
+    predicates, exhaustive FP32 method: full score matrix, per-relation terms
+    and bindings, TopK and breakdown against the oracle."""
+    cfg, scene, qb = _rank_world(31)
+    mem, ws, s64 = _check_full(farm, scene, qb, "rank predicates")
+    _topk_against_full(farm, mem, ws, scene, qb, s64, cfg.k, "rank predicates")
+
+
+@pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "bf16"])
+def test_rank_predicates_bounded_and_precision(farm, dtype):
+    """The bound-pruned method (FP32 and BF16 similarities) and the BF16
+    exhaustive precision form with Closest/Farthest: certified, the oracle's
+    exact TopK; FP32 bound-pruned equals the exhaustive FP32 path bit for bit."""
+    from tests import _gpu
+    cfg, scene, qb = _rank_world(33)
+    mem = _gpu.build_memory(scene, flags=farm.FARM_BUILD_BF16)
+    ws = _ws(farm, mem, qb)
+    oidx, osc, ot, ob, ns = oracle.topk_bounded(scene, qb, cfg.k + 8)
+    bd = _gpu.query_topk(mem, ws, qb, cfg.k, dtype=dtype, with_cert=True, method=farm.BOUNDED)
+    assert np.all(bd[4] == 1)
+    _check_bounded(scene, qb, bd[0], bd[1], oidx, osc, cfg.k)
+    ex = _gpu.query_topk(mem, ws, qb, cfg.k, dtype=dtype, with_cert=True, method=farm.EXHAUSTIVE)
+    # the precision form certifies a query when its rescored set provably holds
+    # the TopK; the rank terms' ladder of values 1/k can leave a query without
+    # that proof (flagged, not wrong): certified queries must be exact
+    cert_rows = [qq for qq in range(qb.q) if ex[4][qq] == 1]
+    assert len(cert_rows) >= qb.q - 3, ex[4]
+    _check_bounded(scene, qb, ex[0], ex[1], oidx[cert_rows], osc[cert_rows], cfg.k, rows=cert_rows)
+    if dtype == 0:
+        assert len(cert_rows) == qb.q
+        for a, b in zip(bd[:4], ex[:4]):
+            np.testing.assert_array_equal(a, b)
+
+
 def test_mid_config_topk_all_queries(farm):
     from tests import _gpu
     cfg = CONFIGS["mid"]

@@ -140,6 +140,27 @@ def test_all_predicates(farm, dtype):
     assert checked > 0 and fell < checked
 
 
+@pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "bf16"])
+def test_rank_predicates(farm, dtype):
+    """Closest/Farthest have no lists: every such term takes the full-scan
+    fallback (LDS-staged and global-memory forms of the pass); results stay
+    bit-identical to BOUNDED, which equals the exact TopK."""
+    from tests import _gpu
+    from tests.test_gpu_parity import _check_bounded, _rank_world
+    cfg, scene, qb = _rank_world(35)
+    mem = _gpu.build_memory(scene, flags=farm.FARM_BUILD_BF16)
+    ws = farm.Workspace(mem, qb.q, qb.r_tot, 64)
+    net = farm.ProposalNet(scene.d, max_batch=4096, seed=5)
+    farm.build_proposals(mem, net, 64)
+    checked, fell = _compare(farm, mem, ws, qb, cfg.k, dtype)
+    ids, sc, _, _, cert = _gpu.query_topk(mem, ws, qb, cfg.k, dtype=dtype, with_cert=True, method=farm.BOUNDED)
+    assert np.all(cert == 1)
+    oidx, osc, ot, ob, ns = oracle.topk_bounded(scene, qb, cfg.k + 8)
+    _check_bounded(scene, qb, ids, sc, oidx, osc, cfg.k)
+    print(f"[proposal rank predicates dtype={dtype}] terms {checked}, fell back {fell}", flush=True)
+    assert checked > 0 and fell > 0
+
+
 def test_proposal_equals_bounded_full_size(farm):
     from tests import _gpu
     cfg = CONFIGS["precision"]
