@@ -45,6 +45,14 @@ PEAK_MFMA_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
 # 1/(2 sigma^2), exp, 1 + e, reciprocal, times the anchor similarity, max);
 # a transcendental counts as one operation.
 FLOP_PER_PAIR = {0: 12, 1: 7, 2: 7, 3: 11, 4: 11, 5: 12, 6: 11, 7: 11, 8: 12}
+# Closest/Farthest (9, 10) have no fixed cost per pair (a count over the query's
+# candidate set): their relations are left out of the ALU counts below.
+
+
+def pred_pool(args):
+    """Predicate ids the benchmark's queries draw from (None: the generator's default five)."""
+    from synth import ALL_PREDS, EVERY_PRED
+    return {"five": None, "all": ALL_PREDS, "every": EVERY_PRED}[args.preds]
 
 
 def log(msg):
@@ -81,9 +89,9 @@ def parse():
     p.add_argument("--train-steps", type=int, default=600)
     p.add_argument("--list-m", type=int, default=256, help="anchors per (object, predicate) list")
     p.add_argument("--k", type=int, default=10)
-    p.add_argument("--preds", default="five", choices=["five", "all"],
-                   help="predicates the queries draw from: the workload's five (Near..RightOf) or all nine "
-                        "(+ NextTo, InFrontOf, Behind, On)")
+    p.add_argument("--preds", default="five", choices=["five", "all", "every"],
+                   help="predicates the queries draw from: the workload's five (Near..RightOf), all nine pairwise "
+                        "ones (+ NextTo, InFrontOf, Behind, On) or every one (+ Closest, Farthest)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=0, help="queries in the CPU-oracle sample (0 = auto)")
     p.add_argument("--serving", action="store_true",
@@ -133,7 +141,7 @@ def main():
     cfg = CONFIGS[args.workload]
     t0 = time.time()
     scene = make_scene(cfg)
-    qb = make_queries(cfg, scene, preds=None if args.preds == "five" else ALL_PREDS)
+    qb = make_queries(cfg, scene, preds=pred_pool(args))
     log(f"[bench] generated {cfg.name}: n={scene.n} d={scene.d} q={qb.q} R={qb.r_tot} in {time.time() - t0:.1f}s")
 
     dev = torch.device("cuda:0")
@@ -234,7 +242,8 @@ def main():
         "config": {"workload": f"{cfg.name}: N={scene.n} objects, D={scene.d}, Q={qb.q} queries, "
                                f"R~U{{{cfg.r_min}..{cfg.r_max}}} (R_tot={qb.r_tot}), K={k}",
                    "form": args.form, "method": args.method, "global_batch": qb.q, "parallelism": "none (1 GPU)",
-                   "predicates": "Near, Above, Below, LeftOf, RightOf" if args.preds == "five" else "all nine"},
+                   "predicates": {"five": "Near, Above, Below, LeftOf, RightOf", "all": "all nine pairwise",
+                                  "every": "all eleven (pairwise + Closest, Farthest)"}[args.preds]},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
                        "what": "whole-batch latency of one step"},
         "phase_ms": phase_ms,
@@ -387,7 +396,7 @@ def train_network(farm, cfg, args):
     for i in range(args.train_scenes):
         seed = 1000 + i
         sc = make_scene(cfg, seed=seed)
-        qt = make_queries(cfg, sc, seed=seed, q=256, preds=None if args.preds == "five" else ALL_PREDS)
+        qt = make_queries(cfg, sc, seed=seed, q=256, preds=pred_pool(args))
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
         m = farm.Memory(t(sc.desc), t(sc.center), t(sc.extent), t(sc.ids.view(np.int32)), t(sc.cls), sc.view_right)
         w = farm.Workspace(m, qt.q, qt.r_tot, 16)
@@ -433,7 +442,7 @@ def dominant_roofline(phases, scene, qb, args, cfg, proposal_info):
     ms, launches = timed[dominant]
     avg_s = ms / launches / 1e3
     if dominant == "pair":
-        flop = sum(FLOP_PER_PAIR[int(p)] for p in qb.rel_pred) * float(n) * (n - 1)
+        flop = sum(FLOP_PER_PAIR.get(int(p), 0) for p in qb.rel_pred) * float(n) * (n - 1)
         achieved = flop / avg_s / 1e12
         return {"bound": "alu", "kernel": "k_pair_exhaustive", "achieved": round(achieved, 3),
                 "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
@@ -478,7 +487,8 @@ def dominant_roofline(phases, scene, qb, args, cfg, proposal_info):
                 "algorithmic_bytes_per_launch": nbytes}
     # full anchor scans of candidate terms (the fallback of the proposal method, or every
     # candidate term of the bound-pruned method): pair evaluations on the ALU
-    per_pair = float(np.mean([FLOP_PER_PAIR[int(p)] for p in qb.rel_pred])) if R else 0.0
+    pairwise = [FLOP_PER_PAIR[int(p)] for p in qb.rel_pred if int(p) in FLOP_PER_PAIR]
+    per_pair = float(np.mean(pairwise)) if pairwise else 0.0
     if dominant == "fallback":
         n_terms, kernel = float(info.get("fallback_rate", 0.0) * terms), "k_rescore_fallback"
     else:

@@ -354,6 +354,23 @@ farm_status farm_build_memory(int64_t n, int32_t d, const float* desc, const flo
       return fail_tmp(hip_fail(e, "read flags"));
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail_tmp(hip_fail(e, "build synchronize"));
     free_all(tmp);
+    if (!h_flags && cls && n > 0) {
+      // class order (host sort of n ints, once per memory)
+      std::vector<int32_t> hc((size_t)n), order((size_t)n);
+      if ((e = hipMemcpy(hc.data(), mem->cls, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost)) != hipSuccess)
+        return fail(hip_fail(e, "read classes"));
+      for (int64_t i = 0; i < n; ++i) order[(size_t)i] = (int32_t)i;
+      std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return hc[a] < hc[b]; });
+      std::vector<int32_t> sorted((size_t)n);
+      for (int64_t i = 0; i < n; ++i) sorted[(size_t)i] = hc[order[(size_t)i]];
+      if ((st = dalloc(mem->allocs, mem->bytes, &mem->cls_order, nn, "class order"))) return fail(st);
+      if ((st = dalloc(mem->allocs, mem->bytes, &mem->cls_sorted, nn, "sorted classes"))) return fail(st);
+      if ((e = hipMemcpy(mem->cls_order, order.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice)) !=
+              hipSuccess ||
+          (e = hipMemcpy(mem->cls_sorted, sorted.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice)) !=
+              hipSuccess)
+        return fail(hip_fail(e, "class order"));
+    }
     if (h_flags) {
       set_error("invalid scene:%s%s%s%s%s%s", (h_flags & kBadDesc) ? " non-finite descriptor;" : "",
                 (h_flags & kZeroNorm) ? " zero-norm descriptor;" : "",

@@ -76,6 +76,10 @@ struct farm_memory {
   float* vz = nullptr;
   uint32_t* id = nullptr;
   int32_t* cls = nullptr;
+  // objects ordered by class (stable): indices and their classes, so that the
+  // candidate set of Closest/Farthest (one class) is a contiguous range
+  int32_t* cls_order = nullptr;
+  int32_t* cls_sorted = nullptr;
   // learned anchor proposals (farm_build_proposals): per predicate p and
   // target o a list of M anchors (target-major: one target's list is contiguous)
   int32_t prop_m = 0;

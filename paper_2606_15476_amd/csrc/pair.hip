@@ -105,14 +105,15 @@ constexpr int kRankWaves = 4;
 __global__ __launch_bounds__(64 * kRankWaves) void k_rank_rows(
     const float* __restrict__ sim, float* __restrict__ lsim, int64_t ld_s, int32_t q, MetaView meta,
     const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
-    const uint32_t* __restrict__ ids, const int32_t* __restrict__ cls, int64_t n, float* __restrict__ rel_terms,
+    const uint32_t* __restrict__ ids, const int32_t* __restrict__ cls, const int32_t* __restrict__ cls_order,
+    const int32_t* __restrict__ cls_sorted, int64_t n, float* __restrict__ rel_terms,
     uint32_t* __restrict__ rel_anchor_id) {
   const int lane = threadIdx.x & 63;
   const int64_t o = (int64_t)blockIdx.x * kRankWaves + (threadIdx.x >> 6);
   if (o >= n) return;  // whole waves leave together
   const int r = meta.rank_rows[blockIdx.y];
   const int qq = meta.rel_query[r];
-  const RankCtx k{x, y, z, ids, cls, meta.tcls[qq], n, meta.rel_pred[r] == FARM_CLOSEST};
+  const RankCtx k{x, y, z, ids, cls, cls_order, cls_sorted, meta.tcls[qq], n, meta.rel_pred[r] == FARM_CLOSEST};
   const float* arow = sim + (int64_t)(q + r) * ld_s;
   float best;
   uint32_t bid;
@@ -282,6 +283,8 @@ __global__ __launch_bounds__(256) void k_explain(const float* __restrict__ sim, 
                                                  const float* __restrict__ hhi,
                                                  const float* __restrict__ hlo, const uint32_t* __restrict__ ids,
                                                  const int32_t* __restrict__ cls,
+                                                 const int32_t* __restrict__ cls_order,
+                                                 const int32_t* __restrict__ cls_sorted,
                                                  int64_t n, float* __restrict__ out_terms,
                                                  uint32_t* __restrict__ out_anchor_id) {
   __shared__ float red_v[256];
@@ -303,7 +306,7 @@ __global__ __launch_bounds__(256) void k_explain(const float* __restrict__ sim, 
       const ZPair zp = z_for(p, z, vz, n);  // On: bottom/top faces
       if (is_rank(p)) {
         // every wave takes the same term (identical arithmetic); thread 0 stores it
-        const RankCtx rk{x, y, z, ids, cls, meta.tcls[qq], n, p == FARM_CLOSEST};
+        const RankCtx rk{x, y, z, ids, cls, cls_order, cls_sorted, meta.tcls[qq], n, p == FARM_CLOSEST};
         float bv;
         rank_term_wave(
             rk, i, (int)(threadIdx.x & 63), [&](int64_t a) { return arow[a]; }, [&](int64_t a) { return arow[a]; },
@@ -347,7 +350,7 @@ hipError_t launch_pair_exhaustive(const farm_memory* mem, const float* sim, cons
   if (meta.rank_n > 0) {
     hipLaunchKernelGGL(k_rank_rows, dim3((unsigned)((n + kRankWaves - 1) / kRankWaves), (unsigned)meta.rank_n),
                        dim3(64 * kRankWaves), 0, s, sim, const_cast<float*>(lsim), ld_s, q, meta, mem->x, mem->y, mem->z,
-                       mem->id, mem->cls, n, rel_terms, rel_anchor_id);
+                       mem->id, mem->cls, mem->cls_order, mem->cls_sorted, n, rel_terms, rel_anchor_id);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -368,7 +371,8 @@ hipError_t launch_explain(const farm_memory* mem, const float* sim, int64_t ld_s
   if (q <= 0 || k <= 0 || (!out_terms && !out_anchor_id)) return hipSuccess;
   dim3 grid((unsigned)k, (unsigned)q);
   hipLaunchKernelGGL(k_explain, grid, dim3(256), 0, s, sim, ld_s, q, meta, idx, k, mem->x, mem->y, mem->z, mem->vz,
-                     mem->hr_hi, mem->hr_lo, mem->id, mem->cls, mem->n, out_terms, out_anchor_id);
+                     mem->hr_hi, mem->hr_lo, mem->id, mem->cls, mem->cls_order, mem->cls_sorted, mem->n, out_terms,
+                     out_anchor_id);
   return hipGetLastError();
 }
 

@@ -13,7 +13,9 @@
 // The term t = max_{a != o} sim(a) * P(o, a) is taken by one wave: anchors
 // whose similarity (or its upper bound) is below the best value so far are
 // skipped, since P <= 1; the others get their rank from a wave-wide count
-// over the objects.  Cost: O(N) per anchor evaluated.
+// over the candidates.  With a class, the candidates are a contiguous range of
+// the memory's class order (found by binary search once per term), so an
+// anchor costs O(|C|); without one, O(N).
 #pragma once
 
 #include <math.h>
@@ -27,11 +29,31 @@ __device__ inline bool is_rank(int p) { return p == FARM_CLOSEST || p == FARM_FA
 struct RankCtx {
   const float *x, *y, *z;
   const uint32_t* ids;
-  const int32_t* cls;  // object classes, or null
-  int32_t tc;          // the query's parsed target class (-1: none)
+  const int32_t* cls;         // object classes, or null
+  const int32_t* cls_order;   // objects in class order (null without classes)
+  const int32_t* cls_sorted;  // their classes, ascending
+  int32_t tc;                 // the query's parsed target class (-1: none)
   int64_t n;
   bool closest;
+  int64_t lo = 0, hi = -1;    // the class's range in cls_order (hi < 0: every object is a candidate)
 };
+
+// The candidates' range in the class order: [lower_bound, upper_bound) of tc.
+__device__ inline void rank_range(RankCtx& k) {
+  if (k.tc < 0 || k.cls == nullptr || k.cls_order == nullptr) return;
+  int64_t a = 0, b = k.n;
+  while (a < b) {
+    const int64_t mid = (a + b) >> 1;
+    if (k.cls_sorted[mid] < k.tc) a = mid + 1; else b = mid;
+  }
+  int64_t c = a, d = k.n;
+  while (c < d) {
+    const int64_t mid = (c + d) >> 1;
+    if (k.cls_sorted[mid] <= k.tc) c = mid + 1; else d = mid;
+  }
+  k.lo = a;
+  k.hi = c;
+}
 
 __device__ inline float rank_d2(float ax, float ay, float az, float bx, float by, float bz) {
 #pragma clang fp contract(off)
@@ -53,14 +75,19 @@ __device__ inline float rank_pred_wave(const RankCtx& k, int64_t o, int64_t a, i
   const float ax = k.x[a], ay = k.y[a], az = k.z[a];
   const float doa = rank_d2(k.x[o], k.y[o], k.z[o], ax, ay, az);
   const uint32_t ido = k.ids[o];
-  const bool filter = k.tc >= 0 && k.cls != nullptr;
   int nearer = 0, m = 0;
-  for (int64_t c = lane; c < k.n; c += 64) {
-    if (c == o || c == a) continue;
-    if (filter && k.cls[c] != k.tc) continue;
+  auto count = [&](int64_t c) {
+    if (c == o || c == a) return;
     ++m;
     const float dc = rank_d2(k.x[c], k.y[c], k.z[c], ax, ay, az);
     nearer += (dc < doa || (dc == doa && k.ids[c] < ido)) ? 1 : 0;
+  };
+  if (k.hi >= 0) {
+    for (int64_t e = k.lo + lane; e < k.hi; e += 64) count(k.cls_order[e]);
+  } else {
+    const bool filter = k.tc >= 0 && k.cls != nullptr;
+    for (int64_t c = lane; c < k.n; c += 64)
+      if (!filter || k.cls[c] == k.tc) count(c);
   }
   nearer = wave_sum_i(nearer);
   m = wave_sum_i(m);
@@ -72,13 +99,38 @@ __device__ inline float rank_pred_wave(const RankCtx& k, int64_t o, int64_t a, i
 
 // t and the binding anchor's id for target o by one wave.  hi_of(a): an upper
 // bound of sim(a) (lane-local); exact_of(a): sim(a), called by the whole wave
-// with a uniform a (it may be a wave-wide dot product).  best is -1 when no
-// anchor exists (n = 1); the caller clamps.
+// with a uniform a (it may be a wave-wide dot product).  Optionally the
+// relation's semantic set (sidx, sn: the anchors of largest similarity) goes
+// first; when the best value then exceeds out_bound, a bound on the
+// similarity of every other anchor, no other anchor can reach it (P <= 1) and
+// the scan ends there.  best is -1 when no anchor exists (n = 1); the caller
+// clamps.
 template <class HiOf, class ExactOf>
-__device__ void rank_term_wave(const RankCtx& k, int64_t o, int lane, HiOf hi_of, ExactOf exact_of, float& out_best,
-                               uint32_t& out_bid) {
+__device__ void rank_term_wave(RankCtx k, int64_t o, int lane, HiOf hi_of, ExactOf exact_of, float& out_best,
+                               uint32_t& out_bid, const int32_t* sidx = nullptr, int sn = 0,
+                               float out_bound = INFINITY) {
+  rank_range(k);
   float best = -1.0f;
   uint32_t bid = FARM_NO_ID;
+  auto visit = [&](int64_t aa) {
+    const float s = exact_of(aa);
+    if (s < best) return;
+    const float v = s * rank_pred_wave(k, o, aa, lane);
+    const uint32_t ida = k.ids[aa];
+    if (v > best || (v == best && ida < bid)) {
+      best = v;
+      bid = ida;
+    }
+  };
+  for (int e = 0; e < sn; ++e) {
+    const int64_t aa = __builtin_amdgcn_readfirstlane(sidx[e]);
+    if (aa != o) visit(aa);
+  }
+  if (sn > 0 && best > out_bound) {
+    out_best = best;
+    out_bid = bid;
+    return;
+  }
   for (int64_t a0 = 0; a0 < k.n; a0 += 64) {
     const int64_t a = a0 + lane;
     const float h = (a < k.n && a != o) ? hi_of(a) : -INFINITY;
@@ -87,15 +139,7 @@ __device__ void rank_term_wave(const RankCtx& k, int64_t o, int lane, HiOf hi_of
       const int src = __ffsll((unsigned long long)mask) - 1;
       mask &= mask - 1;
       if (__shfl(h, src) < best) continue;  // the best grew meanwhile
-      const int64_t aa = a0 + src;
-      const float s = exact_of(aa);
-      if (s < best) continue;
-      const float v = s * rank_pred_wave(k, o, aa, lane);
-      const uint32_t ida = k.ids[aa];
-      if (v > best || (v == best && ida < bid)) {
-        best = v;
-        bid = ida;
-      }
+      visit(a0 + src);
     }
   }
   out_best = best;

@@ -176,6 +176,7 @@ struct Geo {
   const uint32_t* ids;
   const float* vz;     // [2][n]: 4 * bottom face, 4 * top face (On)
   const int32_t* cls;  // object classes or null (the candidate set of Closest/Farthest)
+  const int32_t *cls_order, *cls_sorted;  // objects in class order, their classes
 };
 
 // The coordinates predicate p uses: InFrontOf/Behind take the depth pair
@@ -567,14 +568,19 @@ enum { kTermsFull = 0, kTermsSubset = 1, kTermsFallback = 2 };
 // Closest/Farthest term of target o by one wave (rank_math.h).  Reduced
 // precision: an anchor whose upper bound (BF16/FP8 value + error bound)
 // reaches the best value so far gets its exact FP32 similarity (wave dot).
+// With the relation's semantic set (sidx, sn) and tau, the largest similarity
+// outside it (plus the error bound for reduced precision), the set goes first
+// and ends the scan when it certifies the term.
 __device__ inline void rank_term(const Geo& g, int32_t tc, int p, const float* __restrict__ arow,
                                  const float* __restrict__ qrow, const float* __restrict__ dn, int32_t ldk, int64_t n,
                                  int64_t o, bool bounded, float qnr, float qer, const float* __restrict__ o_err,
-                                 int lane, float& best, uint32_t& bid, uint32_t& dots) {
-  const RankCtx k{g.x, g.y, g.z, g.ids, g.cls, tc, n, p == FARM_CLOSEST};
+                                 int lane, float& best, uint32_t& bid, uint32_t& dots,
+                                 const int32_t* __restrict__ sidx = nullptr, int sn = 0, float tau = INFINITY) {
+  const RankCtx k{g.x, g.y, g.z, g.ids, g.cls, g.cls_order, g.cls_sorted, tc, n, p == FARM_CLOSEST};
   if (!bounded) {
     rank_term_wave(
-        k, o, lane, [&](int64_t a) { return arow[a]; }, [&](int64_t a) { return arow[a]; }, best, bid);
+        k, o, lane, [&](int64_t a) { return arow[a]; }, [&](int64_t a) { return arow[a]; }, best, bid, sidx, sn,
+        tau);
   } else {
     rank_term_wave(
         k, o, lane, [&](int64_t a) { return arow[a] + fmaf(qnr, o_err[a], qer); },
@@ -582,7 +588,7 @@ __device__ inline void rank_term(const Geo& g, int32_t tc, int p, const float* _
           ++dots;
           return fmaxf(0.f, wave_dot(qrow, dn + a * ldk, ldk, lane));
         },
-        best, bid);
+        best, bid, sidx, sn, tau);
   }
 }
 
@@ -633,7 +639,10 @@ __global__ __launch_bounds__(64 * kTermWaves) void k_rescore_terms(
     float best;
     uint32_t bid;
     if (is_rank(p)) {
-      rank_term(gp, meta.tcls[qq], p, arow, qrow, dn, ldk, n, o, bounded, qnr, qer, bound.o_err, lane, best, bid, dots);
+      // with a semantic set (proposal fallback) the set goes first and may certify the term
+      const float tau = sidx ? pv.sem_tau[r] + (bounded ? fmaf(qnr, err_max, qer) : 0.f) : INFINITY;
+      rank_term(gp, meta.tcls[qq], p, arow, qrow, dn, ldk, n, o, bounded, qnr, qer, bound.o_err, lane, best, bid, dots,
+                sidx, sn, tau);
     } else
     switch (family_of(p)) {
       case kFamNear:
@@ -1201,10 +1210,11 @@ __global__ __launch_bounds__(kFbThreads) void k_rescore_fallback(
     const float* ssim = pv.sem_sim ? pv.sem_sim + (int64_t)r * kSemMax : nullptr;
     float best = 0.f;
     uint32_t bid = FARM_NO_ID;
-    if (is_rank(p)) {  // one wave takes the term
+    if (is_rank(p)) {  // one wave takes the term; the semantic set goes first and may certify it
+      const float tau = pv.sem_tau[r] + (BOUNDED ? fmaf(qnr, *bound.o_err_max, qer) : 0.f);
       if (threadIdx.x < 64)
         rank_term(gp, meta.tcls[qq], p, arow, qrow, dn, ldk, n, o, BOUNDED, qnr, qer, bound.o_err, (int)threadIdx.x,
-                  best, bid, dots);
+                  best, bid, dots, sidx, sn, tau);
     } else
     switch (family_of(p)) {
       case kFamNear:
@@ -1442,7 +1452,8 @@ hipError_t launch_rescore_terms(const farm_memory* mem, const farm_workspace* ws
                                 const int32_t* cand_count, int32_t c, const PropView& prop, bool fallback_pass,
                                 hipStream_t s) {
   if (q <= 0 || c <= 0) return hipSuccess;
-  const Geo g{mem->x, mem->y, mem->z, mem->z, mem->hr_hi, mem->hr_lo, mem->id, mem->vz, mem->cls};
+  const Geo g{mem->x, mem->y, mem->z,   mem->z,   mem->hr_hi,     mem->hr_lo,
+              mem->id, mem->vz, mem->cls, mem->cls_order, mem->cls_sorted};
   const dim3 grid(kTermBlocksX, (unsigned)q), block(64 * kTermWaves);
 #define FARM_TERMS(MODE, B)                                                                                      \
   hipLaunchKernelGGL((k_rescore_terms<MODE, B>), grid, block, 0, s, sim, ld_s, q, meta, bound, ws->qn, mem->dn, \
