@@ -105,33 +105,37 @@ __device__ inline float rank_pred_wave(const RankCtx& k, int64_t o, int64_t a, i
 // similarity of every other anchor, no other anchor can reach it (P <= 1) and
 // the scan ends there.  best is -1 when no anchor exists (n = 1); the caller
 // clamps.
-template <class HiOf, class ExactOf>
-__device__ void rank_term_wave(RankCtx k, int64_t o, int lane, HiOf hi_of, ExactOf exact_of, float& out_best,
-                               uint32_t& out_bid, const int32_t* sidx = nullptr, int sn = 0,
-                               float out_bound = INFINITY) {
-  rank_range(k);
-  float best = -1.0f;
-  uint32_t bid = FARM_NO_ID;
-  auto visit = [&](int64_t aa) {
-    const float s = exact_of(aa);
-    if (s < best) return;
-    const float v = s * rank_pred_wave(k, o, aa, lane);
-    const uint32_t ida = k.ids[aa];
-    if (v > best || (v == best && ida < bid)) {
-      best = v;
-      bid = ida;
-    }
-  };
-  for (int e = 0; e < sn; ++e) {
+// The two phases of a term, each over a share of its anchors: part w of
+// parts takes semantic-set entries w, w + parts, ... and anchor chunks of 64
+// starting at 64 w with stride 64 parts (several waves of a block can split
+// one term and merge (best, id) afterwards).  best/bid carry the running
+// maximum in and out; k must have its range set (rank_range).
+template <class ExactOf>
+__device__ inline void rank_visit(const RankCtx& k, int64_t o, int64_t aa, int lane, ExactOf& exact_of, float& best,
+                                  uint32_t& bid) {
+  const float s = exact_of(aa);
+  if (s < best) return;
+  const float v = s * rank_pred_wave(k, o, aa, lane);
+  const uint32_t ida = k.ids[aa];
+  if (v > best || (v == best && ida < bid)) {
+    best = v;
+    bid = ida;
+  }
+}
+
+template <class ExactOf>
+__device__ void rank_set_part(const RankCtx& k, int64_t o, int lane, ExactOf exact_of, const int32_t* sidx, int sn,
+                              int w, int parts, float& best, uint32_t& bid) {
+  for (int e = w; e < sn; e += parts) {
     const int64_t aa = __builtin_amdgcn_readfirstlane(sidx[e]);
-    if (aa != o) visit(aa);
+    if (aa != o) rank_visit(k, o, aa, lane, exact_of, best, bid);
   }
-  if (sn > 0 && best > out_bound) {
-    out_best = best;
-    out_bid = bid;
-    return;
-  }
-  for (int64_t a0 = 0; a0 < k.n; a0 += 64) {
+}
+
+template <class HiOf, class ExactOf>
+__device__ void rank_scan_part(const RankCtx& k, int64_t o, int lane, HiOf hi_of, ExactOf exact_of, int w, int parts,
+                               float& best, uint32_t& bid) {
+  for (int64_t a0 = (int64_t)64 * w; a0 < k.n; a0 += (int64_t)64 * parts) {
     const int64_t a = a0 + lane;
     const float h = (a < k.n && a != o) ? hi_of(a) : -INFINITY;
     uint64_t mask = __ballot(h >= best);
@@ -139,9 +143,20 @@ __device__ void rank_term_wave(RankCtx k, int64_t o, int lane, HiOf hi_of, Exact
       const int src = __ffsll((unsigned long long)mask) - 1;
       mask &= mask - 1;
       if (__shfl(h, src) < best) continue;  // the best grew meanwhile
-      visit(a0 + src);
+      rank_visit(k, o, a0 + src, lane, exact_of, best, bid);
     }
   }
+}
+
+template <class HiOf, class ExactOf>
+__device__ void rank_term_wave(RankCtx k, int64_t o, int lane, HiOf hi_of, ExactOf exact_of, float& out_best,
+                               uint32_t& out_bid, const int32_t* sidx = nullptr, int sn = 0,
+                               float out_bound = INFINITY) {
+  rank_range(k);
+  float best = -1.0f;
+  uint32_t bid = FARM_NO_ID;
+  rank_set_part(k, o, lane, exact_of, sidx, sn, 0, 1, best, bid);
+  if (!(sn > 0 && best > out_bound)) rank_scan_part(k, o, lane, hi_of, exact_of, 0, 1, best, bid);
   out_best = best;
   out_bid = bid;
 }

@@ -1176,6 +1176,53 @@ __device__ void full_term_block(const float* __restrict__ arow, const float* __r
   out_bid = bid;
 }
 
+// Closest/Farthest term of target o by a whole fallback block: its waves
+// split the semantic set and then (unless the set certifies the term) the
+// anchor scan, merging (best, id) through LDS after each phase.
+template <bool BOUNDED>
+__device__ void rank_term_block(const Geo& g, int32_t tc, int p, const float* __restrict__ arow,
+                                const float* __restrict__ qrow, const float* __restrict__ dn, int32_t ldk, int64_t n,
+                                int64_t o, float qnr, float qer, const float* __restrict__ o_err,
+                                const int32_t* __restrict__ sidx, int sn, float tau, float* sv, uint32_t* sid,
+                                float& out_best, uint32_t& out_bid, uint32_t& dots) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  constexpr int parts = kFbThreads / 64;
+  RankCtx k{g.x, g.y, g.z, g.ids, g.cls, g.cls_order, g.cls_sorted, tc, n, p == FARM_CLOSEST};
+  rank_range(k);
+  auto hi_of = [&](int64_t a) { return BOUNDED ? arow[a] + fmaf(qnr, o_err[a], qer) : arow[a]; };
+  auto exact_of = [&](int64_t a) {
+    if (!BOUNDED) return arow[a];
+    ++dots;
+    return fmaxf(0.f, wave_dot(qrow, dn + a * ldk, ldk, lane));
+  };
+  float best = -1.0f;
+  uint32_t bid = FARM_NO_ID;
+  auto merge = [&]() {
+    __syncthreads();
+    if (lane == 0) {
+      sv[w] = best;
+      sid[w] = bid;
+    }
+    __syncthreads();
+    for (int u = 0; u < parts; ++u) {
+      const float v = sv[u];
+      const uint32_t id = sid[u];
+      if (v > best || (v == best && id < bid)) {
+        best = v;
+        bid = id;
+      }
+    }
+  };
+  rank_set_part(k, o, lane, exact_of, sidx, sn, w, parts, best, bid);
+  merge();
+  if (!(sn > 0 && best > tau)) {
+    rank_scan_part(k, o, lane, hi_of, exact_of, w, parts, best, bid);
+    merge();
+  }
+  out_best = best;
+  out_bid = bid;
+}
+
 // One block per listed uncertified term (grid-stride over the worklist).
 template <bool BOUNDED>
 __global__ __launch_bounds__(kFbThreads) void k_rescore_fallback(
@@ -1210,11 +1257,10 @@ __global__ __launch_bounds__(kFbThreads) void k_rescore_fallback(
     const float* ssim = pv.sem_sim ? pv.sem_sim + (int64_t)r * kSemMax : nullptr;
     float best = 0.f;
     uint32_t bid = FARM_NO_ID;
-    if (is_rank(p)) {  // one wave takes the term; the semantic set goes first and may certify it
+    if (is_rank(p)) {  // the block's waves split the term; the semantic set goes first and may certify it
       const float tau = pv.sem_tau[r] + (BOUNDED ? fmaf(qnr, *bound.o_err_max, qer) : 0.f);
-      if (threadIdx.x < 64)
-        rank_term(gp, meta.tcls[qq], p, arow, qrow, dn, ldk, n, o, BOUNDED, qnr, qer, bound.o_err, (int)threadIdx.x,
-                  best, bid, dots, sidx, sn, tau);
+      rank_term_block<BOUNDED>(gp, meta.tcls[qq], p, arow, qrow, dn, ldk, n, o, qnr, qer, bound.o_err, sidx, sn, tau,
+                               sv, sid, best, bid, dots);
     } else
     switch (family_of(p)) {
       case kFamNear:
