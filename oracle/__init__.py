@@ -209,7 +209,7 @@ def binding_value(scene, pred: int, anchor_vec, i: int, j: int, target_cls: int 
                                                int(target_cls), int(pred), pa, int(i), int(j)))
 
 
-NUM_PRED = 11  # predicates the scorer evaluates (ids 0..10: On = 8, Closest = 9, Farthest = 10)
+NUM_PRED = 12  # predicates the scorer evaluates (ids 0..11: On = 8, Closest = 9, Farthest = 10, Inside = 11)
 NPRED = 9      # proposal-network outputs, one per predicate
 NGEO = 12
 

@@ -41,9 +41,14 @@ def _sigmoid(x):
 
 
 def soft_relation(pred, ci, cj, right, ei=(0.0, 0.0, 0.0), ej=(0.0, 0.0, 0.0)):
-    """The nine closed-form soft predicates, written from their definitions
-    (ei, ej: full box extents of target and anchor, used by On only)."""
+    """The ten closed-form soft predicates, written from their definitions
+    (ei, ej: full box extents of target and anchor, used by On and Inside)."""
     dx, dy, dz = (float(ci[0]) - float(cj[0]), float(ci[1]) - float(cj[1]), float(ci[2]) - float(cj[2]))
+    if pred == 11:  # inside: the target's center within the anchor's box, softly per axis
+        v = 1.0
+        for k in range(3):
+            v *= _sigmoid((float(ej[k]) / 2.0 - abs(float(ci[k]) - float(cj[k]))) / 0.1)
+        return v
     if pred == 8:  # on: gate on the horizontal distance (sigma 0.5 m) times a band on the
         # gap between the target's bottom face and the anchor's top face (sigma 0.125 m)
         bottom_i = float(ci[2]) - float(ei[2]) / 2.0

@@ -36,6 +36,7 @@
  *              g = (c_i,z - e_i,z / 2) - (c_j,z + e_j,z / 2)
  *   CLOSEST  = 1 / rank,  FARTHEST = 1 / (last rank - rank + 1): the rank of i
  *              among the query's candidates by distance to j (see rank_value)
+ *   INSIDE   = prod_k sig((e_j,k / 2 - |D_k|) / 0.1): i's center within j's box
  * where (r_x, r_y) is the scene viewer's right vector, f = (-r_y, r_x) its
  * viewing direction and e the full box extents.  The temperatures
  * (0.1 m), the Gaussian's normalisation, the clamp at zero, the viewer
@@ -63,7 +64,7 @@
 #define ORACLE_NO_ID 0xFFFFFFFFu
 
 enum { P_NEAR = 0, P_ABOVE = 1, P_BELOW = 2, P_LEFT_OF = 3, P_RIGHT_OF = 4, P_NEXT_TO = 5, P_IN_FRONT_OF = 6,
-       P_BEHIND = 7, P_ON = 8, P_CLOSEST = 9, P_FARTHEST = 10, P_COUNT = 11 };
+       P_BEHIND = 7, P_ON = 8, P_CLOSEST = 9, P_FARTHEST = 10, P_INSIDE = 11, P_COUNT = 12 };
 
 static double logistic(double u) { return 1.0 / (1.0 + exp(-u)); }
 
@@ -96,6 +97,13 @@ double oracle_predicate(int p, const double* ci, const double* cj, const double*
     case P_LEFT_OF: return logistic(-(dx * right[0] + dy * right[1]) / ORACLE_TAU);
     case P_IN_FRONT_OF: return logistic(-depth / ORACLE_TAU);
     case P_BEHIND: return logistic(depth / ORACLE_TAU);
+    case P_INSIDE: {
+        /* a soft containment test: along each axis the target's center lies
+         * within the anchor's half extent (logistic of the margin, 0.1 m) */
+        double v = 1.0;
+        for (int k = 0; k < 3; ++k) v *= logistic((0.5 * ej[k] - fabs(ci[k] - cj[k])) / ORACLE_TAU);
+        return v;
+    }
     case P_ON: {
         double h2 = dx * dx + dy * dy;
         double gap = (ci[2] - 0.5 * ei[2]) - (cj[2] + 0.5 * ej[2]);  /* bottom of i minus top of j */

@@ -27,13 +27,13 @@ import numpy as np
 # Predicate ids, in the order the C ABI uses.
 NEAR, ABOVE, BELOW, LEFT_OF, RIGHT_OF = 0, 1, 2, 3, 4
 NEXT_TO, IN_FRONT_OF, BEHIND, ON = 5, 6, 7, 8
-CLOSEST, FARTHEST = 9, 10
-ALL_PREDS = tuple(range(9))                 # the pairwise predicates
+CLOSEST, FARTHEST, INSIDE = 9, 10, 11
+ALL_PREDS = tuple(range(9))                 # the pairwise predicates with learned anchor lists
 RANK_PREDS = (CLOSEST, FARTHEST)            # rank within the query's candidate set
-EVERY_PRED = ALL_PREDS + RANK_PREDS
+EVERY_PRED = ALL_PREDS + RANK_PREDS + (INSIDE,)
 DEFAULT_PREDS = (NEAR, ABOVE, BELOW, LEFT_OF, RIGHT_OF)  # the pool query batches draw from by default
 PRED_NAMES = ("near", "above", "below", "left_of", "right_of", "next_to", "in_front_of", "behind", "on", "closest",
-              "farthest")
+              "farthest", "inside")
 
 
 @dataclasses.dataclass
@@ -188,7 +188,7 @@ def _plant_anchor(rng, scene: Scene, o: int, pred: int, c64: np.ndarray, r64: np
     d = c64 - c64[o]
     dist = np.sqrt((d * d).sum(axis=1))
     dist[o] = np.inf
-    if pred in (NEAR, NEXT_TO, CLOSEST):
+    if pred in (NEAR, NEXT_TO, CLOSEST, INSIDE):
         ok = np.isfinite(dist)
     elif pred == FARTHEST:
         ok = np.isfinite(dist)

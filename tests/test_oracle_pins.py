@@ -14,8 +14,8 @@ import pytest
 
 import oracle
 from oracle.brute import brute_scores
-from synth import (ABOVE, ALL_PREDS, BEHIND, BELOW, CLOSEST, EVERY_PRED, FARTHEST, IN_FRONT_OF, LEFT_OF, NEAR,
-                   NEXT_TO, ON, RIGHT_OF, CONFIGS,
+from synth import (ABOVE, ALL_PREDS, BEHIND, BELOW, CLOSEST, EVERY_PRED, FARTHEST, IN_FRONT_OF, INSIDE, LEFT_OF,
+                   NEAR, NEXT_TO, ON, RIGHT_OF, CONFIGS,
                    QueryBatch, Scene, make_queries, make_scene)
 from tests import _golden
 
@@ -169,6 +169,39 @@ def test_on_closed_form_gate_and_band():
         band = oracle.predicate(ON, np.array([b[0], b[1], a[2]], np.float32), b, r, ea, eb)
         assert v == pytest.approx(gate * band, rel=1e-14, abs=1e-300)
 
+
+
+def test_inside_closed_form():
+    """Inside: along each axis a logistic (0.1 m) of the margin between the
+    anchor's half extent and the target's center offset; the product of the
+    three.  Values on exact inputs."""
+    r = [1.0, 0.0]
+    box = [2.0, 4.0, 1.0]  # half extents 1, 2, 0.5
+    sig = lambda u: 1.0 / (1.0 + math.exp(-u))
+    # centred: margins 1, 2, 0.5 m -> sig(10) sig(20) sig(5)
+    assert oracle.predicate(INSIDE, [0, 0, 0], [0, 0, 0], r, [0.1, 0.1, 0.1], box) == pytest.approx(
+        sig(10) * sig(20) * sig(5), rel=1e-15)
+    # on the x face: sig(0) = 1/2 for that axis
+    assert oracle.predicate(INSIDE, [1, 0, 0], [0, 0, 0], r, [0.1, 0.1, 0.1], box) == pytest.approx(
+        0.5 * sig(20) * sig(5), rel=1e-15)
+    # 0.25 m outside in z (offset 0.75 against half extent 0.5), either side
+    for dz in (0.75, -0.75):
+        assert oracle.predicate(INSIDE, [0, 0, dz], [0, 0, 0], r, [0.1, 0.1, 0.1], box) == pytest.approx(
+            sig(10) * sig(20) * sig(-2.5), rel=1e-14)
+    rng = np.random.default_rng(9)
+    for _ in range(30):
+        a, b = rng.uniform(-3, 3, 3).astype(np.float32), rng.uniform(-3, 3, 3).astype(np.float32)
+        ea, eb = rng.uniform(0.1, 4, 3).astype(np.float32), rng.uniform(0.1, 4, 3).astype(np.float32)
+        v = oracle.predicate(INSIDE, a, b, r, ea, eb)
+        assert 0.0 < v < 1.0
+        # the target's own extent and the viewer play no part
+        yaw = rng.uniform(0, 2 * math.pi)
+        r2 = np.array([math.sin(yaw), -math.cos(yaw)], np.float32)
+        assert oracle.predicate(INSIDE, a, b, r2, ea * 2, eb) == v
+        # mirrored offsets give the same value
+        assert oracle.predicate(INSIDE, 2 * b - a, b, r, ea, eb) == pytest.approx(v, rel=1e-5)
+        # a larger anchor box contains more
+        assert oracle.predicate(INSIDE, a, b, r, ea, eb * 2) > v
 
 
 def _rank_scene():
