@@ -41,8 +41,10 @@
  *                    equal distances by id}, m = |C minus i and j|; distances
  *                    compared as FP32 ((dx*dx + dy*dy) + dz*dz).  A rank within
  *                    the candidate set, scored 1 / (|rank - r*| + 1).  Cost
- *                    O(N) per evaluated anchor: meant for small scenes or few
- *                    such relations
+ *                    O(|C|) per evaluated anchor (O(N) without a class)
+ *   FARM_INSIDE      prod_k sig((e_j,k / 2 - |D_k|) / 0.1): the target's center
+ *                    within the anchor's box (e = full extents), a soft
+ *                    containment test
  *
  * Conventions shared by every entry point:
  *   - Every function returns a farm_status; farm_last_error() gives a message
@@ -95,9 +97,10 @@ typedef enum {
   FARM_BEHIND = 7,
   FARM_ON = 8,
   FARM_CLOSEST = 9,
-  FARM_FARTHEST = 10
+  FARM_FARTHEST = 10,
+  FARM_INSIDE = 11
 } farm_pred;
-#define FARM_NUM_PRED 11        /* predicate ids 0 .. FARM_NUM_PRED - 1 */
+#define FARM_NUM_PRED 12        /* predicate ids 0 .. FARM_NUM_PRED - 1 */
 #define FARM_NUM_PROP_PRED 9    /* predicates with learned anchor lists (network outputs): 0 .. 8 */
 
 #define FARM_MAX_REL 8          /* relations per query */

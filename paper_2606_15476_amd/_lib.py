@@ -14,8 +14,8 @@ EXHAUSTIVE, BOUNDED, PROPOSAL = 0, 1, 2
 OPT_GLOBAL_PROPOSAL_PASS = 1
 NEAR, ABOVE, BELOW, LEFT_OF, RIGHT_OF = 0, 1, 2, 3, 4
 NEXT_TO, IN_FRONT_OF, BEHIND, ON = 5, 6, 7, 8
-CLOSEST, FARTHEST = 9, 10
-NUM_PRED, NUM_PROP_PRED = 11, 9  # predicate ids; those with learned anchor lists
+CLOSEST, FARTHEST, INSIDE = 9, 10, 11
+NUM_PRED, NUM_PROP_PRED = 12, 9  # predicate ids; those with learned anchor lists
 FARM_MAX_REL = 8
 FARM_MAX_K = 1024
 FARM_NO_ID = 0xFFFFFFFF

@@ -170,10 +170,10 @@ farm_status stage_meta(farm_workspace* ws, int32_t q, int32_t R, const int32_t* 
   int32_t* rq = h + 2 * q + 1 + R;
   for (int32_t k = 0; k < q; ++k)
     for (int32_t r = rel_off[k]; r < rel_off[k + 1]; ++r) rq[r] = k;
-  int32_t* rk = h + 2 * q + 1 + 2 * R;  // rows of the rank predicates
+  int32_t* rk = h + 2 * q + 1 + 2 * R;  // rows of the scanned predicates (Closest, Farthest, Inside)
   int32_t nrank = 0;
   for (int32_t r = 0; r < R; ++r)
-    if (rel_pred[r] == FARM_CLOSEST || rel_pred[r] == FARM_FARTHEST) rk[nrank++] = r;
+    if (rel_pred[r] == FARM_CLOSEST || rel_pred[r] == FARM_FARTHEST || rel_pred[r] == FARM_INSIDE) rk[nrank++] = r;
   size_t len = (size_t)(2 * q + 1 + 2 * R + nrank);
   FARM_HIP(hipMemcpyAsync(ws->d_meta, h, len * sizeof(int32_t), hipMemcpyHostToDevice, s), "metadata copy");
   FARM_HIP(hipEventRecord(ws->meta_done, s), "metadata event");
@@ -182,8 +182,8 @@ farm_status stage_meta(farm_workspace* ws, int32_t q, int32_t R, const int32_t* 
   view->rel_off = ws->d_meta + q;
   view->rel_pred = ws->d_meta + 2 * q + 1;
   view->rel_query = ws->d_meta + 2 * q + 1 + R;
-  view->rank_rows = ws->d_meta + 2 * q + 1 + 2 * R;
-  view->rank_n = nrank;
+  view->scan_rows = ws->d_meta + 2 * q + 1 + 2 * R;
+  view->scan_n = nrank;
   return FARM_OK;
 }
 

@@ -193,8 +193,8 @@ struct MetaView {
   const int32_t* rel_off;
   const int32_t* rel_pred;
   const int32_t* rel_query;
-  const int32_t* rank_rows = nullptr;  // relation rows of Closest/Farthest (rank_n of them)
-  int32_t rank_n = 0;
+  const int32_t* scan_rows = nullptr;  // relation rows of Closest/Farthest/Inside (scan_n of them)
+  int32_t scan_n = 0;
 };
 
 namespace farm {

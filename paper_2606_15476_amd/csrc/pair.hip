@@ -26,14 +26,14 @@
 // overlaps the block's own targets carries the j != i test.
 //
 // Closest/Farthest depend on the query's candidate set, not on the pair alone:
-// k_rank_rows computes their terms first (one wave per target, rank_math.h)
+// k_scan_rows computes their terms first (one wave per target, scan_math.h)
 // into the relation's row of lsim (as log t), and the exhaustive kernel adds
 // that row like a Near term.
 #include <math.h>
 
 #include "farm_internal.h"
 #include "pair_math.h"
-#include "rank_math.h"
+#include "scan_math.h"
 
 namespace farm {
 namespace {
@@ -98,27 +98,28 @@ __device__ void relation_pass(const float* __restrict__ arow, const float* __res
 }
 
 // Closest/Farthest terms of every target for the relation rows listed in
-// meta.rank_rows: one wave per (target, row); lsim's row gets log t, and the
+// meta.scan_rows: one wave per (target, row); lsim's row gets log t, and the
 // term and anchor outputs are written here when requested.
-constexpr int kRankWaves = 4;
+constexpr int kScanWaves = 4;
 
-__global__ __launch_bounds__(64 * kRankWaves) void k_rank_rows(
+__global__ __launch_bounds__(64 * kScanWaves) void k_scan_rows(
     const float* __restrict__ sim, float* __restrict__ lsim, int64_t ld_s, int32_t q, MetaView meta,
     const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
-    const uint32_t* __restrict__ ids, const int32_t* __restrict__ cls, const int32_t* __restrict__ cls_order,
-    const int32_t* __restrict__ cls_sorted, int64_t n, float* __restrict__ rel_terms,
+    const float* __restrict__ ext, const uint32_t* __restrict__ ids, const int32_t* __restrict__ cls,
+    const int32_t* __restrict__ cls_order, const int32_t* __restrict__ cls_sorted, int64_t n,
+    float* __restrict__ rel_terms,
     uint32_t* __restrict__ rel_anchor_id) {
   const int lane = threadIdx.x & 63;
-  const int64_t o = (int64_t)blockIdx.x * kRankWaves + (threadIdx.x >> 6);
+  const int64_t o = (int64_t)blockIdx.x * kScanWaves + (threadIdx.x >> 6);
   if (o >= n) return;  // whole waves leave together
-  const int r = meta.rank_rows[blockIdx.y];
+  const int r = meta.scan_rows[blockIdx.y];
   const int qq = meta.rel_query[r];
-  const RankCtx k{x, y, z, ids, cls, cls_order, cls_sorted, meta.tcls[qq], n, meta.rel_pred[r] == FARM_CLOSEST};
+  const ScanCtx k{x, y, z, ext, ids, cls, cls_order, cls_sorted, meta.tcls[qq], n, meta.rel_pred[r]};
   const float* arow = sim + (int64_t)(q + r) * ld_s;
   float best;
   uint32_t bid;
-  rank_term_wave(
-      k, o, lane, [&](int64_t a) { return arow[a]; }, [&](int64_t a) { return arow[a]; }, best, bid);
+  auto sim_of = [&](int64_t a) { return arow[a]; };  // lower bound, upper bound and value alike
+  scan_term_wave(k, o, lane, sim_of, sim_of, sim_of, best, bid);
   const float t = best > 0.f ? best : 0.f;
   if (lane == 0) {
     lsim[(int64_t)r * ld_s + o] = logf(t);
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(kThreads) void k_pair_exhaustive(
     const float* lrow = lsim + (int64_t)r * ld_s;
     // largest similarity error of this relation row (upper-bound output only)
     const float dmax = bounded ? fmaf(bound.q_nrm[q + r], err_max, bound.q_err[q + r] + bound.acc) : 0.f;
-    if (is_rank(p)) {  // log t from k_rank_rows, which also wrote the term and anchor outputs
+    if (is_scanned(p)) {  // log t from k_scan_rows, which also wrote the term and anchor outputs
 #pragma unroll
       for (int u = 0; u < kTpt; ++u) {
         const float l = lrow[ti[u]];
@@ -282,7 +283,7 @@ __global__ __launch_bounds__(256) void k_explain(const float* __restrict__ sim, 
                                                  const float* __restrict__ z, const float* __restrict__ vz,
                                                  const float* __restrict__ hhi,
                                                  const float* __restrict__ hlo, const uint32_t* __restrict__ ids,
-                                                 const int32_t* __restrict__ cls,
+                                                 const float* __restrict__ ext, const int32_t* __restrict__ cls,
                                                  const int32_t* __restrict__ cls_order,
                                                  const int32_t* __restrict__ cls_sorted,
                                                  int64_t n, float* __restrict__ out_terms,
@@ -304,13 +305,12 @@ __global__ __launch_bounds__(256) void k_explain(const float* __restrict__ sim, 
       const float* rhi = hhi + (is_depth(p) ? n : 0);  // depth pair of InFrontOf/Behind
       const float* rlo = hlo + (is_depth(p) ? n : 0);
       const ZPair zp = z_for(p, z, vz, n);  // On: bottom/top faces
-      if (is_rank(p)) {
+      if (is_scanned(p)) {
         // every wave takes the same term (identical arithmetic); thread 0 stores it
-        const RankCtx rk{x, y, z, ids, cls, cls_order, cls_sorted, meta.tcls[qq], n, p == FARM_CLOSEST};
+        const ScanCtx rk{x, y, z, ext, ids, cls, cls_order, cls_sorted, meta.tcls[qq], n, p};
         float bv;
-        rank_term_wave(
-            rk, i, (int)(threadIdx.x & 63), [&](int64_t a) { return arow[a]; }, [&](int64_t a) { return arow[a]; },
-            bv, b);
+        auto sim_of = [&](int64_t a) { return arow[a]; };
+        scan_term_wave(rk, i, (int)(threadIdx.x & 63), sim_of, sim_of, sim_of, bv, b);
         tv = bv > 0.f ? bv : 0.f;
       } else
       switch (family_of(p)) {
@@ -347,10 +347,10 @@ hipError_t launch_pair_exhaustive(const farm_memory* mem, const float* sim, cons
                                   uint32_t* rel_anchor_id, float* scores_hi, hipStream_t s) {
   if (q <= 0) return hipSuccess;
   int64_t n = mem->n;
-  if (meta.rank_n > 0) {
-    hipLaunchKernelGGL(k_rank_rows, dim3((unsigned)((n + kRankWaves - 1) / kRankWaves), (unsigned)meta.rank_n),
-                       dim3(64 * kRankWaves), 0, s, sim, const_cast<float*>(lsim), ld_s, q, meta, mem->x, mem->y, mem->z,
-                       mem->id, mem->cls, mem->cls_order, mem->cls_sorted, n, rel_terms, rel_anchor_id);
+  if (meta.scan_n > 0) {
+    hipLaunchKernelGGL(k_scan_rows, dim3((unsigned)((n + kScanWaves - 1) / kScanWaves), (unsigned)meta.scan_n),
+                       dim3(64 * kScanWaves), 0, s, sim, const_cast<float*>(lsim), ld_s, q, meta, mem->x, mem->y, mem->z,
+                       mem->ext, mem->id, mem->cls, mem->cls_order, mem->cls_sorted, n, rel_terms, rel_anchor_id);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -371,7 +371,8 @@ hipError_t launch_explain(const farm_memory* mem, const float* sim, int64_t ld_s
   if (q <= 0 || k <= 0 || (!out_terms && !out_anchor_id)) return hipSuccess;
   dim3 grid((unsigned)k, (unsigned)q);
   hipLaunchKernelGGL(k_explain, grid, dim3(256), 0, s, sim, ld_s, q, meta, idx, k, mem->x, mem->y, mem->z, mem->vz,
-                     mem->hr_hi, mem->hr_lo, mem->id, mem->cls, mem->cls_order, mem->cls_sorted, mem->n, out_terms,
+                     mem->hr_hi, mem->hr_lo, mem->id, mem->ext, mem->cls, mem->cls_order, mem->cls_sorted, mem->n,
+                     out_terms,
                      out_anchor_id);
   return hipGetLastError();
 }

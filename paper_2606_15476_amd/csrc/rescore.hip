@@ -32,7 +32,7 @@
 
 #include "farm_internal.h"
 #include "pair_math.h"
-#include "rank_math.h"
+#include "scan_math.h"
 #include "sort_util.h"
 
 namespace farm {
@@ -177,6 +177,7 @@ struct Geo {
   const float* vz;     // [2][n]: 4 * bottom face, 4 * top face (On)
   const int32_t* cls;  // object classes or null (the candidate set of Closest/Farthest)
   const int32_t *cls_order, *cls_sorted;  // objects in class order, their classes
+  const float* ext;    // [3][n] full extents (Inside)
 };
 
 // The coordinates predicate p uses: InFrontOf/Behind take the depth pair
@@ -565,25 +566,26 @@ constexpr int kTermBlocksX = 8;  // blocks per query: 32 waves sweep a query's t
 
 enum { kTermsFull = 0, kTermsSubset = 1, kTermsFallback = 2 };
 
-// Closest/Farthest term of target o by one wave (rank_math.h).  Reduced
+// Closest/Farthest term of target o by one wave (scan_math.h).  Reduced
 // precision: an anchor whose upper bound (BF16/FP8 value + error bound)
 // reaches the best value so far gets its exact FP32 similarity (wave dot).
 // With the relation's semantic set (sidx, sn) and tau, the largest similarity
 // outside it (plus the error bound for reduced precision), the set goes first
 // and ends the scan when it certifies the term.
-__device__ inline void rank_term(const Geo& g, int32_t tc, int p, const float* __restrict__ arow,
+__device__ inline void scan_term(const Geo& g, int32_t tc, int p, const float* __restrict__ arow,
                                  const float* __restrict__ qrow, const float* __restrict__ dn, int32_t ldk, int64_t n,
                                  int64_t o, bool bounded, float qnr, float qer, const float* __restrict__ o_err,
                                  int lane, float& best, uint32_t& bid, uint32_t& dots,
                                  const int32_t* __restrict__ sidx = nullptr, int sn = 0, float tau = INFINITY) {
-  const RankCtx k{g.x, g.y, g.z, g.ids, g.cls, g.cls_order, g.cls_sorted, tc, n, p == FARM_CLOSEST};
+  const ScanCtx k{g.x, g.y, g.z, g.ext, g.ids, g.cls, g.cls_order, g.cls_sorted, tc, n, p};
   if (!bounded) {
-    rank_term_wave(
-        k, o, lane, [&](int64_t a) { return arow[a]; }, [&](int64_t a) { return arow[a]; }, best, bid, sidx, sn,
-        tau);
+    scan_term_wave(
+        k, o, lane, [&](int64_t a) { return arow[a]; }, [&](int64_t a) { return arow[a]; },
+        [&](int64_t a) { return arow[a]; }, best, bid, sidx, sn, tau);
   } else {
-    rank_term_wave(
-        k, o, lane, [&](int64_t a) { return arow[a] + fmaf(qnr, o_err[a], qer); },
+    scan_term_wave(
+        k, o, lane, [&](int64_t a) { return fmaxf(0.f, arow[a] - fmaf(qnr, o_err[a], qer)); },
+        [&](int64_t a) { return arow[a] + fmaf(qnr, o_err[a], qer); },
         [&](int64_t a) {
           ++dots;
           return fmaxf(0.f, wave_dot(qrow, dn + a * ldk, ldk, lane));
@@ -638,10 +640,10 @@ __global__ __launch_bounds__(64 * kTermWaves) void k_rescore_terms(
     const float qer = bounded ? bound.q_err[q + r] + bound.acc : 0.f;
     float best;
     uint32_t bid;
-    if (is_rank(p)) {
+    if (is_scanned(p)) {
       // with a semantic set (proposal fallback) the set goes first and may certify the term
       const float tau = sidx ? pv.sem_tau[r] + (bounded ? fmaf(qnr, err_max, qer) : 0.f) : INFINITY;
-      rank_term(gp, meta.tcls[qq], p, arow, qrow, dn, ldk, n, o, bounded, qnr, qer, bound.o_err, lane, best, bid, dots,
+      scan_term(gp, meta.tcls[qq], p, arow, qrow, dn, ldk, n, o, bounded, qnr, qer, bound.o_err, lane, best, bid, dots,
                 sidx, sn, tau);
     } else
     switch (family_of(p)) {
@@ -1180,16 +1182,17 @@ __device__ void full_term_block(const float* __restrict__ arow, const float* __r
 // split the semantic set and then (unless the set certifies the term) the
 // anchor scan, merging (best, id) through LDS after each phase.
 template <bool BOUNDED>
-__device__ void rank_term_block(const Geo& g, int32_t tc, int p, const float* __restrict__ arow,
+__device__ void scan_term_block(const Geo& g, int32_t tc, int p, const float* __restrict__ arow,
                                 const float* __restrict__ qrow, const float* __restrict__ dn, int32_t ldk, int64_t n,
                                 int64_t o, float qnr, float qer, const float* __restrict__ o_err,
                                 const int32_t* __restrict__ sidx, int sn, float tau, float* sv, uint32_t* sid,
                                 float& out_best, uint32_t& out_bid, uint32_t& dots) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   constexpr int parts = kFbThreads / 64;
-  RankCtx k{g.x, g.y, g.z, g.ids, g.cls, g.cls_order, g.cls_sorted, tc, n, p == FARM_CLOSEST};
+  ScanCtx k{g.x, g.y, g.z, g.ext, g.ids, g.cls, g.cls_order, g.cls_sorted, tc, n, p};
   rank_range(k);
   auto hi_of = [&](int64_t a) { return BOUNDED ? arow[a] + fmaf(qnr, o_err[a], qer) : arow[a]; };
+  auto lo_of = [&](int64_t a) { return BOUNDED ? fmaxf(0.f, arow[a] - fmaf(qnr, o_err[a], qer)) : arow[a]; };
   auto exact_of = [&](int64_t a) {
     if (!BOUNDED) return arow[a];
     ++dots;
@@ -1213,10 +1216,10 @@ __device__ void rank_term_block(const Geo& g, int32_t tc, int p, const float* __
       }
     }
   };
-  rank_set_part(k, o, lane, exact_of, sidx, sn, w, parts, best, bid);
+  scan_set_part(k, o, lane, exact_of, sidx, sn, w, parts, best, bid);
   merge();
   if (!(sn > 0 && best > tau)) {
-    rank_scan_part(k, o, lane, hi_of, exact_of, w, parts, best, bid);
+    scan_anchor_part(k, o, lane, lo_of, hi_of, exact_of, w, parts, best, bid);
     merge();
   }
   out_best = best;
@@ -1257,9 +1260,9 @@ __global__ __launch_bounds__(kFbThreads) void k_rescore_fallback(
     const float* ssim = pv.sem_sim ? pv.sem_sim + (int64_t)r * kSemMax : nullptr;
     float best = 0.f;
     uint32_t bid = FARM_NO_ID;
-    if (is_rank(p)) {  // the block's waves split the term; the semantic set goes first and may certify it
+    if (is_scanned(p)) {  // the block's waves split the term; the semantic set goes first and may certify it
       const float tau = pv.sem_tau[r] + (BOUNDED ? fmaf(qnr, *bound.o_err_max, qer) : 0.f);
-      rank_term_block<BOUNDED>(gp, meta.tcls[qq], p, arow, qrow, dn, ldk, n, o, qnr, qer, bound.o_err, sidx, sn, tau,
+      scan_term_block<BOUNDED>(gp, meta.tcls[qq], p, arow, qrow, dn, ldk, n, o, qnr, qer, bound.o_err, sidx, sn, tau,
                                sv, sid, best, bid, dots);
     } else
     switch (family_of(p)) {
@@ -1499,7 +1502,7 @@ hipError_t launch_rescore_terms(const farm_memory* mem, const farm_workspace* ws
                                 hipStream_t s) {
   if (q <= 0 || c <= 0) return hipSuccess;
   const Geo g{mem->x, mem->y, mem->z,   mem->z,   mem->hr_hi,     mem->hr_lo,
-              mem->id, mem->vz, mem->cls, mem->cls_order, mem->cls_sorted};
+              mem->id, mem->vz, mem->cls, mem->cls_order, mem->cls_sorted, mem->ext};
   const dim3 grid(kTermBlocksX, (unsigned)q), block(64 * kTermWaves);
 #define FARM_TERMS(MODE, B)                                                                                      \
   hipLaunchKernelGGL((k_rescore_terms<MODE, B>), grid, block, 0, s, sim, ld_s, q, meta, bound, ws->qn, mem->dn, \

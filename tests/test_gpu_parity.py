@@ -133,22 +133,22 @@ def test_all_predicates_full_parity(farm):
 
 
 def _rank_world(seed, n=700, q=24):
-    """A mid-config scene and queries drawing from every predicate, Closest and
-    Farthest included; every third query has no class (every object is then a
-    candidate of the rank predicates)."""
+    """A mid-config scene and queries drawing from every predicate, Closest,
+    Farthest and Inside (the scanned ones) included; every third query has no
+    class (every object is then a candidate of the rank predicates)."""
     import synth
     cfg = CONFIGS["mid"]
     scene = make_scene(cfg, n=n, seed=seed)
     qb = make_queries(cfg, scene, seed=seed + 1, q=q, preds=synth.EVERY_PRED)
     qb.target_cls[::3] = -1
-    assert set(synth.RANK_PREDS) <= set(np.unique(qb.rel_pred).tolist())
+    assert set(synth.RANK_PREDS + (synth.INSIDE,)) <= set(np.unique(qb.rel_pred).tolist())
     return cfg, scene, qb
 
 
 def test_rank_predicates_full_parity(farm):
-    """Closest/Farthest (rank within the candidate set) beside the pairwise
-    predicates, exhaustive FP32 method: full score matrix, per-relation terms
-    and bindings, TopK and breakdown against the oracle."""
+    """Closest/Farthest (rank within the candidate set) and Inside beside the
+    pairwise predicates, exhaustive FP32 method: full score matrix,
+    per-relation terms and bindings, TopK and breakdown against the oracle."""
     cfg, scene, qb = _rank_world(31)
     mem, ws, s64 = _check_full(farm, scene, qb, "rank predicates")
     _topk_against_full(farm, mem, ws, scene, qb, s64, cfg.k, "rank predicates")

@@ -142,8 +142,8 @@ def test_all_predicates(farm, dtype):
 
 @pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "bf16"])
 def test_rank_predicates(farm, dtype):
-    """Closest/Farthest have no lists: every such term takes the full-scan
-    fallback (LDS-staged and global-memory forms of the pass); results stay
+    """Closest/Farthest and Inside have no lists: every such term takes the
+    full-scan fallback (LDS-staged and global-memory forms of the pass); results stay
     bit-identical to BOUNDED, which equals the exact TopK."""
     from tests import _gpu
     from tests.test_gpu_parity import _check_bounded, _rank_world
