@@ -91,7 +91,7 @@ def parse():
     p.add_argument("--k", type=int, default=10)
     p.add_argument("--preds", default="five", choices=["five", "all", "every"],
                    help="predicates the queries draw from: the workload's five (Near..RightOf), all nine pairwise "
-                        "ones (+ NextTo, InFrontOf, Behind, On) or every one (+ Closest, Farthest)")
+                        "ones (+ NextTo, InFrontOf, Behind, On) or every one (+ Closest, Farthest, Inside)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=0, help="queries in the CPU-oracle sample (0 = auto)")
     p.add_argument("--serving", action="store_true",
@@ -243,7 +243,7 @@ def main():
                                f"R~U{{{cfg.r_min}..{cfg.r_max}}} (R_tot={qb.r_tot}), K={k}",
                    "form": args.form, "method": args.method, "global_batch": qb.q, "parallelism": "none (1 GPU)",
                    "predicates": {"five": "Near, Above, Below, LeftOf, RightOf", "all": "all nine pairwise",
-                                  "every": "all eleven (pairwise + Closest, Farthest)"}[args.preds]},
+                                  "every": "all twelve (pairwise + Closest, Farthest, Inside)"}[args.preds]},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
                        "what": "whole-batch latency of one step"},
         "phase_ms": phase_ms,
