@@ -628,6 +628,7 @@ __global__ __launch_bounds__(64 * kTermWaves) void k_rescore_terms(
   };
   auto full = [&](int64_t slot, int e, int64_t o) {
     const int r = r0 + e;
+    if (is_scanned(meta.rel_pred[r])) return;  // k_scan_terms takes these
     const int32_t* sidx = pv.sem_idx ? pv.sem_idx + (int64_t)r * kSemMax : nullptr;
     const int sn = pv.sem_idx ? pv.sem_cnt[r] : 0;
     const float* ssim = pv.sem_sim ? pv.sem_sim + (int64_t)r * kSemMax : nullptr;
@@ -640,12 +641,6 @@ __global__ __launch_bounds__(64 * kTermWaves) void k_rescore_terms(
     const float qer = bounded ? bound.q_err[q + r] + bound.acc : 0.f;
     float best;
     uint32_t bid;
-    if (is_scanned(p)) {
-      // with a semantic set (proposal fallback) the set goes first and may certify the term
-      const float tau = sidx ? pv.sem_tau[r] + (bounded ? fmaf(qnr, err_max, qer) : 0.f) : INFINITY;
-      scan_term(gp, meta.tcls[qq], p, arow, qrow, dn, ldk, n, o, bounded, qnr, qer, bound.o_err, lane, best, bid, dots,
-                sidx, sn, tau);
-    } else
     switch (family_of(p)) {
       case kFamNear:
         full_term<kFamNear>(arow, qrow, dn, ldk, n, o, c, bounded, qnr, qer, bound.o_err, gp, lane, sidx, sn, ssim,
@@ -741,6 +736,55 @@ __global__ __launch_bounds__(64 * kTermWaves) void k_rescore_terms(
     if (fell) atomicAdd(&pv.stats[1], fell);
     if (dots) atomicAdd(&pv.stats[MODE == kTermsSubset ? 2 : 3], (unsigned long long)dots);
   }
+}
+
+// Terms of the scanned predicates (Closest, Farthest, Inside), one wave per
+// term: every such term of the candidates (SWEEP = false: the bound-pruned
+// method), or those still unresolved (NaN) after the listed fallback (SWEEP =
+// true).  A kernel of its own keeps k_rescore_terms' register budget.
+template <bool BOUNDED, bool SWEEP>
+__global__ __launch_bounds__(64 * kTermWaves) void k_scan_terms(
+    const float* __restrict__ sim, int64_t ld_s, int32_t q, MetaView meta, SimBound bound,
+    const float* __restrict__ qn, const float* __restrict__ dn, int32_t ldk, const int32_t* __restrict__ cand,
+    const int32_t* __restrict__ cand_count, int32_t C, Geo g, int64_t n,
+    float* __restrict__ rs_terms, uint32_t* __restrict__ rs_anchor, PropView pv) {
+  const int lane = threadIdx.x & 63;
+  const int32_t qq = blockIdx.y;
+  const int r0 = meta.rel_off[qq], R = meta.rel_off[qq + 1] - r0;
+  if (R == 0) return;
+  const int32_t cnt = cand_count ? (cand_count[qq] < C ? cand_count[qq] : C) : C;
+  const int64_t terms = (int64_t)cnt * R;
+  const int wave = blockIdx.x * kTermWaves + (threadIdx.x >> 6);
+  const int stride = kTermBlocksX * kTermWaves;
+  const float err_max = BOUNDED ? *bound.o_err_max : 0.f;
+  uint32_t dots = 0;
+  for (int64_t tix = wave; tix < terms; tix += stride) {
+    const int e = (int)(tix % R);
+    const int r = r0 + e;
+    const int p = meta.rel_pred[r];
+    if (!is_scanned(p)) continue;
+    const int64_t slot = (int64_t)qq * C + tix / R;
+    const int64_t o = cand[slot];
+    if (o < 0) continue;
+    if (SWEEP && !isnan(rs_terms[slot * kMaxRel + e])) continue;
+    const float* arow = sim + (int64_t)(q + r) * ld_s;
+    const float* qrow = qn + (int64_t)(q + r) * ldk;
+    const float qnr = BOUNDED ? bound.q_nrm[q + r] : 0.f;
+    const float qer = BOUNDED ? bound.q_err[q + r] + bound.acc : 0.f;
+    // with a semantic set (proposal fallback) the set goes first and may certify the term
+    const int32_t* sidx = pv.sem_idx ? pv.sem_idx + (int64_t)r * kSemMax : nullptr;
+    const int sn = pv.sem_idx ? pv.sem_cnt[r] : 0;
+    const float tau = sidx ? pv.sem_tau[r] + (BOUNDED ? fmaf(qnr, err_max, qer) : 0.f) : INFINITY;
+    float best;
+    uint32_t bid;
+    scan_term(geo_for(g, p, n), meta.tcls[qq], p, arow, qrow, dn, ldk, n, o, BOUNDED, qnr, qer, bound.o_err, lane,
+              best, bid, dots, sidx, sn, tau);
+    if (lane == 0) {
+      rs_terms[slot * kMaxRel + e] = best;
+      rs_anchor[slot * kMaxRel + e] = bid;
+    }
+  }
+  if (pv.stats && lane == 0 && dots) atomicAdd(&pv.stats[3], (unsigned long long)dots);
 }
 
 // Proposal pass with the relation's similarity row staged in LDS: one block
@@ -1249,6 +1293,7 @@ __global__ __launch_bounds__(kFbThreads) void k_rescore_fallback(
     const int64_t o = cand[slot];
     const int r = r0 + e;
     const int p = meta.rel_pred[r];
+    if (is_scanned(p)) continue;  // k_scan_fallback takes these (block-uniform skip)
     const float c = sigmoid_scale(p);
     const Geo gp = geo_for(g, p, n);
     const float* arow = sim + (int64_t)(q + r) * ld_s;
@@ -1260,11 +1305,6 @@ __global__ __launch_bounds__(kFbThreads) void k_rescore_fallback(
     const float* ssim = pv.sem_sim ? pv.sem_sim + (int64_t)r * kSemMax : nullptr;
     float best = 0.f;
     uint32_t bid = FARM_NO_ID;
-    if (is_scanned(p)) {  // the block's waves split the term; the semantic set goes first and may certify it
-      const float tau = pv.sem_tau[r] + (BOUNDED ? fmaf(qnr, *bound.o_err_max, qer) : 0.f);
-      scan_term_block<BOUNDED>(gp, meta.tcls[qq], p, arow, qrow, dn, ldk, n, o, qnr, qer, bound.o_err, sidx, sn, tau,
-                               sv, sid, best, bid, dots);
-    } else
     switch (family_of(p)) {
       case kFamNear:
         full_term_block<kFamNear, BOUNDED>(arow, qrow, dn, ldk, n, o, c, qnr, qer, bound.o_err, gp, sidx, sn, ssim, sv,
@@ -1279,6 +1319,50 @@ __global__ __launch_bounds__(kFbThreads) void k_rescore_fallback(
                                           sid, hup, best, bid, dots);
         break;
     }
+    if (threadIdx.x == 0) {
+      rs_terms[slot * kMaxRel + e] = best;
+      rs_anchor[slot * kMaxRel + e] = bid;
+    }
+    __syncthreads();
+  }
+  if (pv.stats && (threadIdx.x & 63) == 0 && dots) atomicAdd(&pv.stats[3], (unsigned long long)dots);
+}
+
+// The worklist's terms of scanned predicates (Closest, Farthest, Inside): the
+// block's waves split each term (scan_term_block).  A kernel of its own so
+// that the pairwise fallback keeps its register budget.
+template <bool BOUNDED>
+__global__ __launch_bounds__(kFbThreads) void k_scan_fallback(
+    const float* __restrict__ sim, int64_t ld_s, int32_t q, MetaView meta, SimBound bound,
+    const float* __restrict__ qn, const float* __restrict__ dn, int32_t ldk, const int32_t* __restrict__ cand,
+    int32_t C, Geo g, int64_t n, float* __restrict__ rs_terms, uint32_t* __restrict__ rs_anchor, PropView pv) {
+  __shared__ float sv[kFbThreads / 64];
+  __shared__ uint32_t sid[kFbThreads / 64];
+  const uint32_t listed = *pv.fb_count;
+  const int64_t count = listed < pv.fb_cap ? (int64_t)listed : pv.fb_cap;
+  uint32_t dots = 0;
+  for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
+    const unsigned long long item = pv.fb_list[i];
+    const int32_t qq = (int32_t)(item >> 32);
+    const int64_t tix = (int64_t)(item & 0xFFFFFFFFull);
+    const int r0 = meta.rel_off[qq], R = meta.rel_off[qq + 1] - r0;
+    const int32_t cc = (int32_t)(tix / R);
+    const int e = (int)(tix % R);
+    const int r = r0 + e;
+    const int p = meta.rel_pred[r];
+    if (!is_scanned(p)) continue;  // block-uniform
+    const int64_t slot = (int64_t)qq * C + cc;
+    const int64_t o = cand[slot];
+    const float* arow = sim + (int64_t)(q + r) * ld_s;
+    const float* qrow = qn + (int64_t)(q + r) * ldk;
+    const float qnr = BOUNDED ? bound.q_nrm[q + r] : 0.f;
+    const float qer = BOUNDED ? bound.q_err[q + r] + bound.acc : 0.f;
+    // the semantic set goes first and may certify the term
+    const float tau = pv.sem_tau[r] + (BOUNDED ? fmaf(qnr, *bound.o_err_max, qer) : 0.f);
+    float best = 0.f;
+    uint32_t bid = FARM_NO_ID;
+    scan_term_block<BOUNDED>(geo_for(g, p, n), meta.tcls[qq], p, arow, qrow, dn, ldk, n, o, qnr, qer, bound.o_err,
+                             pv.sem_idx + (int64_t)r * kSemMax, pv.sem_cnt[r], tau, sv, sid, best, bid, dots);
     if (threadIdx.x == 0) {
       rs_terms[slot * kMaxRel + e] = best;
       rs_anchor[slot * kMaxRel + e] = bid;
@@ -1525,6 +1609,15 @@ hipError_t launch_rescore_terms(const farm_memory* mem, const farm_workspace* ws
                          ws->qn, mem->dn, mem->ldk, cand, c, g, mem->n, ws->rs_terms, ws->rs_anchor, prop);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (meta.scan_n > 0) {  // terms of Closest/Farthest/Inside on the worklist
+      if (bounded)
+        hipLaunchKernelGGL((k_scan_fallback<true>), dim3(blocks), dim3(kFbThreads), 0, s, sim, ld_s, q, meta, bound,
+                           ws->qn, mem->dn, mem->ldk, cand, c, g, mem->n, ws->rs_terms, ws->rs_anchor, prop);
+      else
+        hipLaunchKernelGGL((k_scan_fallback<false>), dim3(blocks), dim3(kFbThreads), 0, s, sim, ld_s, q, meta, bound,
+                           ws->qn, mem->dn, mem->ldk, cand, c, g, mem->n, ws->rs_terms, ws->rs_anchor, prop);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
   }
   if (mode == kTermsSubset) {
     const size_t lds = (size_t)round_up(mem->n, 4) * (bounded ? sizeof(uint16_t) : sizeof(float));
@@ -1557,6 +1650,22 @@ hipError_t launch_rescore_terms(const farm_memory* mem, const farm_workspace* ws
     else FARM_TERMS(kTermsFull, false);
   }
 #undef FARM_TERMS
+  if (meta.scan_n > 0 && mode != kTermsSubset) {  // the scanned predicates' terms
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+#define FARM_SCAN(B, SW)                                                                                         \
+  hipLaunchKernelGGL((k_scan_terms<B, SW>), grid, block, 0, s, sim, ld_s, q, meta, bound, ws->qn, mem->dn,       \
+                     mem->ldk, cand, cand_count, c, g, mem->n, ws->rs_terms, ws->rs_anchor, prop)
+    const bool sweep = mode == kTermsFallback;
+    if (bounded) {
+      if (sweep) FARM_SCAN(true, true);
+      else FARM_SCAN(true, false);
+    } else {
+      if (sweep) FARM_SCAN(false, true);
+      else FARM_SCAN(false, false);
+    }
+#undef FARM_SCAN
+  }
   return hipGetLastError();
 }
 
