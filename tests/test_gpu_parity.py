@@ -297,6 +297,36 @@ def test_edge_shapes(farm, n, d, rs):
     _topk_against_full(farm, mem, ws, scene, qb, s64, 10, "edge")
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 70])
+def test_scanned_predicates_degenerate(farm, n):
+    """Closest, Farthest and Inside in degenerate cases: one object (no
+    anchor), two or three objects, a target class absent from the scene
+    (empty candidate set), objects without a class (-1) and queries without
+    one; full parity with the oracle, the bound-pruned method and the TopK."""
+    from tests import _gpu
+    scene = _random_scene(n, 16, seed=100 + n)
+    scene.cls[::4] = -1  # some objects without a class
+    rng = np.random.default_rng(200 + n)
+    q = 8
+    offs, preds = [0], []
+    for k in range(q):
+        for _ in range(1 + k % 3):
+            preds.append(int(rng.choice([9, 10, 11])))
+        offs.append(len(preds))
+    # classes present in the scene, absent from it (7), and none (-1)
+    tcls = np.array([int(scene.cls[0]), 7, -1, 0, 1, 7, -1, 2], np.int32)
+    qb = QueryBatch(target=rng.standard_normal((q, 16)).astype(np.float32), target_cls=tcls,
+                    rel_off=np.asarray(offs, np.int32), rel_pred=np.asarray(preds, np.int32),
+                    rel_anchor=rng.standard_normal((len(preds), 16)).astype(np.float32),
+                    planted=np.zeros(q, np.int64))
+    mem, ws, s64 = _check_full(farm, scene, qb, f"scanned n={n}")
+    _topk_against_full(farm, mem, ws, scene, qb, s64, 10, f"scanned n={n}")
+    bd = _gpu.query_topk(mem, ws, qb, 10, with_cert=True, method=farm.BOUNDED)
+    ex = _gpu.query_topk(mem, ws, qb, 10, with_cert=True, method=farm.EXHAUSTIVE)
+    for a_, b_ in zip(bd[:4], ex[:4]):
+        np.testing.assert_array_equal(a_, b_)
+
+
 def test_k_larger_than_n_pads(farm):
     from tests import _gpu
     scene = _random_scene(7, 16, seed=1)
