@@ -6,7 +6,8 @@
   * a budget that holds one workspace at a time defers batches (and releases
     idle workspaces) instead of failing, with the same answers;
   * a budget below any workspace leaves requests pending, without errors;
-  * cancelled requests complete as cancelled and do not disturb the others.
+  * cancelled requests complete as cancelled and do not disturb the others;
+  * requests over all twelve predicates batch like the others.
 """
 import time
 
@@ -162,3 +163,34 @@ def test_invalid_requests_rejected(farm, scenes):
             sv.submit(*r)
     assert sv.progress() == (0, 0)
     sv.close()
+
+
+def test_every_predicate_mix_equals_direct(farm):
+    """Requests drawing from all twelve predicates (On, Closest, Farthest and
+    Inside included), batched across scenes: the same answers as the direct
+    library call on the same queries (BF16 learned-proposal form)."""
+    import synth
+    from tests import _gpu
+    cfg = CONFIGS["precision"]
+    scenes = []
+    for i, n in enumerate((400, 1200)):
+        sc = make_scene(cfg, seed=3200 + i, n=n)
+        qb = make_queries(cfg, sc, seed=3300 + i, q=20, preds=synth.EVERY_PRED)
+        mem = _gpu.build_memory(sc, flags=farm.FARM_BUILD_BF16)
+        scenes.append((sc, qb, mem))
+    net = farm.ProposalNet(scenes[0][0].d, max_batch=256, seed=4)
+    for _, _, mem in scenes:
+        farm.build_proposals(mem, net, 64)
+    reqs = _requests(scenes)
+    mix, stats = _run(farm, scenes, reqs, slots=2, max_batch_q=8, max_batch_rel=32, dtype=1, method=farm.PROPOSAL)
+    assert stats["batches"] < len(reqs)
+    for s, (sc, qb, mem) in enumerate(scenes):
+        ws = farm.Workspace(mem, qb.q, qb.r_tot, 16)
+        ids, sco = _gpu.query_topk(mem, ws, qb, 10, dtype=1, method=farm.PROPOSAL)[:2]
+        for (rs, tgt, *_), m in zip(reqs, mix):
+            if rs != s:
+                continue
+            assert m[0] == 0
+            qi = int(np.where((qb.target == tgt).all(axis=1))[0][0])
+            np.testing.assert_array_equal(m[2], ids[qi])
+            np.testing.assert_array_equal(m[3], sco[qi])
