@@ -25,10 +25,11 @@
 // float4 records that every lane reads as a broadcast.  Only the chunk that
 // overlaps the block's own targets carries the j != i test.
 //
-// Closest/Farthest depend on the query's candidate set, not on the pair alone:
-// k_scan_rows computes their terms first (one wave per target, scan_math.h)
-// into the relation's row of lsim (as log t), and the exhaustive kernel adds
-// that row like a Near term.
+// The scanned predicates (scan_math.h) do not fit the anchor records: Closest
+// and Farthest depend on the query's candidate set, Inside on the anchor's
+// extents.  k_scan_rows computes their terms first (one wave per target) into
+// the relation's row of lsim (as log t), and the exhaustive kernel adds that
+// row like a Near term.
 #include <math.h>
 
 #include "farm_internal.h"
@@ -97,8 +98,8 @@ __device__ void relation_pass(const float* __restrict__ arow, const float* __res
   }
 }
 
-// Closest/Farthest terms of every target for the relation rows listed in
-// meta.scan_rows: one wave per (target, row); lsim's row gets log t, and the
+// Terms of the scanned predicates (Closest, Farthest, Inside) of every target
+// for the relation rows listed in meta.scan_rows: one wave per (target, row); lsim's row gets log t, and the
 // term and anchor outputs are written here when requested.
 constexpr int kScanWaves = 4;
 

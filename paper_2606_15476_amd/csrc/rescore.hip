@@ -566,7 +566,8 @@ constexpr int kTermBlocksX = 8;  // blocks per query: 32 waves sweep a query's t
 
 enum { kTermsFull = 0, kTermsSubset = 1, kTermsFallback = 2 };
 
-// Closest/Farthest term of target o by one wave (scan_math.h).  Reduced
+// Term of a scanned predicate (Closest, Farthest, Inside) of target o by one
+// wave (scan_math.h).  Reduced
 // precision: an anchor whose upper bound (BF16/FP8 value + error bound)
 // reaches the best value so far gets its exact FP32 similarity (wave dot).
 // With the relation's semantic set (sidx, sn) and tau, the largest similarity
@@ -1222,7 +1223,7 @@ __device__ void full_term_block(const float* __restrict__ arow, const float* __r
   out_bid = bid;
 }
 
-// Closest/Farthest term of target o by a whole fallback block: its waves
+// Term of a scanned predicate of target o by a whole fallback block: its waves
 // split the semantic set and then (unless the set certifies the term) the
 // anchor scan, merging (best, id) through LDS after each phase.
 template <bool BOUNDED>
