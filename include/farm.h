@@ -130,7 +130,9 @@ typedef struct farm_workspace farm_workspace; /* per-stream scratch for scoring 
  * The library copies everything it needs; the inputs can be freed afterwards.
  * Synchronises `stream` to validate the inputs (finite values, non-zero
  * norms, positive extents, unique ids): FARM_ERR_INVALID_ARG names the first
- * violation.  Free with farm_free_memory.
+ * violation.  With classes it also keeps the objects in class order (two
+ * int32 arrays of n; a host sort of the class ids), the candidate sets of
+ * FARM_CLOSEST / FARM_FARTHEST.  Free with farm_free_memory.
  */
 FARM_API farm_status farm_build_memory(int64_t n, int32_t d, const float* desc, const float* center,
                               const float* extent, const uint32_t* id, const int32_t* cls,
