@@ -38,8 +38,10 @@
  *                    rank of i among the query's candidates (objects of its
  *                    target class; all objects without a class), by distance
  *                    to j: 1 + #{c in C, c != i, j : |c_c - c_j| < |c_i - c_j|,
- *                    equal distances by id}, m = |C minus i and j|; distances
- *                    compared as FP32 ((dx*dx + dy*dy) + dz*dz).  A rank within
+ *                    equal distances by id}, m = |C minus i and j|; squared
+ *                    distances summed in FP32 from FP32 center differences
+ *                    (within 5 * 2^-24 relative of the exact ones, so two
+ *                    candidates closer than that may take either order).  A rank within
  *                    the candidate set, scored 1 / (|rank - r*| + 1).  Cost
  *                    O(|C|) per evaluated anchor (O(N) without a class)
  *   FARM_INSIDE      prod_k sig((e_j,k / 2 - |D_k|) / 0.1): the target's center

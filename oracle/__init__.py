@@ -40,7 +40,9 @@ def build(force: bool = False) -> str:
 def _load():
     global _lib
     if _lib is None:
-        lib = ctypes.CDLL(build())
+        # FARM_ORACLE_LIB names another build of farm_oracle.c (the mutation
+        # test loads deliberately broken copies to show that the pins catch them)
+        lib = ctypes.CDLL(os.environ.get("FARM_ORACLE_LIB") or build())
         P = ctypes.c_void_p
         i64, i32 = ctypes.c_int64, ctypes.c_int32
         lib.farm_oracle_predicate.restype = ctypes.c_double
@@ -60,6 +62,8 @@ def _load():
         lib.farm_oracle_mlp.restype = ctypes.c_int
         lib.farm_oracle_mlp.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, i64, P, P, P, P,
                                         P, P, P, P, P, P, P]
+        lib.farm_oracle_set_rank_tolerance.restype = None
+        lib.farm_oracle_set_rank_tolerance.argtypes = [ctypes.c_int, ctypes.c_double]
         lib.farm_oracle_topk_bounded.restype = ctypes.c_int
         lib.farm_oracle_topk_bounded.argtypes = [i64, ctypes.c_int, P, P, P, P, P, P, i32, P, P, P, P, P,
                                                  i32, P, P, P, P, P]
@@ -78,6 +82,26 @@ def set_threads(n: int | None):
         os.environ.pop("OMP_NUM_THREADS", None)
     else:
         os.environ["OMP_NUM_THREADS"] = str(int(n))
+
+
+class rank_tolerance:
+    """Context manager: within it the rank predicates (Closest/Farthest) take
+    the lowest (mode -1) or highest (mode +1) value over every rank that
+    results when candidates whose squared distances to the anchor lie within a
+    relative ``eps`` of the target's are ordered either way (a tie-aware check
+    of an implementation that compares distances at lower precision).  Outside
+    it the rank is exact (FP64 distances, ties by id)."""
+
+    def __init__(self, mode: int, eps: float):
+        self.mode, self.eps = int(mode), float(eps)
+
+    def __enter__(self):
+        _load().farm_oracle_set_rank_tolerance(self.mode, self.eps)
+        return self
+
+    def __exit__(self, *exc):
+        _load().farm_oracle_set_rank_tolerance(0, 0.0)
+        return False
 
 
 def predicate(p: int, ci, cj, right, ei=(0.0, 0.0, 0.0), ej=(0.0, 0.0, 0.0)) -> float:

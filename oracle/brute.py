@@ -12,8 +12,7 @@ Appendix "Retrieval Details", composite-scoring step:
 
 Each relation's term folds the anchor's own description match sim(a, q_r)
 into the relational score (the anchor's unary predicate and the relation share
-the anchor variable).  Pure Python on math.* in double precision (the rank of
-Closest/Farthest is decided in FP32, see ``rank_relation``); it shares no code
+the anchor variable).  Pure Python on math.* in double precision; it shares no code
 with ``farm_oracle.c`` and costs O(N^(R+1)) -- use N <= 16, R <= 3.
 """
 from __future__ import annotations
@@ -82,18 +81,14 @@ def soft_relation(pred, ci, cj, right, ei=(0.0, 0.0, 0.0), ej=(0.0, 0.0, 0.0)):
 def rank_relation(pred, scene, tcls, i, j):
     """Closest (9) / Farthest (10): 1 / (|rank - r*| + 1), the rank of target i
     among the query's candidates (objects of class tcls; all objects without a
-    class) by distance to anchor j, nearer first, equal distances by id.  The
-    distances are compared in FP32 in the order ((dx*dx + dy*dy) + dz*dz), as
-    the scorers decide the rank."""
-    c = scene.center.astype(np.float32)
+    class) by Euclidean distance to anchor j, nearer first, equal distances by
+    id; r* = 1 for Closest and the last rank for Farthest."""
+    c = [[float(v) for v in row] for row in scene.center]
 
-    def d2(a, b):
-        dx, dy, dz = c[a, 0] - c[b, 0], c[a, 1] - c[b, 1], c[a, 2] - c[b, 2]
-        s = dx * dx
-        s = s + dy * dy
-        return s + dz * dz
+    def dist(a, b):
+        return math.sqrt(sum((c[a][k] - c[b][k]) ** 2 for k in range(3)))
 
-    dij = d2(i, j)
+    dij = dist(i, j)
     nearer = m = 0
     for k in range(scene.desc.shape[0]):
         if k in (i, j):
@@ -101,7 +96,7 @@ def rank_relation(pred, scene, tcls, i, j):
         if tcls >= 0 and scene.cls is not None and int(scene.cls[k]) != tcls:
             continue
         m += 1
-        dk = d2(k, j)
+        dk = dist(k, j)
         if dk < dij or (dk == dij and int(scene.ids[k]) < int(scene.ids[i])):
             nearer += 1
     rank = nearer + 1

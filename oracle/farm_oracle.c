@@ -142,7 +142,6 @@ typedef struct {
     double* u;        /* [n][d] normalised descriptors */
     double* c;        /* [n][3] centers */
     double* e;        /* [n][3] full extents */
-    const float* cf;  /* [n][3] centers as given (FP32), for the rank predicates */
     const uint32_t* id;
     const int32_t* cls;
     double right[2];
@@ -161,7 +160,6 @@ static int scene_init(scene64* s, int64_t n, int d, const float* desc, const flo
         for (int k = 0; k < 3; ++k) s->c[i * 3 + k] = center[i * 3 + k];
         for (int k = 0; k < 3; ++k) s->e[i * 3 + k] = extent[i * 3 + k];
     }
-    s->cf = center;
     s->id = id;
     s->cls = cls;
     s->right[0] = right[0];
@@ -219,35 +217,52 @@ static void query_free(query64* qs) {
  * query or the scene has no class); for target i and anchor j the rank is one
  * plus the number of other candidates c (c != i, c != j) nearer to j than i,
  * equal distances ordered by object id; r* = 1 for Closest and the last rank,
- * |C minus i and j| + 1, for Farthest.  The rank is an integer decided by
- * comparing distances, so it is decided in FP32 in one fixed order, the
- * precision the GPU uses: ((dx*dx + dy*dy) + dz*dz) of FP32 center
- * differences (this file is compiled without contraction). */
-static float dist2_f32(const float* c, int64_t a, int64_t b) {
-    float dx = c[a * 3] - c[b * 3];
-    float dy = c[a * 3 + 1] - c[b * 3 + 1];
-    float dz = c[a * 3 + 2] - c[b * 3 + 2];
-    float d2 = dx * dx;
-    d2 = d2 + dy * dy;
-    d2 = d2 + dz * dz;
-    return d2;
+ * |C minus i and j| + 1, for Farthest.  Distances are the Euclidean distances
+ * of the box centers, compared as squared distances in double precision from
+ * the double differences of the float centers. */
+static double dist2(const double* c, int64_t a, int64_t b) {
+    double dx = c[a * 3] - c[b * 3];
+    double dy = c[a * 3 + 1] - c[b * 3 + 1];
+    double dz = c[a * 3 + 2] - c[b * 3 + 2];
+    return dx * dx + dy * dy + dz * dz;
 }
 
 static int is_rank_pred(int p) { return p == P_CLOSEST || p == P_FARTHEST; }
 
+/* Tie-aware mode of the rank predicates, for checking another implementation
+ * that compares distances at a lower precision (a check, not a reading of the
+ * paper).  mode 0 (default): the exact rank above.  mode -1 / +1: every
+ * candidate whose squared distance to j lies within a relative rank_eps of
+ * i's, |d_c - d_i| <= rank_eps (d_c + d_i), may be ordered either way; the
+ * value returned is the lowest / highest 1 / (|rank - r*| + 1) over the ranks
+ * this allows.  Set per call by farm_oracle_set_rank_tolerance. */
+static int g_rank_mode = 0;
+static double g_rank_eps = 0.0;
+
+void farm_oracle_set_rank_tolerance(int mode, double eps) {
+    g_rank_mode = mode < 0 ? -1 : (mode > 0 ? 1 : 0);
+    g_rank_eps = eps > 0.0 ? eps : 0.0;
+}
+
 static double rank_value(const scene64* s, int32_t tcls, int p, int64_t i, int64_t j) {
-    float dij = dist2_f32(s->cf, i, j);
-    int64_t nearer = 0, m = 0;
+    double dij = dist2(s->c, i, j);
+    int64_t nearer = 0, open = 0, m = 0;
     for (int64_t c = 0; c < s->n; ++c) {
         if (c == i || c == j) continue;
         if (tcls >= 0 && s->cls && s->cls[c] != tcls) continue;
         ++m;
-        float dc = dist2_f32(s->cf, c, j);
+        double dc = dist2(s->c, c, j);
+        if (g_rank_mode != 0 && fabs(dc - dij) <= g_rank_eps * (dc + dij)) { ++open; continue; }
         if (dc < dij || (dc == dij && s->id[c] < s->id[i])) ++nearer;
     }
-    int64_t rank = nearer + 1;
     int64_t rstar = p == P_CLOSEST ? 1 : m + 1;
-    int64_t off = rank > rstar ? rank - rstar : rstar - rank;
+    int64_t lo = nearer + 1, hi = nearer + 1 + open;  /* the ranks i can take */
+    int64_t dlo = lo > rstar ? lo - rstar : rstar - lo;
+    int64_t dhi = hi > rstar ? hi - rstar : rstar - hi;
+    int64_t off;
+    if (g_rank_mode < 0) off = dlo > dhi ? dlo : dhi;                       /* farthest from r* */
+    else if (g_rank_mode > 0) off = (lo <= rstar && rstar <= hi) ? 0 : (dlo < dhi ? dlo : dhi);
+    else off = dlo;                                                           /* open = 0: lo = hi */
     return 1.0 / (double)(off + 1);
 }
 
@@ -522,10 +537,13 @@ double farm_oracle_binding_value(int64_t n, int d, const float* desc, const floa
         scene64 s0;
         memset(&s0, 0, sizeof(s0));
         s0.n = n;
-        s0.cf = center;
+        s0.c = (double*)malloc(sizeof(double) * (size_t)n * 3);
+        if (!s0.c) { free(u); free(v); return NAN; }
+        for (int64_t k = 0; k < n * 3; ++k) s0.c[k] = center[k];
         s0.id = id;
         s0.cls = cls;
         val = a * rank_value(&s0, tcls, p, i, j);
+        free(s0.c);
     } else {
         val = a * oracle_predicate(p, ci, cj, ei, ej, r);
     }

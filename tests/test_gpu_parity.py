@@ -13,7 +13,8 @@ import pytest
 import oracle
 from synth import CONFIGS, QueryBatch, Scene, make_queries, make_scene
 from tests import _golden
-from tests._parity import ABS, REL, assert_topk_valid, assert_values_close
+from tests._parity import (ABS, RANK_EPS, RANK_PREDS, REL, assert_topk_valid, assert_topk_valid_bounds,
+                           assert_values_close, assert_values_within, oracle_bounds)
 
 pytestmark = pytest.mark.gpu
 
@@ -29,42 +30,64 @@ def _ws(farm, mem, qb, max_k=64):
 
 
 def _check_full(farm, scene, qb, label):
+    """Full score matrix, relation terms and bound anchors against the oracle;
+    returns (mem, ws, full) with full = (s64, s_lo, s_hi): exact scores and the
+    interval the rank predicates' open orders allow (equal without them)."""
     from tests import _gpu
     mem = _gpu.build_memory(scene)
     ws = _ws(farm, mem, qb)
     s, t, b = _gpu.score_full(mem, ws, qb, terms=True)
-    s64, sem64, t64, b64 = oracle.score(scene, qb, terms=True)
+    s64, sem64, t64, b64, s_lo, s_hi, t_lo, t_hi = oracle_bounds(scene, qb)
     print(f"[{label}] n={scene.n} d={scene.d} q={qb.q} R={qb.r_tot}", flush=True)
-    assert_values_close(s, s64, f"{label} scores")
+    assert_values_within(s, s_lo, s_hi, f"{label} scores")
     if qb.r_tot:
-        assert_values_close(t, t64, f"{label} relation terms")
+        assert_values_within(t, t_lo, t_hi, f"{label} relation terms")
         # every bound anchor attains its term (within tolerance), never the target itself
         idx_of = {int(v): i for i, v in enumerate(scene.ids)}
         rng = np.random.default_rng(0)
         for r in range(qb.r_tot):
             cols = rng.choice(scene.n, size=min(scene.n, 24), replace=False)
+            qq = int(np.searchsorted(qb.rel_off, r, side="right")) - 1
+            p = int(qb.rel_pred[r])
             for i in cols:
                 if scene.n == 1:
                     assert b[r, i] == 0xFFFFFFFF
                     continue
                 j = idx_of[int(b[r, i])]
                 assert j != i
-                qq = int(np.searchsorted(qb.rel_off, r, side="right")) - 1
-                v = oracle.binding_value(scene, int(qb.rel_pred[r]), qb.rel_anchor[r], int(i), j,
-                                         int(qb.target_cls[qq]))
-                assert abs(v - t64[r, i]) <= REL * t64[r, i] + ABS, (label, r, i)
-    return mem, ws, s64
+                args = (scene, p, qb.rel_anchor[r], int(i), j, int(qb.target_cls[qq]))
+                if p in RANK_PREDS:
+                    with oracle.rank_tolerance(-1, RANK_EPS):
+                        v_lo = oracle.binding_value(*args)
+                    with oracle.rank_tolerance(+1, RANK_EPS):
+                        v_hi = oracle.binding_value(*args)
+                    assert v_lo - REL * v_lo - ABS <= t[r, i] <= v_hi + REL * v_hi + ABS, (label, r, i)
+                else:
+                    v = oracle.binding_value(*args)
+                    assert abs(v - t64[r, i]) <= REL * t64[r, i] + ABS, (label, r, i)
+    return mem, ws, (s64, s_lo, s_hi)
 
 
-def _topk_against_full(farm, mem, ws, scene, qb, s64, k, label):
+def _check_topk_rows(scene, ids, sc, full, k, rows=None):
+    """GPU TopK rows against full oracle score rows: exact where no rank order is
+    open (lo == hi over the row), else the interval check."""
+    s64, s_lo, s_hi = full
+    rows = range(len(s64)) if rows is None else rows
+    for row, qq in enumerate(rows):
+        if np.array_equal(s_lo[row], s_hi[row]):
+            order = oracle.topk(s64[row], scene.ids, min(k + 8, scene.n))
+            o_ids = scene.ids[order[order >= 0]]
+            o_sc = s64[row, order[order >= 0]]
+            by_id = {int(v): s64[row, i] for i, v in enumerate(scene.ids)}
+            assert_topk_valid(ids[qq], sc[qq], o_ids, o_sc, lambda g: by_id[g], k)
+        else:
+            assert_topk_valid_bounds(ids[qq], sc[qq], scene.ids, s_lo[row], s_hi[row], k)
+
+
+def _topk_against_full(farm, mem, ws, scene, qb, full, k, label):
     from tests import _gpu
     ids, sc, terms, anch = _gpu.query_topk(mem, ws, qb, k)
-    for qq in range(qb.q):
-        order = oracle.topk(s64[qq], scene.ids, min(k + 8, scene.n))
-        o_ids = scene.ids[order[order >= 0]]
-        o_sc = s64[qq, order[order >= 0]]
-        by_id = {int(v): s64[qq, i] for i, v in enumerate(scene.ids)}
-        assert_topk_valid(ids[qq], sc[qq], o_ids, o_sc, lambda g: by_id[g], k)
+    _check_topk_rows(scene, ids, sc, full, k)
     return ids, sc, terms, anch
 
 
@@ -97,16 +120,16 @@ def test_tiny_config_full_parity(farm):
     cfg = CONFIGS["tiny"]
     scene = make_scene(cfg)
     qb = make_queries(cfg, scene)
-    mem, ws, s64 = _check_full(farm, scene, qb, "tiny")
-    _topk_against_full(farm, mem, ws, scene, qb, s64, cfg.k, "tiny")
+    mem, ws, full = _check_full(farm, scene, qb, "tiny")
+    _topk_against_full(farm, mem, ws, scene, qb, full, cfg.k, "tiny")
 
 
 def test_mid_config_subset_full_parity(farm):
     cfg = CONFIGS["mid"]
     scene = make_scene(cfg)
     qb = make_queries(cfg, scene).subset(range(0, 256, 8))  # 32 queries, all predicate mixes
-    mem, ws, s64 = _check_full(farm, scene, qb, "mid/32")
-    ids, sc, terms, anch = _topk_against_full(farm, mem, ws, scene, qb, s64, cfg.k, "mid/32")
+    mem, ws, full = _check_full(farm, scene, qb, "mid/32")
+    ids, sc, terms, anch = _topk_against_full(farm, mem, ws, scene, qb, full, cfg.k, "mid/32")
     # ScoredCandidate breakdown: terms of the returned objects match the oracle's
     idx_of = {int(v): i for i, v in enumerate(scene.ids)}
     _, _, t64, _ = oracle.score(scene, qb, terms=True)
@@ -128,8 +151,8 @@ def test_all_predicates_full_parity(farm):
     scene = make_scene(cfg, seed=21)
     qb = make_queries(cfg, scene, seed=22, q=48, preds=synth.ALL_PREDS)
     assert set(np.unique(qb.rel_pred)) == set(synth.ALL_PREDS)
-    mem, ws, s64 = _check_full(farm, scene, qb, "mid/all predicates")
-    _topk_against_full(farm, mem, ws, scene, qb, s64, cfg.k, "mid/all predicates")
+    mem, ws, full = _check_full(farm, scene, qb, "mid/all predicates")
+    _topk_against_full(farm, mem, ws, scene, qb, full, cfg.k, "mid/all predicates")
 
 
 def _rank_world(seed, n=700, q=24):
@@ -150,8 +173,8 @@ def test_rank_predicates_full_parity(farm):
     pairwise predicates, exhaustive FP32 method: full score matrix,
     per-relation terms and bindings, TopK and breakdown against the oracle."""
     cfg, scene, qb = _rank_world(31)
-    mem, ws, s64 = _check_full(farm, scene, qb, "rank predicates")
-    _topk_against_full(farm, mem, ws, scene, qb, s64, cfg.k, "rank predicates")
+    mem, ws, full = _check_full(farm, scene, qb, "rank predicates")
+    _topk_against_full(farm, mem, ws, scene, qb, full, cfg.k, "rank predicates")
 
 
 @pytest.mark.parametrize("dtype", [0, 1], ids=["f32", "bf16"])
@@ -163,17 +186,18 @@ def test_rank_predicates_bounded_and_precision(farm, dtype):
     cfg, scene, qb = _rank_world(33)
     mem = _gpu.build_memory(scene, flags=farm.FARM_BUILD_BF16)
     ws = _ws(farm, mem, qb)
-    oidx, osc, ot, ob, ns = oracle.topk_bounded(scene, qb, cfg.k + 8)
+    s64, _, _, _, s_lo, s_hi, _, _ = oracle_bounds(scene, qb)
     bd = _gpu.query_topk(mem, ws, qb, cfg.k, dtype=dtype, with_cert=True, method=farm.BOUNDED)
     assert np.all(bd[4] == 1)
-    _check_bounded(scene, qb, bd[0], bd[1], oidx, osc, cfg.k)
+    _check_topk_rows(scene, bd[0], bd[1], (s64, s_lo, s_hi), cfg.k)
     ex = _gpu.query_topk(mem, ws, qb, cfg.k, dtype=dtype, with_cert=True, method=farm.EXHAUSTIVE)
     # the precision form certifies a query when its rescored set provably holds
     # the TopK; the rank terms' ladder of values 1/k can leave a query without
     # that proof (flagged, not wrong): certified queries must be exact
     cert_rows = [qq for qq in range(qb.q) if ex[4][qq] == 1]
     assert len(cert_rows) >= qb.q - 3, ex[4]
-    _check_bounded(scene, qb, ex[0], ex[1], oidx[cert_rows], osc[cert_rows], cfg.k, rows=cert_rows)
+    _check_topk_rows(scene, ex[0], ex[1], (s64[cert_rows], s_lo[cert_rows], s_hi[cert_rows]), cfg.k,
+                     rows=cert_rows)
     if dtype == 0:
         assert len(cert_rows) == qb.q
         for a, b in zip(bd[:4], ex[:4]):
@@ -293,8 +317,8 @@ def _random_queries(scene, q, rs, seed):
 def test_edge_shapes(farm, n, d, rs):
     scene = _random_scene(n, d, seed=n + d)
     qb = _random_queries(scene, 6, rs, seed=n)
-    mem, ws, s64 = _check_full(farm, scene, qb, f"edge n={n} d={d}")
-    _topk_against_full(farm, mem, ws, scene, qb, s64, 10, "edge")
+    mem, ws, full = _check_full(farm, scene, qb, f"edge n={n} d={d}")
+    _topk_against_full(farm, mem, ws, scene, qb, full, 10, "edge")
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 70])
@@ -319,8 +343,8 @@ def test_scanned_predicates_degenerate(farm, n):
                     rel_off=np.asarray(offs, np.int32), rel_pred=np.asarray(preds, np.int32),
                     rel_anchor=rng.standard_normal((len(preds), 16)).astype(np.float32),
                     planted=np.zeros(q, np.int64))
-    mem, ws, s64 = _check_full(farm, scene, qb, f"scanned n={n}")
-    _topk_against_full(farm, mem, ws, scene, qb, s64, 10, f"scanned n={n}")
+    mem, ws, full = _check_full(farm, scene, qb, f"scanned n={n}")
+    _topk_against_full(farm, mem, ws, scene, qb, full, 10, f"scanned n={n}")
     bd = _gpu.query_topk(mem, ws, qb, 10, with_cert=True, method=farm.BOUNDED)
     ex = _gpu.query_topk(mem, ws, qb, 10, with_cert=True, method=farm.EXHAUSTIVE)
     for a_, b_ in zip(bd[:4], ex[:4]):

@@ -146,7 +146,8 @@ def test_rank_predicates(farm, dtype):
     full-scan fallback (LDS-staged and global-memory forms of the pass); results stay
     bit-identical to BOUNDED, which equals the exact TopK."""
     from tests import _gpu
-    from tests.test_gpu_parity import _check_bounded, _rank_world
+    from tests._parity import oracle_bounds
+    from tests.test_gpu_parity import _check_topk_rows, _rank_world
     cfg, scene, qb = _rank_world(35)
     mem = _gpu.build_memory(scene, flags=farm.FARM_BUILD_BF16)
     ws = farm.Workspace(mem, qb.q, qb.r_tot, 64)
@@ -155,8 +156,8 @@ def test_rank_predicates(farm, dtype):
     checked, fell = _compare(farm, mem, ws, qb, cfg.k, dtype)
     ids, sc, _, _, cert = _gpu.query_topk(mem, ws, qb, cfg.k, dtype=dtype, with_cert=True, method=farm.BOUNDED)
     assert np.all(cert == 1)
-    oidx, osc, ot, ob, ns = oracle.topk_bounded(scene, qb, cfg.k + 8)
-    _check_bounded(scene, qb, ids, sc, oidx, osc, cfg.k)
+    s64, _, _, _, s_lo, s_hi, _, _ = oracle_bounds(scene, qb)
+    _check_topk_rows(scene, ids, sc, (s64, s_lo, s_hi), cfg.k)
     print(f"[proposal rank predicates dtype={dtype}] terms {checked}, fell back {fell}", flush=True)
     assert checked > 0 and fell > 0
 

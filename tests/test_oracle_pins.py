@@ -269,6 +269,90 @@ def test_rank_values_are_a_permutation():
         np.testing.assert_allclose(np.asarray(vals_f)[order], [1 / (m - k) for k in range(m)], rtol=1e-12)
 
 
+def _exact_rank_value(scene, pred, tcls, i, j):
+    """1 / (|rank - r*| + 1) with squared distances in exact rational arithmetic
+    from the float32 centers (a check independent of floating point)."""
+    from fractions import Fraction
+    c = [[Fraction(float(v)) for v in row] for row in scene.center]
+    d2 = lambda a, b: sum((c[a][k] - c[b][k]) ** 2 for k in range(3))
+    dij = d2(i, j)
+    nearer = m = 0
+    for k in range(scene.n):
+        if k in (i, j) or (tcls >= 0 and int(scene.cls[k]) != tcls):
+            continue
+        m += 1
+        dk = d2(k, j)
+        nearer += dk < dij or (dk == dij and int(scene.ids[k]) < int(scene.ids[i]))
+    rstar = 1 if pred == CLOSEST else m + 1
+    return 1.0 / (abs(nearer + 1 - rstar) + 1)
+
+
+def _near_tie_scene():
+    """An anchor at the origin; chair A at x = 1 m and chair B at
+    (1 - 2^-24, y) with y the float just above sqrt(2^-23 - 2^-48): exactly,
+    |B|^2 = 1 + a few 2^-49 > 1 = |A|^2, but the float32 sum of squares of B
+    rounds to exactly 1 (a tie that the smaller id of B would win)."""
+    y = np.nextafter(np.float32(math.sqrt(2.0 ** -23 - 2.0 ** -48)), np.float32(1))
+    center = np.array([[0, 0, 0], [1, 0, 0], [1 - 2.0 ** -24, y, 0], [3, 0, 0]], np.float32)
+    d = 4
+    e = np.eye(d, dtype=np.float32)
+    scene = Scene(desc=np.stack([e[1], e[0], e[0], e[0]]), center=center, extent=np.full((4, 3), 0.5, np.float32),
+                  ids=np.array([7, 20, 10, 30], np.uint32), cls=np.array([2, 1, 1, 1], np.int32),
+                  view_right=np.array([1, 0], np.float32), centroids=np.zeros((1, d), np.float32))
+    return scene, e
+
+
+def test_rank_near_tie_is_exact():
+    """The rank follows the exact distances even where float32 sums of squares
+    tie; the tolerance mode opens exactly that pair."""
+    from fractions import Fraction
+    scene, e = _near_tie_scene()
+    xa, xb, yb = (Fraction(float(v)) for v in (scene.center[1, 0], scene.center[2, 0], scene.center[2, 1]))
+    assert xb * xb + yb * yb > xa * xa  # B is farther, exactly
+    c32 = scene.center.astype(np.float32)
+    f32 = lambda v: np.float32(v[0]) * np.float32(v[0]) + np.float32(v[1]) * np.float32(v[1])
+    assert f32(c32[2]) == f32(c32[1]) == np.float32(1)  # ... but float32 sums tie
+    anchor = e[1]
+    # Closest among the chairs by distance to the anchor (index 0): A first, B second
+    assert oracle.binding_value(scene, CLOSEST, anchor, 1, 0, 1) == 1.0
+    assert oracle.binding_value(scene, CLOSEST, anchor, 2, 0, 1) == 0.5
+    assert oracle.binding_value(scene, FARTHEST, anchor, 2, 0, 1) == 0.5
+    # tolerance mode: A and B may take either order, the far chair may not
+    for i, hi, lo in ((1, 1.0, 0.5), (2, 1.0, 0.5)):
+        with oracle.rank_tolerance(+1, 1e-6):
+            assert oracle.binding_value(scene, CLOSEST, anchor, i, 0, 1) == hi
+        with oracle.rank_tolerance(-1, 1e-6):
+            assert oracle.binding_value(scene, CLOSEST, anchor, i, 0, 1) == lo
+    with oracle.rank_tolerance(-1, 1e-6):
+        assert oracle.binding_value(scene, CLOSEST, anchor, 3, 0, 1) == 1 / 3
+    # outside the context manager the exact rank is back
+    assert oracle.binding_value(scene, CLOSEST, anchor, 2, 0, 1) == 0.5
+
+
+def test_rank_matches_rational_arithmetic():
+    """Closest/Farthest values of random bindings (objects on a coarse grid, so
+    that exact distance ties occur and are ordered by id) equal the rank taken
+    with exact rational squared distances."""
+    rng = np.random.default_rng(51)
+    n, d = 40, 6
+    scene = Scene(desc=rng.standard_normal((n, d)).astype(np.float32),
+                  center=(rng.integers(0, 5, (n, 3)) * 0.5).astype(np.float32),
+                  extent=np.full((n, 3), 0.3, np.float32), ids=(rng.permutation(3 * n)[:n] + 1).astype(np.uint32),
+                  cls=rng.integers(0, 3, n).astype(np.int32), view_right=np.array([0, -1], np.float32),
+                  centroids=np.zeros((1, d), np.float32))
+    ties = 0
+    for _ in range(60):
+        i, j = (int(x) for x in rng.choice(n, 2, replace=False))
+        tcls = int(rng.integers(-1, 3))
+        anchor = scene.desc[j]
+        for pred in (CLOSEST, FARTHEST):  # the anchor's own descriptor: sim(j, q_r) = 1
+            got = oracle.binding_value(scene, pred, anchor, i, j, tcls)
+            assert got == pytest.approx(_exact_rank_value(scene, pred, tcls, i, j), rel=1e-12)
+        dij = np.sum((scene.center[i] - scene.center[j]).astype(np.float64) ** 2)
+        ties += int(np.sum(np.sum((scene.center - scene.center[j]).astype(np.float64) ** 2, axis=1) == dij) > 2)
+    assert ties > 0  # the grid produced exact distance ties
+
+
 # ---------------------------------------------------------------- hand scenes
 @pytest.mark.parametrize("path", _golden.all_paths(), ids=lambda p: p.rsplit("/", 1)[-1])
 def test_golden_scenes(path):
