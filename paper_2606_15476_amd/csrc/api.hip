@@ -74,27 +74,73 @@ void free_all(std::vector<void*>& allocs) {
     if (e_ != hipSuccess) return hip_fail(e_, what); \
   } while (0)
 
-size_t workspace_bytes_for(const farm_memory* mem, int32_t max_q, int32_t max_rel, int32_t max_k) {
-  size_t rows = (size_t)max_q + (size_t)max_rel;
-  size_t ld_s = (size_t)round_up(mem->n, kRowAlign);
-  size_t b = 0;
-  b += rows * mem->ldk * sizeof(float);                    // qn
-  if (mem->dn_bf16) b += rows * mem->ldk * sizeof(uint16_t) + 2 * rows * sizeof(float);
-  if (mem->dn_fp8) b += rows * mem->ldk + 3 * rows * sizeof(float);
-  b += rows * ld_s * sizeof(float);                         // sim
-  b += (size_t)(max_rel > 0 ? max_rel : 1) * ld_s * sizeof(float);  // log similarities
-  b += (size_t)max_q * ld_s * sizeof(float) * ((mem->dn_bf16 || mem->dn_fp8) ? 2 : 1);  // scores (+ bounds)
-  b += (size_t)(2 * max_q + 1 + 2 * (size_t)max_rel) * sizeof(int32_t);
-  b += sizeof(int);
-  b += 2 * (size_t)topk_candidate_capacity(mem->n, max_q, max_k + 1) * (sizeof(uint64_t) + sizeof(int32_t));
-  b += 2 * sizeof(float);
-  const size_t cap = (size_t)(max_k > kBoundCap ? max_k : kBoundCap);
-  b += (size_t)max_q * cap * (sizeof(int32_t) + sizeof(float) + kMaxRel * (sizeof(float) + sizeof(uint32_t)));
-  b += (size_t)max_q * sizeof(int32_t);
+// The workspace's device buffers, in one place for the three ways a workspace
+// is laid out: hipMalloc per buffer (farm_workspace_create), a byte count
+// (farm_workspace_estimate) and bump allocation inside the library's static
+// scratch array (farm_query_topk_static).  alloc(T** p, size_t count, const
+// char* what) returns a farm_status.
+template <class Alloc>
+farm_status layout_workspace(farm_workspace* ws, const farm_memory* mem, int32_t max_q, int32_t max_rel,
+                             int32_t max_k, Alloc&& alloc) {
+  ws->mem = mem;
+  ws->device = mem->device;
+  ws->max_q = max_q;
+  ws->max_rel = max_rel;
+  ws->ld_s = round_up(mem->n, kRowAlign);
+  const size_t rows = (size_t)max_q + (size_t)max_rel;
   const size_t rel1 = (size_t)(max_rel > 0 ? max_rel : 1);
-  b += rel1 * (kSemMax * (sizeof(int32_t) + sizeof(float)) + sizeof(int32_t) + sizeof(float));  // semantic sets
-  b += 4 * sizeof(unsigned long long);
-  b += (size_t)fallback_cap(max_q) * sizeof(unsigned long long) + sizeof(uint32_t);  // fallback worklist
+  FARM_TRY(alloc(&ws->qn, rows * mem->ldk, "query vectors"));
+  if (mem->dn_bf16) {
+    FARM_TRY(alloc(&ws->qn_bf16, rows * mem->ldk, "BF16 query vectors"));
+    FARM_TRY(alloc(&ws->qerr_bf16, rows, "BF16 query error norms"));
+    FARM_TRY(alloc(&ws->qnrm_bf16, rows, "BF16 query norms"));
+  }
+  if (mem->dn_fp8) {
+    FARM_TRY(alloc(&ws->qn_fp8, rows * mem->ldk, "FP8 query vectors"));
+    FARM_TRY(alloc(&ws->qn_scale, rows, "FP8 query scales"));
+    FARM_TRY(alloc(&ws->qerr_fp8, rows, "FP8 query error norms"));
+    FARM_TRY(alloc(&ws->qnrm_fp8, rows, "FP8 query norms"));
+  }
+  FARM_TRY(alloc(&ws->sim, rows * ws->ld_s, "similarity matrix"));
+  FARM_TRY(alloc(&ws->lsim, rel1 * ws->ld_s, "log similarities"));
+  FARM_TRY(alloc(&ws->scores, (size_t)max_q * ws->ld_s, "scores"));
+  if (mem->dn_bf16 || mem->dn_fp8) FARM_TRY(alloc(&ws->scores_hi, (size_t)max_q * ws->ld_s, "score bounds"));
+  ws->meta_len = 2 * (int64_t)max_q + 1 + 3 * (int64_t)max_rel;
+  FARM_TRY(alloc(&ws->d_meta, (size_t)ws->meta_len, "metadata"));
+  FARM_TRY(alloc(&ws->status, 1, "status"));
+  ws->cand_cap = topk_candidate_capacity(mem->n, max_q, max_k + 1);
+  for (int b = 0; b < 2; ++b) {
+    FARM_TRY(alloc(&ws->cand_key[b], (size_t)ws->cand_cap, "TopK keys"));
+    FARM_TRY(alloc(&ws->cand_idx[b], (size_t)ws->cand_cap, "TopK indices"));
+  }
+  ws->max_k = max_k;
+  ws->rs_cap = max_k > kBoundCap ? max_k : kBoundCap;
+  const size_t nk = (size_t)max_q * ws->rs_cap;
+  FARM_TRY(alloc(&ws->cand_count, (size_t)max_q, "candidate counts"));
+  FARM_TRY(alloc(&ws->rs_idx, nk, "winner indices"));
+  FARM_TRY(alloc(&ws->rs_score, nk, "rescored scores"));
+  FARM_TRY(alloc(&ws->rs_terms, nk * kMaxRel, "rescored terms"));
+  FARM_TRY(alloc(&ws->rs_anchor, nk * kMaxRel, "rescored anchors"));
+  FARM_TRY(alloc(&ws->sem_idx, rel1 * kSemMax, "semantic sets"));
+  FARM_TRY(alloc(&ws->sem_cnt, rel1, "semantic set sizes"));
+  FARM_TRY(alloc(&ws->sem_tau, rel1, "semantic bounds"));
+  FARM_TRY(alloc(&ws->sem_sim, rel1 * kSemMax, "semantic similarities"));
+  FARM_TRY(alloc(&ws->prop_stats, 4, "proposal counters"));
+  ws->fb_cap = fallback_cap(max_q);
+  FARM_TRY(alloc(&ws->fb_list, (size_t)ws->fb_cap, "fallback worklist"));
+  FARM_TRY(alloc(&ws->fb_count, 1, "fallback count"));
+  return FARM_OK;
+}
+
+// Device bytes of a workspace of this shape (what farm_workspace_create allocates).
+size_t workspace_bytes_for(const farm_memory* mem, int32_t max_q, int32_t max_rel, int32_t max_k) {
+  farm_workspace tmp;
+  size_t b = 0;
+  (void)layout_workspace(&tmp, mem, max_q, max_rel, max_k, [&](auto** p, size_t count, const char*) {
+    b += (count ? count : 1) * sizeof(**p);
+    *p = nullptr;
+    return FARM_OK;
+  });
   return b;
 }
 
@@ -242,6 +288,169 @@ farm_status similarities(const farm_memory* mem, farm_workspace* ws, int32_t q, 
   }
   if (need_log)
     FARM_HIP(launch_log_rows(ws->sim + (int64_t)q * ws->ld_s, ws->ld_s, R, mem->n, ws->lsim, s), "log similarities");
+  return FARM_OK;
+}
+
+// Options of the fused path, checked against the memory: dtype, method, flags
+// and the number c of candidates that leave the first TopK (rescore_mult * k
+// for the reduced-precision exhaustive form, else k).
+struct TopkPlan {
+  int32_t dtype = FARM_F32, method = FARM_METHOD_EXHAUSTIVE, opt_flags = 0, c = 0;
+  int32_t* certified = nullptr;
+};
+
+farm_status plan_topk(const farm_memory* mem, const farm_score_opts* opts, int32_t k, TopkPlan* plan) {
+  if (k < 1 || k > FARM_MAX_K) { set_error("k = %d outside [1, %d]", k, FARM_MAX_K); return FARM_ERR_INVALID_ARG; }
+  const int32_t dtype = opts ? opts->dtype : FARM_F32;
+  const int32_t method = opts ? opts->method : FARM_METHOD_EXHAUSTIVE;
+  if (method != FARM_METHOD_EXHAUSTIVE && method != FARM_METHOD_BOUNDED && method != FARM_METHOD_PROPOSAL) {
+    set_error("unknown method %d", method);
+    return FARM_ERR_INVALID_ARG;
+  }
+  if (method == FARM_METHOD_PROPOSAL && mem->prop_m == 0 && mem->n >= 2) {
+    set_error("method PROPOSAL needs farm_build_proposals on this memory");
+    return FARM_ERR_UNSUPPORTED;
+  }
+  const int32_t opt_flags = opts ? opts->flags : 0;
+  if (opt_flags & ~FARM_OPT_GLOBAL_PROPOSAL_PASS) {
+    set_error("unknown option flags 0x%x", opt_flags);
+    return FARM_ERR_INVALID_ARG;
+  }
+  if (dtype != FARM_F32 && dtype != FARM_BF16 && dtype != FARM_FP8_E4M3) {
+    set_error("unknown dtype %d", dtype);
+    return FARM_ERR_INVALID_ARG;
+  }
+  if ((dtype == FARM_BF16 && !mem->dn_bf16) || (dtype == FARM_FP8_E4M3 && !mem->dn_fp8)) {
+    set_error("memory was built without the %s copy", dtype == FARM_BF16 ? "BF16" : "FP8");
+    return FARM_ERR_UNSUPPORTED;
+  }
+  int32_t c = k;
+  if (dtype != FARM_F32 && method == FARM_METHOD_EXHAUSTIVE) {
+    const int32_t mult = opts->rescore_mult;
+    if (mult < 1) { set_error("rescore_mult = %d must be >= 1", mult); return FARM_ERR_INVALID_ARG; }
+    if ((int64_t)mult * k > FARM_MAX_K) {
+      set_error("rescore_mult * k = %lld exceeds %d", (long long)mult * k, FARM_MAX_K);
+      return FARM_ERR_INVALID_ARG;
+    }
+    c = mult * k;
+  }
+  plan->dtype = dtype;
+  plan->method = method;
+  plan->opt_flags = opt_flags;
+  plan->c = c;
+  plan->certified = opts ? opts->certified : nullptr;
+  return FARM_OK;
+}
+
+// Steps 2-5 of the fused path once the metadata is on the device: shared by
+// farm_query_topk (a created workspace) and farm_query_topk_static (a
+// workspace laid out in the static scratch array).
+farm_status query_topk_core(const farm_memory* mem, farm_workspace* ws, int32_t q, int32_t R, const float* target,
+                            const float* rel_anchor, const MetaView& meta, const TopkPlan& plan, int32_t k,
+                            uint32_t* out_id, float* out_score, float* out_terms, uint32_t* out_anchor_id,
+                            hipStream_t s) {
+  const int32_t dtype = plan.dtype, method = plan.method, opt_flags = plan.opt_flags, c = plan.c;
+  int32_t* certified = plan.certified;
+  SimBound bound;
+  FARM_TRY(similarities(mem, ws, q, R, target, rel_anchor, meta, dtype, &bound, method == FARM_METHOD_EXHAUSTIVE, s));
+  if (method == FARM_METHOD_BOUNDED || method == FARM_METHOD_PROPOSAL) {
+    {
+      PhaseTimer t(ws, s, FARM_PHASE_TOPK);
+      FARM_HIP(launch_bound_candidates(mem, ws->sim, ws->ld_s, q, meta, bound, k, kBoundCap, ws->rs_idx,
+                                       ws->cand_count, certified, s),
+               "bound candidates");
+    }
+    PropView pv;
+    pv.stats = ws->prop_stats;  // term and dot counters (full scans of BOUNDED too)
+    if (method == FARM_METHOD_PROPOSAL && mem->prop_m > 0) {
+      const bool in_lds = !(opt_flags & FARM_OPT_GLOBAL_PROPOSAL_PASS) && proposal_pass_in_lds(mem, dtype != FARM_F32);
+      if (!in_lds) {
+        // the LDS-staged pass selects the semantic sets itself; otherwise a scan per relation row
+        PhaseTimer t(ws, s, FARM_PHASE_PROPOSE);
+        FARM_HIP(launch_semantic_sets(ws->sim, ws->ld_s, q, R, mem->n, ws->sem_idx, ws->sem_cnt, ws->sem_tau, s),
+                 "semantic sets");
+        if (dtype != FARM_F32) FARM_HIP(launch_semantic_exact(mem, ws, q, R, s), "semantic similarities");
+      }
+      pv.m = mem->prop_m;
+      pv.idx = mem->prop_idx;
+      pv.val = mem->prop_val;
+      pv.out = mem->prop_out;
+      pv.sem_idx = ws->sem_idx;
+      pv.sem_cnt = ws->sem_cnt;
+      pv.sem_tau = ws->sem_tau;
+      pv.sem_sim = dtype != FARM_F32 ? ws->sem_sim : nullptr;
+      pv.stats = ws->prop_stats;
+      pv.fb_list = ws->fb_list;
+      pv.fb_count = ws->fb_count;
+      pv.fb_cap = ws->fb_cap;
+      pv.rel_total = R;
+      pv.in_lds = in_lds;
+      pv.sem_idx_out = ws->sem_idx;
+      pv.sem_cnt_out = ws->sem_cnt;
+      pv.sem_tau_out = ws->sem_tau;
+      pv.sem_sim_out = ws->sem_sim;
+    }
+    {
+      PhaseTimer t(ws, s, FARM_PHASE_RESCORE);
+      FARM_HIP(launch_rescore_terms(mem, ws, ws->sim, ws->ld_s, q, meta, bound, ws->rs_idx, ws->cand_count,
+                                    kBoundCap, pv, false, s),
+               "candidate terms");
+    }
+    if (pv.m > 0) {
+      PhaseTimer t(ws, s, FARM_PHASE_FALLBACK);
+      FARM_HIP(launch_rescore_terms(mem, ws, ws->sim, ws->ld_s, q, meta, bound, ws->rs_idx, ws->cand_count,
+                                    kBoundCap, pv, true, s),
+               "fallback terms");
+    }
+    PhaseTimer t(ws, s, FARM_PHASE_SELECT);
+    FARM_HIP(launch_rescore_combine(mem, ws, ws->sim, ws->ld_s, q, meta, bound, ws->rs_idx, ws->cand_count,
+                                    kBoundCap, s),
+             "candidate scores");
+    FARM_HIP(launch_rescore_select(ws, q, kBoundCap, k, nullptr, nullptr, ws->cand_count, mem->n, out_id, out_score,
+                                   out_terms, out_anchor_id, nullptr, s),
+             "candidate select");
+    return FARM_OK;
+  }
+  {
+    PhaseTimer t(ws, s, FARM_PHASE_PAIR);
+    FARM_HIP(launch_pair_exhaustive(mem, ws->sim, ws->lsim, ws->ld_s, q, meta, bound, ws->scores, ws->ld_s, nullptr, nullptr,
+                                    dtype == FARM_F32 ? nullptr : ws->scores_hi, s),
+             "relational pass");
+  }
+  uint64_t* key;
+  int32_t* idx;
+  {
+    PhaseTimer t(ws, s, FARM_PHASE_TOPK);
+    FARM_HIP(launch_topk(mem, ws, ws->scores, ws->ld_s, q, c, &key, &idx, s), "topk");
+    if (dtype == FARM_F32)
+      FARM_HIP(launch_topk_emit(key, idx, q, k, out_id, out_score, ws->rs_idx, s), "topk emit");
+    else
+      FARM_HIP(launch_topk_emit(key, idx, q, c, nullptr, nullptr, ws->rs_idx, s), "candidate emit");
+  }
+  if (dtype == FARM_F32) {
+    PhaseTimer t(ws, s, FARM_PHASE_EXPLAIN);
+    FARM_HIP(launch_explain(mem, ws->sim, ws->ld_s, q, meta, ws->rs_idx, k, out_terms, out_anchor_id, s), "explain");
+    if (certified) FARM_HIP(launch_fill_i32(certified, q, 1, s), "certificate");
+    return FARM_OK;
+  }
+  uint64_t* hi_key = nullptr;
+  int32_t* hi_idx = nullptr;
+  if (certified) {  // the c + 1 largest upper bounds (the first non-candidate among them bounds the rest)
+    PhaseTimer t(ws, s, FARM_PHASE_TOPK);
+    FARM_HIP(launch_topk(mem, ws, ws->scores_hi, ws->ld_s, q, c + 1, &hi_key, &hi_idx, s), "bound topk");
+  }
+  {
+    PhaseTimer t(ws, s, FARM_PHASE_RESCORE);
+    FARM_HIP(launch_rescore_terms(mem, ws, ws->sim, ws->ld_s, q, meta, bound, ws->rs_idx, nullptr, c, PropView{},
+                                  false, s),
+             "rescore terms");
+  }
+  PhaseTimer t(ws, s, FARM_PHASE_SELECT);
+  FARM_HIP(launch_rescore_combine(mem, ws, ws->sim, ws->ld_s, q, meta, bound, ws->rs_idx, nullptr, c, s),
+           "rescore scores");
+  FARM_HIP(launch_rescore_select(ws, q, c, k, hi_key, hi_idx, nullptr, mem->n, out_id, out_score, out_terms,
+                                 out_anchor_id, certified, s),
+           "rescore select");
   return FARM_OK;
 }
 
@@ -427,11 +636,6 @@ farm_status farm_workspace_create(const farm_memory* mem, int32_t max_q, int32_t
     DeviceGuard g(mem->device);
     auto* ws = new (std::nothrow) farm_workspace();
     if (!ws) { set_error("host allocation failed"); return FARM_ERR_OOM; }
-    ws->mem = mem;
-    ws->device = mem->device;
-    ws->max_q = max_q;
-    ws->max_rel = max_rel;
-    ws->ld_s = round_up(mem->n, kRowAlign);
     auto fail = [&](farm_status st) {
       free_all(ws->allocs);
       if (ws->h_meta) (void)hipHostFree(ws->h_meta);
@@ -439,54 +643,10 @@ farm_status farm_workspace_create(const farm_memory* mem, int32_t max_q, int32_t
       delete ws;
       return st;
     };
-    const size_t rows = (size_t)max_q + (size_t)max_rel;
-    farm_status st;
-    if ((st = dalloc(ws->allocs, ws->bytes, &ws->qn, rows * mem->ldk, "query vectors"))) return fail(st);
-    if (mem->dn_bf16) {
-      if ((st = dalloc(ws->allocs, ws->bytes, &ws->qn_bf16, rows * mem->ldk, "BF16 query vectors"))) return fail(st);
-      if ((st = dalloc(ws->allocs, ws->bytes, &ws->qerr_bf16, rows, "BF16 query error norms"))) return fail(st);
-      if ((st = dalloc(ws->allocs, ws->bytes, &ws->qnrm_bf16, rows, "BF16 query norms"))) return fail(st);
-    }
-    if (mem->dn_fp8) {
-      if ((st = dalloc(ws->allocs, ws->bytes, &ws->qn_fp8, rows * mem->ldk, "FP8 query vectors"))) return fail(st);
-      if ((st = dalloc(ws->allocs, ws->bytes, &ws->qn_scale, rows, "FP8 query scales"))) return fail(st);
-      if ((st = dalloc(ws->allocs, ws->bytes, &ws->qerr_fp8, rows, "FP8 query error norms"))) return fail(st);
-      if ((st = dalloc(ws->allocs, ws->bytes, &ws->qnrm_fp8, rows, "FP8 query norms"))) return fail(st);
-    }
-    if ((st = dalloc(ws->allocs, ws->bytes, &ws->sim, rows * ws->ld_s, "similarity matrix"))) return fail(st);
-    if ((st = dalloc(ws->allocs, ws->bytes, &ws->lsim, (size_t)(max_rel > 0 ? max_rel : 1) * ws->ld_s,
-                     "log similarities")))
-      return fail(st);
-    if ((st = dalloc(ws->allocs, ws->bytes, &ws->scores, (size_t)max_q * ws->ld_s, "scores"))) return fail(st);
-    if ((mem->dn_bf16 || mem->dn_fp8) &&
-        (st = dalloc(ws->allocs, ws->bytes, &ws->scores_hi, (size_t)max_q * ws->ld_s, "score bounds")))
-      return fail(st);
-    ws->meta_len = 2 * (int64_t)max_q + 1 + 3 * (int64_t)max_rel;
-    if ((st = dalloc(ws->allocs, ws->bytes, &ws->d_meta, (size_t)ws->meta_len, "metadata"))) return fail(st);
-    if ((st = dalloc(ws->allocs, ws->bytes, &ws->status, 1, "status"))) return fail(st);
-    ws->cand_cap = topk_candidate_capacity(mem->n, max_q, max_k + 1);
-    for (int b = 0; b < 2; ++b) {
-      if ((st = dalloc(ws->allocs, ws->bytes, &ws->cand_key[b], (size_t)ws->cand_cap, "TopK keys"))) return fail(st);
-      if ((st = dalloc(ws->allocs, ws->bytes, &ws->cand_idx[b], (size_t)ws->cand_cap, "TopK indices"))) return fail(st);
-    }
-    ws->max_k = max_k;
-    ws->rs_cap = max_k > kBoundCap ? max_k : kBoundCap;
-    const size_t nk = (size_t)max_q * ws->rs_cap;
-    if ((st = dalloc(ws->allocs, ws->bytes, &ws->cand_count, (size_t)max_q, "candidate counts"))) return fail(st);
-    if ((st = dalloc(ws->allocs, ws->bytes, &ws->rs_idx, nk, "winner indices"))) return fail(st);
-    if ((st = dalloc(ws->allocs, ws->bytes, &ws->rs_score, nk, "rescored scores"))) return fail(st);
-    if ((st = dalloc(ws->allocs, ws->bytes, &ws->rs_terms, nk * kMaxRel, "rescored terms"))) return fail(st);
-    if ((st = dalloc(ws->allocs, ws->bytes, &ws->rs_anchor, nk * kMaxRel, "rescored anchors"))) return fail(st);
-    const size_t rel1 = (size_t)(max_rel > 0 ? max_rel : 1);
-    if ((st = dalloc(ws->allocs, ws->bytes, &ws->sem_idx, rel1 * kSemMax, "semantic sets")) ||
-        (st = dalloc(ws->allocs, ws->bytes, &ws->sem_cnt, rel1, "semantic set sizes")) ||
-        (st = dalloc(ws->allocs, ws->bytes, &ws->sem_tau, rel1, "semantic bounds")) ||
-        (st = dalloc(ws->allocs, ws->bytes, &ws->sem_sim, rel1 * kSemMax, "semantic similarities")) ||
-        (st = dalloc(ws->allocs, ws->bytes, &ws->prop_stats, 4, "proposal counters")) ||
-        (st = dalloc(ws->allocs, ws->bytes, &ws->fb_list, (size_t)fallback_cap(max_q), "fallback worklist")) ||
-        (st = dalloc(ws->allocs, ws->bytes, &ws->fb_count, 1, "fallback count")))
-      return fail(st);
-    ws->fb_cap = fallback_cap(max_q);
+    farm_status st = layout_workspace(ws, mem, max_q, max_rel, max_k, [&](auto** p, size_t count, const char* what) {
+      return dalloc(ws->allocs, ws->bytes, p, count, what);
+    });
+    if (st) return fail(st);
     hipError_t e = hipHostMalloc((void**)&ws->h_meta, (size_t)ws->meta_len * sizeof(int32_t), hipHostMallocDefault);
     if (e != hipSuccess) { ws->h_meta = nullptr; return fail(hip_fail(e, "pinned metadata staging")); }
     e = hipEventCreateWithFlags(&ws->meta_done, hipEventDisableTiming);
@@ -650,149 +810,20 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
   try {
     int32_t R = 0;
     FARM_TRY(check_queries(mem, ws, q, d, target, rel_off, rel_pred, rel_anchor, &R));
-    if (k < 1 || k > FARM_MAX_K) { set_error("k = %d outside [1, %d]", k, FARM_MAX_K); return FARM_ERR_INVALID_ARG; }
+    TopkPlan plan;
+    FARM_TRY(plan_topk(mem, opts, k, &plan));
     if (q == 0) return FARM_OK;
     if (!out_id || !out_score) { set_error("null output pointer"); return FARM_ERR_INVALID_ARG; }
-    const int32_t dtype = opts ? opts->dtype : FARM_F32;
-    const int32_t method = opts ? opts->method : FARM_METHOD_EXHAUSTIVE;
-    int32_t* certified = opts ? opts->certified : nullptr;
-    if (method != FARM_METHOD_EXHAUSTIVE && method != FARM_METHOD_BOUNDED && method != FARM_METHOD_PROPOSAL) {
-      set_error("unknown method %d", method);
+    if (plan.c > ws->max_k) {
+      set_error("%s = %d exceeds the workspace's max_k %d", plan.c > k ? "rescore_mult * k" : "k", plan.c, ws->max_k);
       return FARM_ERR_INVALID_ARG;
     }
-    if (method == FARM_METHOD_PROPOSAL && mem->prop_m == 0 && mem->n >= 2) {
-      set_error("method PROPOSAL needs farm_build_proposals on this memory");
-      return FARM_ERR_UNSUPPORTED;
-    }
-    const int32_t opt_flags = opts ? opts->flags : 0;
-    if (opt_flags & ~FARM_OPT_GLOBAL_PROPOSAL_PASS) {
-      set_error("unknown option flags 0x%x", opt_flags);
-      return FARM_ERR_INVALID_ARG;
-    }
-    if (dtype != FARM_F32 && dtype != FARM_BF16 && dtype != FARM_FP8_E4M3) {
-      set_error("unknown dtype %d", dtype);
-      return FARM_ERR_INVALID_ARG;
-    }
-    if ((dtype == FARM_BF16 && !mem->dn_bf16) || (dtype == FARM_FP8_E4M3 && !mem->dn_fp8)) {
-      set_error("memory was built without the %s copy", dtype == FARM_BF16 ? "BF16" : "FP8");
-      return FARM_ERR_UNSUPPORTED;
-    }
-    int32_t c = k;  // candidates that leave the first TopK
-    if (dtype != FARM_F32 && method == FARM_METHOD_EXHAUSTIVE) {
-      const int32_t mult = opts->rescore_mult;
-      if (mult < 1) { set_error("rescore_mult = %d must be >= 1", mult); return FARM_ERR_INVALID_ARG; }
-      if ((int64_t)mult * k > ws->max_k) {
-        set_error("rescore_mult * k = %lld exceeds the workspace's max_k %d", (long long)mult * k, ws->max_k);
-        return FARM_ERR_INVALID_ARG;
-      }
-      c = mult * k;
-    }
-    if (k > ws->max_k) { set_error("k = %d exceeds the workspace's max_k %d", k, ws->max_k); return FARM_ERR_INVALID_ARG; }
     DeviceGuard g(mem->device);
     hipStream_t s = (hipStream_t)stream;
     MetaView meta;
     FARM_TRY(stage_meta(ws, q, R, target_cls, rel_off, rel_pred, s, &meta));
-    SimBound bound;
-    FARM_TRY(similarities(mem, ws, q, R, target, rel_anchor, meta, dtype, &bound, method == FARM_METHOD_EXHAUSTIVE, s));
-    if (method == FARM_METHOD_BOUNDED || method == FARM_METHOD_PROPOSAL) {
-      {
-        PhaseTimer t(ws, s, FARM_PHASE_TOPK);
-        FARM_HIP(launch_bound_candidates(mem, ws->sim, ws->ld_s, q, meta, bound, k, kBoundCap, ws->rs_idx,
-                                         ws->cand_count, certified, s),
-                 "bound candidates");
-      }
-      PropView pv;
-      pv.stats = ws->prop_stats;  // term and dot counters (full scans of BOUNDED too)
-      if (method == FARM_METHOD_PROPOSAL && mem->prop_m > 0) {
-        const bool in_lds = !(opt_flags & FARM_OPT_GLOBAL_PROPOSAL_PASS) && proposal_pass_in_lds(mem, dtype != FARM_F32);
-        if (!in_lds) {
-          // the LDS-staged pass selects the semantic sets itself; otherwise a scan per relation row
-          PhaseTimer t(ws, s, FARM_PHASE_PROPOSE);
-          FARM_HIP(launch_semantic_sets(ws->sim, ws->ld_s, q, R, mem->n, ws->sem_idx, ws->sem_cnt, ws->sem_tau, s),
-                   "semantic sets");
-          if (dtype != FARM_F32) FARM_HIP(launch_semantic_exact(mem, ws, q, R, s), "semantic similarities");
-        }
-        pv.m = mem->prop_m;
-        pv.idx = mem->prop_idx;
-        pv.val = mem->prop_val;
-        pv.out = mem->prop_out;
-        pv.sem_idx = ws->sem_idx;
-        pv.sem_cnt = ws->sem_cnt;
-        pv.sem_tau = ws->sem_tau;
-        pv.sem_sim = dtype != FARM_F32 ? ws->sem_sim : nullptr;
-        pv.stats = ws->prop_stats;
-        pv.fb_list = ws->fb_list;
-        pv.fb_count = ws->fb_count;
-        pv.fb_cap = ws->fb_cap;
-        pv.rel_total = R;
-        pv.in_lds = in_lds;
-        pv.sem_idx_out = ws->sem_idx;
-        pv.sem_cnt_out = ws->sem_cnt;
-        pv.sem_tau_out = ws->sem_tau;
-        pv.sem_sim_out = ws->sem_sim;
-      }
-      {
-        PhaseTimer t(ws, s, FARM_PHASE_RESCORE);
-        FARM_HIP(launch_rescore_terms(mem, ws, ws->sim, ws->ld_s, q, meta, bound, ws->rs_idx, ws->cand_count,
-                                      kBoundCap, pv, false, s),
-                 "candidate terms");
-      }
-      if (pv.m > 0) {
-        PhaseTimer t(ws, s, FARM_PHASE_FALLBACK);
-        FARM_HIP(launch_rescore_terms(mem, ws, ws->sim, ws->ld_s, q, meta, bound, ws->rs_idx, ws->cand_count,
-                                      kBoundCap, pv, true, s),
-                 "fallback terms");
-      }
-      PhaseTimer t(ws, s, FARM_PHASE_SELECT);
-      FARM_HIP(launch_rescore_combine(mem, ws, ws->sim, ws->ld_s, q, meta, bound, ws->rs_idx, ws->cand_count,
-                                      kBoundCap, s),
-               "candidate scores");
-      FARM_HIP(launch_rescore_select(ws, q, kBoundCap, k, nullptr, nullptr, ws->cand_count, mem->n, out_id, out_score,
-                                     out_terms, out_anchor_id, nullptr, s),
-               "candidate select");
-      return FARM_OK;
-    }
-    {
-      PhaseTimer t(ws, s, FARM_PHASE_PAIR);
-      FARM_HIP(launch_pair_exhaustive(mem, ws->sim, ws->lsim, ws->ld_s, q, meta, bound, ws->scores, ws->ld_s, nullptr, nullptr,
-                                      dtype == FARM_F32 ? nullptr : ws->scores_hi, s),
-               "relational pass");
-    }
-    uint64_t* key;
-    int32_t* idx;
-    {
-      PhaseTimer t(ws, s, FARM_PHASE_TOPK);
-      FARM_HIP(launch_topk(mem, ws, ws->scores, ws->ld_s, q, c, &key, &idx, s), "topk");
-      if (dtype == FARM_F32)
-        FARM_HIP(launch_topk_emit(key, idx, q, k, out_id, out_score, ws->rs_idx, s), "topk emit");
-      else
-        FARM_HIP(launch_topk_emit(key, idx, q, c, nullptr, nullptr, ws->rs_idx, s), "candidate emit");
-    }
-    if (dtype == FARM_F32) {
-      PhaseTimer t(ws, s, FARM_PHASE_EXPLAIN);
-      FARM_HIP(launch_explain(mem, ws->sim, ws->ld_s, q, meta, ws->rs_idx, k, out_terms, out_anchor_id, s), "explain");
-      if (certified) FARM_HIP(launch_fill_i32(certified, q, 1, s), "certificate");
-      return FARM_OK;
-    }
-    uint64_t* hi_key = nullptr;
-    int32_t* hi_idx = nullptr;
-    if (certified) {  // the c + 1 largest upper bounds (the first non-candidate among them bounds the rest)
-      PhaseTimer t(ws, s, FARM_PHASE_TOPK);
-      FARM_HIP(launch_topk(mem, ws, ws->scores_hi, ws->ld_s, q, c + 1, &hi_key, &hi_idx, s), "bound topk");
-    }
-    {
-      PhaseTimer t(ws, s, FARM_PHASE_RESCORE);
-      FARM_HIP(launch_rescore_terms(mem, ws, ws->sim, ws->ld_s, q, meta, bound, ws->rs_idx, nullptr, c, PropView{},
-                                    false, s),
-               "rescore terms");
-    }
-    PhaseTimer t(ws, s, FARM_PHASE_SELECT);
-    FARM_HIP(launch_rescore_combine(mem, ws, ws->sim, ws->ld_s, q, meta, bound, ws->rs_idx, nullptr, c, s),
-             "rescore scores");
-    FARM_HIP(launch_rescore_select(ws, q, c, k, hi_key, hi_idx, nullptr, mem->n, out_id, out_score, out_terms,
-                                   out_anchor_id, certified, s),
-             "rescore select");
-    return FARM_OK;
+    return query_topk_core(mem, ws, q, R, target, rel_anchor, meta, plan, k, out_id, out_score, out_terms,
+                           out_anchor_id, s);
   } catch (...) {
     set_error("unexpected host exception in farm_query_topk");
     return FARM_ERR_HIP;
