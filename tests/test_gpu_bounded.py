@@ -62,7 +62,8 @@ def test_bounded_reduced_precision_is_exact(farm, world, dtype):
     for qq in range(qb.q):
         if list(ids[qq]) != list(ex[0][qq]):
             d = np.abs(sc[qq] - ex[1][qq])
-            assert np.all(d <= 1e-5 * np.abs(ex[1][qq]) + 4e-6), qq
+            # both within 1e-5 * max(s, 0.01) of the oracle's scores
+            assert np.all(d <= 2e-5 * np.maximum(np.abs(ex[1][qq]), 1e-2)), qq
         else:
             gaps_ok += 1
     rows = list(np.random.default_rng(5).choice(qb.q, size=12, replace=False))

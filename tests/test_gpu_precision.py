@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from synth import CONFIGS, make_queries, make_scene
-from tests._parity import ABS, REL, assert_topk_valid, assert_values_close
+from tests._parity import ABS, REL, assert_returned_scores, assert_topk_valid, assert_values_close
 
 pytestmark = pytest.mark.gpu
 
@@ -32,7 +32,7 @@ def _check_rows(scene, qb, rows, ids, sc, terms, anch, cert, oidx, osc, k):
     qsel = np.repeat(np.arange(len(rows)), k).astype(np.int32)
     osel = np.array([idx_of[int(g)] for r in rows for g in ids[r]], np.int64)
     ps, psem, pt, pb = oracle.score_pairs(scene, sub, qsel, osel)
-    assert_values_close(sc[rows].reshape(-1), ps, "rescored scores")
+    assert_returned_scores(sc[rows].reshape(-1), ps, "rescored scores")
     for m in range(len(qsel)):
         row = rows[qsel[m]]
         R = int(qb.rel_off[row + 1] - qb.rel_off[row])
