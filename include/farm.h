@@ -273,6 +273,36 @@ FARM_API farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws,
                             const farm_score_opts* opts, int32_t k, uint32_t* out_id, float* out_score,
                             float* out_terms, uint32_t* out_anchor_id, void* stream);
 
+/*
+ * farm_query_topk without a workspace and without any allocation, for callers
+ * that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Arguments, options,
+ * results and errors as farm_query_topk (q, d, the query arrays, opts, k and
+ * the outputs), minus the workspace.  The call calls no hipMalloc, hipFree,
+ * pinned-host or other allocating routine: the scratch it needs (query
+ * vectors, similarity matrix, candidate buffers, counters, metadata) is laid
+ * out in a static device array of FARM_STATIC_SCRATCH_BYTES that the library
+ * holds on every device it runs on until the process ends, and the per-call
+ * metadata reaches the device in kernel arguments.
+ * Limit: a call whose layout does not fit FARM_STATIC_SCRATCH_BYTES (about
+ * q + 2R rows of n floats plus 150 KB per query, e.g. q = 32, R = 96 at
+ * n = 20,000) fails with FARM_ERR_INVALID_ARG and a message giving the bytes
+ * it needs.
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents: calls that overlap on one device (on different streams or
+ * from different host threads) race; the caller orders them.  Device query
+ * vectors are not validated here (there is no workspace status to report
+ * to): a non-finite or zero-norm vector leaves its query's results
+ * unspecified.
+ */
+#define FARM_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+FARM_API farm_status farm_query_topk_static(const farm_memory* mem, int32_t q, int32_t d, const float* target,
+                                            const int32_t* target_cls, const int32_t* rel_off,
+                                            const int32_t* rel_pred, const float* rel_anchor,
+                                            const farm_score_opts* opts, int32_t k, uint32_t* out_id,
+                                            float* out_score, float* out_terms, uint32_t* out_anchor_id,
+                                            void* stream);
+
 /* Phases timed by the workspace's optional phase timer. */
 typedef enum {
   FARM_PHASE_NORMALIZE = 0, /* query vector normalisation (and quantisation) */

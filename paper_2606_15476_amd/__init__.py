@@ -20,7 +20,7 @@ from ._lib import (FARM_BUILD_BF16, FARM_BUILD_FP8, FARM_MAX_K, FARM_MAX_REL, FA
                    FARTHEST, INSIDE, NUM_PRED, NUM_PROP_PRED, FarmError, lib_path)
 
 __all__ = [
-    "Memory", "Workspace", "ProposalNet", "Server", "build_proposals", "get_proposals", "score_query", "topk", "query_topk", "workspace_estimate", "FarmError",
+    "Memory", "Workspace", "ProposalNet", "Server", "build_proposals", "get_proposals", "score_query", "topk", "query_topk", "query_topk_static", "workspace_estimate", "FarmError",
     "FARM_BUILD_BF16", "FARM_BUILD_FP8", "FARM_MAX_K", "FARM_MAX_REL", "FARM_NO_ID", "F32", "BF16",
     "FP8_E4M3", "EXHAUSTIVE", "BOUNDED", "PROPOSAL", "OPT_GLOBAL_PROPOSAL_PASS", "NEAR", "ABOVE", "BELOW", "LEFT_OF", "RIGHT_OF", "NEXT_TO", "IN_FRONT_OF", "BEHIND", "ON", "CLOSEST", "FARTHEST", "INSIDE", "NUM_PRED",
     "NUM_PROP_PRED", "lib_path",
@@ -200,6 +200,23 @@ def query_topk(mem: Memory, ws: Workspace, target, target_cls, rel_off, rel_pred
                                       _ptr(rel_anchor) if rel_anchor is not None and rel_anchor.numel() else None,
                                       ctypes.byref(opts), int(k), _ptr(out_id), _ptr(out_score), _ptr(out_terms),
                                       _ptr(out_anchor_id), _stream(stream)))
+    del tc, ro, rp
+
+
+def query_topk_static(mem: Memory, target, target_cls, rel_off, rel_pred, rel_anchor, k: int, out_id, out_score,
+                      out_terms=None, out_anchor_id=None, dtype: int = F32, rescore_mult: int = 4, certified=None,
+                      method: int = EXHAUSTIVE, flags: int = 0, stream=None):
+    """farm_query_topk_static: query_topk without a workspace or any allocation (the library's static scratch)."""
+    tc, ptc = _host_i32(target_cls)
+    ro, pro = _host_i32(rel_off)
+    rp, prp = _host_i32(rel_pred)
+    q, d = int(target.shape[0]), int(target.shape[1])
+    cp = _ptr(certified)
+    opts = _lib.ScoreOpts(int(dtype), int(method), int(rescore_mult), int(flags), cp.value if cp is not None else None)
+    _lib.check(_lib.L.farm_query_topk_static(mem.handle, q, d, _ptr(target), ptc, pro, prp,
+                                             _ptr(rel_anchor) if rel_anchor is not None and rel_anchor.numel() else None,
+                                             ctypes.byref(opts), int(k), _ptr(out_id), _ptr(out_score),
+                                             _ptr(out_terms), _ptr(out_anchor_id), _stream(stream)))
     del tc, ro, rp
 
 

@@ -23,7 +23,7 @@ FARM_BUILD_BF16, FARM_BUILD_FP8 = 0x1, 0x2
 
 EXPORTS = (
     "farm_build_memory", "farm_free_memory", "farm_memory_info", "farm_workspace_create", "farm_workspace_free",
-    "farm_workspace_bytes", "farm_workspace_estimate", "farm_score_query", "farm_topk", "farm_query_topk",
+    "farm_workspace_bytes", "farm_workspace_estimate", "farm_score_query", "farm_topk", "farm_query_topk", "farm_query_topk_static",
     "farm_workspace_status", "farm_last_error", "farm_version", "farm_workspace_set_timing",
     "farm_workspace_timings", "farm_mlp_create", "farm_mlp_free", "farm_mlp_shape", "farm_mlp_get_weights",
     "farm_mlp_get_grads", "farm_mlp_set_weights", "farm_mlp_inputs", "farm_mlp_logits", "farm_mlp_step",
@@ -74,6 +74,7 @@ def _declare(lib):
         "farm_score_query": [P, P, i32, i32, P, P, P, P, P, P, P, P, P],
         "farm_topk": [P, P, P, i32, i32, P, P, P, P],
         "farm_query_topk": [P, P, i32, i32, P, P, P, P, P, ctypes.POINTER(ScoreOpts), i32, P, P, P, P, P],
+        "farm_query_topk_static": [P, i32, i32, P, P, P, P, P, ctypes.POINTER(ScoreOpts), i32, P, P, P, P, P],
         "farm_workspace_status": [P, P],
         "farm_workspace_set_timing": [P, i32],
         "farm_workspace_timings": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32],

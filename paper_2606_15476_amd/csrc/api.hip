@@ -16,9 +16,17 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
+#include <type_traits>
 
 #include "farm_internal.h"
+
+// Scratch of farm_query_topk_static (see include/farm.h): one copy per device,
+// held until the process ends.  Host code never passes this name to a kernel
+// or a copy -- on the host it is a stand-in, not a device address -- but the
+// address hipGetSymbolAddress returns for the current device (static_scratch).
+static __device__ __align__(256) unsigned char scratch[FARM_STATIC_SCRATCH_BYTES];
 
 namespace farm {
 
@@ -454,6 +462,81 @@ farm_status query_topk_core(const farm_memory* mem, farm_workspace* ws, int32_t 
   return FARM_OK;
 }
 
+// ---- farm_query_topk_static: the workspace laid out in a static device array.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be current: looked up
+// once per device (hipGetSymbolAddress) and kept.
+farm_status static_scratch(int device, unsigned char** out) {
+  if (device < 0 || device >= kMaxDevices) {
+    set_error("device %d outside the %d the static scratch table covers", device, kMaxDevices);
+    return FARM_ERR_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "static scratch address");
+    g_scratch_ptr[device] = p;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_ptr[device]);
+  return FARM_OK;
+}
+
+// Per-call metadata of the static path travels in kernel arguments (no host
+// staging buffer to allocate or keep alive): one launch per chunk.
+constexpr int kMetaChunk = 248;
+struct MetaChunk {
+  int32_t off, cnt;
+  int32_t v[kMetaChunk];
+};
+
+__global__ void k_meta_chunk(int32_t* __restrict__ dst, MetaChunk c) {
+  for (int i = threadIdx.x; i < c.cnt; i += blockDim.x) dst[c.off + i] = c.v[i];
+}
+
+// The metadata block of stage_meta, written through kernel arguments.
+farm_status stage_meta_args(farm_workspace* ws, int32_t q, int32_t R, const int32_t* target_cls,
+                            const int32_t* rel_off, const int32_t* rel_pred, hipStream_t s, MetaView* view) {
+  MetaChunk ch;
+  ch.off = 0;
+  ch.cnt = 0;
+  hipError_t err = hipSuccess;
+  auto flush = [&]() {
+    if (ch.cnt == 0 || err != hipSuccess) return;
+    hipLaunchKernelGGL(k_meta_chunk, dim3(1), dim3(256), 0, s, ws->d_meta, ch);
+    err = hipGetLastError();
+    ch.off += ch.cnt;
+    ch.cnt = 0;
+  };
+  auto push = [&](int32_t v) {
+    ch.v[ch.cnt++] = v;
+    if (ch.cnt == kMetaChunk) flush();
+  };
+  for (int32_t k = 0; k < q; ++k) push(target_cls ? target_cls[k] : -1);
+  for (int32_t k = 0; k <= q; ++k) push(rel_off[k]);
+  for (int32_t r = 0; r < R; ++r) push(rel_pred[r]);
+  for (int32_t k = 0; k < q; ++k)
+    for (int32_t r = rel_off[k]; r < rel_off[k + 1]; ++r) push(k);
+  int32_t nrank = 0;
+  for (int32_t r = 0; r < R; ++r)
+    if (rel_pred[r] == FARM_CLOSEST || rel_pred[r] == FARM_FARTHEST || rel_pred[r] == FARM_INSIDE) {
+      push(r);
+      ++nrank;
+    }
+  flush();
+  if (err != hipSuccess) return hip_fail(err, "metadata launch");
+  view->tcls = ws->d_meta;
+  view->rel_off = ws->d_meta + q;
+  view->rel_pred = ws->d_meta + 2 * q + 1;
+  view->rel_query = ws->d_meta + 2 * q + 1 + R;
+  view->scan_rows = ws->d_meta + 2 * q + 1 + 2 * R;
+  view->scan_n = nrank;
+  return FARM_OK;
+}
+
 }  // namespace
 }  // namespace farm
 
@@ -826,6 +909,56 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
                            out_anchor_id, s);
   } catch (...) {
     set_error("unexpected host exception in farm_query_topk");
+    return FARM_ERR_HIP;
+  }
+}
+
+farm_status farm_query_topk_static(const farm_memory* mem, int32_t q, int32_t d, const float* target,
+                                   const int32_t* target_cls, const int32_t* rel_off, const int32_t* rel_pred,
+                                   const float* rel_anchor, const farm_score_opts* opts, int32_t k, uint32_t* out_id,
+                                   float* out_score, float* out_terms, uint32_t* out_anchor_id, void* stream) {
+  try {
+    if (!mem) { set_error("null memory"); return FARM_ERR_INVALID_ARG; }
+    farm_workspace ws;  // host-side descriptor only: its buffers point into the static scratch
+    ws.mem = mem;
+    ws.max_q = q > 0 ? q : 0;
+    ws.max_rel = INT32_MAX;
+    int32_t R = 0;
+    FARM_TRY(check_queries(mem, &ws, q, d, target, rel_off, rel_pred, rel_anchor, &R));
+    TopkPlan plan;
+    FARM_TRY(plan_topk(mem, opts, k, &plan));
+    if (q == 0) return FARM_OK;
+    if (!out_id || !out_score) { set_error("null output pointer"); return FARM_ERR_INVALID_ARG; }
+    DeviceGuard g(mem->device);
+    if (!g.ok) { set_error("cannot make device %d current", mem->device); return FARM_ERR_HIP; }
+    unsigned char* base = nullptr;
+    FARM_TRY(static_scratch(mem->device, &base));
+    size_t used = 0;
+    farm_status st = layout_workspace(&ws, mem, q, R, plan.c, [&](auto** p, size_t count, const char*) {
+      const size_t bytes = (count ? count : 1) * sizeof(**p);
+      const size_t off = (size_t)round_up((int64_t)used, 256);
+      used = off + bytes;
+      *p = used <= FARM_STATIC_SCRATCH_BYTES ? reinterpret_cast<std::decay_t<decltype(*p)>>(base + off) : nullptr;
+      return FARM_OK;
+    });
+    if (st) return st;
+    if (used > FARM_STATIC_SCRATCH_BYTES) {
+      set_error("farm_query_topk_static: q = %d, R = %d, k = %d over n = %lld objects needs %zu bytes of scratch; "
+                "the static scratch holds %zu",
+                q, R, plan.c, (long long)mem->n, used, (size_t)FARM_STATIC_SCRATCH_BYTES);
+      return FARM_ERR_INVALID_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    // the array keeps the previous call's contents: clear the flags and counters
+    // this call accumulates into (fill kernels, no memset nodes)
+    FARM_HIP(launch_fill_i32(ws.status, 1, 0, s), "status clear");
+    FARM_HIP(launch_fill_i32(reinterpret_cast<int32_t*>(ws.prop_stats), 8, 0, s), "counter clear");
+    MetaView meta;
+    FARM_TRY(stage_meta_args(&ws, q, R, target_cls, rel_off, rel_pred, s, &meta));
+    return query_topk_core(mem, &ws, q, R, target, rel_anchor, meta, plan, k, out_id, out_score, out_terms,
+                           out_anchor_id, s);
+  } catch (...) {
+    set_error("unexpected host exception in farm_query_topk_static");
     return FARM_ERR_HIP;
   }
 }
