@@ -76,7 +76,7 @@ def recorded_traffic(kernel: str, workload: str):
     return float(rec["bytes_per_launch"])
 
 
-def parse():
+def parse(argv=None):
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
@@ -102,7 +102,7 @@ def parse():
                    help="closed-loop batch-1 latency per scene size instead (one query at a time, p50/p99)")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                    help="only run one plain device copy of BYTES (reference for the HBM byte counters) and exit")
-    return p.parse_args()
+    return p.parse_args(argv)
 
 
 def copy_calibration(nbytes):

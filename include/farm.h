@@ -362,6 +362,14 @@ FARM_API farm_status farm_mlp_get_weights(const farm_mlp* mlp, float* W1, float*
                                           float* W3, float* b3);
 FARM_API farm_status farm_mlp_get_grads(const farm_mlp* mlp, float* W1, float* b1, float* W2, float* b2,
                                         float* W3, float* b3);
+/* Host copies of the last training step's batch tensors, first nb rows
+   (synchronising; any pointer may be NULL): pre-activations Z1, Z2 [nb][256]
+   FP32, activations A1, A2 [nb][256] BF16, logits Y [nb][FARM_NUM_PROP_PRED]
+   FP32, the back-propagated dZ2 [nb][256] BF16, dA1 = dZ2 W2 [nb][256] FP32
+   and dZ1 [nb][256] BF16.  They stay valid until the next step, logits or
+   table call of this network; for checking each layer on its own inputs. */
+FARM_API farm_status farm_mlp_get_batch(const farm_mlp* mlp, int32_t nb, float* Z1, uint16_t* A1, float* Z2,
+                                        uint16_t* A2, float* Y, uint16_t* dZ2, float* dA1, uint16_t* dZ1);
 FARM_API farm_status farm_mlp_set_weights(farm_mlp* mlp, const float* W1, const float* b1, const float* W2,
                                           const float* b2, const float* W3, const float* b3);
 /* Network inputs of nb pairs (device o_idx, a_idx: object indices into mem)
@@ -400,6 +408,28 @@ FARM_API farm_status farm_mlp_step(farm_mlp* mlp, const farm_memory* mem, int32_
  * UNSUPPORTED (n > 500,000), OOM, HIP.
  */
 FARM_API farm_status farm_build_proposals(farm_memory* mem, farm_mlp* mlp, int32_t M, void* stream);
+
+/*
+ * The non-learned baseline of the same tables: for every object o and
+ * predicate p < FARM_NUM_PROP_PRED the M anchors with the largest predicate
+ * value P_p(o, a) (ties by id), their values and the largest value left out --
+ * the tightest Pout any list of M can have -- ranked without a network.
+ * Same layout, certificate, memory and errors as farm_build_proposals; the
+ * results of FARM_METHOD_PROPOSAL do not depend on how the lists were ranked,
+ * only how often a term falls back to the full scan.
+ */
+FARM_API farm_status farm_build_proposals_by_value(farm_memory* mem, int32_t M, void* stream);
+
+/*
+ * Logits of the table build's forward pass (the factorised first layer that
+ * farm_build_proposals ranks anchors by) for targets t0 .. t0 + tc - 1
+ * against every anchor of the memory:
+ *   logits   device [FARM_NUM_PROP_PRED][tc][n] FP32 (self pairs -INFINITY)
+ * 1 <= tc <= 16, tc * n <= 2^22.  Allocates and frees its temporaries;
+ * synchronises `stream`.  Errors: INVALID_ARG, OOM, HIP.
+ */
+FARM_API farm_status farm_mlp_table_logits(farm_mlp* mlp, const farm_memory* mem, int64_t t0, int32_t tc,
+                                           float* logits, void* stream);
 
 /*
  * Copy of the proposal tables (stream-ordered device-to-device copies):

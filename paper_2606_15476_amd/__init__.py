@@ -20,7 +20,7 @@ from ._lib import (FARM_BUILD_BF16, FARM_BUILD_FP8, FARM_MAX_K, FARM_MAX_REL, FA
                    FARTHEST, INSIDE, NUM_PRED, NUM_PROP_PRED, FarmError, lib_path)
 
 __all__ = [
-    "Memory", "Workspace", "ProposalNet", "Server", "build_proposals", "get_proposals", "score_query", "topk", "query_topk", "query_topk_static", "workspace_estimate", "FarmError",
+    "Memory", "Workspace", "ProposalNet", "Server", "build_proposals", "build_proposals_by_value", "get_proposals", "score_query", "topk", "query_topk", "query_topk_static", "workspace_estimate", "FarmError",
     "FARM_BUILD_BF16", "FARM_BUILD_FP8", "FARM_MAX_K", "FARM_MAX_REL", "FARM_NO_ID", "F32", "BF16",
     "FP8_E4M3", "EXHAUSTIVE", "BOUNDED", "PROPOSAL", "OPT_GLOBAL_PROPOSAL_PASS", "NEAR", "ABOVE", "BELOW", "LEFT_OF", "RIGHT_OF", "NEXT_TO", "IN_FRONT_OF", "BEHIND", "ON", "CLOSEST", "FARTHEST", "INSIDE", "NUM_PRED",
     "NUM_PROP_PRED", "lib_path",
@@ -225,6 +225,11 @@ def build_proposals(mem: Memory, net: "ProposalNet", m: int = 256, stream=None):
     _lib.check(_lib.L.farm_build_proposals(mem.handle, net.handle, int(m), _stream(stream)))
 
 
+def build_proposals_by_value(mem: Memory, m: int = 256, stream=None):
+    """farm_build_proposals_by_value: lists of the m anchors of largest exact predicate value (no network)."""
+    _lib.check(_lib.L.farm_build_proposals_by_value(mem.handle, int(m), _stream(stream)))
+
+
 def get_proposals(mem: Memory, stream=None):
     """(M, idx [P,n,M] int32, val [P,n,M] float32, out [P,n] float32) device tensors (P = NUM_PROP_PRED), or
     (0, None, None, None)."""
@@ -280,6 +285,22 @@ class ProposalNet:
     def set_weights(self, w: dict):
         arrays = {k: np.ascontiguousarray(w[k], np.float32).reshape(v) for k, v in self._shapes().items()}
         self._io(_lib.L.farm_mlp_set_weights, arrays)
+
+    def batch(self, nb: int) -> dict:
+        """Host copies of the last step's batch tensors (farm_mlp_get_batch): Z1, Z2, dA1 FP32 [nb, h],
+        A1, A2, dZ2, dZ1 as BF16 bit patterns (uint16) [nb, h], Y FP32 [nb, NUM_PROP_PRED]."""
+        h = self.hidden
+        out = {"Z1": np.zeros((nb, h), np.float32), "A1": np.zeros((nb, h), np.uint16),
+               "Z2": np.zeros((nb, h), np.float32), "A2": np.zeros((nb, h), np.uint16),
+               "Y": np.zeros((nb, NUM_PROP_PRED), np.float32), "dZ2": np.zeros((nb, h), np.uint16),
+               "dA1": np.zeros((nb, h), np.float32), "dZ1": np.zeros((nb, h), np.uint16)}
+        ptrs = [out[k].ctypes.data_as(ctypes.c_void_p) for k in ("Z1", "A1", "Z2", "A2", "Y", "dZ2", "dA1", "dZ1")]
+        _lib.check(_lib.L.farm_mlp_get_batch(self.handle, int(nb), *ptrs))
+        return out
+
+    def table_logits(self, mem: "Memory", t0: int, tc: int, out, stream=None):
+        """farm_mlp_table_logits: the table build's logits [NUM_PROP_PRED, tc, n] of targets t0..t0+tc-1."""
+        _lib.check(_lib.L.farm_mlp_table_logits(self.handle, mem.handle, int(t0), int(tc), _ptr(out), _stream(stream)))
 
     def inputs(self, mem: "Memory", o_idx, a_idx, out, stream=None):
         _lib.check(_lib.L.farm_mlp_inputs(self.handle, mem.handle, int(o_idx.shape[0]), _ptr(o_idx), _ptr(a_idx),

@@ -26,8 +26,8 @@ EXPORTS = (
     "farm_workspace_bytes", "farm_workspace_estimate", "farm_score_query", "farm_topk", "farm_query_topk", "farm_query_topk_static",
     "farm_workspace_status", "farm_last_error", "farm_version", "farm_workspace_set_timing",
     "farm_workspace_timings", "farm_mlp_create", "farm_mlp_free", "farm_mlp_shape", "farm_mlp_get_weights",
-    "farm_mlp_get_grads", "farm_mlp_set_weights", "farm_mlp_inputs", "farm_mlp_logits", "farm_mlp_step",
-    "farm_build_proposals", "farm_workspace_proposal_stats", "farm_get_proposals", "farm_proposal_pass_form",
+    "farm_mlp_get_grads", "farm_mlp_get_batch", "farm_mlp_set_weights", "farm_mlp_table_logits", "farm_mlp_inputs", "farm_mlp_logits", "farm_mlp_step",
+    "farm_build_proposals", "farm_build_proposals_by_value", "farm_workspace_proposal_stats", "farm_get_proposals", "farm_proposal_pass_form",
     "farm_server_create", "farm_server_add_scene", "farm_server_submit", "farm_server_cancel", "farm_server_progress",
     "farm_server_poll", "farm_server_stats", "farm_server_free",
 )
@@ -84,10 +84,13 @@ def _declare(lib):
         "farm_mlp_get_weights": [P, P, P, P, P, P, P],
         "farm_mlp_get_grads": [P, P, P, P, P, P, P],
         "farm_mlp_set_weights": [P, P, P, P, P, P, P],
+        "farm_mlp_get_batch": [P, i32, P, P, P, P, P, P, P, P],
+        "farm_mlp_table_logits": [P, P, i64, i32, P, P],
         "farm_mlp_inputs": [P, P, i32, P, P, P, P],
         "farm_mlp_logits": [P, P, i32, P, P, P, P],
         "farm_mlp_step": [P, P, i32, P, P, P, P, ctypes.c_float, ctypes.c_float, i32, P, P],
         "farm_build_proposals": [P, P, i32, P],
+        "farm_build_proposals_by_value": [P, i32, P],
         "farm_workspace_proposal_stats": [P, ctypes.POINTER(i64), i32, P],
         "farm_get_proposals": [P, ctypes.POINTER(i32), P, P, P, P],
         "farm_proposal_pass_form": [P, i32, ctypes.POINTER(i32)],

@@ -83,9 +83,9 @@ struct farm_memory {
   // learned anchor proposals (farm_build_proposals): per predicate p and
   // target o a list of M anchors (target-major: one target's list is contiguous)
   int32_t prop_m = 0;
-  int32_t* prop_idx = nullptr;  // [5][n][M] anchor indices
-  float* prop_val = nullptr;    // [5][n][M] predicate value (Near: log P, others: P)
-  float* prop_out = nullptr;    // [5][n] largest predicate value over anchors left out (same domain)
+  int32_t* prop_idx = nullptr;  // [P][n][M] anchor indices (P = FARM_NUM_PROP_PRED)
+  float* prop_val = nullptr;    // [P][n][M] predicate value (Near family: log P, others: P)
+  float* prop_out = nullptr;    // [P][n] largest predicate value over anchors left out (same domain)
   std::vector<void*> prop_allocs;
   size_t bytes = 0;
   std::vector<void*> allocs;
@@ -163,7 +163,7 @@ struct farm_mlp {
   uint16_t* W1b = nullptr;   // [h][ldx]
   uint16_t* W2b = nullptr;   // [h][h]
   uint16_t* W2bT = nullptr;  // [h][h] transpose
-  float* W3r = nullptr;      // [5][h]
+  float* W3r = nullptr;      // [P][h]
   // batch activations
   uint16_t* X = nullptr;     // [bpad][ldx]
   uint16_t* XT = nullptr;    // [ldx][bpad]
@@ -172,10 +172,11 @@ struct farm_mlp {
   uint16_t* A1 = nullptr;    // [bpad][h]
   uint16_t* A1T = nullptr;   // [h][bpad]
   uint16_t* A2 = nullptr;
-  float* Y = nullptr;        // [bpad][5]
-  float* dY = nullptr;       // [bpad][5]
+  float* Y = nullptr;        // [bpad][P]
+  float* dY = nullptr;       // [bpad][P]
   float* dA = nullptr;       // [bpad][h]
-  uint16_t* dZ = nullptr;    // [bpad][h]
+  uint16_t* dZ = nullptr;    // [bpad][h] dZ2 of the last step
+  uint16_t* dZ1 = nullptr;   // [bpad][h] dZ1 of the last step
   uint16_t* dZT = nullptr;   // [h][bpad]
   float* loss_part = nullptr;
   float* red_part = nullptr;  // partial sums of the chunked batch reductions
@@ -226,9 +227,9 @@ struct SimBound {
 // Anchor proposals seen by the rescoring kernel; m == 0 means full anchor scans.
 struct PropView {
   int32_t m = 0;
-  const int32_t* idx = nullptr;      // [5][n][m]
-  const float* val = nullptr;        // [5][n][m]
-  const float* out = nullptr;        // [5][n]
+  const int32_t* idx = nullptr;      // [P][n][m]
+  const float* val = nullptr;        // [P][n][m]
+  const float* out = nullptr;        // [P][n]
   const int32_t* sem_idx = nullptr;  // [R][kSemMax]
   const int32_t* sem_cnt = nullptr;  // [R]
   const float* sem_tau = nullptr;    // [R]

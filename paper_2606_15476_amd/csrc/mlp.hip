@@ -1,6 +1,6 @@
 // mlp.hip -- the anchor proposal network: BF16 training and inference kernels.
 //
-// Network (per (target o, anchor a) pair; five logits, one per predicate):
+// Network (per (target o, anchor a) pair; nine logits, one per predicate with a list):
 //   x  = [u_o (dp) | u_a (dp) | g(o, a) / 4 m (12) | 0 pad]   dp = d rounded up to 64
 //   h1 = GELU(W1 x + b1),  h2 = GELU(W2 h1 + b2),  y = W3 h2 + b3
 //   g  = [c_o - c_a, e_o, e_a, |c_o - c_a|, (c_o - c_a) . r, bottom_o - top_a]
@@ -13,6 +13,8 @@
 // Backward: dY = (sigmoid(y_p) - label) / B on the labelled logit;
 //   dW3 = dY^T h2, dh2 = dY W3, dZ2 = dh2 * GELU'(Z2), dW2 = dZ2^T h1,
 //   dh1 = dZ2 W2, dZ1 = dh1 * GELU'(Z1), dW1 = dZ1^T x, db = column sums.
+// The last step's batch tensors (Z1, A1, Z2, A2, Y, dZ2, dh1, dZ1) stay in
+// their buffers until the next step (farm_mlp_get_batch copies them out).
 #include <math.h>
 #include <string.h>
 
@@ -301,7 +303,8 @@ farm_status alloc_mlp(farm_mlp* m) {
             take(&m->W1b, h * ldx) && take(&m->W2b, h * h) && take(&m->W2bT, h * h) && take(&m->W3r, kNPred * h) &&
             take(&m->X, B * ldx) && take(&m->XT, ldx * B) && take(&m->Z1, B * h) && take(&m->Z2, B * h) &&
             take(&m->A1, B * h) && take(&m->A1T, h * B) && take(&m->A2, B * h) && take(&m->Y, B * kNPred) &&
-            take(&m->dY, B * kNPred) && take(&m->dA, B * h) && take(&m->dZ, B * h) && take(&m->dZT, h * B) &&
+            take(&m->dY, B * kNPred) && take(&m->dA, B * h) && take(&m->dZ, B * h) && take(&m->dZ1, B * h) &&
+            take(&m->dZT, h * B) &&
             take(&m->loss_part, B / 256 + 1) &&
             take(&m->red_part, (B / kRedRows + 1) * (kNPred * (h + 1)));
   if (!ok) {
@@ -385,6 +388,7 @@ farm_status farm_mlp_create(int32_t d, int32_t max_batch, uint64_t seed, farm_ml
                          hipMemset(m->grad, 0, sizeof(float) * m->n_par) == hipSuccess &&
                          hipMemset(m->X, 0, sizeof(uint16_t) * (size_t)m->bpad * ldx) == hipSuccess &&
                          hipMemset(m->dZ, 0, sizeof(uint16_t) * (size_t)m->bpad * h) == hipSuccess &&
+                         hipMemset(m->dZ1, 0, sizeof(uint16_t) * (size_t)m->bpad * h) == hipSuccess &&
                          hipMemset(m->A1, 0, sizeof(uint16_t) * (size_t)m->bpad * h) == hipSuccess;
     if (!cleared || refresh_copies(m, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
       free_mlp(m);
@@ -423,6 +427,25 @@ farm_status farm_mlp_get_weights(const farm_mlp* m, float* W1, float* b1, float*
 farm_status farm_mlp_get_grads(const farm_mlp* m, float* W1, float* b1, float* W2, float* b2, float* W3, float* b3) {
   if (!m) { set_error("null network"); return FARM_ERR_INVALID_ARG; }
   return host_io(m, m->grad, W1, b1, W2, b2, W3, b3, true);
+}
+
+farm_status farm_mlp_get_batch(const farm_mlp* m, int32_t nb, float* Z1, uint16_t* A1, float* Z2, uint16_t* A2,
+                              float* Y, uint16_t* dZ2, float* dA1, uint16_t* dZ1) {
+  if (!m) { set_error("null network"); return FARM_ERR_INVALID_ARG; }
+  if (nb < 1 || nb > m->bmax) { set_error("nb = %d outside [1, %d]", nb, m->bmax); return FARM_ERR_INVALID_ARG; }
+  if (hipDeviceSynchronize() != hipSuccess) { set_error("synchronize failed"); return FARM_ERR_HIP; }
+  const size_t hs = (size_t)nb * m->h;
+  struct Part { void* host; const void* dev; size_t bytes; } parts[8] = {
+      {Z1, m->Z1, hs * sizeof(float)},   {A1, m->A1, hs * sizeof(uint16_t)},
+      {Z2, m->Z2, hs * sizeof(float)},   {A2, m->A2, hs * sizeof(uint16_t)},
+      {Y, m->Y, (size_t)nb * kNPred * sizeof(float)},
+      {dZ2, m->dZ, hs * sizeof(uint16_t)}, {dA1, m->dA, hs * sizeof(float)}, {dZ1, m->dZ1, hs * sizeof(uint16_t)}};
+  for (auto& pt : parts) {
+    if (!pt.host) continue;
+    hipError_t e = hipMemcpy(pt.host, pt.dev, pt.bytes, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "batch copy");
+  }
+  return FARM_OK;
 }
 
 farm_status farm_mlp_set_weights(farm_mlp* m, const float* W1, const float* b1, const float* W2, const float* b2,
@@ -500,13 +523,15 @@ farm_status farm_mlp_step(farm_mlp* m, const farm_memory* mem, int32_t nb, const
       return hip_fail(e, "dW2");
     if ((e = launch_gemm_nt_bf16(m->dZ, h, m->W2bT, h, nb, h, h, m->dA, h, nullptr, false, s)))
       return hip_fail(e, "dA1");
-    // layer 1
+    // layer 1 (dZ1 in a buffer of its own, so that dZ2 stays readable after the step)
     hipLaunchKernelGGL(k_gelu_back, dim3(blocks((int64_t)nb * h)), dim3(256), 0, s, m->dA, m->Z1, (int64_t)nb * h,
-                       m->dZ);
-    hipLaunchKernelGGL(k_colsum_part, dim3(blocks(h), chunks), dim3(256), 0, s, m->dZ, nb, (int32_t)h, m->red_part);
+                       m->dZ1);
+    if (nbp > nb)
+      hipLaunchKernelGGL(k_zero_u16, dim3(blocks((nbp - nb) * h)), dim3(256), 0, s, m->dZ1 + nb * h, (nbp - nb) * h);
+    hipLaunchKernelGGL(k_colsum_part, dim3(blocks(h), chunks), dim3(256), 0, s, m->dZ1, nb, (int32_t)h, m->red_part);
     hipLaunchKernelGGL(k_sum_chunks, dim3(blocks(h)), dim3(256), 0, s, m->red_part, (int32_t)chunks, (int32_t)h,
                        (int32_t)h, false, m->gb1, nullptr);
-    hipLaunchKernelGGL(k_transpose_u16, dim3(blocks(h, 32), blocks(nbp, 32)), dim3(32, 8), 0, s, m->dZ, nbp, h, h,
+    hipLaunchKernelGGL(k_transpose_u16, dim3(blocks(h, 32), blocks(nbp, 32)), dim3(32, 8), 0, s, m->dZ1, nbp, h, h,
                        m->dZT, nbp);
     hipLaunchKernelGGL(k_transpose_u16, dim3(blocks(ldx, 32), blocks(nbp, 32)), dim3(32, 8), 0, s, m->X, nbp, ldx,
                        ldx, m->XT, nbp);

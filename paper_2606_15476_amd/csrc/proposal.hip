@@ -118,6 +118,21 @@ __device__ inline float pred_value(int p, int64_t o, int64_t a, const float* x, 
   return pair_value<kFamLat>(t, r, c);
 }
 
+// Non-learned ranking: L[p][t][a] = P_p(o_t, a) in the family's comparison
+// domain (self pairs -inf), so that a list holds the M anchors of largest
+// predicate value and Pout is the (M+1)-th largest.
+__global__ void k_value_rows(int64_t t0, int64_t tc, int64_t n, const float* __restrict__ x,
+                             const float* __restrict__ y, const float* __restrict__ z, const float* __restrict__ vz,
+                             const float* __restrict__ hhi, const float* __restrict__ hlo, float* __restrict__ L) {
+  const int p = blockIdx.y;
+  const int64_t pr = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pr >= tc * n) return;
+  const int64_t t = pr / n, a = pr % n, o = t0 + t;
+  const int64_t sh = is_depth(p) ? n : 0;
+  const ZPair zp = z_for(p, z, vz, n);
+  L[((int64_t)p * tc + t) * n + a] = a == o ? -INFINITY : pred_value(p, o, a, x, y, zp, hhi + sh, hlo + sh);
+}
+
 // One block per (target t of the chunk, predicate): write the list (entries
 // that selection could not fill repeat a real anchor) and Pout.
 __global__ __launch_bounds__(256) void k_prop_finalize(const int32_t* __restrict__ top_idx, int32_t M, int64_t t0,
@@ -248,15 +263,43 @@ hipError_t launch_semantic_sets(const float* sim, int64_t ld_s, int32_t q, int32
   return hipGetLastError();
 }
 
+// The table build's forward pass, shared by farm_build_proposals and
+// farm_mlp_table_logits.  First-layer factors U = D W1o^T, V = D W1a^T
+// ([n][H] FP32) from the BF16 descriptors dnb.
+static hipError_t table_factors(const farm_memory* mem, const farm_mlp* mlp, const uint16_t* dnb, float* U, float* V,
+                                hipStream_t s) {
+  const int64_t H = FARM_MLP_HIDDEN;
+  hipError_t e = launch_gemm_nt_bf16(dnb, mem->ldk, mlp->W1b, mlp->ldx, mem->n, H, mlp->dp, U, H, nullptr, false, s);
+  if (e == hipSuccess)
+    e = launch_gemm_nt_bf16(dnb, mem->ldk, mlp->W1b + mlp->dp, mlp->ldx, mem->n, H, mlp->dp, V, H, nullptr, false, s);
+  return e;
+}
+
+// Logits L[p][t][a] of targets t0 .. t0 + tc - 1 against every anchor a (self
+// pairs -inf); A1, A2: [tc * n][H] BF16 activation buffers.
+static hipError_t table_logits_chunk(const farm_memory* mem, const farm_mlp* mlp, const float* U, const float* V,
+                                     int64_t t0, int64_t tc, uint16_t* A1, uint16_t* A2, float* L, hipStream_t s) {
+  const int64_t H = FARM_MLP_HIDDEN, n = mem->n, pairs = tc * n;
+  hipLaunchKernelGGL(k_hidden1, dim3((unsigned)pairs), dim3((unsigned)H), 0, s, U, V, mlp->b1, mlp->W1b, mlp->ldx,
+                     2 * mlp->dp, t0, n, mem->x, mem->y, mem->z, mem->ext, mem->rx, mem->ry, A1);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = launch_gemm_nt_bf16(A1, H, mlp->W2b, H, pairs, H, H, A2, H, mlp->b2, true, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_head_rows, dim3(nblk(pairs)), dim3(256), 0, s, A2, mlp->W3r, mlp->b3, t0, tc, n, L);
+  return hipGetLastError();
+}
+
 }  // namespace farm
 
 using namespace farm;
 
-extern "C" farm_status farm_build_proposals(farm_memory* mem, farm_mlp* mlp, int32_t M, void* stream) {
+// The lists of a memory ranked by the network's logits (mlp != null) or by
+// the exact predicate value (mlp == null, the non-learned baseline).
+static farm_status build_lists(farm_memory* mem, farm_mlp* mlp, int32_t M, void* stream) {
   try {
-    if (!mem || !mlp) { set_error("null memory or network"); return FARM_ERR_INVALID_ARG; }
-    if (mlp->device != mem->device) { set_error("network and memory live on different devices"); return FARM_ERR_INVALID_ARG; }
-    if (mlp->d != mem->d) { set_error("network width %d != memory width %d", mlp->d, mem->d); return FARM_ERR_INVALID_ARG; }
+    if (!mem) { set_error("null memory"); return FARM_ERR_INVALID_ARG; }
+    if (mlp && mlp->device != mem->device) { set_error("network and memory live on different devices"); return FARM_ERR_INVALID_ARG; }
+    if (mlp && mlp->d != mem->d) { set_error("network width %d != memory width %d", mlp->d, mem->d); return FARM_ERR_INVALID_ARG; }
     if (M < 1 || M > FARM_MAX_K) { set_error("M = %d outside [1, %d]", M, FARM_MAX_K); return FARM_ERR_INVALID_ARG; }
     const int64_t n = mem->n;
     // the per-target bitmap of listed anchors lives in LDS (n / 8 bytes, at most 62.5 KiB)
@@ -294,30 +337,30 @@ extern "C" farm_status farm_build_proposals(farm_memory* mem, farm_mlp* mlp, int
         !alloc(mem->prop_allocs, sizeof(float) * kNPred * M * n, (void**)&pval) ||
         !alloc(mem->prop_allocs, sizeof(float) * kNPred * n, (void**)&pout))
       return fail(FARM_ERR_OOM, "table allocation");
-    // BF16 descriptors, U = D W1o^T, V = D W1a^T
+    // network ranking: BF16 descriptors, U = D W1o^T, V = D W1a^T
     const int64_t ldk = mem->ldk;
     uint16_t* dnb = mem->dn_bf16;
-    float *U, *V;
-    if (!dnb && !alloc(tmp, sizeof(uint16_t) * n * ldk, (void**)&dnb)) return fail(FARM_ERR_OOM, "descriptor copy");
-    if (!alloc(tmp, sizeof(float) * n * H, (void**)&U) || !alloc(tmp, sizeof(float) * n * H, (void**)&V))
-      return fail(FARM_ERR_OOM, "first-layer factors");
+    float *U = nullptr, *V = nullptr;
     hipError_t e;
-    if (!mem->dn_bf16) {
-      hipLaunchKernelGGL(k_rows_to_bf16, dim3(nblk(n * ldk)), dim3(256), 0, s, mem->dn, n * ldk, dnb);
-      if ((e = hipGetLastError()) != hipSuccess) return fail(FARM_ERR_HIP, "descriptor copy");
+    if (mlp) {
+      if (!dnb && !alloc(tmp, sizeof(uint16_t) * n * ldk, (void**)&dnb)) return fail(FARM_ERR_OOM, "descriptor copy");
+      if (!alloc(tmp, sizeof(float) * n * H, (void**)&U) || !alloc(tmp, sizeof(float) * n * H, (void**)&V))
+        return fail(FARM_ERR_OOM, "first-layer factors");
+      if (!mem->dn_bf16) {
+        hipLaunchKernelGGL(k_rows_to_bf16, dim3(nblk(n * ldk)), dim3(256), 0, s, mem->dn, n * ldk, dnb);
+        if ((e = hipGetLastError()) != hipSuccess) return fail(FARM_ERR_HIP, "descriptor copy");
+      }
+      if ((e = table_factors(mem, mlp, dnb, U, V, s))) return fail(FARM_ERR_HIP, "first-layer GEMMs");
     }
-    if ((e = launch_gemm_nt_bf16(dnb, ldk, mlp->W1b, mlp->ldx, n, H, mlp->dp, U, H, nullptr, false, s)) ||
-        (e = launch_gemm_nt_bf16(dnb, ldk, mlp->W1b + mlp->dp, mlp->ldx, n, H, mlp->dp, V, H, nullptr, false, s)))
-      return fail(FARM_ERR_HIP, "first-layer GEMMs");
     // chunks of targets
     // chunk of targets: at most 16, and at most 2^22 pairs (2 GiB of BF16 activations per buffer)
     int64_t tc_max = ((int64_t)1 << 22) / n;
     tc_max = tc_max < 1 ? 1 : tc_max > 16 ? 16 : tc_max;
     if (tc_max > n) tc_max = n;
-    uint16_t *A1, *A2;
+    uint16_t *A1 = nullptr, *A2 = nullptr;
     float* L;
-    if (!alloc(tmp, sizeof(uint16_t) * tc_max * n * H, (void**)&A1) ||
-        !alloc(tmp, sizeof(uint16_t) * tc_max * n * H, (void**)&A2) ||
+    if ((mlp && (!alloc(tmp, sizeof(uint16_t) * tc_max * n * H, (void**)&A1) ||
+                 !alloc(tmp, sizeof(uint16_t) * tc_max * n * H, (void**)&A2))) ||
         !alloc(tmp, sizeof(float) * kNPred * tc_max * n, (void**)&L))
       return fail(FARM_ERR_OOM, "chunk buffers");
     // TopK candidate buffers in a scratch workspace
@@ -333,12 +376,13 @@ extern "C" farm_status farm_build_proposals(farm_memory* mem, farm_mlp* mlp, int
     const size_t bitmap = sizeof(uint32_t) * (size_t)((n + 31) / 32);
     for (int64_t t0 = 0; t0 < n; t0 += tc_max) {
       const int64_t tc = n - t0 < tc_max ? n - t0 : tc_max;
-      const int64_t pairs = tc * n;
-      hipLaunchKernelGGL(k_hidden1, dim3((unsigned)pairs), dim3((unsigned)H), 0, s, U, V, mlp->b1, mlp->W1b, mlp->ldx,
-                         2 * mlp->dp, t0, n, mem->x, mem->y, mem->z, mem->ext, mem->rx, mem->ry, A1);
-      if ((e = launch_gemm_nt_bf16(A1, H, mlp->W2b, H, pairs, H, H, A2, H, mlp->b2, true, s)))
-        return fail(FARM_ERR_HIP, "second layer");
-      hipLaunchKernelGGL(k_head_rows, dim3(nblk(pairs)), dim3(256), 0, s, A2, mlp->W3r, mlp->b3, t0, tc, n, L);
+      if (mlp) {
+        if ((e = table_logits_chunk(mem, mlp, U, V, t0, tc, A1, A2, L, s))) return fail(FARM_ERR_HIP, "table forward");
+      } else {
+        hipLaunchKernelGGL(k_value_rows, dim3(nblk(tc * n), kNPred), dim3(256), 0, s, t0, tc, n, mem->x, mem->y, mem->z,
+                           mem->vz, mem->hr_hi, mem->hr_lo, L);
+        if ((e = hipGetLastError()) != hipSuccess) return fail(FARM_ERR_HIP, "predicate values");
+      }
       uint64_t* key;
       int32_t* idx;
       if ((e = launch_topk(mem, &tw, L, n, (int32_t)(kNPred * tc), M, &key, &idx, s)))
@@ -362,6 +406,15 @@ extern "C" farm_status farm_build_proposals(farm_memory* mem, farm_mlp* mlp, int
   }
 }
 
+extern "C" farm_status farm_build_proposals(farm_memory* mem, farm_mlp* mlp, int32_t M, void* stream) {
+  if (!mlp) { set_error("null network"); return FARM_ERR_INVALID_ARG; }
+  return build_lists(mem, mlp, M, stream);
+}
+
+extern "C" farm_status farm_build_proposals_by_value(farm_memory* mem, int32_t M, void* stream) {
+  return build_lists(mem, nullptr, M, stream);
+}
+
 extern "C" farm_status farm_get_proposals(const farm_memory* mem, int32_t* m_out, int32_t* idx, float* val, float* out,
                                           void* stream) {
   try {
@@ -380,6 +433,56 @@ extern "C" farm_status farm_get_proposals(const farm_memory* mem, int32_t* m_out
     return e == hipSuccess ? FARM_OK : hip_fail(e, "copying proposal tables");
   } catch (...) {
     set_error("unexpected host exception in farm_get_proposals");
+    return FARM_ERR_HIP;
+  }
+}
+
+extern "C" farm_status farm_mlp_table_logits(farm_mlp* mlp, const farm_memory* mem, int64_t t0, int32_t tc,
+                                             float* logits, void* stream) {
+  try {
+    if (!mem || !mlp || !logits) { set_error("null memory, network or output"); return FARM_ERR_INVALID_ARG; }
+    if (mlp->device != mem->device || mlp->d != mem->d) { set_error("network and memory do not match"); return FARM_ERR_INVALID_ARG; }
+    const int64_t n = mem->n, H = FARM_MLP_HIDDEN;
+    if (tc < 1 || tc > 16 || t0 < 0 || t0 + tc > n || (int64_t)tc * n > ((int64_t)1 << 22)) {
+      set_error("targets [%lld, %lld) outside the memory or the chunk limits", (long long)t0, (long long)(t0 + tc));
+      return FARM_ERR_INVALID_ARG;
+    }
+    DeviceGuard guard(mem->device);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<void*> tmp;
+    auto alloc = [&](size_t bytes, void** p) -> bool {
+      if (hipMalloc(p, bytes ? bytes : 1) != hipSuccess) { (void)hipGetLastError(); return false; }
+      tmp.push_back(*p);
+      return true;
+    };
+    auto done = [&](farm_status st, const char* what) {
+      (void)hipStreamSynchronize(s);
+      for (void* p : tmp) (void)hipFree(p);
+      if (st != FARM_OK) set_error("table logits: %s", what);
+      return st;
+    };
+    uint16_t* dnb = mem->dn_bf16;
+    float *U, *V;
+    uint16_t *A1, *A2;
+    if (!dnb && !alloc(sizeof(uint16_t) * n * mem->ldk, (void**)&dnb)) return done(FARM_ERR_OOM, "descriptor copy");
+    if (!alloc(sizeof(float) * n * H, (void**)&U) || !alloc(sizeof(float) * n * H, (void**)&V) ||
+        !alloc(sizeof(uint16_t) * tc * n * H, (void**)&A1) || !alloc(sizeof(uint16_t) * tc * n * H, (void**)&A2))
+      return done(FARM_ERR_OOM, "buffers");
+    hipError_t e = hipSuccess;
+    if (!mem->dn_bf16) {
+      hipLaunchKernelGGL(k_rows_to_bf16, dim3(nblk(n * mem->ldk)), dim3(256), 0, s, mem->dn, n * mem->ldk, dnb);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = table_factors(mem, mlp, dnb, U, V, s);
+    if (e == hipSuccess) e = table_logits_chunk(mem, mlp, U, V, t0, tc, A1, A2, logits, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      done(FARM_OK, "");
+      return hip_fail(e, "table logits forward");
+    }
+    return done(FARM_OK, "");
+  } catch (...) {
+    set_error("unexpected host exception in farm_mlp_table_logits");
     return FARM_ERR_HIP;
   }
 }

@@ -88,3 +88,109 @@ def test_gradients_match_central_differences():
             flat[i] = old
             fd = (lp - lm) / (2 * eps)
             assert g[name].reshape(-1)[i] == pytest.approx(fd, rel=1e-5, abs=1e-9), (name, i)
+
+
+# ---------------------------------------------------------------- layer-by-layer references (oracle/mlp_layers.py)
+def _fp64_chain(W, X, pred, lab):
+    """Stage values of an exact FP64 evaluation (what the layer references
+    consume when no rounding happened)."""
+    from oracle import mlp_layers as ml
+    z1 = X @ W["W1"].T + W["b1"]
+    a1 = ml.gelu(z1)
+    z2 = a1 @ W["W2"].T + W["b2"]
+    a2 = ml.gelu(z2)
+    y = a2 @ W["W3"].T + W["b3"]
+    _, dY, _ = ml.loss_and_dy(y, pred, lab)
+    dz2 = (dY @ W["W3"]) * ml.gelu_grad(z2)
+    da1 = dz2 @ W["W2"]
+    dz1 = da1 * ml.gelu_grad(z1)
+    return {"Z1": z1, "A1": a1, "Z2": z2, "A2": a2, "Y": y, "dZ2": dz2, "dA1": da1, "dZ1": dz1}
+
+
+def test_layer_references_equal_the_loop_oracle():
+    """Fed the exact FP64 stage values, the layer references reproduce the C
+    oracle's plain-loop forward, loss and every gradient (two independent
+    implementations); predicates without an output (9..11) add nothing."""
+    from oracle import mlp_layers as ml
+    rng = np.random.default_rng(4)
+    inp, h, nb = 11, 6, 40
+    W = _weights(rng, inp, h)
+    X = rng.standard_normal((nb, inp))
+    pred = rng.integers(0, 12, nb).astype(np.int32)
+    lab = rng.integers(0, 2, nb).astype(np.float64)
+    # the C oracle takes every sample's predicate as an output index: give it only the labelled rows,
+    # scaled to the mean over all nb rows
+    keep = pred < NP
+    loss_c, logits_c, g_c = oracle.mlp(W, X[keep], pred[keep], lab[keep])
+    scale = keep.sum() / nb
+    st = _fp64_chain(W, X, pred, lab)
+    fw = ml.forward_stages(W, X, st)
+    np.testing.assert_allclose(fw["Y"][0][keep], logits_c, rtol=1e-12, atol=1e-14)
+    for name in ("Z1", "A1", "Z2", "A2", "Y"):
+        np.testing.assert_allclose(fw[name][0], st[name], rtol=1e-12, atol=1e-14)
+    bw = ml.backward_stages(W, X, st, pred, lab)
+    assert bw["loss"][0] == pytest.approx(loss_c * scale, rel=1e-12)
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        np.testing.assert_allclose(bw["g" + k][0], g_c[k] * scale, rtol=1e-10, atol=1e-15)
+
+
+def test_gelu_derivative_by_central_differences():
+    from oracle import mlp_layers as ml
+    v = np.linspace(-6, 6, 97)
+    h = 1e-6
+    fd = (ml.gelu(v + h) - ml.gelu(v - h)) / (2 * h)
+    np.testing.assert_allclose(ml.gelu_grad(v), fd, rtol=1e-7, atol=1e-9)
+    assert np.max(np.abs(ml.gelu_grad(np.linspace(-10, 10, 20001)))) <= ml.GELU_SLOPE_MAX
+
+
+def test_forward_bound_covers_an_fp32_bf16_evaluation():
+    """An explicit evaluation with FP32 products/sums and BF16-stored
+    activations (numpy float32, round-to-nearest-even to 8 significant bits)
+    lies within forward_bound of the FP64 logits."""
+    from oracle import mlp_layers as ml
+
+    def bf16(a):
+        u = np.asarray(a, np.float32).view(np.uint32).astype(np.uint64)
+        u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+        return u.astype(np.uint32).view(np.float32)
+
+    rng = np.random.default_rng(6)
+    inp, h, nb = 80, 64, 50
+    W = {k: (bf16(v).astype(np.float64) if k.startswith("W") else v) for k, v in _weights(rng, inp, h, 0.2).items()}
+    X = bf16(rng.standard_normal((nb, inp))).astype(np.float64)
+    f = {k: v.astype(np.float32) for k, v in W.items()}
+    g32 = lambda z: (np.float32(0.5) * z * (np.float32(1) + erf_f32(z / np.float32(math.sqrt(2))))).astype(np.float32)
+    a1 = bf16(g32(X.astype(np.float32) @ f["W1"].T + f["b1"]))
+    a2 = bf16(g32(a1 @ f["W2"].T + f["b2"]))
+    y32 = a2 @ f["W3"].T + f["b3"]
+    y, bound = ml.forward_bound(W, X)
+    err = np.abs(y32.astype(np.float64) - y)
+    assert np.all(err <= bound), float(np.max(err / bound))
+    assert np.max(err / bound) > 1e-3  # the bound is not vacuous
+
+
+def erf_f32(z):
+    from scipy.special import erf
+    return erf(z.astype(np.float64)).astype(np.float32)
+
+
+def test_adamw_reference():
+    """Step 1 from zero moments: m_hat = g, v_hat = g^2, so the step is
+    lr (g / (|g| + eps) + wd w); two steps equal torch.optim.AdamW (float64)."""
+    import torch
+    from oracle import mlp_layers as ml
+    rng = np.random.default_rng(8)
+    w = rng.standard_normal(50)
+    g1 = rng.standard_normal(50) * 1e-2
+    g1[:3] = [0.0, 1e-12, -1e-9]
+    lr, wd = 2e-3, 1e-4
+    w1, m1, v1, _ = ml.adamw(w, g1, np.zeros(50), np.zeros(50), 1, lr, wd)
+    np.testing.assert_allclose(w1, w - lr * (g1 / (np.abs(g1) + 1e-8) + wd * w), rtol=1e-13, atol=1e-16)
+    g2 = rng.standard_normal(50) * 1e-2
+    w2, _, _, _ = ml.adamw(w1, g2, m1, v1, 2, lr, wd)
+    p = torch.nn.Parameter(torch.tensor(w, dtype=torch.float64))
+    opt = torch.optim.AdamW([p], lr=lr, betas=(0.9, 0.999), eps=1e-8, weight_decay=wd)
+    for g in (g1, g2):
+        p.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+    np.testing.assert_allclose(w2, p.detach().numpy(), rtol=1e-12, atol=1e-15)
