@@ -62,6 +62,14 @@ def _load():
         lib.farm_oracle_mlp.restype = ctypes.c_int
         lib.farm_oracle_mlp.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, i64, P, P, P, P,
                                         P, P, P, P, P, P, P]
+        lib.farm_oracle_threads.restype = ctypes.c_int
+        lib.farm_oracle_threads.argtypes = []
+        lib.farm_oracle_set_threads.restype = None
+        lib.farm_oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.farm_oracle_between.restype = ctypes.c_double
+        lib.farm_oracle_between.argtypes = [P, P, P]
+        lib.farm_oracle_between_binding_value.restype = ctypes.c_double
+        lib.farm_oracle_between_binding_value.argtypes = [i64, ctypes.c_int, P, P, P, P, i64, i64, i64]
         lib.farm_oracle_set_rank_tolerance.restype = None
         lib.farm_oracle_set_rank_tolerance.argtypes = [ctypes.c_int, ctypes.c_double]
         lib.farm_oracle_topk_bounded.restype = ctypes.c_int
@@ -76,12 +84,9 @@ def _c(a, dtype):
     return a, a.ctypes.data_as(ctypes.c_void_p)
 
 
-def set_threads(n: int | None):
-    """Limit OpenMP threads (None = library default)."""
-    if n is None:
-        os.environ.pop("OMP_NUM_THREADS", None)
-    else:
-        os.environ["OMP_NUM_THREADS"] = str(int(n))
+def threads() -> int:
+    """Threads the oracle's parallel loops use."""
+    return int(_load().farm_oracle_threads())
 
 
 class rank_tolerance:
@@ -104,6 +109,11 @@ class rank_tolerance:
         return False
 
 
+def set_threads(n: int):
+    """Threads of the oracle's parallel loops from now on."""
+    _load().farm_oracle_set_threads(int(n))
+
+
 def predicate(p: int, ci, cj, right, ei=(0.0, 0.0, 0.0), ej=(0.0, 0.0, 0.0)) -> float:
     """P_p(i, j) in FP64 for float32 centers, full extents (used by On only) and
     viewer right vector."""
@@ -114,6 +124,26 @@ def predicate(p: int, ci, cj, right, ei=(0.0, 0.0, 0.0), ej=(0.0, 0.0, 0.0)) -> 
     eb, peb = _c(ej, np.float32)
     r, pr = _c(right, np.float32)
     return float(lib.farm_oracle_predicate(int(p), pa, pb, pea, peb, pr))
+
+
+def between(ci, c1, c2) -> float:
+    """Between(i; j1, j2) in FP64 for float32 centers of the target and the two anchors."""
+    lib = _load()
+    a, pa = _c(ci, np.float32)
+    b, pb = _c(c1, np.float32)
+    c, pc = _c(c2, np.float32)
+    return float(lib.farm_oracle_between(pa, pb, pc))
+
+
+def between_binding_value(scene, anchor1, anchor2, i: int, j1: int, j2: int) -> float:
+    """sim(j1, q1) * sim(j2, q2) * Between(i; j1, j2) in FP64 for one binding of a Between invocation."""
+    lib = _load()
+    desc, pd = _c(scene.desc, np.float32)
+    cen, pc = _c(scene.center, np.float32)
+    a1, p1 = _c(anchor1, np.float32)
+    a2, p2 = _c(anchor2, np.float32)
+    return float(lib.farm_oracle_between_binding_value(int(desc.shape[0]), int(desc.shape[1]), pd, pc, p1, p2,
+                                                       int(i), int(j1), int(j2)))
 
 
 def _scene_args(scene):
@@ -233,7 +263,8 @@ def binding_value(scene, pred: int, anchor_vec, i: int, j: int, target_cls: int 
                                                int(target_cls), int(pred), pa, int(i), int(j)))
 
 
-NUM_PRED = 12  # predicates the scorer evaluates (ids 0..11: On = 8, Closest = 9, Farthest = 10, Inside = 11)
+NUM_PRED = 14  # predicate ids 0..13 (On = 8, Closest = 9, Farthest = 10, Inside = 11, Between = 12 and its
+#               second anchor 13)
 NPRED = 9      # proposal-network outputs, one per predicate
 NGEO = 12
 

@@ -78,6 +78,23 @@ def soft_relation(pred, ci, cj, right, ei=(0.0, 0.0, 0.0), ej=(0.0, 0.0, 0.0)):
     raise ValueError(pred)
 
 
+def between_relation(ci, c1, c2):
+    """Between (ternary): the target's center projects inside the segment
+    joining the two anchors' centers (a logistic, 0.1 m, of each margin along
+    it) and lies near it (Gaussian, 0.5 m, of the distance to the foot of the
+    projection); 0 for coincident anchors."""
+    ci, c1, c2 = ([float(v) for v in c] for c in (ci, c1, c2))
+    u = [c2[k] - c1[k] for k in range(3)]
+    uu = sum(x * x for x in u)
+    if uu == 0.0:
+        return 0.0
+    lam = sum((ci[k] - c1[k]) * u[k] for k in range(3)) / uu  # position along the segment, 0 at c1, 1 at c2
+    foot = [c1[k] + lam * u[k] for k in range(3)]
+    h2 = sum((ci[k] - foot[k]) ** 2 for k in range(3))
+    L = math.sqrt(uu)
+    return _sigmoid(lam * L / 0.1) * _sigmoid((1.0 - lam) * L / 0.1) * math.exp(-h2 / (2 * 0.25))
+
+
 def rank_relation(pred, scene, tcls, i, j):
     """Closest (9) / Farthest (10): 1 / (|rank - r*| + 1), the rank of target i
     among the query's candidates (objects of class tcls; all objects without a
@@ -127,16 +144,26 @@ def brute_scores(scene, qb):
             best = None
             if not others:
                 best = s_sem * (1 - W)
+            # predicate invocations: a Between (12) takes its slot's and the next
+            # slot's (13) anchor variables together and counts once
+            n_inv = sum(1 for pred, _ in rels if pred != 13)
             for binding in itertools.product(others, repeat=len(rels)):
                 prod = 1.0
-                for (pred, qr), j in zip(rels, binding):
+                for k, ((pred, qr), j) in enumerate(zip(rels, binding)):
+                    if pred == 13:
+                        continue
+                    if pred == 12:
+                        j2 = binding[k + 1]
+                        pv = between_relation(scene.center[e], scene.center[j], scene.center[j2])
+                        prod *= _sim(units[j], qr) * _sim(units[j2], rels[k + 1][1]) * pv
+                        continue
                     if pred in (9, 10):
                         pv = rank_relation(pred, scene, tcls, e, j)
                     else:
                         pv = soft_relation(pred, scene.center[e], scene.center[j], scene.view_right,
                                            scene.extent[e], scene.extent[j])
                     prod *= _sim(units[j], qr) * pv
-                v = s_sem * ((1 - W) + W * prod ** (1.0 / len(rels)))
+                v = s_sem * ((1 - W) + W * prod ** (1.0 / n_inv))
                 if best is None or v > best:
                     best = v
             row.append(best)

@@ -37,6 +37,10 @@
  *   CLOSEST  = 1 / rank,  FARTHEST = 1 / (last rank - rank + 1): the rank of i
  *              among the query's candidates by distance to j (see rank_value)
  *   INSIDE   = prod_k sig((e_j,k / 2 - |D_k|) / 0.1): i's center within j's box
+ *   BETWEEN  (ternary, two anchors j1, j2; see between_value) = sig(s / 0.1)
+ *              sig((L - s) / 0.1) exp(-h^2 / (2 * 0.5^2)): s the offset of i's
+ *              center along the axis from j1 to j2, L = |c_j2 - c_j1|, h its
+ *              distance from that axis; 0 when L = 0
  * where (r_x, r_y) is the scene viewer's right vector, f = (-r_y, r_x) its
  * viewing direction and e the full box extents.  The temperatures
  * (0.1 m), the Gaussian's normalisation, the clamp at zero, the viewer
@@ -44,14 +48,18 @@
  * where the paper is silent.
  *
  * Everything is computed in double precision from the float inputs, with plain
- * loops in the order of the definition.  OpenMP parallelises only the
- * independent outer loop over queries (or sampled targets).
+ * loops in the order of the definition.  OpenMP parallelises only independent
+ * loops: over the objects of a query (full scores) or over queries (sampled
+ * pairs, bounded TopK).
  */
 #define _GNU_SOURCE
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORACLE_W 0.5
 #define ORACLE_CLASS_FACTOR 0.3
@@ -64,7 +72,8 @@
 #define ORACLE_NO_ID 0xFFFFFFFFu
 
 enum { P_NEAR = 0, P_ABOVE = 1, P_BELOW = 2, P_LEFT_OF = 3, P_RIGHT_OF = 4, P_NEXT_TO = 5, P_IN_FRONT_OF = 6,
-       P_BEHIND = 7, P_ON = 8, P_CLOSEST = 9, P_FARTHEST = 10, P_INSIDE = 11, P_COUNT = 12 };
+       P_BEHIND = 7, P_ON = 8, P_CLOSEST = 9, P_FARTHEST = 10, P_INSIDE = 11, P_BETWEEN = 12, P_AND = 13,
+       P_COUNT = 14 };
 
 static double logistic(double u) { return 1.0 / (1.0 + exp(-u)); }
 
@@ -121,6 +130,32 @@ double farm_oracle_predicate(int p, const float* ci, const float* cj, const floa
     double a[3] = {ci[0], ci[1], ci[2]}, b[3] = {cj[0], cj[1], cj[2]}, r[2] = {right[0], right[1]};
     double ea[3] = {ei[0], ei[1], ei[2]}, eb[3] = {ej[0], ej[1], ej[2]};
     return oracle_predicate(p, a, b, ea, eb, r);
+}
+
+/* Between(i; j1, j2) (Appendix "Retrieval Details": a predicate of the
+ * vocabulary; Appendix "Robust Relational Retrieval Formulation", query-time
+ * complexity: a higher-arity predicate coupling the target and two anchors).
+ * The paper gives no form; reading: i lies between the anchors when its
+ * center projects inside the segment joining their centers -- both margins
+ * along the axis positive, each a logistic with the other sigmoids'
+ * temperature (0.1 m) -- and lies near that axis -- Near's Gaussian (0.5 m) of
+ * the perpendicular distance.  Symmetric in j1, j2; 0 for coincident anchors. */
+static double between_value(const double* ci, const double* c1, const double* c2) {
+    double u[3], w[3];
+    for (int k = 0; k < 3; ++k) { u[k] = c2[k] - c1[k]; w[k] = ci[k] - c1[k]; }
+    double L2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    if (L2 == 0.0) return 0.0;
+    double L = sqrt(L2);
+    double s = (w[0] * u[0] + w[1] * u[1] + w[2] * u[2]) / L;
+    double h2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2] - s * s;
+    if (h2 < 0.0) h2 = 0.0;
+    return logistic(s / ORACLE_TAU) * logistic((L - s) / ORACLE_TAU) *
+           exp(-h2 / (2.0 * ORACLE_NEAR_SIGMA * ORACLE_NEAR_SIGMA));
+}
+
+double farm_oracle_between(const float* ci, const float* c1, const float* c2) {
+    double a[3] = {ci[0], ci[1], ci[2]}, b[3] = {c1[0], c1[1], c1[2]}, c[3] = {c2[0], c2[1], c2[2]};
+    return between_value(a, b, c);
 }
 
 static void unit_vector(const float* v, int d, double* out) {
@@ -193,6 +228,7 @@ static int query_init(query64* qs, const scene64* s, const float* target, int32_
     double* v = (double*)malloc(sizeof(double) * (size_t)d);
     if (!qs->sem || !qs->asim || !v) { free(v); return -2; }
     unit_vector(target, d, v);
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double kappa = (tcls >= 0 && s->cls && s->cls[i] >= 0 && s->cls[i] != tcls) ? ORACLE_CLASS_FACTOR : 1.0;
         qs->sem[i] = kappa * clamped_cosine(s->u + (size_t)i * d, v, d);
@@ -200,6 +236,7 @@ static int query_init(query64* qs, const scene64* s, const float* target, int32_
     for (int rr = 0; rr < r; ++rr) {
         qs->pred[rr] = pred[rr];
         unit_vector(anchors + (size_t)rr * d, d, v);
+#pragma omp parallel for schedule(static)
         for (int64_t j = 0; j < n; ++j) qs->asim[(size_t)rr * n + j] = clamped_cosine(s->u + (size_t)j * d, v, d);
     }
     free(v);
@@ -225,6 +262,23 @@ static double dist2(const double* c, int64_t a, int64_t b) {
     double dy = c[a * 3 + 1] - c[b * 3 + 1];
     double dz = c[a * 3 + 2] - c[b * 3 + 2];
     return dx * dx + dy * dy + dz * dz;
+}
+
+/* Threads the parallel loops use (OpenMP's maximum), and a way to set it. */
+int farm_oracle_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void farm_oracle_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }
 
 static int is_rank_pred(int p) { return p == P_CLOSEST || p == P_FARTHEST; }
@@ -266,8 +320,37 @@ static double rank_value(const scene64* s, int32_t tcls, int p, int64_t i, int64
     return 1.0 / (double)(off + 1);
 }
 
+/* Between's term: max over anchor pairs j1 != j2, both != i, of
+ * sim(j1, q_rr) sim(j2, q_rr+1) Between(i; j1, j2) (the two relation slots
+ * rr, rr + 1 hold the two anchor descriptions); ties by the smaller
+ * (id(j1), id(j2)); no binding (NO_ID) when the term is 0. */
+static void between_term(const scene64* s, const query64* qs, int rr, int64_t i, double* t, uint32_t* b1,
+                         uint32_t* b2) {
+    const double* a1 = qs->asim + (size_t)rr * s->n;
+    const double* a2 = qs->asim + (size_t)(rr + 1) * s->n;
+    double best = 0.0;
+    uint32_t id1 = ORACLE_NO_ID, id2 = ORACLE_NO_ID;
+    for (int64_t j1 = 0; j1 < s->n; ++j1) {
+        if (j1 == i || a1[j1] == 0.0) continue;
+        for (int64_t j2 = 0; j2 < s->n; ++j2) {
+            if (j2 == i || j2 == j1) continue;
+            double v = a1[j1] * a2[j2] * between_value(s->c + i * 3, s->c + j1 * 3, s->c + j2 * 3);
+            if (v <= 0.0) continue;
+            if (v > best || (v == best && (s->id[j1] < id1 || (s->id[j1] == id1 && s->id[j2] < id2)))) {
+                best = v;
+                id1 = s->id[j1];
+                id2 = s->id[j2];
+            }
+        }
+    }
+    *t = best;
+    *b1 = id1;
+    if (b2) *b2 = id2;
+}
+
 /* t_r(i) and b_r(i): exhaustive maximum over anchors j != i. */
 static void relation_term(const scene64* s, const query64* qs, int rr, int64_t i, double* t, uint32_t* b) {
+    if (qs->pred[rr] == P_BETWEEN) { between_term(s, qs, rr, i, t, b, NULL); return; }
     double best = -1.0;
     uint32_t best_id = ORACLE_NO_ID;
     const double* a = qs->asim + (size_t)rr * s->n;
@@ -287,13 +370,32 @@ static void relation_term(const scene64* s, const query64* qs, int rr, int64_t i
     *b = best_id;
 }
 
-static double composite(double sem, int r, const double* t) {
-    double gbar = 1.0;
-    if (r > 0) {
-        double prod = 1.0;
-        for (int rr = 0; rr < r; ++rr) prod *= t[rr];
-        gbar = pow(prod, 1.0 / (double)r);
+/* Every slot's term and binding of object i.  A Between invocation spans two
+ * slots: both report its term, the first binds j1 and the second j2. */
+static void query_terms(const scene64* s, const query64* qs, int64_t i, double* t, uint32_t* b) {
+    for (int rr = 0; rr < qs->r; ++rr) {
+        if (qs->pred[rr] == P_BETWEEN) {
+            between_term(s, qs, rr, i, &t[rr], &b[rr], &b[rr + 1]);
+            t[rr + 1] = t[rr];
+            ++rr;
+        } else {
+            relation_term(s, qs, rr, i, &t[rr], &b[rr]);
+        }
     }
+}
+
+/* The composite over the query's predicate invocations: geometric mean of the
+ * terms (a Between invocation's two slots count once). */
+static double composite(double sem, int r, const double* t, const int* pred) {
+    double gbar = 1.0;
+    double prod = 1.0;
+    int cnt = 0;
+    for (int rr = 0; rr < r; ++rr) {
+        if (pred[rr] == P_AND) continue;
+        prod *= t[rr];
+        ++cnt;
+    }
+    if (cnt > 0) gbar = pow(prod, 1.0 / (double)cnt);
     return sem * ((1.0 - ORACLE_W) + ORACLE_W * gbar);
 }
 
@@ -302,8 +404,12 @@ static int check_query_meta(int32_t q, const int32_t* rel_off, const int32_t* re
     for (int32_t k = 0; k < q; ++k) {
         int r = rel_off[k + 1] - rel_off[k];
         if (r < 0 || r > ORACLE_MAX_REL) return -1;
-        for (int rr = rel_off[k]; rr < rel_off[k + 1]; ++rr)
+        for (int rr = rel_off[k]; rr < rel_off[k + 1]; ++rr) {
             if (rel_pred[rr] < 0 || rel_pred[rr] >= P_COUNT) return -1;
+            /* Between's second anchor follows it in the same query, and only there */
+            if (rel_pred[rr] == P_BETWEEN && (rr + 1 >= rel_off[k + 1] || rel_pred[rr + 1] != P_AND)) return -1;
+            if (rel_pred[rr] == P_AND && (rr == rel_off[k] || rel_pred[rr - 1] != P_BETWEEN)) return -1;
+        }
     }
     return 0;
 }
@@ -325,27 +431,28 @@ int farm_oracle_score(int64_t n, int d, const float* desc, const float* center, 
     scene64 s;
     if (scene_init(&s, n, d, desc, center, extent, id, cls, right)) { scene_free(&s); return -2; }
     int err = 0;
-#pragma omp parallel for schedule(dynamic, 1)
-    for (int32_t k = 0; k < q; ++k) {
+    /* queries one after another; the objects of a query (and its similarity
+     * rows) in parallel, so that every thread works whatever the query count */
+    for (int32_t k = 0; k < q && !err; ++k) {
         query64 qs;
         int r = rel_off[k + 1] - rel_off[k];
         int r0 = rel_off[k];
         if (query_init(&qs, &s, target + (size_t)k * d, target_cls ? target_cls[k] : -1, r,
                        rel_pred + r0, rel_anchor + (size_t)r0 * d)) {
             query_free(&qs);
-#pragma omp atomic write
             err = -2;
             continue;
         }
+#pragma omp parallel for schedule(dynamic, 16)
         for (int64_t i = 0; i < n; ++i) {
             double t[ORACLE_MAX_REL];
+            uint32_t b[ORACLE_MAX_REL];
+            query_terms(&s, &qs, i, t, b);
             for (int rr = 0; rr < r; ++rr) {
-                uint32_t b;
-                relation_term(&s, &qs, rr, i, &t[rr], &b);
                 if (rel_terms) rel_terms[(size_t)(r0 + rr) * n + i] = t[rr];
-                if (rel_anchor_id) rel_anchor_id[(size_t)(r0 + rr) * n + i] = b;
+                if (rel_anchor_id) rel_anchor_id[(size_t)(r0 + rr) * n + i] = b[rr];
             }
-            scores[(size_t)k * n + i] = composite(qs.sem[i], r, t);
+            scores[(size_t)k * n + i] = composite(qs.sem[i], r, t, qs.pred);
             if (sem) sem[(size_t)k * n + i] = qs.sem[i];
         }
         query_free(&qs);
@@ -389,14 +496,14 @@ int farm_oracle_score_pairs(int64_t n, int d, const float* desc, const float* ce
             if (qsel[p] != k) continue;
             int64_t i = osel[p];
             double t[ORACLE_MAX_REL];
+            uint32_t b[ORACLE_MAX_REL];
+            for (int rr = 0; rr < ORACLE_MAX_REL; ++rr) { t[rr] = 0.0; b[rr] = ORACLE_NO_ID; }
+            query_terms(&s, &qs, i, t, b);
             for (int rr = 0; rr < ORACLE_MAX_REL; ++rr) {
-                uint32_t b = ORACLE_NO_ID;
-                t[rr] = 0.0;
-                if (rr < r) relation_term(&s, &qs, rr, i, &t[rr], &b);
                 if (rel_terms) rel_terms[p * ORACLE_MAX_REL + rr] = t[rr];
-                if (rel_anchor_id) rel_anchor_id[p * ORACLE_MAX_REL + rr] = b;
+                if (rel_anchor_id) rel_anchor_id[p * ORACLE_MAX_REL + rr] = b[rr];
             }
-            out[p] = composite(qs.sem[i], r, t);
+            out[p] = composite(qs.sem[i], r, t, qs.pred);
             if (out_sem) out_sem[p] = qs.sem[i];
         }
         query_free(&qs);
@@ -486,8 +593,9 @@ int farm_oracle_topk_bounded(int64_t n, int d, const float* desc, const float* c
         for (int64_t i = 0; i < n; ++i) {
             if (qs.sem[i] >= L) {
                 double t[ORACLE_MAX_REL];
-                for (int rr = 0; rr < r; ++rr) { uint32_t b; relation_term(&s, &qs, rr, i, &t[rr], &b); }
-                full[i] = composite(qs.sem[i], r, t);
+                uint32_t b[ORACLE_MAX_REL];
+                query_terms(&s, &qs, i, t, b);
+                full[i] = composite(qs.sem[i], r, t, qs.pred);
                 ++cnt;
             } else {
                 full[i] = -INFINITY; /* provably outside the TopK */
@@ -498,12 +606,13 @@ int farm_oracle_topk_bounded(int64_t n, int d, const float* desc, const float* c
         for (int32_t rr = 0; rr < k; ++rr) {
             out_idx[(size_t)qq * k + rr] = sel[rr];
             out_score[(size_t)qq * k + rr] = sel[rr] >= 0 ? full[sel[rr]] : -INFINITY;
+            double tv[ORACLE_MAX_REL];
+            uint32_t bv[ORACLE_MAX_REL];
+            for (int e = 0; e < ORACLE_MAX_REL; ++e) { tv[e] = 0.0; bv[e] = ORACLE_NO_ID; }
+            if (sel[rr] >= 0) query_terms(&s, &qs, sel[rr], tv, bv);
             for (int e = 0; e < ORACLE_MAX_REL; ++e) {
-                double tv = 0.0;
-                uint32_t b = ORACLE_NO_ID;
-                if (sel[rr] >= 0 && e < r) relation_term(&s, &qs, e, sel[rr], &tv, &b);
-                if (out_terms) out_terms[((size_t)qq * k + rr) * ORACLE_MAX_REL + e] = tv;
-                if (out_anchor_id) out_anchor_id[((size_t)qq * k + rr) * ORACLE_MAX_REL + e] = b;
+                if (out_terms) out_terms[((size_t)qq * k + rr) * ORACLE_MAX_REL + e] = tv[e];
+                if (out_anchor_id) out_anchor_id[((size_t)qq * k + rr) * ORACLE_MAX_REL + e] = bv[e];
             }
         }
         free(full); free(lower); free(sel);
@@ -550,6 +659,27 @@ double farm_oracle_binding_value(int64_t n, int d, const float* desc, const floa
     free(u);
     free(v);
     return val;
+}
+
+/* Value of one Between binding: sim(j1, v1) sim(j2, v2) Between(i; j1, j2). */
+double farm_oracle_between_binding_value(int64_t n, int d, const float* desc, const float* center,
+                                         const float* anchor1, const float* anchor2, int64_t i, int64_t j1,
+                                         int64_t j2) {
+    if (i < 0 || j1 < 0 || j2 < 0 || i >= n || j1 >= n || j2 >= n) return NAN;
+    double* u = (double*)malloc(sizeof(double) * (size_t)d);
+    double* v = (double*)malloc(sizeof(double) * (size_t)d);
+    if (!u || !v) { free(u); free(v); return NAN; }
+    unit_vector(desc + (size_t)j1 * d, d, u);
+    unit_vector(anchor1, d, v);
+    double a1 = clamped_cosine(u, v, d);
+    unit_vector(desc + (size_t)j2 * d, d, u);
+    unit_vector(anchor2, d, v);
+    double a2 = clamped_cosine(u, v, d);
+    free(u);
+    free(v);
+    double ci[3], c1[3], c2[3];
+    for (int k = 0; k < 3; ++k) { ci[k] = center[i * 3 + k]; c1[k] = center[j1 * 3 + k]; c2[k] = center[j2 * 3 + k]; }
+    return a1 * a2 * between_value(ci, c1, c2);
 }
 
 /* ------------------------------------------------------------------------

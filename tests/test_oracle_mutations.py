@@ -38,10 +38,13 @@ MUTATIONS = [
     ("anchor tie-break by larger id", "(v == best && s->id[j] < best_id)", "(v == best && s->id[j] > best_id)"),
     ("rank tie-break by larger id", "(dc == dij && s->id[c] < s->id[i])", "(dc == dij && s->id[c] > s->id[i])"),
     ("farthest target rank off by one", "p == P_CLOSEST ? 1 : m + 1;", "p == P_CLOSEST ? 1 : m;"),
-    ("geometric mean without the root", "gbar = pow(prod, 1.0 / (double)r);", "gbar = prod;"),
+    ("geometric mean without the root", "gbar = pow(prod, 1.0 / (double)cnt);", "gbar = prod;"),
     ("blend floor dropped", "return sem * ((1.0 - ORACLE_W) + ORACLE_W * gbar);", "return sem * (ORACLE_W * gbar);"),
     ("topk tie-break by larger id", "return (id[a] < id[b]) ? -1 : (id[a] > id[b]);",
      "return (id[a] > id[b]) ? -1 : (id[a] < id[b]);"),
+    ("between drops the far-side margin", "return logistic(s / ORACLE_TAU) * logistic((L - s) / ORACLE_TAU) *",
+     "return logistic(s / ORACLE_TAU) *"),
+    ("between's invocation counted twice in the mean", "        if (pred[rr] == P_AND) continue;\n", ""),
     ("gelu derivative drops its second term",
      "return 0.5 * (1.0 + erf(v / sqrt(2.0))) + v * exp(-0.5 * v * v) / sqrt(2.0 * M_PI);",
      "return 0.5 * (1.0 + erf(v / sqrt(2.0)));"),

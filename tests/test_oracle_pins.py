@@ -550,3 +550,99 @@ def test_bounded_topk_equals_full_topk(small_world):
     osel = np.tile(np.arange(0, scene.n, scene.n // 5)[:5], qb.q).astype(np.int64)
     ps, psem, pt, pb = oracle.score_pairs(scene, qb, qsel, osel)
     np.testing.assert_allclose(ps, s[qsel, osel], rtol=1e-15)
+
+
+# ---------------------------------------------------------------- Between (ternary)
+BETWEEN, AND = 12, 13
+
+
+def test_between_closed_forms():
+    """Between(i; j1, j2) = sig(s/0.1) sig((L-s)/0.1) exp(-h^2/(2*0.5^2)): the
+    midpoint, an endpoint, a perpendicular offset, beyond an anchor,
+    coincident anchors; symmetric in the anchors, invariant to rigid motions."""
+    sig = lambda u: 1 / (1 + math.exp(-u))
+    a1, a2 = np.array([0, 0, 0], np.float32), np.array([2, 0, 0], np.float32)
+    assert oracle.between([1, 0, 0], a1, a2) == pytest.approx(sig(10) ** 2, rel=1e-14)
+    assert oracle.between([0, 0, 0], a1, a2) == pytest.approx(0.5 * sig(20), rel=1e-14)
+    assert oracle.between([1, 0.5, 0], a1, a2) == pytest.approx(sig(10) ** 2 * math.exp(-0.5), rel=1e-14)
+    assert oracle.between([2.5, 0, 0], a1, a2) == pytest.approx(sig(25) * sig(-5), rel=1e-14)
+    assert oracle.between([1, 0, 0], a1, a1) == 0.0
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        ci, c1, c2 = (rng.uniform(-3, 3, 3).astype(np.float32) for _ in range(3))
+        v = oracle.between(ci, c1, c2)
+        assert 0.0 <= v <= 1.0
+        assert oracle.between(ci, c2, c1) == pytest.approx(v, rel=1e-12, abs=1e-300)
+        # a rotation about z by 90 degrees and a translation
+        rot = lambda c: np.array([-c[1], c[0], c[2]], np.float64) + np.array([5.0, -2.0, 1.0])
+        assert oracle.between(rot(ci), rot(c1), rot(c2)) == pytest.approx(v, rel=1e-5, abs=1e-12)
+
+
+def _between_scene():
+    """A target at the origin, chairs A (id 5) at x = -1 m and B (id 3) at
+    x = +1 m, a third chair C (id 9) off the axis; the anchor descriptions both
+    match every chair equally."""
+    d = 4
+    e = np.eye(d, dtype=np.float32)
+    center = np.array([[0, 0, 0], [-1, 0, 0], [1, 0, 0], [0, 3, 0]], np.float32)
+    scene = Scene(desc=np.stack([e[0], e[1], e[1], e[1]]), center=center, extent=np.full((4, 3), 0.5, np.float32),
+                  ids=np.array([1, 5, 3, 9], np.uint32), cls=np.array([0, 1, 1, 1], np.int32),
+                  view_right=np.array([1, 0], np.float32), centroids=np.zeros((1, d), np.float32))
+    qb = QueryBatch(target=e[0][None], target_cls=np.array([-1], np.int32), rel_off=np.array([0, 2], np.int32),
+                    rel_pred=np.array([BETWEEN, AND], np.int32), rel_anchor=np.stack([e[1], e[1]]),
+                    planted=np.zeros(1, np.int64))
+    return scene, qb
+
+
+def test_between_term_binding_and_ties():
+    """The target between A and B: t = Between(o; A, B) with sim = 1 for both;
+    (A, B) and (B, A) tie, so the binding is the smaller id pair (3, 5); both
+    slots report the term, and it counts once in the geometric mean."""
+    scene, qb = _between_scene()
+    s, sem, t, b = oracle.score(scene, qb, terms=True)
+    sig = lambda u: 1 / (1 + math.exp(-u))
+    want = sig(10) ** 2
+    assert t[0, 0] == pytest.approx(want, rel=1e-14) and t[1, 0] == t[0, 0]
+    assert (int(b[0, 0]), int(b[1, 0])) == (3, 5)
+    assert s[0, 0] == pytest.approx(1.0 * (0.5 + 0.5 * want), rel=1e-14)  # one invocation, not two
+    # no pair of distinct anchors other than the target in a two-object memory
+    two = Scene(desc=scene.desc[:2], center=scene.center[:2], extent=scene.extent[:2], ids=scene.ids[:2],
+                cls=scene.cls[:2], view_right=scene.view_right, centroids=scene.centroids)
+    s2, _, t2, b2 = oracle.score(two, qb, terms=True)
+    assert np.all(t2 == 0) and np.all(b2 == 0xFFFFFFFF)
+
+
+def test_between_must_pair_with_its_second_anchor():
+    scene, qb = _between_scene()
+    for preds in ([BETWEEN, 0], [AND, BETWEEN], [0, AND]):
+        bad = QueryBatch(target=qb.target, target_cls=qb.target_cls, rel_off=qb.rel_off,
+                         rel_pred=np.array(preds, np.int32), rel_anchor=qb.rel_anchor, planted=qb.planted)
+        with pytest.raises(ValueError):
+            oracle.score(scene, bad)
+
+
+def _with_between(scene, qb, rng):
+    """Each query gets one Between invocation (two slots) after its relations."""
+    offs, preds, anchors = [0], [], []
+    d = scene.desc.shape[1]
+    for k in range(qb.target.shape[0]):
+        a, b = int(qb.rel_off[k]), int(qb.rel_off[k + 1])
+        preds += list(qb.rel_pred[a:b]) + [BETWEEN, AND]
+        anchors += list(qb.rel_anchor[a:b]) + [rng.standard_normal(d).astype(np.float32) for _ in range(2)]
+        offs.append(len(preds))
+    return QueryBatch(target=qb.target, target_cls=qb.target_cls, rel_off=np.asarray(offs, np.int32),
+                      rel_pred=np.asarray(preds, np.int32), rel_anchor=np.asarray(anchors, np.float32),
+                      planted=qb.planted)
+
+
+@pytest.mark.parametrize("n,r", [(2, 0), (3, 0), (4, 1), (6, 1), (7, 0)])
+def test_between_star_decomposition_equals_joint_enumeration(n, r):
+    """Bucket elimination of the Between factor (its two anchor variables
+    maximised together, per target) equals the joint enumeration of every
+    anchor variable."""
+    for seed in range(3):
+        scene, qb = _tiny(seed * 13 + n * 3 + r, n, r, npred=len(EVERY_PRED))
+        qb = _with_between(scene, qb, np.random.default_rng(seed))
+        s = oracle.score(scene, qb)
+        bs = np.asarray(brute_scores(scene, qb))
+        np.testing.assert_allclose(s, bs, rtol=1e-12, atol=1e-14)
