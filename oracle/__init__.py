@@ -70,6 +70,8 @@ def _load():
         lib.farm_oracle_between.argtypes = [P, P, P]
         lib.farm_oracle_between_binding_value.restype = ctypes.c_double
         lib.farm_oracle_between_binding_value.argtypes = [i64, ctypes.c_int, P, P, P, P, i64, i64, i64]
+        lib.farm_oracle_set_between_tolerance.restype = None
+        lib.farm_oracle_set_between_tolerance.argtypes = [ctypes.c_int, ctypes.c_double]
         lib.farm_oracle_set_rank_tolerance.restype = None
         lib.farm_oracle_set_rank_tolerance.argtypes = [ctypes.c_int, ctypes.c_double]
         lib.farm_oracle_topk_bounded.restype = ctypes.c_int
@@ -107,6 +109,28 @@ class rank_tolerance:
     def __exit__(self, *exc):
         _load().farm_oracle_set_rank_tolerance(0, 0.0)
         return False
+
+
+class between_tolerance:
+    """Context manager: within it Between's candidate sets keep only the
+    anchors surely among the 64 of largest similarity (mode -1: more than
+    ``eps`` above the 64th largest) or add every anchor within ``eps`` of it
+    (mode +1), the lowest and highest terms an implementation whose
+    similarities are within eps of the oracle's can return."""
+
+    def __init__(self, mode: int, eps: float):
+        self.mode, self.eps = int(mode), float(eps)
+
+    def __enter__(self):
+        _load().farm_oracle_set_between_tolerance(self.mode, self.eps)
+        return self
+
+    def __exit__(self, *exc):
+        _load().farm_oracle_set_between_tolerance(0, 0.0)
+        return False
+
+
+BETWEEN_K = 64
 
 
 def set_threads(n: int):

@@ -24,6 +24,7 @@ import numpy as np
 
 W = 0.5
 CLASS_FACTOR = 0.3
+BETWEEN_K = 64
 
 
 def _unit(v):
@@ -36,6 +37,9 @@ def _sim(u, v):
 
 
 def _sigmoid(x):
+    if x < 0:  # the same value without overflowing exp(-x)
+        e = math.exp(x)
+        return e / (1.0 + e)
     return 1.0 / (1.0 + math.exp(-x))
 
 
@@ -145,16 +149,26 @@ def brute_scores(scene, qb):
             if not others:
                 best = s_sem * (1 - W)
             # predicate invocations: a Between (12) takes its slot's and the next
-            # slot's (13) anchor variables together and counts once
+            # slot's (13) anchor variables together and counts once; those two
+            # variables range over their candidate sets (the 64 anchors of
+            # largest similarity, ties by smaller id)
             n_inv = sum(1 for pred, _ in rels if pred != 13)
-            for binding in itertools.product(others, repeat=len(rels)):
+            domains = []
+            for pred, qr in rels:
+                if pred in (12, 13):
+                    order = sorted(range(n), key=lambda j: (-_sim(units[j], qr), int(scene.ids[j])))
+                    cand = set(order[:BETWEEN_K])
+                    domains.append([j for j in others if j in cand])
+                else:
+                    domains.append(others)
+            for binding in itertools.product(*domains):
                 prod = 1.0
                 for k, ((pred, qr), j) in enumerate(zip(rels, binding)):
                     if pred == 13:
                         continue
                     if pred == 12:
                         j2 = binding[k + 1]
-                        pv = between_relation(scene.center[e], scene.center[j], scene.center[j2])
+                        pv = 0.0 if j2 == j else between_relation(scene.center[e], scene.center[j], scene.center[j2])
                         prod *= _sim(units[j], qr) * _sim(units[j2], rels[k + 1][1]) * pv
                         continue
                     if pred in (9, 10):

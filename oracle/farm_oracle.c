@@ -40,7 +40,8 @@
  *   BETWEEN  (ternary, two anchors j1, j2; see between_value) = sig(s / 0.1)
  *              sig((L - s) / 0.1) exp(-h^2 / (2 * 0.5^2)): s the offset of i's
  *              center along the axis from j1 to j2, L = |c_j2 - c_j1|, h its
- *              distance from that axis; 0 when L = 0
+ *              distance from that axis; 0 when L = 0.  Its anchors range over
+ *              candidate sets of 64 (see between_set)
  * where (r_x, r_y) is the scene viewer's right vector, f = (-r_y, r_x) its
  * viewing direction and e the full box extents.  The temperatures
  * (0.1 m), the Gaussian's normalisation, the clamp at zero, the viewer
@@ -320,19 +321,70 @@ static double rank_value(const scene64* s, int32_t tcls, int p, int64_t i, int64
     return 1.0 / (double)(off + 1);
 }
 
-/* Between's term: max over anchor pairs j1 != j2, both != i, of
- * sim(j1, q_rr) sim(j2, q_rr+1) Between(i; j1, j2) (the two relation slots
- * rr, rr + 1 hold the two anchor descriptions); ties by the smaller
- * (id(j1), id(j2)); no binding (NO_ID) when the term is 0. */
+/* Between's candidate sets.  Bucket elimination of a factor over two anchor
+ * variables costs K^2 per target for candidate sets of K anchors (Appendix
+ * "Robust Relational Retrieval Formulation", query-time complexity: the cost
+ * grows with the candidate-set size); reading: each of Between's anchor
+ * variables ranges over the ORACLE_BETWEEN_K anchors of largest similarity to
+ * its description (ties by the smaller id) -- the paper's per-anchor
+ * candidate sets K_a -- where the binary relations take every anchor.
+ * set[k] = object indices, returns the set's size (min(K, n)).
+ * Tie-aware mode (a check of another implementation's similarity rounding,
+ * see farm_oracle_set_between_tolerance): mode -1 keeps only the members
+ * whose similarity exceeds the K-th largest by more than eps (surely in any
+ * set computed within eps), mode +1 adds every anchor within eps of it. */
+#define ORACLE_BETWEEN_K 64
+static int g_btw_mode = 0;
+static double g_btw_eps = 0.0;
+
+void farm_oracle_set_between_tolerance(int mode, double eps) {
+    g_btw_mode = mode < 0 ? -1 : (mode > 0 ? 1 : 0);
+    g_btw_eps = eps > 0.0 ? eps : 0.0;
+}
+
+static int64_t between_set(const scene64* s, const double* a, int64_t* set) {
+    int64_t k = s->n < ORACLE_BETWEEN_K ? s->n : ORACLE_BETWEEN_K;
+    unsigned char* taken = (unsigned char*)calloc((size_t)(s->n > 0 ? s->n : 1), 1);
+    if (!taken) return 0;
+    double kth = 0.0;
+    for (int64_t r = 0; r < k; ++r) {  /* selection by repeated scans */
+        int64_t best = -1;
+        for (int64_t j = 0; j < s->n; ++j) {
+            if (taken[j]) continue;
+            if (best < 0 || a[j] > a[best] || (a[j] == a[best] && s->id[j] < s->id[best])) best = j;
+        }
+        taken[best] = 1;
+        kth = a[best];
+    }
+    int64_t m = 0;
+    for (int64_t j = 0; j < s->n; ++j) {
+        int in = taken[j];
+        if (g_btw_mode < 0 && in && !(a[j] > kth + g_btw_eps)) in = k == s->n;  /* all anchors: surely in */
+        if (g_btw_mode > 0 && !in && a[j] >= kth - g_btw_eps) in = 1;
+        if (in) set[m++] = j;
+    }
+    free(taken);
+    return m;
+}
+
+/* Between's term: max over j1 in the first set, j2 in the second, j1 != j2,
+ * both != i, of sim(j1, q_rr) sim(j2, q_rr+1) Between(i; j1, j2) (the two
+ * relation slots rr, rr + 1 hold the two anchor descriptions); ties by the
+ * smaller (id(j1), id(j2)); no binding (NO_ID) when the term is 0. */
 static void between_term(const scene64* s, const query64* qs, int rr, int64_t i, double* t, uint32_t* b1,
                          uint32_t* b2) {
     const double* a1 = qs->asim + (size_t)rr * s->n;
     const double* a2 = qs->asim + (size_t)(rr + 1) * s->n;
+    int64_t* set1 = (int64_t*)malloc(sizeof(int64_t) * (size_t)(s->n > 0 ? s->n : 1));
+    int64_t* set2 = (int64_t*)malloc(sizeof(int64_t) * (size_t)(s->n > 0 ? s->n : 1));
     double best = 0.0;
     uint32_t id1 = ORACLE_NO_ID, id2 = ORACLE_NO_ID;
-    for (int64_t j1 = 0; j1 < s->n; ++j1) {
-        if (j1 == i || a1[j1] == 0.0) continue;
-        for (int64_t j2 = 0; j2 < s->n; ++j2) {
+    int64_t m1 = set1 ? between_set(s, a1, set1) : 0, m2 = set2 ? between_set(s, a2, set2) : 0;
+    for (int64_t u = 0; u < m1; ++u) {
+        const int64_t j1 = set1[u];
+        if (j1 == i) continue;
+        for (int64_t w = 0; w < m2; ++w) {
+            const int64_t j2 = set2[w];
             if (j2 == i || j2 == j1) continue;
             double v = a1[j1] * a2[j2] * between_value(s->c + i * 3, s->c + j1 * 3, s->c + j2 * 3);
             if (v <= 0.0) continue;
@@ -343,6 +395,8 @@ static void between_term(const scene64* s, const query64* qs, int rr, int64_t i,
             }
         }
     }
+    free(set1);
+    free(set2);
     *t = best;
     *b1 = id1;
     if (b2) *b2 = id2;

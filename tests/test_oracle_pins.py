@@ -646,3 +646,67 @@ def test_between_star_decomposition_equals_joint_enumeration(n, r):
         s = oracle.score(scene, qb)
         bs = np.asarray(brute_scores(scene, qb))
         np.testing.assert_allclose(s, bs, rtol=1e-12, atol=1e-14)
+
+
+def test_between_candidate_sets_of_64():
+    """With more than 64 objects, Between's anchors range over the 64 of
+    largest similarity per description: the oracle equals the joint
+    enumeration over those sets (oracle/brute.py), and on this scene the
+    restriction changes some terms (a better pair uses an anchor ranked below
+    64).  The tie-aware modes bracket the exact term."""
+    rng = np.random.default_rng(77)
+    n, d = 150, 3
+    desc = rng.standard_normal((n, d)).astype(np.float32)
+    anchors = rng.standard_normal((4, d)).astype(np.float32)
+    center = rng.uniform(0, 4, (n, 3)).astype(np.float32)
+    # a target of query 0 sits between two anchors ranked just below 64 in similarity,
+    # far from every other object: only the unrestricted maximum finds that pair
+    un = desc.astype(np.float64) / np.linalg.norm(desc.astype(np.float64), axis=1, keepdims=True)
+    ranked = [np.argsort(-(un @ (v / np.linalg.norm(v)))) for v in anchors[:2].astype(np.float64)]
+    j1 = int(ranked[0][66])
+    j2 = next(int(j) for j in ranked[1][66:] if int(j) != j1)
+    o = next(i for i in range(n) if i not in (j1, j2))
+    center[o] = (50, 50, 50)
+    center[j1] = (49, 50, 50)
+    center[j2] = (51, 50, 50)
+    scene = Scene(desc=desc, center=center,
+                  extent=np.full((n, 3), 0.3, np.float32), ids=(rng.permutation(400)[:n] + 1).astype(np.uint32),
+                  cls=np.zeros(n, np.int32), view_right=np.array([1, 0], np.float32),
+                  centroids=np.zeros((1, d), np.float32))
+    qb = QueryBatch(target=rng.standard_normal((2, d)).astype(np.float32), target_cls=np.array([-1, -1], np.int32),
+                    rel_off=np.array([0, 2, 4], np.int32), rel_pred=np.array([BETWEEN, AND] * 2, np.int32),
+                    rel_anchor=anchors, planted=np.zeros(2, np.int64))
+    sub = QueryBatch(target=qb.target[:1], target_cls=qb.target_cls[:1], rel_off=qb.rel_off[:2],
+                     rel_pred=qb.rel_pred[:2], rel_anchor=qb.rel_anchor[:2], planted=qb.planted[:1])
+    small = Scene(desc=desc[:70], center=scene.center[:70], extent=scene.extent[:70], ids=scene.ids[:70],
+                  cls=scene.cls[:70], view_right=scene.view_right, centroids=scene.centroids)
+    np.testing.assert_allclose(oracle.score(small, sub), np.asarray(brute_scores(small, sub)), rtol=1e-12, atol=1e-14)
+    # unrestricted maximum over every pair (numpy, vectorised), for comparison
+    c = scene.center.astype(np.float64)
+    u = desc.astype(np.float64) / np.linalg.norm(desc.astype(np.float64), axis=1, keepdims=True)
+    _, _, t, _ = oracle.score(scene, qb, terms=True)
+    sig = lambda v: 1 / (1 + np.exp(-v))
+    differs = 0
+    for k in range(2):
+        a = [np.maximum(0, u @ (v / np.linalg.norm(v))) for v in qb.rel_anchor[2 * k:2 * k + 2].astype(np.float64)]
+        ax = c[:, None, :] - c[None, :, :]           # c_j2 - c_j1 as [j2, j1]
+        L = np.linalg.norm(ax, axis=2)
+        for i in sorted(set(range(0, n, 3)) | {o}):
+            w = c[i][None, :] - c                    # c_i - c_j1 as [j1]
+            with np.errstate(divide="ignore", invalid="ignore"):
+                s_ = np.einsum("bak,ak->ba", ax, w) / L   # along the axis from j1, [j2, j1]
+                h2 = np.sum(w * w, axis=1)[None, :] - s_ * s_
+                B = sig(s_ / 0.1) * sig((L - s_) / 0.1) * np.exp(-np.maximum(h2, 0) / 0.5)
+            B[L == 0] = 0
+            val = a[1][:, None] * a[0][None, :] * B
+            val[i, :] = 0
+            val[:, i] = 0
+            full = float(np.nanmax(val))
+            assert full >= t[2 * k, i] * (1 - 1e-9) - 1e-300
+            differs += full > t[2 * k, i] * (1 + 1e-9)
+    assert differs > 0
+    with oracle.between_tolerance(-1, 0.05):
+        _, _, t_lo, _ = oracle.score(scene, qb, terms=True)
+    with oracle.between_tolerance(+1, 0.05):
+        _, _, t_hi, _ = oracle.score(scene, qb, terms=True)
+    assert np.all(t_lo <= t + 1e-15) and np.all(t <= t_hi + 1e-15) and np.any(t_hi > t)
