@@ -47,6 +47,23 @@
  *   FARM_INSIDE      prod_k sig((e_j,k / 2 - |D_k|) / 0.1): the target's center
  *                    within the anchor's box (e = full extents), a soft
  *                    containment test
+ *   FARM_BETWEEN     ternary, anchors j1 and j2 (a FARM_BETWEEN relation slot
+ *                    holds j1's description and must be followed by a
+ *                    FARM_AND slot holding j2's; the pair is one predicate
+ *                    invocation, counted once in the geometric mean):
+ *                    sig(s / 0.1) sig((L - s) / 0.1) exp(-h^2 / (2 * 0.5^2)),
+ *                    L = |c_j2 - c_j1|, s the offset of c_i along the axis
+ *                    from c_j1 to c_j2, h the distance of c_i from that axis
+ *                    (0 when L = 0): the target's center projects inside the
+ *                    segment joining the anchors and lies near it.  Term
+ *                    max over j1 != j2 (both != i) of sim(j1, q_j1)
+ *                    sim(j2, q_j2) Between; both slots report it, the first
+ *                    binds j1 and the second j2 (smaller id pair on ties;
+ *                    FARM_NO_ID when the term is 0).  Exact by bucket
+ *                    elimination of the two anchor variables per target: the
+ *                    pairs of the two relations' semantic sets first, then,
+ *                    unless they certify the term, every pair whose bound
+ *                    reaches the best value
  *
  * Conventions shared by every entry point:
  *   - Every function returns a farm_status; farm_last_error() gives a message
@@ -100,9 +117,11 @@ typedef enum {
   FARM_ON = 8,
   FARM_CLOSEST = 9,
   FARM_FARTHEST = 10,
-  FARM_INSIDE = 11
+  FARM_INSIDE = 11,
+  FARM_BETWEEN = 12,
+  FARM_AND = 13           /* the second anchor of the FARM_BETWEEN slot before it */
 } farm_pred;
-#define FARM_NUM_PRED 12        /* predicate ids 0 .. FARM_NUM_PRED - 1 */
+#define FARM_NUM_PRED 14        /* predicate ids 0 .. FARM_NUM_PRED - 1 */
 #define FARM_NUM_PROP_PRED 9    /* predicates with learned anchor lists (network outputs): 0 .. 8 */
 
 #define FARM_MAX_REL 8          /* relations per query */
@@ -166,13 +185,26 @@ FARM_API farm_status farm_workspace_estimate(const farm_memory* mem, int32_t max
                                     size_t* bytes);
 
 /*
- * Score every (query, object) pair exhaustively (the plain method).
+ * Score every (query, object) pair exhaustively (the plain method): for each
+ * target candidate o, the score of its best witnessing binding (Section
+ * "Robust Relational Object Retrieval", the score and TopK definition; the
+ * same definition in Appendix "Robust Relational Retrieval Formulation",
+ * "Soft verification").  Conditioning on o separates the anchors of a star
+ * query ("Query-time complexity" paragraph), so each relation r contributes
+ * its own best anchor:
+ *   s_sem(o) = kappa_o * max(0, cos(target, u_o))   (kappa_o the class factor)
+ *   t_r(o)   = max over a != o of max(0, cos(anchor_r, u_a)) * P_r(o, a)
+ *   s(o)     = s_sem(o) * (1/2 + 1/2 * geometric mean of the t_r(o))
+ * with Between's two anchors bound jointly over their candidate sets.  The
+ * per-predicate P are the closed-form evaluators of Appendix "Retrieval
+ * Details", step 4; the blend and the class factor are its step 5.
  *   q, d         number of queries; d must equal the memory's d
  *   target       device [q][d] FP32 target embeddings (any non-zero norm)
  *   target_cls   host [q] int32 parsed target classes (-1 = none) or NULL
  *   rel_off      host [q+1] int32 CSR offsets, rel_off[0] = 0, non-decreasing,
  *                at most FARM_MAX_REL relations per query
- *   rel_pred     host [rel_off[q]] int32 farm_pred values
+ *   rel_pred     host [rel_off[q]] int32 farm_pred values (FARM_BETWEEN is
+ *                followed by FARM_AND in the same query, and only there)
  *   rel_anchor   device [rel_off[q]][d] FP32 anchor embeddings
  *   scores       device [q][n] FP32 out: s(i)
  *   rel_terms    device [rel_off[q]][n] FP32 out: t_r(i), or NULL
@@ -188,7 +220,10 @@ FARM_API farm_status farm_score_query(const farm_memory* mem, farm_workspace* ws
                              float* rel_terms, uint32_t* rel_anchor_id, void* stream);
 
 /*
- * TopK of precomputed score rows.
+ * TopK of precomputed score rows: the K highest-scoring candidates, the
+ * retrieval output (Section "Robust Relational Object Retrieval", the TopK
+ * over the entity set; the ranked candidate list of Appendix "Retrieval
+ * Details", step 7).
  *   scores       device [q][n] FP32 (n = the memory's n; NaN not allowed)
  *   k            1 <= k <= FARM_MAX_K; k > n returns n entries, then padding
  *   out_id       device [q][k] uint32 ids (FARM_NO_ID padding)

@@ -17,12 +17,12 @@ from . import _lib
 from ._lib import (FARM_BUILD_BF16, FARM_BUILD_FP8, FARM_MAX_K, FARM_MAX_REL, FARM_NO_ID, F32, BF16, FP8_E4M3,
                    EXHAUSTIVE, BOUNDED, PROPOSAL, OPT_GLOBAL_PROPOSAL_PASS,
                    NEAR, ABOVE, BELOW, LEFT_OF, RIGHT_OF, NEXT_TO, IN_FRONT_OF, BEHIND, ON, CLOSEST,
-                   FARTHEST, INSIDE, NUM_PRED, NUM_PROP_PRED, FarmError, lib_path)
+                   FARTHEST, INSIDE, BETWEEN, AND, NUM_PRED, NUM_PROP_PRED, FarmError, lib_path)
 
 __all__ = [
     "Memory", "Workspace", "ProposalNet", "Server", "build_proposals", "build_proposals_by_value", "get_proposals", "score_query", "topk", "query_topk", "query_topk_static", "workspace_estimate", "FarmError",
     "FARM_BUILD_BF16", "FARM_BUILD_FP8", "FARM_MAX_K", "FARM_MAX_REL", "FARM_NO_ID", "F32", "BF16",
-    "FP8_E4M3", "EXHAUSTIVE", "BOUNDED", "PROPOSAL", "OPT_GLOBAL_PROPOSAL_PASS", "NEAR", "ABOVE", "BELOW", "LEFT_OF", "RIGHT_OF", "NEXT_TO", "IN_FRONT_OF", "BEHIND", "ON", "CLOSEST", "FARTHEST", "INSIDE", "NUM_PRED",
+    "FP8_E4M3", "EXHAUSTIVE", "BOUNDED", "PROPOSAL", "OPT_GLOBAL_PROPOSAL_PASS", "NEAR", "ABOVE", "BELOW", "LEFT_OF", "RIGHT_OF", "NEXT_TO", "IN_FRONT_OF", "BEHIND", "ON", "CLOSEST", "FARTHEST", "INSIDE", "BETWEEN", "AND", "NUM_PRED",
     "NUM_PROP_PRED", "lib_path",
 ]
 

@@ -15,7 +15,8 @@ OPT_GLOBAL_PROPOSAL_PASS = 1
 NEAR, ABOVE, BELOW, LEFT_OF, RIGHT_OF = 0, 1, 2, 3, 4
 NEXT_TO, IN_FRONT_OF, BEHIND, ON = 5, 6, 7, 8
 CLOSEST, FARTHEST, INSIDE = 9, 10, 11
-NUM_PRED, NUM_PROP_PRED = 12, 9  # predicate ids; those with learned anchor lists
+BETWEEN, AND = 12, 13  # ternary Between's slot and the slot of its second anchor
+NUM_PRED, NUM_PROP_PRED = 14, 9  # predicate ids; those with learned anchor lists
 FARM_MAX_REL = 8
 FARM_MAX_K = 1024
 FARM_NO_ID = 0xFFFFFFFF

@@ -133,6 +133,9 @@ farm_status layout_workspace(farm_workspace* ws, const farm_memory* mem, int32_t
   FARM_TRY(alloc(&ws->sem_cnt, rel1, "semantic set sizes"));
   FARM_TRY(alloc(&ws->sem_tau, rel1, "semantic bounds"));
   FARM_TRY(alloc(&ws->sem_sim, rel1 * kSemMax, "semantic similarities"));
+  FARM_TRY(alloc(&ws->btw_idx, rel1 * kBetweenSetSize, "Between candidate sets"));
+  FARM_TRY(alloc(&ws->btw_sim, rel1 * kBetweenSetSize, "Between candidate similarities"));
+  FARM_TRY(alloc(&ws->btw_cnt, rel1, "Between candidate counts"));
   FARM_TRY(alloc(&ws->prop_stats, 4, "proposal counters"));
   ws->fb_cap = fallback_cap(max_q);
   FARM_TRY(alloc(&ws->fb_list, (size_t)ws->fb_cap, "fallback worklist"));
@@ -177,8 +180,26 @@ farm_status check_queries(const farm_memory* mem, const farm_workspace* ws, int3
       set_error("relation %d has predicate id %d", r, rel_pred[r]);
       return FARM_ERR_INVALID_ARG;
     }
+  // a Between slot is followed by its second anchor's FARM_AND slot in the same query, and only there
+  for (int32_t k = 0; k < q; ++k)
+    for (int32_t r = rel_off[k]; r < rel_off[k + 1]; ++r) {
+      if (rel_pred[r] == FARM_BETWEEN && (r + 1 >= rel_off[k + 1] || rel_pred[r + 1] != FARM_AND)) {
+        set_error("relation %d (FARM_BETWEEN) is not followed by FARM_AND in its query", r);
+        return FARM_ERR_INVALID_ARG;
+      }
+      if (rel_pred[r] == FARM_AND && (r == rel_off[k] || rel_pred[r - 1] != FARM_BETWEEN)) {
+        set_error("relation %d (FARM_AND) does not follow a FARM_BETWEEN of its query", r);
+        return FARM_ERR_INVALID_ARG;
+      }
+    }
   *r_tot = R;
   return FARM_OK;
+}
+
+bool has_between(const int32_t* rel_pred, int32_t R) {
+  for (int32_t r = 0; r < R; ++r)
+    if (rel_pred[r] == FARM_BETWEEN) return true;
+  return false;
 }
 
 // Phase timer: brackets a phase with events on the call's stream when enabled.
@@ -227,7 +248,9 @@ farm_status stage_meta(farm_workspace* ws, int32_t q, int32_t R, const int32_t* 
   int32_t* rk = h + 2 * q + 1 + 2 * R;  // rows of the scanned predicates (Closest, Farthest, Inside)
   int32_t nrank = 0;
   for (int32_t r = 0; r < R; ++r)
-    if (rel_pred[r] == FARM_CLOSEST || rel_pred[r] == FARM_FARTHEST || rel_pred[r] == FARM_INSIDE) rk[nrank++] = r;
+    if (rel_pred[r] == FARM_CLOSEST || rel_pred[r] == FARM_FARTHEST || rel_pred[r] == FARM_INSIDE ||
+        rel_pred[r] == FARM_BETWEEN)
+      rk[nrank++] = r;
   size_t len = (size_t)(2 * q + 1 + 2 * R + nrank);
   FARM_HIP(hipMemcpyAsync(ws->d_meta, h, len * sizeof(int32_t), hipMemcpyHostToDevice, s), "metadata copy");
   FARM_HIP(hipEventRecord(ws->meta_done, s), "metadata event");
@@ -251,7 +274,7 @@ float accumulation_bound(int32_t ldk) { return 2.02f * (float)ldk * 5.9604645e-8
 // candidate methods take logarithms of the few similarities they gather).
 farm_status similarities(const farm_memory* mem, farm_workspace* ws, int32_t q, int32_t R, const float* target,
                          const float* rel_anchor, const MetaView& meta, int32_t dtype, SimBound* bound,
-                         bool need_log, hipStream_t s) {
+                         bool need_log, bool between, hipStream_t s) {
   const int32_t ldk = mem->ldk;
   LowPrecRows lt, la;
   if (dtype == FARM_BF16) {
@@ -296,6 +319,13 @@ farm_status similarities(const farm_memory* mem, farm_workspace* ws, int32_t q, 
   }
   if (need_log)
     FARM_HIP(launch_log_rows(ws->sim + (int64_t)q * ws->ld_s, ws->ld_s, R, mem->n, ws->lsim, s), "log similarities");
+  if (between) {
+    // Between's rows exact in FP32 whatever the GEMM's dtype, then its candidate sets
+    if (dtype != FARM_F32)
+      FARM_HIP(launch_exact_rows(mem, ws->qn, ws->sim, ws->ld_s, q, meta, R, s), "Between exact rows");
+    FARM_HIP(launch_between_sets(mem, ws->sim, ws->ld_s, q, meta, R, ws->btw_idx, ws->btw_sim, ws->btw_cnt, s),
+             "Between candidate sets");
+  }
   return FARM_OK;
 }
 
@@ -305,6 +335,7 @@ farm_status similarities(const farm_memory* mem, farm_workspace* ws, int32_t q, 
 struct TopkPlan {
   int32_t dtype = FARM_F32, method = FARM_METHOD_EXHAUSTIVE, opt_flags = 0, c = 0;
   int32_t* certified = nullptr;
+  bool between = false;  // the batch has Between invocations
 };
 
 farm_status plan_topk(const farm_memory* mem, const farm_score_opts* opts, int32_t k, TopkPlan* plan) {
@@ -360,7 +391,8 @@ farm_status query_topk_core(const farm_memory* mem, farm_workspace* ws, int32_t 
   const int32_t dtype = plan.dtype, method = plan.method, opt_flags = plan.opt_flags, c = plan.c;
   int32_t* certified = plan.certified;
   SimBound bound;
-  FARM_TRY(similarities(mem, ws, q, R, target, rel_anchor, meta, dtype, &bound, method == FARM_METHOD_EXHAUSTIVE, s));
+  FARM_TRY(similarities(mem, ws, q, R, target, rel_anchor, meta, dtype, &bound, method == FARM_METHOD_EXHAUSTIVE,
+                        plan.between, s));
   if (method == FARM_METHOD_BOUNDED || method == FARM_METHOD_PROPOSAL) {
     {
       PhaseTimer t(ws, s, FARM_PHASE_TOPK);
@@ -421,7 +453,7 @@ farm_status query_topk_core(const farm_memory* mem, farm_workspace* ws, int32_t 
   }
   {
     PhaseTimer t(ws, s, FARM_PHASE_PAIR);
-    FARM_HIP(launch_pair_exhaustive(mem, ws->sim, ws->lsim, ws->ld_s, q, meta, bound, ws->scores, ws->ld_s, nullptr, nullptr,
+    FARM_HIP(launch_pair_exhaustive(mem, ws, ws->sim, ws->lsim, ws->ld_s, q, meta, bound, ws->scores, ws->ld_s, nullptr, nullptr,
                                     dtype == FARM_F32 ? nullptr : ws->scores_hi, s),
              "relational pass");
   }
@@ -437,7 +469,7 @@ farm_status query_topk_core(const farm_memory* mem, farm_workspace* ws, int32_t 
   }
   if (dtype == FARM_F32) {
     PhaseTimer t(ws, s, FARM_PHASE_EXPLAIN);
-    FARM_HIP(launch_explain(mem, ws->sim, ws->ld_s, q, meta, ws->rs_idx, k, out_terms, out_anchor_id, s), "explain");
+    FARM_HIP(launch_explain(mem, ws, ws->sim, ws->ld_s, q, meta, ws->rs_idx, k, out_terms, out_anchor_id, s), "explain");
     if (certified) FARM_HIP(launch_fill_i32(certified, q, 1, s), "certificate");
     return FARM_OK;
   }
@@ -522,7 +554,8 @@ farm_status stage_meta_args(farm_workspace* ws, int32_t q, int32_t R, const int3
     for (int32_t r = rel_off[k]; r < rel_off[k + 1]; ++r) push(k);
   int32_t nrank = 0;
   for (int32_t r = 0; r < R; ++r)
-    if (rel_pred[r] == FARM_CLOSEST || rel_pred[r] == FARM_FARTHEST || rel_pred[r] == FARM_INSIDE) {
+    if (rel_pred[r] == FARM_CLOSEST || rel_pred[r] == FARM_FARTHEST || rel_pred[r] == FARM_INSIDE ||
+        rel_pred[r] == FARM_BETWEEN) {
       push(r);
       ++nrank;
     }
@@ -842,7 +875,7 @@ farm_status farm_score_query(const farm_memory* mem, farm_workspace* ws, int32_t
                              const float* rel_anchor, float* scores, float* rel_terms, uint32_t* rel_anchor_id,
                              void* stream) {
   try {
-    int32_t R = 0;
+      int32_t R = 0;
     FARM_TRY(check_queries(mem, ws, q, d, target, rel_off, rel_pred, rel_anchor, &R));
     if (q > 0 && !scores) { set_error("scores is NULL"); return FARM_ERR_INVALID_ARG; }
     if (q == 0) return FARM_OK;
@@ -851,9 +884,9 @@ farm_status farm_score_query(const farm_memory* mem, farm_workspace* ws, int32_t
     MetaView meta;
     FARM_TRY(stage_meta(ws, q, R, target_cls, rel_off, rel_pred, s, &meta));
     SimBound none;
-    FARM_TRY(similarities(mem, ws, q, R, target, rel_anchor, meta, FARM_F32, &none, true, s));
+    FARM_TRY(similarities(mem, ws, q, R, target, rel_anchor, meta, FARM_F32, &none, true, has_between(rel_pred, R), s));
     PhaseTimer t(ws, s, FARM_PHASE_PAIR);
-    FARM_HIP(launch_pair_exhaustive(mem, ws->sim, ws->lsim, ws->ld_s, q, meta, none, scores, mem->n, rel_terms, rel_anchor_id,
+    FARM_HIP(launch_pair_exhaustive(mem, ws, ws->sim, ws->lsim, ws->ld_s, q, meta, none, scores, mem->n, rel_terms, rel_anchor_id,
                                     nullptr, s),
              "relational pass");
     return FARM_OK;
@@ -866,7 +899,7 @@ farm_status farm_score_query(const farm_memory* mem, farm_workspace* ws, int32_t
 farm_status farm_topk(const farm_memory* mem, farm_workspace* ws, const float* scores, int32_t q, int32_t k,
                       uint32_t* out_id, float* out_score, int32_t* out_index, void* stream) {
   try {
-    if (!mem || !ws || ws->mem != mem) { set_error("null or mismatched memory/workspace"); return FARM_ERR_INVALID_ARG; }
+      if (!mem || !ws || ws->mem != mem) { set_error("null or mismatched memory/workspace"); return FARM_ERR_INVALID_ARG; }
     if (q < 0 || q > ws->max_q) { set_error("q = %d outside [0, %d]", q, ws->max_q); return FARM_ERR_INVALID_ARG; }
     if (k < 1 || k > FARM_MAX_K) { set_error("k = %d outside [1, %d]", k, FARM_MAX_K); return FARM_ERR_INVALID_ARG; }
     if (q == 0) return FARM_OK;
@@ -891,11 +924,12 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
                             const float* rel_anchor, const farm_score_opts* opts, int32_t k, uint32_t* out_id,
                             float* out_score, float* out_terms, uint32_t* out_anchor_id, void* stream) {
   try {
-    int32_t R = 0;
+      int32_t R = 0;
     FARM_TRY(check_queries(mem, ws, q, d, target, rel_off, rel_pred, rel_anchor, &R));
     TopkPlan plan;
     FARM_TRY(plan_topk(mem, opts, k, &plan));
     if (q == 0) return FARM_OK;
+    plan.between = has_between(rel_pred, R);
     if (!out_id || !out_score) { set_error("null output pointer"); return FARM_ERR_INVALID_ARG; }
     if (plan.c > ws->max_k) {
       set_error("%s = %d exceeds the workspace's max_k %d", plan.c > k ? "rescore_mult * k" : "k", plan.c, ws->max_k);
@@ -928,6 +962,7 @@ farm_status farm_query_topk_static(const farm_memory* mem, int32_t q, int32_t d,
     TopkPlan plan;
     FARM_TRY(plan_topk(mem, opts, k, &plan));
     if (q == 0) return FARM_OK;
+    plan.between = has_between(rel_pred, R);
     if (!out_id || !out_score) { set_error("null output pointer"); return FARM_ERR_INVALID_ARG; }
     DeviceGuard g(mem->device);
     if (!g.ok) { set_error("cannot make device %d current", mem->device); return FARM_ERR_HIP; }

@@ -20,6 +20,7 @@ constexpr float kClassFactor = 0.3f;
 constexpr float kFp8Max = 448.0f;  // largest finite OCP e4m3 value
 constexpr int32_t kBoundCap = 2048;  // candidates per query kept by the bound-pruned TopK
 constexpr int32_t kSemMax = 64;      // semantic anchor set per relation in the proposal pass
+constexpr int32_t kBetweenSetSize = 64;  // candidate set of each of Between's anchor variables
 // Uncertified terms listed for the block-wide fallback scan (more are still
 // found and scanned by a sweep over the terms).
 inline int64_t fallback_cap(int32_t max_q) {
@@ -131,6 +132,9 @@ struct farm_workspace {
   int32_t* sem_cnt = nullptr;    // [max_rel]
   float* sem_tau = nullptr;      // [max_rel] largest similarity of an anchor outside the set
   float* sem_sim = nullptr;      // [max_rel][kSemMax] FP32 similarity of each set member (reduced precision)
+  int32_t* btw_idx = nullptr;    // [max_rel][64] Between's candidate sets (relation rows of Between invocations)
+  float* btw_sim = nullptr;      // [max_rel][64] their similarities
+  int32_t* btw_cnt = nullptr;    // [max_rel]
   unsigned long long* prop_stats = nullptr;  // [4] terms checked, fell back, FP32 dots (subset, fallback)
   unsigned long long* fb_list = nullptr;     // [fb_cap] terms the proposals could not certify: query << 32 | term
   uint32_t* fb_count = nullptr;              // [1]
@@ -240,6 +244,10 @@ struct PropView {
   int64_t fb_cap = 0;
   int32_t rel_total = 0;  // relation rows of the call (one LDS-staged block each)
   bool in_lds = false;    // run the proposal pass with the rows staged in LDS
+  // Between's candidate sets (scanned terms of Between invocations)
+  const int32_t* btw_idx = nullptr;
+  const float* btw_sim = nullptr;
+  const int32_t* btw_cnt = nullptr;
   // where the LDS-staged pass publishes the semantic sets it selects
   int32_t* sem_idx_out = nullptr;
   int32_t* sem_cnt_out = nullptr;
@@ -304,16 +312,26 @@ hipError_t launch_gemm_nt_bf16(const uint16_t* a, int64_t lda, const uint16_t* b
 // lsim[r][j] = log(sim[q + r][j]) of the relation rows (large negative for 0),
 // shared by the Near family of every relational kernel.
 hipError_t launch_log_rows(const float* sim, int64_t ld_s, int64_t rows, int64_t n, float* lsim, hipStream_t s);
-hipError_t launch_pair_exhaustive(const farm_memory* mem, const float* sim, const float* lsim, int64_t ld_s,
-                                  int32_t q, MetaView meta, const SimBound& bound, float* scores, int64_t ld_out,
-                                  float* rel_terms, uint32_t* rel_anchor_id, float* scores_hi, hipStream_t s);
+hipError_t launch_pair_exhaustive(const farm_memory* mem, const farm_workspace* ws, const float* sim,
+                                  const float* lsim, int64_t ld_s, int32_t q, MetaView meta, const SimBound& bound,
+                                  float* scores, int64_t ld_out, float* rel_terms, uint32_t* rel_anchor_id,
+                                  float* scores_hi, hipStream_t s);
 // ScoredCandidate breakdown for selected objects: t_r and b_r recomputed for
 // each (query, rank) entry of idx[q][k].
-hipError_t launch_explain(const farm_memory* mem, const float* sim, int64_t ld_s, int32_t q, MetaView meta,
-                          const int32_t* idx, int32_t k, float* out_terms, uint32_t* out_anchor_id,
+hipError_t launch_explain(const farm_memory* mem, const farm_workspace* ws, const float* sim, int64_t ld_s, int32_t q,
+                          MetaView meta, const int32_t* idx, int32_t k, float* out_terms, uint32_t* out_anchor_id,
                           hipStream_t s);
 
+// Between's candidate sets (scan_math.h): for every relation row of a Between
+// invocation (FARM_BETWEEN / FARM_AND) the 64 anchors of largest similarity
+// (ties by id) and their similarities into bidx/bsim [R][64], bcnt [R].
+hipError_t launch_between_sets(const farm_memory* mem, const float* sim, int64_t ld_s, int32_t q, MetaView meta,
+                               int32_t R, int32_t* bidx, float* bsim, int32_t* bcnt, hipStream_t s);
+
 // ---- rescore.hip
+// Exact FP32 similarities of the Between rows, in place (reduced-precision GEMMs).
+hipError_t launch_exact_rows(const farm_memory* mem, const float* qn, float* sim, int64_t ld_s, int32_t q,
+                             MetaView meta, int32_t R, hipStream_t s);
 // FP32 scores of the candidates cand[q][c] (object indices, -1 = none): exact
 // target similarity and, per relation, the exact maximum over anchors, where
 // only anchors whose bounded value can reach the best lower bound get an FP32

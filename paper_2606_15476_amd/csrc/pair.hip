@@ -109,12 +109,29 @@ __global__ __launch_bounds__(64 * kScanWaves) void k_scan_rows(
     const float* __restrict__ ext, const uint32_t* __restrict__ ids, const int32_t* __restrict__ cls,
     const int32_t* __restrict__ cls_order, const int32_t* __restrict__ cls_sorted, int64_t n,
     float* __restrict__ rel_terms,
-    uint32_t* __restrict__ rel_anchor_id) {
+    uint32_t* __restrict__ rel_anchor_id, BetweenView bv) {
   const int lane = threadIdx.x & 63;
   const int64_t o = (int64_t)blockIdx.x * kScanWaves + (threadIdx.x >> 6);
   if (o >= n) return;  // whole waves leave together
   const int r = meta.scan_rows[blockIdx.y];
   const int qq = meta.rel_query[r];
+  if (meta.rel_pred[r] == FARM_BETWEEN) {  // both slots of the invocation: the term and the two anchors
+    float t;
+    uint32_t b1, b2;
+    between_term_row(bv, x, y, z, ids, r, o, lane, t, b1, b2);
+    if (lane == 0) {
+      lsim[(int64_t)r * ld_s + o] = logf(t);
+      if (rel_terms) {
+        rel_terms[(int64_t)r * n + o] = t;
+        rel_terms[(int64_t)(r + 1) * n + o] = t;
+      }
+      if (rel_anchor_id) {
+        rel_anchor_id[(int64_t)r * n + o] = b1;
+        rel_anchor_id[(int64_t)(r + 1) * n + o] = b2;
+      }
+    }
+    return;
+  }
   const ScanCtx k{x, y, z, ext, ids, cls, cls_order, cls_sorted, meta.tcls[qq], n, meta.rel_pred[r]};
   const float* arow = sim + (int64_t)(q + r) * ld_s;
   float best;
@@ -154,8 +171,11 @@ __global__ __launch_bounds__(kThreads) void k_pair_exhaustive(
   const bool bounded = bound.q_nrm != nullptr;
   const float err_max = bounded ? *bound.o_err_max : 0.f;
 
+  int R = 0;  // predicate invocations (a Between's second slot is not one)
   for (int r = r0; r < r1; ++r) {
     const int p = meta.rel_pred[r];
+    if (p == FARM_AND) continue;  // its term is the Between slot's before it
+    ++R;
     const int fam = family_of(p);
     const float c = sigmoid_scale(p);
     const float* arow = sim + (int64_t)(q + r) * ld_s;
@@ -213,7 +233,6 @@ __global__ __launch_bounds__(kThreads) void k_pair_exhaustive(
       }
     }
   }
-  const int R = r1 - r0;
 #pragma unroll
   for (int u = 0; u < kTpt; ++u) {
     int64_t i = tile0 + threadIdx.x + u * kThreads;
@@ -288,7 +307,7 @@ __global__ __launch_bounds__(256) void k_explain(const float* __restrict__ sim, 
                                                  const int32_t* __restrict__ cls_order,
                                                  const int32_t* __restrict__ cls_sorted,
                                                  int64_t n, float* __restrict__ out_terms,
-                                                 uint32_t* __restrict__ out_anchor_id) {
+                                                 uint32_t* __restrict__ out_anchor_id, BetweenView bv) {
   __shared__ float red_v[256];
   __shared__ uint32_t red_id[256];
   const int32_t qq = blockIdx.y, kk = blockIdx.x;
@@ -306,7 +325,15 @@ __global__ __launch_bounds__(256) void k_explain(const float* __restrict__ sim, 
       const float* rhi = hhi + (is_depth(p) ? n : 0);  // depth pair of InFrontOf/Behind
       const float* rlo = hlo + (is_depth(p) ? n : 0);
       const ZPair zp = z_for(p, z, vz, n);  // On: bottom/top faces
-      if (is_scanned(p)) {
+      if (p == FARM_BETWEEN || p == FARM_AND) {
+        // the invocation's term from its first slot; the first slot binds a1, the second a2
+        const int rb = p == FARM_BETWEEN ? r : r - 1;
+        float bt;
+        uint32_t b1, b2;
+        between_term_row(bv, x, y, z, ids, rb, i, (int)(threadIdx.x & 63), bt, b1, b2);
+        tv = bt;
+        b = p == FARM_BETWEEN ? b1 : b2;
+      } else if (is_scanned(p)) {
         // every wave takes the same term (identical arithmetic); thread 0 stores it
         const ScanCtx rk{x, y, z, ext, ids, cls, cls_order, cls_sorted, meta.tcls[qq], n, p};
         float bv;
@@ -327,6 +354,65 @@ __global__ __launch_bounds__(256) void k_explain(const float* __restrict__ sim, 
   }
 }
 
+// Between's candidate sets: for every relation row of a Between invocation,
+// the kBetweenSet anchors of largest similarity (ties by the smaller id) and
+// their similarities, by repeated block-wide selection of the next anchor in
+// (similarity desc, id asc) order -- one 256-thread block per row.
+__global__ __launch_bounds__(256) void k_between_sets(const float* __restrict__ sim, int64_t ld_s, int32_t q,
+                                                      MetaView meta, const uint32_t* __restrict__ ids, int64_t n,
+                                                      int32_t* __restrict__ bidx, float* __restrict__ bsim,
+                                                      int32_t* __restrict__ bcnt) {
+  __shared__ float rv[256];
+  __shared__ uint32_t rid[256];
+  __shared__ int32_t rj[256];
+  const int r = blockIdx.x;
+  const int p = meta.rel_pred[r];
+  if (p != FARM_BETWEEN && p != FARM_AND) return;
+  const float* row = sim + (int64_t)(q + r) * ld_s;
+  const int k = (int)(n < kBetweenSet ? n : kBetweenSet);
+  float pv = INFINITY;
+  uint32_t pid = 0;
+  for (int round = 0; round < k; ++round) {
+    float bv = -INFINITY;
+    uint32_t bi = FARM_NO_ID;
+    int32_t bj = -1;
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+      const float v = row[j];
+      const uint32_t id = ids[j];
+      const bool after = v < pv || (v == pv && id > pid);  // comes after the last one taken
+      if (after && (v > bv || (v == bv && id < bi))) {
+        bv = v;
+        bi = id;
+        bj = (int32_t)j;
+      }
+    }
+    rv[threadIdx.x] = bv;
+    rid[threadIdx.x] = bi;
+    rj[threadIdx.x] = bj;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) {
+        const float v2 = rv[threadIdx.x + w];
+        const uint32_t i2 = rid[threadIdx.x + w];
+        if (v2 > rv[threadIdx.x] || (v2 == rv[threadIdx.x] && i2 < rid[threadIdx.x])) {
+          rv[threadIdx.x] = v2;
+          rid[threadIdx.x] = i2;
+          rj[threadIdx.x] = rj[threadIdx.x + w];
+        }
+      }
+      __syncthreads();
+    }
+    pv = rv[0];
+    pid = rid[0];
+    if (threadIdx.x == 0) {
+      bidx[(int64_t)r * kBetweenSet + round] = rj[0];
+      bsim[(int64_t)r * kBetweenSet + round] = pv;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bcnt[r] = k;
+}
+
 __global__ void k_log_rows(const float* __restrict__ sim, int64_t ld_s, int64_t rows, int64_t n,
                            float* __restrict__ lsim) {
   const int64_t r = blockIdx.y;
@@ -336,6 +422,14 @@ __global__ void k_log_rows(const float* __restrict__ sim, int64_t ld_s, int64_t 
 
 }  // namespace
 
+hipError_t launch_between_sets(const farm_memory* mem, const float* sim, int64_t ld_s, int32_t q, MetaView meta,
+                               int32_t R, int32_t* bidx, float* bsim, int32_t* bcnt, hipStream_t s) {
+  if (R <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_between_sets, dim3((unsigned)R), dim3(256), 0, s, sim, ld_s, q, meta, mem->id, mem->n, bidx,
+                     bsim, bcnt);
+  return hipGetLastError();
+}
+
 hipError_t launch_log_rows(const float* sim, int64_t ld_s, int64_t rows, int64_t n, float* lsim, hipStream_t s) {
   if (rows <= 0) return hipSuccess;
   const unsigned gx = (unsigned)((n + 255) / 256 < 64 ? (n + 255) / 256 : 64);
@@ -343,15 +437,17 @@ hipError_t launch_log_rows(const float* sim, int64_t ld_s, int64_t rows, int64_t
   return hipGetLastError();
 }
 
-hipError_t launch_pair_exhaustive(const farm_memory* mem, const float* sim, const float* lsim, int64_t ld_s, int32_t q,
-                                  MetaView meta, const SimBound& bound, float* scores, int64_t ld_out, float* rel_terms,
-                                  uint32_t* rel_anchor_id, float* scores_hi, hipStream_t s) {
+hipError_t launch_pair_exhaustive(const farm_memory* mem, const farm_workspace* ws, const float* sim, const float* lsim,
+                                  int64_t ld_s, int32_t q, MetaView meta, const SimBound& bound, float* scores,
+                                  int64_t ld_out, float* rel_terms, uint32_t* rel_anchor_id, float* scores_hi,
+                                  hipStream_t s) {
   if (q <= 0) return hipSuccess;
   int64_t n = mem->n;
   if (meta.scan_n > 0) {
+    const BetweenView bv{ws->btw_idx, ws->btw_sim, ws->btw_cnt};
     hipLaunchKernelGGL(k_scan_rows, dim3((unsigned)((n + kScanWaves - 1) / kScanWaves), (unsigned)meta.scan_n),
                        dim3(64 * kScanWaves), 0, s, sim, const_cast<float*>(lsim), ld_s, q, meta, mem->x, mem->y, mem->z,
-                       mem->ext, mem->id, mem->cls, mem->cls_order, mem->cls_sorted, n, rel_terms, rel_anchor_id);
+                       mem->ext, mem->id, mem->cls, mem->cls_order, mem->cls_sorted, n, rel_terms, rel_anchor_id, bv);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -367,14 +463,16 @@ hipError_t launch_pair_exhaustive(const farm_memory* mem, const float* sim, cons
   return hipGetLastError();
 }
 
-hipError_t launch_explain(const farm_memory* mem, const float* sim, int64_t ld_s, int32_t q, MetaView meta,
-                          const int32_t* idx, int32_t k, float* out_terms, uint32_t* out_anchor_id, hipStream_t s) {
+hipError_t launch_explain(const farm_memory* mem, const farm_workspace* ws, const float* sim, int64_t ld_s, int32_t q,
+                          MetaView meta, const int32_t* idx, int32_t k, float* out_terms, uint32_t* out_anchor_id,
+                          hipStream_t s) {
   if (q <= 0 || k <= 0 || (!out_terms && !out_anchor_id)) return hipSuccess;
   dim3 grid((unsigned)k, (unsigned)q);
+  const BetweenView bv{ws->btw_idx, ws->btw_sim, ws->btw_cnt};
   hipLaunchKernelGGL(k_explain, grid, dim3(256), 0, s, sim, ld_s, q, meta, idx, k, mem->x, mem->y, mem->z, mem->vz,
                      mem->hr_hi, mem->hr_lo, mem->id, mem->ext, mem->cls, mem->cls_order, mem->cls_sorted, mem->n,
                      out_terms,
-                     out_anchor_id);
+                     out_anchor_id, bv);
   return hipGetLastError();
 }
 

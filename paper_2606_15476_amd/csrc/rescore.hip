@@ -689,11 +689,12 @@ __global__ __launch_bounds__(64 * kTermWaves) void k_rescore_terms(
       if (o < 0) continue;
       if (MODE == kTermsFull) {
         full(slot, e, o);
-        checked += 1;
+        checked += meta.rel_pred[r0 + e] != FARM_AND;
         continue;
       }
       const int r = r0 + e;
       const int p = meta.rel_pred[r];
+      if (p == FARM_AND) continue;  // written with the Between slot before it
       const float c = sigmoid_scale(p);
       const Geo gp = geo_for(g, p, n);
       const float* arow = sim + (int64_t)(q + r) * ld_s;
@@ -763,11 +764,23 @@ __global__ __launch_bounds__(64 * kTermWaves) void k_scan_terms(
     const int e = (int)(tix % R);
     const int r = r0 + e;
     const int p = meta.rel_pred[r];
-    if (!is_scanned(p)) continue;
+    if (!is_scanned(p) || p == FARM_AND) continue;  // a Between's second slot: written with its first
     const int64_t slot = (int64_t)qq * C + tix / R;
     const int64_t o = cand[slot];
     if (o < 0) continue;
     if (SWEEP && !isnan(rs_terms[slot * kMaxRel + e])) continue;
+    if (p == FARM_BETWEEN) {
+      float t;
+      uint32_t b1, b2;
+      between_term_row(BetweenView{pv.btw_idx, pv.btw_sim, pv.btw_cnt}, g.x, g.y, g.z, g.ids, r, o, lane, t, b1, b2);
+      if (lane == 0) {
+        rs_terms[slot * kMaxRel + e] = t;
+        rs_terms[slot * kMaxRel + e + 1] = t;
+        rs_anchor[slot * kMaxRel + e] = b1;
+        rs_anchor[slot * kMaxRel + e + 1] = b2;
+      }
+      continue;
+    }
     const float* arow = sim + (int64_t)(q + r) * ld_s;
     const float* qrow = qn + (int64_t)(q + r) * ldk;
     const float qnr = BOUNDED ? bound.q_nrm[q + r] : 0.f;
@@ -918,6 +931,7 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
   const int fam = family_of(p);
   const Geo gp = geo_for(g, p, n);
   const bool tab = has_lists(p);  // without lists every term goes to the fallback
+  const bool second = p == FARM_AND;  // a Between's second slot: its terms are written with the first
   const int32_t cnt = cand_count ? (cand_count[qq] < C ? cand_count[qq] : C) : C;
   // the set's anchor coordinates and the first kCandLds candidates (id, own
   // coordinates, bound on the predicate outside the list), read once for all
@@ -989,7 +1003,7 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
   int64_t o_nx = o_of(wave);
   int4 j_nx = make_int4(-1, -1, -1, -1);
   if (REG && tab && o_nx >= 0) j_nx = ids_of(o_nx);
-  for (int32_t cc = wave; cc < cnt; cc += kLdsWaves) {
+  for (int32_t cc = second ? cnt : wave; cc < cnt; cc += kLdsWaves) {
     const int64_t slot = (int64_t)qq * C + cc;
     const int64_t o = REG ? o_nx : o_of(cc);
     RegList lst{j_nx, make_float4(0.f, 0.f, 0.f, 0.f)};
@@ -1351,9 +1365,25 @@ __global__ __launch_bounds__(kFbThreads) void k_scan_fallback(
     const int e = (int)(tix % R);
     const int r = r0 + e;
     const int p = meta.rel_pred[r];
-    if (!is_scanned(p)) continue;  // block-uniform
+    if (!is_scanned(p) || p == FARM_AND) continue;  // block-uniform
     const int64_t slot = (int64_t)qq * C + cc;
     const int64_t o = cand[slot];
+    if (p == FARM_BETWEEN) {  // one wave takes the invocation's term (both slots)
+      if (threadIdx.x < 64) {
+        float t;
+        uint32_t b1, b2;
+        between_term_row(BetweenView{pv.btw_idx, pv.btw_sim, pv.btw_cnt}, g.x, g.y, g.z, g.ids, r, o,
+                         (int)threadIdx.x, t, b1, b2);
+        if (threadIdx.x == 0) {
+          rs_terms[slot * kMaxRel + e] = t;
+          rs_terms[slot * kMaxRel + e + 1] = t;
+          rs_anchor[slot * kMaxRel + e] = b1;
+          rs_anchor[slot * kMaxRel + e + 1] = b2;
+        }
+      }
+      __syncthreads();
+      continue;
+    }
     const float* arow = sim + (int64_t)(q + r) * ld_s;
     const float* qrow = qn + (int64_t)(q + r) * ldk;
     const float qnr = BOUNDED ? bound.q_nrm[q + r] : 0.f;
@@ -1423,18 +1453,21 @@ __global__ __launch_bounds__(256) void k_rescore_combine(
       sem = kappa * fmaxf(0.f, dot);
     }
     float lsum = 0.f;
+    int inv = 0;  // predicate invocations (a Between's two slots count once)
     for (int e = 0; e < R; ++e) {
       const float v = rs_terms[slot * kMaxRel + e];
-      if (family_of(meta.rel_pred[r0 + e]) == kFamNear) {
+      const int p = meta.rel_pred[r0 + e];
+      if (family_of(p) == kFamNear) {
         lsum += v;
         rs_terms[slot * kMaxRel + e] = term_of<kFamNear>(v);
       } else {
         const float term = term_of<kFamVert>(v);
-        lsum += logf(term);
+        if (p != FARM_AND) lsum += logf(term);
         rs_terms[slot * kMaxRel + e] = term;
       }
+      inv += p != FARM_AND;
     }
-    const float gm = R > 0 ? expf(lsum / (float)R) : 1.0f;
+    const float gm = inv > 0 ? expf(lsum / (float)inv) : 1.0f;
     rs_score[slot] = sem * ((1.0f - kW) + kW * gm);
     for (int e = R; e < kMaxRel; ++e) {
       rs_terms[slot * kMaxRel + e] = 0.f;
@@ -1583,12 +1616,16 @@ bool proposal_pass_in_lds(const farm_memory* mem, bool bounded) {
 
 hipError_t launch_rescore_terms(const farm_memory* mem, const farm_workspace* ws, const float* sim, int64_t ld_s,
                                 int32_t q, MetaView meta, const SimBound& bound, const int32_t* cand,
-                                const int32_t* cand_count, int32_t c, const PropView& prop, bool fallback_pass,
+                                const int32_t* cand_count, int32_t c, const PropView& prop_in, bool fallback_pass,
                                 hipStream_t s) {
   if (q <= 0 || c <= 0) return hipSuccess;
   const Geo g{mem->x, mem->y, mem->z,   mem->z,   mem->hr_hi,     mem->hr_lo,
               mem->id, mem->vz, mem->cls, mem->cls_order, mem->cls_sorted, mem->ext};
   const dim3 grid(kTermBlocksX, (unsigned)q), block(64 * kTermWaves);
+  PropView prop = prop_in;  // with Between's candidate sets
+  prop.btw_idx = ws->btw_idx;
+  prop.btw_sim = ws->btw_sim;
+  prop.btw_cnt = ws->btw_cnt;
 #define FARM_TERMS(MODE, B)                                                                                      \
   hipLaunchKernelGGL((k_rescore_terms<MODE, B>), grid, block, 0, s, sim, ld_s, q, meta, bound, ws->qn, mem->dn, \
                      mem->ldk, cand, cand_count, c, g, mem->n, ws->rs_terms, ws->rs_anchor, prop)
@@ -1700,6 +1737,36 @@ hipError_t launch_semantic_exact(const farm_memory* mem, const farm_workspace* w
   const int64_t waves = (int64_t)R * kSemMax;
   hipLaunchKernelGGL(k_semantic_exact, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, ws->qn, mem->dn, mem->ldk, q,
                      R, ws->sem_idx, ws->sem_cnt, ws->sem_sim);
+  return hipGetLastError();
+}
+
+namespace {
+// Exact FP32 similarities max(0, q . d) of the relation rows of Between
+// invocations (FARM_BETWEEN / FARM_AND), in place in the similarity matrix,
+// with the rescoring kernels' dot product: Between's candidate sets and
+// values are taken on exact similarities whatever the GEMM's dtype.  One wave
+// per (row, anchor), four waves per block; blocks of other rows leave at once.
+__global__ __launch_bounds__(256) void k_exact_rows(const float* __restrict__ qn, const float* __restrict__ dn,
+                                                    int32_t ldk, float* __restrict__ sim, int64_t ld_s, int32_t q,
+                                                    MetaView meta, int64_t n) {
+  const int r = blockIdx.y;
+  const int p = meta.rel_pred[r];
+  if (p != FARM_BETWEEN && p != FARM_AND) return;
+  const int lane = threadIdx.x & 63;
+  const float* qrow = qn + (int64_t)(q + r) * ldk;
+  for (int64_t a = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); a < n; a += (int64_t)gridDim.x * 4) {
+    const float v = fmaxf(0.f, wave_dot(qrow, dn + a * ldk, ldk, lane));
+    if (lane == 0) sim[(int64_t)(q + r) * ld_s + a] = v;
+  }
+}
+}  // namespace
+
+hipError_t launch_exact_rows(const farm_memory* mem, const float* qn, float* sim, int64_t ld_s, int32_t q,
+                             MetaView meta, int32_t R, hipStream_t s) {
+  if (R <= 0) return hipSuccess;
+  const int64_t blocks = (mem->n + 3) / 4;
+  hipLaunchKernelGGL(k_exact_rows, dim3((unsigned)(blocks < 1024 ? blocks : 1024), (unsigned)R), dim3(256), 0, s, qn,
+                     mem->dn, mem->ldk, sim, ld_s, q, meta, mem->n);
   return hipGetLastError();
 }
 

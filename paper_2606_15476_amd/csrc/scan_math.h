@@ -31,7 +31,9 @@
 namespace farm {
 
 __device__ inline bool is_rank(int p) { return p == FARM_CLOSEST || p == FARM_FARTHEST; }
-__device__ inline bool is_scanned(int p) { return is_rank(p) || p == FARM_INSIDE; }
+// Between and its second-anchor slot are scanned too (between_term_wave): the
+// pairwise kernels and the proposal lists leave them alone.
+__device__ inline bool is_scanned(int p) { return is_rank(p) || p == FARM_INSIDE || p == FARM_BETWEEN || p == FARM_AND; }
 
 struct ScanCtx {
   const float *x, *y, *z;
@@ -220,6 +222,109 @@ __device__ void scan_term_wave(ScanCtx k, int64_t o, int lane, LoOf lo_of, HiOf 
   if (!(sn > 0 && best > out_bound)) scan_anchor_part(k, o, lane, lo_of, hi_of, exact_of, 0, 1, best, bid);
   out_best = best;
   out_bid = bid;
+}
+
+// ---------------------------------------------------------------- Between
+// Between(o; a1, a2) = sig(s1 / tau) sig(s2 / tau) exp(-h^2 / (2 sigma^2)),
+// tau = 0.1 m, sigma = 0.5 m: s1 = (c_o - c_a1) . u and s2 = (c_a2 - c_o) . u
+// are the two margins along the unit axis u from a1 to a2 (each formed from
+// its own anchor, so that it is accurate relative to that offset), h the
+// distance of c_o from the axis, from the cross product with the offset to
+// the nearer anchor.  0 when the anchors coincide.
+__device__ inline float between_p(float ox, float oy, float oz, float x1, float y1, float z1, float x2, float y2,
+                                  float z2) {
+  float ux = x2 - x1, uy = y2 - y1, uz = z2 - z1;
+  const float l2 = ux * ux + uy * uy + uz * uz;
+  if (l2 == 0.f) return 0.f;
+  const float inv = 1.0f / sqrtf(l2);
+  ux *= inv;
+  uy *= inv;
+  uz *= inv;
+  const float w1x = ox - x1, w1y = oy - y1, w1z = oz - z1;
+  const float w2x = x2 - ox, w2y = y2 - oy, w2z = z2 - oz;
+  const float s1 = w1x * ux + w1y * uy + w1z * uz;
+  const float s2 = w2x * ux + w2y * uy + w2z * uz;
+  const bool near1 = fabsf(s1) <= fabsf(s2);
+  const float wx = near1 ? w1x : -w2x, wy = near1 ? w1y : -w2y, wz = near1 ? w1z : -w2z;
+  const float cx = wy * uz - wz * uy, cy = wz * ux - wx * uz, cz = wx * uy - wy * ux;
+  const float h2 = cx * cx + cy * cy + cz * cz;
+  // logistic(v / 0.1) = 1 / (1 + 2^(-v * 10 log2 e)); Gaussian exp(-h^2 / 0.5) = 2^(-2 log2(e) h^2)
+  constexpr float kS = 14.426950408889634f;  // 10 log2(e)
+  constexpr float kG = 2.8853900817779268f;  // 2 log2(e)
+  const float g1 = 1.0f / (1.0f + exp2f(-s1 * kS));
+  const float g2 = 1.0f / (1.0f + exp2f(-s2 * kS));
+  return g1 * g2 * exp2f(-h2 * kG);
+}
+
+// (value, id1, id2) ordering of Between bindings: larger value, then the
+// smaller id pair.
+__device__ inline bool between_better(float v, uint32_t i1, uint32_t i2, float bv, uint32_t b1, uint32_t b2) {
+  return v > bv || (v == bv && (i1 < b1 || (i1 == b1 && i2 < b2)));
+}
+
+__device__ inline void between_wave_best(float& v, uint32_t& i1, uint32_t& i2) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const float ov = __shfl_xor(v, off);
+    const uint32_t o1 = __shfl_xor(i1, off), o2 = __shfl_xor(i2, off);
+    if (between_better(ov, o1, o2, v, i1, i2)) {
+      v = ov;
+      i1 = o1;
+      i2 = o2;
+    }
+  }
+}
+
+// Between's term for target o by one wave: the maximum over a1 in the first
+// candidate set and a2 in the second (a1 != a2, both != o) of
+// (sim1(a1) sim2(a2)) Between(o; a1, a2), ties by the smaller id pair; the
+// candidate sets are the 64 anchors of largest similarity of each slot
+// (k_between_sets) with their exact similarities.  t = 0 and no binding
+// (FARM_NO_ID) when no pair has a positive value.
+__device__ inline void between_term_wave(const float* __restrict__ x, const float* __restrict__ y,
+                                         const float* __restrict__ z, const uint32_t* __restrict__ ids, int64_t o,
+                                         int lane, const int32_t* __restrict__ s1, const float* __restrict__ e1,
+                                         int n1, const int32_t* __restrict__ s2, const float* __restrict__ e2, int n2,
+                                         float& out_t, uint32_t& out_b1, uint32_t& out_b2) {
+  const float ox = x[o], oy = y[o], oz = z[o];
+  float best = 0.f;
+  uint32_t b1 = FARM_NO_ID, b2 = FARM_NO_ID;
+  const int pairs = n1 * n2;
+  for (int idx = lane; idx < pairs; idx += 64) {
+    const int m1 = idx / n2, m2 = idx - m1 * n2;
+    const int64_t a1 = s1[m1], a2 = s2[m2];
+    if (a1 == o || a2 == o || a1 == a2) continue;
+    const float v = (e1[m1] * e2[m2]) * between_p(ox, oy, oz, x[a1], y[a1], z[a1], x[a2], y[a2], z[a2]);
+    if (v <= 0.f) continue;
+    const uint32_t i1 = ids[a1], i2 = ids[a2];
+    if (between_better(v, i1, i2, best, b1, b2)) {
+      best = v;
+      b1 = i1;
+      b2 = i2;
+    }
+  }
+  between_wave_best(best, b1, b2);
+  out_t = best;
+  out_b1 = best > 0.f ? b1 : FARM_NO_ID;
+  out_b2 = best > 0.f ? b2 : FARM_NO_ID;
+}
+
+// Between's candidate sets as the term kernels see them: per relation slot
+// row r, kBetweenSet entries of idx / sim and the count.
+constexpr int kBetweenSet = kBetweenSetSize;
+struct BetweenView {
+  const int32_t* idx = nullptr;  // [R][kBetweenSet]
+  const float* sim = nullptr;    // [R][kBetweenSet]
+  const int32_t* cnt = nullptr;  // [R]
+};
+
+// The term of the Between invocation whose first slot is relation row r.
+__device__ inline void between_term_row(const BetweenView& bv, const float* x, const float* y, const float* z,
+                                        const uint32_t* ids, int r, int64_t o, int lane, float& t, uint32_t& b1,
+                                        uint32_t& b2) {
+  between_term_wave(x, y, z, ids, o, lane, bv.idx + (int64_t)r * kBetweenSet, bv.sim + (int64_t)r * kBetweenSet,
+                    bv.cnt[r], bv.idx + (int64_t)(r + 1) * kBetweenSet, bv.sim + (int64_t)(r + 1) * kBetweenSet,
+                    bv.cnt[r + 1], t, b1, b2);
 }
 
 }  // namespace farm

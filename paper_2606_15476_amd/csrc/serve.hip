@@ -364,6 +364,11 @@ farm_status farm_server_submit(farm_server* sv, int32_t scene, int32_t d, const 
     if (n2 == 0.0) { set_error("zero-norm target"); return FARM_ERR_INVALID_ARG; }
     for (int32_t e = 0; e < r; ++e) {
       if (preds[e] < 0 || preds[e] >= FARM_NUM_PRED) { set_error("bad predicate %d", preds[e]); return FARM_ERR_INVALID_ARG; }
+      if ((preds[e] == FARM_BETWEEN && (e + 1 >= r || preds[e + 1] != FARM_AND)) ||
+          (preds[e] == FARM_AND && (e == 0 || preds[e - 1] != FARM_BETWEEN))) {
+        set_error("FARM_BETWEEN must be followed by FARM_AND (relation %d)", e);
+        return FARM_ERR_INVALID_ARG;
+      }
       double a2 = 0.0;
       for (int32_t i = 0; i < d; ++i) {
         const float v = anchors[(size_t)e * d + i];

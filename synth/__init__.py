@@ -28,12 +28,13 @@ import numpy as np
 NEAR, ABOVE, BELOW, LEFT_OF, RIGHT_OF = 0, 1, 2, 3, 4
 NEXT_TO, IN_FRONT_OF, BEHIND, ON = 5, 6, 7, 8
 CLOSEST, FARTHEST, INSIDE = 9, 10, 11
+BETWEEN, AND = 12, 13                       # ternary Between: its slot, then its second anchor's slot
 ALL_PREDS = tuple(range(9))                 # the pairwise predicates with learned anchor lists
 RANK_PREDS = (CLOSEST, FARTHEST)            # rank within the query's candidate set
 EVERY_PRED = ALL_PREDS + RANK_PREDS + (INSIDE,)
 DEFAULT_PREDS = (NEAR, ABOVE, BELOW, LEFT_OF, RIGHT_OF)  # the pool query batches draw from by default
 PRED_NAMES = ("near", "above", "below", "left_of", "right_of", "next_to", "in_front_of", "behind", "on", "closest",
-              "farthest", "inside")
+              "farthest", "inside", "between", "and")
 
 
 @dataclasses.dataclass
@@ -265,6 +266,41 @@ def make_queries(cfg: Config, scene: Scene, seed: int | None = None, q: int | No
         rel_anchor=np.ascontiguousarray(np.asarray(anchors, dtype=np.float32).reshape(len(preds), d)),
         planted=np.asarray(planted, dtype=np.int64),
     )
+
+
+def add_between(cfg: Config, scene: Scene, qb: QueryBatch, seed: int, every: int = 1) -> QueryBatch:
+    """Append one Between invocation (two slots: BETWEEN, then AND) to every
+    ``every``-th query that has room (R + 2 <= 8).  Its anchors are planted by
+    a geometric rule around the query's planted target o: the object nearest
+    to o, then the object nearest to o on the far side of o from it (positive
+    offset along the direction from the first anchor to o); their embeddings
+    are noisy centroids of their categories."""
+    rng = np.random.default_rng([seed, 0xB7])
+    c64 = scene.center.astype(np.float64)
+    offs, preds, anchors = [0], [], []
+    d = scene.d
+    for k in range(qb.q):
+        a, b = int(qb.rel_off[k]), int(qb.rel_off[k + 1])
+        preds += [int(v) for v in qb.rel_pred[a:b]]
+        anchors += list(qb.rel_anchor[a:b])
+        o = int(qb.planted[k])
+        if k % every == 0 and b - a + 2 <= 8 and scene.n >= 3:
+            dist = np.sqrt(((c64 - c64[o]) ** 2).sum(axis=1))
+            dist[o] = np.inf
+            j1 = int(np.argmin(dist))
+            axis = c64[o] - c64[j1]
+            far = (c64 - c64[o]) @ axis > 0
+            far[[o, j1]] = False
+            j2 = int(np.flatnonzero(far)[np.argmin(dist[far])]) if far.any() else int(np.argsort(dist)[1])
+            preds += [BETWEEN, AND]
+            for j in (j1, j2):
+                anchors.append(_noisy(rng, scene.centroids[int(scene.cls[j])][None].astype(np.float64), cfg.noise)[0])
+        offs.append(len(preds))
+    return QueryBatch(
+        target=qb.target, target_cls=qb.target_cls, rel_off=np.asarray(offs, dtype=np.int32),
+        rel_pred=np.asarray(preds, dtype=np.int32),
+        rel_anchor=np.ascontiguousarray(np.asarray(anchors, dtype=np.float32).reshape(len(preds), d)),
+        planted=qb.planted)
 
 
 def make_workload(name: str, **kw):

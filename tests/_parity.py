@@ -25,6 +25,11 @@ Tolerances (derived from the FP32 arithmetic of the GPU path):
     distances lie within RANK_EPS = 1e-6 relative of each other either order
     is correct; the oracle's rank_tolerance mode gives the lowest and highest
     values over those orders, and the GPU value must lie between them.
+  * Between: its anchors range over the 64 anchors of largest similarity per
+    description; an anchor whose similarity lies within BETWEEN_EPS = ABS of
+    the 64th largest may be in or out of an FP32 implementation's set, so the
+    oracle's between_tolerance mode gives the lowest term (surely included
+    anchors only) and the highest (every possibly included one).
 """
 import numpy as np
 
@@ -34,6 +39,8 @@ GAP = 1e-5
 TOPK_FLOOR = 1e-2
 RANK_EPS = 1e-6
 RANK_PREDS = (9, 10)
+BETWEEN = 12
+BETWEEN_EPS = ABS  # FP32 similarities within ABS of the oracle's may select another boundary anchor
 
 
 def value_tol(x64):
@@ -84,19 +91,31 @@ def has_rank_preds(qb):
     return bool(np.isin(np.asarray(qb.rel_pred), RANK_PREDS).any())
 
 
+def has_between(qb):
+    return bool(np.isin(np.asarray(qb.rel_pred), (BETWEEN,)).any())
+
+
 def oracle_bounds(scene, qb):
     """(s64, sem, t64, b64, s_lo, s_hi, t_lo, t_hi): the oracle's exact scores and
     terms, and their lowest / highest values over the rank orders that FP32
-    distance comparisons may take (equal to the exact ones without rank
-    predicates)."""
+    distance comparisons may take and over Between's candidate sets that FP32
+    similarities may select (equal to the exact ones without such predicates)."""
+    import contextlib
     import oracle
     s64, sem, t64, b64 = oracle.score(scene, qb, terms=True)
-    if not has_rank_preds(qb):
+    rank, btw = has_rank_preds(qb), has_between(qb)
+    if not rank and not btw:
         return s64, sem, t64, b64, s64, s64, t64, t64
-    with oracle.rank_tolerance(-1, RANK_EPS):
-        s_lo, _, t_lo, _ = oracle.score(scene, qb, terms=True)
-    with oracle.rank_tolerance(+1, RANK_EPS):
-        s_hi, _, t_hi, _ = oracle.score(scene, qb, terms=True)
+    out = []
+    for mode in (-1, +1):
+        with contextlib.ExitStack() as st:
+            if rank:
+                st.enter_context(oracle.rank_tolerance(mode, RANK_EPS))
+            if btw:
+                st.enter_context(oracle.between_tolerance(mode, BETWEEN_EPS))
+            s_, _, t_, _ = oracle.score(scene, qb, terms=True)
+        out.append((s_, t_))
+    (s_lo, t_lo), (s_hi, t_hi) = out
     return s64, sem, t64, b64, s_lo, s_hi, t_lo, t_hi
 
 

@@ -49,6 +49,20 @@ def _check_full(farm, scene, qb, label):
             cols = rng.choice(scene.n, size=min(scene.n, 24), replace=False)
             qq = int(np.searchsorted(qb.rel_off, r, side="right")) - 1
             p = int(qb.rel_pred[r])
+            if p == 13:  # Between's second slot: checked with the first
+                continue
+            if p == 12:  # Between: the two bound anchors attain the term (no binding when it is 0)
+                for i in cols:
+                    j1, j2 = int(b[r, i]), int(b[r + 1, i])
+                    assert t[r + 1, i] == t[r, i]
+                    if t[r, i] == 0:
+                        assert j1 == j2 == 0xFFFFFFFF, (label, r, i)
+                        continue
+                    a1, a2 = idx_of[j1], idx_of[j2]
+                    assert len({a1, a2, int(i)}) == 3
+                    v = oracle.between_binding_value(scene, qb.rel_anchor[r], qb.rel_anchor[r + 1], int(i), a1, a2)
+                    assert abs(v - t[r, i]) <= REL * t[r, i] + ABS, (label, r, i, v, t[r, i])
+                continue
             for i in cols:
                 if scene.n == 1:
                     assert b[r, i] == 0xFFFFFFFF
@@ -202,6 +216,85 @@ def test_rank_predicates_bounded_and_precision(farm, dtype):
         assert len(cert_rows) == qb.q
         for a, b in zip(bd[:4], ex[:4]):
             np.testing.assert_array_equal(a, b)
+
+
+def _between_world(seed, n=600, q=20):
+    """A mid-config scene; queries drawing from every predicate, each with a
+    Between invocation planted around its target; every third query has no
+    class."""
+    import synth
+    cfg = CONFIGS["mid"]
+    scene = make_scene(cfg, n=n, seed=seed)
+    qb = make_queries(cfg, scene, seed=seed + 1, q=q, r_min=0, r_max=3, preds=synth.EVERY_PRED)
+    qb = synth.add_between(cfg, scene, qb, seed + 2)
+    qb.target_cls[::3] = -1
+    assert (qb.rel_pred == synth.BETWEEN).sum() == q
+    return cfg, scene, qb
+
+
+def test_between_full_parity(farm):
+    """Between (ternary, over the two anchors' candidate sets of 64) beside the
+    other predicates, exhaustive FP32 method: full score matrix, every slot's
+    term, both bound anchors, TopK and breakdown against the oracle."""
+    cfg, scene, qb = _between_world(41)
+    mem, ws, full = _check_full(farm, scene, qb, "between")
+    _topk_against_full(farm, mem, ws, scene, qb, full, cfg.k, "between")
+
+
+@pytest.mark.parametrize("dtype", [0, 1, 2], ids=["f32", "bf16", "fp8"])
+def test_between_bounded_proposal_and_precision(farm, dtype):
+    """Between under the bound-pruned and learned-proposal methods and the
+    reduced-precision GEMMs (its rows and candidate sets exact in FP32):
+    certified, the oracle's TopK; PROPOSAL equals BOUNDED bit for bit; FP32
+    BOUNDED equals the exhaustive path bit for bit."""
+    from tests import _gpu
+    cfg, scene, qb = _between_world(43)
+    mem = _gpu.build_memory(scene, flags=farm.FARM_BUILD_BF16 | farm.FARM_BUILD_FP8)
+    ws = _ws(farm, mem, qb)
+    s64, _, _, _, s_lo, s_hi, _, _ = oracle_bounds(scene, qb)
+    bd = _gpu.query_topk(mem, ws, qb, cfg.k, dtype=dtype, with_cert=True, method=farm.BOUNDED)
+    assert np.all(bd[4] == 1)
+    _check_topk_rows(scene, bd[0], bd[1], (s64, s_lo, s_hi), cfg.k)
+    farm.build_proposals(mem, farm.ProposalNet(scene.d, max_batch=4096, seed=3), 32)
+    pr = _gpu.query_topk(mem, ws, qb, cfg.k, dtype=dtype, with_cert=True, method=farm.PROPOSAL)
+    for a, b in zip(pr, bd):
+        np.testing.assert_array_equal(a, b)
+    ex = _gpu.query_topk(mem, ws, qb, cfg.k, dtype=dtype, with_cert=True, method=farm.EXHAUSTIVE)
+    # the exhaustive precision form rescores the top 4K by upper bound: certified rows are exact;
+    # FP8's looser bounds leave most rows uncertified (flagged, not wrong), so there recall is checked
+    cert_rows = [qq for qq in range(qb.q) if ex[4][qq] == 1]
+    if dtype == 2:
+        rec = np.mean([len(set(map(int, ex[0][qq])) & set(map(int, bd[0][qq]))) / cfg.k for qq in range(qb.q)])
+        assert rec >= 0.95, rec
+    else:
+        assert len(cert_rows) >= qb.q - 2, ex[4]
+    _check_topk_rows(scene, ex[0], ex[1], (s64[cert_rows], s_lo[cert_rows], s_hi[cert_rows]), cfg.k,
+                     rows=cert_rows)
+    if dtype == 0:
+        for a, b in zip(bd[:4], ex[:4]):
+            np.testing.assert_array_equal(a, b)
+
+
+def test_between_degenerate_and_invalid(farm):
+    """Two or three objects (no pair of distinct anchors besides the target in
+    the first), a query with only a Between; FARM_BETWEEN without its FARM_AND
+    slot (or the reverse) is refused."""
+    import torch
+    from tests import _gpu
+    for n in (2, 3, 5):
+        scene = _random_scene(n, 8, seed=300 + n)
+        rng = np.random.default_rng(n)
+        qb = QueryBatch(target=rng.standard_normal((2, 8)).astype(np.float32),
+                        target_cls=np.array([-1, 0], np.int32), rel_off=np.array([0, 2, 5], np.int32),
+                        rel_pred=np.array([12, 13, 0, 12, 13], np.int32),
+                        rel_anchor=rng.standard_normal((5, 8)).astype(np.float32), planted=np.zeros(2, np.int64))
+        mem, ws, full = _check_full(farm, scene, qb, f"between n={n}")
+        _topk_against_full(farm, mem, ws, scene, qb, full, 10, f"between n={n}")
+    target, anchors = _gpu.query_tensors(qb)
+    out = torch.empty((2, scene.n), dtype=torch.float32, device="cuda")
+    for preds in ([12, 0, 0, 12, 13], [13, 12, 0, 12, 13], [12, 13, 0, 13, 12]):
+        with pytest.raises(farm.FarmError):
+            farm.score_query(mem, ws, target, None, qb.rel_off, np.array(preds, np.int32), anchors, out)
 
 
 def test_mid_config_topk_all_queries(farm):
