@@ -17,10 +17,11 @@
 // 16-byte fragment reads of 32 consecutive rows hit distinct banks, and the
 // next slab is fetched into registers while the current one is consumed.
 // Each 32-byte slice of a slab feeds the MFMA pipe from two lane halves of 16
-// bytes: four v_mfma_f32_32x32x2f32, one v_mfma_f32_32x32x16_bf16 or two
-// v_mfma_f32_32x32x16_fp8_fp8 per slice.  Lane half h supplies bytes 16h..16h+15
-// of the slice to both operands, a fixed permutation of the K order shared by
-// A and B (the sum is unchanged).
+// bytes: four v_mfma_f32_32x32x2f32 or one v_mfma_f32_32x32x16_bf16 per slice.
+// Lane half h supplies bytes 16h..16h+15 of the slice to both operands, a fixed
+// permutation of the K order shared by A and B (the sum is unchanged).  FP8
+// takes 64-byte chunks instead, one gfx950 32x32x64 MFMA each (lane half h:
+// bytes 32h..32h+31), twice the K per instruction of the 32x32x16 FP8 form.
 #include "farm_internal.h"
 
 namespace farm {
@@ -28,6 +29,7 @@ namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int intx8 __attribute__((ext_vector_type(8)));
 
 enum { kT32 = 0, kTBF16 = 1, kTFP8 = 2 };
 
@@ -63,6 +65,16 @@ __device__ inline void tile_of_block(int64_t& tm, int64_t& tn, int64_t tiles_m, 
   tn = in / gm;
 }
 
+// FP8 (OCP e4m3) 32x32x64 MFMA of gfx950 on 32 bytes of K per lane: the
+// block-scaled form with unit scales (E8M0 127 = 2^0) -- the per-row scales are
+// applied in the epilogue.  Twice the K of 32x32x16 per instruction.
+__device__ inline void mfma_fp8_64(floatx16& acc, const uint4& a_lo, const uint4& a_hi, const uint4& b_lo,
+                                   const uint4& b_hi) {
+  const intx8 a = {(int)a_lo.x, (int)a_lo.y, (int)a_lo.z, (int)a_lo.w, (int)a_hi.x, (int)a_hi.y, (int)a_hi.z, (int)a_hi.w};
+  const intx8 b = {(int)b_lo.x, (int)b_lo.y, (int)b_lo.z, (int)b_lo.w, (int)b_hi.x, (int)b_hi.y, (int)b_hi.z, (int)b_hi.w};
+  acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, acc, 0, 0, 0, 127, 0, 127);
+}
+
 template <int T>
 __device__ inline void mfma_slice(floatx16& acc, const uint4& a, const uint4& b) {
   if constexpr (T == kT32) {
@@ -96,7 +108,7 @@ __device__ inline uint16_t to_bf16(float f) {
 }
 
 template <int T, int EPI = kEpiSim>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_sim_gemm(const uint8_t* __restrict__ A, const uint8_t* __restrict__ B,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(T == kTFP8 ? 2 : 3))) void k_sim_gemm(const uint8_t* __restrict__ A, const uint8_t* __restrict__ B,
                                                   int64_t M, int64_t N, int64_t K_bytes, int64_t lda_bytes,
                                                   int64_t ldb_bytes, void* __restrict__ Cv, int64_t ldc,
                                                   const float* __restrict__ a_scale,
@@ -180,16 +192,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     rb0 = b0p[kn]; rb1 = b1p[kn]; rb2 = b2p[kn]; rb3 = b3p[kn];
     // keep the next slab's loads in flight under this slab's MFMAs
     __builtin_amdgcn_sched_barrier(0);
+    if constexpr (T == kTFP8) {
+      // two 64-byte K chunks per slab; lane half h takes bytes 32h..32h+31 of a chunk for both operands
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const uint4 a_0 = As[(wm * 64 + r) * kRowU4 + 2 * s + h];
-      const uint4 a_1 = As[(wm * 64 + 32 + r) * kRowU4 + 2 * s + h];
-      const uint4 b_0 = Bs[(wn * 64 + r) * kRowU4 + 2 * s + h];
-      const uint4 b_1 = Bs[(wn * 64 + 32 + r) * kRowU4 + 2 * s + h];
-      mfma_slice<T>(acc[0][0], a_0, b_0);
-      mfma_slice<T>(acc[0][1], a_0, b_1);
-      mfma_slice<T>(acc[1][0], a_1, b_0);
-      mfma_slice<T>(acc[1][1], a_1, b_1);
+      for (int c = 0; c < 2; ++c) {
+        const int u = 4 * c + 2 * h;
+        const uint4 b0l = Bs[(wn * 64 + r) * kRowU4 + u], b0h = Bs[(wn * 64 + r) * kRowU4 + u + 1];
+        const uint4 b1l = Bs[(wn * 64 + 32 + r) * kRowU4 + u], b1h = Bs[(wn * 64 + 32 + r) * kRowU4 + u + 1];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const uint4 al = As[(wm * 64 + 32 * i + r) * kRowU4 + u], ah = As[(wm * 64 + 32 * i + r) * kRowU4 + u + 1];
+          mfma_fp8_64(acc[i][0], al, ah, b0l, b0h);
+          mfma_fp8_64(acc[i][1], al, ah, b1l, b1h);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const uint4 a_0 = As[(wm * 64 + r) * kRowU4 + 2 * s + h];
+        const uint4 a_1 = As[(wm * 64 + 32 + r) * kRowU4 + 2 * s + h];
+        const uint4 b_0 = Bs[(wn * 64 + r) * kRowU4 + 2 * s + h];
+        const uint4 b_1 = Bs[(wn * 64 + 32 + r) * kRowU4 + 2 * s + h];
+        mfma_slice<T>(acc[0][0], a_0, b_0);
+        mfma_slice<T>(acc[0][1], a_0, b_1);
+        mfma_slice<T>(acc[1][0], a_1, b_0);
+        mfma_slice<T>(acc[1][1], a_1, b_1);
+      }
     }
     __syncthreads();
     if (kt + 1 < nk) {
