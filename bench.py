@@ -85,7 +85,8 @@ def parse(argv=None):
     p.add_argument("--form", default="bf16", choices=["f32", "bf16", "fp8"])
     p.add_argument("--rescore-mult", type=int, default=4)
     p.add_argument("--method", default="proposal", choices=["exhaustive", "bounded", "proposal"])
-    p.add_argument("--train-scenes", type=int, default=8, help="training scenes of the proposal network")
+    p.add_argument("--train-scenes", type=int, default=32,
+                   help="training scenes of the proposal network (seeds 1000.., held out from the benchmark scene)")
     p.add_argument("--train-steps", type=int, default=600)
     p.add_argument("--list-m", type=int, default=256, help="anchors per (object, predicate) list")
     p.add_argument("--k", type=int, default=10)
@@ -93,6 +94,9 @@ def parse(argv=None):
                    help="predicates the queries draw from: the workload's five (Near..RightOf), all nine pairwise "
                         "ones (+ NextTo, InFrontOf, Behind, On) or every one (+ Closest, Farthest, Inside)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-value-lists", dest="value_lists", action="store_false",
+                   help="skip the non-learned baseline (lists ranked by exact predicate value)")
+    p.add_argument("--latency-queries", type=int, default=256, help="batch-1 requests timed for latency_ms")
     p.add_argument("--cpu-sample", type=int, default=0, help="queries in the CPU-oracle sample (0 = auto)")
     p.add_argument("--serving", action="store_true",
                    help="run the request loop over 16 resident scenes instead (p50/p99 latency per arrival rate)")
@@ -219,10 +223,19 @@ def main():
     roofline = dominant_roofline(phases, scene, qb, args, cfg, proposal_info)
     phase_ms = {p: round(v[0] / max(v[1], 1), 3) for p, v in phases.items() if v[1]}
 
+    # per-request latency: closed-loop batch-1 calls of the same form on the same scene
+    req_lat = request_latency(farm, mem, qb, target, anchors, k, dtype, method, args) if args.latency_queries else None
+
     cpu = None
     recall = None
+    errors = None
     if not args.no_cpu_baseline:
-        cpu, recall = cpu_baseline(scene, qb, oid, osc, k, args.cpu_sample)
+        cpu, recall, sample_rows, s64 = cpu_baseline(scene, qb, oid, osc, k, args.cpu_sample)
+        errors = dtype_errors(farm, mem, ws, scene, qb, sample_rows, s64, k, method)
+
+    baseline_lists = None
+    if method == farm.PROPOSAL and args.value_lists:
+        baseline_lists = value_list_baseline(farm, mem, ws, step, args)
 
     lat = np.asarray(times) * 1e3
     out = {
@@ -244,16 +257,19 @@ def main():
                    "form": args.form, "method": args.method, "global_batch": qb.q, "parallelism": "none (1 GPU)",
                    "predicates": {"five": "Near, Above, Below, LeftOf, RightOf", "all": "all nine pairwise",
                                   "every": "all twelve (pairwise + Closest, Farthest, Inside)"}[args.preds]},
-        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
-                       "what": "whole-batch latency of one step"},
+        "latency_ms": req_lat,
+        "batch_latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                             "p99": round(float(np.percentile(lat, 99)), 3), "what": "one step (the whole batch)"},
         "phase_ms": phase_ms,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "recall_at_10_vs_oracle": recall,
+        "score_error_vs_oracle": errors,
         "recall_at_10_vs_exact_f32": recall_exact,
         "certified_queries": certified,
         "form": form_name(args),
         ("bounded" if method == farm.BOUNDED else "proposal"): proposal_info,
+        "value_lists_baseline": baseline_lists,
     }
     print(json.dumps(out), flush=True)
 
@@ -475,16 +491,21 @@ def dominant_roofline(phases, scene, qb, args, cfg, proposal_info):
     if dominant == "rescore" and args.method == "proposal" and info:
         in_lds = bool(info.get("pass_in_lds"))
         kernel = "k_rescore_subset_lds" if in_lds else "k_rescore_terms<subset>"
-        # proposal pass: each relation's similarity row once (4 B per object); per term the
-        # list (4 B index + 4 B cached value per entry; + a 4 B similarity gather from global
-        # memory when the row is not staged in LDS); per FP32 dot product (semantic-set
-        # members and bound survivors) one descriptor row (4 B x D)
-        nbytes = (4.0 * R * n + float(terms) * m * (8.0 if in_lds else 12.0) + float(dots) * 4.0 * scene.d)
+        # proposal pass, algorithmic bytes: each relation's similarity row once (4 B per
+        # object) and, per evaluated term, its list (4 B anchor index + 4 B cached predicate
+        # value per entry; + a 4 B similarity gather when the row is not staged in LDS).
+        # The FP32 dot products of unresolved anchors read descriptor rows (4 B x D each)
+        # that are re-read across terms from the caches: reported beside, not counted.
+        nbytes = 4.0 * R * n + float(terms) * m * (8.0 if in_lds else 12.0)
+        dot_bytes = float(dots) * 4.0 * scene.d
         achieved = nbytes / avg_s / 1e9
         return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                 "traffic": recorded_traffic(kernel, cfg.name), "avg_launch_ms": round(avg_s * 1e3, 3),
-                "algorithmic_bytes_per_launch": nbytes}
+                "algorithmic_bytes_per_launch": nbytes,
+                "bytes_detail": {"relation_rows": 4.0 * R * n, "list_entries": float(terms) * m * 8.0,
+                                 "terms": int(terms), "list_m": int(m),
+                                 "fp32_dot_descriptor_bytes_not_counted": dot_bytes, "fp32_dots": int(dots)}}
     # full anchor scans of candidate terms (the fallback of the proposal method, or every
     # candidate term of the bound-pruned method): pair evaluations on the ALU
     pairwise = [FLOP_PER_PAIR[int(p)] for p in qb.rel_pred if int(p) in FLOP_PER_PAIR]
@@ -498,6 +519,105 @@ def dominant_roofline(phases, scene, qb, args, cfg, proposal_info):
     return {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3),
             "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
             "traffic": None, "avg_launch_ms": round(avg_s * 1e3, 3), "pair_evals_per_launch": n_terms * n}
+
+
+def request_latency(farm, mem, qb, target, anchors, k, dtype, method, args):
+    """Per-request latency: one query per farm_query_topk call, the next after
+    the previous result (host wall time of the call plus its synchronisation),
+    on the benchmark's scene and form; p50/p99 over args.latency_queries
+    requests after 16 untimed ones."""
+    import torch
+    ws1 = farm.Workspace(mem, 1, farm.FARM_MAX_REL, 64)
+    oid = torch.empty((1, k), dtype=torch.int32, device=target.device)
+    osc = torch.empty((1, k), dtype=torch.float32, device=target.device)
+    lat = []
+    nq = min(qb.q, args.latency_queries + 16)
+    for i in range(nq):
+        r0, r1 = int(qb.rel_off[i]), int(qb.rel_off[i + 1])
+        ro = np.array([0, r1 - r0], np.int32)
+        a = time.perf_counter()
+        farm.query_topk(mem, ws1, target[i:i + 1], qb.target_cls[i:i + 1], ro, qb.rel_pred[r0:r1], anchors[r0:r1], k,
+                        oid, osc, dtype=dtype, method=method)
+        torch.cuda.synchronize()
+        if i >= 16:
+            lat.append(time.perf_counter() - a)
+    v = np.asarray(lat) * 1e3
+    del ws1
+    return {"p50": round(float(np.percentile(v, 50)), 4), "p99": round(float(np.percentile(v, 99)), 4),
+            "requests": len(lat), "what": "per request: closed-loop batch-1 farm_query_topk calls on the benchmark "
+                                          "scene (host wall time incl. synchronisation)"}
+
+
+def dtype_errors(farm, mem, ws, scene, qb, rows, s64, k, method):
+    """Per similarity dtype, on the CPU sample's queries against the FP64
+    oracle: the similarity GEMM's own s_sem (before any FP32 rescoring: max and
+    RMS absolute error over all sample rows x N objects), and the returned TopK
+    scores (max and median relative error, Recall@K of the ids)."""
+    import oracle
+    import torch
+    from synth import QueryBatch
+    sub = qb.subset(rows)
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    target, anchors = t(sub.target), t(sub.rel_anchor)
+    idx_of = {int(v): i for i, v in enumerate(scene.ids)}
+    sem = QueryBatch(sub.target, sub.target_cls, np.zeros(sub.q + 1, np.int32), np.zeros(0, np.int32),
+                     np.zeros((0, sub.target.shape[1]), np.float32), sub.planted)
+    sem64 = oracle.score(scene, sem)  # no relations: the score is s_sem
+    sim = torch.empty((sub.q, scene.n), dtype=torch.float32, device=dev)
+    out = {}
+    for name, dt in (("f32", farm.F32), ("bf16", farm.BF16), ("fp8", farm.FP8_E4M3)):
+        oid = torch.empty((sub.q, k), dtype=torch.int32, device=dev)
+        osc = torch.empty((sub.q, k), dtype=torch.float32, device=dev)
+        farm.query_topk(mem, ws, target, sub.target_cls, sub.rel_off, sub.rel_pred, anchors, k, oid, osc, dtype=dt,
+                        method=method)
+        torch.cuda.synchronize()
+        ids, sc = oid.cpu().numpy().view(np.uint32), osc.cpu().numpy().astype(np.float64)
+        rel, hits = [], []
+        for i in range(sub.q):
+            want = set(int(x) for x in scene.ids[oracle.topk(s64[i], scene.ids, k)])
+            hits.append(len(want & set(int(x) for x in ids[i])) / k)
+            for g, v in zip(ids[i], sc[i]):
+                ref = s64[i, idx_of[int(g)]]
+                rel.append(abs(v - ref) / max(abs(ref), 1e-30))
+        farm.similarity(mem, ws, target, sub.target_cls, sim, dtype=dt)
+        torch.cuda.synchronize()
+        e = sim.cpu().numpy().astype(np.float64) - sem64
+        out[name] = {"gemm_sim_max_abs_err": float(np.max(np.abs(e))),
+                     "gemm_sim_rms_err": float(np.sqrt(np.mean(e * e))),
+                     "max_rel_err": float(np.max(rel)), "median_rel_err": float(np.median(rel)),
+                     "recall_at_k_vs_oracle": float(np.mean(hits)), "queries": int(sub.q)}
+        log(f"[bench] {name}: GEMM s_sem vs FP64 oracle max abs err {out[name]['gemm_sim_max_abs_err']:.2e}; "
+            f"returned scores max rel err {out[name]['max_rel_err']:.2e}, "
+            f"recall {out[name]['recall_at_k_vs_oracle']:.4f}")
+    return out
+
+
+def value_list_baseline(farm, mem, ws, step, args):
+    """The same form with non-learned lists: per (object, predicate) the M
+    anchors of largest exact predicate value (farm_build_proposals_by_value).
+    Replaces the memory's lists; measured after every other leg."""
+    import torch
+    t0 = time.time()
+    farm.build_proposals_by_value(mem, args.list_m)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    ws.proposal_stats(reset=True)
+    a = time.perf_counter()
+    steps = max(3, args.steps // 2)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - a) / steps * 1e3
+    checked, fell, dots, fb_dots = ws.proposal_stats(reset=True)
+    res = {"ms_per_step": round(ms, 3), "queries_per_s": None, "fallback_rate": round(fell / max(checked, 1), 5),
+           "fp32_dots_per_step": dots // steps, "list_build_s": round(build_s, 3), "steps": steps,
+           "what": "lists of the M anchors of largest exact predicate value (no network), same certificate"}
+    log(f"[bench] value-ranked lists: {ms:.3f} ms/step, fallback rate {res['fallback_rate']}")
+    return res
 
 
 def form_name(args):
@@ -514,12 +634,15 @@ def form_name(args):
 
 
 def cpu_baseline(scene, qb, oid, osc, k, sample):
-    """Time the FP64 oracle (plain exhaustive scoring + TopK) on a sample of the batch."""
+    """Time the FP64 oracle (plain exhaustive scoring + TopK) on a sample of
+    the batch, with every host thread (the oracle parallelises over the objects
+    of a query), and one query with a single thread."""
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    m = sample or max(4, min(16, threads))
-    sub = qb.subset(range(m))
     oracle._load()
+    threads = oracle.threads()
+    m = sample or 16
+    rows = list(range(m))
+    sub = qb.subset(rows)
     log(f"[bench] cpu baseline: oracle on {m} queries, {threads} threads")
     a = time.perf_counter()
     s64 = oracle.score(scene, sub)
@@ -528,10 +651,11 @@ def cpu_baseline(scene, qb, oid, osc, k, sample):
     ids = oid[:m].cpu().numpy().view(np.uint32)
     hits = [len(set(int(x) for x in ids[i]) & set(int(x) for x in scene.ids[order[i]])) / k for i in range(m)]
     log(f"[bench] cpu baseline: {secs:.1f}s, recall@{k} on the sample {np.mean(hits):.4f}")
-    # the first query alone: the oracle parallelises over queries, so one thread does all of it
+    oracle.set_threads(1)
     a = time.perf_counter()
     oracle.score(scene, qb.subset(range(1)))
     secs1 = time.perf_counter() - a
+    oracle.set_threads(threads)
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -539,10 +663,12 @@ def cpu_baseline(scene, qb, oid, osc, k, sample):
     except OSError:
         pass
     log(f"[bench] cpu baseline, one thread: {secs1:.1f}s for one query")
-    return ({"value": round(m / secs, 4), "unit": "queries/s", "cores": min(threads, m), "kind": "oracle",
+    return ({"value": round(m / secs, 4), "unit": "queries/s", "cores": threads, "kind": "oracle",
              "sample": f"first {m} queries of the batch, full exhaustive FP64 scoring of all {scene.n} objects + TopK",
-             "seconds": round(secs, 2), "one_thread_seconds_per_query": round(secs1, 2), "cpu": model},
-            {"value": float(np.mean(hits)), "queries": m, "what": "|TopK_gpu & TopK_oracle| / K on the CPU sample"})
+             "seconds": round(secs, 2), "one_thread_seconds_per_query": round(secs1, 2), "cpu": model,
+             "nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0))},
+            {"value": float(np.mean(hits)), "queries": m, "what": "|TopK_gpu & TopK_oracle| / K on the CPU sample"},
+            rows, s64)
 
 
 if __name__ == "__main__":

@@ -100,7 +100,11 @@ typedef enum {
                                 non-finite or zero-norm vector, duplicate id */
   FARM_ERR_OOM = -2,         /* device allocation failed or exceeds a budget */
   FARM_ERR_HIP = -3,         /* a HIP runtime call failed */
-  FARM_ERR_UNSUPPORTED = -4  /* valid request outside what this build serves */
+  FARM_ERR_UNSUPPORTED = -4, /* valid request outside what this build serves */
+  FARM_ERR_BUSY = -5         /* the object is in use: a workspace entered by a
+                                second host thread during a call on it, or a
+                                memory freed while workspaces or servers still
+                                use it; nothing was done, retry later */
 } farm_status;
 
 typedef enum { FARM_F32 = 0, FARM_BF16 = 1, FARM_FP8_E4M3 = 2 } farm_dtype;
@@ -160,7 +164,9 @@ FARM_API farm_status farm_build_memory(int64_t n, int32_t d, const float* desc, 
                               float view_right_x, float view_right_y, uint32_t flags, void* stream,
                               farm_memory** out);
 
-/* Release a memory handle (synchronises the device first). NULL is a no-op. */
+/* Release a memory handle (synchronises the device first). NULL is a no-op.
+   FARM_ERR_BUSY while workspaces created on it or servers it was added to
+   have not been freed; the handle then stays valid. */
 FARM_API farm_status farm_free_memory(farm_memory* mem);
 
 /* n, d and the device bytes the handle holds (any out pointer may be NULL). */
@@ -172,8 +178,11 @@ FARM_API farm_status farm_memory_info(const farm_memory* mem, int64_t* n, int32_
  * to max_q queries, max_rel relations (all queries together) and TopK size
  * max_k (1..FARM_MAX_K; with reduced-precision rescoring the candidate count
  * rescore_mult*k must fit too) per call.  A workspace serves one stream at a
- * time: calls that share it must be ordered on one stream.  Allocates device
- * memory and one pinned host staging block; free with farm_workspace_free.
+ * time: calls that share it must be ordered on one stream.  It serves one host
+ * thread at a time too: a call entered while another call on the same
+ * workspace runs returns FARM_ERR_BUSY without doing anything.  Allocates
+ * device memory and one pinned host staging block; free with
+ * farm_workspace_free.
  */
 FARM_API farm_status farm_workspace_create(const farm_memory* mem, int32_t max_q, int32_t max_rel, int32_t max_k,
                                   farm_workspace** out);
@@ -218,6 +227,22 @@ FARM_API farm_status farm_score_query(const farm_memory* mem, farm_workspace* ws
                              const float* target, const int32_t* target_cls, const int32_t* rel_off,
                              const int32_t* rel_pred, const float* rel_anchor, float* scores,
                              float* rel_terms, uint32_t* rel_anchor_id, void* stream);
+
+/*
+ * The target similarity s_sem alone, as the similarity GEMM of `dtype`
+ * produces it: out[j][i] = kappa_i * max(0, cos(target_j, u_i)) with the
+ * class factor of Appendix "Retrieval Details", step 5 (kappa = 0.3 when the
+ * object's class differs from target_cls[j], else 1; the target similarity of
+ * its step 3, one embedding channel).  FARM_BF16 / FARM_FP8_E4M3 return the
+ * reduced-precision estimate the precision form starts from (before any FP32
+ * rescoring), for measuring its error.
+ *   q, d, target, target_cls   as in farm_score_query (no relations)
+ *   dtype        farm_dtype; UNSUPPORTED when the memory lacks that copy
+ *   out          device [q][n] FP32
+ */
+FARM_API farm_status farm_similarity(const farm_memory* mem, farm_workspace* ws, int32_t q, int32_t d,
+                                     const float* target, const int32_t* target_cls, int32_t dtype, float* out,
+                                     void* stream);
 
 /*
  * TopK of precomputed score rows: the K highest-scoring candidates, the

@@ -20,7 +20,7 @@ from ._lib import (FARM_BUILD_BF16, FARM_BUILD_FP8, FARM_MAX_K, FARM_MAX_REL, FA
                    FARTHEST, INSIDE, BETWEEN, AND, NUM_PRED, NUM_PROP_PRED, FarmError, lib_path)
 
 __all__ = [
-    "Memory", "Workspace", "ProposalNet", "Server", "build_proposals", "build_proposals_by_value", "get_proposals", "score_query", "topk", "query_topk", "query_topk_static", "workspace_estimate", "FarmError",
+    "Memory", "Workspace", "ProposalNet", "Server", "build_proposals", "build_proposals_by_value", "get_proposals", "score_query", "similarity", "topk", "query_topk", "query_topk_static", "workspace_estimate", "FarmError",
     "FARM_BUILD_BF16", "FARM_BUILD_FP8", "FARM_MAX_K", "FARM_MAX_REL", "FARM_NO_ID", "F32", "BF16",
     "FP8_E4M3", "EXHAUSTIVE", "BOUNDED", "PROPOSAL", "OPT_GLOBAL_PROPOSAL_PASS", "NEAR", "ABOVE", "BELOW", "LEFT_OF", "RIGHT_OF", "NEXT_TO", "IN_FRONT_OF", "BEHIND", "ON", "CLOSEST", "FARTHEST", "INSIDE", "BETWEEN", "AND", "NUM_PRED",
     "NUM_PROP_PRED", "lib_path",
@@ -94,8 +94,10 @@ class Memory:
         return bool(v.value)
 
     def close(self):
+        """Free the device memory.  Raises FarmError (FARM_ERR_BUSY) while
+        workspaces or servers still use it; the handle then stays valid."""
         if getattr(self, "_h", None) is not None:
-            _lib.L.farm_free_memory(self._h)
+            _lib.check(_lib.L.farm_free_memory(self._h))
             self._h = None
 
     def __del__(self):
@@ -177,6 +179,15 @@ def score_query(mem: Memory, ws: Workspace, target, target_cls, rel_off, rel_pre
                                        _ptr(rel_anchor) if rel_anchor is not None and rel_anchor.numel() else None,
                                        _ptr(scores), _ptr(rel_terms), _ptr(rel_anchor_id), _stream(stream)))
     del tc, ro, rp
+
+
+def similarity(mem: Memory, ws: Workspace, target, target_cls, out, dtype: int = F32, stream=None):
+    """farm_similarity: the similarity GEMM's s_sem rows in `dtype` into out [q][n]."""
+    tc, ptc = _host_i32(target_cls)
+    q, d = int(target.shape[0]), int(target.shape[1])
+    _lib.check(_lib.L.farm_similarity(mem.handle, ws.handle, q, d, _ptr(target), ptc, int(dtype), _ptr(out),
+                                      _stream(stream)))
+    del tc
 
 
 def topk(mem: Memory, ws: Workspace, scores, k: int, out_id, out_score, out_index=None, stream=None):

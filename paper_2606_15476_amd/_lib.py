@@ -8,7 +8,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _PATH = os.path.join(_HERE, "libfarm.so")
 
-FARM_OK, FARM_ERR_INVALID_ARG, FARM_ERR_OOM, FARM_ERR_HIP, FARM_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
+FARM_OK, FARM_ERR_INVALID_ARG, FARM_ERR_OOM, FARM_ERR_HIP, FARM_ERR_UNSUPPORTED, FARM_ERR_BUSY = 0, -1, -2, -3, -4, -5
 F32, BF16, FP8_E4M3 = 0, 1, 2
 EXHAUSTIVE, BOUNDED, PROPOSAL = 0, 1, 2
 OPT_GLOBAL_PROPOSAL_PASS = 1
@@ -24,7 +24,7 @@ FARM_BUILD_BF16, FARM_BUILD_FP8 = 0x1, 0x2
 
 EXPORTS = (
     "farm_build_memory", "farm_free_memory", "farm_memory_info", "farm_workspace_create", "farm_workspace_free",
-    "farm_workspace_bytes", "farm_workspace_estimate", "farm_score_query", "farm_topk", "farm_query_topk", "farm_query_topk_static",
+    "farm_workspace_bytes", "farm_workspace_estimate", "farm_score_query", "farm_similarity", "farm_topk", "farm_query_topk", "farm_query_topk_static",
     "farm_workspace_status", "farm_last_error", "farm_version", "farm_workspace_set_timing",
     "farm_workspace_timings", "farm_mlp_create", "farm_mlp_free", "farm_mlp_shape", "farm_mlp_get_weights",
     "farm_mlp_get_grads", "farm_mlp_get_batch", "farm_mlp_set_weights", "farm_mlp_table_logits", "farm_mlp_inputs", "farm_mlp_logits", "farm_mlp_step",
@@ -36,7 +36,7 @@ MLP_HIDDEN = 256
 PHASES = ("normalize", "gemm", "pair", "topk", "rescore", "explain", "propose", "fallback", "select")
 
 _STATUS = {FARM_ERR_INVALID_ARG: "invalid argument", FARM_ERR_OOM: "out of memory", FARM_ERR_HIP: "HIP error",
-           FARM_ERR_UNSUPPORTED: "unsupported"}
+           FARM_ERR_UNSUPPORTED: "unsupported", FARM_ERR_BUSY: "busy"}
 
 
 class FarmError(RuntimeError):
@@ -73,6 +73,7 @@ def _declare(lib):
         "farm_workspace_bytes": [P, ctypes.POINTER(sz)],
         "farm_workspace_estimate": [P, i32, i32, i32, ctypes.POINTER(sz)],
         "farm_score_query": [P, P, i32, i32, P, P, P, P, P, P, P, P, P],
+        "farm_similarity": [P, P, i32, i32, P, P, i32, P, P],
         "farm_topk": [P, P, P, i32, i32, P, P, P, P],
         "farm_query_topk": [P, P, i32, i32, P, P, P, P, P, ctypes.POINTER(ScoreOpts), i32, P, P, P, P, P],
         "farm_query_topk_static": [P, i32, i32, P, P, P, P, P, ctypes.POINTER(ScoreOpts), i32, P, P, P, P, P],

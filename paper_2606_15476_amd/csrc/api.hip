@@ -82,6 +82,25 @@ void free_all(std::vector<void*>& allocs) {
     if (e_ != hipSuccess) return hip_fail(e_, what); \
   } while (0)
 
+// Marks a workspace as inside a library call for the claim's lifetime; a
+// second host thread that enters a call on the same workspace meanwhile is
+// turned away with FARM_ERR_BUSY instead of racing on its host state.
+struct WorkspaceClaim {
+  farm_workspace* ws;
+  bool ok;
+  explicit WorkspaceClaim(farm_workspace* w) : ws(w), ok(!w || !w->in_call.exchange(true, std::memory_order_acquire)) {}
+  ~WorkspaceClaim() {
+    if (ws && ok) ws->in_call.store(false, std::memory_order_release);
+  }
+};
+
+#define FARM_CLAIM(ws_)                                                                  \
+  WorkspaceClaim claim_(ws_);                                                            \
+  if (!claim_.ok) {                                                                      \
+    set_error("workspace is in use by another call (one caller at a time)");             \
+    return FARM_ERR_BUSY;                                                                \
+  }
+
 // The workspace's device buffers, in one place for the three ways a workspace
 // is laid out: hipMalloc per buffer (farm_workspace_create), a byte count
 // (farm_workspace_estimate) and bump allocation inside the library's static
@@ -714,6 +733,10 @@ farm_status farm_build_memory(int64_t n, int32_t d, const float* desc, const flo
 
 farm_status farm_free_memory(farm_memory* mem) {
   if (!mem) return FARM_OK;
+  if (const int32_t u = mem->users.load(std::memory_order_acquire)) {
+    set_error("memory still has %d workspace(s) or server registration(s); free those first", u);
+    return FARM_ERR_BUSY;
+  }
   DeviceGuard g(mem->device);
   (void)hipDeviceSynchronize();
   free_all(mem->allocs);
@@ -771,6 +794,7 @@ farm_status farm_workspace_create(const farm_memory* mem, int32_t max_q, int32_t
     if (e != hipSuccess) return fail(hip_fail(e, "status clear"));
     e = hipMemset(ws->prop_stats, 0, 4 * sizeof(unsigned long long));
     if (e != hipSuccess) return fail(hip_fail(e, "counter clear"));
+    mem->users.fetch_add(1, std::memory_order_acq_rel);
     *out = ws;
     return FARM_OK;
   } catch (...) {
@@ -781,12 +805,14 @@ farm_status farm_workspace_create(const farm_memory* mem, int32_t max_q, int32_t
 
 farm_status farm_workspace_set_timing(farm_workspace* ws, int32_t enable) {
   if (!ws) { set_error("null workspace"); return FARM_ERR_INVALID_ARG; }
+  FARM_CLAIM(ws);
   ws->timing = enable != 0;
   return FARM_OK;
 }
 
 farm_status farm_workspace_timings(farm_workspace* ws, double* ms, int64_t* count, int32_t reset) {
   if (!ws) { set_error("null workspace"); return FARM_ERR_INVALID_ARG; }
+  FARM_CLAIM(ws);
   DeviceGuard g(ws->device);
   for (auto& p : ws->pending) {
     FARM_HIP(hipEventSynchronize(p.b), "timer synchronize");
@@ -811,6 +837,11 @@ farm_status farm_workspace_timings(farm_workspace* ws, double* ms, int64_t* coun
 
 farm_status farm_workspace_free(farm_workspace* ws) {
   if (!ws) return FARM_OK;
+  if (ws->in_call.load(std::memory_order_acquire)) {
+    set_error("workspace is in use by another call");
+    return FARM_ERR_BUSY;
+  }
+  ws->mem->users.fetch_sub(1, std::memory_order_acq_rel);
   DeviceGuard g(ws->device);
   (void)hipDeviceSynchronize();
   for (auto& p : ws->pending) {
@@ -840,6 +871,7 @@ farm_status farm_proposal_pass_form(const farm_memory* mem, int32_t dtype, int32
 
 farm_status farm_workspace_proposal_stats(farm_workspace* ws, int64_t* stats, int32_t reset, void* stream) {
   if (!ws || !stats) { set_error("null workspace or output"); return FARM_ERR_INVALID_ARG; }
+  FARM_CLAIM(ws);
   DeviceGuard g(ws->device);
   hipStream_t s = (hipStream_t)stream;
   unsigned long long h[4] = {0, 0, 0, 0};
@@ -855,6 +887,7 @@ farm_status farm_workspace_proposal_stats(farm_workspace* ws, int64_t* stats, in
 
 farm_status farm_workspace_status(farm_workspace* ws, void* stream) {
   if (!ws) { set_error("null workspace"); return FARM_ERR_INVALID_ARG; }
+  FARM_CLAIM(ws);
   DeviceGuard g(ws->device);
   hipStream_t s = (hipStream_t)stream;
   int h = 0;
@@ -875,7 +908,8 @@ farm_status farm_score_query(const farm_memory* mem, farm_workspace* ws, int32_t
                              const float* rel_anchor, float* scores, float* rel_terms, uint32_t* rel_anchor_id,
                              void* stream) {
   try {
-      int32_t R = 0;
+    FARM_CLAIM(ws);
+    int32_t R = 0;
     FARM_TRY(check_queries(mem, ws, q, d, target, rel_off, rel_pred, rel_anchor, &R));
     if (q > 0 && !scores) { set_error("scores is NULL"); return FARM_ERR_INVALID_ARG; }
     if (q == 0) return FARM_OK;
@@ -896,10 +930,44 @@ farm_status farm_score_query(const farm_memory* mem, farm_workspace* ws, int32_t
   }
 }
 
+farm_status farm_similarity(const farm_memory* mem, farm_workspace* ws, int32_t q, int32_t d, const float* target,
+                            const int32_t* target_cls, int32_t dtype, float* out, void* stream) {
+  try {
+    FARM_CLAIM(ws);
+    if (dtype != FARM_F32 && dtype != FARM_BF16 && dtype != FARM_FP8_E4M3) {
+      set_error("unknown dtype %d", dtype);
+      return FARM_ERR_INVALID_ARG;
+    }
+    std::vector<int32_t> rel_off((size_t)std::max(q, 0) + 1, 0);
+    int32_t R = 0;
+    FARM_TRY(check_queries(mem, ws, q, d, target, rel_off.data(), nullptr, nullptr, &R));
+    if (q == 0) return FARM_OK;
+    if (!out) { set_error("out is NULL"); return FARM_ERR_INVALID_ARG; }
+    if ((dtype == FARM_BF16 && !mem->dn_bf16) || (dtype == FARM_FP8_E4M3 && !mem->dn_fp8)) {
+      set_error("the memory was built without the %s copy", dtype == FARM_BF16 ? "BF16" : "FP8");
+      return FARM_ERR_UNSUPPORTED;
+    }
+    DeviceGuard g(mem->device);
+    hipStream_t s = (hipStream_t)stream;
+    MetaView meta;
+    FARM_TRY(stage_meta(ws, q, 0, target_cls, rel_off.data(), nullptr, s, &meta));
+    SimBound bound;
+    FARM_TRY(similarities(mem, ws, q, 0, target, nullptr, meta, dtype, &bound, false, false, s));
+    FARM_HIP(hipMemcpy2DAsync(out, (size_t)mem->n * sizeof(float), ws->sim, (size_t)ws->ld_s * sizeof(float),
+                              (size_t)mem->n * sizeof(float), (size_t)q, hipMemcpyDeviceToDevice, s),
+             "similarity copy");
+    return FARM_OK;
+  } catch (...) {
+    set_error("unexpected host exception in farm_similarity");
+    return FARM_ERR_HIP;
+  }
+}
+
 farm_status farm_topk(const farm_memory* mem, farm_workspace* ws, const float* scores, int32_t q, int32_t k,
                       uint32_t* out_id, float* out_score, int32_t* out_index, void* stream) {
   try {
-      if (!mem || !ws || ws->mem != mem) { set_error("null or mismatched memory/workspace"); return FARM_ERR_INVALID_ARG; }
+    FARM_CLAIM(ws);
+    if (!mem || !ws || ws->mem != mem) { set_error("null or mismatched memory/workspace"); return FARM_ERR_INVALID_ARG; }
     if (q < 0 || q > ws->max_q) { set_error("q = %d outside [0, %d]", q, ws->max_q); return FARM_ERR_INVALID_ARG; }
     if (k < 1 || k > FARM_MAX_K) { set_error("k = %d outside [1, %d]", k, FARM_MAX_K); return FARM_ERR_INVALID_ARG; }
     if (q == 0) return FARM_OK;
@@ -924,7 +992,8 @@ farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws, int32_t 
                             const float* rel_anchor, const farm_score_opts* opts, int32_t k, uint32_t* out_id,
                             float* out_score, float* out_terms, uint32_t* out_anchor_id, void* stream) {
   try {
-      int32_t R = 0;
+    FARM_CLAIM(ws);
+    int32_t R = 0;
     FARM_TRY(check_queries(mem, ws, q, d, target, rel_off, rel_pred, rel_anchor, &R));
     TopkPlan plan;
     FARM_TRY(plan_topk(mem, opts, k, &plan));

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include <string>
 #include <vector>
 
@@ -90,10 +92,16 @@ struct farm_memory {
   std::vector<void*> prop_allocs;
   size_t bytes = 0;
   std::vector<void*> allocs;
+  // workspaces created on this memory plus servers it is registered with:
+  // farm_free_memory refuses (FARM_ERR_BUSY) while any remain
+  mutable std::atomic<int32_t> users{0};
 };
 
 struct farm_workspace {
   const farm_memory* mem = nullptr;
+  // set while a library call runs on this workspace (WorkspaceClaim): a second
+  // host thread entering meanwhile gets FARM_ERR_BUSY
+  std::atomic<bool> in_call{false};
   int device = 0;
   int32_t max_q = 0, max_rel = 0;
   int64_t ld_s = 0;          // row stride of the similarity / score matrices

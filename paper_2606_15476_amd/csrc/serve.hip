@@ -338,6 +338,7 @@ farm_status farm_server_add_scene(farm_server* sv, const farm_memory* mem, int32
       }
     }
     sv->scenes.push_back(mem);
+    mem->users.fetch_add(1, std::memory_order_acq_rel);
     *scene_out = (int32_t)sv->scenes.size() - 1;
     return FARM_OK;
   } catch (...) {
@@ -492,6 +493,7 @@ farm_status farm_server_free(farm_server* sv) {
   }
   for (PooledWs& p : sv->pool)
     if (p.ws) (void)farm_workspace_free(p.ws);
+  for (const farm_memory* m : sv->scenes) m->users.fetch_sub(1, std::memory_order_acq_rel);
   delete sv;
   return FARM_OK;
 }

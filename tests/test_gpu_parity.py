@@ -552,3 +552,27 @@ def test_invalid_queries_rejected(farm):
     with pytest.raises(farm.FarmError):
         ws.status()
     ws.status()  # cleared
+
+
+def test_memory_in_use_is_busy(farm):
+    """farm_free_memory refuses (FARM_ERR_BUSY) while a workspace or a server still uses the
+    memory; the handle stays valid and scoring goes on; once they are freed the memory frees."""
+    from tests import _gpu
+    scene = _random_scene(40, 8, seed=12)
+    mem = _gpu.build_memory(scene)
+    ws = farm.Workspace(mem, 2, 2, 8)
+    sv = farm.Server(slots=1, max_batch_q=2, max_batch_rel=4, k=4)
+    sv.add_scene(mem)
+    with pytest.raises(farm.FarmError) as e:
+        mem.close()
+    assert e.value.status == -5
+    qb = _random_queries(scene, 2, [1], seed=4)
+    s, _, _ = _gpu.score_full(mem, ws, qb)
+    assert_values_close(s, oracle.score(scene, qb), "scores after a refused free")
+    ws.close()
+    with pytest.raises(farm.FarmError) as e:  # the server's registration remains
+        mem.close()
+    assert e.value.status == -5
+    sv.close()
+    mem.close()
+    assert mem._h is None

@@ -134,3 +134,86 @@ def test_precision_form_requires_built_copy(farm):
         mem2 = _gpu.build_memory(scene, flags=farm.FARM_BUILD_BF16)
         ws2 = farm.Workspace(mem2, qb.q, qb.r_tot, 16)
         _gpu.query_topk(mem2, ws2, qb, 10, dtype=1, rescore_mult=4)
+
+
+def _semantic_only(qb):
+    """The batch's targets and classes without relations: the oracle's score is then s_sem."""
+    from synth import QueryBatch
+    d = qb.target.shape[1]
+    return QueryBatch(qb.target, qb.target_cls, np.zeros(qb.q + 1, np.int32), np.zeros(0, np.int32),
+                      np.zeros((0, d), np.float32), qb.planted)
+
+
+def _gemm_bound(scene, qb, dtype):
+    """Per-element bound on |GEMM s_sem - exact s_sem| from the operands' rounding alone (FP64):
+    BF16 rounds each unit-vector element to nearest, |x~ - x| <= 2^-9 |x|; FP8-e4m3 with the row
+    scale amax/448 has 3 fraction bits (half ulp 2^-4 |x| for normal values) and subnormal
+    spacing 2^-9 of the scale (|x~ - x| <= 2^-10 scale).  The elementwise product errors
+    |e_q||d| + |q||e_d| + |e_q||e_d| are summed over the row; FP32 accumulation of the exact
+    products adds (K + 2) u sum|q~ d~|; clamp and class factor do not increase the error."""
+    u = 2.0 ** -24
+    Q = qb.target.astype(np.float64)
+    Q /= np.linalg.norm(Q, axis=1, keepdims=True)
+    D = scene.desc.astype(np.float64)
+    D /= np.linalg.norm(D, axis=1, keepdims=True)
+    aq, ad = np.abs(Q), np.abs(D)
+    if dtype == "bf16":
+        eq, ed = (2.0 ** -9 + 8 * u) * aq, (2.0 ** -9 + 8 * u) * ad
+    else:
+        sq = aq.max(axis=1, keepdims=True) / 448.0
+        sd = ad.max(axis=1, keepdims=True) / 448.0
+        eq = np.maximum((2.0 ** -4) * aq, 2.0 ** -10 * sq) * (1 + 8 * u)
+        ed = np.maximum((2.0 ** -4) * ad, 2.0 ** -10 * sd) * (1 + 8 * u)
+    quant = eq @ ad.T + aq @ ed.T + eq @ ed.T
+    absum = aq @ ad.T + quant
+    K = scene.desc.shape[1]
+    return quant + (K + 2) * u * absum + 4 * u
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+def test_similarity_gemm_elementwise(farm, dtype):
+    """Every element of the similarity GEMM (s_sem with the class factor) against the oracle's
+    FP64 s_sem: FP32 within the parity tolerance, BF16 / FP8 within the a-priori bound of their
+    operands' rounding; the reduced-precision errors are also far from zero (the GEMM really ran in
+    that precision) and their maximum is printed."""
+    import torch
+    from tests import _gpu
+    cfg = CONFIGS["mid"]
+    scene = make_scene(cfg, n=1500, seed=21)
+    qb = _semantic_only(make_queries(cfg, scene, seed=22, q=96))
+    mem = _gpu.build_memory(scene, flags=farm.FARM_BUILD_BF16 | farm.FARM_BUILD_FP8)
+    ws = farm.Workspace(mem, qb.q, 1)
+    out = torch.empty((qb.q, scene.n), dtype=torch.float32, device="cuda")
+    target, _ = _gpu.query_tensors(qb)
+    farm.similarity(mem, ws, target, qb.target_cls, out, dtype={"f32": 0, "bf16": 1, "fp8": 2}[dtype])
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    ref = oracle.score(scene, qb)
+    err = np.abs(got - ref)
+    if dtype == "f32":
+        assert_values_close(got, ref, "FP32 similarity GEMM")
+        return
+    bound = _gemm_bound(scene, qb, dtype)
+    worst = float(np.max(err / bound))
+    print(f"{dtype}: max |err| {err.max():.3e}, max err / bound {worst:.3f}", flush=True)
+    bad = err > bound
+    assert not bad.any(), (int(bad.sum()), np.argwhere(bad)[:5])
+    assert err.max() > {"bf16": 1e-5, "fp8": 1e-3}[dtype]
+
+
+def test_similarity_requires_copy_and_valid_dtype(farm):
+    import torch
+    from tests import _gpu
+    cfg = CONFIGS["tiny"]
+    scene = make_scene(cfg, seed=3)
+    qb = _semantic_only(make_queries(cfg, scene, seed=4, q=4))
+    mem = _gpu.build_memory(scene)  # no reduced-precision copies
+    ws = farm.Workspace(mem, 4, 1)
+    out = torch.empty((4, scene.n), dtype=torch.float32, device="cuda")
+    target, _ = _gpu.query_tensors(qb)
+    for dt, code in ((1, farm.FarmError), (2, farm.FarmError), (7, farm.FarmError)):
+        with pytest.raises(code):
+            farm.similarity(mem, ws, target, qb.target_cls, out, dtype=dt)
+    farm.similarity(mem, ws, target, qb.target_cls, out, dtype=0)
+    torch.cuda.synchronize()
+    assert_values_close(out.cpu().numpy().astype(np.float64), oracle.score(scene, qb), "FP32 similarity GEMM")
