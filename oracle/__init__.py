@@ -74,6 +74,12 @@ def _load():
         lib.farm_oracle_set_between_tolerance.argtypes = [ctypes.c_int, ctypes.c_double]
         lib.farm_oracle_set_rank_tolerance.restype = None
         lib.farm_oracle_set_rank_tolerance.argtypes = [ctypes.c_int, ctypes.c_double]
+        lib.farm_oracle_hellinger_near.restype = ctypes.c_double
+        lib.farm_oracle_hellinger_near.argtypes = [P, P, P, P]
+        lib.farm_oracle_view_predicate.restype = ctypes.c_double
+        lib.farm_oracle_view_predicate.argtypes = [ctypes.c_int, P, P, P]
+        lib.farm_oracle_set_entity_geometry.restype = None
+        lib.farm_oracle_set_entity_geometry.argtypes = [i64, P, P]
         lib.farm_oracle_topk_bounded.restype = ctypes.c_int
         lib.farm_oracle_topk_bounded.argtypes = [i64, ctypes.c_int, P, P, P, P, P, P, i32, P, P, P, P, P,
                                                  i32, P, P, P, P, P]
@@ -170,6 +176,46 @@ def between_binding_value(scene, anchor1, anchor2, i: int, j1: int, j2: int) -> 
                                                        int(i), int(j1), int(j2)))
 
 
+def hellinger_near(ci, cov_i, cj, cov_j) -> float:
+    """Near over entity Gaussians, 1 - H(N(ci, cov_i), N(cj, cov_j)), FP64 from float32 centers and
+    packed covariances (xx, xy, xz, yy, yz, zz)."""
+    lib = _load()
+    a, pa = _c(ci, np.float32)
+    A, pA = _c(cov_i, np.float32)
+    b, pb = _c(cj, np.float32)
+    B, pB = _c(cov_j, np.float32)
+    return float(lib.farm_oracle_hellinger_near(pa, pA, pb, pB))
+
+
+def view_predicate(p: int, view_i, ci, cj) -> float:
+    """A viewpoint-dependent predicate (15..18) of target center ci and anchor center cj in the
+    target's stored view [camera center, right, down, forward axes], FP64 from float32 inputs."""
+    lib = _load()
+    v, pv = _c(view_i, np.float32)
+    a, pa = _c(ci, np.float32)
+    b, pb = _c(cj, np.float32)
+    return float(lib.farm_oracle_view_predicate(int(p), pv, pa, pb))
+
+
+class _geometry:
+    """Context manager: the scene's entity Gaussians and stored views, when it has them, are what the
+    oracle's scoring calls see inside it; cleared on exit."""
+
+    def __init__(self, scene):
+        self.cov = None if getattr(scene, "cov", None) is None else np.ascontiguousarray(scene.cov, np.float32)
+        self.view = None if getattr(scene, "view", None) is None else np.ascontiguousarray(scene.view, np.float32)
+        self.n = int(scene.desc.shape[0])
+
+    def __enter__(self):
+        ptr = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+        _load().farm_oracle_set_entity_geometry(self.n, ptr(self.cov), ptr(self.view))
+        return self
+
+    def __exit__(self, *exc):
+        _load().farm_oracle_set_entity_geometry(-1, None, None)
+        return False
+
+
 def _scene_args(scene):
     desc, pd = _c(scene.desc, np.float32)
     cen, pc = _c(scene.center, np.float32)
@@ -210,7 +256,8 @@ def score(scene, qb, terms: bool = False):
     t = np.zeros((r_tot, n), np.float64) if terms else None
     b = np.zeros((r_tot, n), np.uint32) if terms else None
     ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p) if a is not None and a.size else None
-    rc = lib.farm_oracle_score(*sa, *qa, ptr(out), ptr(sem), ptr(t), ptr(b))
+    with _geometry(scene):
+        rc = lib.farm_oracle_score(*sa, *qa, ptr(out), ptr(sem), ptr(t), ptr(b))
     if rc:
         raise ValueError(f"oracle score failed ({rc})")
     del k1, k2
@@ -229,9 +276,10 @@ def score_pairs(scene, qb, qsel, osel):
     sem = np.zeros(max(m, 1), np.float64)
     t = np.zeros((max(m, 1), MAX_REL), np.float64)
     b = np.zeros((max(m, 1), MAX_REL), np.uint32)
-    rc = lib.farm_oracle_score_pairs(*sa, *qa, m, pq, po, out.ctypes.data_as(ctypes.c_void_p),
-                                     sem.ctypes.data_as(ctypes.c_void_p), t.ctypes.data_as(ctypes.c_void_p),
-                                     b.ctypes.data_as(ctypes.c_void_p))
+    with _geometry(scene):
+        rc = lib.farm_oracle_score_pairs(*sa, *qa, m, pq, po, out.ctypes.data_as(ctypes.c_void_p),
+                                         sem.ctypes.data_as(ctypes.c_void_p), t.ctypes.data_as(ctypes.c_void_p),
+                                         b.ctypes.data_as(ctypes.c_void_p))
     if rc:
         raise ValueError(f"oracle score_pairs failed ({rc})")
     del k1, k2
@@ -262,7 +310,8 @@ def topk_bounded(scene, qb, k: int):
     b = np.zeros((q, k, MAX_REL), np.uint32)
     ns = np.zeros(q, np.int64)
     p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
-    rc = lib.farm_oracle_topk_bounded(*sa, *qa, int(k), p(idx), p(sc), p(t), p(b), p(ns))
+    with _geometry(scene):
+        rc = lib.farm_oracle_topk_bounded(*sa, *qa, int(k), p(idx), p(sc), p(t), p(b), p(ns))
     if rc:
         raise ValueError(f"oracle topk_bounded failed ({rc})")
     del k1, k2
@@ -283,12 +332,13 @@ def binding_value(scene, pred: int, anchor_vec, i: int, j: int, target_cls: int 
         cls, pk = _c(scene.cls, np.int32)
     vr, pv = _c(scene.view_right, np.float32)
     av, pa = _c(anchor_vec, np.float32)
-    return float(lib.farm_oracle_binding_value(int(desc.shape[0]), int(desc.shape[1]), pd, pc, pe, pi, pk, pv,
-                                               int(target_cls), int(pred), pa, int(i), int(j)))
+    with _geometry(scene):
+        return float(lib.farm_oracle_binding_value(int(desc.shape[0]), int(desc.shape[1]), pd, pc, pe, pi, pk, pv,
+                                                   int(target_cls), int(pred), pa, int(i), int(j)))
 
 
-NUM_PRED = 14  # predicate ids 0..13 (On = 8, Closest = 9, Farthest = 10, Inside = 11, Between = 12 and its
-#               second anchor 13)
+NUM_PRED = 19  # predicate ids 0..18 (On = 8, Closest = 9, Farthest = 10, Inside = 11, Between = 12 and its
+#               second anchor 13, Hellinger Near = 14, the stored-view LeftOf, RightOf, InFrontOf, Behind = 15..18)
 NPRED = 9      # proposal-network outputs, one per predicate
 NGEO = 12
 

@@ -99,6 +99,72 @@ def between_relation(ci, c1, c2):
     return _sigmoid(lam * L / 0.1) * _sigmoid((1.0 - lam) * L / 0.1) * math.exp(-h2 / (2 * 0.25))
 
 
+def _solve_and_logdet(M, v):
+    """x with M x = v, and log det M, by Gaussian elimination with partial pivoting (M 3x3, positive definite)."""
+    A = [list(map(float, M[r])) + [float(v[r])] for r in range(3)]
+    logdet = 0.0
+    for c in range(3):
+        piv = max(range(c, 3), key=lambda r: abs(A[r][c]))
+        if piv != c:
+            A[c], A[piv] = A[piv], A[c]
+        logdet += math.log(abs(A[c][c]))
+        for r in range(c + 1, 3):
+            f = A[r][c] / A[c][c]
+            for k in range(c, 4):
+                A[r][k] -= f * A[c][k]
+    x = [0.0, 0.0, 0.0]
+    for r in (2, 1, 0):
+        x[r] = (A[r][3] - sum(A[r][k] * x[k] for k in range(r + 1, 3))) / A[r][r]
+    return x, logdet
+
+
+def _sym(p6):
+    a, b, c, d, e, f = (float(v) for v in p6)
+    return [[a, b, c], [b, d, e], [c, e, f]]
+
+
+def hellinger_relation(ci, cov_i, cj, cov_j):
+    """Near over entity Gaussians: 1 - H, H^2 = 1 - exp(-D_B) with the Bhattacharyya distance
+    D_B = (mu_i - mu_j)^T M^-1 (mu_i - mu_j) / 8 + log(det M / sqrt(det A det B)) / 2, M = (A + B) / 2."""
+    A, B = _sym(cov_i), _sym(cov_j)
+    M = [[(A[r][k] + B[r][k]) / 2.0 for k in range(3)] for r in range(3)]
+    dmu = [float(ci[k]) - float(cj[k]) for k in range(3)]
+    x, ld_m = _solve_and_logdet(M, dmu)
+    _, ld_a = _solve_and_logdet(A, [0.0, 0.0, 0.0])
+    _, ld_b = _solve_and_logdet(B, [0.0, 0.0, 0.0])
+    db = sum(dmu[k] * x[k] for k in range(3)) / 8.0 + 0.5 * (ld_m - 0.5 * (ld_a + ld_b))
+    return 1.0 - math.sqrt(max(0.0, 1.0 - math.exp(-db)))
+
+
+def view_relation(pred, view_i, ci, cj):
+    """LeftOf / RightOf / InFrontOf / Behind (15..18) in target i's stored view: a pinhole camera at
+    view_i[0:3] with right, down and forward axes view_i[3:6], [6:9], [9:12]; horizontal image-plane
+    coordinate u = (w . right) / (w . forward), depth w . forward, w the offset from the camera.  Both
+    objects must be in the view (depth >= 0.1 m, |x| <= depth, |y| <= 0.75 depth), else 0."""
+    v = [float(x) for x in view_i]
+    pos, right, down, fwd = v[0:3], v[3:6], v[6:9], v[9:12]
+
+    def cam(c):
+        w = [float(c[k]) - pos[k] for k in range(3)]
+        return (sum(w[k] * right[k] for k in range(3)), sum(w[k] * down[k] for k in range(3)),
+                sum(w[k] * fwd[k] for k in range(3)))
+
+    (xi, yi, zi), (xj, yj, zj) = cam(ci), cam(cj)
+    for x, y, z in ((xi, yi, zi), (xj, yj, zj)):
+        if not (z >= 0.1 and abs(x) <= z and abs(y) <= 0.75 * z):
+            return 0.0
+    ui, uj = xi / zi, xj / zj
+    if pred == 15:
+        return _sigmoid((uj - ui) / 0.05)
+    if pred == 16:
+        return _sigmoid((ui - uj) / 0.05)
+    if pred == 17:  # in front of: nearer the camera
+        return _sigmoid((zj - zi) / 0.1)
+    if pred == 18:
+        return _sigmoid((zi - zj) / 0.1)
+    raise ValueError(pred)
+
+
 def rank_relation(pred, scene, tcls, i, j):
     """Closest (9) / Farthest (10): 1 / (|rank - r*| + 1), the rank of target i
     among the query's candidates (objects of class tcls; all objects without a
@@ -173,6 +239,10 @@ def brute_scores(scene, qb):
                         continue
                     if pred in (9, 10):
                         pv = rank_relation(pred, scene, tcls, e, j)
+                    elif pred == 14:
+                        pv = hellinger_relation(scene.center[e], scene.cov[e], scene.center[j], scene.cov[j])
+                    elif 15 <= pred <= 18:
+                        pv = view_relation(pred, scene.view[e], scene.center[e], scene.center[j])
                     else:
                         pv = soft_relation(pred, scene.center[e], scene.center[j], scene.view_right,
                                            scene.extent[e], scene.extent[j])

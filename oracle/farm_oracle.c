@@ -43,7 +43,22 @@
  *              distance from that axis; 0 when L = 0.  Its anchors range over
  *              candidate sets of 64 (see between_set)
  * where (r_x, r_y) is the scene viewer's right vector, f = (-r_y, r_x) its
- * viewing direction and e the full box extents.  The temperatures
+ * viewing direction and e the full box extents.
+ *
+ * With entity Gaussians and stored views (Section "Memory Construction": each
+ * entity's 3D Gaussian N(mu, Sigma), mu its center, and its representative
+ * posed views; Section "Robust Relational Object Retrieval", implementation
+ * paragraph: Hellinger distance for Near; Appendix "Retrieval Details", step
+ * 4: the viewpoint-dependent predicates in stored camera views of the target
+ * candidate):
+ *   NEAR_H   = 1 - H(N_i, N_j), H^2 = 1 - BC, BC the Bhattacharyya
+ *              coefficient of the two Gaussians (see hellinger_near)
+ *   LEFT_OF_V / RIGHT_OF_V = sig(+-(u_j - u_i) / 0.05), u = x_c / z_c the
+ *              horizontal image-plane coordinate of a center in target i's
+ *              stored view; IN_FRONT_OF_V / BEHIND_V = sig(+-(z_j - z_i) /
+ *              0.1), z the camera-frame depth; 0 unless both centers are in
+ *              that view (see view_predicate).
+ * The temperatures
  * (0.1 m), the Gaussian's normalisation, the clamp at zero, the viewer
  * convention and On's Gaussian gate and band with their widths are readings
  * where the paper is silent.
@@ -74,7 +89,8 @@
 
 enum { P_NEAR = 0, P_ABOVE = 1, P_BELOW = 2, P_LEFT_OF = 3, P_RIGHT_OF = 4, P_NEXT_TO = 5, P_IN_FRONT_OF = 6,
        P_BEHIND = 7, P_ON = 8, P_CLOSEST = 9, P_FARTHEST = 10, P_INSIDE = 11, P_BETWEEN = 12, P_AND = 13,
-       P_COUNT = 14 };
+       P_NEAR_H = 14, P_LEFT_OF_V = 15, P_RIGHT_OF_V = 16, P_IN_FRONT_OF_V = 17, P_BEHIND_V = 18,
+       P_COUNT = 19 };
 
 static double logistic(double u) { return 1.0 / (1.0 + exp(-u)); }
 
@@ -159,6 +175,123 @@ double farm_oracle_between(const float* ci, const float* c1, const float* c2) {
     return between_value(a, b, c);
 }
 
+/* ------------------------------------------------ Gaussians and stored views */
+
+/* A symmetric 3x3 matrix from its packed upper triangle (xx, xy, xz, yy, yz, zz). */
+static void unpack_sym(const double* p6, double m[3][3]) {
+    m[0][0] = p6[0]; m[0][1] = p6[1]; m[0][2] = p6[2];
+    m[1][0] = p6[1]; m[1][1] = p6[3]; m[1][2] = p6[4];
+    m[2][0] = p6[2]; m[2][1] = p6[4]; m[2][2] = p6[5];
+}
+
+static double det3(double m[3][3]) {
+    return m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) - m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+           m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+}
+
+/* v^T m^-1 v: solve m x = v by Cramer's rule (column k of m replaced by v). */
+static double inverse_quadratic_form(double m[3][3], const double* v) {
+    double d = det3(m), q = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        double c[3][3];
+        for (int r = 0; r < 3; ++r)
+            for (int col = 0; col < 3; ++col) c[r][col] = (col == k) ? v[r] : m[r][col];
+        q += v[k] * det3(c) / d;
+    }
+    return q;
+}
+
+/* Near over entity Gaussians (Section "Robust Relational Object Retrieval",
+ * implementation paragraph: the Hellinger distance for Near; the Gaussian
+ * N(mu, Sigma) of each entity, Section "Memory Construction").  The
+ * Bhattacharyya coefficient of N(mu_i, A) and N(mu_j, B) with M = (A + B) / 2
+ * is BC = det(A)^(1/4) det(B)^(1/4) / det(M)^(1/2) exp(-(mu_i - mu_j)^T M^-1
+ * (mu_i - mu_j) / 8), the squared Hellinger distance H^2 = 1 - BC, and the
+ * soft relation -- a membership in [0, 1] that is 1 for identical Gaussians --
+ * is 1 - H (a reading: the paper names the distance, not the map). */
+static double hellinger_near(const double* ci, const double* cov_i, const double* cj, const double* cov_j) {
+    double A[3][3], B[3][3], M[3][3];
+    unpack_sym(cov_i, A);
+    unpack_sym(cov_j, B);
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) M[r][c] = 0.5 * (A[r][c] + B[r][c]);
+    double dmu[3] = {ci[0] - cj[0], ci[1] - cj[1], ci[2] - cj[2]};
+    double q = inverse_quadratic_form(M, dmu);
+    double bc = pow(det3(A), 0.25) * pow(det3(B), 0.25) / sqrt(det3(M)) * exp(-q / 8.0);
+    double h2 = 1.0 - bc;
+    if (h2 < 0.0) h2 = 0.0;
+    return 1.0 - sqrt(h2);
+}
+
+/* A stored view: the camera center p (3) and the rows of the world-to-camera
+ * rotation R (9: the camera's right, down and forward axes in world
+ * coordinates), so that a point x has camera coordinates R (x - p), depth
+ * along the third. */
+#define ORACLE_VIEW_TAU_U 0.05   /* temperature of the image-plane offset (normalised coordinates) */
+#define ORACLE_VIEW_Z_MIN 0.1    /* a center is in the view when its depth is at least 0.1 m ... */
+#define ORACLE_VIEW_HALF_W 1.0   /* ... and it projects within the 90 x 73.7 degree field of view */
+#define ORACLE_VIEW_HALF_H 0.75
+
+static void camera_coords(const double* view, const double* x, double* xc) {
+    double w[3] = {x[0] - view[0], x[1] - view[1], x[2] - view[2]};
+    for (int r = 0; r < 3; ++r) xc[r] = view[3 + 3 * r] * w[0] + view[4 + 3 * r] * w[1] + view[5 + 3 * r] * w[2];
+}
+
+static int in_view(const double* xc) {
+    return xc[2] >= ORACLE_VIEW_Z_MIN && fabs(xc[0]) <= ORACLE_VIEW_HALF_W * xc[2] &&
+           fabs(xc[1]) <= ORACLE_VIEW_HALF_H * xc[2];
+}
+
+/* The viewpoint-dependent predicates in a stored camera view of the target
+ * candidate i (Appendix "Retrieval Details", step 4): left/right from the
+ * anchor-relative horizontal offset of the two objects on the image plane,
+ * front/behind from their relative camera-frame depth.  Readings: the view is
+ * the target's first stored view; a center stands in for its mask centroid
+ * (projected at u = x_c / z_c); the offsets pass through the logistic with
+ * temperature 0.05 (image plane) and 0.1 m (depth); an object outside the
+ * view (behind the near plane at 0.1 m or outside the field of view) gives 0. */
+static double view_predicate(int p, const double* view_i, const double* ci, const double* cj) {
+    double a[3], b[3];
+    camera_coords(view_i, ci, a);
+    camera_coords(view_i, cj, b);
+    if (!in_view(a) || !in_view(b)) return 0.0;
+    double ua = a[0] / a[2], ub = b[0] / b[2];
+    switch (p) {
+    case P_LEFT_OF_V: return logistic((ub - ua) / ORACLE_VIEW_TAU_U);
+    case P_RIGHT_OF_V: return logistic((ua - ub) / ORACLE_VIEW_TAU_U);
+    case P_IN_FRONT_OF_V: return logistic((b[2] - a[2]) / ORACLE_TAU);
+    case P_BEHIND_V: return logistic((a[2] - b[2]) / ORACLE_TAU);
+    default: return NAN;
+    }
+}
+
+/* Exported for pins: one value of the predicates above for float inputs
+ * (cov: packed 6-vectors of target and anchor; view: the target's view). */
+double farm_oracle_hellinger_near(const float* ci, const float* cov_i, const float* cj, const float* cov_j) {
+    double a[3] = {ci[0], ci[1], ci[2]}, b[3] = {cj[0], cj[1], cj[2]}, A[6], B[6];
+    for (int k = 0; k < 6; ++k) { A[k] = cov_i[k]; B[k] = cov_j[k]; }
+    return hellinger_near(a, A, b, B);
+}
+
+double farm_oracle_view_predicate(int p, const float* view_i, const float* ci, const float* cj) {
+    double v[12], a[3] = {ci[0], ci[1], ci[2]}, b[3] = {cj[0], cj[1], cj[2]};
+    for (int k = 0; k < 12; ++k) v[k] = view_i[k];
+    return view_predicate(p, v, a, b);
+}
+
+/* Entity Gaussians [n][6] and stored views [n][12] of the scene the next
+ * scoring calls receive (NULL: the scene has none); the arrays must stay
+ * valid until cleared.  Predicates that need them fail (-1) without them. */
+static const float* g_cov = NULL;
+static const float* g_view = NULL;
+static int64_t g_ext_n = -1;
+
+void farm_oracle_set_entity_geometry(int64_t n, const float* cov6, const float* view12) {
+    g_ext_n = n;
+    g_cov = cov6;
+    g_view = view12;
+}
+
 static void unit_vector(const float* v, int d, double* out) {
     double ss = 0.0;
     for (int k = 0; k < d; ++k) ss += (double)v[k] * (double)v[k];
@@ -181,12 +314,16 @@ typedef struct {
     const uint32_t* id;
     const int32_t* cls;
     double right[2];
+    double* cov;      /* [n][6] packed entity covariances, or NULL */
+    double* view;     /* [n][12] stored views, or NULL */
 } scene64;
 
 static int scene_init(scene64* s, int64_t n, int d, const float* desc, const float* center,
                       const float* extent, const uint32_t* id, const int32_t* cls, const float* right) {
     s->n = n;
     s->d = d;
+    s->cov = NULL;
+    s->view = NULL;
     s->u = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * (size_t)d);
     s->c = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * 3);
     s->e = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * 3);
@@ -200,6 +337,16 @@ static int scene_init(scene64* s, int64_t n, int d, const float* desc, const flo
     s->cls = cls;
     s->right[0] = right[0];
     s->right[1] = right[1];
+    if (g_ext_n == n && g_cov) {
+        s->cov = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * 6);
+        if (!s->cov) return -2;
+        for (int64_t k = 0; k < n * 6; ++k) s->cov[k] = g_cov[k];
+    }
+    if (g_ext_n == n && g_view) {
+        s->view = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * 12);
+        if (!s->view) return -2;
+        for (int64_t k = 0; k < n * 12; ++k) s->view[k] = g_view[k];
+    }
     return 0;
 }
 
@@ -207,6 +354,26 @@ static void scene_free(scene64* s) {
     free(s->u);
     free(s->c);
     free(s->e);
+    free(s->cov);
+    free(s->view);
+}
+
+static int is_view_pred(int p) { return p >= P_LEFT_OF_V && p <= P_BEHIND_V; }
+
+/* P_p(i, j) of every pairwise predicate but the rank ones and Between. */
+static double pair_value(const scene64* s, int p, int64_t i, int64_t j) {
+    if (p == P_NEAR_H) return hellinger_near(s->c + i * 3, s->cov + i * 6, s->c + j * 3, s->cov + j * 6);
+    if (is_view_pred(p)) return view_predicate(p, s->view + i * 12, s->c + i * 3, s->c + j * 3);
+    return oracle_predicate(p, s->c + i * 3, s->c + j * 3, s->e + i * 3, s->e + j * 3, s->right);
+}
+
+/* Queries that name a Gaussian or view predicate need the scene to carry them. */
+static int check_scene_geometry(const scene64* s, int32_t q, const int32_t* rel_off, const int32_t* rel_pred) {
+    for (int32_t r = 0; r < rel_off[q]; ++r) {
+        if (rel_pred[r] == P_NEAR_H && !s->cov) return -1;
+        if (is_view_pred(rel_pred[r]) && !s->view) return -1;
+    }
+    return 0;
 }
 
 /* Per-query state: normalised target, anchor similarities per relation. */
@@ -411,9 +578,7 @@ static void relation_term(const scene64* s, const query64* qs, int rr, int64_t i
     const int p = qs->pred[rr];
     for (int64_t j = 0; j < s->n; ++j) {
         if (j == i) continue;
-        double v = a[j] * (is_rank_pred(p) ? rank_value(s, qs->tcls, p, i, j)
-                                           : oracle_predicate(p, s->c + i * 3, s->c + j * 3, s->e + i * 3,
-                                                              s->e + j * 3, s->right));
+        double v = a[j] * (is_rank_pred(p) ? rank_value(s, qs->tcls, p, i, j) : pair_value(s, p, i, j));
         if (v > best || (v == best && s->id[j] < best_id)) {
             best = v;
             best_id = s->id[j];
@@ -484,6 +649,7 @@ int farm_oracle_score(int64_t n, int d, const float* desc, const float* center, 
     if (check_query_meta(q, rel_off, rel_pred)) return -1;
     scene64 s;
     if (scene_init(&s, n, d, desc, center, extent, id, cls, right)) { scene_free(&s); return -2; }
+    if (check_scene_geometry(&s, q, rel_off, rel_pred)) { scene_free(&s); return -1; }
     int err = 0;
     /* queries one after another; the objects of a query (and its similarity
      * rows) in parallel, so that every thread works whatever the query count */
@@ -530,6 +696,7 @@ int farm_oracle_score_pairs(int64_t n, int d, const float* desc, const float* ce
         if (qsel[p] < 0 || qsel[p] >= q || osel[p] < 0 || osel[p] >= n) return -1;
     scene64 s;
     if (scene_init(&s, n, d, desc, center, extent, id, cls, right)) { scene_free(&s); return -2; }
+    if (check_scene_geometry(&s, q, rel_off, rel_pred)) { scene_free(&s); return -1; }
     int err = 0;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int32_t k = 0; k < q; ++k) {
@@ -610,6 +777,7 @@ int farm_oracle_topk_bounded(int64_t n, int d, const float* desc, const float* c
     if (check_query_meta(q, rel_off, rel_pred) || k < 1) return -1;
     scene64 s;
     if (scene_init(&s, n, d, desc, center, extent, id, cls, right)) { scene_free(&s); return -2; }
+    if (check_scene_geometry(&s, q, rel_off, rel_pred)) { scene_free(&s); return -1; }
     int err = 0;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int32_t qq = 0; qq < q; ++qq) {
@@ -707,6 +875,19 @@ double farm_oracle_binding_value(int64_t n, int d, const float* desc, const floa
         s0.cls = cls;
         val = a * rank_value(&s0, tcls, p, i, j);
         free(s0.c);
+    } else if (p == P_NEAR_H || is_view_pred(p)) {
+        /* the entity geometry of the scene (farm_oracle_set_entity_geometry) */
+        if (g_ext_n != n || (p == P_NEAR_H && !g_cov) || (p != P_NEAR_H && !g_view)) {
+            val = NAN;
+        } else if (p == P_NEAR_H) {
+            double A[6], B[6];
+            for (int k = 0; k < 6; ++k) { A[k] = g_cov[i * 6 + k]; B[k] = g_cov[j * 6 + k]; }
+            val = a * hellinger_near(ci, A, cj, B);
+        } else {
+            double w[12];
+            for (int k = 0; k < 12; ++k) w[k] = g_view[i * 12 + k];
+            val = a * view_predicate(p, w, ci, cj);
+        }
     } else {
         val = a * oracle_predicate(p, ci, cj, ei, ej, r);
     }

@@ -29,12 +29,17 @@ NEAR, ABOVE, BELOW, LEFT_OF, RIGHT_OF = 0, 1, 2, 3, 4
 NEXT_TO, IN_FRONT_OF, BEHIND, ON = 5, 6, 7, 8
 CLOSEST, FARTHEST, INSIDE = 9, 10, 11
 BETWEEN, AND = 12, 13                       # ternary Between: its slot, then its second anchor's slot
+# over entity Gaussians (Hellinger Near) and per-object stored views (image-plane / depth offsets)
+NEAR_H, LEFT_OF_V, RIGHT_OF_V, IN_FRONT_OF_V, BEHIND_V = 14, 15, 16, 17, 18
+VIEW_PREDS = (LEFT_OF_V, RIGHT_OF_V, IN_FRONT_OF_V, BEHIND_V)
+GEOMETRY_PREDS = (NEAR_H,) + VIEW_PREDS
 ALL_PREDS = tuple(range(9))                 # the pairwise predicates with learned anchor lists
 RANK_PREDS = (CLOSEST, FARTHEST)            # rank within the query's candidate set
 EVERY_PRED = ALL_PREDS + RANK_PREDS + (INSIDE,)
 DEFAULT_PREDS = (NEAR, ABOVE, BELOW, LEFT_OF, RIGHT_OF)  # the pool query batches draw from by default
 PRED_NAMES = ("near", "above", "below", "left_of", "right_of", "next_to", "in_front_of", "behind", "on", "closest",
-              "farthest", "inside", "between", "and")
+              "farthest", "inside", "between", "and", "near_hellinger", "left_of_view", "right_of_view",
+              "in_front_of_view", "behind_view")
 
 
 @dataclasses.dataclass
@@ -46,6 +51,9 @@ class Scene:
     cls: np.ndarray         # [n] int32, category id (>= 0)
     view_right: np.ndarray  # [2] float32, viewer right vector (x, y)
     centroids: np.ndarray   # [C, d] float32, category centroids (unit rows)
+    cov: np.ndarray | None = None   # [n, 6] float32 entity covariances (xx, xy, xz, yy, yz, zz), or None
+    view: np.ndarray | None = None  # [n, 12] float32 stored views: camera center, then its right, down and
+    #                                 forward axes (the rows of the world-to-camera rotation), or None
 
     @property
     def n(self) -> int:
@@ -179,6 +187,50 @@ def make_scene(cfg: Config, seed: int | None = None, n: int | None = None) -> Sc
     )
 
 
+def add_entity_geometry(scene: Scene, seed: int = 0) -> Scene:
+    """The scene with an entity Gaussian and one stored view per object.
+
+    Gaussian: mean = the box center; covariance = the second moment of a
+    uniform distribution over the box (e^2 / 12 per axis), each axis scaled by
+    a factor in [0.8, 1.25] and turned by a random yaw.  View: a camera 0.8 to
+    3.0 m from the object horizontally (the viewpoint-distance range of the
+    paper's HM3D trajectories), 0.2 to 0.8 m above its center, looking at it
+    with a level horizon.
+    """
+    rng = np.random.default_rng([seed, 0x6A55])
+    n = scene.n
+    e = scene.extent.astype(np.float64)
+    var = (e * e / 12.0) * rng.uniform(0.8, 1.25, size=(n, 3))
+    yaw = rng.uniform(0.0, math.pi, size=n)
+    cov = np.zeros((n, 6))
+    for i in range(n):
+        c, s_ = math.cos(yaw[i]), math.sin(yaw[i])
+        R = np.array([[c, -s_, 0.0], [s_, c, 0.0], [0.0, 0.0, 1.0]])
+        S = R @ np.diag(var[i]) @ R.T
+        cov[i] = [S[0, 0], S[0, 1], S[0, 2], S[1, 1], S[1, 2], S[2, 2]]
+    c64 = scene.center.astype(np.float64)
+    dist = rng.uniform(0.8, 3.0, size=n)
+    az = rng.uniform(0.0, 2.0 * math.pi, size=n)
+    up = rng.uniform(0.2, 0.8, size=n)
+    view = np.zeros((n, 12))
+    for i in range(n):
+        pos = c64[i] + np.array([dist[i] * math.cos(az[i]), dist[i] * math.sin(az[i]), up[i]])
+        fwd = c64[i] - pos
+        fwd /= np.linalg.norm(fwd)
+        right = np.cross(fwd, [0.0, 0.0, 1.0])
+        right /= np.linalg.norm(right)
+        down = np.cross(fwd, right)
+        view[i] = np.concatenate([pos, right, down, fwd])
+    return dataclasses.replace(scene, cov=np.ascontiguousarray(cov, dtype=np.float32),
+                               view=np.ascontiguousarray(view, dtype=np.float32))
+
+
+def _camera(scene: Scene, o: int, c64: np.ndarray) -> np.ndarray:
+    """Camera-frame coordinates of every center in object o's stored view."""
+    v = scene.view[o].astype(np.float64)
+    return (c64 - v[:3]) @ v[3:].reshape(3, 3).T
+
+
 def _plant_anchor(rng, scene: Scene, o: int, pred: int, c64: np.ndarray, r64: np.ndarray) -> int:
     """Pick the anchor object for a planted relation by a geometric rule.
 
@@ -189,8 +241,17 @@ def _plant_anchor(rng, scene: Scene, o: int, pred: int, c64: np.ndarray, r64: np
     d = c64 - c64[o]
     dist = np.sqrt((d * d).sum(axis=1))
     dist[o] = np.inf
-    if pred in (NEAR, NEXT_TO, CLOSEST, INSIDE):
+    if pred in (NEAR, NEXT_TO, CLOSEST, INSIDE, NEAR_H):
         ok = np.isfinite(dist)
+    elif pred in VIEW_PREDS and scene.view is not None:
+        # in o's stored view: both in front of the camera, the anchor on the named side
+        # (0.1 of the image plane) or at the named depth (0.3 m)
+        xc = _camera(scene, o, c64)
+        vis = (xc[:, 2] > 0.3) & (np.abs(xc[:, 0]) < 0.9 * xc[:, 2]) & (np.abs(xc[:, 1]) < 0.7 * xc[:, 2])
+        u = xc[:, 0] / np.where(xc[:, 2] > 0, xc[:, 2], 1.0)
+        side = {LEFT_OF_V: u - u[o], RIGHT_OF_V: u[o] - u, IN_FRONT_OF_V: (xc[:, 2] - xc[o, 2]) / 3.0,
+                BEHIND_V: (xc[o, 2] - xc[:, 2]) / 3.0}[pred]
+        ok = vis & (side > 0.1)
     elif pred == FARTHEST:
         ok = np.isfinite(dist)
         dist = np.where(ok, -dist, np.inf)  # the farthest object

@@ -45,6 +45,22 @@ MUTATIONS = [
     ("between drops the far-side margin", "return logistic(s / ORACLE_TAU) * logistic((L - s) / ORACLE_TAU) *",
      "return logistic(s / ORACLE_TAU) *"),
     ("between's invocation counted twice in the mean", "        if (pred[rr] == P_AND) continue;\n", ""),
+    ("hellinger drops the determinant factor",
+     "double bc = pow(det3(A), 0.25) * pow(det3(B), 0.25) / sqrt(det3(M)) * exp(-q / 8.0);",
+     "double bc = exp(-q / 8.0);"),
+    ("hellinger quadratic form scaled by 1/2", "* exp(-q / 8.0);", "* exp(-q / 2.0);"),
+    ("hellinger similarity taken as the squared distance", "return 1.0 - sqrt(h2);", "return 1.0 - h2;"),
+    ("stored view rotation transposed",
+     "xc[r] = view[3 + 3 * r] * w[0] + view[4 + 3 * r] * w[1] + view[5 + 3 * r] * w[2];",
+     "xc[r] = view[3 + r] * w[0] + view[6 + r] * w[1] + view[9 + r] * w[2];"),
+    ("view gate ignores the field of view",
+     "return xc[2] >= ORACLE_VIEW_Z_MIN && fabs(xc[0]) <= ORACLE_VIEW_HALF_W * xc[2] &&",
+     "return xc[2] >= ORACLE_VIEW_Z_MIN; return 1 &&"),
+    ("left-of compares image coordinates the other way", "case P_LEFT_OF_V: return logistic((ub - ua) / ORACLE_VIEW_TAU_U);",
+     "case P_LEFT_OF_V: return logistic((ua - ub) / ORACLE_VIEW_TAU_U);"),
+    ("in-front-of on world height instead of camera depth",
+     "case P_IN_FRONT_OF_V: return logistic((b[2] - a[2]) / ORACLE_TAU);",
+     "case P_IN_FRONT_OF_V: return logistic((cj[2] - ci[2]) / ORACLE_TAU);"),
     ("gelu derivative drops its second term",
      "return 0.5 * (1.0 + erf(v / sqrt(2.0))) + v * exp(-0.5 * v * v) / sqrt(2.0 * M_PI);",
      "return 0.5 * (1.0 + erf(v / sqrt(2.0)));"),

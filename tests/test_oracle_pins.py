@@ -710,3 +710,172 @@ def test_between_candidate_sets_of_64():
     with oracle.between_tolerance(+1, 0.05):
         _, _, t_hi, _ = oracle.score(scene, qb, terms=True)
     assert np.all(t_lo <= t + 1e-15) and np.all(t <= t_hi + 1e-15) and np.any(t_hi > t)
+
+
+# ------------------------------------------------- entity Gaussians, stored views
+def _rot(yaw, pitch, roll):
+    cz, sz, cy, sy, cx, sx = (math.cos(yaw), math.sin(yaw), math.cos(pitch), math.sin(pitch), math.cos(roll),
+                              math.sin(roll))
+    Rz = np.array([[cz, -sz, 0], [sz, cz, 0], [0, 0, 1]])
+    Ry = np.array([[cy, 0, sy], [0, 1, 0], [-sy, 0, cy]])
+    Rx = np.array([[1, 0, 0], [0, cx, -sx], [0, sx, cx]])
+    return Rz @ Ry @ Rx
+
+
+def _pack(S):
+    return np.array([S[0, 0], S[0, 1], S[0, 2], S[1, 1], S[1, 2], S[2, 2]])
+
+
+def test_hellinger_near_closed_forms():
+    """Identical Gaussians give 1; equal isotropic Gaussians at distance d give
+    1 - sqrt(1 - exp(-d^2 / (8 s^2))); concentric isotropic ones with sigmas a, b
+    have Bhattacharyya coefficient (2ab / (a^2 + b^2))^(3/2)."""
+    c = [1.0, -2.0, 0.5]
+    cov = _pack(np.diag([0.04, 0.09, 0.01]))
+    assert oracle.hellinger_near(c, cov, c, cov) == pytest.approx(1.0, abs=1e-15)
+    s = 0.25
+    for d in (0.0, 0.1, 0.4, 1.0):
+        cj = [c[0] + d * 0.6, c[1] - d * 0.8, c[2]]
+        want = 1 - math.sqrt(max(0.0, 1 - math.exp(-d * d / (8 * s * s))))
+        got = oracle.hellinger_near(c, _pack(np.eye(3) * s * s), cj, _pack(np.eye(3) * s * s))
+        assert got == pytest.approx(want, rel=1e-6, abs=1e-12), d
+    for a, b in ((0.1, 0.1), (0.1, 0.3), (0.5, 0.125)):
+        bc = (2 * a * b / (a * a + b * b)) ** 1.5
+        got = oracle.hellinger_near(c, _pack(np.eye(3) * a * a), c, _pack(np.eye(3) * b * b))
+        assert got == pytest.approx(1 - math.sqrt(1 - bc), rel=1e-6, abs=1e-12), (a, b)
+
+
+def test_hellinger_near_matches_the_integral():
+    """The Bhattacharyya coefficient is the integral of sqrt(p q) over space: a
+    Riemann sum on a fine grid (spacing far below the smallest sigma, range 7
+    sigma) for rotated, anisotropic, offset Gaussians."""
+    rng = np.random.default_rng(7)
+    for case in range(3):
+        Ra = _rot(*rng.uniform(0, math.pi, 3))
+        Rb = _rot(*rng.uniform(0, math.pi, 3))
+        A = Ra @ np.diag(rng.uniform(0.18, 0.4, 3) ** 2) @ Ra.T
+        B = Rb @ np.diag(rng.uniform(0.18, 0.4, 3) ** 2) @ Rb.T
+        A, B = (np.asarray(_sym_from(_pack(M).astype(np.float32))) for M in (A, B))
+        mu_a = np.zeros(3)
+        mu_b = rng.uniform(-0.3, 0.3, 3).astype(np.float32).astype(np.float64)
+        h = 0.025
+        ax = np.arange(-2.9, 2.9 + h / 2, h)
+        X, Y, Z = np.meshgrid(ax, ax, ax, indexing="ij")
+        P = np.stack([X, Y, Z], axis=-1)
+
+        def logpdf(mu, S):
+            Si = np.linalg.inv(S)
+            D = P - mu
+            return -0.5 * np.einsum("...i,ij,...j->...", D, Si, D) - 0.5 * math.log((2 * math.pi) ** 3 * np.linalg.det(S))
+
+        bc = float(np.exp(0.5 * (logpdf(mu_a, A) + logpdf(mu_b, B))).sum() * h ** 3)
+        want = 1 - math.sqrt(max(0.0, 1 - bc))
+        got = oracle.hellinger_near(mu_a, _pack(A), mu_b, _pack(B))
+        assert got == pytest.approx(want, abs=1e-7), case
+
+
+def _sym_from(p6):
+    a, b, c, d, e, f = (float(v) for v in p6)
+    return [[a, b, c], [b, d, e], [c, e, f]]
+
+
+def test_hellinger_near_symmetric_and_rigid_invariant():
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        Ra, Rb = _rot(*rng.uniform(0, 3, 3)), _rot(*rng.uniform(0, 3, 3))
+        A = Ra @ np.diag(rng.uniform(0.1, 0.5, 3) ** 2) @ Ra.T
+        B = Rb @ np.diag(rng.uniform(0.1, 0.5, 3) ** 2) @ Rb.T
+        ca, cb = rng.uniform(-1, 1, 3), rng.uniform(-1, 1, 3)
+        v = oracle.hellinger_near(ca, _pack(A), cb, _pack(B))
+        assert 0.0 <= v <= 1.0
+        assert oracle.hellinger_near(cb, _pack(B), ca, _pack(A)) == pytest.approx(v, rel=1e-12)
+        Q, t = _rot(*rng.uniform(0, 3, 3)), rng.uniform(-5, 5, 3)
+        w = oracle.hellinger_near(Q @ ca + t, _pack(Q @ A @ Q.T), Q @ cb + t, _pack(Q @ B @ Q.T))
+        assert w == pytest.approx(v, rel=2e-5, abs=1e-6)
+
+
+def _camera(pos, yaw, pitch):
+    """A level pinhole camera at pos looking along (yaw, pitch): [pos, right, down, forward]."""
+    f = np.array([math.cos(pitch) * math.cos(yaw), math.cos(pitch) * math.sin(yaw), math.sin(pitch)])
+    r = np.array([math.sin(yaw), -math.cos(yaw), 0.0])
+    dn = np.cross(f, r)
+    return np.concatenate([pos, r, dn, f]), (r, dn, f)
+
+
+def test_view_predicates_recover_camera_coordinates():
+    """Points placed at known camera-frame coordinates (x, y, z) of a tilted,
+    turned camera: left/right follow the image-plane coordinates x / z, front /
+    behind the depths z, whatever the camera's pose."""
+    sig = lambda v: 1.0 / (1.0 + math.exp(-v))
+    for yaw, pitch in ((0.3, -0.4), (2.5, 0.2), (-1.2, -0.9)):
+        pos = np.array([1.0, -3.0, 1.5])
+        view, (r, dn, f) = _camera(pos, yaw, pitch)
+        world = lambda x, y, z: pos + x * r + y * dn + z * f
+        for (xo, yo, zo), (xa, ya, za) in (((-0.2, 0.1, 2.0), (0.3, -0.2, 3.0)), ((0.5, 0.0, 1.0), (0.1, 0.3, 2.5)),
+                                           ((0.0, 0.0, 1.5), (0.0, 0.0, 1.2))):
+            ci, cj = world(xo, yo, zo).astype(np.float32), world(xa, ya, za).astype(np.float32)
+            vw = view.astype(np.float32)
+            uo, ua = xo / zo, xa / za
+            tol = dict(rel=1e-4, abs=1e-6)  # the float32 rounding of the world coordinates
+            assert oracle.view_predicate(15, vw, ci, cj) == pytest.approx(sig((ua - uo) / 0.05), **tol)
+            assert oracle.view_predicate(16, vw, ci, cj) == pytest.approx(sig((uo - ua) / 0.05), **tol)
+            assert oracle.view_predicate(17, vw, ci, cj) == pytest.approx(sig((za - zo) / 0.1), **tol)
+            assert oracle.view_predicate(18, vw, ci, cj) == pytest.approx(sig((zo - za) / 0.1), **tol)
+
+
+def test_view_predicates_need_both_objects_in_view():
+    view, (r, dn, f) = _camera(np.zeros(3), 0.7, -0.3)
+    world = lambda x, y, z: (x * r + y * dn + z * f).astype(np.float32)
+    vw = view.astype(np.float32)
+    o = world(0.0, 0.0, 2.0)
+    inside = [(0.0, 0.0, 0.15), (1.9, 0.0, 2.0), (0.0, -1.4, 2.0)]
+    outside = [(0.0, 0.0, 0.05), (0.0, 0.0, -2.0), (2.1, 0.0, 2.0), (0.0, 1.6, 2.0)]
+    for p in (15, 16, 17, 18):
+        for c in inside:
+            assert oracle.view_predicate(p, vw, o, world(*c)) > 0.0, (p, c)
+            assert oracle.view_predicate(p, vw, world(*c), o) > 0.0, (p, c)
+        for c in outside:
+            assert oracle.view_predicate(p, vw, o, world(*c)) == 0.0, (p, c)
+            assert oracle.view_predicate(p, vw, world(*c), o) == 0.0, (p, c)
+    # complements for a visible pair
+    a = world(0.4, 0.2, 3.0)
+    assert oracle.view_predicate(15, vw, o, a) + oracle.view_predicate(16, vw, o, a) == pytest.approx(1.0, abs=1e-12)
+    assert oracle.view_predicate(17, vw, o, a) + oracle.view_predicate(18, vw, o, a) == pytest.approx(1.0, abs=1e-12)
+
+
+def _tiny_geometry(seed, n, r, q=3):
+    from synth import GEOMETRY_PREDS, add_entity_geometry
+    scene, qb = _tiny(seed, n, r, q=q)
+    scene = add_entity_geometry(scene, seed)
+    rng = np.random.default_rng(seed + 77)
+    preds = rng.choice(list(GEOMETRY_PREDS) + [NEAR, LEFT_OF], size=qb.rel_pred.shape[0]).astype(np.int32)
+    return scene, QueryBatch(qb.target, qb.target_cls, qb.rel_off, preds, qb.rel_anchor, qb.planted)
+
+
+@pytest.mark.parametrize("n,r", [(2, 1), (5, 2), (7, 3)])
+def test_geometry_predicates_star_decomposition(n, r):
+    """Hellinger Near and the stored-view predicates: the star decomposition
+    equals joint enumeration, whose evaluators (elimination-based Hellinger,
+    basis-vector projection) are written independently."""
+    for seed in range(3):
+        scene, qb = _tiny_geometry(seed * 13 + n + r, n, r)
+        s = oracle.score(scene, qb)
+        bs = np.asarray(brute_scores(scene, qb))
+        np.testing.assert_allclose(s, bs, rtol=1e-12, atol=1e-14)
+
+
+def test_geometry_predicates_need_the_scene_geometry():
+    scene, qb = _tiny_geometry(5, 6, 2)
+    bare = Scene(scene.desc, scene.center, scene.extent, scene.ids, scene.cls, scene.view_right, scene.centroids)
+    for drop in ("cov", "view"):
+        s2 = Scene(scene.desc, scene.center, scene.extent, scene.ids, scene.cls, scene.view_right, scene.centroids,
+                   cov=None if drop == "cov" else scene.cov, view=None if drop == "view" else scene.view)
+        needs = {"cov": [14], "view": [15, 16, 17, 18]}[drop]
+        if np.isin(qb.rel_pred, needs).any():
+            with pytest.raises(ValueError):
+                oracle.score(s2, qb)
+    with pytest.raises(ValueError):
+        oracle.score(bare, qb)
+    # the scene's geometry does not leak into a later call on another scene
+    plain = QueryBatch(qb.target, qb.target_cls, qb.rel_off, np.zeros_like(qb.rel_pred), qb.rel_anchor, qb.planted)
+    np.testing.assert_array_equal(oracle.score(bare, plain), oracle.score(scene, plain))
