@@ -65,6 +65,25 @@
  *                    unless they certify the term, every pair whose bound
  *                    reaches the best value
  *
+ *   over the entity Gaussians and stored views of farm_set_entity_geometry
+ *   (Section "Memory Construction": a 3D Gaussian and representative posed
+ *   views per entity; Section "Robust Relational Object Retrieval",
+ *   implementation paragraph: Hellinger distance for Near; Appendix
+ *   "Retrieval Details", step 4: the viewpoint-dependent predicates in stored
+ *   camera views of the target candidate).  A memory without them answers
+ *   FARM_ERR_UNSUPPORTED to queries that name these:
+ *   FARM_NEAR_HELLINGER  1 - H(N_i, N_j), H^2 = 1 - BC, BC = det(A)^(1/4)
+ *                    det(B)^(1/4) / det(M)^(1/2) exp(-D^T M^-1 D / 8),
+ *                    M = (A + B) / 2, A and B the covariances (means = centers)
+ *   FARM_LEFT_OF_VIEW    sig((u_j - u_i) / 0.05)   FARM_RIGHT_OF_VIEW sig((u_i - u_j) / 0.05)
+ *   FARM_IN_FRONT_OF_VIEW sig((z_j - z_i) / 0.1)   FARM_BEHIND_VIEW   sig((z_i - z_j) / 0.1)
+ *                    (x, y, z) = R_i (c - p_i) the camera coordinates of a
+ *                    center in target i's stored view (camera center p_i,
+ *                    rotation rows right, down, forward), u = x / z its
+ *                    horizontal image-plane coordinate; 0 unless both centers
+ *                    are in the view: z >= 0.1 m, |x| <= z, |y| <= 0.75 z
+ *   These five are evaluated in FP64 and scanned per anchor like Inside.
+ *
  * Conventions shared by every entry point:
  *   - Every function returns a farm_status; farm_last_error() gives a message
  *     for the calling thread's last failure.  Nothing aborts and no C++
@@ -123,9 +142,14 @@ typedef enum {
   FARM_FARTHEST = 10,
   FARM_INSIDE = 11,
   FARM_BETWEEN = 12,
-  FARM_AND = 13           /* the second anchor of the FARM_BETWEEN slot before it */
+  FARM_AND = 13,          /* the second anchor of the FARM_BETWEEN slot before it */
+  FARM_NEAR_HELLINGER = 14,
+  FARM_LEFT_OF_VIEW = 15,
+  FARM_RIGHT_OF_VIEW = 16,
+  FARM_IN_FRONT_OF_VIEW = 17,
+  FARM_BEHIND_VIEW = 18
 } farm_pred;
-#define FARM_NUM_PRED 14        /* predicate ids 0 .. FARM_NUM_PRED - 1 */
+#define FARM_NUM_PRED 19        /* predicate ids 0 .. FARM_NUM_PRED - 1 */
 #define FARM_NUM_PROP_PRED 9    /* predicates with learned anchor lists (network outputs): 0 .. 8 */
 
 #define FARM_MAX_REL 8          /* relations per query */
@@ -163,6 +187,23 @@ FARM_API farm_status farm_build_memory(int64_t n, int32_t d, const float* desc, 
                               const float* extent, const uint32_t* id, const int32_t* cls,
                               float view_right_x, float view_right_y, uint32_t flags, void* stream,
                               farm_memory** out);
+
+/*
+ * Attach entity Gaussians and stored views to a built memory (Section "Memory
+ * Construction": each entity's 3D Gaussian N(mu, Sigma), mu its center, and
+ * its representative posed views), for FARM_NEAR_HELLINGER and the
+ * FARM_*_VIEW predicates.
+ *   cov    device [n][6] FP32 covariances, packed (xx, xy, xz, yy, yz, zz),
+ *          positive definite; or NULL (keep the current ones, if any)
+ *   view   device [n][12] FP32 stored views: camera center (3), then the
+ *          camera's right, down and forward axes in world coordinates (the
+ *          rows of the world-to-camera rotation, orthonormal within 1e-3);
+ *          or NULL (keep the current ones)
+ * The library copies them.  Synchronises `stream` to validate: INVALID_ARG
+ * (naming the first bad object) leaves the memory as it was.  Must not run
+ * while scoring calls on the memory are in flight.
+ */
+FARM_API farm_status farm_set_entity_geometry(farm_memory* mem, const float* cov, const float* view, void* stream);
 
 /* Release a memory handle (synchronises the device first). NULL is a no-op.
    FARM_ERR_BUSY while workspaces created on it or servers it was added to

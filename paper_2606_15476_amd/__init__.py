@@ -17,12 +17,13 @@ from . import _lib
 from ._lib import (FARM_BUILD_BF16, FARM_BUILD_FP8, FARM_MAX_K, FARM_MAX_REL, FARM_NO_ID, F32, BF16, FP8_E4M3,
                    EXHAUSTIVE, BOUNDED, PROPOSAL, OPT_GLOBAL_PROPOSAL_PASS,
                    NEAR, ABOVE, BELOW, LEFT_OF, RIGHT_OF, NEXT_TO, IN_FRONT_OF, BEHIND, ON, CLOSEST,
-                   FARTHEST, INSIDE, BETWEEN, AND, NUM_PRED, NUM_PROP_PRED, FarmError, lib_path)
+                   FARTHEST, INSIDE, BETWEEN, AND, NEAR_HELLINGER, LEFT_OF_VIEW, RIGHT_OF_VIEW,
+                   IN_FRONT_OF_VIEW, BEHIND_VIEW, NUM_PRED, NUM_PROP_PRED, FarmError, lib_path)
 
 __all__ = [
     "Memory", "Workspace", "ProposalNet", "Server", "build_proposals", "build_proposals_by_value", "get_proposals", "score_query", "similarity", "topk", "query_topk", "query_topk_static", "workspace_estimate", "FarmError",
     "FARM_BUILD_BF16", "FARM_BUILD_FP8", "FARM_MAX_K", "FARM_MAX_REL", "FARM_NO_ID", "F32", "BF16",
-    "FP8_E4M3", "EXHAUSTIVE", "BOUNDED", "PROPOSAL", "OPT_GLOBAL_PROPOSAL_PASS", "NEAR", "ABOVE", "BELOW", "LEFT_OF", "RIGHT_OF", "NEXT_TO", "IN_FRONT_OF", "BEHIND", "ON", "CLOSEST", "FARTHEST", "INSIDE", "BETWEEN", "AND", "NUM_PRED",
+    "FP8_E4M3", "EXHAUSTIVE", "BOUNDED", "PROPOSAL", "OPT_GLOBAL_PROPOSAL_PASS", "NEAR", "ABOVE", "BELOW", "LEFT_OF", "RIGHT_OF", "NEXT_TO", "IN_FRONT_OF", "BEHIND", "ON", "CLOSEST", "FARTHEST", "INSIDE", "BETWEEN", "AND", "NEAR_HELLINGER", "LEFT_OF_VIEW", "RIGHT_OF_VIEW", "IN_FRONT_OF_VIEW", "BEHIND_VIEW", "NUM_PRED",
     "NUM_PROP_PRED", "lib_path",
 ]
 
@@ -80,6 +81,16 @@ class Memory:
         if self._h is None:
             raise ValueError("memory was freed")
         return self._h
+
+    def set_entity_geometry(self, cov=None, view=None, stream=None):
+        """farm_set_entity_geometry: entity Gaussians cov [n, 6] (packed xx, xy, xz, yy, yz, zz) and
+        stored views view [n, 12] (camera center, right, down, forward axes), FP32 device tensors;
+        either may be None (kept as it is)."""
+        import torch
+        for name, t, w in (("cov", cov, 6), ("view", view, 12)):
+            if t is not None and (t.dtype != torch.float32 or tuple(t.shape) != (self.n, w) or not t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous float32 [{self.n}, {w}] tensor")
+        _lib.check(_lib.L.farm_set_entity_geometry(self.handle, _ptr(cov), _ptr(view), _stream(stream)))
 
     @property
     def bytes(self) -> int:

@@ -16,14 +16,16 @@ NEAR, ABOVE, BELOW, LEFT_OF, RIGHT_OF = 0, 1, 2, 3, 4
 NEXT_TO, IN_FRONT_OF, BEHIND, ON = 5, 6, 7, 8
 CLOSEST, FARTHEST, INSIDE = 9, 10, 11
 BETWEEN, AND = 12, 13  # ternary Between's slot and the slot of its second anchor
-NUM_PRED, NUM_PROP_PRED = 14, 9  # predicate ids; those with learned anchor lists
+# over entity Gaussians (Hellinger Near) and stored views (farm_set_entity_geometry)
+NEAR_HELLINGER, LEFT_OF_VIEW, RIGHT_OF_VIEW, IN_FRONT_OF_VIEW, BEHIND_VIEW = 14, 15, 16, 17, 18
+NUM_PRED, NUM_PROP_PRED = 19, 9  # predicate ids; those with learned anchor lists
 FARM_MAX_REL = 8
 FARM_MAX_K = 1024
 FARM_NO_ID = 0xFFFFFFFF
 FARM_BUILD_BF16, FARM_BUILD_FP8 = 0x1, 0x2
 
 EXPORTS = (
-    "farm_build_memory", "farm_free_memory", "farm_memory_info", "farm_workspace_create", "farm_workspace_free",
+    "farm_build_memory", "farm_set_entity_geometry", "farm_free_memory", "farm_memory_info", "farm_workspace_create", "farm_workspace_free",
     "farm_workspace_bytes", "farm_workspace_estimate", "farm_score_query", "farm_similarity", "farm_topk", "farm_query_topk", "farm_query_topk_static",
     "farm_workspace_status", "farm_last_error", "farm_version", "farm_workspace_set_timing",
     "farm_workspace_timings", "farm_mlp_create", "farm_mlp_free", "farm_mlp_shape", "farm_mlp_get_weights",
@@ -66,6 +68,7 @@ def _declare(lib):
     pp = ctypes.POINTER(ctypes.c_void_p)
     sig = {
         "farm_build_memory": [i64, i32, P, P, P, P, P, f32, f32, u32, P, pp],
+        "farm_set_entity_geometry": [P, P, P, P],
         "farm_free_memory": [P],
         "farm_memory_info": [P, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(sz)],
         "farm_workspace_create": [P, i32, i32, i32, pp],

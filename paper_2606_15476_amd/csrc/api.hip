@@ -76,6 +76,12 @@ void free_all(std::vector<void*>& allocs) {
     if (st_ != FARM_OK) return st_;     \
   } while (0)
 
+#define FARM_TRY_OR(expr, on_fail)      \
+  do {                                  \
+    farm_status st_ = (expr);           \
+    if (st_ != FARM_OK) return on_fail(st_); \
+  } while (0)
+
 #define FARM_HIP(expr, what)                     \
   do {                                           \
     hipError_t e_ = (expr);                      \
@@ -174,6 +180,14 @@ size_t workspace_bytes_for(const farm_memory* mem, int32_t max_q, int32_t max_re
   return b;
 }
 
+// Relation rows whose terms k_scan_rows takes in the exhaustive method: the
+// rank predicates, Inside, the entity-geometry predicates and the first slot
+// of a Between invocation.
+bool entity_geo_pred(int32_t p) { return p >= FARM_NEAR_HELLINGER && p <= FARM_BEHIND_VIEW; }
+bool scanned_row(int32_t p) {
+  return p == FARM_CLOSEST || p == FARM_FARTHEST || p == FARM_INSIDE || p == FARM_BETWEEN || entity_geo_pred(p);
+}
+
 farm_status check_queries(const farm_memory* mem, const farm_workspace* ws, int32_t q, int32_t d,
                           const float* target, const int32_t* rel_off, const int32_t* rel_pred,
                           const float* rel_anchor, int32_t* r_tot) {
@@ -199,6 +213,16 @@ farm_status check_queries(const farm_memory* mem, const farm_workspace* ws, int3
       set_error("relation %d has predicate id %d", r, rel_pred[r]);
       return FARM_ERR_INVALID_ARG;
     }
+  for (int32_t r = 0; r < R; ++r) {
+    if (rel_pred[r] == FARM_NEAR_HELLINGER && !mem->cov) {
+      set_error("relation %d (FARM_NEAR_HELLINGER) needs entity Gaussians (farm_set_entity_geometry)", r);
+      return FARM_ERR_UNSUPPORTED;
+    }
+    if (rel_pred[r] >= FARM_LEFT_OF_VIEW && rel_pred[r] <= FARM_BEHIND_VIEW && !mem->view) {
+      set_error("relation %d (predicate %d) needs stored views (farm_set_entity_geometry)", r, rel_pred[r]);
+      return FARM_ERR_UNSUPPORTED;
+    }
+  }
   // a Between slot is followed by its second anchor's FARM_AND slot in the same query, and only there
   for (int32_t k = 0; k < q; ++k)
     for (int32_t r = rel_off[k]; r < rel_off[k + 1]; ++r) {
@@ -265,11 +289,12 @@ farm_status stage_meta(farm_workspace* ws, int32_t q, int32_t R, const int32_t* 
   for (int32_t k = 0; k < q; ++k)
     for (int32_t r = rel_off[k]; r < rel_off[k + 1]; ++r) rq[r] = k;
   int32_t* rk = h + 2 * q + 1 + 2 * R;  // rows of the scanned predicates (Closest, Farthest, Inside)
-  int32_t nrank = 0;
+  int32_t nrank = 0, ngeo = 0;
   for (int32_t r = 0; r < R; ++r)
-    if (rel_pred[r] == FARM_CLOSEST || rel_pred[r] == FARM_FARTHEST || rel_pred[r] == FARM_INSIDE ||
-        rel_pred[r] == FARM_BETWEEN)
+    if (scanned_row(rel_pred[r])) {
       rk[nrank++] = r;
+      ngeo += entity_geo_pred(rel_pred[r]) ? 1 : 0;
+    }
   size_t len = (size_t)(2 * q + 1 + 2 * R + nrank);
   FARM_HIP(hipMemcpyAsync(ws->d_meta, h, len * sizeof(int32_t), hipMemcpyHostToDevice, s), "metadata copy");
   FARM_HIP(hipEventRecord(ws->meta_done, s), "metadata event");
@@ -280,6 +305,7 @@ farm_status stage_meta(farm_workspace* ws, int32_t q, int32_t R, const int32_t* 
   view->rel_query = ws->d_meta + 2 * q + 1 + R;
   view->scan_rows = ws->d_meta + 2 * q + 1 + 2 * R;
   view->scan_n = nrank;
+  view->geo_n = ngeo;
   return FARM_OK;
 }
 
@@ -571,12 +597,12 @@ farm_status stage_meta_args(farm_workspace* ws, int32_t q, int32_t R, const int3
   for (int32_t r = 0; r < R; ++r) push(rel_pred[r]);
   for (int32_t k = 0; k < q; ++k)
     for (int32_t r = rel_off[k]; r < rel_off[k + 1]; ++r) push(k);
-  int32_t nrank = 0;
+  int32_t nrank = 0, ngeo = 0;
   for (int32_t r = 0; r < R; ++r)
-    if (rel_pred[r] == FARM_CLOSEST || rel_pred[r] == FARM_FARTHEST || rel_pred[r] == FARM_INSIDE ||
-        rel_pred[r] == FARM_BETWEEN) {
+    if (scanned_row(rel_pred[r])) {
       push(r);
       ++nrank;
+      ngeo += entity_geo_pred(rel_pred[r]) ? 1 : 0;
     }
   flush();
   if (err != hipSuccess) return hip_fail(err, "metadata launch");
@@ -586,6 +612,7 @@ farm_status stage_meta_args(farm_workspace* ws, int32_t q, int32_t R, const int3
   view->rel_query = ws->d_meta + 2 * q + 1 + R;
   view->scan_rows = ws->d_meta + 2 * q + 1 + 2 * R;
   view->scan_n = nrank;
+  view->geo_n = ngeo;
   return FARM_OK;
 }
 
@@ -731,6 +758,67 @@ farm_status farm_build_memory(int64_t n, int32_t d, const float* desc, const flo
   }
 }
 
+farm_status farm_set_entity_geometry(farm_memory* mem, const float* cov, const float* view, void* stream) {
+  try {
+    if (!mem) { set_error("null memory"); return FARM_ERR_INVALID_ARG; }
+    if (!cov && !view) return FARM_OK;
+    DeviceGuard g(mem->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = mem->n;
+    std::vector<void*> cov_allocs, view_allocs, tmp;
+    size_t cov_bytes = 0, view_bytes = 0, tmp_bytes = 0;
+    float* c = nullptr;
+    double* ld = nullptr;
+    float* v = nullptr;
+    int* flags = nullptr;
+    auto fail = [&](farm_status st) {
+      free_all(cov_allocs);
+      free_all(view_allocs);
+      free_all(tmp);
+      return st;
+    };
+    if (cov) {
+      FARM_TRY_OR(dalloc(cov_allocs, cov_bytes, &c, (size_t)n * 6, "entity covariances"), fail);
+      FARM_TRY_OR(dalloc(cov_allocs, cov_bytes, &ld, (size_t)n, "covariance log determinants"), fail);
+    }
+    if (view) FARM_TRY_OR(dalloc(view_allocs, view_bytes, &v, (size_t)n * 12, "stored views"), fail);
+    FARM_TRY_OR(dalloc(tmp, tmp_bytes, &flags, 2, "validation flags"), fail);
+    hipError_t e = launch_fill_i32(flags, 1, 0, s);
+    if (e == hipSuccess) e = launch_fill_i32(flags + 1, 1, INT32_MAX, s);
+    if (e == hipSuccess) e = launch_entity_geometry(cov, view, n, c, ld, v, flags, flags + 1, s);
+    int h[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(h, flags, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(hip_fail(e, "entity geometry"));
+    if (h[0]) {
+      set_error("invalid entity geometry at object %d:%s%s", h[1],
+                (h[0] & kBadCov) ? " covariance not finite or not positive definite;" : "",
+                (h[0] & kBadView) ? " view not finite or its rotation rows not orthonormal;" : "");
+      return fail(FARM_ERR_INVALID_ARG);
+    }
+    free_all(tmp);
+    if (cov) {
+      mem->bytes -= std::min(mem->bytes, (size_t)n * (6 * sizeof(float) + sizeof(double)) * (mem->cov ? 1 : 0));
+      free_all(mem->cov_allocs);
+      mem->cov_allocs = cov_allocs;
+      mem->cov = c;
+      mem->cov_ld = ld;
+      mem->bytes += cov_bytes;
+    }
+    if (view) {
+      mem->bytes -= std::min(mem->bytes, (size_t)n * 12 * sizeof(float) * (mem->view ? 1 : 0));
+      free_all(mem->view_allocs);
+      mem->view_allocs = view_allocs;
+      mem->view = v;
+      mem->bytes += view_bytes;
+    }
+    return FARM_OK;
+  } catch (...) {
+    set_error("unexpected host exception in farm_set_entity_geometry");
+    return FARM_ERR_OOM;
+  }
+}
+
 farm_status farm_free_memory(farm_memory* mem) {
   if (!mem) return FARM_OK;
   if (const int32_t u = mem->users.load(std::memory_order_acquire)) {
@@ -741,6 +829,8 @@ farm_status farm_free_memory(farm_memory* mem) {
   (void)hipDeviceSynchronize();
   free_all(mem->allocs);
   free_all(mem->prop_allocs);
+  free_all(mem->cov_allocs);
+  free_all(mem->view_allocs);
   delete mem;
   return FARM_OK;
 }

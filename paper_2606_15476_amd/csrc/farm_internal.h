@@ -39,6 +39,8 @@ enum : int {
   kBadId = 1 << 4,
   kDupId = 1 << 5,
   kBadQuery = 1 << 6,
+  kBadCov = 1 << 7,   // non-finite or not positive definite covariance
+  kBadView = 1 << 8,  // non-finite view or rotation rows not orthonormal
 };
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
@@ -90,6 +92,12 @@ struct farm_memory {
   float* prop_val = nullptr;    // [P][n][M] predicate value (Near family: log P, others: P)
   float* prop_out = nullptr;    // [P][n] largest predicate value over anchors left out (same domain)
   std::vector<void*> prop_allocs;
+  // entity Gaussians and stored views (farm_set_entity_geometry), structure of
+  // arrays; null when the memory has none
+  float* cov = nullptr;      // [6][n] packed covariances (xx, xy, xz, yy, yz, zz)
+  double* cov_ld = nullptr;  // [n] log det of each covariance
+  float* view = nullptr;     // [12][n] camera center, then its right, down and forward axes
+  std::vector<void*> cov_allocs, view_allocs;
   size_t bytes = 0;
   std::vector<void*> allocs;
   // workspaces created on this memory plus servers it is registered with:
@@ -206,8 +214,9 @@ struct MetaView {
   const int32_t* rel_off;
   const int32_t* rel_pred;
   const int32_t* rel_query;
-  const int32_t* scan_rows = nullptr;  // relation rows of Closest/Farthest/Inside (scan_n of them)
+  const int32_t* scan_rows = nullptr;  // relation rows of the scanned predicates (scan_n of them)
   int32_t scan_n = 0;
+  int32_t geo_n = 0;  // how many of them name an entity-geometry predicate (Gaussians, stored views)
 };
 
 namespace farm {
@@ -263,6 +272,15 @@ struct PropView {
   float* sem_sim_out = nullptr;
 };
 
+// Entity Gaussians and stored views of a memory, passed to kernels by value
+// (null pointers when the memory has none).
+struct EntityGeo {
+  const float* cov = nullptr;      // [6][n]
+  const double* cov_ld = nullptr;  // [n]
+  const float* view = nullptr;     // [12][n]
+};
+inline EntityGeo entity_geo(const farm_memory* m) { return EntityGeo{m->cov, m->cov_ld, m->view}; }
+
 // Whether the proposal pass stages similarity rows of this memory in LDS
 // (and then selects the semantic sets itself).
 bool proposal_pass_in_lds(const farm_memory* mem, bool bounded);
@@ -291,6 +309,12 @@ hipError_t launch_validate_memory(const float* desc, const float* center, const 
 hipError_t launch_normalize_rows(const float* src, int64_t rows, int32_t d, int32_t ldk, float* dst_f32,
                                  const LowPrecRows& lp, int* flags, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+// Validate and lay out entity Gaussians (cov_in [n][6] -> cov [6][n] and
+// cov_ld [n]) and stored views (view_in [n][12] -> view [12][n]); either
+// input may be null.  Raises kBadCov / kBadView in flags and lowers
+// first_bad[0] to the first offending object.
+hipError_t launch_entity_geometry(const float* cov_in, const float* view_in, int64_t n, float* cov, double* cov_ld,
+                                  float* view, int* flags, int* first_bad, hipStream_t s);
 hipError_t launch_geometry(const float* center, const float* extent, int64_t n, float rx, float ry, float* vz,
                            float* x, float* y, float* z, float* hr_hi, float* hr_lo, float* ext,
                            hipStream_t s);

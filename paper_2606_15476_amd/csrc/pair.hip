@@ -103,19 +103,21 @@ __device__ void relation_pass(const float* __restrict__ arow, const float* __res
 // term and anchor outputs are written here when requested.
 constexpr int kScanWaves = 4;
 
+template <bool GEO>
 __global__ __launch_bounds__(64 * kScanWaves) void k_scan_rows(
     const float* __restrict__ sim, float* __restrict__ lsim, int64_t ld_s, int32_t q, MetaView meta,
     const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
     const float* __restrict__ ext, const uint32_t* __restrict__ ids, const int32_t* __restrict__ cls,
     const int32_t* __restrict__ cls_order, const int32_t* __restrict__ cls_sorted, int64_t n,
     float* __restrict__ rel_terms,
-    uint32_t* __restrict__ rel_anchor_id, BetweenView bv) {
+    uint32_t* __restrict__ rel_anchor_id, BetweenView bv, EntityGeo eg) {
   const int lane = threadIdx.x & 63;
   const int64_t o = (int64_t)blockIdx.x * kScanWaves + (threadIdx.x >> 6);
   if (o >= n) return;  // whole waves leave together
   const int r = meta.scan_rows[blockIdx.y];
   const int qq = meta.rel_query[r];
-  if (meta.rel_pred[r] == FARM_BETWEEN) {  // both slots of the invocation: the term and the two anchors
+  if (is_entity_geo(meta.rel_pred[r]) != GEO) return;  // the other instance takes this row
+  if (!GEO && meta.rel_pred[r] == FARM_BETWEEN) {  // both slots of the invocation: the term and the two anchors
     float t;
     uint32_t b1, b2;
     between_term_row(bv, x, y, z, ids, r, o, lane, t, b1, b2);
@@ -132,12 +134,13 @@ __global__ __launch_bounds__(64 * kScanWaves) void k_scan_rows(
     }
     return;
   }
-  const ScanCtx k{x, y, z, ext, ids, cls, cls_order, cls_sorted, meta.tcls[qq], n, meta.rel_pred[r]};
+  ScanCtx k{x, y, z, ext, ids, cls, cls_order, cls_sorted, meta.tcls[qq], n, meta.rel_pred[r]};
+  k.eg = eg;
   const float* arow = sim + (int64_t)(q + r) * ld_s;
   float best;
   uint32_t bid;
   auto sim_of = [&](int64_t a) { return arow[a]; };  // lower bound, upper bound and value alike
-  scan_term_wave(k, o, lane, sim_of, sim_of, sim_of, best, bid);
+  scan_term_wave<GEO>(k, o, lane, sim_of, sim_of, sim_of, best, bid);
   const float t = best > 0.f ? best : 0.f;
   if (lane == 0) {
     lsim[(int64_t)r * ld_s + o] = logf(t);
@@ -297,6 +300,7 @@ __device__ void explain_relation(const float* __restrict__ arow, int64_t n, int6
   __syncthreads();
 }
 
+template <bool GEO>
 __global__ __launch_bounds__(256) void k_explain(const float* __restrict__ sim, int64_t ld_s, int32_t q,
                                                  MetaView meta, const int32_t* __restrict__ idx, int32_t k,
                                                  const float* __restrict__ x, const float* __restrict__ y,
@@ -307,7 +311,7 @@ __global__ __launch_bounds__(256) void k_explain(const float* __restrict__ sim, 
                                                  const int32_t* __restrict__ cls_order,
                                                  const int32_t* __restrict__ cls_sorted,
                                                  int64_t n, float* __restrict__ out_terms,
-                                                 uint32_t* __restrict__ out_anchor_id, BetweenView bv) {
+                                                 uint32_t* __restrict__ out_anchor_id, BetweenView bv, EntityGeo eg) {
   __shared__ float red_v[256];
   __shared__ uint32_t red_id[256];
   const int32_t qq = blockIdx.y, kk = blockIdx.x;
@@ -317,6 +321,9 @@ __global__ __launch_bounds__(256) void k_explain(const float* __restrict__ sim, 
   for (int e = 0; e < kMaxRel; ++e) {
     float tv = 0.f;
     uint32_t b = FARM_NO_ID;
+    // the entity-geometry slots belong to the GEO instance (launched after this one), the rest to the other
+    const bool geo_slot = e < r1 - r0 && is_entity_geo(meta.rel_pred[r0 + e]);
+    if (geo_slot != GEO) continue;
     if (i >= 0 && e < r1 - r0) {
       const int r = r0 + e;
       const int p = meta.rel_pred[r];
@@ -325,7 +332,14 @@ __global__ __launch_bounds__(256) void k_explain(const float* __restrict__ sim, 
       const float* rhi = hhi + (is_depth(p) ? n : 0);  // depth pair of InFrontOf/Behind
       const float* rlo = hlo + (is_depth(p) ? n : 0);
       const ZPair zp = z_for(p, z, vz, n);  // On: bottom/top faces
-      if (p == FARM_BETWEEN || p == FARM_AND) {
+      if (GEO) {
+        ScanCtx rk{x, y, z, ext, ids, cls, cls_order, cls_sorted, meta.tcls[qq], n, p};
+        rk.eg = eg;
+        float bv;
+        auto sim_of = [&](int64_t a) { return arow[a]; };
+        scan_term_wave<true>(rk, i, (int)(threadIdx.x & 63), sim_of, sim_of, sim_of, bv, b);
+        tv = bv > 0.f ? bv : 0.f;
+      } else if (p == FARM_BETWEEN || p == FARM_AND) {
         // the invocation's term from its first slot; the first slot binds a1, the second a2
         const int rb = p == FARM_BETWEEN ? r : r - 1;
         float bt;
@@ -335,12 +349,13 @@ __global__ __launch_bounds__(256) void k_explain(const float* __restrict__ sim, 
         b = p == FARM_BETWEEN ? b1 : b2;
       } else if (is_scanned(p)) {
         // every wave takes the same term (identical arithmetic); thread 0 stores it
-        const ScanCtx rk{x, y, z, ext, ids, cls, cls_order, cls_sorted, meta.tcls[qq], n, p};
+        ScanCtx rk{x, y, z, ext, ids, cls, cls_order, cls_sorted, meta.tcls[qq], n, p};
+        rk.eg = eg;
         float bv;
         auto sim_of = [&](int64_t a) { return arow[a]; };
-        scan_term_wave(rk, i, (int)(threadIdx.x & 63), sim_of, sim_of, sim_of, bv, b);
+        scan_term_wave<false>(rk, i, (int)(threadIdx.x & 63), sim_of, sim_of, sim_of, bv, b);
         tv = bv > 0.f ? bv : 0.f;
-      } else
+      } else if (!GEO)
       switch (family_of(p)) {
         case kFamNear: explain_relation<kFamNear>(arow, n, i, c, x, y, zp, rhi, rlo, ids, red_v, red_id, tv, b); break;
         case kFamVert: explain_relation<kFamVert>(arow, n, i, c, x, y, zp, rhi, rlo, ids, red_v, red_id, tv, b); break;
@@ -445,11 +460,22 @@ hipError_t launch_pair_exhaustive(const farm_memory* mem, const farm_workspace* 
   int64_t n = mem->n;
   if (meta.scan_n > 0) {
     const BetweenView bv{ws->btw_idx, ws->btw_sim, ws->btw_cnt};
-    hipLaunchKernelGGL(k_scan_rows, dim3((unsigned)((n + kScanWaves - 1) / kScanWaves), (unsigned)meta.scan_n),
-                       dim3(64 * kScanWaves), 0, s, sim, const_cast<float*>(lsim), ld_s, q, meta, mem->x, mem->y, mem->z,
-                       mem->ext, mem->id, mem->cls, mem->cls_order, mem->cls_sorted, n, rel_terms, rel_anchor_id, bv);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    // two instances: the entity-geometry rows (FP64) and the others; each skips the other's rows
+    const dim3 grid((unsigned)((n + kScanWaves - 1) / kScanWaves), (unsigned)meta.scan_n);
+    if (meta.scan_n > meta.geo_n) {
+      hipLaunchKernelGGL(k_scan_rows<false>, grid, dim3(64 * kScanWaves), 0, s, sim, const_cast<float*>(lsim), ld_s, q,
+                         meta, mem->x, mem->y, mem->z, mem->ext, mem->id, mem->cls, mem->cls_order, mem->cls_sorted,
+                         n, rel_terms, rel_anchor_id, bv, entity_geo(mem));
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    if (meta.geo_n > 0) {
+      hipLaunchKernelGGL(k_scan_rows<true>, grid, dim3(64 * kScanWaves), 0, s, sim, const_cast<float*>(lsim), ld_s, q,
+                         meta, mem->x, mem->y, mem->z, mem->ext, mem->id, mem->cls, mem->cls_order, mem->cls_sorted,
+                         n, rel_terms, rel_anchor_id, bv, entity_geo(mem));
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
   }
   dim3 grid((unsigned)((n + kTile - 1) / kTile), (unsigned)q);
   if (rel_anchor_id)
@@ -469,10 +495,16 @@ hipError_t launch_explain(const farm_memory* mem, const farm_workspace* ws, cons
   if (q <= 0 || k <= 0 || (!out_terms && !out_anchor_id)) return hipSuccess;
   dim3 grid((unsigned)k, (unsigned)q);
   const BetweenView bv{ws->btw_idx, ws->btw_sim, ws->btw_cnt};
-  hipLaunchKernelGGL(k_explain, grid, dim3(256), 0, s, sim, ld_s, q, meta, idx, k, mem->x, mem->y, mem->z, mem->vz,
-                     mem->hr_hi, mem->hr_lo, mem->id, mem->ext, mem->cls, mem->cls_order, mem->cls_sorted, mem->n,
-                     out_terms,
-                     out_anchor_id, bv);
+  hipLaunchKernelGGL(k_explain<false>, grid, dim3(256), 0, s, sim, ld_s, q, meta, idx, k, mem->x, mem->y, mem->z,
+                     mem->vz, mem->hr_hi, mem->hr_lo, mem->id, mem->ext, mem->cls, mem->cls_order, mem->cls_sorted,
+                     mem->n, out_terms, out_anchor_id, bv, entity_geo(mem));
+  if (meta.geo_n > 0) {  // the entity-geometry slots
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_explain<true>, grid, dim3(256), 0, s, sim, ld_s, q, meta, idx, k, mem->x, mem->y, mem->z,
+                       mem->vz, mem->hr_hi, mem->hr_lo, mem->id, mem->ext, mem->cls, mem->cls_order, mem->cls_sorted,
+                       mem->n, out_terms, out_anchor_id, bv, entity_geo(mem));
+  }
   return hipGetLastError();
 }
 

@@ -52,6 +52,52 @@ __global__ void k_validate(const float* __restrict__ desc, const float* __restri
   (void)d;
 }
 
+// Entity Gaussians and stored views: checks, structure-of-arrays layout and
+// the log determinant of each covariance (FP64, cofactor expansion).
+__global__ void k_entity_geometry(const float* __restrict__ cov_in, const float* __restrict__ view_in, int64_t n,
+                                  float* __restrict__ cov, double* __restrict__ cov_ld, float* __restrict__ view,
+                                  int* __restrict__ flags, int* __restrict__ first_bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int bad = 0;
+  if (cov_in) {
+    float c[6];
+    bool fin = true;
+    for (int k = 0; k < 6; ++k) {
+      c[k] = cov_in[i * 6 + k];
+      fin = fin && finitef(c[k]);
+      cov[k * n + i] = c[k];
+    }
+    const double a = c[0], b = c[1], cc = c[2], d = c[3], e = c[4], f = c[5];
+    const double m2 = a * d - b * b;                                    // leading 2x2 minor
+    const double det = a * (d * f - e * e) - b * (b * f - e * cc) + cc * (b * e - d * cc);
+    if (!fin || !(a > 0.0) || !(m2 > 0.0) || !(det > 0.0)) bad |= kBadCov;  // Sylvester's criterion
+    cov_ld[i] = det > 0.0 ? log(det) : 0.0;
+  }
+  if (view_in) {
+    float v[12];
+    bool fin = true;
+    for (int k = 0; k < 12; ++k) {
+      v[k] = view_in[i * 12 + k];
+      fin = fin && finitef(v[k]);
+      view[k * n + i] = v[k];
+    }
+    // the rotation rows (right, down, forward) must be orthonormal
+    bool ortho = true;
+    for (int r = 0; r < 3; ++r)
+      for (int t = r; t < 3; ++t) {
+        const double g = (double)v[3 + 3 * r] * v[3 + 3 * t] + (double)v[4 + 3 * r] * v[4 + 3 * t] +
+                         (double)v[5 + 3 * r] * v[5 + 3 * t];
+        ortho = ortho && fabs(g - (r == t ? 1.0 : 0.0)) <= 1e-3;
+      }
+    if (!fin || !ortho) bad |= kBadView;
+  }
+  if (bad) {
+    atomicOr(flags, bad);
+    atomicMin(first_bad, (int)i);
+  }
+}
+
 __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -226,6 +272,14 @@ hipError_t launch_normalize_rows(const float* src, int64_t rows, int32_t d, int3
   if (rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_normalize_rows, dim3((unsigned)((rows + kNormRows - 1) / kNormRows)), dim3(64 * kNormRows), 0, s,
                      src, rows, d, ldk, dst_f32, lp, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_entity_geometry(const float* cov_in, const float* view_in, int64_t n, float* cov, double* cov_ld,
+                                  float* view, int* flags, int* first_bad, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_entity_geometry, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cov_in, view_in, n, cov,
+                     cov_ld, view, flags, first_bad);
   return hipGetLastError();
 }
 

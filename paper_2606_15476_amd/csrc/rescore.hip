@@ -178,6 +178,7 @@ struct Geo {
   const int32_t* cls;  // object classes or null (the candidate set of Closest/Farthest)
   const int32_t *cls_order, *cls_sorted;  // objects in class order, their classes
   const float* ext;    // [3][n] full extents (Inside)
+  EntityGeo eg;        // Gaussians and stored views (entity-geometry predicates)
 };
 
 // The coordinates predicate p uses: InFrontOf/Behind take the depth pair
@@ -573,18 +574,20 @@ enum { kTermsFull = 0, kTermsSubset = 1, kTermsFallback = 2 };
 // With the relation's semantic set (sidx, sn) and tau, the largest similarity
 // outside it (plus the error bound for reduced precision), the set goes first
 // and ends the scan when it certifies the term.
+template <bool GEO>
 __device__ inline void scan_term(const Geo& g, int32_t tc, int p, const float* __restrict__ arow,
                                  const float* __restrict__ qrow, const float* __restrict__ dn, int32_t ldk, int64_t n,
                                  int64_t o, bool bounded, float qnr, float qer, const float* __restrict__ o_err,
                                  int lane, float& best, uint32_t& bid, uint32_t& dots,
                                  const int32_t* __restrict__ sidx = nullptr, int sn = 0, float tau = INFINITY) {
-  const ScanCtx k{g.x, g.y, g.z, g.ext, g.ids, g.cls, g.cls_order, g.cls_sorted, tc, n, p};
+  ScanCtx k{g.x, g.y, g.z, g.ext, g.ids, g.cls, g.cls_order, g.cls_sorted, tc, n, p};
+  k.eg = g.eg;
   if (!bounded) {
-    scan_term_wave(
+    scan_term_wave<GEO>(
         k, o, lane, [&](int64_t a) { return arow[a]; }, [&](int64_t a) { return arow[a]; },
         [&](int64_t a) { return arow[a]; }, best, bid, sidx, sn, tau);
   } else {
-    scan_term_wave(
+    scan_term_wave<GEO>(
         k, o, lane, [&](int64_t a) { return fmaxf(0.f, arow[a] - fmaf(qnr, o_err[a], qer)); },
         [&](int64_t a) { return arow[a] + fmaf(qnr, o_err[a], qer); },
         [&](int64_t a) {
@@ -744,7 +747,7 @@ __global__ __launch_bounds__(64 * kTermWaves) void k_rescore_terms(
 // term: every such term of the candidates (SWEEP = false: the bound-pruned
 // method), or those still unresolved (NaN) after the listed fallback (SWEEP =
 // true).  A kernel of its own keeps k_rescore_terms' register budget.
-template <bool BOUNDED, bool SWEEP>
+template <bool BOUNDED, bool SWEEP, bool GEO>
 __global__ __launch_bounds__(64 * kTermWaves) void k_scan_terms(
     const float* __restrict__ sim, int64_t ld_s, int32_t q, MetaView meta, SimBound bound,
     const float* __restrict__ qn, const float* __restrict__ dn, int32_t ldk, const int32_t* __restrict__ cand,
@@ -765,11 +768,12 @@ __global__ __launch_bounds__(64 * kTermWaves) void k_scan_terms(
     const int r = r0 + e;
     const int p = meta.rel_pred[r];
     if (!is_scanned(p) || p == FARM_AND) continue;  // a Between's second slot: written with its first
+    if (is_entity_geo(p) != GEO) continue;           // the other instance takes it
     const int64_t slot = (int64_t)qq * C + tix / R;
     const int64_t o = cand[slot];
     if (o < 0) continue;
     if (SWEEP && !isnan(rs_terms[slot * kMaxRel + e])) continue;
-    if (p == FARM_BETWEEN) {
+    if (!GEO && p == FARM_BETWEEN) {
       float t;
       uint32_t b1, b2;
       between_term_row(BetweenView{pv.btw_idx, pv.btw_sim, pv.btw_cnt}, g.x, g.y, g.z, g.ids, r, o, lane, t, b1, b2);
@@ -791,8 +795,8 @@ __global__ __launch_bounds__(64 * kTermWaves) void k_scan_terms(
     const float tau = sidx ? pv.sem_tau[r] + (BOUNDED ? fmaf(qnr, err_max, qer) : 0.f) : INFINITY;
     float best;
     uint32_t bid;
-    scan_term(geo_for(g, p, n), meta.tcls[qq], p, arow, qrow, dn, ldk, n, o, BOUNDED, qnr, qer, bound.o_err, lane,
-              best, bid, dots, sidx, sn, tau);
+    scan_term<GEO>(geo_for(g, p, n), meta.tcls[qq], p, arow, qrow, dn, ldk, n, o, BOUNDED, qnr, qer, bound.o_err,
+                   lane, best, bid, dots, sidx, sn, tau);
     if (lane == 0) {
       rs_terms[slot * kMaxRel + e] = best;
       rs_anchor[slot * kMaxRel + e] = bid;
@@ -1240,7 +1244,7 @@ __device__ void full_term_block(const float* __restrict__ arow, const float* __r
 // Term of a scanned predicate of target o by a whole fallback block: its waves
 // split the semantic set and then (unless the set certifies the term) the
 // anchor scan, merging (best, id) through LDS after each phase.
-template <bool BOUNDED>
+template <bool BOUNDED, bool GEO>
 __device__ void scan_term_block(const Geo& g, int32_t tc, int p, const float* __restrict__ arow,
                                 const float* __restrict__ qrow, const float* __restrict__ dn, int32_t ldk, int64_t n,
                                 int64_t o, float qnr, float qer, const float* __restrict__ o_err,
@@ -1249,6 +1253,7 @@ __device__ void scan_term_block(const Geo& g, int32_t tc, int p, const float* __
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   constexpr int parts = kFbThreads / 64;
   ScanCtx k{g.x, g.y, g.z, g.ext, g.ids, g.cls, g.cls_order, g.cls_sorted, tc, n, p};
+  k.eg = g.eg;
   rank_range(k);
   auto hi_of = [&](int64_t a) { return BOUNDED ? arow[a] + fmaf(qnr, o_err[a], qer) : arow[a]; };
   auto lo_of = [&](int64_t a) { return BOUNDED ? fmaxf(0.f, arow[a] - fmaf(qnr, o_err[a], qer)) : arow[a]; };
@@ -1275,10 +1280,10 @@ __device__ void scan_term_block(const Geo& g, int32_t tc, int p, const float* __
       }
     }
   };
-  scan_set_part(k, o, lane, exact_of, sidx, sn, w, parts, best, bid);
+  scan_set_part<GEO>(k, o, lane, exact_of, sidx, sn, w, parts, best, bid);
   merge();
   if (!(sn > 0 && best > tau)) {
-    scan_anchor_part(k, o, lane, lo_of, hi_of, exact_of, w, parts, best, bid);
+    scan_anchor_part<GEO>(k, o, lane, lo_of, hi_of, exact_of, w, parts, best, bid);
     merge();
   }
   out_best = best;
@@ -1346,7 +1351,7 @@ __global__ __launch_bounds__(kFbThreads) void k_rescore_fallback(
 // The worklist's terms of scanned predicates (Closest, Farthest, Inside): the
 // block's waves split each term (scan_term_block).  A kernel of its own so
 // that the pairwise fallback keeps its register budget.
-template <bool BOUNDED>
+template <bool BOUNDED, bool GEO>
 __global__ __launch_bounds__(kFbThreads) void k_scan_fallback(
     const float* __restrict__ sim, int64_t ld_s, int32_t q, MetaView meta, SimBound bound,
     const float* __restrict__ qn, const float* __restrict__ dn, int32_t ldk, const int32_t* __restrict__ cand,
@@ -1366,9 +1371,10 @@ __global__ __launch_bounds__(kFbThreads) void k_scan_fallback(
     const int r = r0 + e;
     const int p = meta.rel_pred[r];
     if (!is_scanned(p) || p == FARM_AND) continue;  // block-uniform
+    if (is_entity_geo(p) != GEO) continue;           // the other instance takes it
     const int64_t slot = (int64_t)qq * C + cc;
     const int64_t o = cand[slot];
-    if (p == FARM_BETWEEN) {  // one wave takes the invocation's term (both slots)
+    if (!GEO && p == FARM_BETWEEN) {  // one wave takes the invocation's term (both slots)
       if (threadIdx.x < 64) {
         float t;
         uint32_t b1, b2;
@@ -1392,7 +1398,7 @@ __global__ __launch_bounds__(kFbThreads) void k_scan_fallback(
     const float tau = pv.sem_tau[r] + (BOUNDED ? fmaf(qnr, *bound.o_err_max, qer) : 0.f);
     float best = 0.f;
     uint32_t bid = FARM_NO_ID;
-    scan_term_block<BOUNDED>(geo_for(g, p, n), meta.tcls[qq], p, arow, qrow, dn, ldk, n, o, qnr, qer, bound.o_err,
+    scan_term_block<BOUNDED, GEO>(geo_for(g, p, n), meta.tcls[qq], p, arow, qrow, dn, ldk, n, o, qnr, qer, bound.o_err,
                              pv.sem_idx + (int64_t)r * kSemMax, pv.sem_cnt[r], tau, sv, sid, best, bid, dots);
     if (threadIdx.x == 0) {
       rs_terms[slot * kMaxRel + e] = best;
@@ -1620,7 +1626,7 @@ hipError_t launch_rescore_terms(const farm_memory* mem, const farm_workspace* ws
                                 hipStream_t s) {
   if (q <= 0 || c <= 0) return hipSuccess;
   const Geo g{mem->x, mem->y, mem->z,   mem->z,   mem->hr_hi,     mem->hr_lo,
-              mem->id, mem->vz, mem->cls, mem->cls_order, mem->cls_sorted, mem->ext};
+              mem->id, mem->vz, mem->cls, mem->cls_order, mem->cls_sorted, mem->ext, entity_geo(mem)};
   const dim3 grid(kTermBlocksX, (unsigned)q), block(64 * kTermWaves);
   PropView prop = prop_in;  // with Between's candidate sets
   prop.btw_idx = ws->btw_idx;
@@ -1647,15 +1653,21 @@ hipError_t launch_rescore_terms(const farm_memory* mem, const farm_workspace* ws
                          ws->qn, mem->dn, mem->ldk, cand, c, g, mem->n, ws->rs_terms, ws->rs_anchor, prop);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (meta.scan_n > 0) {  // terms of Closest/Farthest/Inside on the worklist
-      if (bounded)
-        hipLaunchKernelGGL((k_scan_fallback<true>), dim3(blocks), dim3(kFbThreads), 0, s, sim, ld_s, q, meta, bound,
-                           ws->qn, mem->dn, mem->ldk, cand, c, g, mem->n, ws->rs_terms, ws->rs_anchor, prop);
-      else
-        hipLaunchKernelGGL((k_scan_fallback<false>), dim3(blocks), dim3(kFbThreads), 0, s, sim, ld_s, q, meta, bound,
-                           ws->qn, mem->dn, mem->ldk, cand, c, g, mem->n, ws->rs_terms, ws->rs_anchor, prop);
+    // terms of the scanned predicates on the worklist: the entity-geometry ones by an instance of their own
+#define FARM_SCANFB(B, GEO)                                                                                       \
+  hipLaunchKernelGGL((k_scan_fallback<B, GEO>), dim3(blocks), dim3(kFbThreads), 0, s, sim, ld_s, q, meta, bound, \
+                     ws->qn, mem->dn, mem->ldk, cand, c, g, mem->n, ws->rs_terms, ws->rs_anchor, prop)
+    if (meta.scan_n > meta.geo_n) {
+      if (bounded) FARM_SCANFB(true, false);
+      else FARM_SCANFB(false, false);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    if (meta.geo_n > 0) {
+      if (bounded) FARM_SCANFB(true, true);
+      else FARM_SCANFB(false, true);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+#undef FARM_SCANFB
   }
   if (mode == kTermsSubset) {
     const size_t lds = (size_t)round_up(mem->n, 4) * (bounded ? sizeof(uint16_t) : sizeof(float));
@@ -1691,16 +1703,20 @@ hipError_t launch_rescore_terms(const farm_memory* mem, const farm_workspace* ws
   if (meta.scan_n > 0 && mode != kTermsSubset) {  // the scanned predicates' terms
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-#define FARM_SCAN(B, SW)                                                                                         \
-  hipLaunchKernelGGL((k_scan_terms<B, SW>), grid, block, 0, s, sim, ld_s, q, meta, bound, ws->qn, mem->dn,       \
+#define FARM_SCAN(B, SW, GEO)                                                                                    \
+  hipLaunchKernelGGL((k_scan_terms<B, SW, GEO>), grid, block, 0, s, sim, ld_s, q, meta, bound, ws->qn, mem->dn,  \
                      mem->ldk, cand, cand_count, c, g, mem->n, ws->rs_terms, ws->rs_anchor, prop)
     const bool sweep = mode == kTermsFallback;
-    if (bounded) {
-      if (sweep) FARM_SCAN(true, true);
-      else FARM_SCAN(true, false);
-    } else {
-      if (sweep) FARM_SCAN(false, true);
-      else FARM_SCAN(false, false);
+    for (int geo = 0; geo < 2; ++geo) {
+      if (geo ? meta.geo_n == 0 : meta.scan_n == meta.geo_n) continue;
+      if (bounded) {
+        if (sweep) { if (geo) FARM_SCAN(true, true, true); else FARM_SCAN(true, true, false); }
+        else { if (geo) FARM_SCAN(true, false, true); else FARM_SCAN(true, false, false); }
+      } else {
+        if (sweep) { if (geo) FARM_SCAN(false, true, true); else FARM_SCAN(false, true, false); }
+        else { if (geo) FARM_SCAN(false, false, true); else FARM_SCAN(false, false, false); }
+      }
+      if ((e = hipGetLastError()) != hipSuccess) return e;
     }
 #undef FARM_SCAN
   }

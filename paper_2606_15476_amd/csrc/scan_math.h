@@ -31,9 +31,15 @@
 namespace farm {
 
 __device__ inline bool is_rank(int p) { return p == FARM_CLOSEST || p == FARM_FARTHEST; }
+// Predicates over the entity Gaussians / stored views (FP64, O(1) per anchor).
+__device__ inline bool is_entity_geo(int p) { return p >= FARM_NEAR_HELLINGER && p <= FARM_BEHIND_VIEW; }
+// O(1) per anchor: Inside and the entity-geometry predicates.
+__device__ inline bool is_local(int p) { return p == FARM_INSIDE || is_entity_geo(p); }
 // Between and its second-anchor slot are scanned too (between_term_wave): the
 // pairwise kernels and the proposal lists leave them alone.
-__device__ inline bool is_scanned(int p) { return is_rank(p) || p == FARM_INSIDE || p == FARM_BETWEEN || p == FARM_AND; }
+__device__ inline bool is_scanned(int p) {
+  return is_rank(p) || is_local(p) || p == FARM_BETWEEN || p == FARM_AND;
+}
 
 struct ScanCtx {
   const float *x, *y, *z;
@@ -44,8 +50,9 @@ struct ScanCtx {
   const int32_t* cls_sorted;  // their classes, ascending
   int32_t tc;                 // the query's parsed target class (-1: none)
   int64_t n;
-  int p;                      // FARM_CLOSEST, FARM_FARTHEST or FARM_INSIDE
+  int p;                      // a scanned predicate other than Between
   int64_t lo = 0, hi = -1;    // the class's range in cls_order (hi < 0: every object is a candidate)
+  EntityGeo eg{};             // Gaussians and stored views (entity-geometry predicates)
 };
 
 // The candidates' range in the class order: [lower_bound, upper_bound) of tc.
@@ -138,16 +145,88 @@ __device__ inline float inside_value(const ScanCtx& k, int64_t o, int64_t a) {
   return v;
 }
 
-__device__ inline float scan_pred_wave(const ScanCtx& k, int64_t o, int64_t a, int lane) {
-  return k.p == FARM_INSIDE ? inside_value(k, o, a) : rank_pred_wave(k, o, a, lane);
+// Near over the entity Gaussians in FP64: 1 - H, H^2 = 1 - BC, written as
+// H^2 = -expm1(-D) with the Bhattacharyya distance D = q / 8 + log det M / 2 -
+// (log det A + log det B) / 4, M = (A + B) / 2 and q = d^T M^-1 d through the
+// adjugate of M (d the center offset; the FP32 centers are exact in FP64).
+__device__ inline float hellinger_near_value(const ScanCtx& k, int64_t o, int64_t a) {
+  const float* C = k.eg.cov;
+  const int64_t n = k.n;
+  const double m00 = 0.5 * ((double)C[o] + (double)C[a]);
+  const double m01 = 0.5 * ((double)C[n + o] + (double)C[n + a]);
+  const double m02 = 0.5 * ((double)C[2 * n + o] + (double)C[2 * n + a]);
+  const double m11 = 0.5 * ((double)C[3 * n + o] + (double)C[3 * n + a]);
+  const double m12 = 0.5 * ((double)C[4 * n + o] + (double)C[4 * n + a]);
+  const double m22 = 0.5 * ((double)C[5 * n + o] + (double)C[5 * n + a]);
+  const double c00 = m11 * m22 - m12 * m12, c01 = m02 * m12 - m01 * m22, c02 = m01 * m12 - m02 * m11;
+  const double c11 = m00 * m22 - m02 * m02, c12 = m01 * m02 - m00 * m12, c22 = m00 * m11 - m01 * m01;
+  const double det = m00 * c00 + m01 * c01 + m02 * c02;
+  const double dx = (double)k.x[o] - (double)k.x[a], dy = (double)k.y[o] - (double)k.y[a],
+               dz = (double)k.z[o] - (double)k.z[a];
+  const double qf = (c00 * dx * dx + c11 * dy * dy + c22 * dz * dz + 2.0 * (c01 * dx * dy + c02 * dx * dz + c12 * dy * dz)) / det;
+  const double db = 0.125 * qf + 0.5 * log(det) - 0.25 * (k.eg.cov_ld[o] + k.eg.cov_ld[a]);
+  double h2 = -expm1(-db);
+  if (h2 < 0.0) h2 = 0.0;
+  return (float)(1.0 - sqrt(h2));
 }
 
-template <class ExactOf>
+// The stored-view predicates in target o's view, FP64: camera coordinates
+// R (c - p) of both centers; 0 unless both lie in the view (depth >= 0.1 m,
+// |x| <= depth, |y| <= 0.75 depth); then a logistic of the image-plane
+// offset x / z (temperature 0.05) or of the depth offset (0.1 m).
+__device__ inline float view_value(const ScanCtx& k, int64_t o, int64_t a) {
+  const float* V = k.eg.view;
+  const int64_t n = k.n;
+  double v[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) v[c] = V[c * n + o];
+  auto cam = [&](int64_t i, double& xc, double& yc, double& zc) {
+    const double w0 = (double)k.x[i] - v[0], w1 = (double)k.y[i] - v[1], w2 = (double)k.z[i] - v[2];
+    xc = v[3] * w0 + v[4] * w1 + v[5] * w2;
+    yc = v[6] * w0 + v[7] * w1 + v[8] * w2;
+    zc = v[9] * w0 + v[10] * w1 + v[11] * w2;
+  };
+  double xo, yo, zo, xa, ya, za;
+  cam(o, xo, yo, zo);
+  cam(a, xa, ya, za);
+  auto in_view = [](double x, double y, double z) { return z >= 0.1 && fabs(x) <= z && fabs(y) <= 0.75 * z; };
+  if (!in_view(xo, yo, zo) || !in_view(xa, ya, za)) return 0.0f;
+  double arg;
+  switch (k.p) {
+    case FARM_LEFT_OF_VIEW: arg = (xa / za - xo / zo) * 20.0; break;
+    case FARM_RIGHT_OF_VIEW: arg = (xo / zo - xa / za) * 20.0; break;
+    case FARM_IN_FRONT_OF_VIEW: arg = (za - zo) * 10.0; break;
+    default: arg = (zo - za) * 10.0; break;  // FARM_BEHIND_VIEW
+  }
+  return (float)(1.0 / (1.0 + exp(-arg)));
+}
+
+// P(o, a) of the O(1) predicates (every lane computes the same value).  The
+// scans are instantiated twice: GEO for the entity-geometry predicates (FP64,
+// many registers) and !GEO for the others, so that the FP64 code does not
+// weigh on the register budget of the rank, Inside and Between scans.
+template <bool GEO>
+__device__ inline float local_value(const ScanCtx& k, int64_t o, int64_t a) {
+  if constexpr (GEO) {
+    if (k.p == FARM_NEAR_HELLINGER) return hellinger_near_value(k, o, a);
+    return view_value(k, o, a);
+  } else {
+    return inside_value(k, o, a);
+  }
+}
+
+template <bool GEO>
+__device__ inline float scan_pred_wave(const ScanCtx& k, int64_t o, int64_t a, int lane) {
+  if constexpr (GEO) return local_value<true>(k, o, a);
+  else return is_local(k.p) ? local_value<false>(k, o, a) : rank_pred_wave(k, o, a, lane);
+}
+
+template <bool GEO, class ExactOf>
 __device__ inline void scan_visit(const ScanCtx& k, int64_t o, int64_t aa, int lane, ExactOf& exact_of, float& best,
                                   uint32_t& bid) {
   const float s = exact_of(aa);
   if (s < best) return;
-  const float v = s * scan_pred_wave(k, o, aa, lane);
+  const float v = s * scan_pred_wave<GEO>(k, o, aa, lane);
   const uint32_t ida = k.ids[aa];
   if (v > best || (v == best && ida < bid)) {
     best = v;
@@ -155,32 +234,32 @@ __device__ inline void scan_visit(const ScanCtx& k, int64_t o, int64_t aa, int l
   }
 }
 
-template <class ExactOf>
+template <bool GEO, class ExactOf>
 __device__ void scan_set_part(const ScanCtx& k, int64_t o, int lane, ExactOf exact_of, const int32_t* sidx, int sn,
                               int w, int parts, float& best, uint32_t& bid) {
   for (int e = w; e < sn; e += parts) {
     const int64_t aa = __builtin_amdgcn_readfirstlane(sidx[e]);
-    if (aa != o) scan_visit(k, o, aa, lane, exact_of, best, bid);
+    if (aa != o) scan_visit<GEO>(k, o, aa, lane, exact_of, best, bid);
   }
 }
 
-template <class LoOf, class HiOf, class ExactOf>
+template <bool GEO, class LoOf, class HiOf, class ExactOf>
 __device__ void scan_anchor_part(const ScanCtx& k, int64_t o, int lane, LoOf lo_of, HiOf hi_of, ExactOf exact_of, int w,
                                  int parts, float& best, uint32_t& bid) {
-  if (k.p == FARM_INSIDE) {
+  if (GEO || is_local(k.p)) {
     // P costs O(1): each lane bounds its anchor's value by sim_lo * P and
     // sim_hi * P (products round monotonically, so they bound the exact s * P);
     // the largest lower bound L prunes every anchor whose upper bound is below it
     float L = best;
     for (int64_t a0 = (int64_t)64 * w; a0 < k.n; a0 += (int64_t)64 * parts) {
       const int64_t a = a0 + lane;
-      if (a < k.n && a != o) L = fmaxf(L, lo_of(a) * inside_value(k, o, a));
+      if (a < k.n && a != o) L = fmaxf(L, lo_of(a) * local_value<GEO>(k, o, a));
     }
     L = wave_max_scan(L);
     for (int64_t a0 = (int64_t)64 * w; a0 < k.n; a0 += (int64_t)64 * parts) {
       const int64_t a = a0 + lane;
       const bool valid = a < k.n && a != o;
-      const float pv = valid ? inside_value(k, o, a) : 0.f;
+      const float pv = valid ? local_value<GEO>(k, o, a) : 0.f;
       const float hb = valid ? hi_of(a) * pv : -INFINITY;
       uint64_t mask = __ballot(hb >= best && hb >= L);
       while (mask) {
@@ -206,20 +285,20 @@ __device__ void scan_anchor_part(const ScanCtx& k, int64_t o, int lane, LoOf lo_
       const int src = __ffsll((unsigned long long)mask) - 1;
       mask &= mask - 1;
       if (__shfl(h, src) < best) continue;  // the best grew meanwhile
-      scan_visit(k, o, a0 + src, lane, exact_of, best, bid);
+      scan_visit<GEO>(k, o, a0 + src, lane, exact_of, best, bid);
     }
   }
 }
 
-template <class LoOf, class HiOf, class ExactOf>
+template <bool GEO, class LoOf, class HiOf, class ExactOf>
 __device__ void scan_term_wave(ScanCtx k, int64_t o, int lane, LoOf lo_of, HiOf hi_of, ExactOf exact_of, float& out_best,
                                uint32_t& out_bid, const int32_t* sidx = nullptr, int sn = 0,
                                float out_bound = INFINITY) {
   rank_range(k);
   float best = -1.0f;
   uint32_t bid = FARM_NO_ID;
-  scan_set_part(k, o, lane, exact_of, sidx, sn, 0, 1, best, bid);
-  if (!(sn > 0 && best > out_bound)) scan_anchor_part(k, o, lane, lo_of, hi_of, exact_of, 0, 1, best, bid);
+  scan_set_part<GEO>(k, o, lane, exact_of, sidx, sn, 0, 1, best, bid);
+  if (!(sn > 0 && best > out_bound)) scan_anchor_part<GEO>(k, o, lane, lo_of, hi_of, exact_of, 0, 1, best, bid);
   out_best = best;
   out_bid = bid;
 }

@@ -370,6 +370,12 @@ farm_status farm_server_submit(farm_server* sv, int32_t scene, int32_t d, const 
         set_error("FARM_BETWEEN must be followed by FARM_AND (relation %d)", e);
         return FARM_ERR_INVALID_ARG;
       }
+      const farm_memory* m = sv->scenes[scene];
+      if ((preds[e] == FARM_NEAR_HELLINGER && !m->cov) ||
+          (preds[e] >= FARM_LEFT_OF_VIEW && preds[e] <= FARM_BEHIND_VIEW && !m->view)) {
+        set_error("predicate %d needs the scene's entity Gaussians / stored views (relation %d)", preds[e], e);
+        return FARM_ERR_UNSUPPORTED;
+      }
       double a2 = 0.0;
       for (int32_t i = 0; i < d; ++i) {
         const float v = anchors[(size_t)e * d + i];

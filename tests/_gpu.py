@@ -24,6 +24,9 @@ def build_memory(scene, flags=0):
     cls = to_dev(scene.cls) if scene.cls is not None else None
     mem = farm.Memory(to_dev(scene.desc), to_dev(scene.center), to_dev(scene.extent), ids, cls,
                       scene.view_right, flags=flags)
+    cov, view = getattr(scene, "cov", None), getattr(scene, "view", None)
+    if cov is not None or view is not None:
+        mem.set_entity_geometry(None if cov is None else to_dev(cov), None if view is None else to_dev(view))
     return mem
 
 
