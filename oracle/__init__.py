@@ -78,6 +78,8 @@ def _load():
         lib.farm_oracle_hellinger_near.argtypes = [P, P, P, P]
         lib.farm_oracle_view_predicate.restype = ctypes.c_double
         lib.farm_oracle_view_predicate.argtypes = [ctypes.c_int, P, P, P]
+        lib.farm_oracle_set_similarities.restype = None
+        lib.farm_oracle_set_similarities.argtypes = [i32, i32, i64, P, P]
         lib.farm_oracle_set_entity_geometry.restype = None
         lib.farm_oracle_set_entity_geometry.argtypes = [i64, P, P]
         lib.farm_oracle_topk_bounded.restype = ctypes.c_int
@@ -242,6 +244,26 @@ def _query_args(qb):
                  np.zeros((1, qb.target.shape[1]), np.float32), np.float32)
     keep = (tg, tc, ro, rp, ra)
     return keep, [int(tg.shape[0]), pt, ptc, pro, prp, pra]
+
+
+class similarities:
+    """Context manager: inside it the oracle's scoring calls take the unary scores from ``sem``
+    [q, n] (target rows, class factor included) and ``asim`` [r_tot, n] (relation rows) instead of
+    the clamped cosines of the query vectors (oracle/rrf.py's fused scores, for instance)."""
+
+    def __init__(self, sem, asim):
+        self.sem = np.ascontiguousarray(sem, np.float64)
+        self.asim = np.ascontiguousarray(asim, np.float64).reshape(-1, self.sem.shape[1])
+
+    def __enter__(self):
+        p = lambda a: a.ctypes.data_as(ctypes.c_void_p) if a.size else None
+        _load().farm_oracle_set_similarities(self.sem.shape[0], self.asim.shape[0], self.sem.shape[1],
+                                             p(self.sem), p(self.asim))
+        return self
+
+    def __exit__(self, *exc):
+        _load().farm_oracle_set_similarities(-1, -1, -1, None, None)
+        return False
 
 
 def score(scene, qb, terms: bool = False):

@@ -191,22 +191,31 @@ def rank_relation(pred, scene, tcls, i, j):
     return 1.0 / (abs(rank - rstar) + 1)
 
 
-def brute_scores(scene, qb):
-    """Scores [q][n] by enumerating all anchor bindings (list of lists of floats)."""
+def brute_scores(scene, qb, sims=None):
+    """Scores [q][n] by enumerating all anchor bindings (list of lists of floats).  ``sims`` =
+    (sem [q][n], asim [r_tot][n]) replaces the clamped cosines as the unary scores (sem with
+    the class factor already applied)."""
     n = scene.desc.shape[0]
     units = [_unit(scene.desc[i]) for i in range(n)]
     out = []
     for k in range(qb.target.shape[0]):
+        kq = k  # (k is reused by the binding loop below)
         qt = _unit(qb.target[k])
         tcls = int(qb.target_cls[k]) if qb.target_cls is not None else -1
         a0, a1 = int(qb.rel_off[k]), int(qb.rel_off[k + 1])
         rels = [(int(qb.rel_pred[r]), _unit(qb.rel_anchor[r])) for r in range(a0, a1)]
+        if sims is not None:  # unary scores given: the anchor "vector" is the row index
+            rels = [(int(qb.rel_pred[r]), r) for r in range(a0, a1)]
+        if sims is None:
+            asim_of = lambda j, qr: _sim(units[j], qr)
+        else:
+            asim_of = lambda j, r: float(sims[1][r][j])
         row = []
         for e in range(n):
             kappa = 1.0
             if tcls >= 0 and scene.cls is not None and int(scene.cls[e]) >= 0 and int(scene.cls[e]) != tcls:
                 kappa = CLASS_FACTOR
-            s_sem = kappa * _sim(units[e], qt)
+            s_sem = kappa * _sim(units[e], qt) if sims is None else float(sims[0][kq][e])
             if not rels:
                 row.append(s_sem)
                 continue
@@ -222,7 +231,7 @@ def brute_scores(scene, qb):
             domains = []
             for pred, qr in rels:
                 if pred in (12, 13):
-                    order = sorted(range(n), key=lambda j: (-_sim(units[j], qr), int(scene.ids[j])))
+                    order = sorted(range(n), key=lambda j: (-asim_of(j, qr), int(scene.ids[j])))
                     cand = set(order[:BETWEEN_K])
                     domains.append([j for j in others if j in cand])
                 else:
@@ -235,7 +244,7 @@ def brute_scores(scene, qb):
                     if pred == 12:
                         j2 = binding[k + 1]
                         pv = 0.0 if j2 == j else between_relation(scene.center[e], scene.center[j], scene.center[j2])
-                        prod *= _sim(units[j], qr) * _sim(units[j2], rels[k + 1][1]) * pv
+                        prod *= asim_of(j, qr) * asim_of(j2, rels[k + 1][1]) * pv
                         continue
                     if pred in (9, 10):
                         pv = rank_relation(pred, scene, tcls, e, j)
@@ -246,7 +255,7 @@ def brute_scores(scene, qb):
                     else:
                         pv = soft_relation(pred, scene.center[e], scene.center[j], scene.view_right,
                                            scene.extent[e], scene.extent[j])
-                    prod *= _sim(units[j], qr) * pv
+                    prod *= asim_of(j, qr) * pv
                 v = s_sem * ((1 - W) + W * prod ** (1.0 / n_inv))
                 if best is None or v > best:
                     best = v

@@ -385,7 +385,26 @@ typedef struct {
     double* asim;               /* [r][n] sim(j, q_r) */
 } query64;
 
-static int query_init(query64* qs, const scene64* s, const float* target, int32_t tcls,
+/* Unary scores supplied from outside (farm_oracle_set_similarities): the
+ * target rows s_sem [q][n], class factor included, and the relation rows
+ * sim(j, q_r) [r_tot][n] of the next scoring calls, in place of the clamped
+ * cosines of the query vectors -- for a unary score with another definition
+ * (the multi-channel reciprocal-rank fusion of oracle/rrf.py).  NULL: cosines. */
+static const double* g_sim_sem = NULL;
+static const double* g_sim_asim = NULL;
+static int64_t g_sim_n = -1;
+static int32_t g_sim_q = -1, g_sim_r = -1;
+
+void farm_oracle_set_similarities(int32_t q, int32_t r_tot, int64_t n, const double* sem, const double* asim) {
+    g_sim_q = q;
+    g_sim_r = r_tot;
+    g_sim_n = n;
+    g_sim_sem = sem;
+    g_sim_asim = asim;
+}
+
+/* query k of the batch (its relations start at row r0) */
+static int query_init(query64* qs, const scene64* s, int32_t k, int32_t r0, const float* target, int32_t tcls,
                       int r, const int32_t* pred, const float* anchors) {
     int64_t n = s->n;
     int d = s->d;
@@ -395,6 +414,15 @@ static int query_init(query64* qs, const scene64* s, const float* target, int32_
     qs->asim = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * (size_t)(r > 0 ? r : 1));
     double* v = (double*)malloc(sizeof(double) * (size_t)d);
     if (!qs->sem || !qs->asim || !v) { free(v); return -2; }
+    if (g_sim_sem && g_sim_n == n && k < g_sim_q && r0 + r <= g_sim_r) {
+        for (int64_t i = 0; i < n; ++i) qs->sem[i] = g_sim_sem[(size_t)k * n + i];
+        for (int rr = 0; rr < r; ++rr) {
+            qs->pred[rr] = pred[rr];
+            for (int64_t j = 0; j < n; ++j) qs->asim[(size_t)rr * n + j] = g_sim_asim[(size_t)(r0 + rr) * n + j];
+        }
+        free(v);
+        return 0;
+    }
     unit_vector(target, d, v);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
@@ -657,7 +685,7 @@ int farm_oracle_score(int64_t n, int d, const float* desc, const float* center, 
         query64 qs;
         int r = rel_off[k + 1] - rel_off[k];
         int r0 = rel_off[k];
-        if (query_init(&qs, &s, target + (size_t)k * d, target_cls ? target_cls[k] : -1, r,
+        if (query_init(&qs, &s, k, r0, target + (size_t)k * d, target_cls ? target_cls[k] : -1, r,
                        rel_pred + r0, rel_anchor + (size_t)r0 * d)) {
             query_free(&qs);
             err = -2;
@@ -706,7 +734,7 @@ int farm_oracle_score_pairs(int64_t n, int d, const float* desc, const float* ce
         query64 qs;
         int r = rel_off[k + 1] - rel_off[k];
         int r0 = rel_off[k];
-        if (query_init(&qs, &s, target + (size_t)k * d, target_cls ? target_cls[k] : -1, r,
+        if (query_init(&qs, &s, k, r0, target + (size_t)k * d, target_cls ? target_cls[k] : -1, r,
                        rel_pred + r0, rel_anchor + (size_t)r0 * d)) {
             query_free(&qs);
 #pragma omp atomic write
@@ -788,7 +816,7 @@ int farm_oracle_topk_bounded(int64_t n, int d, const float* desc, const float* c
         double* lower = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
         int64_t* sel = (int64_t*)malloc(sizeof(int64_t) * (size_t)k);
         if (!full || !lower || !sel ||
-            query_init(&qs, &s, target + (size_t)qq * d, target_cls ? target_cls[qq] : -1, r,
+            query_init(&qs, &s, qq, r0, target + (size_t)qq * d, target_cls ? target_cls[qq] : -1, r,
                        rel_pred + r0, rel_anchor + (size_t)r0 * d)) {
             free(full); free(lower); free(sel);
 #pragma omp atomic write

@@ -3,9 +3,10 @@
 Each case plants one mistake in a copy of oracle/farm_oracle.c (a sign flip, a
 dropped term, a transposed operand, a missing self-exclusion, a reversed
 tie-break, a wrong constant or derivative), builds it with gcc, and runs the
-oracle pin suites (tests/test_oracle_pins.py, tests/test_oracle_mlp_pins.py)
-against that build in a child process.  Every mutant must fail at least one
-pin; the unmodified oracle passes them in the main suite.
+oracle pin suites (tests/test_oracle_pins.py, tests/test_oracle_mlp_pins.py,
+tests/test_oracle_rrf_pins.py) against that build in a child process.  Every
+mutant must fail at least one pin; the unmodified oracle passes them in the
+main suite.
 """
 import concurrent.futures
 import os
@@ -61,6 +62,9 @@ MUTATIONS = [
     ("in-front-of on world height instead of camera depth",
      "case P_IN_FRONT_OF_V: return logistic((b[2] - a[2]) / ORACLE_TAU);",
      "case P_IN_FRONT_OF_V: return logistic((cj[2] - ci[2]) / ORACLE_TAU);"),
+    ("supplied relation rows read without the query's offset",
+     "qs->asim[(size_t)rr * n + j] = g_sim_asim[(size_t)(r0 + rr) * n + j];",
+     "qs->asim[(size_t)rr * n + j] = g_sim_asim[(size_t)rr * n + j];"),
     ("gelu derivative drops its second term",
      "return 0.5 * (1.0 + erf(v / sqrt(2.0))) + v * exp(-0.5 * v * v) / sqrt(2.0 * M_PI);",
      "return 0.5 * (1.0 + erf(v / sqrt(2.0)));"),
@@ -80,7 +84,8 @@ def _run_mutant(tmp, idx, name, old, new):
     env = dict(os.environ, FARM_ORACLE_LIB=so_path, OMP_NUM_THREADS="2")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_mlp_pins.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_mlp_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_rrf_pins.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return name, r.returncode, r.stdout[-600:]
 
