@@ -374,6 +374,57 @@ FARM_API farm_status farm_query_topk(const farm_memory* mem, farm_workspace* ws,
                             const farm_score_opts* opts, int32_t k, uint32_t* out_id, float* out_score,
                             float* out_terms, uint32_t* out_anchor_id, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Multi-channel reciprocal-rank fusion of the unary scores (Appendix
+ * "Retrieval Details", step 3: the whole pool ranked per query channel, each
+ * channel adding w / (mu + rank), mu = 5; Section "Robust Relational Object
+ * Retrieval", implementation paragraph: unary scores fused over the
+ * retrieval embeddings stored per entity).  The memory holds several
+ * embedding spaces (space 0 is its descriptor table); a query channel is a
+ * query vector in one space with a weight.  For every row (targets, then the
+ * relations' anchors, analogously):
+ *   rank_c(i) = 1 + #{j != i : cos_c(j) > cos_c(i), or equal and id_j < id_i}
+ *   fused(i)  = sum_c w_c / (5 + rank_c(i)) / (sum_c w_c / 6)    in (0, 1]
+ * and the fused target row takes the class factor; the fused rows replace
+ * the clamped cosines as s_sem and sim(a, q_r), and scoring proceeds as in
+ * farm_query_topk.  Cosines are FP32 (the FP32 GEMM); the ranks are exact
+ * for those values.  Cost per channel: one FP32 GEMM over the space, one
+ * bucketed ranking pass per row (quadratic only in the size of groups of
+ * equal-bucket cosines).
+ * ---------------------------------------------------------------------- */
+
+/* Add an embedding space: desc device [n][d] FP32 (any non-zero norms; n =
+   the memory's).  Copies and normalises it.  space_out receives its index
+   (1, 2, ...).  At most 7 added spaces.  Errors: INVALID_ARG (non-finite or
+   zero-norm row, d out of 1..8192), OOM, HIP. */
+FARM_API farm_status farm_add_embedding_space(farm_memory* mem, int32_t d, const float* desc, void* stream,
+                                              int32_t* space_out);
+
+typedef struct {
+  int32_t space;          /* embedding space (0 = the memory's descriptor table) */
+  float weight;           /* w_c > 0 */
+  const float* target;    /* device [q][d_space] the targets' query vectors */
+  const float* anchor;    /* device [R][d_space] the relations' anchor query vectors, or NULL when R = 0 */
+} farm_rrf_channel;
+
+/* The fused rows alone: out device [q + R][n] FP32 (targets, then the relation
+   rows).  channels: host array of n_channels (1..8) entries; other arguments
+   as in farm_query_topk_rrf. */
+FARM_API farm_status farm_rrf_similarity(const farm_memory* mem, farm_workspace* ws, int32_t q, int32_t n_channels,
+                                         const farm_rrf_channel* channels, const int32_t* target_cls,
+                                         const int32_t* rel_off, const int32_t* rel_pred, float* out, void* stream);
+
+/* farm_query_topk with fused unary scores.  opts->dtype must be FARM_F32
+   (the fused rows are exact functions of the FP32 cosines; reduced-precision
+   forms are UNSUPPORTED); every method works.  The workspace allocates its
+   fusion buffers on the first call (one cosine matrix of the workspace's
+   shape and per-row ranking scratch). */
+FARM_API farm_status farm_query_topk_rrf(const farm_memory* mem, farm_workspace* ws, int32_t q, int32_t n_channels,
+                                         const farm_rrf_channel* channels, const int32_t* target_cls,
+                                         const int32_t* rel_off, const int32_t* rel_pred, const farm_score_opts* opts,
+                                         int32_t k, uint32_t* out_id, float* out_score, float* out_terms,
+                                         uint32_t* out_anchor_id, void* stream);
+
 /*
  * farm_query_topk without a workspace and without any allocation, for callers
  * that cannot allocate device memory: code under HIP graph capture, tight

@@ -21,7 +21,7 @@ from ._lib import (FARM_BUILD_BF16, FARM_BUILD_FP8, FARM_MAX_K, FARM_MAX_REL, FA
                    IN_FRONT_OF_VIEW, BEHIND_VIEW, NUM_PRED, NUM_PROP_PRED, FarmError, lib_path)
 
 __all__ = [
-    "Memory", "Workspace", "ProposalNet", "Server", "build_proposals", "build_proposals_by_value", "get_proposals", "score_query", "similarity", "topk", "query_topk", "query_topk_static", "workspace_estimate", "FarmError",
+    "Memory", "Workspace", "ProposalNet", "Server", "build_proposals", "build_proposals_by_value", "get_proposals", "score_query", "similarity", "topk", "query_topk", "rrf_similarity", "query_topk_rrf", "query_topk_static", "workspace_estimate", "FarmError",
     "FARM_BUILD_BF16", "FARM_BUILD_FP8", "FARM_MAX_K", "FARM_MAX_REL", "FARM_NO_ID", "F32", "BF16",
     "FP8_E4M3", "EXHAUSTIVE", "BOUNDED", "PROPOSAL", "OPT_GLOBAL_PROPOSAL_PASS", "NEAR", "ABOVE", "BELOW", "LEFT_OF", "RIGHT_OF", "NEXT_TO", "IN_FRONT_OF", "BEHIND", "ON", "CLOSEST", "FARTHEST", "INSIDE", "BETWEEN", "AND", "NEAR_HELLINGER", "LEFT_OF_VIEW", "RIGHT_OF_VIEW", "IN_FRONT_OF_VIEW", "BEHIND_VIEW", "NUM_PRED",
     "NUM_PROP_PRED", "lib_path",
@@ -81,6 +81,17 @@ class Memory:
         if self._h is None:
             raise ValueError("memory was freed")
         return self._h
+
+    def add_embedding_space(self, desc, stream=None) -> int:
+        """farm_add_embedding_space: another per-entity embedding table desc [n, d] (FP32 device
+        tensor); returns its space index (1, 2, ...)."""
+        import torch
+        if desc.dtype != torch.float32 or desc.dim() != 2 or int(desc.shape[0]) != self.n or not desc.is_contiguous():
+            raise ValueError(f"desc must be a contiguous float32 [{self.n}, d] tensor")
+        sp = ctypes.c_int32()
+        _lib.check(_lib.L.farm_add_embedding_space(self.handle, int(desc.shape[1]), _ptr(desc), _stream(stream),
+                                                   ctypes.byref(sp)))
+        return int(sp.value)
 
     def set_entity_geometry(self, cov=None, view=None, stream=None):
         """farm_set_entity_geometry: entity Gaussians cov [n, 6] (packed xx, xy, xz, yy, yz, zz) and
@@ -222,6 +233,46 @@ def query_topk(mem: Memory, ws: Workspace, target, target_cls, rel_off, rel_pred
                                       _ptr(rel_anchor) if rel_anchor is not None and rel_anchor.numel() else None,
                                       ctypes.byref(opts), int(k), _ptr(out_id), _ptr(out_score), _ptr(out_terms),
                                       _ptr(out_anchor_id), _stream(stream)))
+    del tc, ro, rp
+
+
+def _channels(channels):
+    """[(space, weight, target [q, d_s] tensor, anchor [R, d_s] tensor or None)] -> ctypes array (+ q)."""
+    arr = (_lib.RrfChannel * len(channels))()
+    q = None
+    for i, (sp, w, tgt, anc) in enumerate(channels):
+        q = int(tgt.shape[0]) if q is None else q
+        if int(tgt.shape[0]) != q:
+            raise ValueError("every channel needs the same number of target rows")
+        arr[i] = _lib.RrfChannel(int(sp), float(w), _ptr(tgt),
+                                 _ptr(anc) if anc is not None and anc.numel() else None)
+    return arr, q
+
+
+def rrf_similarity(mem: Memory, ws: Workspace, channels, target_cls, rel_off, rel_pred, out, stream=None):
+    """farm_rrf_similarity: the fused unary rows [q + R, n] into out."""
+    arr, q = _channels(channels)
+    tc, ptc = _host_i32(target_cls)
+    ro, pro = _host_i32(rel_off)
+    rp, prp = _host_i32(rel_pred)
+    _lib.check(_lib.L.farm_rrf_similarity(mem.handle, ws.handle, q, len(channels), arr, ptc, pro, prp, _ptr(out),
+                                          _stream(stream)))
+    del tc, ro, rp
+
+
+def query_topk_rrf(mem: Memory, ws: Workspace, channels, target_cls, rel_off, rel_pred, k: int, out_id, out_score,
+                   out_terms=None, out_anchor_id=None, certified=None, method: int = EXHAUSTIVE, dtype: int = F32,
+                   stream=None):
+    """farm_query_topk_rrf: fused scoring + TopK with multi-channel reciprocal-rank fusion unary scores."""
+    arr, q = _channels(channels)
+    tc, ptc = _host_i32(target_cls)
+    ro, pro = _host_i32(rel_off)
+    rp, prp = _host_i32(rel_pred)
+    cp = _ptr(certified)
+    opts = _lib.ScoreOpts(int(dtype), int(method), 4, 0, cp.value if cp is not None else None)
+    _lib.check(_lib.L.farm_query_topk_rrf(mem.handle, ws.handle, q, len(channels), arr, ptc, pro, prp,
+                                          ctypes.byref(opts), int(k), _ptr(out_id), _ptr(out_score), _ptr(out_terms),
+                                          _ptr(out_anchor_id), _stream(stream)))
     del tc, ro, rp
 
 

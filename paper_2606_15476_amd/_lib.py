@@ -25,7 +25,8 @@ FARM_NO_ID = 0xFFFFFFFF
 FARM_BUILD_BF16, FARM_BUILD_FP8 = 0x1, 0x2
 
 EXPORTS = (
-    "farm_build_memory", "farm_set_entity_geometry", "farm_free_memory", "farm_memory_info", "farm_workspace_create", "farm_workspace_free",
+    "farm_build_memory", "farm_set_entity_geometry", "farm_add_embedding_space", "farm_rrf_similarity",
+    "farm_query_topk_rrf", "farm_free_memory", "farm_memory_info", "farm_workspace_create", "farm_workspace_free",
     "farm_workspace_bytes", "farm_workspace_estimate", "farm_score_query", "farm_similarity", "farm_topk", "farm_query_topk", "farm_query_topk_static",
     "farm_workspace_status", "farm_last_error", "farm_version", "farm_workspace_set_timing",
     "farm_workspace_timings", "farm_mlp_create", "farm_mlp_free", "farm_mlp_shape", "farm_mlp_get_weights",
@@ -53,6 +54,11 @@ class ServerConfig(ctypes.Structure):
                 ("hbm_budget", ctypes.c_size_t)]
 
 
+class RrfChannel(ctypes.Structure):
+    _fields_ = [("space", ctypes.c_int32), ("weight", ctypes.c_float), ("target", ctypes.c_void_p),
+                ("anchor", ctypes.c_void_p)]
+
+
 class ScoreOpts(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int32), ("method", ctypes.c_int32), ("rescore_mult", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("certified", ctypes.c_void_p)]
@@ -69,6 +75,9 @@ def _declare(lib):
     sig = {
         "farm_build_memory": [i64, i32, P, P, P, P, P, f32, f32, u32, P, pp],
         "farm_set_entity_geometry": [P, P, P, P],
+        "farm_add_embedding_space": [P, i32, P, P, P],
+        "farm_rrf_similarity": [P, P, i32, i32, P, P, P, P, P, P],
+        "farm_query_topk_rrf": [P, P, i32, i32, P, P, P, P, P, i32, P, P, P, P, P],
         "farm_free_memory": [P],
         "farm_memory_info": [P, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(sz)],
         "farm_workspace_create": [P, i32, i32, i32, pp],

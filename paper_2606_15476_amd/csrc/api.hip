@@ -188,6 +188,9 @@ bool scanned_row(int32_t p) {
   return p == FARM_CLOSEST || p == FARM_FARTHEST || p == FARM_INSIDE || p == FARM_BETWEEN || entity_geo_pred(p);
 }
 
+farm_status check_meta(const farm_memory* mem, const farm_workspace* ws, int32_t q, const int32_t* rel_off,
+                       const int32_t* rel_pred, int32_t* r_tot);
+
 farm_status check_queries(const farm_memory* mem, const farm_workspace* ws, int32_t q, int32_t d,
                           const float* target, const int32_t* rel_off, const int32_t* rel_pred,
                           const float* rel_anchor, int32_t* r_tot) {
@@ -195,7 +198,17 @@ farm_status check_queries(const farm_memory* mem, const farm_workspace* ws, int3
   if (ws->mem != mem) { set_error("workspace was created for another memory"); return FARM_ERR_INVALID_ARG; }
   if (q < 0 || q > ws->max_q) { set_error("q = %d outside [0, %d]", q, ws->max_q); return FARM_ERR_INVALID_ARG; }
   if (d != mem->d) { set_error("query width %d != memory width %d", d, mem->d); return FARM_ERR_INVALID_ARG; }
-  if (q > 0 && (!target || !rel_off)) { set_error("null target or rel_off"); return FARM_ERR_INVALID_ARG; }
+  if (q > 0 && !target) { set_error("null target"); return FARM_ERR_INVALID_ARG; }
+  FARM_TRY(check_meta(mem, ws, q, rel_off, rel_pred, r_tot));
+  if (*r_tot > 0 && !rel_anchor) { set_error("null rel_anchor"); return FARM_ERR_INVALID_ARG; }
+  return FARM_OK;
+}
+
+// The host metadata of a query batch: CSR offsets, predicate ids, Between
+// pairing, the entity geometry the predicates need.  *r_tot: the relations.
+farm_status check_meta(const farm_memory* mem, const farm_workspace* ws, int32_t q, const int32_t* rel_off,
+                       const int32_t* rel_pred, int32_t* r_tot) {
+  if (q > 0 && !rel_off) { set_error("null rel_off"); return FARM_ERR_INVALID_ARG; }
   if (q == 0) { *r_tot = 0; return FARM_OK; }
   if (rel_off[0] != 0) { set_error("rel_off[0] = %d, expected 0", rel_off[0]); return FARM_ERR_INVALID_ARG; }
   for (int32_t k = 0; k < q; ++k) {
@@ -207,7 +220,7 @@ farm_status check_queries(const farm_memory* mem, const farm_workspace* ws, int3
   }
   int32_t R = rel_off[q];
   if (R > ws->max_rel) { set_error("%d relations exceed the workspace's %d", R, ws->max_rel); return FARM_ERR_INVALID_ARG; }
-  if (R > 0 && (!rel_pred || !rel_anchor)) { set_error("null rel_pred or rel_anchor"); return FARM_ERR_INVALID_ARG; }
+  if (R > 0 && !rel_pred) { set_error("null rel_pred"); return FARM_ERR_INVALID_ARG; }
   for (int32_t r = 0; r < R; ++r)
     if (rel_pred[r] < 0 || rel_pred[r] >= FARM_NUM_PRED) {
       set_error("relation %d has predicate id %d", r, rel_pred[r]);
@@ -317,6 +330,9 @@ float accumulation_bound(int32_t ldk) { return 2.02f * (float)ldk * 5.9604645e-8
 // Steps 2 and 3: normalised query rows and the similarity matrix in `dtype`.
 // need_log: also write lsim (the exhaustive relational pass stages it; the
 // candidate methods take logarithms of the few similarities they gather).
+farm_status similarity_tail(const farm_memory* mem, farm_workspace* ws, int32_t q, int32_t R, const MetaView& meta,
+                            int32_t dtype, bool need_log, bool between, hipStream_t s);
+
 farm_status similarities(const farm_memory* mem, farm_workspace* ws, int32_t q, int32_t R, const float* target,
                          const float* rel_anchor, const MetaView& meta, int32_t dtype, SimBound* bound,
                          bool need_log, bool between, hipStream_t s) {
@@ -362,6 +378,13 @@ farm_status similarities(const farm_memory* mem, farm_workspace* ws, int32_t q, 
              "FP8 similarity GEMM");
     *bound = SimBound{ws->qnrm_fp8, ws->qerr_fp8, mem->err_fp8, mem->err_max + 1, accumulation_bound(ldk)};
   }
+  return similarity_tail(mem, ws, q, R, meta, dtype, need_log, between, s);
+}
+
+// What every form derives from the similarity rows: their logarithms (the
+// exhaustive relational pass) and Between's candidate sets.
+farm_status similarity_tail(const farm_memory* mem, farm_workspace* ws, int32_t q, int32_t R, const MetaView& meta,
+                            int32_t dtype, bool need_log, bool between, hipStream_t s) {
   if (need_log)
     FARM_HIP(launch_log_rows(ws->sim + (int64_t)q * ws->ld_s, ws->ld_s, R, mem->n, ws->lsim, s), "log similarities");
   if (between) {
@@ -381,6 +404,7 @@ struct TopkPlan {
   int32_t dtype = FARM_F32, method = FARM_METHOD_EXHAUSTIVE, opt_flags = 0, c = 0;
   int32_t* certified = nullptr;
   bool between = false;  // the batch has Between invocations
+  bool presim = false;   // ws->sim already holds the unary rows (fused); only derive from them
 };
 
 farm_status plan_topk(const farm_memory* mem, const farm_score_opts* opts, int32_t k, TopkPlan* plan) {
@@ -436,8 +460,11 @@ farm_status query_topk_core(const farm_memory* mem, farm_workspace* ws, int32_t 
   const int32_t dtype = plan.dtype, method = plan.method, opt_flags = plan.opt_flags, c = plan.c;
   int32_t* certified = plan.certified;
   SimBound bound;
-  FARM_TRY(similarities(mem, ws, q, R, target, rel_anchor, meta, dtype, &bound, method == FARM_METHOD_EXHAUSTIVE,
-                        plan.between, s));
+  if (plan.presim)
+    FARM_TRY(similarity_tail(mem, ws, q, R, meta, dtype, method == FARM_METHOD_EXHAUSTIVE, plan.between, s));
+  else
+    FARM_TRY(similarities(mem, ws, q, R, target, rel_anchor, meta, dtype, &bound, method == FARM_METHOD_EXHAUSTIVE,
+                          plan.between, s));
   if (method == FARM_METHOD_BOUNDED || method == FARM_METHOD_PROPOSAL) {
     {
       PhaseTimer t(ws, s, FARM_PHASE_TOPK);
@@ -543,6 +570,117 @@ farm_status query_topk_core(const farm_memory* mem, farm_workspace* ws, int32_t 
 constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
 void* g_scratch_ptr[kMaxDevices] = {};
+
+// ---- reciprocal-rank fusion of the unary scores (farm_query_topk_rrf)
+constexpr int32_t kMaxAddedSpaces = 7;
+constexpr int32_t kMaxChannels = 8;
+constexpr int32_t kRrfMaxBlocks = 1024;
+
+struct SpaceView {
+  int32_t d = 0, ldk = 0;
+  const float* dn = nullptr;
+};
+
+bool space_view(const farm_memory* mem, int32_t sp, SpaceView* v) {
+  if (sp == 0) {
+    *v = SpaceView{mem->d, mem->ldk, mem->dn};
+    return true;
+  }
+  if (sp < 0 || sp > (int32_t)mem->spaces.size()) return false;
+  const farm_memory::Space& e = mem->spaces[(size_t)sp - 1];
+  *v = SpaceView{e.d, e.ldk, e.dn};
+  return true;
+}
+
+farm_status check_channels(const farm_memory* mem, int32_t q, int32_t R, int32_t nch, const farm_rrf_channel* ch) {
+  if (nch < 1 || nch > kMaxChannels || !ch) {
+    set_error("n_channels = %d outside [1, %d] or no channel array", nch, kMaxChannels);
+    return FARM_ERR_INVALID_ARG;
+  }
+  for (int32_t c = 0; c < nch; ++c) {
+    SpaceView v;
+    if (!space_view(mem, ch[c].space, &v)) {
+      set_error("channel %d names embedding space %d (the memory has %d)", c, ch[c].space, 1 + (int)mem->spaces.size());
+      return FARM_ERR_INVALID_ARG;
+    }
+    if (!(ch[c].weight > 0.0f) || !std::isfinite(ch[c].weight)) {
+      set_error("channel %d has weight %g (must be positive and finite)", c, (double)ch[c].weight);
+      return FARM_ERR_INVALID_ARG;
+    }
+    if ((q > 0 && !ch[c].target) || (R > 0 && !ch[c].anchor)) {
+      set_error("channel %d lacks its target or anchor vectors", c);
+      return FARM_ERR_INVALID_ARG;
+    }
+  }
+  return FARM_OK;
+}
+
+// The workspace's fusion buffers, sized for its shape and the memory's widest space.
+farm_status ensure_rrf(const farm_memory* mem, farm_workspace* ws) {
+  int32_t ldk = mem->ldk;
+  for (const farm_memory::Space& e : mem->spaces) ldk = std::max(ldk, e.ldk);
+  if (ws->rrf_cos && ws->rrf_ldk >= ldk) return FARM_OK;
+  free_all(ws->rrf_allocs);
+  ws->rrf_qn = ws->rrf_cos = ws->rrf_val = nullptr;
+  ws->rrf_idx = nullptr;
+  ws->rrf_ldk = ws->rrf_blocks = 0;
+  const int64_t rows = (int64_t)ws->max_q + ws->max_rel;
+  const int32_t blocks = (int32_t)std::min<int64_t>(rows, kRrfMaxBlocks);
+  const int64_t n = std::max<int64_t>(mem->n, 1);
+  size_t bytes = 0;
+  farm_status st = dalloc(ws->rrf_allocs, bytes, &ws->rrf_qn, (size_t)(rows * ldk), "fusion query vectors");
+  if (!st) st = dalloc(ws->rrf_allocs, bytes, &ws->rrf_cos, (size_t)(rows * ws->ld_s), "fusion cosines");
+  if (!st) st = dalloc(ws->rrf_allocs, bytes, &ws->rrf_val, (size_t)(blocks * n), "ranking scratch");
+  if (!st) st = dalloc(ws->rrf_allocs, bytes, &ws->rrf_idx, (size_t)(blocks * n), "ranking scratch");
+  if (st) {
+    free_all(ws->rrf_allocs);
+    ws->rrf_qn = ws->rrf_cos = ws->rrf_val = nullptr;
+    ws->rrf_idx = nullptr;
+    return st;
+  }
+  ws->rrf_ldk = ldk;
+  ws->rrf_blocks = blocks;
+  ws->bytes += bytes;
+  return FARM_OK;
+}
+
+// ws->sim rows [q + R][n] := the fused unary scores of the channels (targets: with the class factor).
+farm_status rrf_fuse(const farm_memory* mem, farm_workspace* ws, int32_t q, int32_t R, int32_t nch,
+                     const farm_rrf_channel* ch, const MetaView& meta, hipStream_t s) {
+  const int32_t rows = q + R;
+  const int64_t n = mem->n;
+  PhaseTimer t(ws, s, FARM_PHASE_GEMM);
+  FARM_HIP(launch_fill_i32(reinterpret_cast<int32_t*>(ws->sim), (int64_t)rows * ws->ld_s, 0, s), "fused rows clear");
+  float total = 0.0f;
+  for (int32_t c = 0; c < nch; ++c) {
+    SpaceView v;
+    space_view(mem, ch[c].space, &v);
+    FARM_HIP(launch_normalize_rows(ch[c].target, q, v.d, v.ldk, ws->rrf_qn, LowPrecRows{}, ws->status, s),
+             "normalize channel targets");
+    FARM_HIP(launch_normalize_rows(ch[c].anchor, R, v.d, v.ldk, ws->rrf_qn + (int64_t)q * v.ldk, LowPrecRows{},
+                                   ws->status, s),
+             "normalize channel anchors");
+    FARM_HIP(launch_gemm_nt_f32(ws->rrf_qn, v.dn, rows, n, v.ldk, ws->rrf_cos, ws->ld_s, s), "channel cosines");
+    FARM_HIP(launch_rrf_rank(ws->rrf_cos, ws->ld_s, rows, n, mem->id, ch[c].weight, ws->sim, ws->rrf_val, ws->rrf_idx,
+                             ws->rrf_blocks, s),
+             "channel ranks");
+    total += ch[c].weight;
+  }
+  // divided by the largest fused value sum(w) / (5 + 1)
+  FARM_HIP(launch_rrf_finish(ws->sim, ws->ld_s, q, rows, n, meta.tcls, mem->cls, 6.0f / total, s), "fused rows");
+  return FARM_OK;
+}
+
+// Shared checks and preparation of the two fusion entry points.
+farm_status rrf_begin(const farm_memory* mem, farm_workspace* ws, int32_t q, int32_t nch, const farm_rrf_channel* ch,
+                      const int32_t* rel_off, const int32_t* rel_pred, int32_t* R) {
+  if (!mem || !ws) { set_error("null memory or workspace"); return FARM_ERR_INVALID_ARG; }
+  if (ws->mem != mem) { set_error("workspace was created for another memory"); return FARM_ERR_INVALID_ARG; }
+  if (q < 0 || q > ws->max_q) { set_error("q = %d outside [0, %d]", q, ws->max_q); return FARM_ERR_INVALID_ARG; }
+  FARM_TRY(check_meta(mem, ws, q, rel_off, rel_pred, R));
+  if (q == 0) return FARM_OK;
+  return check_channels(mem, q, *R, nch, ch);
+}
 
 // Device address of `scratch` on `device`, which must be current: looked up
 // once per device (hipGetSymbolAddress) and kept.
@@ -831,6 +969,7 @@ farm_status farm_free_memory(farm_memory* mem) {
   free_all(mem->prop_allocs);
   free_all(mem->cov_allocs);
   free_all(mem->view_allocs);
+  free_all(mem->space_allocs);
   delete mem;
   return FARM_OK;
 }
@@ -940,6 +1079,7 @@ farm_status farm_workspace_free(farm_workspace* ws) {
   }
   for (hipEvent_t e : ws->ev_pool) (void)hipEventDestroy(e);
   free_all(ws->allocs);
+  free_all(ws->rrf_allocs);
   if (ws->h_meta) (void)hipHostFree(ws->h_meta);
   if (ws->meta_done) (void)hipEventDestroy(ws->meta_done);
   delete ws;
@@ -1153,6 +1293,111 @@ farm_status farm_query_topk_static(const farm_memory* mem, int32_t q, int32_t d,
                            out_anchor_id, s);
   } catch (...) {
     set_error("unexpected host exception in farm_query_topk_static");
+    return FARM_ERR_HIP;
+  }
+}
+
+farm_status farm_add_embedding_space(farm_memory* mem, int32_t d, const float* desc, void* stream, int32_t* space_out) {
+  try {
+    if (!mem || !desc || !space_out) { set_error("null memory, descriptors or output"); return FARM_ERR_INVALID_ARG; }
+    if (d < 1 || d > 8192) { set_error("width %d outside [1, 8192]", d); return FARM_ERR_INVALID_ARG; }
+    if ((int32_t)mem->spaces.size() >= kMaxAddedSpaces) {
+      set_error("the memory already holds %d added embedding spaces", kMaxAddedSpaces);
+      return FARM_ERR_INVALID_ARG;
+    }
+    DeviceGuard g(mem->device);
+    hipStream_t s = (hipStream_t)stream;
+    farm_memory::Space sp;
+    sp.d = d;
+    sp.ldk = (int32_t)round_up(d, kKPad);
+    std::vector<void*> allocs, tmp;
+    size_t bytes = 0, tmp_bytes = 0;
+    int* flags = nullptr;
+    auto fail = [&](farm_status st) {
+      free_all(allocs);
+      free_all(tmp);
+      return st;
+    };
+    FARM_TRY_OR(dalloc(allocs, bytes, &sp.dn, (size_t)(std::max<int64_t>(mem->n, 1) * sp.ldk), "embedding space"),
+                fail);
+    FARM_TRY_OR(dalloc(tmp, tmp_bytes, &flags, 1, "validation flag"), fail);
+    hipError_t e = launch_fill_i32(flags, 1, 0, s);
+    if (e == hipSuccess) e = launch_normalize_rows(desc, mem->n, d, sp.ldk, sp.dn, LowPrecRows{}, flags, s);
+    int h = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, flags, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(hip_fail(e, "embedding space"));
+    if (h) {
+      set_error("invalid embedding space:%s%s", (h & kBadDesc) ? " non-finite value;" : "",
+                (h & kZeroNorm) ? " zero-norm row;" : "");
+      return fail(FARM_ERR_INVALID_ARG);
+    }
+    free_all(tmp);
+    mem->spaces.push_back(sp);
+    mem->space_allocs.insert(mem->space_allocs.end(), allocs.begin(), allocs.end());
+    mem->bytes += bytes;
+    *space_out = (int32_t)mem->spaces.size();
+    return FARM_OK;
+  } catch (...) {
+    set_error("unexpected host exception in farm_add_embedding_space");
+    return FARM_ERR_OOM;
+  }
+}
+
+farm_status farm_rrf_similarity(const farm_memory* mem, farm_workspace* ws, int32_t q, int32_t n_channels,
+                                const farm_rrf_channel* channels, const int32_t* target_cls, const int32_t* rel_off,
+                                const int32_t* rel_pred, float* out, void* stream) {
+  try {
+    FARM_CLAIM(ws);
+    int32_t R = 0;
+    FARM_TRY(rrf_begin(mem, ws, q, n_channels, channels, rel_off, rel_pred, &R));
+    if (q == 0) return FARM_OK;
+    if (!out) { set_error("out is NULL"); return FARM_ERR_INVALID_ARG; }
+    DeviceGuard g(mem->device);
+    hipStream_t s = (hipStream_t)stream;
+    FARM_TRY(ensure_rrf(mem, ws));
+    MetaView meta;
+    FARM_TRY(stage_meta(ws, q, R, target_cls, rel_off, rel_pred, s, &meta));
+    FARM_TRY(rrf_fuse(mem, ws, q, R, n_channels, channels, meta, s));
+    FARM_HIP(hipMemcpy2DAsync(out, (size_t)mem->n * sizeof(float), ws->sim, (size_t)ws->ld_s * sizeof(float),
+                              (size_t)mem->n * sizeof(float), (size_t)(q + R), hipMemcpyDeviceToDevice, s),
+             "fused rows copy");
+    return FARM_OK;
+  } catch (...) {
+    set_error("unexpected host exception in farm_rrf_similarity");
+    return FARM_ERR_HIP;
+  }
+}
+
+farm_status farm_query_topk_rrf(const farm_memory* mem, farm_workspace* ws, int32_t q, int32_t n_channels,
+                                const farm_rrf_channel* channels, const int32_t* target_cls, const int32_t* rel_off,
+                                const int32_t* rel_pred, const farm_score_opts* opts, int32_t k, uint32_t* out_id,
+                                float* out_score, float* out_terms, uint32_t* out_anchor_id, void* stream) {
+  try {
+    FARM_CLAIM(ws);
+    int32_t R = 0;
+    FARM_TRY(rrf_begin(mem, ws, q, n_channels, channels, rel_off, rel_pred, &R));
+    TopkPlan plan;
+    FARM_TRY(plan_topk(mem, opts, k, &plan));
+    if (plan.dtype != FARM_F32) {
+      set_error("fused unary scores need the FP32 form (dtype FARM_F32)");
+      return FARM_ERR_UNSUPPORTED;
+    }
+    if (q == 0) return FARM_OK;
+    plan.between = has_between(rel_pred, R);
+    plan.presim = true;
+    if (!out_id || !out_score) { set_error("null output pointer"); return FARM_ERR_INVALID_ARG; }
+    if (plan.c > ws->max_k) { set_error("k = %d exceeds the workspace's max_k %d", plan.c, ws->max_k); return FARM_ERR_INVALID_ARG; }
+    DeviceGuard g(mem->device);
+    hipStream_t s = (hipStream_t)stream;
+    FARM_TRY(ensure_rrf(mem, ws));
+    MetaView meta;
+    FARM_TRY(stage_meta(ws, q, R, target_cls, rel_off, rel_pred, s, &meta));
+    FARM_TRY(rrf_fuse(mem, ws, q, R, n_channels, channels, meta, s));
+    return query_topk_core(mem, ws, q, R, nullptr, nullptr, meta, plan, k, out_id, out_score, out_terms,
+                           out_anchor_id, s);
+  } catch (...) {
+    set_error("unexpected host exception in farm_query_topk_rrf");
     return FARM_ERR_HIP;
   }
 }

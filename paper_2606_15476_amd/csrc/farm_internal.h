@@ -98,6 +98,14 @@ struct farm_memory {
   double* cov_ld = nullptr;  // [n] log det of each covariance
   float* view = nullptr;     // [12][n] camera center, then its right, down and forward axes
   std::vector<void*> cov_allocs, view_allocs;
+  // further embedding spaces (farm_add_embedding_space): normalised FP32 rows,
+  // zero-padded like dn; spaces[s - 1] is space s (space 0 is dn)
+  struct Space {
+    int32_t d = 0, ldk = 0;
+    float* dn = nullptr;  // [n][ldk]
+  };
+  std::vector<Space> spaces;
+  std::vector<void*> space_allocs;
   size_t bytes = 0;
   std::vector<void*> allocs;
   // workspaces created on this memory plus servers it is registered with:
@@ -162,6 +170,14 @@ struct farm_workspace {
   std::vector<PendingPhase> pending;
   double phase_ms[FARM_PHASE_COUNT] = {0};
   int64_t phase_count[FARM_PHASE_COUNT] = {0};
+  // reciprocal-rank fusion buffers, allocated on first use (farm_query_topk_rrf)
+  float* rrf_qn = nullptr;       // [max_q + max_rel][rrf_ldk] one channel's normalised query vectors
+  int32_t rrf_ldk = 0;
+  float* rrf_cos = nullptr;      // [max_q + max_rel][ld_s] one channel's cosines
+  float* rrf_val = nullptr;      // [rrf_blocks][n] ranking scratch: cosines in bucket order ...
+  int32_t* rrf_idx = nullptr;    // [rrf_blocks][n] ... and their object indices
+  int32_t rrf_blocks = 0;
+  std::vector<void*> rrf_allocs;
   size_t bytes = 0;
   std::vector<void*> allocs;
 };
@@ -331,6 +347,10 @@ hipError_t launch_sim_gemm_fp8(const uint8_t* a, const float* a_scale, const uin
                                const int32_t* row_cls, int64_t n_cls_rows, const int32_t* col_cls,
                                hipStream_t s);
 
+// Plain FP32 "NT" GEMM without epilogue: C[m][n] = <A row, B row> (k a multiple of 32).
+hipError_t launch_gemm_nt_f32(const float* a, const float* b, int64_t m, int64_t n, int32_t ldk, float* c, int64_t ldc,
+                              hipStream_t s);
+
 // Plain BF16 "NT" GEMM for the proposal network: C[m][n] = A[m][k] . B[n][k]^T
 // (+ bias[n]) in FP32, or BF16 GELU(A . B^T + bias) when gelu_bf16_out; k a
 // multiple of 64, leading dimensions in elements (rows 16-byte aligned).
@@ -413,6 +433,15 @@ hipError_t launch_semantic_exact(const farm_memory* mem, const farm_workspace* w
 // largest similarities) and the largest similarity of the anchors outside it.
 hipError_t launch_semantic_sets(const float* sim, int64_t ld_s, int32_t q, int32_t R, int64_t n, int32_t* sem_idx,
                                 int32_t* sem_cnt, float* sem_tau, hipStream_t s);
+
+// ---- rrf.hip
+// Reciprocal-rank fusion: out[row][i] += w / (5 + rank of cos[row][i] in its row), ranks by
+// (cosine descending, id ascending); val/idx: blocks x n scratch.
+hipError_t launch_rrf_rank(const float* cos, int64_t ld, int32_t rows, int64_t n, const uint32_t* ids, float w,
+                           float* out, float* val, int32_t* idx, int32_t blocks, hipStream_t s);
+// out[row][i] *= inv_norm, times the class factor on target rows (row < q).
+hipError_t launch_rrf_finish(float* out, int64_t ld, int32_t q, int32_t rows, int64_t n, const int32_t* tcls,
+                             const int32_t* cls, float inv_norm, hipStream_t s);
 
 // ---- topk.hip
 // Select the top k of each score row.  Writes (key, index) of the winners in

@@ -294,6 +294,18 @@ hipError_t launch_sim_gemm_fp8(const uint8_t* a, const float* a_scale, const uin
   return launch_gemm<kTFP8>(a, a_scale, b, b_scale, m, n, ldk, 1, c, ldc, row_cls, n_cls_rows, col_cls, s);
 }
 
+hipError_t launch_gemm_nt_f32(const float* a, const float* b, int64_t m, int64_t n, int32_t ldk, float* c, int64_t ldc,
+                              hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  const int64_t ld_bytes = (int64_t)ldk * 4;
+  if (ld_bytes % kSlab) return hipErrorInvalidValue;
+  const int64_t tiles_m = (m + kBM - 1) / kBM, tiles_n = (n + kBN - 1) / kBN;
+  hipLaunchKernelGGL((k_sim_gemm<kT32, kEpiBias>), dim3((unsigned)(tiles_m * tiles_n)), dim3(256), 0, s,
+                     reinterpret_cast<const uint8_t*>(a), reinterpret_cast<const uint8_t*>(b), m, n, ld_bytes, ld_bytes,
+                     ld_bytes, static_cast<void*>(c), ldc, nullptr, nullptr, nullptr, 0, nullptr, tiles_m, tiles_n);
+  return hipGetLastError();
+}
+
 hipError_t launch_gemm_nt_bf16(const uint16_t* a, int64_t lda, const uint16_t* b, int64_t ldb, int64_t m, int64_t n,
                                int64_t k, void* c, int64_t ldc, const float* bias, bool gelu_bf16_out, hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;

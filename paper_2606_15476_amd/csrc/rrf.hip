@@ -1,0 +1,166 @@
+// rrf.hip -- multi-channel reciprocal-rank fusion of the unary scores
+// (Appendix "Retrieval Details", step 3: each query channel ranks the whole
+// pool and adds w / (mu + rank), mu = 5).
+//
+// One block ranks one row of a channel's cosines at a time (grid-stride over
+// the rows).  The exact rank of every element -- 1 + the number of elements
+// with a larger cosine, or an equal one and a smaller object id -- comes from
+// a bucketed counting sort: the row's value range is cut into 8192 buckets by
+// a map that is monotone in the value, so every element of an earlier bucket
+// ranks before every element of a later one; a histogram and its prefix sum
+// give each bucket's first rank, the elements are scattered into bucket order
+// (block scratch in global memory, L2-resident), and each element counts the
+// elements of its own bucket that precede it.  Work per row O(n + sum of the
+// squared bucket sizes): linear for cosines spread over their range,
+// quadratic only in the size of groups of (nearly) equal values.
+#include <math.h>
+
+#include "farm_internal.h"
+
+namespace farm {
+namespace {
+
+constexpr int kRrfBuckets = 8192;
+constexpr int kRrfThreads = 256;
+constexpr float kRrfMu = 5.0f;
+
+// Bucket of value v for a row with largest value vmax: non-decreasing as v
+// decreases (a rounded difference, a product with a positive factor and a
+// truncation are each monotone).
+__device__ inline int rrf_bucket(float v, float vmax, float scale) {
+  const float t = (vmax - v) * scale;
+  return t < (float)(kRrfBuckets - 1) ? (int)t : kRrfBuckets - 1;
+}
+
+__global__ __launch_bounds__(kRrfThreads) void k_rrf_rank(const float* __restrict__ cos, int64_t ld, int32_t rows,
+                                                          int64_t n, const uint32_t* __restrict__ ids, float w,
+                                                          float* __restrict__ out, float* __restrict__ sval,
+                                                          int32_t* __restrict__ sidx) {
+  __shared__ int32_t start[kRrfBuckets];  // first position of each bucket (after the scan)
+  __shared__ int32_t fill[kRrfBuckets];   // elements placed so far, then the bucket sizes
+  __shared__ int32_t part[kRrfThreads];
+  __shared__ float red_lo[kRrfThreads / 64], red_hi[kRrfThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  float* val = sval + (int64_t)blockIdx.x * n;
+  int32_t* idx = sidx + (int64_t)blockIdx.x * n;
+  for (int32_t row = blockIdx.x; row < rows; row += gridDim.x) {
+    const float* c = cos + (int64_t)row * ld;
+    // the row's range
+    float lo = INFINITY, hi = -INFINITY;
+    for (int64_t j = tid; j < n; j += kRrfThreads) {
+      const float v = c[j];
+      lo = fminf(lo, v);
+      hi = fmaxf(hi, v);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      lo = fminf(lo, __shfl_xor(lo, off));
+      hi = fmaxf(hi, __shfl_xor(hi, off));
+    }
+    if (lane == 0) {
+      red_lo[wave] = lo;
+      red_hi[wave] = hi;
+    }
+    for (int b = tid; b < kRrfBuckets; b += kRrfThreads) {
+      start[b] = 0;
+      fill[b] = 0;
+    }
+    __syncthreads();
+    lo = red_lo[0];
+    hi = red_hi[0];
+#pragma unroll
+    for (int u = 1; u < kRrfThreads / 64; ++u) {
+      lo = fminf(lo, red_lo[u]);
+      hi = fmaxf(hi, red_hi[u]);
+    }
+    float scale = hi > lo ? (float)(kRrfBuckets - 1) / (hi - lo) : 0.0f;
+    if (!(scale < INFINITY)) scale = 0.0f;  // a range too small to divide: one bucket
+    // histogram
+    for (int64_t j = tid; j < n; j += kRrfThreads) atomicAdd(&start[rrf_bucket(c[j], hi, scale)], 1);
+    __syncthreads();
+    // exclusive prefix sum over the buckets: per-thread runs of 32, then the run totals
+    constexpr int kRun = kRrfBuckets / kRrfThreads;
+    int sum = 0;
+#pragma unroll 4
+    for (int e = 0; e < kRun; ++e) {
+      const int v = start[tid * kRun + e];
+      start[tid * kRun + e] = sum;
+      sum += v;
+    }
+    part[tid] = sum;
+    __syncthreads();
+    if (tid == 0) {
+      int acc = 0;
+      for (int t = 0; t < kRrfThreads; ++t) {
+        const int v = part[t];
+        part[t] = acc;
+        acc += v;
+      }
+    }
+    __syncthreads();
+    {
+      const int add = part[tid];
+#pragma unroll 4
+      for (int e = 0; e < kRun; ++e) start[tid * kRun + e] += add;
+    }
+    __syncthreads();
+    // scatter into bucket order
+    for (int64_t j = tid; j < n; j += kRrfThreads) {
+      const float v = c[j];
+      const int b = rrf_bucket(v, hi, scale);
+      const int p = start[b] + atomicAdd(&fill[b], 1);
+      val[p] = v;
+      idx[p] = (int32_t)j;
+    }
+    __syncthreads();
+    // exact rank: the elements of earlier buckets, plus those of the own bucket that precede
+    for (int64_t p = tid; p < n; p += kRrfThreads) {
+      const float v = val[p];
+      const int32_t i = idx[p];
+      const uint32_t id = ids[i];
+      const int b = rrf_bucket(v, hi, scale);
+      const int s0 = start[b], s1 = s0 + fill[b];
+      int before = 0;
+      for (int e = s0; e < s1; ++e) {
+        const float u = val[e];
+        before += (u > v || (u == v && ids[idx[e]] < id)) ? 1 : 0;
+      }
+      const float rank = (float)(s0 + before + 1);
+      out[(int64_t)row * ld + i] += w / (kRrfMu + rank);
+    }
+    __syncthreads();  // the next row reuses the tables and the scratch
+  }
+}
+
+__global__ void k_rrf_finish(float* __restrict__ out, int64_t ld, int32_t q, int32_t rows, int64_t n,
+                             const int32_t* __restrict__ tcls, const int32_t* __restrict__ cls, float inv_norm) {
+  const int32_t row = blockIdx.y;
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= rows || j >= n) return;
+  float f = inv_norm;
+  if (row < q && cls) {
+    const int32_t tc = tcls[row], oc = cls[j];
+    if (tc >= 0 && oc >= 0 && tc != oc) f *= kClassFactor;
+  }
+  out[(int64_t)row * ld + j] *= f;
+}
+
+}  // namespace
+
+hipError_t launch_rrf_rank(const float* cos, int64_t ld, int32_t rows, int64_t n, const uint32_t* ids, float w,
+                           float* out, float* val, int32_t* idx, int32_t blocks, hipStream_t s) {
+  if (rows <= 0 || n <= 0) return hipSuccess;
+  const int32_t g = rows < blocks ? rows : blocks;
+  hipLaunchKernelGGL(k_rrf_rank, dim3((unsigned)g), dim3(kRrfThreads), 0, s, cos, ld, rows, n, ids, w, out, val, idx);
+  return hipGetLastError();
+}
+
+hipError_t launch_rrf_finish(float* out, int64_t ld, int32_t q, int32_t rows, int64_t n, const int32_t* tcls,
+                             const int32_t* cls, float inv_norm, hipStream_t s) {
+  if (rows <= 0 || n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rrf_finish, dim3((unsigned)((n + 255) / 256), (unsigned)rows), dim3(256), 0, s, out, ld, q,
+                     rows, n, tcls, cls, inv_norm);
+  return hipGetLastError();
+}
+
+}  // namespace farm

@@ -364,6 +364,28 @@ def add_between(cfg: Config, scene: Scene, qb: QueryBatch, seed: int, every: int
         planted=qb.planted)
 
 
+def add_embedding_spaces(cfg: Config, scene: Scene, qb: QueryBatch, dims=(512, 768), seed: int = 0):
+    """Further per-entity embedding spaces and the batch's query vectors in them, standing in for
+    the several retrieval embeddings stored per entity (a caption-text and two image embeddings).
+
+    Space s has class centroids of its own; an entity's embedding is a noisy copy of its class's
+    centroid.  The targets' vectors are noisy centroids of the planted object's class; an anchor's
+    vector is a noisy centroid of the class whose descriptor-space centroid its descriptor-space
+    vector lies closest to (the class it was drawn from).  Returns (spaces [n, d_s] list,
+    target vectors [q, d_s] list, anchor vectors [r_tot, d_s] list)."""
+    rng = np.random.default_rng([seed, 0xE3B5])
+    anchor_cls = (np.asarray(qb.rel_anchor, np.float64) @ scene.centroids.astype(np.float64).T).argmax(axis=1) \
+        if qb.r_tot else np.zeros(0, np.int64)
+    target_cls = scene.cls[np.asarray(qb.planted, np.int64)]
+    spaces, tv, av = [], [], []
+    for d in dims:
+        cent = _unit_rows(rng.standard_normal((scene.centroids.shape[0], d)))
+        spaces.append(np.ascontiguousarray(_noisy(rng, cent[scene.cls], cfg.noise), np.float32))
+        tv.append(np.ascontiguousarray(_noisy(rng, cent[target_cls], cfg.noise), np.float32))
+        av.append(np.ascontiguousarray(_noisy(rng, cent[anchor_cls], cfg.noise), np.float32).reshape(qb.r_tot, d))
+    return spaces, tv, av
+
+
 def make_workload(name: str, **kw):
     cfg = CONFIGS[name]
     scene = make_scene(cfg, n=kw.pop("n", None), seed=kw.pop("scene_seed", None))
