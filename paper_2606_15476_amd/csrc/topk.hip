@@ -7,71 +7,100 @@
 // where ord() maps IEEE floats monotonically onto unsigned integers.  Key 0
 // never arises from a real entry (it would need a NaN score), so it pads.
 //
-// Pass 1 sorts blocks of up to 4096 entries of a row in LDS (bitonic network,
-// 256 threads) and keeps each block's best k; merge passes sort groups of
-// those candidate lists the same way until one list of k remains.  The network
-// is data-oblivious: the cost depends only on the sizes.
+// One block per row.  A first pass takes the largest key of every chunk of
+// consecutive entries (64 entries, more for rows longer than 4096 chunks) and
+// sorts those chunk maxima: the k-th largest of them, L, has at least k keys
+// at or above it (the maxima of the k best chunks), so no key below L can be
+// in the TopK.  A second pass keeps a running list of the best k in LDS and
+// adds the keys >= L of each segment of the row (at most 4096 - k entries), a
+// bitonic sort of the list and the new keys keeping the best k.  For spread
+// scores the keys >= L number little more than k, so the row costs two reads
+// and a few small sorts; a row of equal scores degenerates into sorting every
+// segment, the cost of a full sort.
 #include "farm_internal.h"
 #include "sort_util.h"
 
 namespace farm {
 namespace {
 
-__global__ __launch_bounds__(256) void k_topk_rows(const float* __restrict__ scores, int64_t ld, int64_t n,
-                                                   const uint32_t* __restrict__ ids, int32_t k, int32_t nblk,
-                                                   uint64_t* __restrict__ out_key, int32_t* __restrict__ out_idx) {
-  __shared__ uint64_t keys[kSortMax];
-  __shared__ int32_t idx[kSortMax];
-  const int32_t qq = blockIdx.y, blk = blockIdx.x;
-  const int64_t base = (int64_t)blk * kSortMax;
-  const int cnt = (int)(n - base < kSortMax ? n - base : kSortMax);
-  const int P = pow2_at_least(cnt);
-  const float* row = scores + (int64_t)qq * ld;
-  for (int e = threadIdx.x; e < P; e += blockDim.x) {
-    if (e < cnt) {
-      int64_t i = base + e;
-      keys[e] = make_key(row[i], ids[i]);
-      idx[e] = (int32_t)i;
-    } else {
-      keys[e] = 0;
-      idx[e] = -1;
-    }
+__device__ inline uint64_t wave_max_u64(uint64_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t o = __shfl_xor(v, off);
+    v = o > v ? o : v;
   }
-  __syncthreads();
-  bitonic_desc(keys, idx, P);
-  uint64_t* ok = out_key + ((int64_t)qq * nblk + blk) * k;
-  int32_t* oi = out_idx + ((int64_t)qq * nblk + blk) * k;
-  for (int e = threadIdx.x; e < k; e += blockDim.x) {
-    ok[e] = e < P ? keys[e] : 0;
-    oi[e] = e < P ? idx[e] : -1;
-  }
+  return v;
 }
 
-// Merge groups of `group` candidate lists (each of length k) per row.
-__global__ __launch_bounds__(256) void k_topk_merge(const uint64_t* __restrict__ in_key,
-                                                    const int32_t* __restrict__ in_idx, int32_t nlist, int32_t k,
-                                                    int32_t group, int32_t nout, uint64_t* __restrict__ out_key,
-                                                    int32_t* __restrict__ out_idx) {
+__global__ __launch_bounds__(256) void k_topk_select(const float* __restrict__ scores, int64_t ld, int64_t n,
+                                                     const uint32_t* __restrict__ ids, int32_t k,
+                                                     uint64_t* __restrict__ out_key, int32_t* __restrict__ out_idx) {
   __shared__ uint64_t keys[kSortMax];
   __shared__ int32_t idx[kSortMax];
-  const int32_t qq = blockIdx.y, g = blockIdx.x;
-  const int32_t l0 = g * group;
-  const int32_t nl = nlist - l0 < group ? nlist - l0 : group;
-  const int cnt = nl * k;
-  const int P = pow2_at_least(cnt);
-  const uint64_t* ik = in_key + ((int64_t)qq * nlist + l0) * k;
-  const int32_t* ii = in_idx + ((int64_t)qq * nlist + l0) * k;
-  for (int e = threadIdx.x; e < P; e += blockDim.x) {
-    keys[e] = e < cnt ? ik[e] : 0;
-    idx[e] = e < cnt ? ii[e] : -1;
+  __shared__ int32_t cnt_s;
+  const int32_t qq = blockIdx.x;
+  const float* row = scores + (int64_t)qq * ld;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  // 1. the largest key of every chunk; at most kSortMax chunks
+  int64_t chunk = 64;
+  while ((n + chunk - 1) / chunk > kSortMax) chunk += 64;
+  const int nch = (int)((n + chunk - 1) / chunk);
+  for (int c = wave; c < nch; c += nwave) {
+    uint64_t m = 0;
+    const int64_t c0 = (int64_t)c * chunk, c1 = c0 + chunk < n ? c0 + chunk : n;
+    for (int64_t i = c0 + lane; i < c1; i += 64) {
+      const uint64_t key = make_key(row[i], ids[i]);
+      m = key > m ? key : m;
+    }
+    m = wave_max_u64(m);
+    if (lane == 0) {
+      keys[c] = m;
+      idx[c] = -1;
+    }
+  }
+  int P = pow2_at_least(nch);
+  for (int e = nch + threadIdx.x; e < P; e += blockDim.x) {
+    keys[e] = 0;
+    idx[e] = -1;
   }
   __syncthreads();
   bitonic_desc(keys, idx, P);
-  uint64_t* ok = out_key + ((int64_t)qq * nout + g) * k;
-  int32_t* oi = out_idx + ((int64_t)qq * nout + g) * k;
+  const uint64_t L = nch >= k ? keys[k - 1] : 0;
+  __syncthreads();
+  // 2. running best k over the keys >= L, one segment at a time
+  int have = 0;
+  const int64_t seg = kSortMax - k;
+  for (int64_t s0 = 0; s0 < n; s0 += seg) {
+    if (threadIdx.x == 0) cnt_s = have;
+    __syncthreads();
+    const int64_t s1 = s0 + seg < n ? s0 + seg : n;
+    for (int64_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
+      const uint64_t key = make_key(row[i], ids[i]);
+      if (key >= L) {
+        const int p = atomicAdd(&cnt_s, 1);
+        keys[p] = key;
+        idx[p] = (int32_t)i;
+      }
+    }
+    __syncthreads();
+    const int c = cnt_s;
+    if (c > have) {  // block-uniform
+      P = pow2_at_least(c);
+      for (int e = c + threadIdx.x; e < P; e += blockDim.x) {
+        keys[e] = 0;
+        idx[e] = -1;
+      }
+      __syncthreads();
+      bitonic_desc(keys, idx, P);
+      have = c < k ? c : k;
+    }
+    __syncthreads();
+  }
+  uint64_t* ok = out_key + (int64_t)qq * k;
+  int32_t* oi = out_idx + (int64_t)qq * k;
   for (int e = threadIdx.x; e < k; e += blockDim.x) {
-    ok[e] = keys[e];
-    oi[e] = idx[e];
+    ok[e] = e < have ? keys[e] : 0;
+    oi[e] = e < have ? idx[e] : -1;
   }
 }
 
@@ -90,35 +119,18 @@ __global__ void k_topk_emit(const uint64_t* __restrict__ key, const int32_t* __r
 }  // namespace
 
 int64_t topk_candidate_capacity(int64_t n, int32_t max_q, int32_t max_k) {
-  int64_t nblk = (n + kSortMax - 1) / kSortMax;
-  if (nblk < 1) nblk = 1;
-  return (int64_t)max_q * nblk * max_k;
+  (void)n;
+  return (int64_t)max_q * max_k;  // one list of k per row
 }
 
 hipError_t launch_topk(const farm_memory* mem, farm_workspace* ws, const float* scores, int64_t ld_scores,
                        int32_t q, int32_t k, uint64_t** out_key, int32_t** out_idx, hipStream_t s) {
-  const int64_t n = mem->n;
-  int32_t nblk = (int32_t)((n + kSortMax - 1) / kSortMax);
-  if ((int64_t)q * nblk * k > ws->cand_cap) return hipErrorInvalidValue;
-  int cur = 0;
-  hipLaunchKernelGGL(k_topk_rows, dim3((unsigned)nblk, (unsigned)q), dim3(256), 0, s, scores, ld_scores, n, mem->id,
-                     k, nblk, ws->cand_key[cur], ws->cand_idx[cur]);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  int32_t nlist = nblk;
-  const int32_t group = kSortMax / k >= 2 ? kSortMax / k : 2;
-  while (nlist > 1) {
-    int32_t nout = (nlist + group - 1) / group;
-    hipLaunchKernelGGL(k_topk_merge, dim3((unsigned)nout, (unsigned)q), dim3(256), 0, s, ws->cand_key[cur],
-                       ws->cand_idx[cur], nlist, k, group, nout, ws->cand_key[cur ^ 1], ws->cand_idx[cur ^ 1]);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    cur ^= 1;
-    nlist = nout;
-  }
-  *out_key = ws->cand_key[cur];
-  *out_idx = ws->cand_idx[cur];
-  return hipSuccess;
+  if ((int64_t)q * k > ws->cand_cap || k > kSortMax / 2) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_topk_select, dim3((unsigned)q), dim3(256), 0, s, scores, ld_scores, mem->n, mem->id, k,
+                     ws->cand_key[0], ws->cand_idx[0]);
+  *out_key = ws->cand_key[0];
+  *out_idx = ws->cand_idx[0];
+  return hipGetLastError();
 }
 
 hipError_t launch_topk_emit(const uint64_t* key, const int32_t* idx, int32_t q, int32_t k, uint32_t* out_id,
