@@ -9,10 +9,11 @@
 // a map that is monotone in the value, so every element of an earlier bucket
 // ranks before every element of a later one; a histogram and its prefix sum
 // give each bucket's first rank, the elements are scattered into bucket order
-// (block scratch in global memory, L2-resident), and each element counts the
-// elements of its own bucket that precede it.  Work per row O(n + sum of the
-// squared bucket sizes): linear for cosines spread over their range,
-// quadratic only in the size of groups of (nearly) equal values.
+// (block scratch in global memory, L2-resident), and a wave per bucket counts,
+// for each of its elements, the bucket's elements that precede it (64 elements
+// at a time in registers, compared through shuffles).  Work per row O(n +
+// buckets + sum of the squared bucket sizes): linear for cosines spread over
+// their range, quadratic only in the size of groups of (nearly) equal values.
 #include <math.h>
 
 #include "farm_internal.h"
@@ -113,20 +114,30 @@ __global__ __launch_bounds__(kRrfThreads) void k_rrf_rank(const float* __restric
       idx[p] = (int32_t)j;
     }
     __syncthreads();
-    // exact rank: the elements of earlier buckets, plus those of the own bucket that precede
-    for (int64_t p = tid; p < n; p += kRrfThreads) {
-      const float v = val[p];
-      const int32_t i = idx[p];
-      const uint32_t id = ids[i];
-      const int b = rrf_bucket(v, hi, scale);
-      const int s0 = start[b], s1 = s0 + fill[b];
-      int before = 0;
-      for (int e = s0; e < s1; ++e) {
-        const float u = val[e];
-        before += (u > v || (u == v && ids[idx[e]] < id)) ? 1 : 0;
+    // exact rank: the elements of earlier buckets, plus those of the own bucket that precede.
+    // One wave per bucket: 64 of its elements at a time in registers, each compared with every
+    // element of the bucket through shuffles.
+    for (int b = wave; b < kRrfBuckets; b += kRrfThreads / 64) {
+      const int s0 = start[b], nb = fill[b];
+      for (int c0 = 0; c0 < nb; c0 += 64) {
+        const bool mine = c0 + lane < nb;
+        const float v = mine ? val[s0 + c0 + lane] : 0.0f;
+        const int32_t i = mine ? idx[s0 + c0 + lane] : 0;
+        const uint32_t id = mine ? ids[i] : 0u;
+        int before = 0;
+        for (int c1 = 0; c1 < nb; c1 += 64) {
+          const bool theirs = c1 + lane < nb;
+          const float u = theirs ? val[s0 + c1 + lane] : 0.0f;
+          const uint32_t uid = theirs ? ids[idx[s0 + c1 + lane]] : 0u;
+          const int cnt = nb - c1 < 64 ? nb - c1 : 64;
+          for (int t = 0; t < cnt; ++t) {
+            const float ut = __shfl(u, t);
+            const uint32_t it = __shfl(uid, t);
+            before += (ut > v || (ut == v && it < id)) ? 1 : 0;
+          }
+        }
+        if (mine) out[(int64_t)row * ld + i] += w / (kRrfMu + (float)(s0 + before + 1));
       }
-      const float rank = (float)(s0 + before + 1);
-      out[(int64_t)row * ld + i] += w / (kRrfMu + rank);
     }
     __syncthreads();  // the next row reuses the tables and the scratch
   }
