@@ -60,10 +60,16 @@ def _oracle_rows(scene, qb, spaces, channels, mode=0):
                             EPS if mode else 0.0)
 
 
-def test_fused_rows_elementwise(farm):
+@pytest.mark.parametrize("seed,n", [(61, 1500), (65, 26000)])
+def test_fused_rows_elementwise(farm, seed, n):
+    """n = 1,500: rows ranked in LDS; n = 26,000: rows too long for LDS, ranked through global scratch.
+    The long case also plants exact ties: 200 objects whose embeddings in the second space copy those
+    of 200 others, so their cosines are equal and only the ids order them."""
     import torch
     from tests import _gpu
-    cfg, scene, qb, spaces, channels = _world(61)
+    cfg, scene, qb, spaces, channels = _world(seed, n=n, q=24 if n < 20000 else 6)
+    if n > 20000:
+        spaces[1][200:400] = spaces[1][0:200]
     mem = _gpu.build_memory(scene)
     dch = _device_channels(farm, mem, spaces, channels)
     ws = farm.Workspace(mem, qb.q, max(qb.r_tot, 1), 16)
