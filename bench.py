@@ -37,8 +37,12 @@ sys.path.insert(0, ROOT)
 
 # Published MI355X peaks
 PEAK_HBM_GBS = 8000.0
-PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_MFMA_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
+# VALU issue peak from the unit counts and clock: 256 CUs x 4 SIMDs x 16 lanes
+# x 2.4 GHz (one wave64 instruction per SIMD every 4 cycles), in tera lane
+# operations per second.  The published FP32 vector figure (157.3 TFLOP/s)
+# counts packed FP32 FMAs, which this library's kernels do not use.
+PEAK_VALU_TLANE_OPS = 39.3216  # = 256 * 4 * 16 * 2.4e9 / 1e12
 
 # Algorithmic floating-point operations of one (target, anchor) evaluation,
 # counted on the definition (offsets, squares/products, scaling by 1/tau or
@@ -74,6 +78,23 @@ def recorded_traffic(kernel: str, workload: str):
     if hashlib.sha256(src).hexdigest()[:16] != rec["sha256_prefix"]:
         return None
     return float(rec["bytes_per_launch"])
+
+
+def recorded_valu(kernel: str, workload: str):
+    """VALU instruction counts of `kernel` from the committed counter record
+    (profiles/valu.json), or None when there is none for this workload or the
+    kernel's source file has changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "valu.json")))["kernels"][kernel]
+    except (OSError, KeyError, ValueError):
+        return None
+    if rec.get("workload") != workload:
+        return None
+    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    if hashlib.sha256(src).hexdigest()[:16] != rec["sha256_prefix"]:
+        return None
+    return rec
 
 
 def parse(argv=None):
@@ -464,12 +485,24 @@ def dominant_roofline(phases, scene, qb, args, cfg, proposal_info):
     ms, launches = timed[dominant]
     avg_s = ms / launches / 1e3
     if dominant == "pair":
-        flop = sum(FLOP_PER_PAIR.get(int(p), 0) for p in qb.rel_pred) * float(n) * (n - 1)
-        achieved = flop / avg_s / 1e12
-        return {"bound": "alu", "kernel": "k_pair_exhaustive", "achieved": round(achieved, 3),
-                "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
-                "traffic": recorded_traffic("k_pair_exhaustive", cfg.name),
-                "pair_evals_per_launch": float(R) * n * (n - 1), "avg_launch_ms": round(avg_s * 1e3, 3)}
+        # ALU: the FP32 arithmetic VALU instructions (add, mul, FMA, transcendental) per
+        # (relation, target, anchor) pair from the committed counter record, times the
+        # launch's pairs, against the VALU issue peak; the fraction of all VALU
+        # instructions (moves, selects, compares included) is reported beside it
+        pairs = float(R) * n * (n - 1)
+        rec = recorded_valu("k_pair_exhaustive", cfg.name)
+        out = {"bound": "alu", "kernel": "k_pair_exhaustive", "achieved": None, "peak": PEAK_VALU_TLANE_OPS,
+               "unit": "T FP32 VALU lane-ops/s", "frac": None, "traffic": recorded_traffic("k_pair_exhaustive", cfg.name),
+               "pair_evals_per_launch": pairs, "avg_launch_ms": round(avg_s * 1e3, 3)}
+        if rec:
+            arith = rec["fp32_arith_insts"] * 64.0 / rec["pair_evals"]
+            every = rec["sq_insts_valu"] * 64.0 / rec["pair_evals"]
+            achieved = arith * pairs / avg_s / 1e12
+            out.update(achieved=round(achieved, 3), frac=round(achieved / PEAK_VALU_TLANE_OPS, 4),
+                       fp32_arith_lane_ops_per_pair=round(arith, 3), valu_lane_instr_per_pair=round(every, 3),
+                       valu_issue_frac=round(every * pairs / avg_s / 1e12 / PEAK_VALU_TLANE_OPS, 4),
+                       counts_from="profiles/valu.json (rocprofv3 SQ_INSTS_VALU and its classes)")
+        return out
     if dominant == "gemm":
         flop = 2.0 * (q + R) * n * scene.d
         achieved = flop / avg_s / 1e12
@@ -520,11 +553,12 @@ def dominant_roofline(phases, scene, qb, args, cfg, proposal_info):
         n_terms, kernel = float(info.get("fallback_rate", 0.0) * terms), "k_rescore_fallback"
     else:
         n_terms, kernel = float(info.get("full_scan_terms_per_step", 0)), "k_rescore_terms<full>"
-    flop = n_terms * n * per_pair
-    achieved = flop / avg_s / 1e12
+    ops = n_terms * n * per_pair
+    achieved = ops / avg_s / 1e12
     return {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3),
-            "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
-            "traffic": None, "avg_launch_ms": round(avg_s * 1e3, 3), "pair_evals_per_launch": n_terms * n}
+            "peak": PEAK_VALU_TLANE_OPS, "unit": "T lane-ops/s (operations counted on the definition)",
+            "frac": round(achieved / PEAK_VALU_TLANE_OPS, 4), "traffic": None, "avg_launch_ms": round(avg_s * 1e3, 3),
+            "pair_evals_per_launch": n_terms * n}
 
 
 def request_latency(farm, mem, qb, target, anchors, k, dtype, method, args):

@@ -73,6 +73,29 @@ __device__ inline float wave_dot(const float* __restrict__ a, const float* __res
   return wave_sum(acc);
 }
 
+// wave_dot with SL slabs of `b` loaded before their FMAs (one memory round
+// trip per SL slabs; `a` is read at the FMA, e.g. from LDS).  Same per-lane
+// order and reduction tree as wave_dot, so the values are bit-identical.
+template <int SL>
+__device__ inline float wave_dot_deep(const float* __restrict__ a, const float* __restrict__ b, int32_t ldk,
+                                      int lane) {
+  float acc = 0.f;
+  for (int base = 0; base < ldk; base += SL * 128) {
+    float2 y[SL];
+#pragma unroll
+    for (int u = 0; u < SL; ++u)
+      if (base + 128 * u < ldk) y[u] = *reinterpret_cast<const float2*>(b + base + 128 * u + 2 * lane);
+#pragma unroll
+    for (int u = 0; u < SL; ++u)
+      if (base + 128 * u < ldk) {
+        const float2 x = *reinterpret_cast<const float2*>(a + base + 128 * u + 2 * lane);
+        acc = fmaf(x.x, y[u].x, acc);
+        acc = fmaf(x.y, y[u].y, acc);
+      }
+  }
+  return wave_sum(acc);
+}
+
 // NN dot products against the same row `a`, interleaved for memory-level
 // parallelism; each one with exactly wave_dot's arithmetic (same per-lane
 // order, same reduction tree), so the values are bit-identical.  SLABS slabs
@@ -342,7 +365,7 @@ __device__ inline RegList load_reg_list(const int32_t* __restrict__ lidx, const 
   return l;
 }
 
-template <int FAM, class Row>
+template <int FAM, class Row, int SL = 2>
 __device__ bool subset_term_reg(Row arow, const float* __restrict__ qrow, const float* __restrict__ dn,
                                 int32_t ldk, int64_t o, float c, bool bounded, float qn, float qe,
                                 const float* __restrict__ o_err, float qd_uniform, const Geo& g, const Subset& sub,
@@ -408,7 +431,7 @@ __device__ bool subset_term_reg(Row arow, const float* __restrict__ qrow, const 
         const int32_t j2 = sub.lidx[e2];
         const float p2 = sub.lval[e2];
         if (list_value(arow.hi(j2, delta(j2)), p2) < B - (fabsf(B) * 1e-6f + 1e-30f)) continue;
-        const float a = fmaxf(0.f, wave_dot(qrow, dn + (int64_t)j2 * ldk, ldk, lane));
+        const float a = fmaxf(0.f, wave_dot_deep<SL>(qrow, dn + (int64_t)j2 * ldk, ldk, lane));
         ++dots;
         const float v = list_value(a, p2);
         take_max_j32(v, j2, g.ids, best, bj);
@@ -524,15 +547,15 @@ __device__ bool subset_term(Row arow, const float* __restrict__ qrow, const floa
 }
 
 // The form fixed at compile time (one form per kernel keeps its register count down).
-template <bool REG, int FAM, class Row>
+template <bool REG, int FAM, class Row, int SL = 2>
 __device__ inline bool subset_term_sel(Row arow, const float* __restrict__ qrow, const float* __restrict__ dn,
                                        int32_t ldk, int64_t o, float c, bool bounded, float qn, float qe,
                                        const float* __restrict__ o_err, float qd_uniform, const Geo& g,
                                        const Subset& sub, const Tgt& t, const RegList& lst, int lane,
                                        float& out_best, uint32_t& out_bid, uint32_t& dots) {
   if constexpr (REG)
-    return subset_term_reg<FAM>(arow, qrow, dn, ldk, o, c, bounded, qn, qe, o_err, qd_uniform, g, sub, t, lst, lane,
-                                out_best, out_bid, dots);
+    return subset_term_reg<FAM, Row, SL>(arow, qrow, dn, ldk, o, c, bounded, qn, qe, o_err, qd_uniform, g, sub, t,
+                                         lst, lane, out_best, out_bid, dots);
   else
     return subset_term_gen<FAM>(arow, qrow, dn, ldk, o, c, bounded, qn, qe, o_err, qd_uniform, g, sub, lane,
                                 out_best, out_bid, dots);
@@ -828,6 +851,13 @@ __device__ inline float block_max_lds(float v, float* red) {
 }
 
 constexpr int kStageLoads = 8;  // row staging: float4 loads per thread in flight
+constexpr int kLdsDotSlabs = 4;  // FP32 dots: descriptor slabs (128 floats) per memory round trip
+
+// Dynamic LDS of the proposal pass: the staged row (BF16 or FP32, padded to a
+// multiple of 4 elements) followed by the relation's query row (ldk floats).
+__host__ __device__ inline size_t subset_row_bytes(int64_t n, bool bounded) {
+  return (size_t)((n + 3) & ~(int64_t)3) * (bounded ? sizeof(uint16_t) : sizeof(float));
+}
 constexpr int kCandLds = 256;   // candidates whose id, coordinates and outside bound are staged in LDS
 
 template <bool BOUNDED, bool REG>
@@ -856,6 +886,12 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
   const int r0 = meta.rel_off[qq], R = meta.rel_off[qq + 1] - r0;
   const int e = r - r0;
   const float* arow = sim + (int64_t)(q + r) * ld_s;
+  // the query row of the relation, read by every FP32 dot product of the block
+  float* q_lds = reinterpret_cast<float*>(reinterpret_cast<char*>(srow) + subset_row_bytes(n, BOUNDED));
+  {
+    const float* qsrc = qn + (int64_t)(q + r) * ldk;
+    for (int i = threadIdx.x; i < ldk; i += kLdsThreads) q_lds[i] = qsrc[i];
+  }
   // stage the row (rows start 256-byte aligned)
   const int64_t n4 = n >> 2;
   const float4* a4 = reinterpret_cast<const float4*>(arow);
@@ -892,26 +928,49 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
     mx = fmaxf(mx, arow[j]);
   }
   const float amax = block_max_lds(mx, red);  // synchronises: the row is staged
-  // semantic set: count above tau, refine tau while more than kSemMax exceed it
-  auto count_above = [&](float tau) {
-    int32_t c = 0;
-    for (int64_t j = threadIdx.x; j < n; j += kLdsThreads) c += staged(j) > tau;
-    // block sum through the wave sums
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
-    __syncthreads();
-    if (lane == 0) red[wave] = __int_as_float(c);
-    __syncthreads();
-    int32_t t = 0;
-    for (int i = 0; i < kLdsWaves; ++i) t += __float_as_int(red[i]);
-    return t;
-  };
-  float tau = 0.5f * amax, gap = 0.5f * amax;
-  int32_t total = count_above(tau);
-  for (int it = 0; it < 30 && total > kSemMax; ++it) {
-    gap *= 0.5f;
-    tau = amax - gap;
-    total = count_above(tau);
+  // semantic set: the threshold is tau_k = amax - amax / 2^k for the smallest
+  // k in 1..kSemLevels with at most kSemMax similarities above it (kSemLevels
+  // if there is none), the thresholds formed by the float operations of
+  // repeated halving.  One pass over the row: tau_k is non-decreasing in k, so
+  // each similarity above tau_1 finds the largest k with v > tau_k by binary
+  // search and is counted in a histogram over k; the count above tau_k is the
+  // histogram's suffix sum from k.
+  constexpr int kSemLevels = 31;
+  __shared__ float tau_tab[kSemLevels + 1];
+  __shared__ int32_t lvl_hist[kSemLevels + 1];
+  if ((int)threadIdx.x <= kSemLevels) {
+    float gap = 0.5f * amax, t = 0.5f * amax;
+    for (int k = 1; k < (int)threadIdx.x; ++k) {
+      gap *= 0.5f;
+      t = amax - gap;
+    }
+    tau_tab[threadIdx.x] = t;  // entry 0 is unused
+    lvl_hist[threadIdx.x] = 0;
   }
+  __syncthreads();
+  const float tau1 = tau_tab[1];
+  for (int64_t j = threadIdx.x; j < n; j += kLdsThreads) {
+    const float v = staged(j);
+    if (!(v > tau1)) continue;
+    int lo = 1, hi = kSemLevels;  // v > tau_tab[lo]
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (v > tau_tab[mid]) lo = mid;
+      else hi = mid - 1;
+    }
+    atomicAdd(&lvl_hist[lo], 1);
+  }
+  __syncthreads();
+  int ks = kSemLevels;
+  {
+    int32_t above = 0;
+    for (int k = kSemLevels; k >= 1; --k) {
+      above += lvl_hist[k];
+      if (above > kSemMax) break;
+      ks = k;
+    }
+  }
+  const float tau = tau_tab[ks];
   if (threadIdx.x == 0) set_n = 0;
   __syncthreads();
   float out = 0.f;
@@ -965,7 +1024,7 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
 #pragma unroll
       for (int u = 0; u < 4; ++u) rows[u] = dn + (int64_t)set_idx[m0 + u < sn ? m0 + u : sn - 1] * ldk;
       float d[4];
-      wave_dots<4, 3>(qrow, rows, ldk, lane, d);
+      wave_dots<4, 3>(q_lds, rows, ldk, lane, d);
       if (lane == 0)
 #pragma unroll
         for (int u = 0; u < 4; ++u)
@@ -1000,8 +1059,11 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
   // term is evaluated (its predicate values at the start of its turn)
   auto ids_of = [&](int64_t o) {
     int4 j = make_int4(-1, -1, -1, -1);
-    if (kRegEntries * lane < pv.m)
-      j = *reinterpret_cast<const int4*>(pv.idx + ((int64_t)p * n + o) * pv.m + kRegEntries * lane);
+    // the lane's offset is formed anew per call (opaque copy): hoisted out of
+    // the terms loop, its 64-bit address would be held, or spilled, across it
+    int l4 = kRegEntries * lane;
+    asm volatile("" : "+v"(l4));
+    if (l4 < pv.m) j = *reinterpret_cast<const int4*>(pv.idx + ((int64_t)p * n + o) * pv.m + l4);
     return j;
   };
   int64_t o_nx = o_of(wave);
@@ -1050,26 +1112,26 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
     if (tab) switch (family_of(p)) {
       case kFamNear:
         if constexpr (BOUNDED)
-          ok = subset_term_sel<REG, kFamNear>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
+          ok = subset_term_sel<REG, kFamNear, RowBF16, kLdsDotSlabs>(RowBF16{srow16}, q_lds, dn, ldk, o, c, true, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
                                      best, bid, dots);
         else
-          ok = subset_term_sel<REG, kFamNear>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
+          ok = subset_term_sel<REG, kFamNear, RowF32, kLdsDotSlabs>(RowF32{srow}, q_lds, dn, ldk, o, c, false, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
                                      best, bid, dots);
         break;
       case kFamVert:
         if constexpr (BOUNDED)
-          ok = subset_term_sel<REG, kFamVert>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
+          ok = subset_term_sel<REG, kFamVert, RowBF16, kLdsDotSlabs>(RowBF16{srow16}, q_lds, dn, ldk, o, c, true, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
                                      best, bid, dots);
         else
-          ok = subset_term_sel<REG, kFamVert>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
+          ok = subset_term_sel<REG, kFamVert, RowF32, kLdsDotSlabs>(RowF32{srow}, q_lds, dn, ldk, o, c, false, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
                                      best, bid, dots);
         break;
       default:
         if constexpr (BOUNDED)
-          ok = subset_term_sel<REG, kFamLat>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
+          ok = subset_term_sel<REG, kFamLat, RowBF16, kLdsDotSlabs>(RowBF16{srow16}, q_lds, dn, ldk, o, c, true, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
                                      best, bid, dots);
         else
-          ok = subset_term_sel<REG, kFamLat>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
+          ok = subset_term_sel<REG, kFamLat, RowF32, kLdsDotSlabs>(RowF32{srow}, q_lds, dn, ldk, o, c, false, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
                                      best, bid, dots);
         break;
     }
@@ -1616,8 +1678,7 @@ bool lds_row_fits(int device, size_t bytes, bool bounded) {
 }
 
 bool proposal_pass_in_lds(const farm_memory* mem, bool bounded) {
-  return lds_row_fits(mem->device, (size_t)round_up(mem->n, 4) * (bounded ? sizeof(uint16_t) : sizeof(float)),
-                      bounded);
+  return lds_row_fits(mem->device, subset_row_bytes(mem->n, bounded) + sizeof(float) * (size_t)mem->ldk, bounded);
 }
 
 hipError_t launch_rescore_terms(const farm_memory* mem, const farm_workspace* ws, const float* sim, int64_t ld_s,
@@ -1670,7 +1731,7 @@ hipError_t launch_rescore_terms(const farm_memory* mem, const farm_workspace* ws
 #undef FARM_SCANFB
   }
   if (mode == kTermsSubset) {
-    const size_t lds = (size_t)round_up(mem->n, 4) * (bounded ? sizeof(uint16_t) : sizeof(float));
+    const size_t lds = subset_row_bytes(mem->n, bounded) + sizeof(float) * (size_t)mem->ldk;
     if (prop.in_lds) {
       const int32_t R = prop.rel_total;
       if (R <= 0) return hipSuccess;

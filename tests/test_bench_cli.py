@@ -45,5 +45,43 @@ def test_roofline_of_each_phase_kind():
         phases[phase] = (1e-3, 1)
         r = bench.dominant_roofline(phases, scene, qb, a, cfg, inf)
         assert r["bound"] == bound and r["kernel"].startswith(kernel), (phase, r)
-        assert 0.0 < r["frac"] == round(r["achieved"] / r["peak"], 4)
+        if phase == "pair":
+            # instruction counts come from the committed counter record of the precision
+            # workload only: none for this scene
+            assert r["frac"] is None and r["achieved"] is None
+        else:
+            assert 0.0 < r["frac"] == round(r["achieved"] / r["peak"], 4)
         json.dumps(r, allow_nan=False)
+
+
+def test_exhaustive_roofline_from_the_counter_record():
+    """The exhaustive pass's ALU fraction: FP32 arithmetic VALU instructions per pair from
+    profiles/valu.json times the launch's pairs, over the VALU issue peak (256 CU x 4 SIMD x 16
+    lanes x 2.4 GHz); skipped when the record no longer matches the kernel source."""
+    import pytest
+    sys.path.insert(0, ROOT)
+    import bench
+    from synth import CONFIGS, make_queries, make_scene
+
+    rec = bench.recorded_valu("k_pair_exhaustive", "precision")
+    if rec is None:
+        pytest.skip("no VALU record for the current kernel source")
+
+    class Args:
+        form, method = "f32", "exhaustive"
+
+    cfg = CONFIGS["tiny"]
+    scene = make_scene(cfg)
+    qb = make_queries(cfg, scene)
+
+    class Precision:
+        name = "precision"
+
+    phases = {"pair": (2.0, 2), "gemm": (0.1, 2)}
+    r = bench.dominant_roofline(phases, scene, qb, Args, Precision, None)
+    pairs = float(qb.r_tot) * scene.n * (scene.n - 1)
+    want = rec["fp32_arith_insts"] * 64.0 / rec["pair_evals"] * pairs / 1e-3 / 1e12
+    assert abs(r["achieved"] - want) <= 1e-3 * want + 1e-3
+    assert r["peak"] == 39.3216
+    assert r["frac"] == round(r["achieved"] / r["peak"], 4)
+    assert r["valu_issue_frac"] >= r["frac"]
