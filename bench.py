@@ -491,9 +491,14 @@ def dominant_roofline(phases, scene, qb, args, cfg, proposal_info):
         # instructions (moves, selects, compares included) is reported beside it
         pairs = float(R) * n * (n - 1)
         rec = recorded_valu("k_pair_exhaustive", cfg.name)
+        # beside it, the pass's algorithmic HBM bytes: every similarity row once (4 B per object
+        # and query or relation row) and the boxes (24 B per object) per query
+        nbytes = 4.0 * (q + R) * n + 24.0 * q * n
         out = {"bound": "alu", "kernel": "k_pair_exhaustive", "achieved": None, "peak": PEAK_VALU_TLANE_OPS,
                "unit": "T FP32 VALU lane-ops/s", "frac": None, "traffic": recorded_traffic("k_pair_exhaustive", cfg.name),
-               "pair_evals_per_launch": pairs, "avg_launch_ms": round(avg_s * 1e3, 3)}
+               "pair_evals_per_launch": pairs, "avg_launch_ms": round(avg_s * 1e3, 3),
+               "algorithmic_gbs": round(nbytes / avg_s / 1e9, 2),
+               "hbm_frac": round(nbytes / avg_s / 1e9 / PEAK_HBM_GBS, 6)}
         if rec:
             arith = rec["fp32_arith_insts"] * 64.0 / rec["pair_evals"]
             every = rec["sq_insts_valu"] * 64.0 / rec["pair_evals"]
