@@ -321,15 +321,18 @@ __device__ void full_term(const float* __restrict__ arow, const float* __restric
 // on every other anchor).
 // Similarity row of the proposal pass: FP32 values (global memory or LDS), or
 // BF16 roundings of a reduced-precision GEMM's values staged in LDS, whose
-// rounding (at most 2^-9 relative, round to nearest even) is folded into
-// the bounds (2^-7 relative, with margin).
+// rounding is folded into the bounds.  BF16 keeps 8 significant bits, so
+// round to nearest even moves x by at most 2^-8 |x|: the staged b satisfies
+// b (1 - 2^-8) <= x (1 - 2^-16) and x <= b (1 + 2^-8 + 2^-15).  The margin
+// m = 2^-8 + 2^-14 therefore gives b (1 - m) <= x <= b (1 + m) with room for
+// the FP32 rounding of the products (2^-24 relative).
 struct RowF32 {
   const float* p;
   __device__ float get(int64_t j) const { return p[j]; }
   __device__ float lo(int64_t j, float d) const { return fmaxf(0.f, p[j] - d); }
   __device__ float hi(int64_t j, float d) const { return fminf(1.0f, p[j] + d); }
 };
-constexpr float kBf16Margin = 1.0f / 128.0f;
+constexpr float kBf16Margin = 1.0f / 256.0f + 1.0f / 16384.0f;
 __device__ inline float bf16_value(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 __device__ inline uint16_t bf16_rne(float f) {
   uint32_t u = __float_as_uint(f);
