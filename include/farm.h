@@ -119,7 +119,7 @@ typedef enum {
                                 non-finite or zero-norm vector, duplicate id */
   FARM_ERR_OOM = -2,         /* device allocation failed or exceeds a budget */
   FARM_ERR_HIP = -3,         /* a HIP runtime call failed */
-  FARM_ERR_UNSUPPORTED = -4, /* valid request outside what this build serves */
+  FARM_ERR_UNSUPPORTED = -4, /* valid request outside what the library supports */
   FARM_ERR_BUSY = -5         /* the object is in use: a workspace entered by a
                                 second host thread during a call on it, or a
                                 memory freed while workspaces or servers still
@@ -486,7 +486,7 @@ FARM_API farm_status farm_workspace_timings(farm_workspace* ws, double* ms, int6
  * The query-time complexity analysis of the paper (Appendix "Robust
  * Relational Retrieval Formulation") bounds the binding cost by the anchor
  * candidate-set size K_a.  This network proposes, per (target, predicate), the
- * anchors worth evaluating; exhaustive scoring stays the fallback and the judge
+ * anchors worth evaluating; exhaustive scoring stays the fallback and the reference
  * of exactness (see farm_build_proposals).
  *
  *   x  = [u_o (dp) | u_a (dp) | g(o,a) / 4 m (12) | 0]     dp = d rounded up to 64
