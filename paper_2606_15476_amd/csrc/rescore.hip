@@ -368,13 +368,44 @@ __device__ inline RegList load_reg_list(const int32_t* __restrict__ lidx, const 
   return l;
 }
 
-template <int FAM, class Row, int SL = 2>
-__device__ bool subset_term_reg(Row arow, const float* __restrict__ qrow, const float* __restrict__ dn,
+// Survivor queue of the proposal pass (LDS): instead of taking each survivor's
+// FP32 dot product inside its term, a wave appends the survivors that can
+// still be the maximum to the block's queue, and after all terms the block's
+// waves take the queued dot products four at a time (one memory round trip
+// serves four) and fold them into the terms' maxima.
+constexpr int kDeferCap = 512;  // survivor queue entries per block
+__shared__ int32_t dq_n;                  // entries reserved so far
+__shared__ uint16_t dq_tag[kDeferCap];    // (term << 8) | list entry index (terms < 256, lists <= 256 entries)
+__shared__ int32_t dq_anchor[kDeferCap];  // anchor index of the entry; -1 for a slot left unused
+
+// 64-bit key whose unsigned order is (value, then smaller id): the value's
+// IEEE bits mapped monotonically onto unsigned integers, then the inverted id.
+// Key 0 stands for "no anchor yet" (below every real key).
+__device__ inline uint64_t value_key(float v, uint32_t id) {
+  const uint32_t u = __float_as_uint(v);
+  const uint32_t ord = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+  return ((uint64_t)ord << 32) | (uint64_t)(0xFFFFFFFFu - id);
+}
+__device__ inline float key_value(uint64_t key) {
+  const uint32_t ord = (uint32_t)(key >> 32);
+  return __uint_as_float((ord & 0x80000000u) ? (ord & 0x7FFFFFFFu) : ~ord);
+}
+__device__ inline uint32_t key_id(uint64_t key) { return 0xFFFFFFFFu - (uint32_t)key; }
+
+// Result codes of subset_term_reg: kTermOpen (not certified: the fallback
+// scans it), kTermDone (certified), kTermQueued (survivors queued; the set's
+// value so far returned).
+enum { kTermOpen = 0, kTermDone = 1, kTermQueued = 2 };
+
+template <int FAM, class Row, int SL = 2, bool DEFER = false>
+__device__ int subset_term_reg(Row arow, const float* __restrict__ qrow, const float* __restrict__ dn,
                                 int32_t ldk, int64_t o, float c, bool bounded, float qn, float qe,
                                 const float* __restrict__ o_err, float qd_uniform, const Geo& g, const Subset& sub,
                                 const Tgt& t, const RegList& lst, int lane, float& out_best, uint32_t& out_bid,
-                                uint32_t& dots) {
+                                uint32_t& dots, int defer_term = -1) {
   const int4 j4 = lst.j;
+  int code = kTermOpen;
+  bool full = false;
   const float4 p4 = lst.p;
   const int32_t jl[kRegEntries] = {j4.x, j4.y, j4.z, j4.w};
   const float pl[kRegEntries] = {p4.x, p4.y, p4.z, p4.w};
@@ -422,6 +453,50 @@ __device__ bool subset_term_reg(Row arow, const float* __restrict__ qrow, const 
       surv |= (list_value(arow.hi(j, delta(j)), pl[k]) >= L ? 1u : 0u) << k;
     }
     float B = wave_max_f(best);
+    if constexpr (DEFER) {
+      // queue the survivors whose upper bound reaches the best exact value so
+      // far (a queued entry is evaluated like one taken here, so the maximum
+      // and its anchor are the same); with the queue full the term is left
+      // uncertified (the fallback scans it in full)
+      const float Bs = B - (fabsf(B) * 1e-6f + 1e-30f);
+      uint32_t keep = 0;
+#pragma unroll
+      for (int k = 0; k < kRegEntries; ++k)
+        if ((surv >> k) & 1u) {
+          const int64_t j = jl[k];
+          keep |= (list_value(arow.hi(j, delta(j)), pl[k]) >= Bs ? 1u : 0u) << k;
+        }
+      const int mine = __popc(keep);
+      int incl = mine;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(incl, off);
+        if (lane >= off) incl += y;
+      }
+      const int total = __shfl(incl, 63);
+      if (total > 0) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&dq_n, total);
+        base = __shfl(base, 0);
+        if (base + total <= kDeferCap) {
+          int pos = base + incl - mine;
+#pragma unroll
+          for (int k = 0; k < kRegEntries; ++k)
+            if ((keep >> k) & 1u) {
+              dq_tag[pos] = (uint16_t)((defer_term << 8) | (kRegEntries * lane + k));
+              dq_anchor[pos] = jl[k];
+              ++pos;
+            }
+          code = kTermQueued;
+        } else {
+          for (int i = base + lane; i < base + total && i < kDeferCap; i += 64) dq_anchor[i] = -1;
+          best = value_floor<FAM>();
+          bj = -1;
+          full = true;
+        }
+      }
+      surv = 0;
+    }
     // survivors: the entry is re-read (one uniform load) so that nothing of
     // the register-held list stays live across the dot products
 #pragma unroll
@@ -446,7 +521,8 @@ __device__ bool subset_term_reg(Row arow, const float* __restrict__ qrow, const 
   wave_argmax(best, bid);
   out_best = best;
   out_bid = bid;
-  return best > sub.cert;
+  if (DEFER && (full || code == kTermQueued)) return code;
+  return best > sub.cert ? kTermDone : kTermOpen;
 }
 
 template <int FAM, class Row>
@@ -550,17 +626,18 @@ __device__ bool subset_term(Row arow, const float* __restrict__ qrow, const floa
 }
 
 // The form fixed at compile time (one form per kernel keeps its register count down).
-template <bool REG, int FAM, class Row, int SL = 2>
-__device__ inline bool subset_term_sel(Row arow, const float* __restrict__ qrow, const float* __restrict__ dn,
+template <bool REG, int FAM, class Row, int SL = 2, bool DEFER = false>
+__device__ inline int subset_term_sel(Row arow, const float* __restrict__ qrow, const float* __restrict__ dn,
                                        int32_t ldk, int64_t o, float c, bool bounded, float qn, float qe,
                                        const float* __restrict__ o_err, float qd_uniform, const Geo& g,
                                        const Subset& sub, const Tgt& t, const RegList& lst, int lane,
-                                       float& out_best, uint32_t& out_bid, uint32_t& dots) {
+                                       float& out_best, uint32_t& out_bid, uint32_t& dots,
+                                       int defer_term = -1) {
   if constexpr (REG)
-    return subset_term_reg<FAM, Row, SL>(arow, qrow, dn, ldk, o, c, bounded, qn, qe, o_err, qd_uniform, g, sub, t,
-                                         lst, lane, out_best, out_bid, dots);
+    return subset_term_reg<FAM, Row, SL, DEFER>(arow, qrow, dn, ldk, o, c, bounded, qn, qe, o_err, qd_uniform, g,
+                                                sub, t, lst, lane, out_best, out_bid, dots, defer_term);
   else
-    return subset_term_gen<FAM>(arow, qrow, dn, ldk, o, c, bounded, qn, qe, o_err, qd_uniform, g, sub, lane,
+    return (int)subset_term_gen<FAM>(arow, qrow, dn, ldk, o, c, bounded, qn, qe, o_err, qd_uniform, g, sub, lane,
                                 out_best, out_bid, dots);
 }
 
@@ -857,11 +934,12 @@ constexpr int kStageLoads = 8;  // row staging: float4 loads per thread in fligh
 constexpr int kLdsDotSlabs = 4;  // FP32 dots: descriptor slabs (128 floats) per memory round trip
 
 // Dynamic LDS of the proposal pass: the staged row (BF16 or FP32, padded to a
-// multiple of 4 elements) followed by the relation's query row (ldk floats).
+// multiple of 4 elements).
 __host__ __device__ inline size_t subset_row_bytes(int64_t n, bool bounded) {
   return (size_t)((n + 3) & ~(int64_t)3) * (bounded ? sizeof(uint16_t) : sizeof(float));
 }
 constexpr int kCandLds = 256;   // candidates whose id, coordinates and outside bound are staged in LDS
+static_assert(kCandLds <= 256, "a queued survivor's term index takes 8 bits");
 
 template <bool BOUNDED, bool REG>
 __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_rescore_subset_lds(
@@ -883,18 +961,17 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
   __shared__ float c_pout[kCandLds];
   __shared__ int32_t set_n;
   __shared__ unsigned long long wave_cnt[kLdsWaves][3];
+  // survivor queue and the queued terms' running maxima (reduced precision, register lists)
+  constexpr bool kDefer = BOUNDED && REG;
+  __shared__ unsigned long long t_key[kDefer ? kCandLds : 1];
+  __shared__ uint32_t t_def[kDefer ? kCandLds / 32 : 1];
+  __shared__ uint32_t fell_def;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int32_t r = blockIdx.x;
   const int32_t qq = meta.rel_query[r];
   const int r0 = meta.rel_off[qq], R = meta.rel_off[qq + 1] - r0;
   const int e = r - r0;
   const float* arow = sim + (int64_t)(q + r) * ld_s;
-  // the query row of the relation, read by every FP32 dot product of the block
-  float* q_lds = reinterpret_cast<float*>(reinterpret_cast<char*>(srow) + subset_row_bytes(n, BOUNDED));
-  {
-    const float* qsrc = qn + (int64_t)(q + r) * ldk;
-    for (int i = threadIdx.x; i < ldk; i += kLdsThreads) q_lds[i] = qsrc[i];
-  }
   // stage the row (rows start 256-byte aligned)
   const int64_t n4 = n >> 2;
   const float4* a4 = reinterpret_cast<const float4*>(arow);
@@ -929,6 +1006,13 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
     if (BOUNDED) srow16[j] = bf16_rne(arow[j]);
     else srow[j] = arow[j];
     mx = fmaxf(mx, arow[j]);
+  }
+  if (kDefer) {
+    if (threadIdx.x == 0) {
+      dq_n = 0;
+      fell_def = 0;
+    }
+    if ((int)threadIdx.x < kCandLds / 32) t_def[threadIdx.x] = 0;
   }
   const float amax = block_max_lds(mx, red);  // synchronises: the row is staged
   // semantic set: the threshold is tau_k = amax - amax / 2^k for the smallest
@@ -1027,7 +1111,7 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
 #pragma unroll
       for (int u = 0; u < 4; ++u) rows[u] = dn + (int64_t)set_idx[m0 + u < sn ? m0 + u : sn - 1] * ldk;
       float d[4];
-      wave_dots<4, 3>(q_lds, rows, ldk, lane, d);
+      wave_dots<4, 3>(qrow, rows, ldk, lane, d);
       if (lane == 0)
 #pragma unroll
         for (int u = 0; u < 4; ++u)
@@ -1054,8 +1138,11 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
   // this wave's terms are candidates wave, wave + kLdsWaves, ...
   // (wave-uniform values are moved to scalar registers: fewer vector registers)
   auto uni = [](float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); };
+  // with the survivor queue the loop takes the first kCandLds candidates (the
+  // queued terms' results have LDS slots); the rest follow after the queue
+  const int32_t cnt1 = kDefer && cnt > kCandLds ? kCandLds : cnt;
   auto o_of = [&](int32_t cc) -> int64_t {
-    if (cc >= cnt) return -1;
+    if (cc >= cnt1) return -1;
     return __builtin_amdgcn_readfirstlane(cc < kCandLds ? c_id[cc] : cand[(int64_t)qq * C + cc]);
   };
   // register form: the next term's list ids are loaded while the current
@@ -1072,7 +1159,7 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
   int64_t o_nx = o_of(wave);
   int4 j_nx = make_int4(-1, -1, -1, -1);
   if (REG && tab && o_nx >= 0) j_nx = ids_of(o_nx);
-  for (int32_t cc = second ? cnt : wave; cc < cnt; cc += kLdsWaves) {
+  for (int32_t cc = second ? cnt1 : wave; cc < cnt1; cc += kLdsWaves) {
     const int64_t slot = (int64_t)qq * C + cc;
     const int64_t o = REG ? o_nx : o_of(cc);
     RegList lst{j_nx, make_float4(0.f, 0.f, 0.f, 0.f)};
@@ -1111,32 +1198,43 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
     }
     float best = 0.f;
     uint32_t bid = FARM_NO_ID;
-    bool ok = false;
+    int code = kTermOpen;
+    const int dterm = kDefer ? (int)cc : -1;
     if (tab) switch (family_of(p)) {
       case kFamNear:
         if constexpr (BOUNDED)
-          ok = subset_term_sel<REG, kFamNear, RowBF16, kLdsDotSlabs>(RowBF16{srow16}, q_lds, dn, ldk, o, c, true, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
-                                     best, bid, dots);
+          code = subset_term_sel<REG, kFamNear, RowBF16, kLdsDotSlabs, kDefer>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
+                                     best, bid, dots, dterm);
         else
-          ok = subset_term_sel<REG, kFamNear, RowF32, kLdsDotSlabs>(RowF32{srow}, q_lds, dn, ldk, o, c, false, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
+          code = subset_term_sel<REG, kFamNear, RowF32, kLdsDotSlabs>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
                                      best, bid, dots);
         break;
       case kFamVert:
         if constexpr (BOUNDED)
-          ok = subset_term_sel<REG, kFamVert, RowBF16, kLdsDotSlabs>(RowBF16{srow16}, q_lds, dn, ldk, o, c, true, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
-                                     best, bid, dots);
+          code = subset_term_sel<REG, kFamVert, RowBF16, kLdsDotSlabs, kDefer>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
+                                     best, bid, dots, dterm);
         else
-          ok = subset_term_sel<REG, kFamVert, RowF32, kLdsDotSlabs>(RowF32{srow}, q_lds, dn, ldk, o, c, false, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
+          code = subset_term_sel<REG, kFamVert, RowF32, kLdsDotSlabs>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
                                      best, bid, dots);
         break;
       default:
         if constexpr (BOUNDED)
-          ok = subset_term_sel<REG, kFamLat, RowBF16, kLdsDotSlabs>(RowBF16{srow16}, q_lds, dn, ldk, o, c, true, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
-                                     best, bid, dots);
+          code = subset_term_sel<REG, kFamLat, RowBF16, kLdsDotSlabs, kDefer>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
+                                     best, bid, dots, dterm);
         else
-          ok = subset_term_sel<REG, kFamLat, RowF32, kLdsDotSlabs>(RowF32{srow}, q_lds, dn, ldk, o, c, false, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
+          code = subset_term_sel<REG, kFamLat, RowF32, kLdsDotSlabs>(RowF32{srow}, qrow, dn, ldk, o, c, false, qnr, qer, nullptr, qd, gp, sub, t, lst, lane,
                                      best, bid, dots);
         break;
+    }
+    checked += 1;
+    const bool ok = code == kTermDone;
+    if (kDefer && code == kTermQueued) {
+      // the set's exact values so far; the queued survivors follow after the loop
+      if (lane == 0) {
+        t_key[cc] = bid == FARM_NO_ID ? 0ull : value_key(best, bid);
+        atomicOr(&t_def[cc >> 5], 1u << (cc & 31));
+      }
+      continue;
     }
     if (lane == 0) {
       rs_terms[slot * kMaxRel + e] = ok ? best : NAN;  // NaN: scanned in full by the fallback pass
@@ -1147,8 +1245,128 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
           pv.fb_list[pos] = ((unsigned long long)qq << 32) | (unsigned long long)((int64_t)cc * R + e);
       }
     }
-    checked += 1;
     fell += ok ? 0 : 1;
+  }
+  if constexpr (kDefer) {
+    // the queued survivors' FP32 dot products, four per wave at a time, folded
+    // into their terms' maxima (value, then smaller id, as in the term loop)
+    __syncthreads();
+    const int nq = dq_n < kDeferCap ? dq_n : kDeferCap;
+    const float floor_v = fam == kFamNear ? -INFINITY : -1.0f;
+    for (int b0 = 4 * wave; b0 < nq; b0 += 4 * kLdsWaves) {
+      int32_t aj[4];
+      const float* rows[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = b0 + u;
+        aj[u] = i < nq ? dq_anchor[i] : -1;
+        rows[u] = dn + (int64_t)(aj[u] >= 0 ? aj[u] : 0) * ldk;
+      }
+      float d[4];
+      wave_dots<4, 3>(qrow, rows, ldk, lane, d);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (aj[u] < 0) continue;
+        ++dots;
+        if (lane == 0) {
+          const uint32_t tg = dq_tag[b0 + u];
+          const int term = (int)(tg >> 8), e2 = (int)(tg & 0xFFu);
+          const int32_t j2 = aj[u];
+          const float p2 = pv.val[((int64_t)p * n + c_id[term]) * pv.m + e2];
+          const float a = fmaxf(0.f, d[u]);
+          const float v = fam == kFamNear ? near_log(a) + p2 : a * p2;
+          // an entry at the floor value binds only where the set already did (as in the term loop)
+          if (v > floor_v || t_key[term] != 0ull) atomicMax(&t_key[term], value_key(v, gp.ids[j2]));
+        }
+      }
+    }
+    __syncthreads();
+    // the queued terms' results: certificate, outputs, fallback worklist
+    const int nt = cnt < kCandLds ? cnt : kCandLds;
+    const float a_hi = tau_out + qd;
+    for (int cc = threadIdx.x; cc < nt; cc += kLdsThreads) {
+      if (!((t_def[cc >> 5] >> (cc & 31)) & 1u)) continue;
+      const unsigned long long key = t_key[cc];
+      const float best = key ? key_value(key) : floor_v;
+      const uint32_t bid = key ? key_id(key) : FARM_NO_ID;
+      const float pout = c_pout[cc];
+      float cert;
+      if (fam == kFamNear) {
+        const float b = near_log(a_hi) + pout;
+        cert = b + fabsf(b) * 1e-6f;
+      } else {
+        cert = a_hi * pout;
+      }
+      const bool ok = best > cert;
+      const int64_t slot = (int64_t)qq * C + cc;
+      rs_terms[slot * kMaxRel + e] = ok ? best : NAN;
+      rs_anchor[slot * kMaxRel + e] = bid;
+      if (!ok) {
+        if (pv.fb_list) {
+          const uint32_t pos = atomicAdd(pv.fb_count, 1u);
+          if (pos < pv.fb_cap)
+            pv.fb_list[pos] = ((unsigned long long)qq << 32) | (unsigned long long)((int64_t)cc * R + e);
+        }
+        atomicAdd(&fell_def, 1u);
+      }
+    }
+    // candidates past the first kCandLds: each term with its survivors' dot products taken in place
+    for (int32_t cc = second ? cnt : kCandLds + wave; cc < cnt; cc += kLdsWaves) {
+      const int64_t o = __builtin_amdgcn_readfirstlane(cand[(int64_t)qq * C + cc]);
+      if (o < 0) continue;
+      const int64_t slot = (int64_t)qq * C + cc;
+      const Tgt t = load_target(fam, o, gp.x, gp.y, gp.z, gp.hhi, gp.hlo);
+      const float pout = tab ? pv.out[(int64_t)p * n + o] : 0.f;
+      Subset sub;
+      const int64_t off = ((int64_t)p * n + o) * pv.m;
+      sub.lidx = pv.idx + off;
+      sub.lval = pv.val + off;
+      sub.M = pv.m;
+      sub.sidx = set_idx;
+      sub.sn = sn;
+      sub.ssim = set_sim;
+      sub.sgeo = set_geo;
+      if (fam == kFamNear) {
+        const float b = near_log(a_hi) + pout;
+        sub.cert = b + fabsf(b) * 1e-6f;
+      } else {
+        sub.cert = a_hi * pout;
+      }
+      float best = 0.f;
+      uint32_t bid = FARM_NO_ID;
+      bool ok = false;
+      if (tab) {
+        const RegList lst = load_reg_list(sub.lidx, sub.lval, sub.M, lane);
+        switch (fam) {
+          case kFamNear:
+            ok = subset_term_sel<REG, kFamNear, RowBF16, kLdsDotSlabs>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr,
+                                                                        qer, nullptr, qd, gp, sub, t, lst, lane, best,
+                                                                        bid, dots);
+            break;
+          case kFamVert:
+            ok = subset_term_sel<REG, kFamVert, RowBF16, kLdsDotSlabs>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr,
+                                                                        qer, nullptr, qd, gp, sub, t, lst, lane, best,
+                                                                        bid, dots);
+            break;
+          default:
+            ok = subset_term_sel<REG, kFamLat, RowBF16, kLdsDotSlabs>(RowBF16{srow16}, qrow, dn, ldk, o, c, true, qnr,
+                                                                       qer, nullptr, qd, gp, sub, t, lst, lane, best,
+                                                                       bid, dots);
+            break;
+        }
+      }
+      if (lane == 0) {
+        rs_terms[slot * kMaxRel + e] = ok ? best : NAN;
+        rs_anchor[slot * kMaxRel + e] = bid;
+        if (!ok && pv.fb_list) {
+          const uint32_t pos = atomicAdd(pv.fb_count, 1u);
+          if (pos < pv.fb_cap)
+            pv.fb_list[pos] = ((unsigned long long)qq << 32) | (unsigned long long)((int64_t)cc * R + e);
+        }
+      }
+      checked += 1;
+      fell += ok ? 0 : 1;
+    }
   }
   // counters: summed over the block's waves, then one atomic each per block
   __syncthreads();
@@ -1161,6 +1379,7 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
   if (pv.stats && threadIdx.x < 3) {
     unsigned long long t = 0;
     for (int i = 0; i < kLdsWaves; ++i) t += wave_cnt[i][threadIdx.x];
+    if (kDefer && threadIdx.x == 1) t += fell_def;
     if (t) atomicAdd(&pv.stats[threadIdx.x], t);
   }
 }
@@ -1681,7 +1900,7 @@ bool lds_row_fits(int device, size_t bytes, bool bounded) {
 }
 
 bool proposal_pass_in_lds(const farm_memory* mem, bool bounded) {
-  return lds_row_fits(mem->device, subset_row_bytes(mem->n, bounded) + sizeof(float) * (size_t)mem->ldk, bounded);
+  return lds_row_fits(mem->device, subset_row_bytes(mem->n, bounded), bounded);
 }
 
 hipError_t launch_rescore_terms(const farm_memory* mem, const farm_workspace* ws, const float* sim, int64_t ld_s,
@@ -1734,7 +1953,7 @@ hipError_t launch_rescore_terms(const farm_memory* mem, const farm_workspace* ws
 #undef FARM_SCANFB
   }
   if (mode == kTermsSubset) {
-    const size_t lds = subset_row_bytes(mem->n, bounded) + sizeof(float) * (size_t)mem->ldk;
+    const size_t lds = subset_row_bytes(mem->n, bounded);
     if (prop.in_lds) {
       const int32_t R = prop.rel_total;
       if (R <= 0) return hipSuccess;
