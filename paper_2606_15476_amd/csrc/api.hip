@@ -497,6 +497,8 @@ farm_status query_topk_core(const farm_memory* mem, farm_workspace* ws, int32_t 
       pv.fb_cap = ws->fb_cap;
       pv.rel_total = R;
       pv.in_lds = in_lds;
+      // the survivor queue suits BF16's error bound; FP8's leaves too many survivors per relation
+      pv.queue = dtype == FARM_BF16;
       pv.sem_idx_out = ws->sem_idx;
       pv.sem_cnt_out = ws->sem_cnt;
       pv.sem_tau_out = ws->sem_tau;

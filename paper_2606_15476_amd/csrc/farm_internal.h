@@ -277,6 +277,7 @@ struct PropView {
   int64_t fb_cap = 0;
   int32_t rel_total = 0;  // relation rows of the call (one LDS-staged block each)
   bool in_lds = false;    // run the proposal pass with the rows staged in LDS
+  bool queue = false;     // LDS pass: queue the survivors' dot products per block (BF16 similarities)
   // Between's candidate sets (scanned terms of Between invocations)
   const int32_t* btw_idx = nullptr;
   const float* btw_sim = nullptr;

@@ -941,7 +941,7 @@ __host__ __device__ inline size_t subset_row_bytes(int64_t n, bool bounded) {
 constexpr int kCandLds = 256;   // candidates whose id, coordinates and outside bound are staged in LDS
 static_assert(kCandLds <= 256, "a queued survivor's term index takes 8 bits");
 
-template <bool BOUNDED, bool REG>
+template <bool BOUNDED, bool REG, bool QUEUE>
 __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_rescore_subset_lds(
     const float* __restrict__ sim, int64_t ld_s, int32_t q, MetaView meta, SimBound bound,
     const float* __restrict__ qn, const float* __restrict__ dn, int32_t ldk, const int32_t* __restrict__ cand,
@@ -962,7 +962,7 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
   __shared__ int32_t set_n;
   __shared__ unsigned long long wave_cnt[kLdsWaves][3];
   // survivor queue and the queued terms' running maxima (reduced precision, register lists)
-  constexpr bool kDefer = BOUNDED && REG;
+  constexpr bool kDefer = BOUNDED && REG && QUEUE;
   __shared__ unsigned long long t_key[kDefer ? kCandLds : 1];
   __shared__ uint32_t t_def[kDefer ? kCandLds / 32 : 1];
   __shared__ uint32_t fell_def;
@@ -972,6 +972,15 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
   const int r0 = meta.rel_off[qq], R = meta.rel_off[qq + 1] - r0;
   const int e = r - r0;
   const float* arow = sim + (int64_t)(q + r) * ld_s;
+  // Reduced precision without the survivor queue (FP8): the relation's query
+  // row is staged in LDS after the similarity row, since every survivor's dot
+  // product reads it
+  constexpr bool kQrowLds = BOUNDED && !kDefer;
+  float* q_lds = reinterpret_cast<float*>(reinterpret_cast<char*>(srow) + subset_row_bytes(n, BOUNDED));
+  if (kQrowLds) {
+    const float* qsrc = qn + (int64_t)(q + r) * ldk;
+    for (int i = threadIdx.x; i < ldk; i += kLdsThreads) q_lds[i] = qsrc[i];
+  }
   // stage the row (rows start 256-byte aligned)
   const int64_t n4 = n >> 2;
   const float4* a4 = reinterpret_cast<const float4*>(arow);
@@ -1076,7 +1085,7 @@ __global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6))
   // largest similarity outside the set (a staged BF16 value bounds its source within the margin)
   const float tau_out = block_max_lds(out, red) * (BOUNDED ? 1.0f + kBf16Margin : 1.0f);  // synchronises
   const int sn = set_n < kSemMax ? set_n : kSemMax;
-  const float* qrow = qn + (int64_t)(q + r) * ldk;
+  const float* qrow = kQrowLds ? q_lds : qn + (int64_t)(q + r) * ldk;
   const int p = meta.rel_pred[r];
   const int fam = family_of(p);
   const Geo gp = geo_for(g, p, n);
@@ -1869,10 +1878,12 @@ bool lds_row_fits(int device, size_t bytes, bool bounded) {
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) v = -1;
     limit[device] = v > 0 ? v : -1;
   }
-  const void* fn[2] = {bounded ? reinterpret_cast<const void*>(&k_rescore_subset_lds<true, false>)
-                               : reinterpret_cast<const void*>(&k_rescore_subset_lds<false, false>),
-                       bounded ? reinterpret_cast<const void*>(&k_rescore_subset_lds<true, true>)
-                               : reinterpret_cast<const void*>(&k_rescore_subset_lds<false, true>)};
+  const void* fn[3] = {bounded ? reinterpret_cast<const void*>(&k_rescore_subset_lds<true, false, false>)
+                               : reinterpret_cast<const void*>(&k_rescore_subset_lds<false, false, false>),
+                       bounded ? reinterpret_cast<const void*>(&k_rescore_subset_lds<true, true, false>)
+                               : reinterpret_cast<const void*>(&k_rescore_subset_lds<false, true, false>),
+                       bounded ? reinterpret_cast<const void*>(&k_rescore_subset_lds<true, true, true>)
+                               : reinterpret_cast<const void*>(&k_rescore_subset_lds<false, true, false>)};
   // the kernels' own (static) LDS comes on top of the row
   static size_t stat[2] = {0, 0};
   size_t& st = stat[bounded ? 1 : 0];
@@ -1900,7 +1911,9 @@ bool lds_row_fits(int device, size_t bytes, bool bounded) {
 }
 
 bool proposal_pass_in_lds(const farm_memory* mem, bool bounded) {
-  return lds_row_fits(mem->device, subset_row_bytes(mem->n, bounded), bounded);
+  // the largest dynamic size an instance uses: the row, plus the query row without the queue
+  return lds_row_fits(mem->device, subset_row_bytes(mem->n, bounded) + (bounded ? sizeof(float) * (size_t)mem->ldk : 0),
+                      bounded);
 }
 
 hipError_t launch_rescore_terms(const farm_memory* mem, const farm_workspace* ws, const float* sim, int64_t ld_s,
@@ -1954,20 +1967,22 @@ hipError_t launch_rescore_terms(const farm_memory* mem, const farm_workspace* ws
   }
   if (mode == kTermsSubset) {
     const size_t lds = subset_row_bytes(mem->n, bounded);
+    const size_t lds_q = lds + (bounded ? sizeof(float) * (size_t)mem->ldk : 0);  // + the query row (no queue)
     if (prop.in_lds) {
       const int32_t R = prop.rel_total;
       if (R <= 0) return hipSuccess;
-#define FARM_LDS(B, REG)                                                                                        \
-  hipLaunchKernelGGL((k_rescore_subset_lds<B, REG>), dim3((unsigned)R), dim3(kLdsThreads), lds, s, sim, ld_s, q, \
+#define FARM_LDS(B, REG, QUEUE, BYTES)                                                                          \
+  hipLaunchKernelGGL((k_rescore_subset_lds<B, REG, QUEUE>), dim3((unsigned)R), dim3(kLdsThreads), BYTES, s, sim, ld_s, q, \
                      meta, bound, ws->qn, mem->dn, mem->ldk, cand, cand_count, c, g, mem->n, ws->rs_terms,        \
                      ws->rs_anchor, prop)
       const bool reg = (prop.m & (kRegEntries - 1)) == 0 && prop.m <= 64 * kRegEntries;
       if (bounded) {
-        if (reg) FARM_LDS(true, true);
-        else FARM_LDS(true, false);
+        if (reg && prop.queue) FARM_LDS(true, true, true, lds);
+        else if (reg) FARM_LDS(true, true, false, lds_q);
+        else FARM_LDS(true, false, false, lds_q);
       } else {
-        if (reg) FARM_LDS(false, true);
-        else FARM_LDS(false, false);
+        if (reg) FARM_LDS(false, true, false, lds);
+        else FARM_LDS(false, false, false, lds);
       }
 #undef FARM_LDS
       return hipGetLastError();
